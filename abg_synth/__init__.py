@@ -1,0 +1,296 @@
+"""Seeded synthetic inputs for TPO clustering jobs.
+
+This module holds no step of the clustering method itself. It produces
+
+* planted-partition attributed bipartite graphs (ABGs): a degree-corrected
+  bipartite stochastic block model with Zipf degree weights, unique unweighted
+  edges in random order, and Gaussian-mixture attributes on the target side U
+  (the paper's ABG model, Section 2.1); and
+* the Gaussian random matrices the method draws (the matrix G of Algorithm 1,
+  the sketching matrices of the randomized SVDs), from a counter-based
+  generator: SplitMix64 (Steele, Lea and Flood, OOPSLA 2014) turned into
+  uniforms on (0, 1] with 53 bits and into normals with the Box-Muller
+  transform.  The native library carries its own implementation of the same
+  published generator; both sides are checked against each other.
+
+Both the FP64 oracle and the GPU path take their inputs from here.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+__all__ = [
+    "ABG",
+    "JobShape",
+    "CONFIGS",
+    "planted_abg",
+    "splitmix64_normals",
+    "method_matrices",
+    "STREAM_OMEGA_REDUCE",
+    "STREAM_G",
+    "STREAM_OMEGA",
+]
+
+# ---------------------------------------------------------------------------
+# Counter-based normal generator (SplitMix64 -> 53-bit uniform -> Box-Muller)
+# ---------------------------------------------------------------------------
+_MASK64 = (1 << 64) - 1
+_GOLDEN_GAMMA = 0x9E3779B97F4A7C15
+_STREAM_SALT = 0x632BE59BD9B4E019
+
+STREAM_OMEGA_REDUCE = 0  # d_U x l_r sketch for the attribute reduction
+STREAM_G = 1             # d x d Gaussian matrix G of Algorithm 1
+STREAM_OMEGA = 2         # 2d x k' sketch for RandomizedSVD(R, k)
+
+
+def _splitmix64_next(state: int) -> tuple[int, int]:
+    state = (state + _GOLDEN_GAMMA) & _MASK64
+    z = state
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK64
+    z = z ^ (z >> 31)
+    return state, z
+
+
+def splitmix64_normals(seed: int, stream: int, count: int) -> np.ndarray:
+    """`count` standard normals of stream `stream` under `seed`.
+
+    The stream's SplitMix64 state starts at seed XOR (salt * (stream + 1)).
+    Each pair of 64-bit outputs (a, b) gives u1 = ((a >> 11) + 1) * 2^-53 and
+    u2 = ((b >> 11) + 1) * 2^-53, both in (0, 1], and the two normals
+    sqrt(-2 ln u1) cos(2 pi u2), sqrt(-2 ln u1) sin(2 pi u2), emitted in that
+    order.  Scalar libm calls (math.log / math.cos / math.sin / math.sqrt) are
+    used so that the native implementation can reproduce every bit.
+    """
+    if count < 0:
+        raise ValueError("count must be >= 0")
+    state = (int(seed) ^ ((_STREAM_SALT * (int(stream) + 1)) & _MASK64)) & _MASK64
+    out = np.empty(count, dtype=np.float64)
+    two_pi = 2.0 * math.pi
+    scale = 1.0 / 9007199254740992.0  # 2^-53
+    i = 0
+    while i < count:
+        state, a = _splitmix64_next(state)
+        state, b = _splitmix64_next(state)
+        u1 = ((a >> 11) + 1) * scale
+        u2 = ((b >> 11) + 1) * scale
+        rad = math.sqrt(-2.0 * math.log(u1))
+        out[i] = rad * math.cos(two_pi * u2)
+        if i + 1 < count:
+            out[i + 1] = rad * math.sin(two_pi * u2)
+        i += 2
+    return out
+
+
+@dataclass(frozen=True)
+class MethodMatrices:
+    """Random matrices one clustering job draws (row-major float64)."""
+
+    omega_reduce: np.ndarray | None  # d_U x l_r, or None when no reduction
+    g: np.ndarray                    # d x d
+    omega: np.ndarray                # 2d x k'
+
+
+def sketch_widths(d_u: int, d: int, k: int, oversample: int) -> tuple[int, int, int]:
+    """(d_eff, l_r, k') for a job: the working attribute width, the width of
+    the reduction sketch, and the width of the embedding sketch.
+
+    d_eff = d_u when d <= 0 or d >= d_u (no reduction).  l_r = min(d + p, d_u),
+    k' = min(k + p, 2 d_eff).  Shared by the generator and the native planner,
+    which compute it independently.
+    """
+    d_eff = d_u if (d <= 0 or d >= d_u) else d
+    l_r = min(d_eff + oversample, d_u) if d_eff < d_u else 0
+    kp = min(k + oversample, 2 * d_eff)
+    return d_eff, l_r, kp
+
+
+def method_matrices(seed: int, d_u: int, d: int, k: int, oversample: int = 10) -> MethodMatrices:
+    d_eff, l_r, kp = sketch_widths(d_u, d, k, oversample)
+    om_r = None
+    if l_r > 0:
+        om_r = splitmix64_normals(seed, STREAM_OMEGA_REDUCE, d_u * l_r).reshape(d_u, l_r)
+    g = splitmix64_normals(seed, STREAM_G, d_eff * d_eff).reshape(d_eff, d_eff)
+    om = splitmix64_normals(seed, STREAM_OMEGA, 2 * d_eff * kp).reshape(2 * d_eff, kp)
+    return MethodMatrices(om_r, g, om)
+
+
+# ---------------------------------------------------------------------------
+# Planted-partition ABG generator
+# ---------------------------------------------------------------------------
+@dataclass
+class ABG:
+    n_u: int
+    n_v: int
+    edge_u: np.ndarray          # int32 [E]
+    edge_v: np.ndarray          # int32 [E]
+    x_u: np.ndarray             # float32 [n_u, d_u]
+    labels_u: np.ndarray        # int32 planted cluster of each u
+    labels_v: np.ndarray        # int32 planted cluster of each v
+    edge_w: np.ndarray | None = None  # float32 [E] or None (unweighted)
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_edges(self) -> int:
+        return int(self.edge_u.shape[0])
+
+    @property
+    def d_u(self) -> int:
+        return int(self.x_u.shape[1])
+
+
+@dataclass(frozen=True)
+class JobShape:
+    """One clustering job: graph recipe plus method parameters."""
+
+    name: str
+    n_u: int
+    n_v: int
+    n_edges: int
+    k: int
+    zipf_a: float
+    d_u: int
+    d: int              # reduced width; 0 => no reduction
+    gamma: int
+    alpha: float = 0.5
+    q: int = 20
+    oversample: int = 10
+    t_f: int = 5
+    t_g: int = 20
+    sigma: float = 1.5
+    in_out_ratio: float = 8.0
+    max_degree: int | None = None
+
+
+CONFIGS: dict[str, JobShape] = {
+    # Plain method at CPU scale: 2,000 x 3,000, 20,000 edges, k = 5, 5 hops.
+    "cpu_scale": JobShape("cpu_scale", 2_000, 3_000, 20_000, k=5, zipf_a=2.1,
+                          d_u=64, d=0, gamma=5),
+    # Mid-size FP32 GPU path: 200k x 400k, 4M edges, k = 20, 10 hops,
+    # 256 attribute columns reduced to 64.
+    "mid_fp32": JobShape("mid_fp32", 200_000, 400_000, 4_000_000, k=20, zipf_a=2.0,
+                         d_u=256, d=64, gamma=10),
+    # Large graph: 5M x 10M, 150M edges, k = 100, 512 attributes -> 64.
+    "large": JobShape("large", 5_000_000, 10_000_000, 150_000_000, k=100, zipf_a=1.9,
+                      d_u=512, d=64, gamma=10, max_degree=100_000),
+}
+
+
+def _zipf_weights(rng: np.random.Generator, a: float, n: int) -> np.ndarray:
+    return rng.zipf(a, size=n).astype(np.float64)
+
+
+def _cap_weights(theta: np.ndarray, n_edges: int, max_degree: float) -> np.ndarray:
+    """Clip weights so that no node's expected degree n_edges*theta/sum(theta)
+    exceeds max_degree (fixed point of the clip, a few rounds suffice)."""
+    t = theta.copy()
+    for _ in range(50):
+        cap = max_degree * t.sum() / n_edges
+        if t.max() <= cap * (1 + 1e-12):
+            break
+        t = np.minimum(t, cap)
+    return t
+
+
+def planted_abg(n_u: int, n_v: int, n_edges: int, k: int, d_u: int, *,
+                zipf_a: float = 2.0, sigma: float = 1.5, in_out_ratio: float = 8.0,
+                max_degree: int | None = None, seed: int = 0,
+                weighted: bool = False) -> ABG:
+    """Degree-corrected bipartite SBM with k equal planted clusters.
+
+    * Planted labels: c_u = i mod k and c_v = j mod k under a seeded shuffle.
+    * Degree weights theta ~ Zipf(zipf_a), clipped so the largest expected
+      degree is max_degree (default: a quarter of the other side, at most 1e5).
+    * Each edge draws u with probability proportional to theta_u, then v's
+      cluster (same as u's with probability r/(r + k - 1), r = in_out_ratio,
+      else uniform over the other k - 1 clusters, so p_in/p_out = r), then v
+      proportional to theta_v inside that cluster.  The first n_edges distinct
+      (u, v) pairs are kept, in draw order; isolated nodes may remain.
+    * Attributes: X_u = mu_{c_u} + sigma * eps with mu_c ~ N(0, I), stored
+      float32.
+    * weighted=True attaches log-normal edge weights (for weighted-path tests).
+    """
+    if k < 1 or n_u < 1 or n_v < 1:
+        raise ValueError("bad sizes")
+    if n_edges > n_u * n_v:
+        raise ValueError("more edges than vertex pairs")
+    rng = np.random.default_rng(seed)
+    cu = (rng.permutation(n_u) % k).astype(np.int32)
+    cv = (rng.permutation(n_v) % k).astype(np.int32)
+
+    th_u = _zipf_weights(rng, zipf_a, n_u)
+    th_v = _zipf_weights(rng, zipf_a, n_v)
+    mdu = max_degree if max_degree is not None else min(max(n_v // 4, 1), 100_000)
+    mdv = max_degree if max_degree is not None else min(max(n_u // 4, 1), 100_000)
+    th_u = _cap_weights(th_u, n_edges, mdu)
+    th_v = _cap_weights(th_v, n_edges, mdv)
+
+    cdf_u = np.cumsum(th_u)
+    cdf_u /= cdf_u[-1]
+    # V nodes grouped by cluster for within-cluster sampling.
+    order_v = np.argsort(cv, kind="stable")
+    cum_v = np.cumsum(th_v[order_v])
+    starts = np.searchsorted(cv[order_v], np.arange(k), side="left")
+    ends = np.searchsorted(cv[order_v], np.arange(k), side="right")
+    lo = np.where(starts > 0, cum_v[np.maximum(starts - 1, 0)], 0.0)
+    hi = cum_v[np.maximum(ends - 1, 0)]
+    hi = np.where(ends > starts, hi, lo)
+
+    p_same = in_out_ratio / (in_out_ratio + k - 1) if k > 1 else 1.0
+    keys_kept = np.empty(0, dtype=np.int64)
+    need = n_edges
+    chunks = []
+    seen = None
+    batch = max(int(n_edges * 1.3), 1024)
+    for _ in range(1000):
+        if need <= 0:
+            break
+        uu = np.searchsorted(cdf_u, rng.random(batch), side="right")
+        uu = np.minimum(uu, n_u - 1)
+        same = rng.random(batch) < p_same
+        if k > 1:
+            off = rng.integers(1, k, size=batch)
+            cl = np.where(same, cu[uu], (cu[uu] + off) % k)
+        else:
+            cl = np.zeros(batch, dtype=np.int64)
+        empty = ends[cl] <= starts[cl]
+        tgt = lo[cl] + rng.random(batch) * (hi[cl] - lo[cl])
+        pos = np.searchsorted(cum_v, tgt, side="right")
+        pos = np.clip(pos, starts[cl], np.maximum(ends[cl] - 1, starts[cl]))
+        vv = order_v[np.minimum(pos, n_v - 1)]
+        keep = ~empty
+        key = uu[keep].astype(np.int64) * n_v + vv[keep].astype(np.int64)
+        # distinct within the batch, first occurrence order
+        _, first = np.unique(key, return_index=True)
+        key = key[np.sort(first)]
+        if seen is not None:
+            key = key[~np.isin(key, seen)]
+        take = key[:need]
+        chunks.append(take)
+        seen = take if seen is None else np.concatenate([seen, take])
+        need -= take.shape[0]
+    if need > 0:
+        raise RuntimeError("could not draw enough distinct edges")
+    keys_kept = np.concatenate(chunks)
+    eu = (keys_kept // n_v).astype(np.int32)
+    ev = (keys_kept % n_v).astype(np.int32)
+
+    mu = rng.standard_normal((k, d_u))
+    x = mu[cu] + sigma * rng.standard_normal((n_u, d_u))
+    w = None
+    if weighted:
+        w = rng.lognormal(0.0, 0.5, size=eu.shape[0]).astype(np.float32)
+    return ABG(n_u, n_v, eu, ev, x.astype(np.float32), cu, cv, w,
+               meta=dict(seed=seed, zipf_a=zipf_a, sigma=sigma, k=k,
+                         in_out_ratio=in_out_ratio, max_degree_u=mdu,
+                         max_degree_v=mdv))
+
+
+def config_abg(shape: JobShape, seed: int = 0) -> ABG:
+    return planted_abg(shape.n_u, shape.n_v, shape.n_edges, shape.k, shape.d_u,
+                       zipf_a=shape.zipf_a, sigma=shape.sigma,
+                       in_out_ratio=shape.in_out_ratio,
+                       max_degree=shape.max_degree, seed=seed)
