@@ -1,0 +1,186 @@
+#!/usr/bin/env python
+"""Throughput of TPO clustering on one MI355X.
+
+One step = one whole clustering job (ingest -> attribute reduction ->
+propagation -> random features -> RandomizedSVD -> ONMF -> NCI -> objective)
+through tpo_execute on inputs already resident in HBM.  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--config mid_fp32] [--cpu-baseline on|off]
+
+Only one GPU is used: --gpus N with N > 1 exits with a message.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "GEdge-hop/s + clusterings/s vs plain FP32 GPU; p50/p99 job latency"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def spmm_u_bytes(n, m, e, d, has_vals):
+    """Algorithmic HBM bytes of one U-side SpMM launch (rows of B):
+    column ids + row pointers + each gathered T row once + X' rows read +
+    output rows written + the per-row scale (+ values when weighted)."""
+    return 4 * e + 4 * (n + 1) + 4 * m * d + 4 * n * d + 4 * n * d + 4 * n + (4 * e if has_vals else 0)
+
+
+def spmm_v_bytes(n, m, e, d, has_vals):
+    """Algorithmic HBM bytes of one V-side SpMM launch (rows of B^T)."""
+    return 4 * e + 4 * (m + 1) + 4 * n * d + 4 * m * d + 4 * m + (4 * e if has_vals else 0)
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="mid_fp32")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cpu-baseline", default="on", choices=["on", "off"])
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(independent jobs shard by job across GPUs; see the design notes)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import abg_synth as synth
+    import paper_2405_11922_amd as tpo
+
+    tpo.load_library()
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    shape = synth.CONFIGS[args.config]
+    t0 = time.time()
+    abg = synth.config_abg(shape, seed=args.seed)
+    log(f"[bench] generated {args.config}: n_u={abg.n_u} n_v={abg.n_v} E={abg.n_edges} "
+        f"d_u={abg.d_u} in {time.time() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    eu = torch.from_numpy(abg.edge_u).to(dev)
+    ev = torch.from_numpy(abg.edge_v).to(dev)
+    x = torch.from_numpy(abg.x_u).to(dev)
+    kw = dict(k=shape.k, alpha=shape.alpha, gamma=shape.gamma, d=shape.d, q=shape.q,
+              oversample=shape.oversample, t_f=shape.t_f, t_g=shape.t_g, seed=args.seed)
+    plan = tpo.Plan.create(abg.n_u, abg.n_v, abg.n_edges, abg.d_u, device=dev, timing=False, **kw)
+    plan_t = tpo.Plan.create(abg.n_u, abg.n_v, abg.n_edges, abg.d_u, device=dev, timing=True, **kw)
+    labels = torch.empty(abg.n_u, dtype=torch.int32, device=dev)
+    emb = torch.empty(abg.n_u, shape.k, dtype=torch.float32, device=dev)
+    d_eff, l_r, kp = tpo.tpo_plan_dims(plan.handle)
+
+    for _ in range(args.warmup):
+        tpo.tpo_execute(plan.handle, eu, ev, x, plan.workspace, labels, emb)
+    torch.cuda.synchronize()
+    step_ms = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        s0 = time.perf_counter()
+        obj = tpo.tpo_execute(plan.handle, eu, ev, x, plan.workspace, labels, emb)
+        step_ms.append((time.perf_counter() - s0) * 1e3)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_per_step = elapsed * 1e3 / args.steps
+    log(f"[bench] {args.steps} steps in {elapsed:.3f}s ({ms_per_step:.3f} ms/step)")
+
+    # stage breakdown and SpMM kernel timing from an instrumented plan
+    stats = []
+    for _ in range(3):
+        tpo.tpo_execute(plan_t.handle, eu, ev, x, plan_t.workspace, labels, emb)
+        stats.append(tpo.tpo_plan_stats(plan_t.handle))
+    st = {key: statistics.median(s[key] for s in stats) for key in stats[0]}
+    log("[bench] stages ms: " + " ".join(f"{k[3:]}={st[k]:.3f}" for k in st if k.startswith("ms_")))
+    e_u = int(st["n_unique_edges"])
+    has_vals = e_u < abg.n_edges
+    gedge_hops = shape.gamma * e_u / (st["ms_propagate"] * 1e-3) / 1e9 if st["ms_propagate"] > 0 else None
+    u_avg = st["ms_spmm_u"] / max(st["n_spmm_u"], 1)
+    v_avg = st["ms_spmm_v"] / max(st["n_spmm_v"], 1)
+    if u_avg >= v_avg:
+        kern, per, avg = "k_spmm_rows<64,U> (Z = X' + alpha D_U^-1/2 B T)", spmm_u_bytes(
+            abg.n_u, abg.n_v, e_u, d_eff, has_vals), u_avg
+    else:
+        kern, per, avg = "k_spmm_rows<64,V> (T = D_V^-1 B^T W)", spmm_v_bytes(
+            abg.n_u, abg.n_v, e_u, d_eff, has_vals), v_avg
+    achieved = per / (avg * 1e-3) / 1e9
+    roofline = {"kernel": kern, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_launch": per, "avg_launch_ms": round(avg, 5),
+                "spmm_u_avg_ms": round(u_avg, 5), "spmm_v_avg_ms": round(v_avg, 5)}
+
+    labels_np = labels.cpu().numpy()
+    result = {
+        "metric": METRIC,
+        "value": round(args.steps / elapsed, 3),
+        "unit": "clusterings/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.config}: planted degree-corrected bipartite SBM, |U|={abg.n_u}, "
+                        f"|V|={abg.n_v}, {abg.n_edges} edges, k={shape.k}, Zipf({shape.zipf_a}) degrees, "
+                        f"d_U={abg.d_u} -> d={d_eff}, gamma={shape.gamma}, alpha={shape.alpha}, "
+                        f"q={shape.q}, T_f={shape.t_f}, T_g={shape.t_g}",
+            "n_u": abg.n_u, "n_v": abg.n_v, "n_edges": abg.n_edges, "k": shape.k, "d_u": abg.d_u,
+            "d": d_eff, "k_prime": kp, "l_r": l_r, "gamma": shape.gamma,
+        },
+        "gedge_hop_per_s": round(gedge_hops, 3) if gedge_hops else None,
+        "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 4),
+                       "p99": round(float(np.percentile(step_ms, 99)), 4)},
+        "stage_ms": {k[3:]: round(v, 4) for k, v in st.items() if k.startswith("ms_")},
+        "roofline": roofline,
+        "objective": obj[0],
+    }
+
+    if args.cpu_baseline == "on":
+        import oracle
+        from threadpoolctl import threadpool_info
+
+        mm = synth.method_matrices(args.seed, abg.d_u, shape.d, shape.k, shape.oversample)
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+        c0 = time.perf_counter()
+        ref = oracle.tpo(abg.n_u, abg.n_v, abg.edge_u, abg.edge_v, abg.x_u, k=shape.k,
+                         alpha=shape.alpha, gamma=shape.gamma, g=mm.g, omega=mm.omega,
+                         omega_r=mm.omega_reduce, d=shape.d, q=shape.q, t_f=shape.t_f,
+                         t_g=shape.t_g)
+        c_el = time.perf_counter() - c0
+        result["cpu_baseline"] = {
+            "value": round(1.0 / c_el, 5), "unit": "clusterings/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"one whole {args.config} job (the FP64 numpy/scipy oracle, {c_el:.1f} s; "
+                      "sparse products single-threaded, dense BLAS on the stated threads)",
+        }
+        result["parity"] = {
+            "labels_match_oracle": bool(oracle.labels_match_up_to_permutation(labels_np, ref.labels)),
+            "objective_rel_err": abs(obj[0] - ref.objective) / abs(ref.objective),
+        }
+        log(f"[bench] oracle {c_el:.1f}s on {threads} threads; parity {result['parity']}")
+    plan.close()
+    plan_t.close()
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

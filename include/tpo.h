@@ -1,0 +1,238 @@
+/*
+ * tpo.h - C ABI of the MI355X (gfx950) implementation of TPO, the three-phase
+ * k-clustering method for attributed bipartite graphs (ABGs) of
+ * "Effective Clustering on Large Attributed Bipartite Graphs" (KDD 2024).
+ *
+ * One call clusters the target node set U of an ABG G = (U u V, E, X_U) into
+ * k disjoint clusters (Definition 1, the k-ABGC problem): edges, attributes,
+ * k and the propagation parameters go in; cluster labels, the k-dimensional
+ * embedding and the objective of Eq. obj1 come out.
+ *
+ * Conventions for every entry point:
+ *  - Plain pointers and sizes only.  "device" pointers are HIP device
+ *    addresses on the current device; "host" pointers are ordinary memory.
+ *  - The caller owns every input, output and workspace buffer.  The library
+ *    never allocates device memory (no hipMalloc); a plan owns host metadata
+ *    only.  Inputs are read-only and not retained after a call returns.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Work is enqueued on it; tpo_execute synchronises it before returning.
+ *  - All arguments are validated before the first launch; on error nothing
+ *    is written to the outputs and tpo_plan_last_error() explains.  Distinct
+ *    plans may be used from different threads; one plan is not reentrant.
+ *  - Matrices are row-major.  Sizes are elements unless stated otherwise.
+ */
+#ifndef TPO_H_
+#define TPO_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TPO_ABI_VERSION 1
+
+typedef enum tpo_status {
+  TPO_OK = 0,
+  TPO_EINVAL = 1,   /* bad shape or parameter, ABI version mismatch */
+  TPO_ERANGE = 2,   /* edge endpoint out of range, negative/non-finite weight */
+  TPO_ENOMEM = 3,   /* workspace smaller than tpo_plan_workspace_bytes() */
+  TPO_EDEVICE = 4,  /* HIP runtime error, or no gfx950 device */
+  TPO_ENUMERIC = 5  /* non-finite attributes, R'[i].r <= 0 (Eq. Ri), or a
+                       Cholesky breakdown in an orthonormalisation */
+} tpo_status;
+
+/* Shape of one clustering job: the ABG model of Section 2.1. */
+typedef struct tpo_problem {
+  int32_t abi_version; /* TPO_ABI_VERSION */
+  int32_t n_u;         /* |U| >= 1, the target node set */
+  int32_t n_v;         /* |V| >= 1 */
+  int32_t d_u;         /* attribute width of X_U, 1..4096 */
+  int64_t n_edges;     /* entries of the edge list, 0 <= n_edges < 2^31;
+                          a (u, v) pair listed twice adds its weights (B_U[i,j]
+                          is the summed weight) */
+  int32_t weighted;    /* 1: tpo_inputs.edge_w is given; 0: every w = 1 */
+  int32_t reserved;
+} tpo_problem;
+
+/* Method parameters: Table 1 of the paper plus the unstated RandomizedSVD
+ * details.  Defaults used in the paper: t_f = 5, t_g = 20. */
+typedef struct tpo_params {
+  int32_t abi_version; /* TPO_ABI_VERSION */
+  int32_t k;           /* clusters, 1 <= k <= 64 and k <= 2 d_eff */
+  double alpha;        /* balance coefficient of Eq. Z-obj, 0 <= alpha < 1 */
+  int32_t gamma;       /* propagation hops of Eq. PX, 0..1000 */
+  int32_t d;           /* reduced attribute width of Section 3.2.1; 0 or
+                          d >= d_u disables the reduction (d_eff = d_u) */
+  int32_t q;           /* power iterations of both randomized SVDs, 0..100 */
+  int32_t oversample;  /* p: sketch width k' = min(k + p, 2 d_eff) for
+                          RandomizedSVD(R, k), l_r = min(d + p, d_u) for the
+                          reduction; 0..64 */
+  int32_t t_f;         /* ONMF rounds (Algorithm 2), 0..1000 */
+  int32_t t_g;         /* NCI rounds (Algorithm 3), 0..1000 */
+  int32_t flags;       /* TPO_FLAG_* */
+  uint64_t seed;       /* seeds the Gaussian matrices not given below */
+  /* Optional host matrices (row-major float64).  NULL: drawn from `seed`
+   * with the library's SplitMix64 + Box-Muller generator, streams 0, 1, 2
+   * (see tpo_draw_normals). */
+  const double* omega_reduce; /* d_u x l_r sketch of the reduction */
+  const double* g;            /* d_eff x d_eff matrix G of Algorithm 1 */
+  const double* omega;        /* 2 d_eff x k' sketch of RandomizedSVD(R, k) */
+} tpo_params;
+
+#define TPO_FLAG_TIMING 1 /* record per-stage device times (tpo_plan_stats) */
+
+/* Inputs of one job (device memory unless stated). */
+typedef struct tpo_inputs {
+  const int32_t* edge_u; /* [n_edges] endpoint in U, 0 <= u < n_u */
+  const int32_t* edge_v; /* [n_edges] endpoint in V, 0 <= v < n_v */
+  const float* edge_w;   /* [n_edges] weights >= 0, or NULL when unweighted */
+  const float* x_u;      /* X_U: n_u rows of ld_x floats, first d_u used */
+  int64_t ld_x;          /* row stride of x_u in elements, >= d_u */
+} tpo_inputs;
+
+/* Outputs of one job. */
+typedef struct tpo_outputs {
+  int32_t* labels;    /* device [n_u]: cluster of each u, in 0..k-1 */
+  float* embedding;   /* device [n_u x k] row-major: Upsilon of Algorithm 2,
+                         or NULL */
+  double* objective;  /* host [2] or NULL: obj1 of Eq. obj1 with
+                         s(u_i,u_j) ~ R[i].R[j], and Tr(Y^T R R^T Y) */
+} tpo_outputs;
+
+/* Per-stage device milliseconds of the last tpo_execute with TPO_FLAG_TIMING. */
+typedef struct tpo_stats {
+  double ms_ingest, ms_reduce, ms_propagate, ms_features, ms_embed, ms_onmf,
+      ms_nci, ms_objective, ms_total;
+  int64_t n_unique_edges; /* distinct (u, v) pairs after summing duplicates */
+  int32_t guard_hits;     /* ONMF guard applications (zero denominators,
+                             negative ratios) */
+  int32_t isolated_u, isolated_v;
+  /* Propagation SpMM row kernels (hub-chunk finalisation excluded), summed
+   * over the first min(gamma, 64) hops: V side (T = D_V^-1 B^T W) and U side
+   * (Z = X' + alpha D_U^-1/2 B T), milliseconds and launch counts. */
+  double ms_spmm_v, ms_spmm_u;
+  int32_t n_spmm_v, n_spmm_u;
+} tpo_stats;
+
+typedef struct tpo_plan tpo_plan;
+
+/* Validate the job shape and parameters and build a plan (host metadata only:
+ * sizes, workspace layout, the Gaussian matrices).  The plan keeps copies of
+ * the optional matrices.  Errors: TPO_EINVAL. */
+tpo_status tpo_plan_create(const tpo_problem* problem, const tpo_params* params,
+                           tpo_plan** out_plan);
+
+/* Bytes of device workspace tpo_execute and the stage calls need (256-byte
+ * alignment required for the workspace base). */
+tpo_status tpo_plan_workspace_bytes(const tpo_plan* plan, size_t* out_bytes);
+
+/* Run the whole method (Section 3: optional attribute reduction, Algorithms
+ * 1, 2 and 3, then Eq. obj1) on `stream`, then synchronise it.
+ * `workspace` is device memory of at least tpo_plan_workspace_bytes(); its
+ * contents on entry do not matter and on return hold the intermediates
+ * described by tpo_plan_buffer.  Errors: TPO_EINVAL (NULL pointers),
+ * TPO_ENOMEM, TPO_ERANGE (found on the device; outputs then unspecified),
+ * TPO_ENUMERIC, TPO_EDEVICE. */
+tpo_status tpo_execute(tpo_plan* plan, const tpo_inputs* in, void* workspace,
+                       size_t workspace_bytes, void* stream,
+                       const tpo_outputs* out);
+
+void tpo_plan_destroy(tpo_plan* plan);
+const char* tpo_status_string(tpo_status status);
+const char* tpo_plan_last_error(const tpo_plan* plan);
+tpo_status tpo_plan_stats(const tpo_plan* plan, tpo_stats* out);
+
+/* The sizes the plan derived: d_eff, the reduction sketch width l_r (0 when
+ * no reduction), the embedding sketch width k'. */
+tpo_status tpo_plan_dims(const tpo_plan* plan, int32_t* d_eff, int32_t* l_r,
+                         int32_t* k_prime);
+
+/* ---- Stage entry points -------------------------------------------------
+ * tpo_execute is exactly these calls in this order.  Each works on the
+ * buffers of `workspace` named by tpo_plan_buffer, so a caller can read an
+ * intermediate after a stage, or overwrite a stage's input buffer before
+ * calling it.  They enqueue on `stream` and do not synchronise (except
+ * tpo_stage_objective, which returns host values). */
+
+/* Section 2.1: CSR of B_U (rows U) and of its transpose (rows V) with
+ * duplicates summed and columns ascending, weighted degrees D_U, D_V and the
+ * scale vectors of the propagation.  Reads in->edge_*. */
+tpo_status tpo_stage_ingest(tpo_plan* plan, const tpo_inputs* in, void* workspace,
+                            size_t workspace_bytes, void* stream);
+/* Section 3.2.1, Eq. Xd: X' = X Psi_d (top-d right singular vectors of X by
+ * randomized subspace iteration on X^T X), or X' = X when d_eff = d_u.
+ * Reads in->x_u. */
+tpo_status tpo_stage_reduce(tpo_plan* plan, const tpo_inputs* in, void* workspace,
+                            size_t workspace_bytes, void* stream);
+/* Algorithm 1 lines 1-4, Eq. PX: Z = (1-alpha) sum_{r<=gamma} alpha^r
+ * (L L^T)^r X' by gamma hops of two CSR SpMMs. */
+tpo_status tpo_stage_propagate(tpo_plan* plan, const tpo_inputs* in, void* workspace,
+                               size_t workspace_bytes, void* stream);
+/* Algorithm 1 lines 5-9, Eqs. Z, R-prime, Ri: R from Z and Q = QR(G). */
+tpo_status tpo_stage_features(tpo_plan* plan, void* workspace, size_t workspace_bytes,
+                              void* stream);
+/* Algorithm 2 line 1 and Eq. init-HY: RandomizedSVD(R, k) -> Gamma, Sigma,
+ * Psi (column sign convention: positive column sums of Gamma). */
+tpo_status tpo_stage_embed(tpo_plan* plan, void* workspace, size_t workspace_bytes,
+                           void* stream);
+/* Algorithm 2 lines 2-5, Eqs. update-Q and update-Y: Upsilon, H. */
+tpo_status tpo_stage_onmf(tpo_plan* plan, void* workspace, size_t workspace_bytes,
+                          void* stream);
+/* Algorithm 3: labels from Upsilon (device [n_u], may be the workspace's own
+ * label buffer when `labels` is NULL). */
+tpo_status tpo_stage_nci(tpo_plan* plan, void* workspace, size_t workspace_bytes,
+                         void* stream, int32_t* labels);
+/* Eq. obj1 and the trace form for the labels in the workspace; synchronises
+ * `stream` and writes objective[0..1] (host). */
+tpo_status tpo_stage_objective(tpo_plan* plan, void* workspace, size_t workspace_bytes,
+                               void* stream, double* objective);
+
+/* Buffers of the workspace, for stage-by-stage inspection. */
+typedef enum tpo_buffer_id {
+  TPO_BUF_ROWPTR_U = 0, /* int32 [n_u + 1]  CSR of B_U */
+  TPO_BUF_COL_U = 1,    /* int32 [n_edges]  first n_unique entries valid */
+  TPO_BUF_VAL_U = 2,    /* float [n_edges]  summed weights (valid when the
+                           input is weighted or has duplicates) */
+  TPO_BUF_ROWPTR_V = 3, /* int32 [n_v + 1]  CSR of B_U^T */
+  TPO_BUF_COL_V = 4,
+  TPO_BUF_VAL_V = 5,
+  TPO_BUF_DEG_U = 6,    /* float [n_u] D_U */
+  TPO_BUF_DEG_V = 7,    /* float [n_v] D_V */
+  TPO_BUF_XPRIME = 8,   /* float [n_u x d_eff] X' (reduction on) */
+  TPO_BUF_PSI_D = 9,    /* double [d_u x d_eff] Psi_d (reduction on) */
+  TPO_BUF_Z = 10,       /* float [n_u x d_eff] Z of Eq. PX */
+  TPO_BUF_Q = 11,       /* double [d_eff x d_eff] Q of Algorithm 1 */
+  TPO_BUF_R = 12,       /* float [n_u x 2 d_eff] R of Eq. Ri */
+  TPO_BUF_GAMMA = 13,   /* float [n_u x k] Gamma */
+  TPO_BUF_SIGMA = 14,   /* double [k] */
+  TPO_BUF_PSI = 15,     /* double [2 d_eff x k] */
+  TPO_BUF_UPSILON = 16, /* float [n_u x k] */
+  TPO_BUF_H = 17,       /* double [2 d_eff x k] */
+  TPO_BUF_LABELS = 18,  /* int32 [n_u] */
+  TPO_BUF_COUNT
+} tpo_buffer_id;
+
+#define TPO_DTYPE_I32 1
+#define TPO_DTYPE_F32 2
+#define TPO_DTYPE_F64 3
+
+/* Device address (inside `workspace`), shape and dtype of buffer `which`. */
+tpo_status tpo_plan_buffer(const tpo_plan* plan, void* workspace, int32_t which,
+                           void** ptr, int64_t* rows, int64_t* cols,
+                           int32_t* dtype);
+
+/* The library's Gaussian generator (host): SplitMix64 (Steele, Lea and Flood
+ * 2014) from state seed ^ (0x632BE59BD9B4E019 * (stream + 1)), pairs of
+ * outputs mapped to 53-bit uniforms on (0, 1] and to two normals by the
+ * Box-Muller transform.  Writes `count` doubles to host memory `out`. */
+tpo_status tpo_draw_normals(uint64_t seed, int32_t stream, int64_t count, double* out);
+
+int32_t tpo_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TPO_H_ */

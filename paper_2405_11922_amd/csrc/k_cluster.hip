@@ -1,0 +1,421 @@
+// Greedy orthogonal NMF (Algorithm 2 lines 2-5), NCI generation (Algorithm 3)
+// and the k-ABGC objective (Eq. obj1).
+//
+// Row passes stream R (n x 2d) once per ONMF round: each row's new Upsilon
+// entries depend only on that row, R H and two k x k matrices, and the same
+// pass accumulates R^T Upsilon and Upsilon^T Upsilon for the next round's H
+// update (Eq. update-Q).  Sums grouped by cluster label (NCI's Phi = Ups^T Y
+// and the cluster sums of R in the objective) use 64-bit fixed point so that
+// their result does not depend on the order of the atomic additions.
+#include "blk_linalg.hpp"
+#include "dev_common.hpp"
+#include "tpo_internal.hpp"
+
+namespace tpo {
+
+constexpr int kTR = 32;  // rows per LDS tile in the row passes
+
+enum RowPassMode { kProject = 0, kOnmf = 1 };
+
+// MODE kProject: O = R S (Gamma), written to out and out2 (Upsilon = Gamma).
+// MODE kOnmf:    P = R H, Q = U A with A = U^T R H,
+//                O = U * sqrt(P / Q)  (Eq. update-Y; zero denominator keeps
+//                U, negative ratio gives 0), written in place of U.
+// Both accumulate per workgroup, in FP64 across tiles, the entries of R^T O
+// (2d x k) followed by O^T O (k x k).
+template <int MODE, int NE>
+__global__ void __launch_bounds__(256)
+k_rowpass(const float* __restrict__ R, int64_t n, int twod, int k, const float* __restrict__ Sm,
+          const float* __restrict__ A32, float* __restrict__ U, float* __restrict__ out, float* __restrict__ out2,
+          int rows_per_block, double* __restrict__ part, DevStatus* __restrict__ st) {
+  extern __shared__ float sm[];
+  float* Ss = sm;                          // twod x k
+  float* As = Ss + twod * k;               // k x k
+  float* Rt = As + k * k;                  // kTR x twod
+  float* Ut = Rt + kTR * twod;             // kTR x k
+  float* Ot = Ut + kTR * k;                // kTR x k
+  const int tid = threadIdx.x;
+  for (int e = tid; e < twod * k; e += 256) Ss[e] = Sm[e];
+  if (MODE == kOnmf)
+    for (int e = tid; e < k * k; e += 256) As[e] = A32[e];
+  double acc[NE];
+#pragma unroll
+  for (int i = 0; i < NE; ++i) acc[i] = 0.0;
+  const int nrt = twod * k, nkk = k * k;
+  float mx = 0.0f;
+  int hits = 0;
+  bool bad = false;
+  const int64_t rb = static_cast<int64_t>(blockIdx.x) * rows_per_block;
+  const int64_t re = min(n, rb + rows_per_block);
+  __syncthreads();
+  for (int64_t r0 = rb; r0 < re; r0 += kTR) {
+    const int nr = static_cast<int>(min(static_cast<int64_t>(kTR), re - r0));
+    for (int e = tid; e < kTR * twod; e += 256) {
+      const int rr = e / twod;
+      Rt[e] = rr < nr ? R[(r0 + rr) * twod + (e - rr * twod)] : 0.0f;
+    }
+    if (MODE == kOnmf)
+      for (int e = tid; e < kTR * k; e += 256) {
+        const int rr = e / k;
+        Ut[e] = rr < nr ? U[(r0 + rr) * k + (e - rr * k)] : 0.0f;
+      }
+    __syncthreads();
+    for (int e = tid; e < kTR * k; e += 256) {
+      const int rr = e / k, c = e - (e / k) * k;
+      float o = 0.0f;
+      if (rr < nr) {
+        float pv = 0.0f;
+        for (int j = 0; j < twod; ++j) pv = fmaf(Rt[rr * twod + j], Ss[j * k + c], pv);
+        if (MODE == kProject) {
+          o = pv;
+        } else {
+          float qv = 0.0f;
+          for (int t = 0; t < k; ++t) qv = fmaf(Ut[rr * k + t], As[t * k + c], qv);
+          const float u = Ut[rr * k + c];
+          if (qv == 0.0f) {
+            o = u;
+            ++hits;
+          } else {
+            const float ratio = pv / qv;
+            if (ratio < 0.0f) {
+              o = 0.0f;
+              ++hits;
+            } else {
+              o = u * sqrtf(ratio);
+            }
+          }
+        }
+        if (!isfinite(o)) bad = true;
+        mx = fmaxf(mx, fabsf(o));
+        const int64_t gi = (r0 + rr) * k + c;
+        if (MODE == kProject) {
+          out[gi] = o;
+          out2[gi] = o;
+        } else {
+          U[gi] = o;
+        }
+      }
+      Ot[e] = o;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+      const int e = tid + 256 * i;
+      float s = 0.0f;
+      if (e < nrt) {
+        const int j = e / k, c = e - (e / k) * k;
+        for (int rr = 0; rr < kTR; ++rr) s = fmaf(Rt[rr * twod + j], Ot[rr * k + c], s);
+      } else if (e < nrt + nkk) {
+        const int a = (e - nrt) / k, b = (e - nrt) - ((e - nrt) / k) * k;
+        for (int rr = 0; rr < kTR; ++rr) s = fmaf(Ot[rr * k + a], Ot[rr * k + b], s);
+      }
+      acc[i] += static_cast<double>(s);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < NE; ++i) {
+    const int e = tid + 256 * i;
+    if (e < nrt + nkk) part[static_cast<int64_t>(blockIdx.x) * (nrt + nkk) + e] = acc[i];
+  }
+  if (hits) atomicAdd(&st->guard_hits, hits);
+  if (bad) atomicOr(&st->err_bits, 32);
+  mx = wave_max(mx);
+  if ((tid & 63) == 0) atomic_max_nonneg(&st->maxabs_ups_bits, mx);
+}
+
+__global__ void k_reduce_parts(const double* __restrict__ part, int nparts, int len, double* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= len) return;
+  double s = 0.0;
+  for (int b = 0; b < nparts; ++b) s += part[static_cast<int64_t>(b) * len + j];
+  out[j] = s;
+}
+
+// H update (Eq. update-Q) and A = (R^T U)^T H_new for the U update.
+// H_new is formed in LDS first (every entry reads the old row of H).
+__global__ void __launch_bounds__(1024)
+k_onmf_small(const double* __restrict__ rtu_utu, int twod, int k, double* __restrict__ H, float* __restrict__ H32,
+             float* __restrict__ A32, DevStatus* __restrict__ st) {
+  extern __shared__ double hn[];  // twod x k
+  const double* RtU = rtu_utu;
+  const double* UtU = rtu_utu + twod * k;
+  int hits = 0;
+  for (int idx = threadIdx.x; idx < twod * k; idx += blockDim.x) {
+    const int j = idx / k, c = idx % k;
+    double den = 0.0;
+    for (int t = 0; t < k; ++t) den = fma(H[j * k + t], UtU[t * k + c], den);
+    const double h = H[idx];
+    if (den == 0.0) {
+      hn[idx] = h;
+      ++hits;
+    } else {
+      hn[idx] = h * (RtU[idx] / den);
+    }
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < twod * k; idx += blockDim.x) {
+    H[idx] = hn[idx];
+    H32[idx] = static_cast<float>(hn[idx]);
+  }
+  for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) {
+    const int a = idx / k, b = idx % k;
+    double s = 0.0;
+    for (int j = 0; j < twod; ++j) s = fma(RtU[j * k + a], hn[j * k + b], s);
+    A32[idx] = static_cast<float>(s);
+  }
+  if (hits) atomicAdd(&st->guard_hits, hits);
+}
+
+template <int NE>
+static void rowpass(const Plan& p, void* ws, int mode, const float* Sm, const float* A32, hipStream_t s) {
+  DevStatus* st = bufp<DevStatus>(p, ws, B_STATUS);
+  const int nb = p.rowpass_blocks;
+  const int rpb = static_cast<int>((p.n + nb - 1) / nb);
+  const size_t lds = sizeof(float) * (p.twod * p.k + p.k * p.k + kTR * p.twod + 2 * kTR * p.k);
+  if (mode == kProject)
+    hipLaunchKernelGGL((k_rowpass<kProject, NE>), dim3(nb), dim3(256), lds, s, bufp<float>(p, ws, B_R),
+                       static_cast<int64_t>(p.n), p.twod, p.k, Sm, A32, bufp<float>(p, ws, B_UPS),
+                       bufp<float>(p, ws, B_GAMMA), bufp<float>(p, ws, B_UPS), rpb,
+                       bufp<double>(p, ws, B_ONMF_PART), st);
+  else
+    hipLaunchKernelGGL((k_rowpass<kOnmf, NE>), dim3(nb), dim3(256), lds, s, bufp<float>(p, ws, B_R),
+                       static_cast<int64_t>(p.n), p.twod, p.k, Sm, A32, bufp<float>(p, ws, B_UPS), nullptr,
+                       nullptr, rpb, bufp<double>(p, ws, B_ONMF_PART), st);
+  TPO_LAUNCH_CHECK();
+}
+
+static void rowpass_any(const Plan& p, void* ws, int mode, const float* Sm, const float* A32, hipStream_t s) {
+  const int ne = (p.twod * p.k + p.k * p.k + 255) / 256;
+  if (ne <= 16)
+    rowpass<16>(p, ws, mode, Sm, A32, s);
+  else if (ne <= 48)
+    rowpass<48>(p, ws, mode, Sm, A32, s);
+  else
+    rowpass<96>(p, ws, mode, Sm, A32, s);
+}
+
+void launch_onmf(const Plan& p, void* ws, hipStream_t s) {
+  DevStatus* st = bufp<DevStatus>(p, ws, B_STATUS);
+  const int len = p.twod * p.k + p.k * p.k;
+  double* rtu = bufp<double>(p, ws, B_RTU);
+  // Gamma = R S, Upsilon = Gamma, and R^T Ups, Ups^T Ups for the first round
+  rowpass_any(p, ws, kProject, bufp<float>(p, ws, B_S32), nullptr, s);
+  for (int t = 0; t < p.par.t_f; ++t) {
+    hipLaunchKernelGGL(k_reduce_parts, dim3(ceil_div(len, 256)), dim3(256), 0, s, bufp<double>(p, ws, B_ONMF_PART),
+                       p.rowpass_blocks, len, rtu);
+    TPO_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_onmf_small, dim3(1), dim3(1024), sizeof(double) * p.twod * p.k, s, rtu, p.twod, p.k, bufp<double>(p, ws, B_H),
+                       bufp<float>(p, ws, B_H32), bufp<float>(p, ws, B_A32), st);
+    TPO_LAUNCH_CHECK();
+    rowpass_any(p, ws, kOnmf, bufp<float>(p, ws, B_H32), bufp<float>(p, ws, B_A32), s);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// NCI (Algorithm 3)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int fixed_point_shift(float maxabs, int64_t n) {
+  // |sum| <= n * maxabs * 2^S < 2^61
+  int ln = 0;
+  while ((1ll << ln) < n) ++ln;
+  int lm = 0;
+  if (maxabs > 0.0f && isfinite(maxabs)) {
+    int e;
+    frexpf(maxabs, &e);  // maxabs < 2^e
+    lm = e;
+  }
+  int sft = 60 - ln - lm;
+  if (sft > 62) sft = 62;
+  if (sft < 0) sft = 0;
+  return sft;
+}
+
+__device__ __forceinline__ long long to_fixed(float v, int sft) {
+  return static_cast<long long>(llrint(ldexp(static_cast<double>(v), sft)));
+}
+
+// One round: scores = U Phi (FP64), l* = first argmax, labels written; when
+// `accumulate`, the fixed-point sums of U rows per label and the label
+// counts are added to acc_dst / cnt_dst.  Phi comes from the previous round's
+// sums (Phi[t][l] = sum_{i in C_l} U[i][t] / sqrt(|C_l|)) or is the identity.
+__global__ void __launch_bounds__(256)
+k_nci_round(const float* __restrict__ U, int64_t n, int k, int identity, const long long* __restrict__ acc_src,
+            const int* __restrict__ cnt_src, long long* __restrict__ acc_dst, int* __restrict__ cnt_dst,
+            long long* __restrict__ acc_zero, int* __restrict__ cnt_zero, int accumulate,
+            int32_t* __restrict__ labels, int rows_per_block, const DevStatus* __restrict__ st) {
+  extern __shared__ char smem_raw[];
+  double* phi = reinterpret_cast<double*>(smem_raw);                 // k x k
+  long long* accl = reinterpret_cast<long long*>(phi + k * k);        // k x k
+  int* cntl = reinterpret_cast<int*>(accl + k * k);                   // k
+  float* ut = reinterpret_cast<float*>(cntl + 64);                    // 4 x 64 x k
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int sft = fixed_point_shift(__uint_as_float(st->maxabs_ups_bits), n);
+  const double inv_scale = ldexp(1.0, -sft);
+  for (int e = tid; e < k * k; e += 256) {
+    const int t = e / k, l = e % k;
+    double v;
+    if (identity) {
+      v = (t == l) ? 1.0 : 0.0;
+    } else {
+      const int c = cnt_src[l];
+      v = c > 0 ? static_cast<double>(acc_src[l * k + t]) * inv_scale / sqrt(static_cast<double>(c)) : 0.0;
+    }
+    phi[e] = v;
+    accl[e] = 0;
+  }
+  if (tid < 64) cntl[tid] = 0;
+  if (blockIdx.x == 0 && acc_zero) {
+    for (int e = tid; e < k * k; e += 256) acc_zero[e] = 0;
+    if (tid < k) cnt_zero[tid] = 0;
+  }
+  __syncthreads();
+  float* myut = ut + w * 64 * k;
+  const int64_t rb = static_cast<int64_t>(blockIdx.x) * rows_per_block;
+  const int64_t re = min(n, rb + rows_per_block);
+  for (int64_t b0 = rb + static_cast<int64_t>(w) * 64; b0 < re; b0 += 256) {
+    const int nr = static_cast<int>(min(static_cast<int64_t>(64), re - b0));
+    for (int e = lane; e < nr * k; e += 64) myut[e] = U[b0 * k + e];
+    wave_sync();
+    int best = 0;
+    if (lane < nr) {
+      double bestv = 0.0;
+      for (int l = 0; l < k; ++l) {
+        double sc = 0.0;
+        for (int t = 0; t < k; ++t) sc = fma(static_cast<double>(myut[lane * k + t]), phi[t * k + l], sc);
+        if (l == 0 || sc > bestv) {
+          bestv = sc;
+          best = l;
+        }
+      }
+      labels[b0 + lane] = best;
+    }
+    if (accumulate) {
+      for (int rr = 0; rr < nr; ++rr) {
+        const int lab = __shfl(best, rr, 64);
+        for (int t = lane; t < k; t += 64) atomicAdd(reinterpret_cast<unsigned long long*>(&accl[lab * k + t]),
+                                                     static_cast<unsigned long long>(to_fixed(myut[rr * k + t], sft)));
+        if (lane == 0) atomicAdd(&cntl[lab], 1);
+      }
+    }
+    wave_sync();
+  }
+  __syncthreads();
+  if (accumulate) {
+    for (int e = tid; e < k * k; e += 256)
+      if (accl[e] != 0)
+        atomicAdd(reinterpret_cast<unsigned long long*>(&acc_dst[e]), static_cast<unsigned long long>(accl[e]));
+    if (tid < k && cntl[tid] != 0) atomicAdd(&cnt_dst[tid], cntl[tid]);
+  }
+}
+
+__global__ void k_zero_ll(long long* __restrict__ a, int na, int* __restrict__ b, int nb) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < na) a[i] = 0;
+  if (i < nb) b[i] = 0;
+}
+
+void launch_nci(const Plan& p, void* ws, hipStream_t s) {
+  DevStatus* st = bufp<DevStatus>(p, ws, B_STATUS);
+  const int k = p.k;
+  long long* acc = bufp<long long>(p, ws, B_NCI_ACC);
+  int* cnt = bufp<int>(p, ws, B_NCI_CNT);
+  const int nb = p.rowpass_blocks;
+  const int rpb = static_cast<int>((p.n + nb - 1) / nb);
+  const size_t lds = sizeof(double) * k * k + sizeof(long long) * k * k + sizeof(int) * 64 + sizeof(float) * 4 * 64 * k;
+  hipLaunchKernelGGL(k_zero_ll, dim3(ceil_div(3 * k * k, 256)), dim3(256), 0, s, acc, 3 * k * k, cnt, 3 * k);
+  TPO_LAUNCH_CHECK();
+  const float* U = bufp<float>(p, ws, B_UPS);
+  int32_t* labels = bufp<int32_t>(p, ws, B_LABELS);
+  if (p.par.t_g == 0) {
+    hipLaunchKernelGGL(k_nci_round, dim3(nb), dim3(256), lds, s, U, static_cast<int64_t>(p.n), k, 1, nullptr,
+                       nullptr, acc, cnt, nullptr, nullptr, 0, labels, rpb, st);
+    TPO_LAUNCH_CHECK();
+    return;
+  }
+  for (int t = 1; t <= p.par.t_g; ++t) {
+    const int src = (t - 1) % 3, dst = t % 3, zer = (t + 1) % 3;
+    hipLaunchKernelGGL(k_nci_round, dim3(nb), dim3(256), lds, s, U, static_cast<int64_t>(p.n), k, t == 1 ? 1 : 0,
+                       acc + src * k * k, cnt + src * k, acc + dst * k * k, cnt + dst * k, acc + zer * k * k,
+                       cnt + zer * k, t < p.par.t_g ? 1 : 0, labels, rpb, st);
+    TPO_LAUNCH_CHECK();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Objective (Eq. obj1 with s ~ R R^T): cluster sums c_l of R rows in fixed
+// point, then obj1 = sum_l c_l.(tot - c_l)/|C_l| and sum_l ||c_l||^2/|C_l|.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_obj_accum(const float* __restrict__ R, int64_t n, int twod, const int32_t* __restrict__ labels, int k,
+            long long* __restrict__ acc, int* __restrict__ cnt, int rows_per_block, const DevStatus* __restrict__ st) {
+  extern __shared__ char smem_raw[];
+  long long* accl = reinterpret_cast<long long*>(smem_raw);  // k x twod
+  int* cntl = reinterpret_cast<int*>(accl + k * twod);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int sft = fixed_point_shift(__uint_as_float(st->maxabs_r_bits), n);
+  for (int e = tid; e < k * twod; e += 256) accl[e] = 0;
+  if (tid < 64) cntl[tid] = 0;
+  __syncthreads();
+  const int64_t rb = static_cast<int64_t>(blockIdx.x) * rows_per_block;
+  const int64_t re = min(n, rb + rows_per_block);
+  for (int64_t r = rb + w; r < re; r += 4) {
+    const int lab = labels[r];
+    for (int j = lane; j < twod; j += 64)
+      atomicAdd(reinterpret_cast<unsigned long long*>(&accl[lab * twod + j]),
+                static_cast<unsigned long long>(to_fixed(R[r * twod + j], sft)));
+    if (lane == 0) atomicAdd(&cntl[lab], 1);
+  }
+  __syncthreads();
+  for (int e = tid; e < k * twod; e += 256)
+    if (accl[e] != 0) atomicAdd(reinterpret_cast<unsigned long long*>(&acc[e]), static_cast<unsigned long long>(accl[e]));
+  if (tid < k && cntl[tid] != 0) atomicAdd(&cnt[tid], cntl[tid]);
+}
+
+__global__ void __launch_bounds__(1024)
+k_obj_final(const long long* __restrict__ acc, const int* __restrict__ cnt, int k, int twod, int64_t n,
+            DevStatus* __restrict__ st) {
+  __shared__ double red[1024];
+  __shared__ double tot[512];
+  const int sft = fixed_point_shift(__uint_as_float(st->maxabs_r_bits), n);
+  const double inv = ldexp(1.0, -sft);
+  for (int j = threadIdx.x; j < twod; j += blockDim.x) {
+    long long s = 0;
+    for (int l = 0; l < k; ++l) s += acc[l * twod + j];
+    tot[j] = static_cast<double>(s) * inv;
+  }
+  __syncthreads();
+  double o = 0.0, t = 0.0;
+  for (int idx = threadIdx.x; idx < k * twod; idx += blockDim.x) {
+    const int l = idx / twod, j = idx % twod;
+    if (cnt[l] <= 0) continue;
+    const double c = static_cast<double>(acc[idx]) * inv;
+    o += c * (tot[j] - c) / cnt[l];
+    t += c * c / cnt[l];
+  }
+  o = blk_sum(o, red);
+  t = blk_sum(t, red);
+  if (threadIdx.x == 0) {
+    st->objective[0] = o;
+    st->objective[1] = t;
+  }
+}
+
+void launch_objective(const Plan& p, void* ws, hipStream_t s) {
+  DevStatus* st = bufp<DevStatus>(p, ws, B_STATUS);
+  long long* acc = bufp<long long>(p, ws, B_OBJ_ACC);
+  int* cnt = bufp<int>(p, ws, B_OBJ_CNT);
+  const int k = p.k, twod = p.twod;
+  hipLaunchKernelGGL(k_zero_ll, dim3(ceil_div(k * twod, 256)), dim3(256), 0, s, acc, k * twod, cnt, k);
+  TPO_LAUNCH_CHECK();
+  const int nb = p.rowpass_blocks;
+  const int rpb = static_cast<int>((p.n + nb - 1) / nb);
+  const size_t lds = sizeof(long long) * k * twod + sizeof(int) * 64;
+  hipLaunchKernelGGL(k_obj_accum, dim3(nb), dim3(256), lds, s, bufp<float>(p, ws, B_R), static_cast<int64_t>(p.n),
+                     twod, bufp<int32_t>(p, ws, B_LABELS), k, acc, cnt, rpb, st);
+  TPO_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_obj_final, dim3(1), dim3(1024), 0, s, acc, cnt, k, twod, static_cast<int64_t>(p.n), st);
+  TPO_LAUNCH_CHECK();
+}
+
+}  // namespace tpo

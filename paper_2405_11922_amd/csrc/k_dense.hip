@@ -1,0 +1,659 @@
+// Dense stages: the attribute reduction (Section 3.2.1), the random features
+// (Algorithm 1 lines 5-9) and RandomizedSVD(R, k) (Algorithm 2 line 1).
+//
+// Both randomized SVDs run the subspace iteration on a Gram matrix that is
+// formed once in FP64 (C = X^T X for the reduction, K = R^T R for the
+// embedding).  For the embedding this is the same iteration as
+// Y <- orth(R orth(R^T Y)) re-associated through K: the basis of R's column
+// space is R M L^{-T}, with M the 2d x k' right factor and L the Cholesky
+// factor of M^T K M, so no n x k' block is ever materialised; Gamma = R S is
+// formed by one final pass (k_cluster.hip).
+#include "blk_linalg.hpp"
+#include "dev_common.hpp"
+#include "tpo_internal.hpp"
+
+namespace tpo {
+
+// ---------------------------------------------------------------------------
+// FP64 Gram of a tall FP32 matrix: G = X^T X and the column sums of X.
+// Grid: (upper-triangular 64x64 tile pairs, row chunks).  Each workgroup
+// accumulates its tile over its chunk of rows in FP64 (products of FP32
+// values are exact in FP64) and writes a partial; k_gram_reduce adds the
+// partials in chunk order.
+// ---------------------------------------------------------------------------
+constexpr int kGT = 64;
+constexpr int kGSub = 32;
+
+__global__ void __launch_bounds__(256)
+k_gram_part(const float* __restrict__ X, int64_t n, int c, int64_t ldx, int ntiles, int rows_per_chunk,
+            double* __restrict__ part, double* __restrict__ colsum_part) {
+  __shared__ float As[kGSub][kGT];
+  __shared__ float Bs[kGSub][kGT];
+  __shared__ double csum[4][kGT];
+  // decode the tile pair (ti <= tj)
+  int pi = blockIdx.x, ti = 0;
+  while (pi >= ntiles - ti) {
+    pi -= ntiles - ti;
+    ++ti;
+  }
+  const int tj = ti + pi;
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int64_t r_beg = static_cast<int64_t>(blockIdx.y) * rows_per_chunk;
+  const int64_t r_end = min(n, r_beg + rows_per_chunk);
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  double cs = 0.0;
+  const bool diag = ti == tj;
+  for (int64_t r0 = r_beg; r0 < r_end; r0 += kGSub) {
+    for (int e = tid; e < kGSub * kGT; e += 256) {
+      const int rr = e / kGT, jj = e % kGT;
+      const int64_t row = r0 + rr;
+      const int ca = ti * kGT + jj, cb = tj * kGT + jj;
+      As[rr][jj] = (row < r_end && ca < c) ? X[row * ldx + ca] : 0.0f;
+      Bs[rr][jj] = (row < r_end && cb < c) ? X[row * ldx + cb] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int rr = 0; rr < kGSub; ++rr) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = static_cast<double>(As[rr][ty * 4 + a]);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = static_cast<double>(Bs[rr][tx * 4 + b]);
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
+    }
+    if (diag) {
+      for (int rr = tid >> 6; rr < kGSub; rr += 4) cs += static_cast<double>(As[rr][tid & 63]);
+    }
+    __syncthreads();
+  }
+  double* out = part + static_cast<int64_t>(blockIdx.y) * c * c;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int i = ti * kGT + ty * 4 + a;
+    if (i >= c) continue;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int j = tj * kGT + tx * 4 + b;
+      if (j < c) out[static_cast<int64_t>(i) * c + j] = acc[a][b];
+    }
+  }
+  if (diag && colsum_part) {
+    csum[tid >> 6][tid & 63] = cs;
+    __syncthreads();
+    if (tid < kGT) {
+      const double v = ((csum[0][tid] + csum[1][tid]) + csum[2][tid]) + csum[3][tid];
+      const int j = ti * kGT + tid;
+      if (j < c) colsum_part[static_cast<int64_t>(blockIdx.y) * c + j] = v;
+    }
+  }
+}
+
+__global__ void k_gram_reduce(const double* __restrict__ part, const double* __restrict__ colsum_part, int nchunks,
+                              int c, double* __restrict__ G, double* __restrict__ colsum) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx < static_cast<int64_t>(c) * c) {
+    const int i = static_cast<int>(idx / c), j = static_cast<int>(idx % c);
+    const int64_t src = (i / kGT <= j / kGT) ? static_cast<int64_t>(i) * c + j : static_cast<int64_t>(j) * c + i;
+    double s = 0.0;
+    for (int ch = 0; ch < nchunks; ++ch) s += part[static_cast<int64_t>(ch) * c * c + src];
+    G[idx] = s;
+  }
+  if (colsum && idx < c) {
+    double s = 0.0;
+    for (int ch = 0; ch < nchunks; ++ch) s += colsum_part[static_cast<int64_t>(ch) * c + idx];
+    colsum[idx] = s;
+  }
+}
+
+static void gram(const float* X, int64_t n, int c, int64_t ldx, int nchunks, double* part, double* colsum_part,
+                 double* G, double* colsum, hipStream_t s) {
+  const int ntiles = (c + kGT - 1) / kGT;
+  const int npairs = ntiles * (ntiles + 1) / 2;
+  const int rows_per_chunk = static_cast<int>((n + nchunks - 1) / nchunks);
+  hipLaunchKernelGGL(k_gram_part, dim3(npairs, nchunks), dim3(256), 0, s, X, n, c, ldx, ntiles, rows_per_chunk,
+                     part, colsum_part);
+  TPO_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_gram_reduce, dim3(ceil_div(static_cast<int64_t>(c) * c, 256)), dim3(256), 0, s, part,
+                     colsum_part, nchunks, c, G, colsum);
+  TPO_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// Multi-workgroup FP64 GEMM C = A B (row-major), 16x16 tile per workgroup.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_gemm_f64(int m, int n, int k, const double* __restrict__ A, int lda, const double* __restrict__ B, int ldb,
+           double* __restrict__ C, int ldc) {
+  __shared__ double As[16][17];
+  __shared__ double Bs[16][17];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int row = blockIdx.y * 16 + ty, col = blockIdx.x * 16 + tx;
+  double acc = 0.0;
+  for (int k0 = 0; k0 < k; k0 += 16) {
+    As[ty][tx] = (row < m && k0 + tx < k) ? A[static_cast<int64_t>(row) * lda + k0 + tx] : 0.0;
+    Bs[ty][tx] = (k0 + ty < k && col < n) ? B[static_cast<int64_t>(k0 + ty) * ldb + col] : 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 16; ++t) acc = fma(As[ty][t], Bs[t][tx], acc);
+    __syncthreads();
+  }
+  if (row < m && col < n) C[static_cast<int64_t>(row) * ldc + col] = acc;
+}
+
+static void gemm_f64(int m, int n, int k, const double* A, int lda, const double* B, int ldb, double* C, int ldc,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_gemm_f64, dim3(ceil_div(n, 16), ceil_div(m, 16)), dim3(256), 0, s, m, n, k, A, lda, B, ldb,
+                     C, ldc);
+  TPO_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// Single-workgroup kernels
+// ---------------------------------------------------------------------------
+constexpr int kSmallThreads = 1024;
+
+// In-place Cholesky QR of A (m x n); G is n x n global scratch.
+__global__ void __launch_bounds__(kSmallThreads)
+k_cholqr(double* __restrict__ A, int m, int n, int lda, double* __restrict__ G, int32_t* __restrict__ err_bits) {
+  __shared__ int flag;
+  if (!blk_cholqr(A, m, n, lda, G, n, &flag)) {
+    if (threadIdx.x == 0) atomicOr(err_bits, 16);
+  }
+}
+
+// Q of Algorithm 1 line 7 from G by Cholesky QR done twice (the unique QR
+// factor with positive diagonal of R, re-orthogonalised), plus Q^T in FP32.
+__global__ void __launch_bounds__(kSmallThreads)
+k_q_from_g(const double* __restrict__ Gm, int d, double* __restrict__ Q, double* __restrict__ scratch,
+           float* __restrict__ Qt32, int32_t* __restrict__ err_bits) {
+  __shared__ int flag;
+  blk_copy(d, d, Gm, d, Q, d);
+  bool ok = blk_cholqr(Q, d, d, d, scratch, d, &flag);
+  if (ok) ok = blk_cholqr(Q, d, d, d, scratch, d, &flag);
+  if (!ok) {
+    if (threadIdx.x == 0) atomicOr(err_bits, 16);
+    return;
+  }
+  for (int idx = threadIdx.x; idx < d * d; idx += blockDim.x) {
+    const int j = idx / d, l = idx % d;
+    Qt32[idx] = static_cast<float>(Q[l * d + j]);  // Qt[j][l] = Q[l][j]
+  }
+}
+
+// Column sign convention: flip column c of the left factor L = Y * Sm (given
+// through its column sums colsum^T Sm[:, c] and norms) and of the right vector
+// Rv[:, c] so that the sum of L's column is positive; a sum within
+// 1e-9 * sqrt(nrows) * ||L[:, c]|| of zero defers to the sign of Rv's entry of
+// largest magnitude (lowest index on ties).
+__device__ void blk_sign_convention(int rows_s, int ncol, const double* colsum, double* Sm, int lds, double* Rv,
+                                    int rows_r, int ldr, const double* norms, double nrows_sqrt, double* sh) {
+  for (int c = threadIdx.x; c < ncol; c += blockDim.x) {
+    double s = 0.0;
+    for (int i = 0; i < rows_s; ++i) s += colsum[i] * Sm[i * lds + c];
+    if (fabs(s) <= 1e-9 * nrows_sqrt * norms[c]) {
+      double best = -1.0;
+      s = 0.0;
+      for (int i = 0; i < rows_r; ++i) {
+        const double v = Rv[i * ldr + c];
+        if (fabs(v) > best) {
+          best = fabs(v);
+          s = v;
+        }
+      }
+    }
+    sh[c] = s < 0.0 ? -1.0 : 1.0;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < rows_s * ncol; idx += blockDim.x) {
+    const int i = idx / ncol, c = idx % ncol;
+    Sm[i * lds + c] *= sh[c];
+  }
+  if (Rv != Sm) {
+    for (int idx = threadIdx.x; idx < rows_r * ncol; idx += blockDim.x) {
+      const int i = idx / ncol, c = idx % ncol;
+      Rv[i * ldr + c] *= sh[c];
+    }
+  }
+  __syncthreads();
+}
+
+// Rayleigh-Ritz step of the reduction: T = M^T (C M), eigenpairs of T, the top
+// d kept: Psi_d = M V_d, sigma = sqrt(lambda); sign convention on X' = X Psi_d.
+__global__ void __launch_bounds__(kSmallThreads)
+k_reduce_rr(const double* __restrict__ M, const double* __restrict__ P, int du, int l, int d, int dp,
+            const double* __restrict__ colsum_x, int64_t n, double* __restrict__ T, double* __restrict__ V,
+            double* __restrict__ evals, double* __restrict__ psi, float* __restrict__ psi32) {
+  __shared__ double red[kSmallThreads];
+  __shared__ double sh[3 * 64 + 8 + 256];
+  __shared__ int perm[256];
+  __shared__ double ev[256];
+  __shared__ double nrm[256];
+  blk_gemm(l, l, du, M, l, true, P, l, false, T, l, 1.0, 0.0);
+  for (int idx = threadIdx.x; idx < l * l; idx += blockDim.x) {
+    const int i = idx / l, j = idx % l;
+    if (i < j) {
+      const double a = 0.5 * (T[i * l + j] + T[j * l + i]);
+      T[i * l + j] = a;
+      T[j * l + i] = a;
+    }
+  }
+  __syncthreads();
+  blk_jacobi(T, l, V, l, l, sh, red, 40);
+  blk_sort_desc(T, l, l, ev, perm);
+  // psi = M V[:, perm[:d]]
+  for (int idx = threadIdx.x; idx < du * d; idx += blockDim.x) {
+    const int i = idx / d, c = idx % d;
+    const int pc = perm[c];
+    double acc = 0.0;
+    for (int t = 0; t < l; ++t) acc = fma(M[i * l + t], V[t * l + pc], acc);
+    psi[i * d + c] = acc;
+  }
+  for (int c = threadIdx.x; c < d; c += blockDim.x) {
+    const double lam = ev[c] > 0.0 ? ev[c] : 0.0;
+    evals[c] = sqrt(lam);
+    nrm[c] = sqrt(lam);
+  }
+  __syncthreads();
+  blk_sign_convention(du, d, colsum_x, psi, d, psi, du, d, nrm, sqrt(static_cast<double>(n)), sh);
+  for (int idx = threadIdx.x; idx < du * dp; idx += blockDim.x) {
+    const int i = idx / dp, c = idx % dp;
+    psi32[idx] = c < d ? static_cast<float>(psi[i * d + c]) : 0.0f;
+  }
+}
+
+// RandomizedSVD(R, k) on K = R^T R (2d x 2d):
+//   M <- Omega;  q times: M <- orth(K M)
+//   L = chol(M^T K M);  B^T = K M L^{-T};  B B^T = U diag(lambda) U^T
+//   S = M L^{-T} U_k (Gamma = R S), sigma = sqrt(lambda_k), Psi = B^T U_k / sigma
+// then the column sign convention, H = Psi Sigma (Eq. init-HY).
+__global__ void __launch_bounds__(kSmallThreads)
+k_embed_small(const double* __restrict__ K, const double* __restrict__ Omega, int twod, int kp, int k, int q,
+              const double* __restrict__ colsum_r, int64_t n, double* __restrict__ M, double* __restrict__ P,
+              double* __restrict__ G, double* __restrict__ BBt, double* __restrict__ V, double* __restrict__ S,
+              float* __restrict__ S32, double* __restrict__ sigma, double* __restrict__ psi,
+              double* __restrict__ H, float* __restrict__ H32, int32_t* __restrict__ err_bits) {
+  __shared__ double red[kSmallThreads];
+  __shared__ double sh[3 * 64 + 8 + 256];
+  __shared__ int perm[128];
+  __shared__ double ev[128];
+  __shared__ double nrm[128];
+  __shared__ int flag;
+  blk_copy(twod, kp, Omega, kp, M, kp);
+  for (int it = 0; it < q; ++it) {
+    blk_gemm(twod, kp, twod, K, twod, false, M, kp, false, P, kp, 1.0, 0.0);
+    if (!blk_cholqr(P, twod, kp, kp, G, kp, &flag)) {
+      if (threadIdx.x == 0) atomicOr(err_bits, 16);
+      return;
+    }
+    blk_copy(twod, kp, P, kp, M, kp);
+  }
+  blk_gemm(twod, kp, twod, K, twod, false, M, kp, false, P, kp, 1.0, 0.0);       // P = K M
+  blk_gemm(kp, kp, twod, M, kp, true, P, kp, false, G, kp, 1.0, 0.0);            // G = M^T K M
+  if (!blk_chol(G, kp, kp, &flag)) {
+    if (threadIdx.x == 0) atomicOr(err_bits, 16);
+    return;
+  }
+  blk_trsm_right_lt(P, twod, kp, kp, G, kp);                                      // P = B^T
+  blk_trsm_right_lt(M, twod, kp, kp, G, kp);                                      // M = M L^-T
+  blk_gemm(kp, kp, twod, P, kp, true, P, kp, false, BBt, kp, 1.0, 0.0);          // B B^T
+  for (int idx = threadIdx.x; idx < kp * kp; idx += blockDim.x) {
+    const int i = idx / kp, j = idx % kp;
+    if (i < j) {
+      const double a = 0.5 * (BBt[i * kp + j] + BBt[j * kp + i]);
+      BBt[i * kp + j] = a;
+      BBt[j * kp + i] = a;
+    }
+  }
+  __syncthreads();
+  blk_jacobi(BBt, kp, V, kp, kp, sh, red, 40);
+  blk_sort_desc(BBt, kp, kp, ev, perm);
+  for (int c = threadIdx.x; c < k; c += blockDim.x) sigma[c] = sqrt(ev[c] > 0.0 ? ev[c] : 0.0);
+  __syncthreads();
+  // S = (M L^-T) U_k ; Psi = B^T U_k / sigma
+  for (int idx = threadIdx.x; idx < twod * k; idx += blockDim.x) {
+    const int i = idx / k, c = idx % k;
+    const int pc = perm[c];
+    double a = 0.0, b = 0.0;
+    for (int t = 0; t < kp; ++t) {
+      a = fma(M[i * kp + t], V[t * kp + pc], a);
+      b = fma(P[i * kp + t], V[t * kp + pc], b);
+    }
+    S[i * k + c] = a;
+    psi[i * k + c] = sigma[c] > 0.0 ? b / sigma[c] : 0.0;
+  }
+  __syncthreads();
+  // ||Gamma[:, c]|| = sqrt(S_c^T K S_c)
+  for (int c = threadIdx.x; c < k; c += blockDim.x) {
+    double acc = 0.0;
+    for (int i = 0; i < twod; ++i) {
+      double ki = 0.0;
+      for (int j = 0; j < twod; ++j) ki = fma(K[i * twod + j], S[j * k + c], ki);
+      acc = fma(S[i * k + c], ki, acc);
+    }
+    nrm[c] = sqrt(acc > 0.0 ? acc : 0.0);
+  }
+  __syncthreads();
+  blk_sign_convention(twod, k, colsum_r, S, k, psi, twod, k, nrm, sqrt(static_cast<double>(n)), sh);
+  for (int idx = threadIdx.x; idx < twod * k; idx += blockDim.x) {
+    const int c = idx % k;
+    S32[idx] = static_cast<float>(S[idx]);
+    H[idx] = psi[idx] * sigma[c];
+    H32[idx] = static_cast<float>(H[idx]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Attribute projection X' = X Psi_d (FP32), rows padded to dp columns, or a
+// padded copy of X when there is no reduction.  Also flags non-finite input.
+// One workgroup per 64 rows; Psi_d^T staged in LDS.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_project_x(const float* __restrict__ X, int64_t n, int du, int64_t ldx, const float* __restrict__ psi32, int d,
+            int dp, float* __restrict__ out, int32_t* __restrict__ err_bits) {
+  extern __shared__ float smem[];
+  // tile: 64 rows x 32 input columns of X, and 32 x dp of psi
+  float* xs = smem;                 // [64][33]
+  float* ps = smem + 64 * 33;       // [32][dp]
+  const int tid = threadIdx.x;
+  const int64_t row0 = static_cast<int64_t>(blockIdx.x) * 64;
+  // thread computes rows (tid / (dp/4)) ... a 64 x dp output tile with 256 threads
+  constexpr int RPT = 4;  // rows per thread
+  const int cols_per_thread = (dp * 64) / (256 * RPT);  // dp/16
+  const int cgroups = dp / cols_per_thread;              // = 16
+  const int tr = tid / cgroups;   // 0..15 -> rows tr*4 .. tr*4+3
+  const int tc = tid % cgroups;   // column group
+  float acc[RPT][16];
+#pragma unroll
+  for (int a = 0; a < RPT; ++a)
+#pragma unroll
+    for (int b = 0; b < 16; ++b) acc[a][b] = 0.0f;
+  bool bad = false;
+  for (int k0 = 0; k0 < du; k0 += 32) {
+    for (int e = tid; e < 64 * 32; e += 256) {
+      const int rr = e / 32, kk = e % 32;
+      const int64_t row = row0 + rr;
+      float v = (row < n && k0 + kk < du) ? X[row * ldx + k0 + kk] : 0.0f;
+      if (!isfinite(v)) {
+        bad = true;
+        v = 0.0f;
+      }
+      xs[rr * 33 + kk] = v;
+    }
+    for (int e = tid; e < 32 * dp; e += 256) {
+      const int kk = e / dp, cc = e % dp;
+      ps[kk * dp + cc] = (k0 + kk < du) ? psi32[static_cast<int64_t>(k0 + kk) * dp + cc] : 0.0f;
+    }
+    __syncthreads();
+    for (int kk = 0; kk < 32; ++kk) {
+      float xv[RPT];
+#pragma unroll
+      for (int a = 0; a < RPT; ++a) xv[a] = xs[(tr * RPT + a) * 33 + kk];
+#pragma unroll
+      for (int b = 0; b < 16; ++b) {
+        if (b < cols_per_thread) {
+          const float pv = ps[kk * dp + tc * cols_per_thread + b];
+#pragma unroll
+          for (int a = 0; a < RPT; ++a) acc[a][b] = fmaf(xv[a], pv, acc[a][b]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (bad) atomicOr(err_bits, 4);
+#pragma unroll
+  for (int a = 0; a < RPT; ++a) {
+    const int64_t row = row0 + tr * RPT + a;
+    if (row >= n) continue;
+#pragma unroll
+    for (int b = 0; b < 16; ++b)
+      if (b < cols_per_thread) out[row * dp + tc * cols_per_thread + b] = acc[a][b];
+  }
+}
+
+__global__ void k_pad_copy(const float* __restrict__ X, int64_t n, int du, int64_t ldx, int dp,
+                           float* __restrict__ out, int32_t* __restrict__ err_bits) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n * dp) return;
+  const int64_t r = i / dp;
+  const int c = static_cast<int>(i % dp);
+  float v = c < du ? X[r * ldx + c] : 0.0f;
+  if (!isfinite(v)) {
+    atomicOr(err_bits, 4);
+    v = 0.0f;
+  }
+  out[i] = v;
+}
+
+void launch_reduce(const Plan& p, void* ws, const float* x, int64_t ldx, hipStream_t s) {
+  DevStatus* st = bufp<DevStatus>(p, ws, B_STATUS);
+  float* xp = bufp<float>(p, ws, B_XPRIME);
+  if (!p.reduce) {
+    hipLaunchKernelGGL(k_pad_copy, dim3(ceil_div(static_cast<int64_t>(p.n) * p.dp, 256)), dim3(256), 0, s, x,
+                       static_cast<int64_t>(p.n), p.du, ldx, p.dp, xp, &st->err_bits);
+    TPO_LAUNCH_CHECK();
+    return;
+  }
+  double* C = bufp<double>(p, ws, B_C);
+  double* colsum = bufp<double>(p, ws, B_COLSUM_X);
+  gram(x, p.n, p.du, ldx, p.gram_chunks_x, bufp<double>(p, ws, B_GRAM_PART), bufp<double>(p, ws, B_COLSUM_PART), C,
+       colsum, s);
+  double* ma = bufp<double>(p, ws, B_MR_A);
+  double* mb = bufp<double>(p, ws, B_MR_B);
+  double* gs = bufp<double>(p, ws, B_SMALL_A);
+  TPO_HIP_CHECK(hipMemcpyAsync(ma, bufp<double>(p, ws, B_OMR), sizeof(double) * p.du * p.lr,
+                               hipMemcpyDeviceToDevice, s));
+  // q + 1 products with C, each followed by Cholesky QR
+  for (int it = 0; it <= p.par.q; ++it) {
+    gemm_f64(p.du, p.lr, p.du, C, p.du, ma, p.lr, mb, p.lr, s);
+    hipLaunchKernelGGL(k_cholqr, dim3(1), dim3(kSmallThreads), 0, s, mb, p.du, p.lr, p.lr, gs, &st->err_bits);
+    TPO_LAUNCH_CHECK();
+    std::swap(ma, mb);
+  }
+  gemm_f64(p.du, p.lr, p.du, C, p.du, ma, p.lr, mb, p.lr, s);  // P = C M
+  hipLaunchKernelGGL(k_reduce_rr, dim3(1), dim3(kSmallThreads), 0, s, ma, mb, p.du, p.lr, p.d, p.dp, colsum,
+                     static_cast<int64_t>(p.n), bufp<double>(p, ws, B_SMALL_B), bufp<double>(p, ws, B_SMALL_C),
+                     bufp<double>(p, ws, B_EVAL), bufp<double>(p, ws, B_PSI_D), bufp<float>(p, ws, B_PSI_D32));
+  TPO_LAUNCH_CHECK();
+  const size_t lds = (64 * 33 + 32 * p.dp) * sizeof(float);
+  hipLaunchKernelGGL(k_project_x, dim3(ceil_div(p.n, 64)), dim3(256), lds, s, x, static_cast<int64_t>(p.n), p.du,
+                     ldx, bufp<float>(p, ws, B_PSI_D32), p.d, p.dp, xp, &st->err_bits);
+  TPO_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// Random features (Eqs. Z, R-prime, Ri)
+// ---------------------------------------------------------------------------
+// Pass 1: one wave per row: Z_hat = Z / ||Z||, Zo = sqrt(d) Z_hat Q^T,
+// R' = sqrt(e/d) [sin Zo || cos Zo]; FP64 column sums of R' per workgroup.
+template <int CPL>  // output columns per lane: d <= 64 * CPL
+__global__ void __launch_bounds__(256)
+k_features1(const float* __restrict__ Z, int64_t n, int d, int dp, const float* __restrict__ Qt32, int rows_per_block,
+            float* __restrict__ R, double* __restrict__ part) {
+  extern __shared__ float qts[];  // d x d, Qt[j][l]
+  __shared__ double cs[4][2 * 64 * CPL];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int e = tid; e < d * d; e += 256) qts[e] = Qt32[e];
+  __syncthreads();
+  const float sqrtd = sqrtf(static_cast<float>(d));
+  const float amp = static_cast<float>(sqrt(2.718281828459045235 / static_cast<double>(d)));
+  double csin[CPL], ccos[CPL];
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) csin[c] = ccos[c] = 0.0;
+  const int64_t rb = static_cast<int64_t>(blockIdx.x) * rows_per_block;
+  const int64_t re = min(n, rb + rows_per_block);
+  for (int64_t r = rb + w; r < re; r += 4) {
+    float z[CPL];
+    float ss = 0.0f;
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      const int j = c * 64 + lane;
+      z[c] = j < d ? Z[r * dp + j] : 0.0f;
+      ss += z[c] * z[c];
+    }
+    ss = wave_sum(ss);
+    const float inv = ss > 0.0f ? 1.0f / sqrtf(ss) : 0.0f;
+    float zo[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) zo[c] = 0.0f;
+#pragma unroll
+    for (int cj = 0; cj < CPL; ++cj) {
+      for (int jj = 0; jj < 64; ++jj) {
+        const int j = cj * 64 + jj;
+        if (j >= d) break;
+        const float zj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(z[cj]), jj));
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+          const int l = c * 64 + lane;
+          if (l < d) zo[c] = fmaf(zj, qts[j * d + l], zo[c]);
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      const int l = c * 64 + lane;
+      if (l < d) {
+        const float a = sqrtd * (zo[c] * inv);
+        float sv, cv;
+        sincosf(a, &sv, &cv);
+        sv *= amp;
+        cv *= amp;
+        R[r * 2 * d + l] = sv;
+        R[r * 2 * d + d + l] = cv;
+        csin[c] += static_cast<double>(sv);
+        ccos[c] += static_cast<double>(cv);
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) {
+    cs[w][c * 64 + lane] = csin[c];
+    cs[w][64 * CPL + c * 64 + lane] = ccos[c];
+  }
+  __syncthreads();
+  for (int j = tid; j < 2 * d; j += 256) {
+    const int src = j < d ? j : 64 * CPL + (j - d);
+    const double v = ((cs[0][src] + cs[1][src]) + cs[2][src]) + cs[3][src];
+    part[static_cast<int64_t>(blockIdx.x) * 2 * d + j] = v;
+  }
+}
+
+// Pass 2: R[i] = R'[i] / sqrt(R'[i] . r); FP64 column sums of R and max |R|.
+template <int CPL>
+__global__ void __launch_bounds__(256)
+k_features2(float* __restrict__ R, int64_t n, int d, const double* __restrict__ rsum, int rows_per_block,
+            double* __restrict__ part, DevStatus* __restrict__ st) {
+  __shared__ double rs[2 * 64 * CPL];
+  __shared__ double cs[4][2 * 64 * CPL];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int twod = 2 * d;
+  for (int j = tid; j < twod; j += 256) rs[j] = rsum[j];
+  __syncthreads();
+  double acc[2 * CPL];
+#pragma unroll
+  for (int c = 0; c < 2 * CPL; ++c) acc[c] = 0.0;
+  float mx = 0.0f;
+  bool bad = false;
+  const int64_t rb = static_cast<int64_t>(blockIdx.x) * rows_per_block;
+  const int64_t re = min(n, rb + rows_per_block);
+  for (int64_t r = rb + w; r < re; r += 4) {
+    float v[2 * CPL];
+    double dot = 0.0;
+#pragma unroll
+    for (int c = 0; c < 2 * CPL; ++c) {
+      const int j = c * 64 + lane;
+      v[c] = j < twod ? R[r * twod + j] : 0.0f;
+      if (j < twod) dot = fma(static_cast<double>(v[c]), rs[j], dot);
+    }
+    dot = wave_sum(dot);
+    if (!(dot > 0.0) || !isfinite(dot)) {
+      bad = true;
+      dot = 1.0;
+    }
+    const float sc = static_cast<float>(1.0 / sqrt(dot));
+#pragma unroll
+    for (int c = 0; c < 2 * CPL; ++c) {
+      const int j = c * 64 + lane;
+      if (j < twod) {
+        const float o = v[c] * sc;
+        R[r * twod + j] = o;
+        acc[c] += static_cast<double>(o);
+        mx = fmaxf(mx, fabsf(o));
+      }
+    }
+  }
+  if (bad && lane == 0) atomicOr(&st->err_bits, 8);
+  mx = wave_max(mx);
+  if (lane == 0) atomic_max_nonneg(&st->maxabs_r_bits, mx);
+#pragma unroll
+  for (int c = 0; c < 2 * CPL; ++c) cs[w][c * 64 + lane] = acc[c];
+  __syncthreads();
+  for (int j = tid; j < twod; j += 256) {
+    const double v = ((cs[0][j] + cs[1][j]) + cs[2][j]) + cs[3][j];
+    part[static_cast<int64_t>(blockIdx.x) * twod + j] = v;
+  }
+}
+
+__global__ void k_reduce_cols(const double* __restrict__ part, int nparts, int len, double* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= len) return;
+  double s = 0.0;
+  for (int b = 0; b < nparts; ++b) s += part[static_cast<int64_t>(b) * len + j];
+  out[j] = s;
+}
+
+template <int CPL>
+static void features_impl(const Plan& p, void* ws, hipStream_t s) {
+  DevStatus* st = bufp<DevStatus>(p, ws, B_STATUS);
+  const int nb = p.rowpass_blocks;
+  const int rpb = static_cast<int>((p.n + nb - 1) / nb);
+  double* part = bufp<double>(p, ws, B_RPART);
+  float* R = bufp<float>(p, ws, B_R);
+  hipLaunchKernelGGL(k_features1<CPL>, dim3(nb), dim3(256), sizeof(float) * p.d * p.d, s,
+                     bufp<float>(p, ws, B_Z), static_cast<int64_t>(p.n), p.d, p.dp, bufp<float>(p, ws, B_QT32), rpb,
+                     R, part);
+  TPO_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_reduce_cols, dim3(ceil_div(p.twod, 256)), dim3(256), 0, s, part, nb, p.twod,
+                     bufp<double>(p, ws, B_RSUM));
+  TPO_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_features2<CPL>, dim3(nb), dim3(256), 0, s, R, static_cast<int64_t>(p.n), p.d,
+                     bufp<double>(p, ws, B_RSUM), rpb, part, st);
+  TPO_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_reduce_cols, dim3(ceil_div(p.twod, 256)), dim3(256), 0, s, part, nb, p.twod,
+                     bufp<double>(p, ws, B_RCOLSUM));
+  TPO_LAUNCH_CHECK();
+}
+
+void launch_features(const Plan& p, void* ws, hipStream_t s) {
+  DevStatus* st = bufp<DevStatus>(p, ws, B_STATUS);
+  hipLaunchKernelGGL(k_q_from_g, dim3(1), dim3(kSmallThreads), 0, s, bufp<double>(p, ws, B_G), p.d,
+                     bufp<double>(p, ws, B_Q), bufp<double>(p, ws, B_SMALL_A), bufp<float>(p, ws, B_QT32),
+                     &st->err_bits);
+  TPO_LAUNCH_CHECK();
+  if (p.d <= 64)
+    features_impl<1>(p, ws, s);
+  else
+    features_impl<2>(p, ws, s);
+}
+
+void launch_embed(const Plan& p, void* ws, hipStream_t s) {
+  DevStatus* st = bufp<DevStatus>(p, ws, B_STATUS);
+  double* K = bufp<double>(p, ws, B_K);
+  gram(bufp<float>(p, ws, B_R), p.n, p.twod, p.twod, p.gram_chunks_r, bufp<double>(p, ws, B_GRAM_PART), nullptr,
+       K, nullptr, s);
+  hipLaunchKernelGGL(k_embed_small, dim3(1), dim3(kSmallThreads), 0, s, K, bufp<double>(p, ws, B_OMEGA), p.twod,
+                     p.kp, p.k, p.par.q, bufp<double>(p, ws, B_RCOLSUM), static_cast<int64_t>(p.n),
+                     bufp<double>(p, ws, B_M_A), bufp<double>(p, ws, B_M_B), bufp<double>(p, ws, B_EK_A),
+                     bufp<double>(p, ws, B_EK_B), bufp<double>(p, ws, B_EK_C), bufp<double>(p, ws, B_EEVAL),
+                     bufp<float>(p, ws, B_S32), bufp<double>(p, ws, B_SIGMA), bufp<double>(p, ws, B_PSI),
+                     bufp<double>(p, ws, B_H), bufp<float>(p, ws, B_H32), &st->err_bits);
+  TPO_LAUNCH_CHECK();
+}
+
+}  // namespace tpo

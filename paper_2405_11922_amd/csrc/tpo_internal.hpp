@@ -1,0 +1,126 @@
+// Internal declarations shared by the host orchestration (tpo_api.cpp) and the
+// HIP kernel files: the workspace layout of a plan and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/tpo.h"
+
+namespace tpo {
+
+// Edges per hub chunk of the propagation SpMM: rows with more neighbours than
+// this are split into chunks whose partial sums are added in chunk order.
+constexpr int kHubChunk = 256;
+// Radix sort tile: 256 threads x 16 keys.
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;
+// Rows per workgroup chunk of the FP64 Gram kernels.
+constexpr int kGramRowsPerChunk = 2048;
+// Rows per workgroup of the row-pass kernels.
+constexpr int kRowPassRows = 1024;
+// Hops whose SpMM kernels are bracketed by events when timing is on.
+constexpr int kMaxTimedHops = 64;
+
+// Device-side status words (one small block, copied back at the end of a job).
+struct DevStatus {
+  int32_t err_bits;        // bit 0: edge out of range, bit 1: bad weight,
+                           // bit 2: non-finite attribute, bit 3: R'.r <= 0,
+                           // bit 4: Cholesky breakdown, bit 5: non-finite value
+  int32_t has_vals;        // CSR carries a value array (weights / duplicates)
+  int32_t n_unique;        // distinct (u, v) pairs
+  int32_t guard_hits;      // ONMF guards applied
+  int32_t iso_u, iso_v;    // isolated nodes
+  int32_t hub_chunks_u, hub_rows_u, hub_chunks_v, hub_rows_v;
+  uint32_t maxabs_r_bits;  // max |R| as float bits
+  uint32_t maxabs_ups_bits;// max |Upsilon| as float bits
+  double objective[2];
+  int32_t pad[2];
+};
+
+enum Buf {
+  B_STATUS,
+  // ingest
+  B_KEYS_A, B_KEYS_B, B_WV_A, B_WV_B, B_HIST, B_SCAN_AUX, B_UPOS,
+  B_ROWPTR_U, B_COL_U, B_VAL_U, B_ROWPTR_V, B_COL_V, B_VAL_V,
+  B_DEG_U, B_DEG_V, B_ISQ_U, B_INV_V,
+  B_HUBCNT_U, B_HUBCNT_V,         // per-row chunk counts / scans (n+1, m+1)
+  B_HUBROW_U, B_HUBROW_V,         // per-row hub index scans (n+1, m+1)
+  B_CHUNK_U, B_CHUNK_V,           // int4 {row, begin, end, slot} per chunk
+  B_HUBLIST_U, B_HUBLIST_V,       // int4 {row, slot_begin, nchunks, 0} per hub row
+  B_PARTIAL,                      // hub chunk partial sums (max chunks x d)
+  // reduce
+  B_GRAM_PART, B_COLSUM_PART, B_C, B_COLSUM_X, B_MR_A, B_MR_B, B_SMALL_A,
+  B_SMALL_B, B_SMALL_C, B_EVAL, B_PSI_D, B_PSI_D32, B_XPRIME,
+  // propagate
+  B_W0, B_W1, B_T, B_Z,
+  // features
+  B_G, B_Q, B_QT32, B_R, B_RPART, B_RSUM, B_RCOLSUM,
+  // embed
+  B_OMEGA, B_K, B_M_A, B_M_B, B_EK_A, B_EK_B, B_EK_C, B_EEVAL, B_S32,
+  B_GAMMA, B_SIGMA, B_PSI, B_OMR,
+  // onmf
+  B_UPS, B_H, B_H32, B_RTU, B_UTU, B_A32, B_ONMF_PART,
+  // nci / objective
+  B_LABELS, B_NCI_ACC, B_NCI_CNT, B_OBJ_ACC, B_OBJ_CNT,
+  B_COUNT
+};
+
+struct Layout {
+  size_t off[B_COUNT];
+  size_t bytes[B_COUNT];
+  size_t total;
+};
+
+struct Plan {
+  tpo_problem prob;
+  tpo_params par;
+  int n, m, du, d, dp, lr, kp, k, twod;
+  int64_t E;
+  bool reduce;
+  int rowbits, colbits;
+  int sort_blocks;          // tiles of the radix sort
+  int max_chunks_u, max_chunks_v;
+  int gram_chunks_x, gram_chunks_r;
+  int rowpass_blocks;
+  std::vector<double> omega_r, g, omega;
+  Layout lay;
+  std::string last_error;
+  tpo_stats stats;
+  hipEvent_t ev[10];
+  bool events_made;
+  bool timing;             // TPO_FLAG_TIMING set
+  hipEvent_t kev[4 * kMaxTimedHops];
+  bool kev_made;
+  DevStatus init_status;  // host copy uploaded at the start of a job
+  DevStatus host_status;  // last status block read back
+};
+
+template <typename T>
+inline T* bufp(const Plan& p, void* ws, Buf b) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + p.lay.off[b]);
+}
+
+// ---------------------------------------------------------------------------
+// Launchers (defined in the .hip files).  All enqueue on `s`.
+// ---------------------------------------------------------------------------
+// k_ingest.hip
+void launch_ingest(const Plan& p, void* ws, const tpo_inputs* in, hipStream_t s);
+// k_spmm.hip
+void launch_propagate(const Plan& p, void* ws, const float* xprime, int64_t ldxp,
+                      hipStream_t s);
+// k_dense.hip
+void launch_reduce(const Plan& p, void* ws, const float* x, int64_t ldx, hipStream_t s);
+void launch_features(const Plan& p, void* ws, hipStream_t s);
+void launch_embed(const Plan& p, void* ws, hipStream_t s);
+// k_cluster.hip
+void launch_onmf(const Plan& p, void* ws, hipStream_t s);
+void launch_nci(const Plan& p, void* ws, hipStream_t s);
+void launch_objective(const Plan& p, void* ws, hipStream_t s);
+
+}  // namespace tpo

@@ -1,0 +1,82 @@
+"""Host-side checks of the C ABI (no GPU work): the library loads, exports
+every entry point include/tpo.h declares, validates arguments, and its
+Gaussian generator reproduces the seeded input generator bit for bit."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import abg_synth as synth
+import paper_2405_11922_amd as tpo
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    with open(os.path.join(ROOT, "include", "tpo.h")) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tpo_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = tpo.load_library()
+    syms = _declared_symbols()
+    assert "tpo_execute" in syms and "tpo_plan_create" in syms and len(syms) >= 18
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert set(syms) == set(tpo.EXPORTED)
+
+
+def test_abi_version():
+    assert tpo.load_library().tpo_abi_version() == tpo.TPO_ABI_VERSION
+
+
+@pytest.mark.parametrize("seed,stream,count", [(0, 0, 1001), (12345, 1, 64 * 64), (2**63 + 7, 2, 4000)])
+def test_native_generator_matches_input_generator(seed, stream, count):
+    a = tpo.tpo_draw_normals(seed, stream, count)
+    b = synth.splitmix64_normals(seed, stream, count)
+    assert np.array_equal(a, b)
+
+
+def test_plan_dims_and_workspace():
+    h = tpo.tpo_plan_create(200_000, 400_000, 4_000_000, 256, k=20, alpha=0.5, gamma=10, d=64)
+    try:
+        assert tpo.tpo_plan_dims(h) == synth.sketch_widths(256, 64, 20, 10)
+        ws = tpo.tpo_plan_workspace_bytes(h)
+        assert 100e6 < ws < 8e9
+    finally:
+        tpo.tpo_plan_destroy(h)
+    h = tpo.tpo_plan_create(2000, 3000, 20_000, 64, k=5, alpha=0.5, gamma=5, d=0)
+    try:
+        assert tpo.tpo_plan_dims(h) == (64, 0, 15)
+    finally:
+        tpo.tpo_plan_destroy(h)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(k=0), dict(k=65), dict(alpha=1.0), dict(alpha=-0.1), dict(gamma=-1), dict(q=-1),
+    dict(t_f=-1), dict(t_g=-2), dict(oversample=-1), dict(k=40, d=16),
+])
+def test_plan_create_rejects_bad_parameters(kw):
+    base = dict(k=5, alpha=0.5, gamma=3, d=0)
+    base.update(kw)
+    with pytest.raises(tpo.TpoError) as e:
+        h = tpo.tpo_plan_create(100, 100, 500, 32, **base)
+        tpo.tpo_plan_destroy(h)
+    assert e.value.status == 1
+
+
+@pytest.mark.parametrize("shape", [(0, 10, 5, 8), (10, 0, 5, 8), (10, 10, -1, 8), (10, 10, 5, 0),
+                                   (10, 10, 2**31, 8), (10, 10, 5, 200)])
+def test_plan_create_rejects_bad_shapes(shape):
+    with pytest.raises(tpo.TpoError):
+        h = tpo.tpo_plan_create(*shape, k=2, alpha=0.5, gamma=2)
+        tpo.tpo_plan_destroy(h)
+
+
+def test_status_strings():
+    assert tpo.tpo_status_string(0) == "ok"
+    assert tpo.tpo_status_string(3) == "workspace too small"
