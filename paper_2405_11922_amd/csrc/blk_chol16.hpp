@@ -1,0 +1,241 @@
+// Blocked FP64 Cholesky QR for one workgroup (16 waves), built from 16 x 16
+// tiles on FP64 MFMA.  The n x n Gram (n <= 80) is padded to 16 * nb with an
+// identity block, so its factor and inverse are blockdiag(L, I) and
+// blockdiag(L^{-1}, I).
+//
+// v_mfma_f64_16x16x4f64 operand layout: lane l supplies A[l % 16][l / 16]
+// (16 x 4) and B[l / 16][l % 16] (4 x 16); its v-th result is
+// D[4 v + l / 16][l % 16].
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "dev_common.hpp"
+
+namespace tpo {
+
+typedef double v4d_t __attribute__((ext_vector_type(4)));
+
+constexpr int kC16Max = 80;          // largest n
+constexpr int kC16Ld = kC16Max + 1;  // LDS leading dimension (odd: spreads banks)
+
+// acc += op(A) op(B) for 16 x 16 tiles; ta / tb read the tile transposed.
+// `neg` negates op(A).
+__device__ __forceinline__ v4d_t mma16(const double* A, int lda, bool ta, const double* B, int ldb, bool tb,
+                                       v4d_t acc, bool neg = false) {
+  const int l = threadIdx.x & 63;
+  const int i = l & 15, k = l >> 4;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int kk = 4 * s + k;
+    double a = ta ? A[kk * lda + i] : A[i * lda + kk];
+    const double b = tb ? B[i * ldb + kk] : B[kk * ldb + i];
+    if (neg) a = -a;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+__device__ __forceinline__ v4d_t load16(const double* C, int ldc) {
+  const int l = threadIdx.x & 63;
+  v4d_t r;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) r[v] = C[(4 * v + (l >> 4)) * ldc + (l & 15)];
+  return r;
+}
+
+__device__ __forceinline__ void store16(double* C, int ldc, v4d_t acc) {
+  const int l = threadIdx.x & 63;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) C[(4 * v + (l >> 4)) * ldc + (l & 15)] = acc[v];
+}
+
+// One wave: in-place lower Cholesky of a 16 x 16 LDS tile (lower triangle
+// read and written).  Returns false (wave-uniform) on a bad pivot.
+__device__ __forceinline__ bool wave_chol16(double* B, int ld) {
+  const int l = threadIdx.x & 63;
+  for (int k = 0; k < 16; ++k) {
+    const double d = B[k * ld + k];
+    wave_sync();
+    if (!(d > 0.0) || !isfinite(d)) return false;
+    const double s = sqrt(d);
+    if (l > k && l < 16) B[l * ld + k] /= s;
+    if (l == k) B[k * ld + k] = s;
+    wave_sync();
+#pragma unroll
+    for (int e0 = 0; e0 < 256; e0 += 64) {
+      const int e = e0 + l, i = e >> 4, c = e & 15;
+      if (c > k && c <= i) B[i * ld + c] -= B[i * ld + k] * B[c * ld + k];
+    }
+    wave_sync();
+  }
+  return true;
+}
+
+// One wave: X = L^{-1} for a 16 x 16 lower LDS tile; lane c < 16 forms
+// column c by forward substitution in registers.
+__device__ __forceinline__ void wave_inv16(const double* L, int ldl, double* X, int ldx) {
+  const int c = threadIdx.x & 63;
+  double x[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    double s = (r == c) ? 1.0 : 0.0;
+#pragma unroll
+    for (int t = 0; t < r; ++t) s -= L[r * ldl + t] * x[t];
+    x[r] = s / L[r * ldl + r];
+  }
+  if (c < 16) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) X[r * ldx + c] = x[r];
+  }
+  wave_sync();
+}
+
+// Blocked Cholesky of the padded nb x nb tile matrix G (LDS, ld) with the
+// inverses of its diagonal tiles left in Li; then Li = L^{-1} (lower).
+// scratch: 16 waves x 16 x 16 doubles (or at least (nb - 1) tiles).
+// Returns false uniformly when a pivot fails.
+__device__ bool blk_chol_inv16(double* G, double* Li, int ld, int nb, double* scratch, int* flag) {
+  const int w = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  if (threadIdx.x == 0) *flag = 0;
+  __syncthreads();
+  for (int J = 0; J < nb; ++J) {
+    double* GJJ = G + 16 * J * ld + 16 * J;
+    double* LJJ = Li + 16 * J * ld + 16 * J;
+    if (w == 0) {
+      if (!wave_chol16(GJJ, ld)) {
+        if ((threadIdx.x & 63) == 0) *flag = 1;
+      } else {
+        wave_inv16(GJJ, ld, LJJ, ld);
+      }
+    }
+    __syncthreads();
+    if (*flag) return false;
+    // panel: L_IJ = G_IJ L_JJ^{-T}
+    for (int I = J + 1 + w; I < nb; I += nw) {
+      double* GIJ = G + 16 * I * ld + 16 * J;
+      v4d_t acc = {0.0, 0.0, 0.0, 0.0};
+      acc = mma16(GIJ, ld, false, LJJ, ld, true, acc);
+      store16(GIJ, ld, acc);
+    }
+    __syncthreads();
+    // trailing: G_IK -= L_IJ L_KJ^T for J < K <= I
+    const int m = nb - 1 - J;
+    for (int p = w; p < m * (m + 1) / 2; p += nw) {
+      int I = 0, rem = p;
+      while (rem > I) {
+        rem -= I + 1;
+        ++I;
+      }
+      const int K = rem;  // 0 <= K <= I
+      double* GIK = G + 16 * (J + 1 + I) * ld + 16 * (J + 1 + K);
+      const double* LIJ = G + 16 * (J + 1 + I) * ld + 16 * J;
+      const double* LKJ = G + 16 * (J + 1 + K) * ld + 16 * J;
+      v4d_t acc = load16(GIK, ld);
+      acc = mma16(LIJ, ld, false, LKJ, ld, true, acc, true);
+      store16(GIK, ld, acc);
+    }
+    __syncthreads();
+  }
+  // zero the strictly upper tiles of Li, then Li_IJ = -Li_II sum_K L_IK Li_KJ
+  for (int e = threadIdx.x; e < 16 * nb * 16 * nb; e += blockDim.x) {
+    const int i = e / (16 * nb), j = e % (16 * nb);
+    if (j / 16 > i / 16) Li[i * ld + j] = 0.0;
+  }
+  __syncthreads();
+  for (int I = 1; I < nb; ++I) {
+    for (int J = w; J < I; J += nw) {
+      v4d_t acc = {0.0, 0.0, 0.0, 0.0};
+      for (int K = J; K < I; ++K)
+        acc = mma16(G + 16 * I * ld + 16 * K, ld, false, Li + 16 * K * ld + 16 * J, ld, false, acc);
+      double* T = scratch + 256 * w;
+      store16(T, 16, acc);
+      wave_sync();
+      v4d_t out = {0.0, 0.0, 0.0, 0.0};
+      out = mma16(Li + 16 * I * ld + 16 * I, ld, false, T, 16, false, out, true);
+      store16(Li + 16 * I * ld + 16 * J, ld, out);
+    }
+    __syncthreads();
+  }
+  return true;
+}
+
+// A (m x n, global, row-major lda) <- A Li^T with Li lower (LDS, padded to
+// 16 nb).  Wave w owns row tiles w, w + 16, ...: it loads the tile's A
+// operands for every k step first, then writes all its column tiles.
+__device__ void apply_linv_t(double* A, int lda, int m, int n, const double* Li, int ld, int nb) {
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int l = threadIdx.x & 63, i = l & 15, k = l >> 4;
+  const int nrt = (m + 15) / 16;
+  for (int rt = w; rt < nrt; rt += nw) {
+    const int row = 16 * rt + i;
+    double a[4 * (kC16Max / 16)];
+#pragma unroll
+    for (int kt = 0; kt < kC16Max / 16; ++kt)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int col = 16 * kt + 4 * s + k;
+        a[4 * kt + s] = (kt < nb && row < m && col < n) ? A[row * lda + col] : 0.0;
+      }
+#pragma unroll
+    for (int ct = 0; ct < kC16Max / 16; ++ct) {
+      if (ct >= nb) break;
+      v4d_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kt = 0; kt <= ct; ++kt)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int kk = 16 * kt + 4 * s + k;  // k index of this lane
+          const double b = Li[(16 * ct + i) * ld + kk];  // Li^T[kk][16 ct + i]
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[4 * kt + s], b, acc, 0, 0, 0);
+        }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * rt + 4 * v + k, c = 16 * ct + i;
+        if (r < m && c < n) A[r * lda + c] = acc[v];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// G (padded, LDS) = A^T A over the m rows of A (global).  Waves take output
+// tiles; each loads 16 k steps (64 rows) of operands before the MFMAs.
+__device__ void gram16(const double* A, int lda, int m, int n, double* G, int ld, int nb) {
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int l = threadIdx.x & 63, i = l & 15, k = l >> 4;
+  const int ntiles = nb * (nb + 1) / 2;
+  for (int t = w; t < ntiles; t += nw) {
+    int ta = 0, rem = t;
+    while (rem >= nb - ta) {
+      rem -= nb - ta;
+      ++ta;
+    }
+    const int tb = ta + rem;
+    const int ca = 16 * ta + i, cb = 16 * tb + i;
+    v4d_t acc = {0.0, 0.0, 0.0, 0.0};
+    for (int r0 = 0; r0 < m; r0 += 64) {
+      double av[16], bv[16];
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        const int r = r0 + 4 * s + k;
+        av[s] = (r < m && ca < n) ? A[r * lda + ca] : 0.0;
+        bv[s] = (r < m && cb < n) ? A[r * lda + cb] : 0.0;
+      }
+#pragma unroll
+      for (int s = 0; s < 16; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[s], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * ta + 4 * v + k, c = 16 * tb + i;
+      double val = acc[v];
+      if (r >= n || c >= n) val = (r == c) ? 1.0 : 0.0;  // identity padding
+      G[r * ld + c] = val;
+      if (ta != tb) G[c * ld + r] = val;
+    }
+  }
+  __syncthreads();
+}
+
+}  // namespace tpo

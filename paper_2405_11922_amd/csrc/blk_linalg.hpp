@@ -165,31 +165,39 @@ __device__ inline void blk_jacobi(double* A, int lda, double* V, int ldv, int n,
         qq[i] = q < n ? q : -1;
       }
       __syncthreads();
-      // rows: A <- J^T A
-      for (int idx = threadIdx.x; idx < npairs * n; idx += blockDim.x) {
-        const int i = idx / n, j = idx % n;
-        const int q = qq[i];
-        if (q < 0 || sn[i] == 0.0) continue;
-        const int p = pp[i];
-        const double c = cs[i], s = sn[i];
-        const double apj = A[p * lda + j], aqj = A[q * lda + j];
-        A[p * lda + j] = c * apj - s * aqj;
-        A[q * lda + j] = s * apj + c * aqj;
+      // rows: A <- J^T A  (threads: 32 pair lanes x 32 column lanes)
+      {
+        const int tr = threadIdx.x >> 5, tcc = threadIdx.x & 31;
+        for (int i = tr; i < npairs; i += (blockDim.x >> 5)) {
+          const int q = qq[i];
+          if (q < 0 || sn[i] == 0.0) continue;
+          const int p = pp[i];
+          const double c = cs[i], s = sn[i];
+          for (int j = tcc; j < n; j += 32) {
+            const double apj = A[p * lda + j], aqj = A[q * lda + j];
+            A[p * lda + j] = c * apj - s * aqj;
+            A[q * lda + j] = s * apj + c * aqj;
+          }
+        }
       }
       __syncthreads();
       // columns: A <- A J, V <- V J
-      for (int idx = threadIdx.x; idx < npairs * n; idx += blockDim.x) {
-        const int i = idx / n, r = idx % n;
-        const int q = qq[i];
-        if (q < 0 || sn[i] == 0.0) continue;
-        const int p = pp[i];
-        const double c = cs[i], s = sn[i];
-        const double arp = A[r * lda + p], arq = A[r * lda + q];
-        A[r * lda + p] = c * arp - s * arq;
-        A[r * lda + q] = s * arp + c * arq;
-        const double vrp = V[r * ldv + p], vrq = V[r * ldv + q];
-        V[r * ldv + p] = c * vrp - s * vrq;
-        V[r * ldv + q] = s * vrp + c * vrq;
+      {
+        const int tr = threadIdx.x >> 5, tcc = threadIdx.x & 31;
+        for (int i = tr; i < npairs; i += (blockDim.x >> 5)) {
+          const int q = qq[i];
+          if (q < 0 || sn[i] == 0.0) continue;
+          const int p = pp[i];
+          const double c = cs[i], s = sn[i];
+          for (int r = tcc; r < n; r += 32) {
+            const double arp = A[r * lda + p], arq = A[r * lda + q];
+            A[r * lda + p] = c * arp - s * arq;
+            A[r * lda + q] = s * arp + c * arq;
+            const double vrp = V[r * ldv + p], vrq = V[r * ldv + q];
+            V[r * ldv + p] = c * vrp - s * vrq;
+            V[r * ldv + q] = s * vrp + c * vrq;
+          }
+        }
       }
       __syncthreads();
     }

@@ -124,14 +124,6 @@ k_rowpass(const float* __restrict__ R, int64_t n, int twod, int k, const float* 
   if ((tid & 63) == 0) atomic_max_nonneg(&st->maxabs_ups_bits, mx);
 }
 
-__global__ void k_reduce_parts(const double* __restrict__ part, int nparts, int len, double* __restrict__ out) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= len) return;
-  double s = 0.0;
-  for (int b = 0; b < nparts; ++b) s += part[static_cast<int64_t>(b) * len + j];
-  out[j] = s;
-}
-
 // H update (Eq. update-Q) and A = (R^T U)^T H_new for the U update.
 // H_new is formed in LDS first (every entry reads the old row of H).
 __global__ void __launch_bounds__(1024)
@@ -202,9 +194,7 @@ void launch_onmf(const Plan& p, void* ws, hipStream_t s) {
   // Gamma = R S, Upsilon = Gamma, and R^T Ups, Ups^T Ups for the first round
   rowpass_any(p, ws, kProject, bufp<float>(p, ws, B_S32), nullptr, s);
   for (int t = 0; t < p.par.t_f; ++t) {
-    hipLaunchKernelGGL(k_reduce_parts, dim3(ceil_div(len, 256)), dim3(256), 0, s, bufp<double>(p, ws, B_ONMF_PART),
-                       p.rowpass_blocks, len, rtu);
-    TPO_LAUNCH_CHECK();
+    reduce_parts(bufp<double>(p, ws, B_ONMF_PART), p.rowpass_blocks, len, bufp<double>(p, ws, B_REDTMP), rtu, s);
     hipLaunchKernelGGL(k_onmf_small, dim3(1), dim3(1024), sizeof(double) * p.twod * p.k, s, rtu, p.twod, p.k, bufp<double>(p, ws, B_H),
                        bufp<float>(p, ws, B_H32), bufp<float>(p, ws, B_A32), st);
     TPO_LAUNCH_CHECK();

@@ -450,17 +450,27 @@ void launch_reduce(const Plan& p, void* ws, const float* x, int64_t ldx, hipStre
   TPO_HIP_CHECK(hipMemcpyAsync(ma, bufp<double>(p, ws, B_OMR), sizeof(double) * p.du * p.lr,
                                hipMemcpyDeviceToDevice, s));
   // q + 1 products with C, each followed by Cholesky QR
+  const bool small_in_lds = p.lr <= kLdsMaxN;
   for (int it = 0; it <= p.par.q; ++it) {
     gemm_f64(p.du, p.lr, p.du, C, p.du, ma, p.lr, mb, p.lr, s);
-    hipLaunchKernelGGL(k_cholqr, dim3(1), dim3(kSmallThreads), 0, s, mb, p.du, p.lr, p.lr, gs, &st->err_bits);
-    TPO_LAUNCH_CHECK();
+    if (small_in_lds) {
+      cholqr_lds(mb, p.du, p.lr, p.lr, &st->err_bits, s);
+    } else {
+      hipLaunchKernelGGL(k_cholqr, dim3(1), dim3(kSmallThreads), 0, s, mb, p.du, p.lr, p.lr, gs, &st->err_bits);
+      TPO_LAUNCH_CHECK();
+    }
     std::swap(ma, mb);
   }
   gemm_f64(p.du, p.lr, p.du, C, p.du, ma, p.lr, mb, p.lr, s);  // P = C M
-  hipLaunchKernelGGL(k_reduce_rr, dim3(1), dim3(kSmallThreads), 0, s, ma, mb, p.du, p.lr, p.d, p.dp, colsum,
-                     static_cast<int64_t>(p.n), bufp<double>(p, ws, B_SMALL_B), bufp<double>(p, ws, B_SMALL_C),
-                     bufp<double>(p, ws, B_EVAL), bufp<double>(p, ws, B_PSI_D), bufp<float>(p, ws, B_PSI_D32));
-  TPO_LAUNCH_CHECK();
+  if (small_in_lds) {
+    rr_reduce_lds(ma, mb, p.du, p.lr, p.d, p.dp, colsum, static_cast<int64_t>(p.n), bufp<double>(p, ws, B_EVAL),
+                  bufp<double>(p, ws, B_PSI_D), bufp<float>(p, ws, B_PSI_D32), s);
+  } else {
+    hipLaunchKernelGGL(k_reduce_rr, dim3(1), dim3(kSmallThreads), 0, s, ma, mb, p.du, p.lr, p.d, p.dp, colsum,
+                       static_cast<int64_t>(p.n), bufp<double>(p, ws, B_SMALL_B), bufp<double>(p, ws, B_SMALL_C),
+                       bufp<double>(p, ws, B_EVAL), bufp<double>(p, ws, B_PSI_D), bufp<float>(p, ws, B_PSI_D32));
+    TPO_LAUNCH_CHECK();
+  }
   const size_t lds = (64 * 33 + 32 * p.dp) * sizeof(float);
   hipLaunchKernelGGL(k_project_x, dim3(ceil_div(p.n, 64)), dim3(256), lds, s, x, static_cast<int64_t>(p.n), p.du,
                      ldx, bufp<float>(p, ws, B_PSI_D32), p.d, p.dp, xp, &st->err_bits);
@@ -600,12 +610,42 @@ k_features2(float* __restrict__ R, int64_t n, int d, const double* __restrict__ 
   }
 }
 
-__global__ void k_reduce_cols(const double* __restrict__ part, int nparts, int len, double* __restrict__ out) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= len) return;
+// Deterministic two-level column sums of part (nparts x len): block (x, y)
+// sums slice y of the parts for 64 columns (4 interleaved sub-sums added in
+// a fixed order), then one thread per column adds the slices in order.
+constexpr int kRedSlices = 16;
+
+__global__ void __launch_bounds__(256)
+k_reduce_slices(const double* __restrict__ part, int nparts, int len, double* __restrict__ tmp) {
+  __shared__ double sh[4][64];
+  const int c = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int g = threadIdx.x >> 6;
+  const int per = (nparts + kRedSlices - 1) / kRedSlices;
+  const int p0 = blockIdx.y * per, p1 = min(nparts, p0 + per);
   double s = 0.0;
-  for (int b = 0; b < nparts; ++b) s += part[static_cast<int64_t>(b) * len + j];
-  out[j] = s;
+  if (c < len)
+    for (int b = p0 + g; b < p1; b += 4) s += part[static_cast<int64_t>(b) * len + c];
+  sh[g][threadIdx.x & 63] = s;
+  __syncthreads();
+  if (g == 0 && c < len) {
+    const int t = threadIdx.x & 63;
+    tmp[static_cast<int64_t>(blockIdx.y) * len + c] = ((sh[0][t] + sh[1][t]) + sh[2][t]) + sh[3][t];
+  }
+}
+
+__global__ void k_reduce_final(const double* __restrict__ tmp, int len, double* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= len) return;
+  double s = 0.0;
+  for (int y = 0; y < kRedSlices; ++y) s += tmp[static_cast<int64_t>(y) * len + c];
+  out[c] = s;
+}
+
+void reduce_parts(const double* part, int nparts, int len, double* tmp, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_slices, dim3(ceil_div(len, 64), kRedSlices), dim3(256), 0, s, part, nparts, len, tmp);
+  TPO_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_reduce_final, dim3(ceil_div(len, 256)), dim3(256), 0, s, tmp, len, out);
+  TPO_LAUNCH_CHECK();
 }
 
 template <int CPL>
@@ -619,23 +659,37 @@ static void features_impl(const Plan& p, void* ws, hipStream_t s) {
                      bufp<float>(p, ws, B_Z), static_cast<int64_t>(p.n), p.d, p.dp, bufp<float>(p, ws, B_QT32), rpb,
                      R, part);
   TPO_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_reduce_cols, dim3(ceil_div(p.twod, 256)), dim3(256), 0, s, part, nb, p.twod,
-                     bufp<double>(p, ws, B_RSUM));
-  TPO_LAUNCH_CHECK();
+  reduce_parts(part, nb, p.twod, bufp<double>(p, ws, B_REDTMP), bufp<double>(p, ws, B_RSUM), s);
   hipLaunchKernelGGL(k_features2<CPL>, dim3(nb), dim3(256), 0, s, R, static_cast<int64_t>(p.n), p.d,
                      bufp<double>(p, ws, B_RSUM), rpb, part, st);
   TPO_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_reduce_cols, dim3(ceil_div(p.twod, 256)), dim3(256), 0, s, part, nb, p.twod,
-                     bufp<double>(p, ws, B_RCOLSUM));
-  TPO_LAUNCH_CHECK();
+  reduce_parts(part, nb, p.twod, bufp<double>(p, ws, B_REDTMP), bufp<double>(p, ws, B_RCOLSUM), s);
+}
+
+__global__ void k_transpose_f32(const double* __restrict__ Q, int d, float* __restrict__ Qt32) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= d * d) return;
+  const int j = idx / d, l = idx % d;
+  Qt32[idx] = static_cast<float>(Q[l * d + j]);
 }
 
 void launch_features(const Plan& p, void* ws, hipStream_t s) {
   DevStatus* st = bufp<DevStatus>(p, ws, B_STATUS);
-  hipLaunchKernelGGL(k_q_from_g, dim3(1), dim3(kSmallThreads), 0, s, bufp<double>(p, ws, B_G), p.d,
-                     bufp<double>(p, ws, B_Q), bufp<double>(p, ws, B_SMALL_A), bufp<float>(p, ws, B_QT32),
-                     &st->err_bits);
-  TPO_LAUNCH_CHECK();
+  if (p.d <= kLdsMaxN) {
+    // Q = G R^-1 by Cholesky QR, done twice (the positive-diagonal QR factor)
+    double* Q = bufp<double>(p, ws, B_Q);
+    TPO_HIP_CHECK(hipMemcpyAsync(Q, bufp<double>(p, ws, B_G), sizeof(double) * p.d * p.d, hipMemcpyDeviceToDevice, s));
+    cholqr_lds(Q, p.d, p.d, p.d, &st->err_bits, s);
+    cholqr_lds(Q, p.d, p.d, p.d, &st->err_bits, s);
+    hipLaunchKernelGGL(k_transpose_f32, dim3(ceil_div(p.d * p.d, 256)), dim3(256), 0, s, Q, p.d,
+                       bufp<float>(p, ws, B_QT32));
+    TPO_LAUNCH_CHECK();
+  } else {
+    hipLaunchKernelGGL(k_q_from_g, dim3(1), dim3(kSmallThreads), 0, s, bufp<double>(p, ws, B_G), p.d,
+                       bufp<double>(p, ws, B_Q), bufp<double>(p, ws, B_SMALL_A), bufp<float>(p, ws, B_QT32),
+                       &st->err_bits);
+    TPO_LAUNCH_CHECK();
+  }
   if (p.d <= 64)
     features_impl<1>(p, ws, s);
   else
@@ -647,6 +701,23 @@ void launch_embed(const Plan& p, void* ws, hipStream_t s) {
   double* K = bufp<double>(p, ws, B_K);
   gram(bufp<float>(p, ws, B_R), p.n, p.twod, p.twod, p.gram_chunks_r, bufp<double>(p, ws, B_GRAM_PART), nullptr,
        K, nullptr, s);
+  if (p.kp <= kLdsMaxN) {
+    double* ma = bufp<double>(p, ws, B_M_A);
+    double* mb = bufp<double>(p, ws, B_M_B);
+    TPO_HIP_CHECK(hipMemcpyAsync(ma, bufp<double>(p, ws, B_OMEGA), sizeof(double) * p.twod * p.kp,
+                                 hipMemcpyDeviceToDevice, s));
+    for (int it = 0; it < p.par.q; ++it) {
+      gemm_f64(p.twod, p.kp, p.twod, K, p.twod, ma, p.kp, mb, p.kp, s);  // K M
+      cholqr_lds(mb, p.twod, p.kp, p.kp, &st->err_bits, s);
+      std::swap(ma, mb);
+    }
+    gemm_f64(p.twod, p.kp, p.twod, K, p.twod, ma, p.kp, mb, p.kp, s);
+    embed_final_lds(ma, mb, p.twod, p.kp, p.k, bufp<double>(p, ws, B_RCOLSUM), static_cast<int64_t>(p.n),
+                    bufp<double>(p, ws, B_EEVAL), bufp<float>(p, ws, B_S32), bufp<double>(p, ws, B_SIGMA),
+                    bufp<double>(p, ws, B_PSI), bufp<double>(p, ws, B_H), bufp<float>(p, ws, B_H32), &st->err_bits,
+                    s);
+    return;
+  }
   hipLaunchKernelGGL(k_embed_small, dim3(1), dim3(kSmallThreads), 0, s, K, bufp<double>(p, ws, B_OMEGA), p.twod,
                      p.kp, p.k, p.par.q, bufp<double>(p, ws, B_RCOLSUM), static_cast<int64_t>(p.n),
                      bufp<double>(p, ws, B_M_A), bufp<double>(p, ws, B_M_B), bufp<double>(p, ws, B_EK_A),

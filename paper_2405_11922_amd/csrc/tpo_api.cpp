@@ -161,6 +161,7 @@ void build_layout(Plan& p) {
   add(B_NCI_CNT, 4 * 3 * k);
   add(B_OBJ_ACC, 8 * k * twod);
   add(B_OBJ_CNT, 4 * k);
+  add(B_REDTMP, 8 * 16 * std::max(twod * k + k * k, twod));
   L.total = align256(cur);
 }
 

@@ -68,6 +68,7 @@ enum Buf {
   B_UPS, B_H, B_H32, B_RTU, B_UTU, B_A32, B_ONMF_PART,
   // nci / objective
   B_LABELS, B_NCI_ACC, B_NCI_CNT, B_OBJ_ACC, B_OBJ_CNT,
+  B_REDTMP,
   B_COUNT
 };
 
@@ -118,6 +119,16 @@ void launch_propagate(const Plan& p, void* ws, const float* xprime, int64_t ldxp
 void launch_reduce(const Plan& p, void* ws, const float* x, int64_t ldx, hipStream_t s);
 void launch_features(const Plan& p, void* ws, hipStream_t s);
 void launch_embed(const Plan& p, void* ws, hipStream_t s);
+// k_smallla.hip (single workgroup, small matrices in LDS, n <= 80)
+constexpr int kLdsMaxN = 80;
+void cholqr_lds(double* A, int m, int n, int lda, int32_t* err_bits, hipStream_t s);
+void rr_reduce_lds(const double* M, const double* P, int du, int l, int d, int dp, const double* colsum_x,
+                   int64_t n, double* evals, double* psi, float* psi32, hipStream_t s);
+void embed_final_lds(double* M, double* P, int twod, int kp, int k, const double* colsum_r, int64_t n, double* S,
+                     float* S32, double* sigma, double* psi, double* H, float* H32, int32_t* err_bits,
+                     hipStream_t s);
+// deterministic two-level sum of nparts rows of length len (k_dense.hip)
+void reduce_parts(const double* part, int nparts, int len, double* tmp, double* out, hipStream_t s);
 // k_cluster.hip
 void launch_onmf(const Plan& p, void* ws, hipStream_t s);
 void launch_nci(const Plan& p, void* ws, hipStream_t s);

@@ -38,6 +38,10 @@ CASES = {
                      dict(k=6, alpha=0.5, gamma=4, d=24)),
     # weighted edges with repeated pairs (summed), odd attribute width
     "weighted_dups": (_abg_with_dups, dict(k=4, alpha=0.7, gamma=3, d=0)),
+    # wide reduction (l_r = 110 > 80: the small matrices take the global-memory
+    # kernels), padded width 128, two output columns per lane in the features
+    "wide": (lambda: synth.planted_abg(2500, 2000, 30_000, 8, 160, zipf_a=2.0, seed=6),
+             dict(k=8, alpha=0.6, gamma=3, d=100)),
     # heavy hubs on both sides (rows split into chunks)
     "hubs": (lambda: synth.planted_abg(1500, 1200, 60_000, 3, 16, zipf_a=1.5, max_degree=1000, seed=3),
              dict(k=3, alpha=0.5, gamma=3, d=0)),
