@@ -51,6 +51,9 @@ def main() -> int:
     ap.add_argument("--config", default="mid_fp32")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-baseline", default="on", choices=["on", "off"])
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also copy a 256 MiB buffer once (a kernel of known traffic, to scale "
+                         "hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -84,6 +87,12 @@ def main() -> int:
     emb = torch.empty(abg.n_u, shape.k, dtype=torch.float32, device=dev)
     d_eff, l_r, kp = tpo.tpo_plan_dims(plan.handle)
 
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         tpo.tpo_execute(plan.handle, eu, ev, x, plan.workspace, labels, emb)
     torch.cuda.synchronize()

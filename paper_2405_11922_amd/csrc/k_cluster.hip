@@ -13,115 +13,178 @@
 
 namespace tpo {
 
-constexpr int kTR = 32;  // rows per LDS tile in the row passes
-
 enum RowPassMode { kProject = 0, kOnmf = 1 };
 
-// MODE kProject: O = R S (Gamma), written to out and out2 (Upsilon = Gamma).
-// MODE kOnmf:    P = R H, Q = U A with A = U^T R H,
-//                O = U * sqrt(P / Q)  (Eq. update-Y; zero denominator keeps
-//                U, negative ratio gives 0), written in place of U.
-// Both accumulate per workgroup, in FP64 across tiles, the entries of R^T O
-// (2d x k) followed by O^T O (k x k).
-template <int MODE, int NE>
+typedef float v4f_t __attribute__((ext_vector_type(4)));
+
+// Row passes on FP32 MFMA (v_mfma_f32_16x16x4f32: lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16], its v-th result is
+// D[4 (l / 16) + v][l % 16]).
+//
+// A workgroup walks 16-row tiles of R (rows padded to TD = 16 JT columns,
+// zeros beyond 2d).  Waves w < KT form output tile w of the 16 x k block:
+//   kProject: O = R S            (Gamma; also written as Upsilon)
+//   kOnmf:    P = R H, Q = U A,  O = U * sqrt(P / Q)   (Eq. update-Y; a zero
+//             denominator keeps U, a negative ratio gives 0)
+// then all waves accumulate R^T O (2d x k) and O^T O (k x k) tiles in FP32
+// registers over the workgroup's rows; the totals are written as FP64 partials.
+template <int MODE, int JT, int KT>
 __global__ void __launch_bounds__(256)
-k_rowpass(const float* __restrict__ R, int64_t n, int twod, int k, const float* __restrict__ Sm,
-          const float* __restrict__ A32, float* __restrict__ U, float* __restrict__ out, float* __restrict__ out2,
-          int rows_per_block, double* __restrict__ part, DevStatus* __restrict__ st) {
-  extern __shared__ float sm[];
-  float* Ss = sm;                          // twod x k
-  float* As = Ss + twod * k;               // k x k
-  float* Rt = As + k * k;                  // kTR x twod
-  float* Ut = Rt + kTR * twod;             // kTR x k
-  float* Ot = Ut + kTR * k;                // kTR x k
-  const int tid = threadIdx.x;
-  for (int e = tid; e < twod * k; e += 256) Ss[e] = Sm[e];
-  if (MODE == kOnmf)
-    for (int e = tid; e < k * k; e += 256) As[e] = A32[e];
-  double acc[NE];
+k_rowpass_mfma(const float* __restrict__ R, int64_t n, int twod, int k, const float* __restrict__ Sm,
+               const float* __restrict__ A32, float* __restrict__ U, float* __restrict__ out,
+               float* __restrict__ out2, int rows_per_block, double* __restrict__ part,
+               DevStatus* __restrict__ st) {
+  constexpr int TD = 16 * JT, KP = 16 * KT;
+  constexpr int RS = TD + 4, OS = KP + 4;
+  constexpr int NQ = (JT * KT + 3) / 4, NQ2 = (KT * KT + 3) / 4;
+  __shared__ float Rt[16 * RS];
+  __shared__ float Ut[16 * OS];
+  __shared__ float Ot[16 * OS];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int i16 = lane & 15, kq = lane >> 4;
+  float sb[TD / 4];
 #pragma unroll
-  for (int i = 0; i < NE; ++i) acc[i] = 0.0;
-  const int nrt = twod * k, nkk = k * k;
+  for (int t = 0; t < TD / 4; ++t) {
+    const int r = 4 * t + kq, c = 16 * w + i16;
+    sb[t] = (w < KT && r < twod && c < k) ? Sm[r * k + c] : 0.0f;
+  }
+  float ab[KP / 4];
+#pragma unroll
+  for (int t = 0; t < KP / 4; ++t) {
+    const int r = 4 * t + kq, c = 16 * w + i16;
+    ab[t] = (MODE == kOnmf && w < KT && r < k && c < k) ? A32[r * k + c] : 0.0f;
+  }
+  v4f_t acc[NQ], acc2[NQ2];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) acc[q] = v4f_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int q = 0; q < NQ2; ++q) acc2[q] = v4f_t{0.f, 0.f, 0.f, 0.f};
   float mx = 0.0f;
   int hits = 0;
   bool bad = false;
   const int64_t rb = static_cast<int64_t>(blockIdx.x) * rows_per_block;
   const int64_t re = min(n, rb + rows_per_block);
-  __syncthreads();
-  for (int64_t r0 = rb; r0 < re; r0 += kTR) {
-    const int nr = static_cast<int>(min(static_cast<int64_t>(kTR), re - r0));
-    for (int e = tid; e < kTR * twod; e += 256) {
-      const int rr = e / twod;
-      Rt[e] = rr < nr ? R[(r0 + rr) * twod + (e - rr * twod)] : 0.0f;
+  for (int64_t r0 = rb; r0 < re; r0 += 16) {
+    for (int e = tid; e < 16 * TD; e += 256) {
+      const int rr = e / TD, c = e - rr * TD;
+      const int64_t row = r0 + rr;
+      Rt[rr * RS + c] = (row < re && c < twod) ? R[row * twod + c] : 0.0f;
     }
     if (MODE == kOnmf)
-      for (int e = tid; e < kTR * k; e += 256) {
-        const int rr = e / k;
-        Ut[e] = rr < nr ? U[(r0 + rr) * k + (e - rr * k)] : 0.0f;
+      for (int e = tid; e < 16 * KP; e += 256) {
+        const int rr = e / KP, c = e - rr * KP;
+        const int64_t row = r0 + rr;
+        Ut[rr * OS + c] = (row < re && c < k) ? U[row * k + c] : 0.0f;
       }
     __syncthreads();
-    for (int e = tid; e < kTR * k; e += 256) {
-      const int rr = e / k, c = e - (e / k) * k;
-      float o = 0.0f;
-      if (rr < nr) {
-        float pv = 0.0f;
-        for (int j = 0; j < twod; ++j) pv = fmaf(Rt[rr * twod + j], Ss[j * k + c], pv);
+    if (w < KT) {
+      v4f_t pv = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int t = 0; t < TD / 4; ++t)
+        pv = __builtin_amdgcn_mfma_f32_16x16x4f32(Rt[i16 * RS + 4 * t + kq], sb[t], pv, 0, 0, 0);
+      v4f_t qv = {0.f, 0.f, 0.f, 0.f};
+      if (MODE == kOnmf) {
+#pragma unroll
+        for (int t = 0; t < KP / 4; ++t)
+          qv = __builtin_amdgcn_mfma_f32_16x16x4f32(Ut[i16 * OS + 4 * t + kq], ab[t], qv, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int rl = 4 * kq + v, c = 16 * w + i16;
+        const int64_t row = r0 + rl;
+        const bool live = row < re && c < k;
+        float o;
         if (MODE == kProject) {
-          o = pv;
+          o = pv[v];
         } else {
-          float qv = 0.0f;
-          for (int t = 0; t < k; ++t) qv = fmaf(Ut[rr * k + t], As[t * k + c], qv);
-          const float u = Ut[rr * k + c];
-          if (qv == 0.0f) {
+          const float u = Ut[rl * OS + c];
+          if (qv[v] == 0.0f) {
             o = u;
-            ++hits;
+            hits += live ? 1 : 0;
           } else {
-            const float ratio = pv / qv;
+            const float ratio = pv[v] / qv[v];
             if (ratio < 0.0f) {
               o = 0.0f;
-              ++hits;
+              hits += live ? 1 : 0;
             } else {
               o = u * sqrtf(ratio);
             }
           }
         }
-        if (!isfinite(o)) bad = true;
-        mx = fmaxf(mx, fabsf(o));
-        const int64_t gi = (r0 + rr) * k + c;
-        if (MODE == kProject) {
-          out[gi] = o;
-          out2[gi] = o;
-        } else {
-          U[gi] = o;
+        if (!live) o = 0.0f;
+        Ot[rl * OS + c] = o;
+        if (live) {
+          if (!isfinite(o)) bad = true;
+          mx = fmaxf(mx, fabsf(o));
+          const int64_t gi = row * k + c;
+          if (MODE == kProject) {
+            out[gi] = o;
+            out2[gi] = o;
+          } else {
+            U[gi] = o;
+          }
         }
       }
-      Ot[e] = o;
     }
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < NE; ++i) {
-      const int e = tid + 256 * i;
-      float s = 0.0f;
-      if (e < nrt) {
-        const int j = e / k, c = e - (e / k) * k;
-        for (int rr = 0; rr < kTR; ++rr) s = fmaf(Rt[rr * twod + j], Ot[rr * k + c], s);
-      } else if (e < nrt + nkk) {
-        const int a = (e - nrt) / k, b = (e - nrt) - ((e - nrt) / k) * k;
-        for (int rr = 0; rr < kTR; ++rr) s = fmaf(Ot[rr * k + a], Ot[rr * k + b], s);
+    for (int qi = 0; qi < NQ; ++qi) {
+      const int q = w + 4 * qi;
+      if (q < JT * KT) {
+        const int jt = q / KT, kt = q - (q / KT) * KT;
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          const int rr = 4 * s4 + kq;
+          acc[qi] = __builtin_amdgcn_mfma_f32_16x16x4f32(Rt[rr * RS + 16 * jt + i16], Ot[rr * OS + 16 * kt + i16],
+                                                         acc[qi], 0, 0, 0);
+        }
       }
-      acc[i] += static_cast<double>(s);
+    }
+#pragma unroll
+    for (int qi = 0; qi < NQ2; ++qi) {
+      const int q = w + 4 * qi;
+      if (q < KT * KT) {
+        const int ta = q / KT, tb = q - (q / KT) * KT;
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          const int rr = 4 * s4 + kq;
+          acc2[qi] = __builtin_amdgcn_mfma_f32_16x16x4f32(Ot[rr * OS + 16 * ta + i16], Ot[rr * OS + 16 * tb + i16],
+                                                          acc2[qi], 0, 0, 0);
+        }
+      }
     }
     __syncthreads();
   }
+  const int len = twod * k + k * k;
+  double* pb = part + static_cast<int64_t>(blockIdx.x) * len;
 #pragma unroll
-  for (int i = 0; i < NE; ++i) {
-    const int e = tid + 256 * i;
-    if (e < nrt + nkk) part[static_cast<int64_t>(blockIdx.x) * (nrt + nkk) + e] = acc[i];
+  for (int qi = 0; qi < NQ; ++qi) {
+    const int q = w + 4 * qi;
+    if (q < JT * KT) {
+      const int jt = q / KT, kt = q - (q / KT) * KT;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int j = 16 * jt + 4 * kq + v, c = 16 * kt + i16;
+        if (j < twod && c < k) pb[j * k + c] = static_cast<double>(acc[qi][v]);
+      }
+    }
+  }
+#pragma unroll
+  for (int qi = 0; qi < NQ2; ++qi) {
+    const int q = w + 4 * qi;
+    if (q < KT * KT) {
+      const int ta = q / KT, tb = q - (q / KT) * KT;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int a = 16 * ta + 4 * kq + v, c = 16 * tb + i16;
+        if (a < k && c < k) pb[twod * k + a * k + c] = static_cast<double>(acc2[qi][v]);
+      }
+    }
   }
   if (hits) atomicAdd(&st->guard_hits, hits);
   if (bad) atomicOr(&st->err_bits, 32);
   mx = wave_max(mx);
-  if ((tid & 63) == 0) atomic_max_nonneg(&st->maxabs_ups_bits, mx);
+  if (lane == 0) atomic_max_nonneg(&st->maxabs_ups_bits, mx);
 }
 
 // H update (Eq. update-Q) and A = (R^T U)^T H_new for the U update.
@@ -159,32 +222,44 @@ k_onmf_small(const double* __restrict__ rtu_utu, int twod, int k, double* __rest
   if (hits) atomicAdd(&st->guard_hits, hits);
 }
 
-template <int NE>
-static void rowpass(const Plan& p, void* ws, int mode, const float* Sm, const float* A32, hipStream_t s) {
+template <int JT, int KT>
+static void rowpass_jk(const Plan& p, void* ws, int mode, const float* Sm, const float* A32, hipStream_t s) {
   DevStatus* st = bufp<DevStatus>(p, ws, B_STATUS);
   const int nb = p.rowpass_blocks;
   const int rpb = static_cast<int>((p.n + nb - 1) / nb);
-  const size_t lds = sizeof(float) * (p.twod * p.k + p.k * p.k + kTR * p.twod + 2 * kTR * p.k);
   if (mode == kProject)
-    hipLaunchKernelGGL((k_rowpass<kProject, NE>), dim3(nb), dim3(256), lds, s, bufp<float>(p, ws, B_R),
+    hipLaunchKernelGGL((k_rowpass_mfma<kProject, JT, KT>), dim3(nb), dim3(256), 0, s, bufp<float>(p, ws, B_R),
                        static_cast<int64_t>(p.n), p.twod, p.k, Sm, A32, bufp<float>(p, ws, B_UPS),
                        bufp<float>(p, ws, B_GAMMA), bufp<float>(p, ws, B_UPS), rpb,
                        bufp<double>(p, ws, B_ONMF_PART), st);
   else
-    hipLaunchKernelGGL((k_rowpass<kOnmf, NE>), dim3(nb), dim3(256), lds, s, bufp<float>(p, ws, B_R),
+    hipLaunchKernelGGL((k_rowpass_mfma<kOnmf, JT, KT>), dim3(nb), dim3(256), 0, s, bufp<float>(p, ws, B_R),
                        static_cast<int64_t>(p.n), p.twod, p.k, Sm, A32, bufp<float>(p, ws, B_UPS), nullptr,
                        nullptr, rpb, bufp<double>(p, ws, B_ONMF_PART), st);
   TPO_LAUNCH_CHECK();
 }
 
-static void rowpass_any(const Plan& p, void* ws, int mode, const float* Sm, const float* A32, hipStream_t s) {
-  const int ne = (p.twod * p.k + p.k * p.k + 255) / 256;
-  if (ne <= 16)
-    rowpass<16>(p, ws, mode, Sm, A32, s);
-  else if (ne <= 48)
-    rowpass<48>(p, ws, mode, Sm, A32, s);
+template <int JT>
+static void rowpass_j(const Plan& p, void* ws, int mode, const float* Sm, const float* A32, hipStream_t s) {
+  if (p.k <= 16)
+    rowpass_jk<JT, 1>(p, ws, mode, Sm, A32, s);
+  else if (p.k <= 32)
+    rowpass_jk<JT, 2>(p, ws, mode, Sm, A32, s);
   else
-    rowpass<96>(p, ws, mode, Sm, A32, s);
+    rowpass_jk<JT, 4>(p, ws, mode, Sm, A32, s);
+}
+
+static void rowpass_any(const Plan& p, void* ws, int mode, const float* Sm, const float* A32, hipStream_t s) {
+  if (p.twod <= 16)
+    rowpass_j<1>(p, ws, mode, Sm, A32, s);
+  else if (p.twod <= 32)
+    rowpass_j<2>(p, ws, mode, Sm, A32, s);
+  else if (p.twod <= 64)
+    rowpass_j<4>(p, ws, mode, Sm, A32, s);
+  else if (p.twod <= 128)
+    rowpass_j<8>(p, ws, mode, Sm, A32, s);
+  else
+    rowpass_j<16>(p, ws, mode, Sm, A32, s);
 }
 
 void launch_onmf(const Plan& p, void* ws, hipStream_t s) {
