@@ -121,10 +121,10 @@ def main() -> int:
     u_avg = st["ms_spmm_u"] / max(st["n_spmm_u"], 1)
     v_avg = st["ms_spmm_v"] / max(st["n_spmm_v"], 1)
     if u_avg >= v_avg:
-        kern, per, avg = "k_spmm_rows<64,U> (Z = X' + alpha D_U^-1/2 B T)", spmm_u_bytes(
+        kern, per, avg = "k_spmm_rowgroup<64,U> (Z = X' + alpha D_U^-1/2 B T)", spmm_u_bytes(
             abg.n_u, abg.n_v, e_u, d_eff, has_vals), u_avg
     else:
-        kern, per, avg = "k_spmm_rows<64,V> (T = D_V^-1 B^T W)", spmm_v_bytes(
+        kern, per, avg = "k_spmm_rowgroup<64,V> (T = D_V^-1 B^T W)", spmm_v_bytes(
             abg.n_u, abg.n_v, e_u, d_eff, has_vals), v_avg
     achieved = per / (avg * 1e-3) / 1e9
     roofline = {"kernel": kern, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,

@@ -8,13 +8,15 @@
 // and the last hop stores (1 - alpha) Z, which is Eq. PX.  Isolated nodes have
 // zero scales, so an isolated u keeps Z[u] = X'[u] (the r = 0 term alone).
 //
-// Kernel shape (d-wide FP32 rows, d a power of two): one wave per output row;
-// a neighbour row of d floats is read by d/4 lanes with float4 loads, so one
-// wave instruction gathers 64/(d/4) neighbour rows.  Column indices are read
-// 64 at a time with one coalesced load and handed to the lane groups with
+// Kernel shape (d-wide FP32 rows, d a power of two): a neighbour row of d
+// floats is read by a group of d/4 lanes with float4 loads.  Ordinary rows
+// (at most kHubChunk neighbours) take one lane group each, so a wave works on
+// 64/(d/4) output rows at once and keeps several gathers in flight per lane;
+// their column ids come in with one load per group and are handed out with
 // cross-lane permutes.  Rows with more than kHubChunk neighbours are split
-// into chunks (one wave each) whose partial sums a second kernel adds in chunk
-// order, so every sum has a fixed order (bitwise reproducible).
+// into chunks of one wave each, in the same launch; a second kernel adds the
+// chunk partials in chunk order, so every sum has a fixed order (bitwise
+// reproducible).
 #include "dev_common.hpp"
 #include "tpo_internal.hpp"
 
@@ -103,31 +105,105 @@ __device__ __forceinline__ void spmm_epilogue(int r, float4 acc, const float* __
   *reinterpret_cast<float4*>(dst + static_cast<int64_t>(r) * D + q * 4) = o;
 }
 
-// Items [0, nrows): rows (hub rows skipped); items [nrows, nrows + n_chunks):
-// hub chunks writing partial sums.
+// One row per lane group: the LPR = D/4 lanes of a group own float4 column
+// slices of the output row, so no cross-group reduction is needed; a wave
+// carries 64/LPR rows at once.  Column ids come 16 (or LPR) at a time from
+// one load by the group and are handed out with cross-lane permutes.
+template <int D>
+__device__ __forceinline__ float4 gather_row_group(const int32_t* __restrict__ col, const float* __restrict__ val,
+                                                   bool has_vals, const float* __restrict__ src, int b, int e) {
+  using S = SpmmShape<D>;
+  constexpr int U = S::LPR >= 16 ? 4 : 8;  // loads in flight per lane
+  const int lane = threadIdx.x & 63;
+  const int q = lane % S::LPR;
+  const int g0 = lane - q;  // first lane of this group
+  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int base = b; base < e; base += S::LPR) {
+    const int cnt = min(S::LPR, e - base);
+    const int myidx = q < cnt ? col[base + q] : 0;
+    const float myval = (has_vals && q < cnt) ? val[base + q] : 1.0f;
+    for (int j0 = 0; j0 < cnt; j0 += U) {
+      float4 x[U];
+      float wv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = j0 + u;
+        const int jj = j < S::LPR ? j : S::LPR - 1;
+        int nb = __shfl(myidx, g0 + jj, 64);
+        const float w = has_vals ? __shfl(myval, g0 + jj, 64) : 1.0f;
+        if (j >= cnt) nb = myidx;
+        x[u] = *reinterpret_cast<const float4*>(src + static_cast<int64_t>(nb) * D + q * 4);
+        wv[u] = (j < cnt) ? w : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (j0 + u < cnt) {
+          acc.x += wv[u] * x[u].x;
+          acc.y += wv[u] * x[u].y;
+          acc.z += wv[u] * x[u].z;
+          acc.w += wv[u] * x[u].w;
+        }
+      }
+    }
+  }
+  return acc;
+}
+
+template <int D, int MODE>
+__device__ __forceinline__ void spmm_epilogue_group(int r, float4 acc, const float* __restrict__ rscale,
+                                                    const float* __restrict__ xp, float alpha,
+                                                    float one_minus_alpha, float* __restrict__ dst) {
+  const int q = (threadIdx.x & 63) % SpmmShape<D>::LPR;
+  const float sc = rscale[r];
+  float4 o;
+  if (MODE == kModeV) {
+    o = make_float4(sc * acc.x, sc * acc.y, sc * acc.z, sc * acc.w);
+  } else {
+    const float4 x = *reinterpret_cast<const float4*>(xp + static_cast<int64_t>(r) * D + q * 4);
+    const float f = alpha * sc;
+    float4 z = make_float4(x.x + f * acc.x, x.y + f * acc.y, x.z + f * acc.z, x.w + f * acc.w);
+    if (MODE == kModeUMid)
+      o = make_float4(sc * z.x, sc * z.y, sc * z.z, sc * z.w);
+    else
+      o = make_float4(one_minus_alpha * z.x, one_minus_alpha * z.y, one_minus_alpha * z.z,
+                      one_minus_alpha * z.w);
+  }
+  *reinterpret_cast<float4*>(dst + static_cast<int64_t>(r) * D + q * 4) = o;
+}
+
+// One launch per SpMM side.  Blocks [0, chunk_blocks) take the hub chunks
+// (one wave per chunk, partial sums to `partial`); the remaining blocks take
+// the rows with at most kHubChunk neighbours, one row per lane group.
 template <int D, int MODE>
 __global__ void __launch_bounds__(256)
-k_spmm_rows(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col, const float* __restrict__ val,
-            const DevStatus* __restrict__ st, const int32_t* __restrict__ n_chunks, const int4* __restrict__ chunks,
-            const float* __restrict__ src, int nrows, const float* __restrict__ rscale,
-            const float* __restrict__ xp, float alpha, float one_minus_alpha, float* __restrict__ dst,
-            float* __restrict__ partial) {
-  const int item = static_cast<int>((static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6);
+k_spmm_rowgroup(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col, const float* __restrict__ val,
+                const DevStatus* __restrict__ st, const int32_t* __restrict__ n_chunks,
+                const int4* __restrict__ chunks, int chunk_blocks, const float* __restrict__ src, int nrows,
+                const float* __restrict__ rscale, const float* __restrict__ xp, float alpha, float one_minus_alpha,
+                float* __restrict__ dst, float* __restrict__ partial) {
+  constexpr int LPR = SpmmShape<D>::LPR;
   const bool has_vals = st->has_vals != 0;
-  if (item < nrows) {
-    const int b = rowptr[item], e = rowptr[item + 1];
-    if (e - b > kHubChunk) return;
-    const float4 acc = gather_sum<D>(col, val, has_vals, src, b, e);
-    spmm_epilogue<D, MODE>(item, acc, rscale, xp, alpha, one_minus_alpha, dst);
-  } else {
-    const int c = item - nrows;
+  if (static_cast<int>(blockIdx.x) < chunk_blocks) {
+    const int c = static_cast<int>((static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6);
     if (c >= *n_chunks) return;
     const int4 ch = chunks[c];
     const float4 acc = gather_sum<D>(col, val, has_vals, src, ch.y, ch.z);
     const int lane = threadIdx.x & 63;
-    if (lane < SpmmShape<D>::LPR)
-      *reinterpret_cast<float4*>(partial + static_cast<int64_t>(ch.w) * D + lane * 4) = acc;
+    if (lane < LPR) *reinterpret_cast<float4*>(partial + static_cast<int64_t>(ch.w) * D + lane * 4) = acc;
+    return;
   }
+  const int64_t gidx =
+      (static_cast<int64_t>(blockIdx.x - chunk_blocks) * blockDim.x + threadIdx.x) / LPR;
+  const int r = static_cast<int>(gidx);
+  int b = 0, e = 0;
+  const bool live = r < nrows;
+  if (live) {
+    b = rowptr[r];
+    e = rowptr[r + 1];
+  }
+  const bool mine = live && e - b <= kHubChunk;
+  const float4 acc = gather_row_group<D>(col, val, has_vals, src, b, mine ? e : b);
+  if (mine) spmm_epilogue_group<D, MODE>(r, acc, rscale, xp, alpha, one_minus_alpha, dst);
 }
 
 // One wave per hub row: add its chunk partials in order, then the epilogue.
@@ -184,19 +260,22 @@ static void propagate_impl(const Plan& p, void* ws, const float* xp, hipStream_t
   hipLaunchKernelGGL(k_scale_rows, dim3(ceil_div(static_cast<int64_t>(n) * D, 256)), dim3(256), 0, s, xp, n, D,
                      isq, 1.0f, w0);
   TPO_LAUNCH_CHECK();
-  const unsigned grid_v = ceil_div((static_cast<int64_t>(m) + p.max_chunks_v) * 64, 256);
-  const unsigned grid_u = ceil_div((static_cast<int64_t>(n) + p.max_chunks_u) * 64, 256);
-  const unsigned hub_v = ceil_div(static_cast<int64_t>(p.max_chunks_v) * 64, 256);
-  const unsigned hub_u = ceil_div(static_cast<int64_t>(p.max_chunks_u) * 64, 256);
+  constexpr int LPR = SpmmShape<D>::LPR;
+  const unsigned ch_v = ceil_div(static_cast<int64_t>(p.max_chunks_v) * 64, 256);
+  const unsigned ch_u = ceil_div(static_cast<int64_t>(p.max_chunks_u) * 64, 256);
+  const unsigned grid_v = ch_v + ceil_div(static_cast<int64_t>(m) * LPR, 256);
+  const unsigned grid_u = ch_u + ceil_div(static_cast<int64_t>(n) * LPR, 256);
+  const unsigned hub_v = ch_v, hub_u = ch_u;
   float* cur = w0;
   float* nxt = w1;
   for (int hop = 1; hop <= p.par.gamma; ++hop) {
     const bool tm = p.timing && p.kev_made && hop <= kMaxTimedHops;
     const hipEvent_t* ev = p.kev + 4 * (hop - 1);
+    // V side: T = D_V^-1 B^T W
     if (tm) TPO_HIP_CHECK(hipEventRecord(ev[0], s));
-    hipLaunchKernelGGL((k_spmm_rows<D, kModeV>), dim3(grid_v), dim3(256), 0, s,
-                       bufp<int32_t>(p, ws, B_ROWPTR_V), bufp<int32_t>(p, ws, B_COL_V), bufp<float>(p, ws, B_VAL_V),
-                       st, &st->hub_chunks_v, bufp<int4>(p, ws, B_CHUNK_V), cur, m, invv, nullptr, alpha, oma, t,
+    hipLaunchKernelGGL((k_spmm_rowgroup<D, kModeV>), dim3(grid_v), dim3(256), 0, s, bufp<int32_t>(p, ws, B_ROWPTR_V),
+                       bufp<int32_t>(p, ws, B_COL_V), bufp<float>(p, ws, B_VAL_V), st, &st->hub_chunks_v,
+                       bufp<int4>(p, ws, B_CHUNK_V), static_cast<int>(ch_v), cur, m, invv, nullptr, alpha, oma, t,
                        partial);
     TPO_LAUNCH_CHECK();
     if (tm) TPO_HIP_CHECK(hipEventRecord(ev[1], s));
@@ -205,35 +284,32 @@ static void propagate_impl(const Plan& p, void* ws, const float* xp, hipStream_t
                          bufp<int4>(p, ws, B_HUBLIST_V), partial, invv, nullptr, alpha, oma, t);
       TPO_LAUNCH_CHECK();
     }
+    // U side: Z = X' + alpha D_U^-1/2 B T  (W = D_U^-1/2 Z between hops)
     const bool last = hop == p.par.gamma;
     float* dst = last ? z : nxt;
     if (tm) TPO_HIP_CHECK(hipEventRecord(ev[2], s));
-    if (last) {
-      hipLaunchKernelGGL((k_spmm_rows<D, kModeUFinal>), dim3(grid_u), dim3(256), 0, s,
-                         bufp<int32_t>(p, ws, B_ROWPTR_U), bufp<int32_t>(p, ws, B_COL_U),
-                         bufp<float>(p, ws, B_VAL_U), st, &st->hub_chunks_u, bufp<int4>(p, ws, B_CHUNK_U), t, n,
-                         isq, xp, alpha, oma, dst, partial);
-      TPO_LAUNCH_CHECK();
-      if (tm) TPO_HIP_CHECK(hipEventRecord(ev[3], s));
-      if (p.max_chunks_u > 0) {
+    if (last)
+      hipLaunchKernelGGL((k_spmm_rowgroup<D, kModeUFinal>), dim3(grid_u), dim3(256), 0, s,
+                         bufp<int32_t>(p, ws, B_ROWPTR_U), bufp<int32_t>(p, ws, B_COL_U), bufp<float>(p, ws, B_VAL_U),
+                         st, &st->hub_chunks_u, bufp<int4>(p, ws, B_CHUNK_U), static_cast<int>(ch_u), t, n, isq, xp,
+                         alpha, oma, dst, partial);
+    else
+      hipLaunchKernelGGL((k_spmm_rowgroup<D, kModeUMid>), dim3(grid_u), dim3(256), 0, s,
+                         bufp<int32_t>(p, ws, B_ROWPTR_U), bufp<int32_t>(p, ws, B_COL_U), bufp<float>(p, ws, B_VAL_U),
+                         st, &st->hub_chunks_u, bufp<int4>(p, ws, B_CHUNK_U), static_cast<int>(ch_u), t, n, isq, xp,
+                         alpha, oma, dst, partial);
+    TPO_LAUNCH_CHECK();
+    if (tm) TPO_HIP_CHECK(hipEventRecord(ev[3], s));
+    if (p.max_chunks_u > 0) {
+      if (last)
         hipLaunchKernelGGL((k_spmm_hubs<D, kModeUFinal>), dim3(hub_u), dim3(256), 0, s, &st->hub_rows_u,
                            bufp<int4>(p, ws, B_HUBLIST_U), partial, isq, xp, alpha, oma, dst);
-        TPO_LAUNCH_CHECK();
-      }
-    } else {
-      hipLaunchKernelGGL((k_spmm_rows<D, kModeUMid>), dim3(grid_u), dim3(256), 0, s,
-                         bufp<int32_t>(p, ws, B_ROWPTR_U), bufp<int32_t>(p, ws, B_COL_U),
-                         bufp<float>(p, ws, B_VAL_U), st, &st->hub_chunks_u, bufp<int4>(p, ws, B_CHUNK_U), t, n,
-                         isq, xp, alpha, oma, dst, partial);
-      TPO_LAUNCH_CHECK();
-      if (tm) TPO_HIP_CHECK(hipEventRecord(ev[3], s));
-      if (p.max_chunks_u > 0) {
+      else
         hipLaunchKernelGGL((k_spmm_hubs<D, kModeUMid>), dim3(hub_u), dim3(256), 0, s, &st->hub_rows_u,
                            bufp<int4>(p, ws, B_HUBLIST_U), partial, isq, xp, alpha, oma, dst);
-        TPO_LAUNCH_CHECK();
-      }
-      std::swap(cur, nxt);
+      TPO_LAUNCH_CHECK();
     }
+    if (!last) std::swap(cur, nxt);
   }
 }
 
