@@ -109,34 +109,36 @@ __device__ inline double blk_sum(double v, double* sh) {
   return r;
 }
 
+// Off-diagonal entries below this multiple of sqrt(|a_pp a_qq|) are treated
+// as converged (relative accuracy at the level of FP64 rounding).
+constexpr double kJacobiTol = 1e-16;
+
 // Cyclic Jacobi eigensolver for a symmetric n x n matrix A (in place; on exit
 // the diagonal holds the eigenvalues) with eigenvectors in the columns of V.
-// Parallel (round-robin) ordering: n/2 disjoint rotations per step.
-// sh: scratch of 3 * ((n + 1) / 2) + 1 doubles; red: blockDim.x doubles.
-__device__ inline void blk_jacobi(double* A, int lda, double* V, int ldv, int n, double* sh, double* red,
+// Parallel (round-robin) ordering: n/2 disjoint rotations per step, applied
+// as A <- J^T A J one 2 x 2 block (pair i rows, pair j columns) per thread,
+// with the annihilated entry of each rotated pair set to zero; stops after a
+// sweep that rotates nothing (or after max_sweeps).  Returns the number of
+// sweeps taken.
+// sh: scratch of 3 * ((n + 1) / 2) + 1 doubles; red: unused.
+__device__ inline int blk_jacobi(double* A, int lda, double* V, int ldv, int n, double* sh, double* red,
                                   int max_sweeps) {
+  (void)red;
   const int np = n + (n & 1);
   const int npairs = np / 2;
   double* cs = sh;               // c
   double* sn = sh + npairs;      // s
   int* pp = reinterpret_cast<int*>(sh + 2 * npairs);
   int* qq = pp + npairs;
+  int* rotated = qq + npairs;    // set when a sweep applied any rotation
   for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
     const int r = idx / n, c = idx % n;
     V[r * ldv + c] = (r == c) ? 1.0 : 0.0;
   }
-  __syncthreads();
-  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    // convergence: off-diagonal mass relative to the diagonal
-    double off = 0.0, dia = 0.0;
-    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
-      const int i = idx / n, j = idx % n;
-      const double v = A[i * lda + j];
-      if (i == j) dia += v * v; else off += v * v;
-    }
-    off = blk_sum(off, red);
-    dia = blk_sum(dia, red);
-    if (off <= 1e-30 * dia || off == 0.0) break;
+  int sweep = 0;
+  for (; sweep < max_sweeps; ++sweep) {
+    if (threadIdx.x == 0) *rotated = 0;
+    __syncthreads();
     for (int step = 0; step < np - 1; ++step) {
       for (int i = threadIdx.x; i < npairs; i += blockDim.x) {
         int p, q;
@@ -151,12 +153,15 @@ __device__ inline void blk_jacobi(double* A, int lda, double* V, int ldv, int n,
         double c = 1.0, s = 0.0;
         if (q < n) {
           const double apq = A[p * lda + q];
-          if (apq != 0.0) {
-            const double app = A[p * lda + p], aqq = A[q * lda + q];
+          const double app = A[p * lda + p], aqq = A[q * lda + q];
+          // rotate only while the pair is coupled above rounding level
+          if (fabs(apq) > kJacobiTol * sqrt(fabs(app * aqq)) && fabs(apq) > 1e-290) {
             const double tau = (aqq - app) / (2.0 * apq);
-            const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            const double t = fabs(tau) > 1e150 ? 0.5 / tau
+                                                : (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
             c = 1.0 / sqrt(1.0 + t * t);
             s = t * c;
+            if (s != 0.0) *rotated = 1;
           }
         }
         cs[i] = c;
@@ -165,43 +170,49 @@ __device__ inline void blk_jacobi(double* A, int lda, double* V, int ldv, int n,
         qq[i] = q < n ? q : -1;
       }
       __syncthreads();
-      // rows: A <- J^T A  (threads: 32 pair lanes x 32 column lanes)
-      {
-        const int tr = threadIdx.x >> 5, tcc = threadIdx.x & 31;
-        for (int i = tr; i < npairs; i += (blockDim.x >> 5)) {
-          const int q = qq[i];
-          if (q < 0 || sn[i] == 0.0) continue;
-          const int p = pp[i];
-          const double c = cs[i], s = sn[i];
-          for (int j = tcc; j < n; j += 32) {
-            const double apj = A[p * lda + j], aqj = A[q * lda + j];
-            A[p * lda + j] = c * apj - s * aqj;
-            A[q * lda + j] = s * apj + c * aqj;
-          }
+      // A <- J^T A J: rows of pair i by J_i^T, then columns of pair j by J_j
+      for (int e = threadIdx.x; e < npairs * npairs; e += blockDim.x) {
+        const int i = e / npairs, j = e - (e / npairs) * npairs;
+        const double si = sn[i], sj = sn[j];
+        if (si == 0.0 && sj == 0.0) continue;
+        const double ci = cs[i], cj = cs[j];
+        const int pi = pp[i], qi = qq[i], pj = pp[j], qj = qq[j];
+        const double a = A[pi * lda + pj];
+        const double b = qj >= 0 ? A[pi * lda + qj] : 0.0;
+        const double c = qi >= 0 ? A[qi * lda + pj] : 0.0;
+        const double d = (qi >= 0 && qj >= 0) ? A[qi * lda + qj] : 0.0;
+        const double a1 = ci * a - si * c, b1 = ci * b - si * d;
+        const double c1 = si * a + ci * c, d1 = si * b + ci * d;
+        double a2 = cj * a1 - sj * b1, b2 = sj * a1 + cj * b1;
+        double c2 = cj * c1 - sj * d1, d2 = sj * c1 + cj * d1;
+        if (i == j) {  // the rotated pair's own coupling is annihilated
+          b2 = 0.0;
+          c2 = 0.0;
         }
+        A[pi * lda + pj] = a2;
+        if (qj >= 0) A[pi * lda + qj] = b2;
+        if (qi >= 0) A[qi * lda + pj] = c2;
+        if (qi >= 0 && qj >= 0) A[qi * lda + qj] = d2;
       }
-      __syncthreads();
-      // columns: A <- A J, V <- V J
-      {
-        const int tr = threadIdx.x >> 5, tcc = threadIdx.x & 31;
-        for (int i = tr; i < npairs; i += (blockDim.x >> 5)) {
-          const int q = qq[i];
-          if (q < 0 || sn[i] == 0.0) continue;
-          const int p = pp[i];
-          const double c = cs[i], s = sn[i];
-          for (int r = tcc; r < n; r += 32) {
-            const double arp = A[r * lda + p], arq = A[r * lda + q];
-            A[r * lda + p] = c * arp - s * arq;
-            A[r * lda + q] = s * arp + c * arq;
-            const double vrp = V[r * ldv + p], vrq = V[r * ldv + q];
-            V[r * ldv + p] = c * vrp - s * vrq;
-            V[r * ldv + q] = s * vrp + c * vrq;
-          }
-        }
+      // V <- V J
+      for (int e = threadIdx.x; e < n * npairs; e += blockDim.x) {
+        const int r = e / npairs, i = e - (e / npairs) * npairs;
+        const double s = sn[i];
+        if (s == 0.0) continue;
+        const double c = cs[i];
+        const int p = pp[i], q = qq[i];
+        const double vp = V[r * ldv + p], vq = V[r * ldv + q];
+        V[r * ldv + p] = c * vp - s * vq;
+        V[r * ldv + q] = s * vp + c * vq;
       }
       __syncthreads();
     }
+    const int any = *rotated;
+    __syncthreads();
+    if (!any) break;
   }
+  __syncthreads();
+  return sweep;
 }
 
 // Order eigenpairs by decreasing eigenvalue (ties keep the lower index):

@@ -300,146 +300,175 @@ __device__ __forceinline__ long long to_fixed(float v, int sft) {
   return static_cast<long long>(llrint(ldexp(static_cast<double>(v), sft)));
 }
 
-// One round: scores = U Phi (FP64), l* = first argmax, labels written; when
-// `accumulate`, the fixed-point sums of U rows per label and the label
-// counts are added to acc_dst / cnt_dst.  Phi comes from the previous round's
-// sums (Phi[t][l] = sum_{i in C_l} U[i][t] / sqrt(|C_l|)) or is the identity.
+// Sum of per-block integer partials.  part holds len x nb values (entry o of
+// block b at part[o * nb + b]); one wave per entry.  Integer addition makes
+// the result independent of the order.
 __global__ void __launch_bounds__(256)
-k_nci_round(const float* __restrict__ U, int64_t n, int k, int identity, const long long* __restrict__ acc_src,
-            const int* __restrict__ cnt_src, long long* __restrict__ acc_dst, int* __restrict__ cnt_dst,
-            long long* __restrict__ acc_zero, int* __restrict__ cnt_zero, int accumulate,
-            int32_t* __restrict__ labels, int rows_per_block, const DevStatus* __restrict__ st) {
+k_sum_parts_i64(const long long* __restrict__ part, int nb, int len, long long* __restrict__ sum) {
+  const int o = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (o >= len) return;
+  long long acc = 0;
+  const long long* src = part + static_cast<int64_t>(o) * nb;
+  for (int b = lane; b < nb; b += 64) acc += src[b];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0) sum[o] = acc;
+}
+
+static void sum_parts_i64(const long long* part, int nb, int len, long long* sum, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_parts_i64, dim3(ceil_div(len, 4)), dim3(256), 0, s, part, nb, len, sum);
+  TPO_LAUNCH_CHECK();
+}
+
+// One round: scores = U Phi (FP64), l* = first argmax, labels written.  Phi
+// is the identity when `sums` is null, else Phi[t][l] = c_l[t] / sqrt(|C_l|)
+// with c_l the fixed-point sum of the U rows labelled l and |C_l| their count
+// (sums: k x k values c_l[t] at l * k + t, then k counts).  When `part` is
+// given, the block's own fixed-point sums and counts for the labels of this
+// round are written there (transposed, entry o at part[o * gridDim.x + block]).
+// KT: compile-time bound on k (scores live in registers).
+template <int KT>
+__global__ void __launch_bounds__(256)
+k_nci_round(const float* __restrict__ U, int64_t n, int k, const long long* __restrict__ sums,
+            long long* __restrict__ part, int32_t* __restrict__ labels, int rows_per_block,
+            const DevStatus* __restrict__ st) {
   extern __shared__ char smem_raw[];
-  double* phi = reinterpret_cast<double*>(smem_raw);                 // k x k
-  long long* accl = reinterpret_cast<long long*>(phi + k * k);        // k x k
-  int* cntl = reinterpret_cast<int*>(accl + k * k);                   // k
-  float* ut = reinterpret_cast<float*>(cntl + 64);                    // 4 x 64 x k
+  double* phi = reinterpret_cast<double*>(smem_raw);                 // k x k, phi[t * k + l]
+  long long* accl = reinterpret_cast<long long*>(phi + k * k);        // k x k sums, then k counts
+  float* ut = reinterpret_cast<float*>(accl + k * k + k);             // 4 waves x 64 rows x (k + 1)
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int kp1 = k + 1;  // odd row stride when k is even: lane-per-row reads avoid bank conflicts
   const int sft = fixed_point_shift(__uint_as_float(st->maxabs_ups_bits), n);
   const double inv_scale = ldexp(1.0, -sft);
   for (int e = tid; e < k * k; e += 256) {
     const int t = e / k, l = e % k;
     double v;
-    if (identity) {
+    if (!sums) {
       v = (t == l) ? 1.0 : 0.0;
     } else {
-      const int c = cnt_src[l];
-      v = c > 0 ? static_cast<double>(acc_src[l * k + t]) * inv_scale / sqrt(static_cast<double>(c)) : 0.0;
+      const long long c = sums[k * k + l];
+      v = c > 0 ? static_cast<double>(sums[l * k + t]) * inv_scale / sqrt(static_cast<double>(c)) : 0.0;
     }
     phi[e] = v;
-    accl[e] = 0;
   }
-  if (tid < 64) cntl[tid] = 0;
-  if (blockIdx.x == 0 && acc_zero) {
-    for (int e = tid; e < k * k; e += 256) acc_zero[e] = 0;
-    if (tid < k) cnt_zero[tid] = 0;
-  }
+  for (int e = tid; e < k * k + k; e += 256) accl[e] = 0;
   __syncthreads();
-  float* myut = ut + w * 64 * k;
+  float* myut = ut + w * 64 * kp1;
   const int64_t rb = static_cast<int64_t>(blockIdx.x) * rows_per_block;
   const int64_t re = min(n, rb + rows_per_block);
+  const int rpi = k <= 64 ? 64 / k : 1;  // rows per accumulation step
   for (int64_t b0 = rb + static_cast<int64_t>(w) * 64; b0 < re; b0 += 256) {
     const int nr = static_cast<int>(min(static_cast<int64_t>(64), re - b0));
-    for (int e = lane; e < nr * k; e += 64) myut[e] = U[b0 * k + e];
+    for (int e = lane; e < nr * k; e += 64) {
+      const int rr = e / k, t = e % k;
+      myut[rr * kp1 + t] = U[b0 * k + e];
+    }
     wave_sync();
     int best = 0;
     if (lane < nr) {
-      double bestv = 0.0;
-      for (int l = 0; l < k; ++l) {
-        double sc = 0.0;
-        for (int t = 0; t < k; ++t) sc = fma(static_cast<double>(myut[lane * k + t]), phi[t * k + l], sc);
-        if (l == 0 || sc > bestv) {
-          bestv = sc;
+      double sc[KT];
+#pragma unroll
+      for (int l = 0; l < KT; ++l) sc[l] = 0.0;
+      for (int t = 0; t < k; ++t) {
+        const double u = static_cast<double>(myut[lane * kp1 + t]);
+        const double* ph = phi + t * k;
+#pragma unroll
+        for (int l = 0; l < KT; ++l)
+          if (l < k) sc[l] = fma(u, ph[l], sc[l]);
+      }
+      double bestv = sc[0];
+#pragma unroll
+      for (int l = 1; l < KT; ++l)
+        if (l < k && sc[l] > bestv) {
+          bestv = sc[l];
           best = l;
         }
-      }
       labels[b0 + lane] = best;
     }
-    if (accumulate) {
-      for (int rr = 0; rr < nr; ++rr) {
-        const int lab = __shfl(best, rr, 64);
-        for (int t = lane; t < k; t += 64) atomicAdd(reinterpret_cast<unsigned long long*>(&accl[lab * k + t]),
-                                                     static_cast<unsigned long long>(to_fixed(myut[rr * k + t], sft)));
-        if (lane == 0) atomicAdd(&cntl[lab], 1);
+    if (part) {
+      const int g = lane / k, t = lane % k;
+      for (int r0 = 0; r0 < nr; r0 += rpi) {
+        const int rr = r0 + g;
+        const int lab = __shfl(best, rr < 64 ? rr : 63, 64);
+        if (g < rpi && rr < nr) {
+          atomicAdd(reinterpret_cast<unsigned long long*>(&accl[lab * k + t]),
+                    static_cast<unsigned long long>(to_fixed(myut[rr * kp1 + t], sft)));
+          if (t == 0) atomicAdd(reinterpret_cast<unsigned long long*>(&accl[k * k + lab]), 1ull);
+        }
       }
     }
     wave_sync();
   }
   __syncthreads();
-  if (accumulate) {
-    for (int e = tid; e < k * k; e += 256)
-      if (accl[e] != 0)
-        atomicAdd(reinterpret_cast<unsigned long long*>(&acc_dst[e]), static_cast<unsigned long long>(accl[e]));
-    if (tid < k && cntl[tid] != 0) atomicAdd(&cnt_dst[tid], cntl[tid]);
+  if (part) {
+    for (int e = tid; e < k * k + k; e += 256) part[static_cast<int64_t>(e) * gridDim.x + blockIdx.x] = accl[e];
   }
 }
 
-__global__ void k_zero_ll(long long* __restrict__ a, int na, int* __restrict__ b, int nb) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < na) a[i] = 0;
-  if (i < nb) b[i] = 0;
+template <int KT>
+static void nci_rounds(const Plan& p, void* ws, hipStream_t s) {
+  DevStatus* st = bufp<DevStatus>(p, ws, B_STATUS);
+  const int k = p.k;
+  long long* part = bufp<long long>(p, ws, B_NCI_PART);
+  long long* sums = bufp<long long>(p, ws, B_NCI_SUM);
+  const int nb = p.rowpass_blocks;
+  const int rpb = static_cast<int>((p.n + nb - 1) / nb);
+  const size_t lds = sizeof(double) * k * k + sizeof(long long) * (k * k + k) + sizeof(float) * 4 * 64 * (k + 1);
+  const float* U = bufp<float>(p, ws, B_UPS);
+  int32_t* labels = bufp<int32_t>(p, ws, B_LABELS);
+  const int rounds = std::max(p.par.t_g, 1);
+  for (int t = 1; t <= rounds; ++t) {
+    // round 1 (and T_g = 0) scores against Phi = I; every round but the last
+    // feeds the label sums to the next
+    const bool acc = t < p.par.t_g;
+    hipLaunchKernelGGL((k_nci_round<KT>), dim3(nb), dim3(256), lds, s, U, static_cast<int64_t>(p.n), k,
+                       t == 1 ? nullptr : sums, acc ? part : nullptr, labels, rpb, st);
+    TPO_LAUNCH_CHECK();
+    if (acc) sum_parts_i64(part, nb, k * k + k, sums, s);
+  }
 }
 
 void launch_nci(const Plan& p, void* ws, hipStream_t s) {
-  DevStatus* st = bufp<DevStatus>(p, ws, B_STATUS);
-  const int k = p.k;
-  long long* acc = bufp<long long>(p, ws, B_NCI_ACC);
-  int* cnt = bufp<int>(p, ws, B_NCI_CNT);
-  const int nb = p.rowpass_blocks;
-  const int rpb = static_cast<int>((p.n + nb - 1) / nb);
-  const size_t lds = sizeof(double) * k * k + sizeof(long long) * k * k + sizeof(int) * 64 + sizeof(float) * 4 * 64 * k;
-  hipLaunchKernelGGL(k_zero_ll, dim3(ceil_div(3 * k * k, 256)), dim3(256), 0, s, acc, 3 * k * k, cnt, 3 * k);
-  TPO_LAUNCH_CHECK();
-  const float* U = bufp<float>(p, ws, B_UPS);
-  int32_t* labels = bufp<int32_t>(p, ws, B_LABELS);
-  if (p.par.t_g == 0) {
-    hipLaunchKernelGGL(k_nci_round, dim3(nb), dim3(256), lds, s, U, static_cast<int64_t>(p.n), k, 1, nullptr,
-                       nullptr, acc, cnt, nullptr, nullptr, 0, labels, rpb, st);
-    TPO_LAUNCH_CHECK();
-    return;
-  }
-  for (int t = 1; t <= p.par.t_g; ++t) {
-    const int src = (t - 1) % 3, dst = t % 3, zer = (t + 1) % 3;
-    hipLaunchKernelGGL(k_nci_round, dim3(nb), dim3(256), lds, s, U, static_cast<int64_t>(p.n), k, t == 1 ? 1 : 0,
-                       acc + src * k * k, cnt + src * k, acc + dst * k * k, cnt + dst * k, acc + zer * k * k,
-                       cnt + zer * k, t < p.par.t_g ? 1 : 0, labels, rpb, st);
-    TPO_LAUNCH_CHECK();
-  }
+  if (p.k <= 8)
+    nci_rounds<8>(p, ws, s);
+  else if (p.k <= 16)
+    nci_rounds<16>(p, ws, s);
+  else if (p.k <= 32)
+    nci_rounds<32>(p, ws, s);
+  else
+    nci_rounds<64>(p, ws, s);
 }
 
 // ---------------------------------------------------------------------------
 // Objective (Eq. obj1 with s ~ R R^T): cluster sums c_l of R rows in fixed
 // point, then obj1 = sum_l c_l.(tot - c_l)/|C_l| and sum_l ||c_l||^2/|C_l|.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(1024)
 k_obj_accum(const float* __restrict__ R, int64_t n, int twod, const int32_t* __restrict__ labels, int k,
-            long long* __restrict__ acc, int* __restrict__ cnt, int rows_per_block, const DevStatus* __restrict__ st) {
+            long long* __restrict__ part, int rows_per_block, const DevStatus* __restrict__ st) {
   extern __shared__ char smem_raw[];
-  long long* accl = reinterpret_cast<long long*>(smem_raw);  // k x twod
-  int* cntl = reinterpret_cast<int*>(accl + k * twod);
+  long long* accl = reinterpret_cast<long long*>(smem_raw);  // k x twod sums, then k counts
+  long long* cntl = accl + k * twod;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int sft = fixed_point_shift(__uint_as_float(st->maxabs_r_bits), n);
-  for (int e = tid; e < k * twod; e += 256) accl[e] = 0;
-  if (tid < 64) cntl[tid] = 0;
+  for (int e = tid; e < k * twod + k; e += blockDim.x) accl[e] = 0;
   __syncthreads();
   const int64_t rb = static_cast<int64_t>(blockIdx.x) * rows_per_block;
   const int64_t re = min(n, rb + rows_per_block);
-  for (int64_t r = rb + w; r < re; r += 4) {
+  for (int64_t r = rb + w; r < re; r += blockDim.x >> 6) {
     const int lab = labels[r];
     for (int j = lane; j < twod; j += 64)
       atomicAdd(reinterpret_cast<unsigned long long*>(&accl[lab * twod + j]),
                 static_cast<unsigned long long>(to_fixed(R[r * twod + j], sft)));
-    if (lane == 0) atomicAdd(&cntl[lab], 1);
+    if (lane == 0) atomicAdd(reinterpret_cast<unsigned long long*>(&cntl[lab]), 1ull);
   }
   __syncthreads();
-  for (int e = tid; e < k * twod; e += 256)
-    if (accl[e] != 0) atomicAdd(reinterpret_cast<unsigned long long*>(&acc[e]), static_cast<unsigned long long>(accl[e]));
-  if (tid < k && cntl[tid] != 0) atomicAdd(&cnt[tid], cntl[tid]);
+  for (int e = tid; e < k * twod + k; e += blockDim.x) part[static_cast<int64_t>(e) * gridDim.x + blockIdx.x] = accl[e];
 }
 
 __global__ void __launch_bounds__(1024)
-k_obj_final(const long long* __restrict__ acc, const int* __restrict__ cnt, int k, int twod, int64_t n,
-            DevStatus* __restrict__ st) {
+k_obj_final(const long long* __restrict__ acc, int k, int twod, int64_t n, DevStatus* __restrict__ st) {
+  const long long* cnt = acc + k * twod;
   __shared__ double red[1024];
   __shared__ double tot[512];
   const int sft = fixed_point_shift(__uint_as_float(st->maxabs_r_bits), n);
@@ -468,18 +497,17 @@ k_obj_final(const long long* __restrict__ acc, const int* __restrict__ cnt, int 
 
 void launch_objective(const Plan& p, void* ws, hipStream_t s) {
   DevStatus* st = bufp<DevStatus>(p, ws, B_STATUS);
-  long long* acc = bufp<long long>(p, ws, B_OBJ_ACC);
-  int* cnt = bufp<int>(p, ws, B_OBJ_CNT);
+  long long* part = bufp<long long>(p, ws, B_OBJ_PART);
+  long long* sums = bufp<long long>(p, ws, B_OBJ_SUM);
   const int k = p.k, twod = p.twod;
-  hipLaunchKernelGGL(k_zero_ll, dim3(ceil_div(k * twod, 256)), dim3(256), 0, s, acc, k * twod, cnt, k);
-  TPO_LAUNCH_CHECK();
-  const int nb = p.rowpass_blocks;
+  const int nb = p.obj_blocks;
   const int rpb = static_cast<int>((p.n + nb - 1) / nb);
-  const size_t lds = sizeof(long long) * k * twod + sizeof(int) * 64;
-  hipLaunchKernelGGL(k_obj_accum, dim3(nb), dim3(256), lds, s, bufp<float>(p, ws, B_R), static_cast<int64_t>(p.n),
-                     twod, bufp<int32_t>(p, ws, B_LABELS), k, acc, cnt, rpb, st);
+  const size_t lds = sizeof(long long) * (k * twod + k);
+  hipLaunchKernelGGL(k_obj_accum, dim3(nb), dim3(1024), lds, s, bufp<float>(p, ws, B_R), static_cast<int64_t>(p.n),
+                     twod, bufp<int32_t>(p, ws, B_LABELS), k, part, rpb, st);
   TPO_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_obj_final, dim3(1), dim3(1024), 0, s, acc, cnt, k, twod, static_cast<int64_t>(p.n), st);
+  sum_parts_i64(part, nb, k * twod + k, sums, s);
+  hipLaunchKernelGGL(k_obj_final, dim3(1), dim3(1024), 0, s, sums, k, twod, static_cast<int64_t>(p.n), st);
   TPO_LAUNCH_CHECK();
 }
 

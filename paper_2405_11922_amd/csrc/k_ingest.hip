@@ -312,34 +312,48 @@ __global__ void k_fill_i32(int32_t* __restrict__ a, int64_t n, int32_t v) {
   if (i < n) a[i] = v;
 }
 
-// Weighted degree per row (one wave per row), the propagation scale and the
-// hub chunk count.  mode 0: U side, scale = D^-1/2; mode 1: V side, D^-1.
+// Weighted degree per row, the propagation scale and the hub chunk count.
+// mode 0: U side, scale = D^-1/2; mode 1: V side, D^-1.  A wave owns 64
+// consecutive rows, one per lane; summed edge weights (when present) are
+// formed row by row by the whole wave in a fixed order.  Isolated rows are
+// counted with one atomic per wave.
 __global__ void k_degrees(const int32_t* __restrict__ rowptr, const float* __restrict__ val, int nrows,
                           const DevStatus* __restrict__ st_ro, int mode, float* __restrict__ deg,
                           float* __restrict__ scale, uint32_t* __restrict__ nchunk,
                           uint32_t* __restrict__ ishub, int32_t* __restrict__ iso_count) {
-  const int wid = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
-  if (wid >= nrows) return;
-  const int b = rowptr[wid], e = rowptr[wid + 1];
-  double s = 0.0;
-  if (st_ro->has_vals) {
-    for (int i = b + lane; i < e; i += 64) s += static_cast<double>(val[i]);
-    s = wave_sum(s);
-  } else {
-    s = static_cast<double>(e - b);
+  const int row0 = static_cast<int>((static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) - lane);
+  const int r = row0 + lane;
+  const bool live = r < nrows;
+  int b = 0, e = 0;
+  if (live) {
+    b = rowptr[r];
+    e = rowptr[r + 1];
   }
-  if (lane == 0) {
-    deg[wid] = static_cast<float>(s);
+  double s = static_cast<double>(e - b);
+  if (st_ro->has_vals) {
+    double mine = 0.0;
+    for (int j = 0; j < 64 && row0 + j < nrows; ++j) {
+      const int bj = __shfl(b, j, 64), ej = __shfl(e, j, 64);
+      double t = 0.0;
+      for (int i = bj + lane; i < ej; i += 64) t += static_cast<double>(val[i]);
+      t = wave_sum(t);
+      if (lane == j) mine = t;
+    }
+    s = mine;
+  }
+  if (live) {
+    deg[r] = static_cast<float>(s);
     double sc = 0.0;
     if (s > 0.0) sc = (mode == 0) ? 1.0 / sqrt(s) : 1.0 / s;
-    scale[wid] = static_cast<float>(sc);
-    if (!(s > 0.0)) atomicAdd(iso_count, 1);
+    scale[r] = static_cast<float>(sc);
     const int cnt = e - b;
     const uint32_t nc = cnt > kHubChunk ? static_cast<uint32_t>((cnt + kHubChunk - 1) / kHubChunk) : 0u;
-    nchunk[wid] = nc;
-    ishub[wid] = nc > 0 ? 1u : 0u;
+    nchunk[r] = nc;
+    ishub[r] = nc > 0 ? 1u : 0u;
   }
+  const uint64_t iso = __ballot(live && !(s > 0.0));
+  if (lane == 0 && iso != 0) atomicAdd(iso_count, static_cast<int32_t>(__popcll(iso)));
 }
 
 __global__ void k_hub_lists(const int32_t* __restrict__ rowptr, int nrows, const uint32_t* __restrict__ nchunk_raw,
@@ -368,7 +382,7 @@ static void side_lists(const Plan& p, void* ws, int nrows, const int32_t* rowptr
   uint32_t* nchunk = bufp<uint32_t>(p, ws, cnt_b);
   uint32_t* ishub = bufp<uint32_t>(p, ws, hub_b);
   uint32_t* aux = bufp<uint32_t>(p, ws, B_SCAN_AUX);
-  hipLaunchKernelGGL(k_degrees, dim3(ceil_div(static_cast<int64_t>(nrows) * 64, 256)), dim3(256), 0, s, rowptr,
+  hipLaunchKernelGGL(k_degrees, dim3(ceil_div(static_cast<int64_t>(nrows), 256)), dim3(256), 0, s, rowptr,
                      val, nrows, st, mode, bufp<float>(p, ws, deg_b), bufp<float>(p, ws, scale_b), nchunk, ishub,
                      iso);
   TPO_LAUNCH_CHECK();

@@ -157,10 +157,10 @@ void build_layout(Plan& p) {
   add(B_A32, 4 * k * k);
   add(B_ONMF_PART, 8 * nbr * (twod * k + k * k));
   add(B_LABELS, 4 * n);
-  add(B_NCI_ACC, 8 * 3 * k * k);
-  add(B_NCI_CNT, 4 * 3 * k);
-  add(B_OBJ_ACC, 8 * k * twod);
-  add(B_OBJ_CNT, 4 * k);
+  add(B_NCI_PART, 8 * nbr * (k * k + k));
+  add(B_NCI_SUM, 8 * (k * k + k));
+  add(B_OBJ_PART, 8 * static_cast<size_t>(p.obj_blocks) * (k * twod + k));
+  add(B_OBJ_SUM, 8 * (k * twod + k));
   add(B_REDTMP, 8 * 16 * std::max(twod * k + k * k, twod));
   L.total = align256(cur);
 }
@@ -308,6 +308,7 @@ tpo_status tpo_plan_create(const tpo_problem* prob, const tpo_params* par, tpo_p
   p->gram_chunks_x = chunks_for(pairs_x);
   p->gram_chunks_r = chunks_for(pairs_r);
   p->rowpass_blocks = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>((p->n + 31) / 32, 1024)));
+  p->obj_blocks = std::min(p->rowpass_blocks, 256);
   // Gaussian matrices
   if (reduce) {
     p->omega_r.resize(static_cast<size_t>(p->du) * p->lr);

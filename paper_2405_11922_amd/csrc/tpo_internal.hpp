@@ -67,7 +67,7 @@ enum Buf {
   // onmf
   B_UPS, B_H, B_H32, B_RTU, B_UTU, B_A32, B_ONMF_PART,
   // nci / objective
-  B_LABELS, B_NCI_ACC, B_NCI_CNT, B_OBJ_ACC, B_OBJ_CNT,
+  B_LABELS, B_NCI_PART, B_NCI_SUM, B_OBJ_PART, B_OBJ_SUM,
   B_REDTMP,
   B_COUNT
 };
@@ -89,6 +89,7 @@ struct Plan {
   int max_chunks_u, max_chunks_v;
   int gram_chunks_x, gram_chunks_r;
   int rowpass_blocks;
+  int obj_blocks;  // blocks of the objective accumulation
   std::vector<double> omega_r, g, omega;
   Layout lay;
   std::string last_error;
