@@ -230,21 +230,28 @@ def orthonormal_basis(a: np.ndarray) -> np.ndarray:
 
 
 def column_sign_convention(gamma: np.ndarray, *others: np.ndarray):
-    """Reading: flip column c of gamma (and of each matrix in `others`) so
-    that sum_i gamma[i, c] > 0; when that sum is within 1e-9 * ||gamma[:, c]||_1
-    of zero, use the sign of the entry of largest magnitude (lowest row index
-    on ties).  Singular vectors are otherwise defined only up to sign."""
+    """Reading (the paper fixes no sign for singular vectors): flip column c
+    of gamma (and of each matrix in `others`) so that sum_i gamma[i, c] > 0.
+    When that sum is within 1e-9 * sqrt(rows) * ||gamma[:, c]||_2 of zero (a
+    bound on 1e-9 * ||gamma[:, c]||_1), use instead the sign of the entry of
+    largest magnitude of the first matrix in `others` (the right singular
+    vector; gamma itself when none is given), lowest row index on ties."""
     gamma = np.array(gamma, dtype=np.float64, copy=True)
     others = [np.array(o, dtype=np.float64, copy=True) for o in others]
+    key = others[0] if others else gamma
+    rows = gamma.shape[0]
     for c in range(gamma.shape[1]):
         col = gamma[:, c]
         s = col.sum()
-        if abs(s) <= 1e-9 * np.abs(col).sum():
-            s = col[int(np.argmax(np.abs(col)))]
+        if abs(s) <= 1e-9 * math.sqrt(rows) * np.linalg.norm(col):
+            kc = key[:, c]
+            s = kc[int(np.argmax(np.abs(kc)))]
         if s < 0:
             gamma[:, c] = -col
             for o in others:
                 o[:, c] = -o[:, c]
+            if not others:
+                key = gamma
     return (gamma, *others)
 
 

@@ -361,6 +361,13 @@ def test_sign_convention_flip_invariance():
     col = col - col.mean()
     (fixed,) = o.column_sign_convention(col)
     assert fixed[np.argmax(np.abs(fixed)), 0] > 0
+    # with a right vector, its largest entry decides the degenerate case
+    right = np.array([[0.1], [-0.9], [0.3]])
+    g3, r3 = o.column_sign_convention(col, right)
+    assert r3[1, 0] > 0 and np.allclose(g3, -col)
+    # a clear column sum wins over the right vector
+    g4, r4 = o.column_sign_convention(-col + 0.2, right)
+    assert np.allclose(g4, -col + 0.2) and np.allclose(r4, right)
 
 
 def test_attribute_reduction_matches_exact_with_gap():
