@@ -166,18 +166,18 @@ tpo_status tpo_stage_ingest(tpo_plan* plan, const tpo_inputs* in, void* workspac
  * Reads in->x_u. */
 tpo_status tpo_stage_reduce(tpo_plan* plan, const tpo_inputs* in, void* workspace,
                             size_t workspace_bytes, void* stream);
-/* Algorithm 1 lines 1-4, Eq. PX: Z = (1-alpha) sum_{r<=gamma} alpha^r
+/* Algorithm 1, Eq. PX: Z = (1-alpha) sum_{r<=gamma} alpha^r
  * (L L^T)^r X' by gamma hops of two CSR SpMMs. */
 tpo_status tpo_stage_propagate(tpo_plan* plan, const tpo_inputs* in, void* workspace,
                                size_t workspace_bytes, void* stream);
-/* Algorithm 1 lines 5-9, Eqs. Z, R-prime, Ri: R from Z and Q = QR(G). */
+/* Algorithm 1, Eqs. Z, R-prime, Ri: R from Z and Q = QR(G). */
 tpo_status tpo_stage_features(tpo_plan* plan, void* workspace, size_t workspace_bytes,
                               void* stream);
-/* Algorithm 2 line 1 and Eq. init-HY: RandomizedSVD(R, k) -> Gamma, Sigma,
+/* Algorithm 2 and Eq. init-HY: RandomizedSVD(R, k) -> Gamma, Sigma,
  * Psi (column sign convention: positive column sums of Gamma). */
 tpo_status tpo_stage_embed(tpo_plan* plan, void* workspace, size_t workspace_bytes,
                            void* stream);
-/* Algorithm 2 lines 2-5, Eqs. update-Q and update-Y: Upsilon, H. */
+/* Algorithm 2, Eqs. update-Q and update-Y: Upsilon, H. */
 tpo_status tpo_stage_onmf(tpo_plan* plan, void* workspace, size_t workspace_bytes,
                           void* stream);
 /* Algorithm 3: labels from Upsilon (device [n_u], may be the workspace's own

@@ -112,7 +112,7 @@ def coneighbour_weights(b: sp.csr_matrix) -> sp.csr_matrix:
 
 
 # ---------------------------------------------------------------------------
-# Section 2.2 / Algorithm 1 lines 1-4: multi-hop propagation
+# Section 2.2 / Algorithm 1: multi-hop propagation
 # ---------------------------------------------------------------------------
 def propagate(b: sp.csr_matrix, x: np.ndarray, alpha: float, gamma: int) -> np.ndarray:
     """Z_U = (1 - alpha) * sum_{r=0..gamma} alpha^r (L L^T)^r X (Eq. PX).
@@ -188,10 +188,10 @@ def msa_matrix(zhat: np.ndarray) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
-# Algorithm 1 lines 6-9: random features (Eqs. R-prime and Ri)
+# Algorithm 1: random features (Eqs. R-prime and Ri)
 # ---------------------------------------------------------------------------
 def orthogonal_from_gaussian(g: np.ndarray) -> np.ndarray:
-    """Q from a QR decomposition of the Gaussian matrix G (Algorithm 1, line 7).
+    """Q from a QR decomposition of the Gaussian matrix G (Algorithm 1).
 
     Reading: Householder QR with the column signs chosen so that diag(R) > 0,
     which makes Q a deterministic function of G and Haar-distributed.
@@ -222,7 +222,7 @@ def random_features(zhat: np.ndarray, q: np.ndarray):
 
 
 # ---------------------------------------------------------------------------
-# Algorithm 2 line 1: RandomizedSVD(R, k) (Halko, Martinsson and Tropp 2011)
+# Algorithm 2: RandomizedSVD(R, k) (Halko, Martinsson and Tropp 2011)
 # ---------------------------------------------------------------------------
 def orthonormal_basis(a: np.ndarray) -> np.ndarray:
     """Orthonormal basis of range(a) by Householder QR (thin Q factor)."""
@@ -331,7 +331,7 @@ def reduce_attributes(x: np.ndarray, d: int, omega_r: np.ndarray, q: int):
 
 
 # ---------------------------------------------------------------------------
-# Algorithm 2 lines 2-5: greedy orthogonal NMF (Eqs. init-HY, update-Q, update-Y)
+# Algorithm 2: greedy orthogonal NMF (Eqs. init-HY, update-Q, update-Y)
 # ---------------------------------------------------------------------------
 def onmf(r: np.ndarray, gam: np.ndarray, sig: np.ndarray, psi: np.ndarray, t_f: int):
     """Upsilon = Gamma, H = Psi Sigma (Eq. init-HY), then t_f rounds of

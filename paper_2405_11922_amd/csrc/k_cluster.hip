@@ -1,4 +1,4 @@
-// Greedy orthogonal NMF (Algorithm 2 lines 2-5), NCI generation (Algorithm 3)
+// Greedy orthogonal NMF (Algorithm 2), NCI generation (Algorithm 3)
 // and the k-ABGC objective (Eq. obj1).
 //
 // Row passes stream R (n x 2d) once per ONMF round: each row's new Upsilon

@@ -1,5 +1,5 @@
 // Dense stages: the attribute reduction (Section 3.2.1), the random features
-// (Algorithm 1 lines 5-9) and RandomizedSVD(R, k) (Algorithm 2 line 1).
+// (Algorithm 1) and RandomizedSVD(R, k) (Algorithm 2).
 //
 // Both randomized SVDs run the subspace iteration on a Gram matrix that is
 // formed once in FP64 (C = X^T X for the reduction, K = R^T R for the
@@ -168,7 +168,7 @@ k_cholqr(double* __restrict__ A, int m, int n, int lda, double* __restrict__ G, 
   }
 }
 
-// Q of Algorithm 1 line 7 from G by Cholesky QR done twice (the unique QR
+// Q of Algorithm 1 from G by Cholesky QR done twice (the unique QR
 // factor with positive diagonal of R, re-orthogonalised), plus Q^T in FP32.
 __global__ void __launch_bounds__(kSmallThreads)
 k_q_from_g(const double* __restrict__ Gm, int d, double* __restrict__ Q, double* __restrict__ scratch,

@@ -1,4 +1,4 @@
-// Multi-hop propagation (Algorithm 1 lines 1-4; Eqs. update-Z and PX).
+// Multi-hop propagation (Algorithm 1; Eqs. update-Z and PX).
 //
 // With L = D_U^-1/2 B D_V^-1/2 the Horner step Z <- X' + alpha L (L^T Z) is
 // evaluated on W = D_U^-1/2 Z as two CSR SpMMs with per-row scales:

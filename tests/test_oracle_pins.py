@@ -242,7 +242,7 @@ def test_normalize_rows():
 
 
 def test_orthogonal_from_gaussian_is_positive_diagonal_qr():
-    """Algorithm 1 line 7: Q orthogonal and Q^T G upper triangular with a
+    """Algorithm 1: Q orthogonal and Q^T G upper triangular with a
     positive diagonal (the unique such QR factor)."""
     rng = np.random.default_rng(9)
     g = rng.standard_normal((16, 16))
@@ -317,7 +317,7 @@ def _gapped(rng, n, m, k, gap=50.0):
 
 
 def test_randomized_svd_matches_exact_on_gapped_spectrum():
-    """Algorithm 2 line 1 (Halko et al.): with q power iterations and a spectral
+    """Algorithm 2 (Halko et al.): with q power iterations and a spectral
     gap the randomized top-k SVD equals the exact one."""
     rng = np.random.default_rng(12)
     a = _gapped(rng, 300, 24, 5)
