@@ -50,31 +50,74 @@ __device__ __forceinline__ void store16(double* C, int ldc, v4d_t acc) {
   for (int v = 0; v < 4; ++v) C[(4 * v + (l >> 4)) * ldc + (l & 15)] = acc[v];
 }
 
-// One wave: in-place lower Cholesky of a 16 x 16 LDS tile (lower triangle
-// read and written).  Returns false (wave-uniform) on a bad pivot.
-__device__ __forceinline__ bool wave_chol16(double* B, int ld) {
-  const int l = threadIdx.x & 63;
-  for (int k = 0; k < 16; ++k) {
-    const double d = B[k * ld + k];
-    wave_sync();
-    if (!(d > 0.0) || !isfinite(d)) return false;
-    const double s = sqrt(d);
-    if (l > k && l < 16) B[l * ld + k] /= s;
-    if (l == k) B[k * ld + k] = s;
-    wave_sync();
+// 1/sqrt(d) for a positive normal d: the hardware estimate refined by two
+// Newton steps y <- y (1 + (1 - d y^2) / 2) (quadratic convergence, so the
+// result is within a few ulp of the exact value).
+__device__ __forceinline__ double rsqrt_refined(double d) {
+  double y = __builtin_amdgcn_rsq(d);
 #pragma unroll
-    for (int e0 = 0; e0 < 256; e0 += 64) {
-      const int e = e0 + l, i = e >> 4, c = e & 15;
-      if (c > k && c <= i) B[i * ld + c] -= B[i * ld + k] * B[c * ld + k];
-    }
-    wave_sync();
+  for (int it = 0; it < 2; ++it) {
+    const double r = fma(-d * y, y, 1.0);
+    y = fma(0.5 * y, r, y);
   }
-  return true;
+  return y;
 }
 
-// One wave: X = L^{-1} for a 16 x 16 lower LDS tile; lane c < 16 forms
-// column c by forward substitution in registers.
-__device__ __forceinline__ void wave_inv16(const double* L, int ldl, double* X, int ldx) {
+// One wave: in-place lower Cholesky of a 16 x 16 LDS tile (lower triangle
+// read and written); dinv[k] receives 1 / L[k][k].  The tile sits in
+// registers for the whole factorisation (lane l holds column l % 16 of rows
+// 4 v + l / 16, v = 0..3); the pivot and the factor column of each step
+// reach the other lanes by cross-lane reads.  Returns false (wave-uniform)
+// on a bad pivot.
+__device__ __forceinline__ bool wave_chol16(double* B, int ld, double* dinv) {
+  const int l = threadIdx.x & 63;
+  const int c = l & 15, g = l >> 4;
+  double x[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) x[v] = B[(4 * v + g) * ld + c];
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const double d = __shfl(x[k >> 2], 16 * (k & 3) + k, 64);
+    if (!(d > 1e-290) || !isfinite(d)) {
+      ok = false;
+      break;
+    }
+    const double inv = rsqrt_refined(d);
+    if (c == k) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 4 * v + g;
+        if (r > k) x[v] *= inv;
+        if (r == k) x[v] = d * inv;
+      }
+    }
+    if (l == 0) dinv[k] = inv;
+    // L[r][k] for this lane's rows r = 4 v + g (lane 16 g + k, register v)
+    double lrk[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) lrk[v] = __shfl(x[v], (l & 48) + k, 64);
+    // L[c][k] (row c sits in lane 16 (c % 4) + k, register c / 4)
+    const int src = 16 * (c & 3) + k;
+    const double t0 = __shfl(x[0], src, 64), t1 = __shfl(x[1], src, 64);
+    const double t2 = __shfl(x[2], src, 64), t3 = __shfl(x[3], src, 64);
+    const int vc = c >> 2;
+    const double lck = vc == 0 ? t0 : (vc == 1 ? t1 : (vc == 2 ? t2 : t3));
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 4 * v + g;
+      if (c > k && c <= r) x[v] -= lrk[v] * lck;
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) B[(4 * v + g) * ld + c] = x[v];
+  wave_sync();
+  return ok;
+}
+
+// One wave: X = L^{-1} for a 16 x 16 lower LDS tile with dinv[r] = 1/L[r][r];
+// lane c < 16 forms column c by forward substitution in registers.
+__device__ __forceinline__ void wave_inv16(const double* L, int ldl, const double* dinv, double* X, int ldx) {
   const int c = threadIdx.x & 63;
   double x[16];
 #pragma unroll
@@ -82,7 +125,7 @@ __device__ __forceinline__ void wave_inv16(const double* L, int ldl, double* X, 
     double s = (r == c) ? 1.0 : 0.0;
 #pragma unroll
     for (int t = 0; t < r; ++t) s -= L[r * ldl + t] * x[t];
-    x[r] = s / L[r * ldl + r];
+    x[r] = s * dinv[r];
   }
   if (c < 16) {
 #pragma unroll
@@ -96,6 +139,7 @@ __device__ __forceinline__ void wave_inv16(const double* L, int ldl, double* X, 
 // scratch: 16 waves x 16 x 16 doubles (or at least (nb - 1) tiles).
 // Returns false uniformly when a pivot fails.
 __device__ bool blk_chol_inv16(double* G, double* Li, int ld, int nb, double* scratch, int* flag) {
+  __shared__ double dinv[kC16Max];
   const int w = threadIdx.x >> 6;
   const int nw = blockDim.x >> 6;
   if (threadIdx.x == 0) *flag = 0;
@@ -104,10 +148,10 @@ __device__ bool blk_chol_inv16(double* G, double* Li, int ld, int nb, double* sc
     double* GJJ = G + 16 * J * ld + 16 * J;
     double* LJJ = Li + 16 * J * ld + 16 * J;
     if (w == 0) {
-      if (!wave_chol16(GJJ, ld)) {
+      if (!wave_chol16(GJJ, ld, dinv + 16 * J)) {
         if ((threadIdx.x & 63) == 0) *flag = 1;
       } else {
-        wave_inv16(GJJ, ld, LJJ, ld);
+        wave_inv16(GJJ, ld, dinv + 16 * J, LJJ, ld);
       }
     }
     __syncthreads();

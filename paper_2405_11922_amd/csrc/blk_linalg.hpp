@@ -6,6 +6,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "dev_common.hpp"
+
 namespace tpo {
 
 // C = alpha * op(A) * op(B) + beta * C; op(A) is m x k, op(B) is k x n.
@@ -113,19 +115,39 @@ __device__ inline double blk_sum(double v, double* sh) {
 // as converged (relative accuracy at the level of FP64 rounding).
 constexpr double kJacobiTol = 1e-16;
 
+// 1/x and 1/sqrt(x) for positive normal x: the hardware estimates refined by
+// two Newton steps each (quadratic convergence: a few ulp from exact).
+__device__ __forceinline__ double rcp_refined(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) y = fma(y, fma(-x, y, 1.0), y);
+  return y;
+}
+
+__device__ __forceinline__ double rsq_refined(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  return y;
+}
+
 // Cyclic Jacobi eigensolver for a symmetric n x n matrix A (in place; on exit
 // the diagonal holds the eigenvalues) with eigenvectors in the columns of V.
-// Parallel (round-robin) ordering: n/2 disjoint rotations per step, applied
-// as A <- J^T A J one 2 x 2 block (pair i rows, pair j columns) per thread,
-// with the annihilated entry of each rotated pair set to zero; stops after a
-// sweep that rotates nothing (or after max_sweeps).  Returns the number of
-// sweeps taken.
+// Parallel (round-robin) ordering: n/2 disjoint rotations per step.  A step
+// is two phases: thread i < n/2 forms the rotation of pair i; then wave w
+// applies A <- J^T A J to the 2 x 2 blocks (pair i rows, pair j columns) of
+// its pairs i = w, w + waves, ... with lane j taking block (i, j), and
+// V <- V J to the rows (one per lane) of the same pairs.  The coupling of a
+// rotated pair is set to zero.  Stops after a sweep that rotates nothing (or
+// after max_sweeps).  Returns the number of sweeps taken.
 // sh: scratch of 3 * ((n + 1) / 2) + 1 doubles; red: unused.
+
 __device__ inline int blk_jacobi(double* A, int lda, double* V, int ldv, int n, double* sh, double* red,
-                                  int max_sweeps) {
+                                 int max_sweeps) {
   (void)red;
   const int np = n + (n & 1);
   const int npairs = np / 2;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
   double* cs = sh;               // c
   double* sn = sh + npairs;      // s
   int* pp = reinterpret_cast<int*>(sh + 2 * npairs);
@@ -155,11 +177,14 @@ __device__ inline int blk_jacobi(double* A, int lda, double* V, int ldv, int n, 
           const double apq = A[p * lda + q];
           const double app = A[p * lda + p], aqq = A[q * lda + q];
           // rotate only while the pair is coupled above rounding level
-          if (fabs(apq) > kJacobiTol * sqrt(fabs(app * aqq)) && fabs(apq) > 1e-290) {
-            const double tau = (aqq - app) / (2.0 * apq);
-            const double t = fabs(tau) > 1e150 ? 0.5 / tau
-                                                : (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + t * t);
+          if (fabs(apq) > kJacobiTol * sqrt(fabs(app * aqq)) && fabs(apq) > 1e-140) {
+            // t = tan of the angle that annihilates a_pq: with a = a_qq - a_pp
+            // and b = 2 a_pq, t = sign(a) b / (|a| + sqrt(a^2 + b^2))
+            const double da = aqq - app, db = 2.0 * apq;
+            const double h = fma(da, da, db * db);
+            const double root = h * rsq_refined(h);
+            const double t = (da >= 0.0 ? db : -db) * rcp_refined(fabs(da) + root);
+            c = rsq_refined(fma(t, t, 1.0));
             s = t * c;
             if (s != 0.0) *rotated = 1;
           }
@@ -170,40 +195,42 @@ __device__ inline int blk_jacobi(double* A, int lda, double* V, int ldv, int n, 
         qq[i] = q < n ? q : -1;
       }
       __syncthreads();
-      // A <- J^T A J: rows of pair i by J_i^T, then columns of pair j by J_j
-      for (int e = threadIdx.x; e < npairs * npairs; e += blockDim.x) {
-        const int i = e / npairs, j = e - (e / npairs) * npairs;
-        const double si = sn[i], sj = sn[j];
-        if (si == 0.0 && sj == 0.0) continue;
-        const double ci = cs[i], cj = cs[j];
-        const int pi = pp[i], qi = qq[i], pj = pp[j], qj = qq[j];
-        const double a = A[pi * lda + pj];
-        const double b = qj >= 0 ? A[pi * lda + qj] : 0.0;
-        const double c = qi >= 0 ? A[qi * lda + pj] : 0.0;
-        const double d = (qi >= 0 && qj >= 0) ? A[qi * lda + qj] : 0.0;
-        const double a1 = ci * a - si * c, b1 = ci * b - si * d;
-        const double c1 = si * a + ci * c, d1 = si * b + ci * d;
-        double a2 = cj * a1 - sj * b1, b2 = sj * a1 + cj * b1;
-        double c2 = cj * c1 - sj * d1, d2 = sj * c1 + cj * d1;
-        if (i == j) {  // the rotated pair's own coupling is annihilated
-          b2 = 0.0;
-          c2 = 0.0;
+      for (int i = w; i < npairs; i += nw) {
+        const double si = sn[i];
+        const double ci = cs[i];
+        const int pi = pp[i], qi = qq[i];
+        // A <- J^T A J on blocks (i, j): rows of pair i by J_i^T, columns of pair j by J_j
+        for (int j = lane; j < npairs; j += 64) {
+          const double sj = sn[j], cj = cs[j];
+          const int pj = pp[j], qj = qq[j];
+          if (si == 0.0 && sj == 0.0) continue;
+          const double a = A[pi * lda + pj];
+          const double b = qj >= 0 ? A[pi * lda + qj] : 0.0;
+          const double c = qi >= 0 ? A[qi * lda + pj] : 0.0;
+          const double d = (qi >= 0 && qj >= 0) ? A[qi * lda + qj] : 0.0;
+          const double a1 = ci * a - si * c, b1 = ci * b - si * d;
+          const double c1 = si * a + ci * c, d1 = si * b + ci * d;
+          const double a2 = cj * a1 - sj * b1;
+          double b2 = sj * a1 + cj * b1;
+          double c2 = cj * c1 - sj * d1;
+          const double d2 = sj * c1 + cj * d1;
+          if (i == j && si != 0.0) {  // the rotated pair's own coupling is annihilated
+            b2 = 0.0;
+            c2 = 0.0;
+          }
+          A[pi * lda + pj] = a2;
+          if (qj >= 0) A[pi * lda + qj] = b2;
+          if (qi >= 0) A[qi * lda + pj] = c2;
+          if (qi >= 0 && qj >= 0) A[qi * lda + qj] = d2;
         }
-        A[pi * lda + pj] = a2;
-        if (qj >= 0) A[pi * lda + qj] = b2;
-        if (qi >= 0) A[qi * lda + pj] = c2;
-        if (qi >= 0 && qj >= 0) A[qi * lda + qj] = d2;
-      }
-      // V <- V J
-      for (int e = threadIdx.x; e < n * npairs; e += blockDim.x) {
-        const int r = e / npairs, i = e - (e / npairs) * npairs;
-        const double s = sn[i];
-        if (s == 0.0) continue;
-        const double c = cs[i];
-        const int p = pp[i], q = qq[i];
-        const double vp = V[r * ldv + p], vq = V[r * ldv + q];
-        V[r * ldv + p] = c * vp - s * vq;
-        V[r * ldv + q] = s * vp + c * vq;
+        // V <- V J_i on this lane's rows
+        if (si != 0.0) {
+          for (int r = lane; r < n; r += 64) {
+            const double vp = V[r * ldv + pi], vq = V[r * ldv + qi];
+            V[r * ldv + pi] = ci * vp - si * vq;
+            V[r * ldv + qi] = si * vp + ci * vq;
+          }
+        }
       }
       __syncthreads();
     }

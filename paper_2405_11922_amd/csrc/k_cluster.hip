@@ -21,13 +21,17 @@ typedef float v4f_t __attribute__((ext_vector_type(4)));
 // A[l % 16][l / 16] and B[l / 16][l % 16], its v-th result is
 // D[4 (l / 16) + v][l % 16]).
 //
-// A workgroup walks 16-row tiles of R (rows padded to TD = 16 JT columns,
-// zeros beyond 2d).  Waves w < KT form output tile w of the 16 x k block:
+// A workgroup walks 64-row slabs of R (rows padded to TD = 16 JT columns,
+// zeros beyond 2d), with the next slab's loads in flight while the current
+// one is processed.  Wave w forms rows 16 w.. of the 64 x k output block:
 //   kProject: O = R S            (Gamma; also written as Upsilon)
 //   kOnmf:    P = R H, Q = U A,  O = U * sqrt(P / Q)   (Eq. update-Y; a zero
 //             denominator keeps U, a negative ratio gives 0)
-// then all waves accumulate R^T O (2d x k) and O^T O (k x k) tiles in FP32
-// registers over the workgroup's rows; the totals are written as FP64 partials.
+// then the waves accumulate the tiles of R^T O (2d x k) and O^T O (k x k) in
+// FP32 registers over the workgroup's rows; the totals are written as FP64
+// partials.
+constexpr int kRpRows = 64;
+
 template <int MODE, int JT, int KT>
 __global__ void __launch_bounds__(256)
 k_rowpass_mfma(const float* __restrict__ R, int64_t n, int twod, int k, const float* __restrict__ Sm,
@@ -37,23 +41,28 @@ k_rowpass_mfma(const float* __restrict__ R, int64_t n, int twod, int k, const fl
   constexpr int TD = 16 * JT, KP = 16 * KT;
   constexpr int RS = TD + 4, OS = KP + 4;
   constexpr int NQ = (JT * KT + 3) / 4, NQ2 = (KT * KT + 3) / 4;
-  __shared__ float Rt[16 * RS];
-  __shared__ float Ut[16 * OS];
-  __shared__ float Ot[16 * OS];
+  constexpr int RPT = kRpRows * TD / 256, UPT = kRpRows * KP / 256;  // prefetched elements per thread
+  __shared__ float Rt[kRpRows * RS];
+  __shared__ float Ut[kRpRows * OS];
+  __shared__ float Ot[kRpRows * OS];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int i16 = lane & 15, kq = lane >> 4;
-  float sb[TD / 4];
+  float sb[KT][TD / 4];
 #pragma unroll
-  for (int t = 0; t < TD / 4; ++t) {
-    const int r = 4 * t + kq, c = 16 * w + i16;
-    sb[t] = (w < KT && r < twod && c < k) ? Sm[r * k + c] : 0.0f;
-  }
-  float ab[KP / 4];
+  for (int kt = 0; kt < KT; ++kt)
 #pragma unroll
-  for (int t = 0; t < KP / 4; ++t) {
-    const int r = 4 * t + kq, c = 16 * w + i16;
-    ab[t] = (MODE == kOnmf && w < KT && r < k && c < k) ? A32[r * k + c] : 0.0f;
-  }
+    for (int t = 0; t < TD / 4; ++t) {
+      const int r = 4 * t + kq, c = 16 * kt + i16;
+      sb[kt][t] = (r < twod && c < k) ? Sm[r * k + c] : 0.0f;
+    }
+  float ab[KT][KP / 4];
+#pragma unroll
+  for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+    for (int t = 0; t < KP / 4; ++t) {
+      const int r = 4 * t + kq, c = 16 * kt + i16;
+      ab[kt][t] = (MODE == kOnmf && r < k && c < k) ? A32[r * k + c] : 0.0f;
+    }
   v4f_t acc[NQ], acc2[NQ2];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) acc[q] = v4f_t{0.f, 0.f, 0.f, 0.f};
@@ -64,33 +73,59 @@ k_rowpass_mfma(const float* __restrict__ R, int64_t n, int twod, int k, const fl
   bool bad = false;
   const int64_t rb = static_cast<int64_t>(blockIdx.x) * rows_per_block;
   const int64_t re = min(n, rb + rows_per_block);
-  for (int64_t r0 = rb; r0 < re; r0 += 16) {
-    for (int e = tid; e < 16 * TD; e += 256) {
+  float rr_[RPT], uu_[UPT];
+  auto fetch = [&](int64_t r0) {
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      const int e = tid + 256 * u;
       const int rr = e / TD, c = e - rr * TD;
       const int64_t row = r0 + rr;
-      Rt[rr * RS + c] = (row < re && c < twod) ? R[row * twod + c] : 0.0f;
+      rr_[u] = (row < re && c < twod) ? R[row * twod + c] : 0.0f;
     }
-    if (MODE == kOnmf)
-      for (int e = tid; e < 16 * KP; e += 256) {
+    if (MODE == kOnmf) {
+#pragma unroll
+      for (int u = 0; u < UPT; ++u) {
+        const int e = tid + 256 * u;
         const int rr = e / KP, c = e - rr * KP;
         const int64_t row = r0 + rr;
-        Ut[rr * OS + c] = (row < re && c < k) ? U[row * k + c] : 0.0f;
+        uu_[u] = (row < re && c < k) ? U[row * k + c] : 0.0f;
       }
+    }
+  };
+  if (rb < re) fetch(rb);
+  for (int64_t r0 = rb; r0 < re; r0 += kRpRows) {
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      const int e = tid + 256 * u;
+      const int rr = e / TD, c = e - rr * TD;
+      Rt[rr * RS + c] = rr_[u];
+    }
+    if (MODE == kOnmf) {
+#pragma unroll
+      for (int u = 0; u < UPT; ++u) {
+        const int e = tid + 256 * u;
+        const int rr = e / KP, c = e - rr * KP;
+        Ut[rr * OS + c] = uu_[u];
+      }
+    }
     __syncthreads();
-    if (w < KT) {
+    if (r0 + kRpRows < re) fetch(r0 + kRpRows);
+    const int rw = 16 * w;  // this wave's rows in the slab
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt) {
       v4f_t pv = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int t = 0; t < TD / 4; ++t)
-        pv = __builtin_amdgcn_mfma_f32_16x16x4f32(Rt[i16 * RS + 4 * t + kq], sb[t], pv, 0, 0, 0);
+        pv = __builtin_amdgcn_mfma_f32_16x16x4f32(Rt[(rw + i16) * RS + 4 * t + kq], sb[kt][t], pv, 0, 0, 0);
       v4f_t qv = {0.f, 0.f, 0.f, 0.f};
       if (MODE == kOnmf) {
 #pragma unroll
         for (int t = 0; t < KP / 4; ++t)
-          qv = __builtin_amdgcn_mfma_f32_16x16x4f32(Ut[i16 * OS + 4 * t + kq], ab[t], qv, 0, 0, 0);
+          qv = __builtin_amdgcn_mfma_f32_16x16x4f32(Ut[(rw + i16) * OS + 4 * t + kq], ab[kt][t], qv, 0, 0, 0);
       }
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int rl = 4 * kq + v, c = 16 * w + i16;
+        const int rl = rw + 4 * kq + v, c = 16 * kt + i16;
         const int64_t row = r0 + rl;
         const bool live = row < re && c < k;
         float o;
@@ -133,7 +168,7 @@ k_rowpass_mfma(const float* __restrict__ R, int64_t n, int twod, int k, const fl
       if (q < JT * KT) {
         const int jt = q / KT, kt = q - (q / KT) * KT;
 #pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4) {
+        for (int s4 = 0; s4 < kRpRows / 4; ++s4) {
           const int rr = 4 * s4 + kq;
           acc[qi] = __builtin_amdgcn_mfma_f32_16x16x4f32(Rt[rr * RS + 16 * jt + i16], Ot[rr * OS + 16 * kt + i16],
                                                          acc[qi], 0, 0, 0);
@@ -146,7 +181,7 @@ k_rowpass_mfma(const float* __restrict__ R, int64_t n, int twod, int k, const fl
       if (q < KT * KT) {
         const int ta = q / KT, tb = q - (q / KT) * KT;
 #pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4) {
+        for (int s4 = 0; s4 < kRpRows / 4; ++s4) {
           const int rr = 4 * s4 + kq;
           acc2[qi] = __builtin_amdgcn_mfma_f32_16x16x4f32(Ot[rr * OS + 16 * ta + i16], Ot[rr * OS + 16 * tb + i16],
                                                           acc2[qi], 0, 0, 0);

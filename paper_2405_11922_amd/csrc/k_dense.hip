@@ -8,6 +8,7 @@
 // space is R M L^{-T}, with M the 2d x k' right factor and L the Cholesky
 // factor of M^T K M, so no n x k' block is ever materialised; Gamma = R S is
 // formed by one final pass (k_cluster.hip).
+#include "blk_chol16.hpp"
 #include "blk_linalg.hpp"
 #include "dev_common.hpp"
 #include "tpo_internal.hpp"
@@ -22,70 +23,90 @@ namespace tpo {
 // partials in chunk order.
 // ---------------------------------------------------------------------------
 constexpr int kGT = 64;
-constexpr int kGSub = 32;
+constexpr int kGSub = 64;
+constexpr int kGLd = kGT + 4;
 
+// One 64 x 64 tile pair (ti <= tj) of the Gram over one chunk of rows, on
+// FP64 MFMA 16x16x4: 64-row slabs of both column tiles are staged in LDS (as
+// FP32; converted exactly to FP64 at the operand read), with the next slab's
+// global loads in flight during the current slab's MFMAs.  Wave w owns the
+// 32 x 32 quadrant (w / 2, w % 2) as 2 x 2 MFMA tiles.  Operand layout: lane
+// l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; result v of lane l is
+// D[4 v + l / 16][l % 16].  part: [chunk][pair][64 x 64].
 __global__ void __launch_bounds__(256)
 k_gram_part(const float* __restrict__ X, int64_t n, int c, int64_t ldx, int ntiles, int rows_per_chunk,
             double* __restrict__ part, double* __restrict__ colsum_part) {
-  __shared__ float As[kGSub][kGT];
-  __shared__ float Bs[kGSub][kGT];
+  constexpr int PER = kGSub * kGT / 256;  // slab elements per thread
+  __shared__ float As[kGSub * kGLd];
+  __shared__ float Bs[kGSub * kGLd];
   __shared__ double csum[4][kGT];
-  // decode the tile pair (ti <= tj)
   int pi = blockIdx.x, ti = 0;
   while (pi >= ntiles - ti) {
     pi -= ntiles - ti;
     ++ti;
   }
   const int tj = ti + pi;
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int i16 = lane & 15, kq = lane >> 4;
+  const int qa = w >> 1, qb = w & 1;
   const int64_t r_beg = static_cast<int64_t>(blockIdx.y) * rows_per_chunk;
   const int64_t r_end = min(n, r_beg + rows_per_chunk);
-  double acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-  double cs = 0.0;
   const bool diag = ti == tj;
-  for (int64_t r0 = r_beg; r0 < r_end; r0 += kGSub) {
-    for (int e = tid; e < kGSub * kGT; e += 256) {
-      const int rr = e / kGT, jj = e % kGT;
+  const float* Bp = diag ? As : Bs;
+  v4d_t acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = v4d_t{0.0, 0.0, 0.0, 0.0};
+  double cs = 0.0;
+  float ra[PER], rb[PER];
+  auto fetch = [&](int64_t r0) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + 256 * u;
+      const int rr = e >> 6, jj = e & 63;
       const int64_t row = r0 + rr;
       const int ca = ti * kGT + jj, cb = tj * kGT + jj;
-      As[rr][jj] = (row < r_end && ca < c) ? X[row * ldx + ca] : 0.0f;
-      Bs[rr][jj] = (row < r_end && cb < c) ? X[row * ldx + cb] : 0.0f;
+      ra[u] = (row < r_end && ca < c) ? X[row * ldx + ca] : 0.0f;
+      rb[u] = (!diag && row < r_end && cb < c) ? X[row * ldx + cb] : 0.0f;
+    }
+  };
+  if (r_beg < r_end) fetch(r_beg);
+  for (int64_t r0 = r_beg; r0 < r_end; r0 += kGSub) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + 256 * u;
+      As[(e >> 6) * kGLd + (e & 63)] = ra[u];
+      if (!diag) Bs[(e >> 6) * kGLd + (e & 63)] = rb[u];
     }
     __syncthreads();
-#pragma unroll 4
-    for (int rr = 0; rr < kGSub; ++rr) {
-      double av[4], bv[4];
+    if (r0 + kGSub < r_end) fetch(r0 + kGSub);
 #pragma unroll
-      for (int a = 0; a < 4; ++a) av[a] = static_cast<double>(As[rr][ty * 4 + a]);
-#pragma unroll
-      for (int b = 0; b < 4; ++b) bv[b] = static_cast<double>(Bs[rr][tx * 4 + b]);
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
+    for (int st = 0; st < kGSub / 4; ++st) {
+      const int k = 4 * st + kq;
+      const double a0 = As[k * kGLd + 32 * qa + i16], a1 = As[k * kGLd + 32 * qa + 16 + i16];
+      const double b0 = Bp[k * kGLd + 32 * qb + i16], b1 = Bp[k * kGLd + 32 * qb + 16 + i16];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
     }
-    if (diag) {
-      for (int rr = tid >> 6; rr < kGSub; rr += 4) cs += static_cast<double>(As[rr][tid & 63]);
+    if (diag && colsum_part) {
+      for (int rr = w; rr < kGSub; rr += 4) cs += static_cast<double>(As[rr * kGLd + lane]);
     }
     __syncthreads();
   }
-  double* out = part + static_cast<int64_t>(blockIdx.y) * c * c;
+  const int npairs = ntiles * (ntiles + 1) / 2;
+  double* out = part + (static_cast<int64_t>(blockIdx.y) * npairs + blockIdx.x) * kGT * kGT;
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int i = ti * kGT + ty * 4 + a;
-    if (i >= c) continue;
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int j = tj * kGT + tx * 4 + b;
-      if (j < c) out[static_cast<int64_t>(i) * c + j] = acc[a][b];
-    }
-  }
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        out[(32 * qa + 16 * a + 4 * v + kq) * kGT + 32 * qb + 16 * b + i16] = acc[a][b][v];
   if (diag && colsum_part) {
-    csum[tid >> 6][tid & 63] = cs;
+    csum[w][lane] = cs;
     __syncthreads();
     if (tid < kGT) {
       const double v = ((csum[0][tid] + csum[1][tid]) + csum[2][tid]) + csum[3][tid];
@@ -95,19 +116,49 @@ k_gram_part(const float* __restrict__ X, int64_t n, int c, int64_t ldx, int ntil
   }
 }
 
-__global__ void k_gram_reduce(const double* __restrict__ part, const double* __restrict__ colsum_part, int nchunks,
-                              int c, double* __restrict__ G, double* __restrict__ colsum) {
+// G (c x c, both triangles) = sum over chunks of the tile partials, in chunk
+// order; every load of a batch is issued before its sums.
+constexpr int kGramBatch = 16;
+
+__global__ void __launch_bounds__(256)
+k_gram_reduce(const double* __restrict__ part, const double* __restrict__ colsum_part, int nchunks, int c,
+              int ntiles, double* __restrict__ G, double* __restrict__ colsum) {
+  const int npairs = ntiles * (ntiles + 1) / 2;
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (idx < static_cast<int64_t>(c) * c) {
-    const int i = static_cast<int>(idx / c), j = static_cast<int>(idx % c);
-    const int64_t src = (i / kGT <= j / kGT) ? static_cast<int64_t>(i) * c + j : static_cast<int64_t>(j) * c + i;
+  if (idx < static_cast<int64_t>(npairs) * kGT * kGT) {
+    const int pr = static_cast<int>(idx / (kGT * kGT)), e = static_cast<int>(idx % (kGT * kGT));
+    int pi = pr, ti = 0;
+    while (pi >= ntiles - ti) {
+      pi -= ntiles - ti;
+      ++ti;
+    }
+    const int tj = ti + pi;
+    const int i = ti * kGT + e / kGT, j = tj * kGT + e % kGT;
+    const double* src = part + idx;
+    const int64_t stride = static_cast<int64_t>(npairs) * kGT * kGT;
     double s = 0.0;
-    for (int ch = 0; ch < nchunks; ++ch) s += part[static_cast<int64_t>(ch) * c * c + src];
-    G[idx] = s;
+    for (int ch0 = 0; ch0 < nchunks; ch0 += kGramBatch) {
+      double v[kGramBatch];
+#pragma unroll
+      for (int u = 0; u < kGramBatch; ++u) v[u] = ch0 + u < nchunks ? src[(ch0 + u) * stride] : 0.0;
+#pragma unroll
+      for (int u = 0; u < kGramBatch; ++u) s += v[u];
+    }
+    if (i < c && j < c) {
+      G[static_cast<int64_t>(i) * c + j] = s;
+      G[static_cast<int64_t>(j) * c + i] = s;
+    }
   }
   if (colsum && idx < c) {
     double s = 0.0;
-    for (int ch = 0; ch < nchunks; ++ch) s += colsum_part[static_cast<int64_t>(ch) * c + idx];
+    for (int ch0 = 0; ch0 < nchunks; ch0 += kGramBatch) {
+      double v[kGramBatch];
+#pragma unroll
+      for (int u = 0; u < kGramBatch; ++u)
+        v[u] = ch0 + u < nchunks ? colsum_part[static_cast<int64_t>(ch0 + u) * c + idx] : 0.0;
+#pragma unroll
+      for (int u = 0; u < kGramBatch; ++u) s += v[u];
+    }
     colsum[idx] = s;
   }
 }
@@ -120,8 +171,9 @@ static void gram(const float* X, int64_t n, int c, int64_t ldx, int nchunks, dou
   hipLaunchKernelGGL(k_gram_part, dim3(npairs, nchunks), dim3(256), 0, s, X, n, c, ldx, ntiles, rows_per_chunk,
                      part, colsum_part);
   TPO_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_gram_reduce, dim3(ceil_div(static_cast<int64_t>(c) * c, 256)), dim3(256), 0, s, part,
-                     colsum_part, nchunks, c, G, colsum);
+  const int64_t outs = std::max<int64_t>(static_cast<int64_t>(npairs) * kGT * kGT, c);
+  hipLaunchKernelGGL(k_gram_reduce, dim3(ceil_div(outs, 256)), dim3(256), 0, s, part, colsum_part, nchunks, c,
+                     ntiles, G, colsum);
   TPO_LAUNCH_CHECK();
 }
 
@@ -352,68 +404,66 @@ k_embed_small(const double* __restrict__ K, const double* __restrict__ Omega, in
 // ---------------------------------------------------------------------------
 // Attribute projection X' = X Psi_d (FP32), rows padded to dp columns, or a
 // padded copy of X when there is no reduction.  Also flags non-finite input.
-// One workgroup per 64 rows; Psi_d^T staged in LDS.
 // ---------------------------------------------------------------------------
+// X' = X Psi_d on FP32 MFMA 16x16x4 (lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16]; its v-th result is D[4 (l / 16) + v][l % 16]).  A
+// workgroup takes 64 rows; wave w owns rows 16 w.. and all CT column tiles.
+// 32-column slabs of X and the matching rows of Psi_d are staged in LDS.
+typedef float v4f_t __attribute__((ext_vector_type(4)));
+constexpr int kPjRows = 64;
+constexpr int kPjK = 32;
+constexpr int kPjXLd = kPjK + 1;
+
+template <int CT>
 __global__ void __launch_bounds__(256)
-k_project_x(const float* __restrict__ X, int64_t n, int du, int64_t ldx, const float* __restrict__ psi32, int d,
-            int dp, float* __restrict__ out, int32_t* __restrict__ err_bits) {
-  extern __shared__ float smem[];
-  // tile: 64 rows x 32 input columns of X, and 32 x dp of psi
-  float* xs = smem;                 // [64][33]
-  float* ps = smem + 64 * 33;       // [32][dp]
-  const int tid = threadIdx.x;
-  const int64_t row0 = static_cast<int64_t>(blockIdx.x) * 64;
-  // thread computes rows (tid / (dp/4)) ... a 64 x dp output tile with 256 threads
-  constexpr int RPT = 4;  // rows per thread
-  const int cols_per_thread = (dp * 64) / (256 * RPT);  // dp/16
-  const int cgroups = dp / cols_per_thread;              // = 16
-  const int tr = tid / cgroups;   // 0..15 -> rows tr*4 .. tr*4+3
-  const int tc = tid % cgroups;   // column group
-  float acc[RPT][16];
+k_project_mfma(const float* __restrict__ X, int64_t n, int du, int64_t ldx, const float* __restrict__ psi32, int dp,
+               float* __restrict__ out, int32_t* __restrict__ err_bits) {
+  constexpr int PLD = 16 * CT + 4;
+  __shared__ float xs[kPjRows * kPjXLd];
+  __shared__ float ps[kPjK * PLD];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int i16 = lane & 15, kq = lane >> 4;
+  const int64_t row0 = static_cast<int64_t>(blockIdx.x) * kPjRows;
+  v4f_t acc[CT];
 #pragma unroll
-  for (int a = 0; a < RPT; ++a)
-#pragma unroll
-    for (int b = 0; b < 16; ++b) acc[a][b] = 0.0f;
+  for (int t = 0; t < CT; ++t) acc[t] = v4f_t{0.f, 0.f, 0.f, 0.f};
   bool bad = false;
-  for (int k0 = 0; k0 < du; k0 += 32) {
-    for (int e = tid; e < 64 * 32; e += 256) {
-      const int rr = e / 32, kk = e % 32;
+  for (int k0 = 0; k0 < du; k0 += kPjK) {
+#pragma unroll
+    for (int u = 0; u < kPjRows * kPjK / 256; ++u) {
+      const int e = tid + 256 * u;
+      const int rr = e / kPjK, kk = e % kPjK;
       const int64_t row = row0 + rr;
       float v = (row < n && k0 + kk < du) ? X[row * ldx + k0 + kk] : 0.0f;
       if (!isfinite(v)) {
         bad = true;
         v = 0.0f;
       }
-      xs[rr * 33 + kk] = v;
+      xs[rr * kPjXLd + kk] = v;
     }
-    for (int e = tid; e < 32 * dp; e += 256) {
-      const int kk = e / dp, cc = e % dp;
-      ps[kk * dp + cc] = (k0 + kk < du) ? psi32[static_cast<int64_t>(k0 + kk) * dp + cc] : 0.0f;
+    for (int e = tid; e < kPjK * 16 * CT; e += 256) {
+      const int kk = e / (16 * CT), cc = e % (16 * CT);
+      ps[kk * PLD + cc] = (k0 + kk < du && cc < dp) ? psi32[static_cast<int64_t>(k0 + kk) * dp + cc] : 0.0f;
     }
     __syncthreads();
-    for (int kk = 0; kk < 32; ++kk) {
-      float xv[RPT];
 #pragma unroll
-      for (int a = 0; a < RPT; ++a) xv[a] = xs[(tr * RPT + a) * 33 + kk];
+    for (int st = 0; st < kPjK / 4; ++st) {
+      const float av = xs[(16 * w + i16) * kPjXLd + 4 * st + kq];
 #pragma unroll
-      for (int b = 0; b < 16; ++b) {
-        if (b < cols_per_thread) {
-          const float pv = ps[kk * dp + tc * cols_per_thread + b];
-#pragma unroll
-          for (int a = 0; a < RPT; ++a) acc[a][b] = fmaf(xv[a], pv, acc[a][b]);
-        }
-      }
+      for (int t = 0; t < CT; ++t)
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, ps[(4 * st + kq) * PLD + 16 * t + i16], acc[t], 0, 0, 0);
     }
     __syncthreads();
   }
   if (bad) atomicOr(err_bits, 4);
 #pragma unroll
-  for (int a = 0; a < RPT; ++a) {
-    const int64_t row = row0 + tr * RPT + a;
-    if (row >= n) continue;
+  for (int t = 0; t < CT; ++t) {
+    const int col = 16 * t + i16;
 #pragma unroll
-    for (int b = 0; b < 16; ++b)
-      if (b < cols_per_thread) out[row * dp + tc * cols_per_thread + b] = acc[a][b];
+    for (int v = 0; v < 4; ++v) {
+      const int64_t row = row0 + 16 * w + 4 * kq + v;
+      if (row < n && col < dp) out[row * dp + col] = acc[t][v];
+    }
   }
 }
 
@@ -446,34 +496,40 @@ void launch_reduce(const Plan& p, void* ws, const float* x, int64_t ldx, hipStre
        colsum, s);
   double* ma = bufp<double>(p, ws, B_MR_A);
   double* mb = bufp<double>(p, ws, B_MR_B);
-  double* gs = bufp<double>(p, ws, B_SMALL_A);
-  TPO_HIP_CHECK(hipMemcpyAsync(ma, bufp<double>(p, ws, B_OMR), sizeof(double) * p.du * p.lr,
-                               hipMemcpyDeviceToDevice, s));
-  // q + 1 products with C, each followed by Cholesky QR
-  const bool small_in_lds = p.lr <= kLdsMaxN;
-  for (int it = 0; it <= p.par.q; ++it) {
-    gemm_f64(p.du, p.lr, p.du, C, p.du, ma, p.lr, mb, p.lr, s);
-    if (small_in_lds) {
-      cholqr_lds(mb, p.du, p.lr, p.lr, &st->err_bits, s);
-    } else {
-      hipLaunchKernelGGL(k_cholqr, dim3(1), dim3(kSmallThreads), 0, s, mb, p.du, p.lr, p.lr, gs, &st->err_bits);
-      TPO_LAUNCH_CHECK();
-    }
-    std::swap(ma, mb);
-  }
-  gemm_f64(p.du, p.lr, p.du, C, p.du, ma, p.lr, mb, p.lr, s);  // P = C M
-  if (small_in_lds) {
-    rr_reduce_lds(ma, mb, p.du, p.lr, p.d, p.dp, colsum, static_cast<int64_t>(p.n), bufp<double>(p, ws, B_EVAL),
+  if (p.lr <= kLdsMaxN) {
+    // q + 1 products with C, each followed by Cholesky QR, then P = C M
+    double* m = bufp<double>(p, ws, B_SI_M);
+    double* pm = bufp<double>(p, ws, B_SI_P);
+    subspace_iterate(C, p.du, bufp<double>(p, ws, B_OMR), p.lr, p.par.q + 1, ma, mb, bufp<double>(p, ws, B_SI_LI),
+                     bufp<double>(p, ws, B_SI_PART), m, pm, &st->err_bits, s);
+    rr_reduce_lds(m, pm, p.du, p.lr, p.d, p.dp, colsum, static_cast<int64_t>(p.n), bufp<double>(p, ws, B_EVAL),
                   bufp<double>(p, ws, B_PSI_D), bufp<float>(p, ws, B_PSI_D32), s);
   } else {
+    double* gs = bufp<double>(p, ws, B_SMALL_A);
+    TPO_HIP_CHECK(hipMemcpyAsync(ma, bufp<double>(p, ws, B_OMR), sizeof(double) * p.du * p.lr,
+                                 hipMemcpyDeviceToDevice, s));
+    for (int it = 0; it <= p.par.q; ++it) {
+      gemm_f64(p.du, p.lr, p.du, C, p.du, ma, p.lr, mb, p.lr, s);
+      hipLaunchKernelGGL(k_cholqr, dim3(1), dim3(kSmallThreads), 0, s, mb, p.du, p.lr, p.lr, gs, &st->err_bits);
+      TPO_LAUNCH_CHECK();
+      std::swap(ma, mb);
+    }
+    gemm_f64(p.du, p.lr, p.du, C, p.du, ma, p.lr, mb, p.lr, s);  // P = C M
     hipLaunchKernelGGL(k_reduce_rr, dim3(1), dim3(kSmallThreads), 0, s, ma, mb, p.du, p.lr, p.d, p.dp, colsum,
                        static_cast<int64_t>(p.n), bufp<double>(p, ws, B_SMALL_B), bufp<double>(p, ws, B_SMALL_C),
                        bufp<double>(p, ws, B_EVAL), bufp<double>(p, ws, B_PSI_D), bufp<float>(p, ws, B_PSI_D32));
     TPO_LAUNCH_CHECK();
   }
-  const size_t lds = (64 * 33 + 32 * p.dp) * sizeof(float);
-  hipLaunchKernelGGL(k_project_x, dim3(ceil_div(p.n, 64)), dim3(256), lds, s, x, static_cast<int64_t>(p.n), p.du,
-                     ldx, bufp<float>(p, ws, B_PSI_D32), p.d, p.dp, xp, &st->err_bits);
+  const dim3 grid(ceil_div(p.n, kPjRows));
+  const float* psi32 = bufp<float>(p, ws, B_PSI_D32);
+  const int64_t n = p.n;
+  switch ((p.dp + 15) / 16) {
+    case 1: hipLaunchKernelGGL((k_project_mfma<1>), grid, dim3(256), 0, s, x, n, p.du, ldx, psi32, p.dp, xp, &st->err_bits); break;
+    case 2: hipLaunchKernelGGL((k_project_mfma<2>), grid, dim3(256), 0, s, x, n, p.du, ldx, psi32, p.dp, xp, &st->err_bits); break;
+    case 4: hipLaunchKernelGGL((k_project_mfma<4>), grid, dim3(256), 0, s, x, n, p.du, ldx, psi32, p.dp, xp, &st->err_bits); break;
+    case 8: hipLaunchKernelGGL((k_project_mfma<8>), grid, dim3(256), 0, s, x, n, p.du, ldx, psi32, p.dp, xp, &st->err_bits); break;
+    default: hipLaunchKernelGGL((k_project_mfma<16>), grid, dim3(256), 0, s, x, n, p.du, ldx, psi32, p.dp, xp, &st->err_bits); break;
+  }
   TPO_LAUNCH_CHECK();
 }
 
@@ -702,17 +758,13 @@ void launch_embed(const Plan& p, void* ws, hipStream_t s) {
   gram(bufp<float>(p, ws, B_R), p.n, p.twod, p.twod, p.gram_chunks_r, bufp<double>(p, ws, B_GRAM_PART), nullptr,
        K, nullptr, s);
   if (p.kp <= kLdsMaxN) {
-    double* ma = bufp<double>(p, ws, B_M_A);
-    double* mb = bufp<double>(p, ws, B_M_B);
-    TPO_HIP_CHECK(hipMemcpyAsync(ma, bufp<double>(p, ws, B_OMEGA), sizeof(double) * p.twod * p.kp,
-                                 hipMemcpyDeviceToDevice, s));
-    for (int it = 0; it < p.par.q; ++it) {
-      gemm_f64(p.twod, p.kp, p.twod, K, p.twod, ma, p.kp, mb, p.kp, s);  // K M
-      cholqr_lds(mb, p.twod, p.kp, p.kp, &st->err_bits, s);
-      std::swap(ma, mb);
-    }
-    gemm_f64(p.twod, p.kp, p.twod, K, p.twod, ma, p.kp, mb, p.kp, s);
-    embed_final_lds(ma, mb, p.twod, p.kp, p.k, bufp<double>(p, ws, B_RCOLSUM), static_cast<int64_t>(p.n),
+    // q products with K, each followed by Cholesky QR, then P = K M
+    double* m = bufp<double>(p, ws, B_SI_M);
+    double* pm = bufp<double>(p, ws, B_SI_P);
+    subspace_iterate(K, p.twod, bufp<double>(p, ws, B_OMEGA), p.kp, p.par.q, bufp<double>(p, ws, B_M_A),
+                     bufp<double>(p, ws, B_M_B), bufp<double>(p, ws, B_SI_LI), bufp<double>(p, ws, B_SI_PART), m, pm,
+                     &st->err_bits, s);
+    embed_final_lds(m, pm, p.twod, p.kp, p.k, bufp<double>(p, ws, B_RCOLSUM), static_cast<int64_t>(p.n),
                     bufp<double>(p, ws, B_EEVAL), bufp<float>(p, ws, B_S32), bufp<double>(p, ws, B_SIGMA),
                     bufp<double>(p, ws, B_PSI), bufp<double>(p, ws, B_H), bufp<float>(p, ws, B_H32), &st->err_bits,
                     s);

@@ -113,7 +113,7 @@ template <int D>
 __device__ __forceinline__ float4 gather_row_group(const int32_t* __restrict__ col, const float* __restrict__ val,
                                                    bool has_vals, const float* __restrict__ src, int b, int e) {
   using S = SpmmShape<D>;
-  constexpr int U = S::LPR >= 16 ? 4 : 8;  // loads in flight per lane
+  constexpr int U = S::LPR >= 16 ? 4 : 8;  // gathers in flight per lane
   const int lane = threadIdx.x & 63;
   const int q = lane % S::LPR;
   const int g0 = lane - q;  // first lane of this group
@@ -131,7 +131,7 @@ __device__ __forceinline__ float4 gather_row_group(const int32_t* __restrict__ c
         const int jj = j < S::LPR ? j : S::LPR - 1;
         int nb = __shfl(myidx, g0 + jj, 64);
         const float w = has_vals ? __shfl(myval, g0 + jj, 64) : 1.0f;
-        if (j >= cnt) nb = myidx;
+        if (j >= cnt) nb = myidx;  // any valid row (a cache hit); its term is skipped
         x[u] = *reinterpret_cast<const float4*>(src + static_cast<int64_t>(nb) * D + q * 4);
         wv[u] = (j < cnt) ? w : 0.0f;
       }
@@ -218,12 +218,24 @@ k_spmm_hubs(const int32_t* __restrict__ n_hubs, const int4* __restrict__ hubs, c
   const int lane = threadIdx.x & 63;
   float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
   if (lane < SpmmShape<D>::LPR) {
-    for (int c = 0; c < hb.z; ++c) {
-      const float4 v = *reinterpret_cast<const float4*>(partial + static_cast<int64_t>(hb.y + c) * D + lane * 4);
-      acc.x += v.x;
-      acc.y += v.y;
-      acc.z += v.z;
-      acc.w += v.w;
+    // chunk partials in chunk order; eight loads in flight at a time
+    for (int c0 = 0; c0 < hb.z; c0 += 8) {
+      float4 v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (c0 + u < hb.z)
+          v[u] = *reinterpret_cast<const float4*>(partial + static_cast<int64_t>(hb.y + c0 + u) * D + lane * 4);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (c0 + u < hb.z) {
+          acc.x += v[u].x;
+          acc.y += v[u].y;
+          acc.z += v[u].z;
+          acc.w += v[u].w;
+        }
+      }
     }
   }
   spmm_epilogue<D, MODE>(hb.x, acc, rscale, xp, alpha, one_minus_alpha, dst);

@@ -110,8 +110,10 @@ void build_layout(Plan& p) {
   add(B_HUBLIST_U, 16 * static_cast<size_t>(p.max_chunks_u + 1));
   add(B_HUBLIST_V, 16 * static_cast<size_t>(p.max_chunks_v + 1));
   add(B_PARTIAL, 4 * dp * (maxch + 1));
-  const size_t gpart_x = p.reduce ? static_cast<size_t>(p.gram_chunks_x) * du * du : 0;
-  const size_t gpart_r = static_cast<size_t>(p.gram_chunks_r) * twod * twod;
+  // Gram partials: one 64 x 64 tile per (chunk, upper tile pair)
+  const size_t tx = (du + 63) / 64, tr = (twod + 63) / 64;
+  const size_t gpart_x = p.reduce ? static_cast<size_t>(p.gram_chunks_x) * (tx * (tx + 1) / 2) * 4096 : 0;
+  const size_t gpart_r = static_cast<size_t>(p.gram_chunks_r) * (tr * (tr + 1) / 2) * 4096;
   add(B_GRAM_PART, 8 * std::max(gpart_x, gpart_r));
   add(B_COLSUM_PART, 8 * (p.reduce ? static_cast<size_t>(p.gram_chunks_x) * du : 1));
   add(B_C, 8 * (p.reduce ? du * du : 1));
@@ -162,6 +164,18 @@ void build_layout(Plan& p) {
   add(B_OBJ_PART, 8 * static_cast<size_t>(p.obj_blocks) * (k * twod + k));
   add(B_OBJ_SUM, 8 * (k * twod + k));
   add(B_REDTMP, 8 * 16 * std::max(twod * k + k * k, twod));
+  {
+    const bool red_si = p.reduce && p.lr <= kLdsMaxN;
+    const bool emb_si = p.kp <= kLdsMaxN;
+    const size_t mp = std::max(red_si ? du * lr : 0, emb_si ? twod * kp : 0);
+    const size_t li = std::max(red_si ? lr * lr : 0, emb_si ? kp * kp : 0);
+    const size_t pt = std::max(red_si ? subspace_part_doubles(static_cast<int>(du), static_cast<int>(lr)) : 0,
+                               emb_si ? subspace_part_doubles(static_cast<int>(twod), static_cast<int>(kp)) : 0);
+    add(B_SI_M, 8 * mp);
+    add(B_SI_P, 8 * mp);
+    add(B_SI_LI, 8 * li);
+    add(B_SI_PART, 8 * pt);
+  }
   L.total = align256(cur);
 }
 
@@ -301,7 +315,7 @@ tpo_status tpo_plan_create(const tpo_problem* prob, const tpo_params* par, tpo_p
   const int tiles_x = (p->du + 63) / 64, tiles_r = (p->twod + 63) / 64;
   const int pairs_x = tiles_x * (tiles_x + 1) / 2, pairs_r = tiles_r * (tiles_r + 1) / 2;
   auto chunks_for = [&](int pairs) {
-    int64_t want = std::max<int64_t>(1, 2048 / pairs);
+    int64_t want = std::max<int64_t>(1, 1024 / pairs);
     int64_t by_rows = std::max<int64_t>(1, (p->n + 255) / 256);
     return static_cast<int>(std::min<int64_t>({want, by_rows, 65535}));
   };
@@ -334,6 +348,8 @@ tpo_status tpo_plan_create(const tpo_problem* prob, const tpo_params* par, tpo_p
   std::memset(&p->stats, 0, sizeof(p->stats));
   p->events_made = false;
   p->kev_made = false;
+  p->side = nullptr;
+  p->side_made = false;
   p->timing = (par->flags & TPO_FLAG_TIMING) != 0;
   *out_plan = p;
   return TPO_OK;
@@ -345,6 +361,12 @@ void tpo_plan_destroy(tpo_plan* plan) {
     for (auto& e : plan->ev) (void)hipEventDestroy(e);
   if (plan->kev_made)
     for (auto& e : plan->kev) (void)hipEventDestroy(e);
+  if (plan->side_made) {
+    (void)hipStreamSynchronize(plan->side);
+    (void)hipEventDestroy(plan->fork_ev);
+    (void)hipEventDestroy(plan->join_ev);
+    (void)hipStreamDestroy(plan->side);
+  }
   delete plan;
 }
 
@@ -512,10 +534,29 @@ tpo_status tpo_execute(tpo_plan* plan, const tpo_inputs* in, void* ws, size_t by
     };
     upload_inputs(plan, ws, s);
     mark(0);
-    launch_ingest(*plan, ws, in, s);
-    mark(1);
-    launch_reduce(*plan, ws, in->x_u, in->ld_x, s);
-    mark(2);
+    if (timing) {
+      // stage by stage on one stream, so that each stage's time is its own
+      launch_ingest(*plan, ws, in, s);
+      mark(1);
+      launch_reduce(*plan, ws, in->x_u, in->ld_x, s);
+      mark(2);
+    } else {
+      // ingest (edges only) and the attribute reduction (X only) are
+      // independent: ingest runs on a second stream beside the reduction's
+      // chain of small dependent kernels
+      if (!plan->side_made) {
+        TPO_HIP_CHECK(hipStreamCreateWithFlags(&plan->side, hipStreamNonBlocking));
+        TPO_HIP_CHECK(hipEventCreateWithFlags(&plan->fork_ev, hipEventDisableTiming));
+        TPO_HIP_CHECK(hipEventCreateWithFlags(&plan->join_ev, hipEventDisableTiming));
+        plan->side_made = true;
+      }
+      TPO_HIP_CHECK(hipEventRecord(plan->fork_ev, s));
+      TPO_HIP_CHECK(hipStreamWaitEvent(plan->side, plan->fork_ev, 0));
+      launch_ingest(*plan, ws, in, plan->side);
+      TPO_HIP_CHECK(hipEventRecord(plan->join_ev, plan->side));
+      launch_reduce(*plan, ws, in->x_u, in->ld_x, s);
+      TPO_HIP_CHECK(hipStreamWaitEvent(s, plan->join_ev, 0));
+    }
     launch_propagate(*plan, ws, bufp<float>(*plan, ws, B_XPRIME), plan->dp, s);
     mark(3);
     launch_features(*plan, ws, s);

@@ -68,6 +68,8 @@ enum Buf {
   B_UPS, B_H, B_H32, B_RTU, B_UTU, B_A32, B_ONMF_PART,
   // nci / objective
   B_LABELS, B_NCI_PART, B_NCI_SUM, B_OBJ_PART, B_OBJ_SUM,
+  // subspace iteration (reduction and embedding)
+  B_SI_M, B_SI_P, B_SI_LI, B_SI_PART,
   B_REDTMP,
   B_COUNT
 };
@@ -99,6 +101,10 @@ struct Plan {
   bool timing;             // TPO_FLAG_TIMING set
   hipEvent_t kev[4 * kMaxTimedHops];
   bool kev_made;
+  // second stream: ingest runs beside the attribute reduction
+  hipStream_t side;
+  hipEvent_t fork_ev, join_ev;
+  bool side_made;
   DevStatus init_status;  // host copy uploaded at the start of a job
   DevStatus host_status;  // last status block read back
 };
@@ -123,6 +129,13 @@ void launch_embed(const Plan& p, void* ws, hipStream_t s);
 // k_smallla.hip (single workgroup, small matrices in LDS, n <= 80)
 constexpr int kLdsMaxN = 80;
 void cholqr_lds(double* A, int m, int n, int lda, int32_t* err_bits, hipStream_t s);
+// n_orth Cholesky-QR steps of subspace iteration on the symmetric N x N A from
+// the N x l start omega (l <= kLdsMaxN); m_out = the last basis (omega when
+// n_orth = 0), p_out = A m_out.  pa, pb: N x l scratch; li: l x l scratch;
+// part: subspace_part_doubles(N, l) scratch.
+void subspace_iterate(const double* A, int N, const double* omega, int l, int n_orth, double* pa, double* pb,
+                      double* li, double* part, double* m_out, double* p_out, int32_t* err_bits, hipStream_t s);
+size_t subspace_part_doubles(int N, int l);
 void rr_reduce_lds(const double* M, const double* P, int du, int l, int d, int dp, const double* colsum_x,
                    int64_t n, double* evals, double* psi, float* psi32, hipStream_t s);
 void embed_final_lds(double* M, double* P, int twod, int kp, int k, const double* colsum_r, int64_t n, double* S,
