@@ -361,78 +361,82 @@ static void sum_parts_i64(const long long* part, int nb, int len, long long* sum
 // (sums: k x k values c_l[t] at l * k + t, then k counts).  When `part` is
 // given, the block's own fixed-point sums and counts for the labels of this
 // round are written there (transposed, entry o at part[o * gridDim.x + block]).
-// KT: compile-time bound on k (scores live in registers).
+// KT: compile-time bound on k; one row per lane, its k entries and k scores in
+// registers, Phi (zero padded to KT x KT) in LDS.
 template <int KT>
 __global__ void __launch_bounds__(256)
 k_nci_round(const float* __restrict__ U, int64_t n, int k, const long long* __restrict__ sums,
             long long* __restrict__ part, int32_t* __restrict__ labels, int rows_per_block,
             const DevStatus* __restrict__ st) {
-  extern __shared__ char smem_raw[];
-  double* phi = reinterpret_cast<double*>(smem_raw);                 // k x k, phi[t * k + l]
-  long long* accl = reinterpret_cast<long long*>(phi + k * k);        // k x k sums, then k counts
-  float* ut = reinterpret_cast<float*>(accl + k * k + k);             // 4 waves x 64 rows x (k + 1)
+  constexpr int LD = KT + 1;  // staging stride (odd for even KT)
+  __shared__ double phi[KT * KT];
+  __shared__ double fac[KT];
+  __shared__ long long accl[KT * KT + KT];  // k x k sums (stride k), then k counts
+  __shared__ float ut[4 * 64 * LD];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int kp1 = k + 1;  // odd row stride when k is even: lane-per-row reads avoid bank conflicts
   const int sft = fixed_point_shift(__uint_as_float(st->maxabs_ups_bits), n);
   const double inv_scale = ldexp(1.0, -sft);
-  for (int e = tid; e < k * k; e += 256) {
-    const int t = e / k, l = e % k;
-    double v;
-    if (!sums) {
-      v = (t == l) ? 1.0 : 0.0;
-    } else {
-      const long long c = sums[k * k + l];
-      v = c > 0 ? static_cast<double>(sums[l * k + t]) * inv_scale / sqrt(static_cast<double>(c)) : 0.0;
-    }
-    phi[e] = v;
+  if (sums && tid < k) {
+    const long long c = sums[k * k + tid];
+    fac[tid] = c > 0 ? inv_scale / sqrt(static_cast<double>(c)) : 0.0;
   }
   for (int e = tid; e < k * k + k; e += 256) accl[e] = 0;
   __syncthreads();
-  float* myut = ut + w * 64 * kp1;
+  for (int e = tid; e < KT * KT; e += 256) {
+    const int t = e / KT, l = e - (e / KT) * KT;
+    double v = 0.0;
+    if (t < k && l < k) v = sums ? static_cast<double>(sums[l * k + t]) * fac[l] : (t == l ? 1.0 : 0.0);
+    phi[e] = v;
+  }
+  __syncthreads();
+  float* myut = ut + w * 64 * LD;
   const int64_t rb = static_cast<int64_t>(blockIdx.x) * rows_per_block;
   const int64_t re = min(n, rb + rows_per_block);
-  const int rpi = k <= 64 ? 64 / k : 1;  // rows per accumulation step
+  const int rpi = 64 / k;  // rows per accumulation step (k <= 64)
   for (int64_t b0 = rb + static_cast<int64_t>(w) * 64; b0 < re; b0 += 256) {
-    const int nr = static_cast<int>(min(static_cast<int64_t>(64), re - b0));
-    for (int e = lane; e < nr * k; e += 64) {
-      const int rr = e / k, t = e % k;
-      myut[rr * kp1 + t] = U[b0 * k + e];
-    }
-    wave_sync();
-    int best = 0;
-    if (lane < nr) {
-      double sc[KT];
+    const int64_t row = b0 + lane;
+    const bool live = row < re;
+    float u[KT];
 #pragma unroll
-      for (int l = 0; l < KT; ++l) sc[l] = 0.0;
-      for (int t = 0; t < k; ++t) {
-        const double u = static_cast<double>(myut[lane * kp1 + t]);
-        const double* ph = phi + t * k;
+    for (int t = 0; t < KT; ++t) u[t] = (live && t < k) ? U[row * k + t] : 0.0f;
+    double sc[KT];
 #pragma unroll
-        for (int l = 0; l < KT; ++l)
-          if (l < k) sc[l] = fma(u, ph[l], sc[l]);
+    for (int l = 0; l < KT; ++l) sc[l] = 0.0;
+#pragma unroll
+    for (int t = 0; t < KT; ++t) {
+      if (t < k) {
+        const double x = static_cast<double>(u[t]);
+#pragma unroll
+        for (int l = 0; l < KT; ++l) sc[l] = fma(x, phi[t * KT + l], sc[l]);
       }
-      double bestv = sc[0];
-#pragma unroll
-      for (int l = 1; l < KT; ++l)
-        if (l < k && sc[l] > bestv) {
-          bestv = sc[l];
-          best = l;
-        }
-      labels[b0 + lane] = best;
     }
+    int best = 0;
+    double bestv = sc[0];
+#pragma unroll
+    for (int l = 1; l < KT; ++l)
+      if (l < k && sc[l] > bestv) {
+        bestv = sc[l];
+        best = l;
+      }
+    if (live) labels[row] = best;
     if (part) {
-      const int g = lane / k, t = lane % k;
+      const int nr = static_cast<int>(min(static_cast<int64_t>(64), re - b0));
+#pragma unroll
+      for (int t = 0; t < KT; ++t)
+        if (t < k) myut[lane * LD + t] = u[t];
+      wave_sync();
+      const int g = lane / k, t = lane - (lane / k) * k;
       for (int r0 = 0; r0 < nr; r0 += rpi) {
         const int rr = r0 + g;
         const int lab = __shfl(best, rr < 64 ? rr : 63, 64);
         if (g < rpi && rr < nr) {
           atomicAdd(reinterpret_cast<unsigned long long*>(&accl[lab * k + t]),
-                    static_cast<unsigned long long>(to_fixed(myut[rr * kp1 + t], sft)));
+                    static_cast<unsigned long long>(to_fixed(myut[rr * LD + t], sft)));
           if (t == 0) atomicAdd(reinterpret_cast<unsigned long long*>(&accl[k * k + lab]), 1ull);
         }
       }
+      wave_sync();
     }
-    wave_sync();
   }
   __syncthreads();
   if (part) {
@@ -448,7 +452,6 @@ static void nci_rounds(const Plan& p, void* ws, hipStream_t s) {
   long long* sums = bufp<long long>(p, ws, B_NCI_SUM);
   const int nb = p.rowpass_blocks;
   const int rpb = static_cast<int>((p.n + nb - 1) / nb);
-  const size_t lds = sizeof(double) * k * k + sizeof(long long) * (k * k + k) + sizeof(float) * 4 * 64 * (k + 1);
   const float* U = bufp<float>(p, ws, B_UPS);
   int32_t* labels = bufp<int32_t>(p, ws, B_LABELS);
   const int rounds = std::max(p.par.t_g, 1);
@@ -456,7 +459,7 @@ static void nci_rounds(const Plan& p, void* ws, hipStream_t s) {
     // round 1 (and T_g = 0) scores against Phi = I; every round but the last
     // feeds the label sums to the next
     const bool acc = t < p.par.t_g;
-    hipLaunchKernelGGL((k_nci_round<KT>), dim3(nb), dim3(256), lds, s, U, static_cast<int64_t>(p.n), k,
+    hipLaunchKernelGGL((k_nci_round<KT>), dim3(nb), dim3(256), 0, s, U, static_cast<int64_t>(p.n), k,
                        t == 1 ? nullptr : sums, acc ? part : nullptr, labels, rpb, st);
     TPO_LAUNCH_CHECK();
     if (acc) sum_parts_i64(part, nb, k * k + k, sums, s);
@@ -464,14 +467,16 @@ static void nci_rounds(const Plan& p, void* ws, hipStream_t s) {
 }
 
 void launch_nci(const Plan& p, void* ws, hipStream_t s) {
-  if (p.k <= 8)
-    nci_rounds<8>(p, ws, s);
-  else if (p.k <= 16)
-    nci_rounds<16>(p, ws, s);
-  else if (p.k <= 32)
-    nci_rounds<32>(p, ws, s);
-  else
-    nci_rounds<64>(p, ws, s);
+  switch ((p.k + 7) / 8) {
+    case 1: nci_rounds<8>(p, ws, s); break;
+    case 2: nci_rounds<16>(p, ws, s); break;
+    case 3: nci_rounds<24>(p, ws, s); break;
+    case 4: nci_rounds<32>(p, ws, s); break;
+    case 5: nci_rounds<40>(p, ws, s); break;
+    case 6: nci_rounds<48>(p, ws, s); break;
+    case 7: nci_rounds<56>(p, ws, s); break;
+    default: nci_rounds<64>(p, ws, s); break;
+  }
 }
 
 // ---------------------------------------------------------------------------

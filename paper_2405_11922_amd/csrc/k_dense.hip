@@ -536,134 +536,176 @@ void launch_reduce(const Plan& p, void* ws, const float* x, int64_t ldx, hipStre
 // ---------------------------------------------------------------------------
 // Random features (Eqs. Z, R-prime, Ri)
 // ---------------------------------------------------------------------------
-// Pass 1: one wave per row: Z_hat = Z / ||Z||, Zo = sqrt(d) Z_hat Q^T,
-// R' = sqrt(e/d) [sin Zo || cos Zo]; FP64 column sums of R' per workgroup.
-template <int CPL>  // output columns per lane: d <= 64 * CPL
+// Random features on FP32 MFMA, two passes over Z (Eqs. Z, R-prime, Ri):
+//   pass 1: Zo = sqrt(d) Z_hat Q^T, R' = sqrt(e/d) [sin Zo || cos Zo], and
+//           only the FP64 column sums r = sum_i R'_i per workgroup;
+//   pass 2: the same R' again (same instructions, so the same values), then
+//           R_i = R'_i / sqrt(R'_i . r) written out, with FP64 column sums of
+//           R and max |R|.
+// A workgroup walks 64-row slabs; wave w takes 16 rows.  The product is
+// formed on the raw rows and scaled by 1 / ||Z_i|| afterwards.  MFMA layout:
+// lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; its v-th result is
+// D[4 (l / 16) + v][l % 16].  DT = ceil(d / 16) column tiles.
+template <int PASS, int DT>
 __global__ void __launch_bounds__(256)
-k_features1(const float* __restrict__ Z, int64_t n, int d, int dp, const float* __restrict__ Qt32, int rows_per_block,
-            float* __restrict__ R, double* __restrict__ part) {
-  extern __shared__ float qts[];  // d x d, Qt[j][l]
-  __shared__ double cs[4][2 * 64 * CPL];
+k_feat_mfma(const float* __restrict__ Z, int64_t n, int d, int dp, const float* __restrict__ Qt32,
+            int rows_per_block, const double* __restrict__ rsum, float* __restrict__ R, double* __restrict__ part,
+            DevStatus* __restrict__ st) {
+  constexpr int DPAD = 16 * DT, KS = 4 * DT;
+  extern __shared__ float qts[];  // DPAD x DPAD, Q^T[j][l], zero padded
+  __shared__ double cs[4][2 * DPAD];
+  __shared__ double rsl[2 * DPAD];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  for (int e = tid; e < d * d; e += 256) qts[e] = Qt32[e];
+  const int i16 = lane & 15, kq = lane >> 4;
+  for (int e = tid; e < DPAD * DPAD; e += 256) {
+    const int j = e / DPAD, l = e - (e / DPAD) * DPAD;
+    qts[e] = (j < d && l < d) ? Qt32[j * d + l] : 0.0f;
+  }
+  if (PASS == 2)
+    for (int c = tid; c < DPAD; c += 256) {
+      rsl[c] = c < d ? rsum[c] : 0.0;
+      rsl[DPAD + c] = c < d ? rsum[d + c] : 0.0;
+    }
   __syncthreads();
   const float sqrtd = sqrtf(static_cast<float>(d));
   const float amp = static_cast<float>(sqrt(2.718281828459045235 / static_cast<double>(d)));
-  double csin[CPL], ccos[CPL];
-#pragma unroll
-  for (int c = 0; c < CPL; ++c) csin[c] = ccos[c] = 0.0;
-  const int64_t rb = static_cast<int64_t>(blockIdx.x) * rows_per_block;
-  const int64_t re = min(n, rb + rows_per_block);
-  for (int64_t r = rb + w; r < re; r += 4) {
-    float z[CPL];
-    float ss = 0.0f;
-#pragma unroll
-    for (int c = 0; c < CPL; ++c) {
-      const int j = c * 64 + lane;
-      z[c] = j < d ? Z[r * dp + j] : 0.0f;
-      ss += z[c] * z[c];
-    }
-    ss = wave_sum(ss);
-    const float inv = ss > 0.0f ? 1.0f / sqrtf(ss) : 0.0f;
-    float zo[CPL];
-#pragma unroll
-    for (int c = 0; c < CPL; ++c) zo[c] = 0.0f;
-#pragma unroll
-    for (int cj = 0; cj < CPL; ++cj) {
-      for (int jj = 0; jj < 64; ++jj) {
-        const int j = cj * 64 + jj;
-        if (j >= d) break;
-        const float zj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(z[cj]), jj));
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-          const int l = c * 64 + lane;
-          if (l < d) zo[c] = fmaf(zj, qts[j * d + l], zo[c]);
-        }
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < CPL; ++c) {
-      const int l = c * 64 + lane;
-      if (l < d) {
-        const float a = sqrtd * (zo[c] * inv);
-        float sv, cv;
-        sincosf(a, &sv, &cv);
-        sv *= amp;
-        cv *= amp;
-        R[r * 2 * d + l] = sv;
-        R[r * 2 * d + d + l] = cv;
-        csin[c] += static_cast<double>(sv);
-        ccos[c] += static_cast<double>(cv);
-      }
-    }
-  }
-#pragma unroll
-  for (int c = 0; c < CPL; ++c) {
-    cs[w][c * 64 + lane] = csin[c];
-    cs[w][64 * CPL + c * 64 + lane] = ccos[c];
-  }
-  __syncthreads();
-  for (int j = tid; j < 2 * d; j += 256) {
-    const int src = j < d ? j : 64 * CPL + (j - d);
-    const double v = ((cs[0][src] + cs[1][src]) + cs[2][src]) + cs[3][src];
-    part[static_cast<int64_t>(blockIdx.x) * 2 * d + j] = v;
-  }
-}
-
-// Pass 2: R[i] = R'[i] / sqrt(R'[i] . r); FP64 column sums of R and max |R|.
-template <int CPL>
-__global__ void __launch_bounds__(256)
-k_features2(float* __restrict__ R, int64_t n, int d, const double* __restrict__ rsum, int rows_per_block,
-            double* __restrict__ part, DevStatus* __restrict__ st) {
-  __shared__ double rs[2 * 64 * CPL];
-  __shared__ double cs[4][2 * 64 * CPL];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int twod = 2 * d;
-  for (int j = tid; j < twod; j += 256) rs[j] = rsum[j];
-  __syncthreads();
-  double acc[2 * CPL];
+  double csn[DT], ccs[DT];
 #pragma unroll
-  for (int c = 0; c < 2 * CPL; ++c) acc[c] = 0.0;
+  for (int t = 0; t < DT; ++t) csn[t] = ccs[t] = 0.0;
   float mx = 0.0f;
   bool bad = false;
   const int64_t rb = static_cast<int64_t>(blockIdx.x) * rows_per_block;
   const int64_t re = min(n, rb + rows_per_block);
-  for (int64_t r = rb + w; r < re; r += 4) {
-    float v[2 * CPL];
-    double dot = 0.0;
+  for (int64_t r0 = rb; r0 < re; r0 += 64) {
+    const int64_t arow = r0 + 16 * w + i16;
+    const bool aok = arow < re;
+    float a[KS];
+    float ss = 0.0f;
 #pragma unroll
-    for (int c = 0; c < 2 * CPL; ++c) {
-      const int j = c * 64 + lane;
-      v[c] = j < twod ? R[r * twod + j] : 0.0f;
-      if (j < twod) dot = fma(static_cast<double>(v[c]), rs[j], dot);
+    for (int st4 = 0; st4 < KS; ++st4) {
+      const int k = 4 * st4 + kq;
+      a[st4] = (aok && k < d) ? Z[arow * dp + k] : 0.0f;
+      ss += a[st4] * a[st4];
     }
-    dot = wave_sum(dot);
-    if (!(dot > 0.0) || !isfinite(dot)) {
-      bad = true;
-      dot = 1.0;
-    }
-    const float sc = static_cast<float>(1.0 / sqrt(dot));
+    ss += __shfl_xor(ss, 16, 64);
+    ss += __shfl_xor(ss, 32, 64);
+    const float inv = ss > 0.0f ? 1.0f / sqrtf(ss) : 0.0f;  // for row i16 of the tile
+    float invr[4];
 #pragma unroll
-    for (int c = 0; c < 2 * CPL; ++c) {
-      const int j = c * 64 + lane;
-      if (j < twod) {
-        const float o = v[c] * sc;
-        R[r * twod + j] = o;
-        acc[c] += static_cast<double>(o);
-        mx = fmaxf(mx, fabsf(o));
+    for (int v = 0; v < 4; ++v) invr[v] = __shfl(inv, 4 * kq + v, 64);
+    float sv[DT][4], cv[DT][4];
+#pragma unroll
+    for (int t = 0; t < DT; ++t) {
+      v4f_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int st4 = 0; st4 < KS; ++st4)
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[st4], qts[(4 * st4 + kq) * DPAD + 16 * t + i16], acc, 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        float sn, cn;
+        sincosf(sqrtd * (acc[v] * invr[v]), &sn, &cn);
+        sv[t][v] = sn * amp;
+        cv[t][v] = cn * amp;
+      }
+    }
+    if (PASS == 1) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const bool live = r0 + 16 * w + 4 * kq + v < re;
+#pragma unroll
+        for (int t = 0; t < DT; ++t) {
+          if (live && 16 * t + i16 < d) {
+            csn[t] += static_cast<double>(sv[t][v]);
+            ccs[t] += static_cast<double>(cv[t][v]);
+          }
+        }
+      }
+    } else {
+      double pd[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        pd[v] = 0.0;
+#pragma unroll
+        for (int t = 0; t < DT; ++t) {
+          const int c = 16 * t + i16;
+          pd[v] = fma(static_cast<double>(sv[t][v]), rsl[c], pd[v]);
+          pd[v] = fma(static_cast<double>(cv[t][v]), rsl[DPAD + c], pd[v]);
+        }
+      }
+#pragma unroll
+      for (int o = 1; o < 16; o <<= 1)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) pd[v] += __shfl_xor(pd[v], o, 64);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = r0 + 16 * w + 4 * kq + v;
+        if (row >= re) continue;
+        double dot = pd[v];
+        if (!(dot > 0.0) || !isfinite(dot)) {
+          bad = true;
+          dot = 1.0;
+        }
+        const float sc = static_cast<float>(1.0 / sqrt(dot));
+#pragma unroll
+        for (int t = 0; t < DT; ++t) {
+          const int c = 16 * t + i16;
+          if (c < d) {
+            const float o1 = sv[t][v] * sc, o2 = cv[t][v] * sc;
+            R[row * twod + c] = o1;
+            R[row * twod + d + c] = o2;
+            csn[t] += static_cast<double>(o1);
+            ccs[t] += static_cast<double>(o2);
+            mx = fmaxf(mx, fmaxf(fabsf(o1), fabsf(o2)));
+          }
+        }
       }
     }
   }
-  if (bad && lane == 0) atomicOr(&st->err_bits, 8);
-  mx = wave_max(mx);
-  if (lane == 0) atomic_max_nonneg(&st->maxabs_r_bits, mx);
+  // per-workgroup column sums: the four lanes of a column, then the waves
 #pragma unroll
-  for (int c = 0; c < 2 * CPL; ++c) cs[w][c * 64 + lane] = acc[c];
+  for (int t = 0; t < DT; ++t) {
+    csn[t] += __shfl_xor(csn[t], 16, 64);
+    csn[t] += __shfl_xor(csn[t], 32, 64);
+    ccs[t] += __shfl_xor(ccs[t], 16, 64);
+    ccs[t] += __shfl_xor(ccs[t], 32, 64);
+    if (kq == 0) {
+      cs[w][16 * t + i16] = csn[t];
+      cs[w][DPAD + 16 * t + i16] = ccs[t];
+    }
+  }
+  if (PASS == 2) {
+    if (bad) atomicOr(&st->err_bits, 8);
+    mx = wave_max(mx);
+    if (lane == 0) atomic_max_nonneg(&st->maxabs_r_bits, mx);
+  }
   __syncthreads();
   for (int j = tid; j < twod; j += 256) {
-    const double v = ((cs[0][j] + cs[1][j]) + cs[2][j]) + cs[3][j];
+    const int src = j < d ? j : DPAD + (j - d);
+    const double v = ((cs[0][src] + cs[1][src]) + cs[2][src]) + cs[3][src];
     part[static_cast<int64_t>(blockIdx.x) * twod + j] = v;
   }
+}
+
+template <int DT>
+static void features_mfma(const Plan& p, void* ws, hipStream_t s) {
+  DevStatus* st = bufp<DevStatus>(p, ws, B_STATUS);
+  const int nb = p.rowpass_blocks;
+  const int rpb = static_cast<int>((p.n + nb - 1) / nb);
+  double* part = bufp<double>(p, ws, B_RPART);
+  float* R = bufp<float>(p, ws, B_R);
+  const float* Z = bufp<float>(p, ws, B_Z);
+  const float* Qt = bufp<float>(p, ws, B_QT32);
+  const size_t lds = sizeof(float) * 16 * DT * 16 * DT;
+  const int64_t n = p.n;
+  hipLaunchKernelGGL((k_feat_mfma<1, DT>), dim3(nb), dim3(256), lds, s, Z, n, p.d, p.dp, Qt, rpb,
+                     static_cast<const double*>(nullptr), R, part, st);
+  TPO_LAUNCH_CHECK();
+  reduce_parts(part, nb, p.twod, bufp<double>(p, ws, B_REDTMP), bufp<double>(p, ws, B_RSUM), s);
+  hipLaunchKernelGGL((k_feat_mfma<2, DT>), dim3(nb), dim3(256), lds, s, Z, n, p.d, p.dp, Qt, rpb,
+                     bufp<double>(p, ws, B_RSUM), R, part, st);
+  TPO_LAUNCH_CHECK();
+  reduce_parts(part, nb, p.twod, bufp<double>(p, ws, B_REDTMP), bufp<double>(p, ws, B_RCOLSUM), s);
 }
 
 // Deterministic two-level column sums of part (nparts x len): block (x, y)
@@ -704,24 +746,6 @@ void reduce_parts(const double* part, int nparts, int len, double* tmp, double* 
   TPO_LAUNCH_CHECK();
 }
 
-template <int CPL>
-static void features_impl(const Plan& p, void* ws, hipStream_t s) {
-  DevStatus* st = bufp<DevStatus>(p, ws, B_STATUS);
-  const int nb = p.rowpass_blocks;
-  const int rpb = static_cast<int>((p.n + nb - 1) / nb);
-  double* part = bufp<double>(p, ws, B_RPART);
-  float* R = bufp<float>(p, ws, B_R);
-  hipLaunchKernelGGL(k_features1<CPL>, dim3(nb), dim3(256), sizeof(float) * p.d * p.d, s,
-                     bufp<float>(p, ws, B_Z), static_cast<int64_t>(p.n), p.d, p.dp, bufp<float>(p, ws, B_QT32), rpb,
-                     R, part);
-  TPO_LAUNCH_CHECK();
-  reduce_parts(part, nb, p.twod, bufp<double>(p, ws, B_REDTMP), bufp<double>(p, ws, B_RSUM), s);
-  hipLaunchKernelGGL(k_features2<CPL>, dim3(nb), dim3(256), 0, s, R, static_cast<int64_t>(p.n), p.d,
-                     bufp<double>(p, ws, B_RSUM), rpb, part, st);
-  TPO_LAUNCH_CHECK();
-  reduce_parts(part, nb, p.twod, bufp<double>(p, ws, B_REDTMP), bufp<double>(p, ws, B_RCOLSUM), s);
-}
-
 __global__ void k_transpose_f32(const double* __restrict__ Q, int d, float* __restrict__ Qt32) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= d * d) return;
@@ -746,10 +770,16 @@ void launch_features(const Plan& p, void* ws, hipStream_t s) {
                        &st->err_bits);
     TPO_LAUNCH_CHECK();
   }
-  if (p.d <= 64)
-    features_impl<1>(p, ws, s);
-  else
-    features_impl<2>(p, ws, s);
+  switch ((p.d + 15) / 16) {
+    case 1: features_mfma<1>(p, ws, s); break;
+    case 2: features_mfma<2>(p, ws, s); break;
+    case 3: features_mfma<3>(p, ws, s); break;
+    case 4: features_mfma<4>(p, ws, s); break;
+    case 5: features_mfma<5>(p, ws, s); break;
+    case 6: features_mfma<6>(p, ws, s); break;
+    case 7: features_mfma<7>(p, ws, s); break;
+    default: features_mfma<8>(p, ws, s); break;
+  }
 }
 
 void launch_embed(const Plan& p, void* ws, hipStream_t s) {

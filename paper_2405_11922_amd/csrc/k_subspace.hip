@@ -40,8 +40,11 @@ k_si_step(const double* __restrict__ A, int N, const double* __restrict__ Pp, in
   const bool arow_ok = arow < N;
   const int col = 16 * w + i16;
   const bool col_ok = col < l;
-  // Y tile (rows 16 rt.., columns 16 w..) = sum_k A[arow][k] Pp[k][col]
-  v4d_t acc = {0.0, 0.0, 0.0, 0.0};
+  // Y tile (rows 16 rt.., columns 16 w..) = sum_k A[arow][k] Pp[k][col], in
+  // four interleaved partial sums (independent MFMA chains) added at the end
+  v4d_t acc4[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) acc4[c] = v4d_t{0.0, 0.0, 0.0, 0.0};
   for (int k0 = 0; k0 < N; k0 += 128) {
     double av[32], bv[32];
 #pragma unroll
@@ -51,8 +54,10 @@ k_si_step(const double* __restrict__ A, int N, const double* __restrict__ Pp, in
       bv[u] = (col_ok && k < N) ? Pp[static_cast<int64_t>(k) * l + col] : 0.0;
     }
 #pragma unroll
-    for (int u = 0; u < 32; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+    for (int u = 0; u < 32; ++u)
+      acc4[u & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc4[u & 3], 0, 0, 0);
   }
+  const v4d_t acc = (acc4[0] + acc4[1]) + (acc4[2] + acc4[3]);
 #pragma unroll
   for (int v = 0; v < 4; ++v) Ys[(4 * v + kq) * LD + col] = acc[v];
   __syncthreads();
