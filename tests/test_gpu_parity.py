@@ -155,6 +155,26 @@ def test_near_tie_input_decisions():
     _decision_checks("near_tie", out, kw["k"], 20)
 
 
+def test_full_size_mid_fp32():
+    """The benchmarked workload at its full size (200,000 x 400,000, 4M edges,
+    d_U 256 -> 64, k 20, 10 hops): every stage against the oracle, the
+    decisions on the device's own inputs, and the end-to-end labels and
+    objective."""
+    shape = synth.CONFIGS["mid_fp32"]
+    abg = synth.config_abg(shape, seed=0)
+    kw = dict(k=shape.k, alpha=shape.alpha, gamma=shape.gamma, d=shape.d, q=shape.q,
+              oversample=shape.oversample, t_f=shape.t_f, t_g=shape.t_g)
+    log(f"[mid_fp32] n_u={abg.n_u} n_v={abg.n_v} E={abg.n_edges} d_u={abg.d_u}")
+    out = gpu_run(abg, **kw, stages=True)
+    ref = oracle_run(abg, **kw)
+    _stage_checks("mid_fp32", abg, ref, out)
+    _decision_checks("mid_fp32", out, shape.k, shape.t_g)
+    assert oracle.labels_match_up_to_permutation(out["labels"], ref.labels)
+    rel = abs(out["objective"][0] - ref.objective) / abs(ref.objective)
+    log(f"[mid_fp32] end to end: objective rel err {rel:.2e}")
+    assert rel < 1e-6
+
+
 def test_execute_equals_stages_and_is_deterministic():
     make, kw = CASES["reduce_small"]
     abg = make()
