@@ -289,6 +289,80 @@ def planted_abg(n_u: int, n_v: int, n_edges: int, k: int, d_u: int, *,
                          max_degree_v=mdv))
 
 
+def planted_abg_device(n_u: int, n_v: int, n_edges: int, k: int, d_u: int, *, device,
+                       zipf_a: float = 2.0, sigma: float = 1.5, in_out_ratio: float = 8.0,
+                       max_degree: int | None = None, seed: int = 0):
+    """The planted model of planted_abg drawn on a GPU with torch, for sizes
+    where the host generator is too slow (hundreds of millions of edges).
+    Same recipe (Zipf degree weights capped at max_degree, p_in/p_out =
+    in_out_ratio, the first n_edges distinct pairs in draw order, X = mu_c +
+    sigma * eps), different random streams: the graphs are not the host
+    generator's.  Returns device tensors (edge_u, edge_v int32, x_u float32
+    n_u x d_u, labels_u, labels_v int64)."""
+    import torch
+
+    rng = np.random.default_rng(seed)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed) * 1000003 + 17)
+    cu = torch.from_numpy((rng.permutation(n_u) % k).astype(np.int64)).to(device)
+    cv_np = (rng.permutation(n_v) % k).astype(np.int64)
+    th_u = _zipf_weights(rng, zipf_a, n_u)
+    th_v = _zipf_weights(rng, zipf_a, n_v)
+    mdu = max_degree if max_degree is not None else min(max(n_v // 4, 1), 100_000)
+    mdv = max_degree if max_degree is not None else min(max(n_u // 4, 1), 100_000)
+    th_u = _cap_weights(th_u, n_edges, mdu)
+    th_v = _cap_weights(th_v, n_edges, mdv)
+    cdf_u = torch.from_numpy(np.cumsum(th_u) / th_u.sum()).to(device)
+    order_v = np.argsort(cv_np, kind="stable")
+    cum_v_np = np.cumsum(th_v[order_v])
+    starts = np.searchsorted(cv_np[order_v], np.arange(k), side="left")
+    ends = np.searchsorted(cv_np[order_v], np.arange(k), side="right")
+    lo = np.where(starts > 0, cum_v_np[np.maximum(starts - 1, 0)], 0.0)
+    hi = np.where(ends > starts, cum_v_np[np.maximum(ends - 1, 0)], lo)
+    cum_v = torch.from_numpy(cum_v_np).to(device)
+    lo_t, hi_t = torch.from_numpy(lo).to(device), torch.from_numpy(hi).to(device)
+    st_t = torch.from_numpy(starts).to(device)
+    en_t = torch.from_numpy(np.maximum(ends - 1, starts)).to(device)
+    order_v_t = torch.from_numpy(order_v.astype(np.int64)).to(device)
+    p_same = in_out_ratio / (in_out_ratio + k - 1) if k > 1 else 1.0
+    kept = None
+    for _ in range(20):
+        batch = int(n_edges * 1.25) + 1024
+        uu = torch.searchsorted(cdf_u, torch.rand(batch, generator=gen, device=device, dtype=torch.float64),
+                                right=True).clamp_(max=n_u - 1)
+        same = torch.rand(batch, generator=gen, device=device) < p_same
+        if k > 1:
+            off = torch.randint(1, k, (batch,), generator=gen, device=device)
+            cl = torch.where(same, cu[uu], (cu[uu] + off) % k)
+        else:
+            cl = torch.zeros(batch, dtype=torch.int64, device=device)
+        tgt = lo_t[cl] + torch.rand(batch, generator=gen, device=device, dtype=torch.float64) * (hi_t[cl] - lo_t[cl])
+        pos = torch.searchsorted(cum_v, tgt, right=True)
+        pos = torch.minimum(torch.maximum(pos, st_t[cl]), en_t[cl])
+        vv = order_v_t[pos]
+        key = uu * n_v + vv
+        del uu, same, cl, tgt, pos, vv
+        key = key if kept is None else torch.cat([kept, key])
+        # distinct keys, first occurrence order
+        sk, perm = torch.sort(key, stable=True)
+        first = torch.ones_like(sk, dtype=torch.bool)
+        first[1:] = sk[1:] != sk[:-1]
+        pos_first = torch.sort(perm[first]).values
+        kept = key[pos_first]
+        del sk, perm, first, pos_first, key
+        if kept.numel() >= n_edges:
+            kept = kept[:n_edges]
+            break
+    if kept.numel() < n_edges:
+        raise RuntimeError("could not draw enough distinct edges")
+    eu = (kept // n_v).to(torch.int32)
+    ev = (kept % n_v).to(torch.int32)
+    del kept
+    mu = torch.randn(k, d_u, generator=gen, device=device)
+    x = torch.randn(n_u, d_u, generator=gen, device=device).mul_(sigma).add_(mu[cu])
+    return eu, ev, x, cu, torch.from_numpy(cv_np).to(device)
+
+
 def config_abg(shape: JobShape, seed: int = 0) -> ABG:
     return planted_abg(shape.n_u, shape.n_v, shape.n_edges, shape.k, shape.d_u,
                        zipf_a=shape.zipf_a, sigma=shape.sigma,

@@ -60,7 +60,7 @@ typedef struct tpo_problem {
  * details.  Defaults used in the paper: t_f = 5, t_g = 20. */
 typedef struct tpo_params {
   int32_t abi_version; /* TPO_ABI_VERSION */
-  int32_t k;           /* clusters, 1 <= k <= 64 and k <= 2 d_eff */
+  int32_t k;           /* clusters, 1 <= k <= 128 and k <= 2 d_eff */
   double alpha;        /* balance coefficient of Eq. Z-obj, 0 <= alpha < 1 */
   int32_t gamma;       /* propagation hops of Eq. PX, 0..1000 */
   int32_t d;           /* reduced attribute width of Section 3.2.1; 0 or
@@ -200,9 +200,10 @@ typedef enum tpo_buffer_id {
   TPO_BUF_VAL_V = 5,
   TPO_BUF_DEG_U = 6,    /* float [n_u] D_U */
   TPO_BUF_DEG_V = 7,    /* float [n_v] D_V */
-  TPO_BUF_XPRIME = 8,   /* float [n_u x d_eff] X' (reduction on) */
+  TPO_BUF_XPRIME = 8,   /* float [n_u x d_pad] X' (d_pad: d_eff rounded up to a
+                           power of two >= 16; padding columns are zero) */
   TPO_BUF_PSI_D = 9,    /* double [d_u x d_eff] Psi_d (reduction on) */
-  TPO_BUF_Z = 10,       /* float [n_u x d_eff] Z of Eq. PX */
+  TPO_BUF_Z = 10,       /* float [n_u x d_pad] Z of Eq. PX */
   TPO_BUF_Q = 11,       /* double [d_eff x d_eff] Q of Algorithm 1 */
   TPO_BUF_R = 12,       /* float [n_u x 2 d_eff] R of Eq. Ri */
   TPO_BUF_GAMMA = 13,   /* float [n_u x k] Gamma */
@@ -211,6 +212,13 @@ typedef enum tpo_buffer_id {
   TPO_BUF_UPSILON = 16, /* float [n_u x k] */
   TPO_BUF_H = 17,       /* double [2 d_eff x k] */
   TPO_BUF_LABELS = 18,  /* int32 [n_u] */
+  TPO_BUF_T = 19,       /* float [n_v x d_pad] T = D_V^-1 B^T W of the last hop */
+  TPO_BUF_W_LAST = 20,  /* float [n_u x d_pad] W = D_U^-1/2 Z that fed the last
+                           hop (gamma >= 1) */
+  TPO_BUF_SCALE_U = 21, /* float [n_u] D_U^-1/2 (0 for isolated nodes) */
+  TPO_BUF_SCALE_V = 22, /* float [n_v] D_V^-1 (0 for isolated nodes) */
+  TPO_BUF_RSUM = 23,    /* double [2 d_eff] r = sum_i R'_i (Eq. Ri) */
+  TPO_BUF_S = 24,       /* double [2 d_eff x k] S with Gamma = R S */
   TPO_BUF_COUNT
 } tpo_buffer_id;
 

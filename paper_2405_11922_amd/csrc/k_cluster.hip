@@ -41,28 +41,41 @@ k_rowpass_mfma(const float* __restrict__ R, int64_t n, int twod, int k, const fl
   constexpr int TD = 16 * JT, KP = 16 * KT;
   constexpr int RS = TD + 4, OS = KP + 4;
   constexpr int NQ = (JT * KT + 3) / 4, NQ2 = (KT * KT + 3) / 4;
-  constexpr int RPT = kRpRows * TD / 256, UPT = kRpRows * KP / 256;  // prefetched elements per thread
-  __shared__ float Rt[kRpRows * RS];
-  __shared__ float Ut[kRpRows * OS];
-  __shared__ float Ot[kRpRows * OS];
+  // S (or H) and A are staged in LDS when they fit (SLDS, ALDS); otherwise
+  // their operands are read from global memory (they are small and cached).
+  // Slab rows: 64, or 32 when 64 would not fit; RTILES row tiles, each formed
+  // by WPR waves that split the output column tiles.
+  constexpr bool SLDS = TD * OS * 4 <= 72 * 1024;
+  constexpr bool ALDS = KT <= 4;
+  constexpr int FIXED = (SLDS ? TD * OS : 0) + (ALDS ? KP * OS : 0);
+  constexpr int ROWS = 4 * (kRpRows * RS + 2 * kRpRows * OS + FIXED) <= 150 * 1024 ? kRpRows : kRpRows / 2;
+  constexpr int RTILES = ROWS / 16, WPR = 4 / RTILES;
+  constexpr int RPT = ROWS * TD / 256, UPT = ROWS * KP / 256;  // prefetched elements per thread
+  __shared__ float Rt[ROWS * RS];
+  __shared__ float Ut[ROWS * OS];
+  __shared__ float Ot[ROWS * OS];
+  __shared__ float Ss[SLDS ? TD * OS : 1];  // S (or H), TD x KP, zero padded
+  __shared__ float As[ALDS ? KP * OS : 1];  // A (kOnmf), KP x KP, zero padded
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int i16 = lane & 15, kq = lane >> 4;
-  float sb[KT][TD / 4];
-#pragma unroll
-  for (int kt = 0; kt < KT; ++kt)
-#pragma unroll
-    for (int t = 0; t < TD / 4; ++t) {
-      const int r = 4 * t + kq, c = 16 * kt + i16;
-      sb[kt][t] = (r < twod && c < k) ? Sm[r * k + c] : 0.0f;
+  if (SLDS)
+    for (int e = tid; e < TD * KP; e += 256) {
+      const int r = e / KP, c = e - (e / KP) * KP;
+      Ss[r * OS + c] = (r < twod && c < k) ? Sm[r * k + c] : 0.0f;
     }
-  float ab[KT][KP / 4];
-#pragma unroll
-  for (int kt = 0; kt < KT; ++kt)
-#pragma unroll
-    for (int t = 0; t < KP / 4; ++t) {
-      const int r = 4 * t + kq, c = 16 * kt + i16;
-      ab[kt][t] = (MODE == kOnmf && r < k && c < k) ? A32[r * k + c] : 0.0f;
+  if (MODE == kOnmf && ALDS)
+    for (int e = tid; e < KP * KP; e += 256) {
+      const int r = e / KP, c = e - (e / KP) * KP;
+      As[r * OS + c] = (r < k && c < k) ? A32[r * k + c] : 0.0f;
     }
+  auto s_op = [&](int r, int c) -> float {
+    if (SLDS) return Ss[r * OS + c];
+    return (r < twod && c < k) ? Sm[r * k + c] : 0.0f;
+  };
+  auto a_op = [&](int r, int c) -> float {
+    if (ALDS) return As[r * OS + c];
+    return (r < k && c < k) ? A32[r * k + c] : 0.0f;
+  };
   v4f_t acc[NQ], acc2[NQ2];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) acc[q] = v4f_t{0.f, 0.f, 0.f, 0.f};
@@ -93,7 +106,7 @@ k_rowpass_mfma(const float* __restrict__ R, int64_t n, int twod, int k, const fl
     }
   };
   if (rb < re) fetch(rb);
-  for (int64_t r0 = rb; r0 < re; r0 += kRpRows) {
+  for (int64_t r0 = rb; r0 < re; r0 += ROWS) {
 #pragma unroll
     for (int u = 0; u < RPT; ++u) {
       const int e = tid + 256 * u;
@@ -109,19 +122,21 @@ k_rowpass_mfma(const float* __restrict__ R, int64_t n, int twod, int k, const fl
       }
     }
     __syncthreads();
-    if (r0 + kRpRows < re) fetch(r0 + kRpRows);
-    const int rw = 16 * w;  // this wave's rows in the slab
+    if (r0 + ROWS < re) fetch(r0 + ROWS);
+    const int rw = 16 * (w % RTILES);  // this wave's rows in the slab
 #pragma unroll
-    for (int kt = 0; kt < KT; ++kt) {
+    for (int kt = w / RTILES; kt < KT; kt += WPR) {
       v4f_t pv = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
+#pragma unroll 8
       for (int t = 0; t < TD / 4; ++t)
-        pv = __builtin_amdgcn_mfma_f32_16x16x4f32(Rt[(rw + i16) * RS + 4 * t + kq], sb[kt][t], pv, 0, 0, 0);
+        pv = __builtin_amdgcn_mfma_f32_16x16x4f32(Rt[(rw + i16) * RS + 4 * t + kq], s_op(4 * t + kq, 16 * kt + i16),
+                                                  pv, 0, 0, 0);
       v4f_t qv = {0.f, 0.f, 0.f, 0.f};
       if (MODE == kOnmf) {
-#pragma unroll
+#pragma unroll 8
         for (int t = 0; t < KP / 4; ++t)
-          qv = __builtin_amdgcn_mfma_f32_16x16x4f32(Ut[(rw + i16) * OS + 4 * t + kq], ab[kt][t], qv, 0, 0, 0);
+          qv = __builtin_amdgcn_mfma_f32_16x16x4f32(Ut[(rw + i16) * OS + 4 * t + kq], a_op(4 * t + kq, 16 * kt + i16),
+                                                    qv, 0, 0, 0);
       }
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -167,8 +182,8 @@ k_rowpass_mfma(const float* __restrict__ R, int64_t n, int twod, int k, const fl
       const int q = w + 4 * qi;
       if (q < JT * KT) {
         const int jt = q / KT, kt = q - (q / KT) * KT;
-#pragma unroll
-        for (int s4 = 0; s4 < kRpRows / 4; ++s4) {
+#pragma unroll 4
+        for (int s4 = 0; s4 < ROWS / 4; ++s4) {
           const int rr = 4 * s4 + kq;
           acc[qi] = __builtin_amdgcn_mfma_f32_16x16x4f32(Rt[rr * RS + 16 * jt + i16], Ot[rr * OS + 16 * kt + i16],
                                                          acc[qi], 0, 0, 0);
@@ -180,8 +195,8 @@ k_rowpass_mfma(const float* __restrict__ R, int64_t n, int twod, int k, const fl
       const int q = w + 4 * qi;
       if (q < KT * KT) {
         const int ta = q / KT, tb = q - (q / KT) * KT;
-#pragma unroll
-        for (int s4 = 0; s4 < kRpRows / 4; ++s4) {
+#pragma unroll 4
+        for (int s4 = 0; s4 < ROWS / 4; ++s4) {
           const int rr = 4 * s4 + kq;
           acc2[qi] = __builtin_amdgcn_mfma_f32_16x16x4f32(Ot[rr * OS + 16 * ta + i16], Ot[rr * OS + 16 * tb + i16],
                                                           acc2[qi], 0, 0, 0);
@@ -226,8 +241,9 @@ k_rowpass_mfma(const float* __restrict__ R, int64_t n, int twod, int k, const fl
 // H_new is formed in LDS first (every entry reads the old row of H).
 __global__ void __launch_bounds__(1024)
 k_onmf_small(const double* __restrict__ rtu_utu, int twod, int k, double* __restrict__ H, float* __restrict__ H32,
-             float* __restrict__ A32, DevStatus* __restrict__ st) {
-  extern __shared__ double hn[];  // twod x k
+             float* __restrict__ A32, double* __restrict__ hn, DevStatus* __restrict__ st) {
+  // hn: twod x k global scratch for the new H (read back by this workgroup
+  // after the barrier)
   const double* RtU = rtu_utu;
   const double* UtU = rtu_utu + twod * k;
   int hits = 0;
@@ -280,8 +296,10 @@ static void rowpass_j(const Plan& p, void* ws, int mode, const float* Sm, const 
     rowpass_jk<JT, 1>(p, ws, mode, Sm, A32, s);
   else if (p.k <= 32)
     rowpass_jk<JT, 2>(p, ws, mode, Sm, A32, s);
-  else
+  else if (p.k <= 64)
     rowpass_jk<JT, 4>(p, ws, mode, Sm, A32, s);
+  else
+    rowpass_jk<JT, 8>(p, ws, mode, Sm, A32, s);
 }
 
 static void rowpass_any(const Plan& p, void* ws, int mode, const float* Sm, const float* A32, hipStream_t s) {
@@ -305,8 +323,8 @@ void launch_onmf(const Plan& p, void* ws, hipStream_t s) {
   rowpass_any(p, ws, kProject, bufp<float>(p, ws, B_S32), nullptr, s);
   for (int t = 0; t < p.par.t_f; ++t) {
     reduce_parts(bufp<double>(p, ws, B_ONMF_PART), p.rowpass_blocks, len, bufp<double>(p, ws, B_REDTMP), rtu, s);
-    hipLaunchKernelGGL(k_onmf_small, dim3(1), dim3(1024), sizeof(double) * p.twod * p.k, s, rtu, p.twod, p.k, bufp<double>(p, ws, B_H),
-                       bufp<float>(p, ws, B_H32), bufp<float>(p, ws, B_A32), st);
+    hipLaunchKernelGGL(k_onmf_small, dim3(1), dim3(1024), 0, s, rtu, p.twod, p.k, bufp<double>(p, ws, B_H),
+                       bufp<float>(p, ws, B_H32), bufp<float>(p, ws, B_A32), bufp<double>(p, ws, B_H_NEW), st);
     TPO_LAUNCH_CHECK();
     rowpass_any(p, ws, kOnmf, bufp<float>(p, ws, B_H32), bufp<float>(p, ws, B_A32), s);
   }
@@ -444,6 +462,115 @@ k_nci_round(const float* __restrict__ U, int64_t n, int k, const long long* __re
   }
 }
 
+// k > 64: scoring and the label sums in two kernels (Phi for 128 labels
+// fills most of the LDS on its own).  Scores go through in quarters of 32
+// labels, keeping the first maximum.
+constexpr int kNciWide = 128;
+
+__global__ void __launch_bounds__(256)
+k_nci_score_wide(const float* __restrict__ U, int64_t n, int k, const long long* __restrict__ sums,
+                 int32_t* __restrict__ labels, int rows_per_block, const DevStatus* __restrict__ st) {
+  constexpr int KT = kNciWide;
+  __shared__ double phi[KT * KT];
+  __shared__ double fac[KT];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int sft = fixed_point_shift(__uint_as_float(st->maxabs_ups_bits), n);
+  const double inv_scale = ldexp(1.0, -sft);
+  if (sums && tid < k) {
+    const long long c = sums[k * k + tid];
+    fac[tid] = c > 0 ? inv_scale / sqrt(static_cast<double>(c)) : 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < KT * KT; e += 256) {
+    const int t = e / KT, l = e - (e / KT) * KT;
+    double v = 0.0;
+    if (t < k && l < k) v = sums ? static_cast<double>(sums[l * k + t]) * fac[l] : (t == l ? 1.0 : 0.0);
+    phi[e] = v;
+  }
+  __syncthreads();
+  const int64_t rb = static_cast<int64_t>(blockIdx.x) * rows_per_block;
+  const int64_t re = min(n, rb + rows_per_block);
+  for (int64_t b0 = rb + static_cast<int64_t>(w) * 64; b0 < re; b0 += 256) {
+    const int64_t row = b0 + lane;
+    const bool live = row < re;
+    float u[KT];
+#pragma unroll
+    for (int t = 0; t < KT; ++t) u[t] = (live && t < k) ? U[row * k + t] : 0.0f;
+    int best = 0;
+    double bestv = 0.0;
+#pragma unroll
+    for (int h = 0; h < KT / 32; ++h) {
+      if (32 * h >= k) break;
+      double sc[32];
+#pragma unroll
+      for (int l = 0; l < 32; ++l) sc[l] = 0.0;
+#pragma unroll
+      for (int t = 0; t < KT; ++t) {
+        if (t < k) {
+          const double x = static_cast<double>(u[t]);
+#pragma unroll
+          for (int l = 0; l < 32; ++l) sc[l] = fma(x, phi[t * KT + 32 * h + l], sc[l]);
+        }
+      }
+#pragma unroll
+      for (int l = 0; l < 32; ++l) {
+        const int L = 32 * h + l;
+        if (L < k && (L == 0 || sc[l] > bestv)) {
+          bestv = sc[l];
+          best = L;
+        }
+      }
+    }
+    if (live) labels[row] = best;
+  }
+}
+
+// Fixed-point sums of the U rows per label and the label counts for this
+// workgroup's rows, written transposed (entry o at part[o * gridDim.x + block]).
+__global__ void __launch_bounds__(256)
+k_nci_accum_wide(const float* __restrict__ U, int64_t n, int k, const int32_t* __restrict__ labels,
+                 long long* __restrict__ part, int rows_per_block, const DevStatus* __restrict__ st) {
+  __shared__ long long accl[kNciWide * kNciWide + kNciWide];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int sft = fixed_point_shift(__uint_as_float(st->maxabs_ups_bits), n);
+  for (int e = tid; e < k * k + k; e += 256) accl[e] = 0;
+  __syncthreads();
+  const int64_t rb = static_cast<int64_t>(blockIdx.x) * rows_per_block;
+  const int64_t re = min(n, rb + rows_per_block);
+  for (int64_t r = rb + w; r < re; r += 4) {
+    const int lab = labels[r];
+    for (int t = lane; t < k; t += 64)
+      atomicAdd(reinterpret_cast<unsigned long long*>(&accl[lab * k + t]),
+                static_cast<unsigned long long>(to_fixed(U[r * k + t], sft)));
+    if (lane == 0) atomicAdd(reinterpret_cast<unsigned long long*>(&accl[k * k + lab]), 1ull);
+  }
+  __syncthreads();
+  for (int e = tid; e < k * k + k; e += 256) part[static_cast<int64_t>(e) * gridDim.x + blockIdx.x] = accl[e];
+}
+
+static void nci_rounds_wide(const Plan& p, void* ws, hipStream_t s) {
+  DevStatus* st = bufp<DevStatus>(p, ws, B_STATUS);
+  const int k = p.k;
+  long long* part = bufp<long long>(p, ws, B_NCI_PART);
+  long long* sums = bufp<long long>(p, ws, B_NCI_SUM);
+  const int nb = p.rowpass_blocks;
+  const int rpb = static_cast<int>((p.n + nb - 1) / nb);
+  const float* U = bufp<float>(p, ws, B_UPS);
+  int32_t* labels = bufp<int32_t>(p, ws, B_LABELS);
+  const int rounds = std::max(p.par.t_g, 1);
+  for (int t = 1; t <= rounds; ++t) {
+    hipLaunchKernelGGL(k_nci_score_wide, dim3(nb), dim3(256), 0, s, U, static_cast<int64_t>(p.n), k,
+                       t == 1 ? nullptr : sums, labels, rpb, st);
+    TPO_LAUNCH_CHECK();
+    if (t < p.par.t_g) {
+      hipLaunchKernelGGL(k_nci_accum_wide, dim3(nb), dim3(256), 0, s, U, static_cast<int64_t>(p.n), k, labels,
+                         part, rpb, st);
+      TPO_LAUNCH_CHECK();
+      sum_parts_i64(part, nb, k * k + k, sums, s);
+    }
+  }
+}
+
 template <int KT>
 static void nci_rounds(const Plan& p, void* ws, hipStream_t s) {
   DevStatus* st = bufp<DevStatus>(p, ws, B_STATUS);
@@ -475,7 +602,8 @@ void launch_nci(const Plan& p, void* ws, hipStream_t s) {
     case 5: nci_rounds<40>(p, ws, s); break;
     case 6: nci_rounds<48>(p, ws, s); break;
     case 7: nci_rounds<56>(p, ws, s); break;
-    default: nci_rounds<64>(p, ws, s); break;
+    case 8: nci_rounds<64>(p, ws, s); break;
+    default: nci_rounds_wide(p, ws, s); break;
   }
 }
 
@@ -483,27 +611,41 @@ void launch_nci(const Plan& p, void* ws, hipStream_t s) {
 // Objective (Eq. obj1 with s ~ R R^T): cluster sums c_l of R rows in fixed
 // point, then obj1 = sum_l c_l.(tot - c_l)/|C_l| and sum_l ||c_l||^2/|C_l|.
 // ---------------------------------------------------------------------------
+// Cluster sums of R rows (fixed point) and label counts for this workgroup's
+// rows, over the column range [c0, c0 + cw) of blockIdx.y (the range is split
+// so that the k x cw sums fit in LDS); counts by the y = 0 workgroups only.
+// Written transposed: entry o (l * twod + j, then k * twod + l for counts) at
+// part[o * gridDim.x + blockIdx.x].
+constexpr int kObjLdsBytes = 128 * 1024;
+
 __global__ void __launch_bounds__(1024)
 k_obj_accum(const float* __restrict__ R, int64_t n, int twod, const int32_t* __restrict__ labels, int k,
-            long long* __restrict__ part, int rows_per_block, const DevStatus* __restrict__ st) {
-  extern __shared__ char smem_raw[];
-  long long* accl = reinterpret_cast<long long*>(smem_raw);  // k x twod sums, then k counts
-  long long* cntl = accl + k * twod;
+            int cw, long long* __restrict__ part, int rows_per_block, const DevStatus* __restrict__ st) {
+  __shared__ long long accl[kObjLdsBytes / 8];  // k x cw sums, then k counts
+  const int c0 = blockIdx.y * cw;
+  const int cn = min(cw, twod - c0);
+  long long* cntl = accl + k * cw;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int sft = fixed_point_shift(__uint_as_float(st->maxabs_r_bits), n);
-  for (int e = tid; e < k * twod + k; e += blockDim.x) accl[e] = 0;
+  for (int e = tid; e < k * cw + k; e += blockDim.x) accl[e] = 0;
   __syncthreads();
   const int64_t rb = static_cast<int64_t>(blockIdx.x) * rows_per_block;
   const int64_t re = min(n, rb + rows_per_block);
   for (int64_t r = rb + w; r < re; r += blockDim.x >> 6) {
     const int lab = labels[r];
-    for (int j = lane; j < twod; j += 64)
-      atomicAdd(reinterpret_cast<unsigned long long*>(&accl[lab * twod + j]),
-                static_cast<unsigned long long>(to_fixed(R[r * twod + j], sft)));
-    if (lane == 0) atomicAdd(reinterpret_cast<unsigned long long*>(&cntl[lab]), 1ull);
+    for (int j = lane; j < cn; j += 64)
+      atomicAdd(reinterpret_cast<unsigned long long*>(&accl[lab * cw + j]),
+                static_cast<unsigned long long>(to_fixed(R[r * twod + c0 + j], sft)));
+    if (lane == 0 && blockIdx.y == 0) atomicAdd(reinterpret_cast<unsigned long long*>(&cntl[lab]), 1ull);
   }
   __syncthreads();
-  for (int e = tid; e < k * twod + k; e += blockDim.x) part[static_cast<int64_t>(e) * gridDim.x + blockIdx.x] = accl[e];
+  for (int e = tid; e < k * cn; e += blockDim.x) {
+    const int l = e / cn, j = e - (e / cn) * cn;
+    part[static_cast<int64_t>(l * twod + c0 + j) * gridDim.x + blockIdx.x] = accl[l * cw + j];
+  }
+  if (blockIdx.y == 0)
+    for (int l = tid; l < k; l += blockDim.x)
+      part[static_cast<int64_t>(k * twod + l) * gridDim.x + blockIdx.x] = cntl[l];
 }
 
 __global__ void __launch_bounds__(1024)
@@ -542,9 +684,10 @@ void launch_objective(const Plan& p, void* ws, hipStream_t s) {
   const int k = p.k, twod = p.twod;
   const int nb = p.obj_blocks;
   const int rpb = static_cast<int>((p.n + nb - 1) / nb);
-  const size_t lds = sizeof(long long) * (k * twod + k);
-  hipLaunchKernelGGL(k_obj_accum, dim3(nb), dim3(1024), lds, s, bufp<float>(p, ws, B_R), static_cast<int64_t>(p.n),
-                     twod, bufp<int32_t>(p, ws, B_LABELS), k, part, rpb, st);
+  const int cw = std::min(twod, (kObjLdsBytes / 8 - k) / k);  // columns per LDS pass
+  const int ny = (twod + cw - 1) / cw;
+  hipLaunchKernelGGL(k_obj_accum, dim3(nb, ny), dim3(1024), 0, s, bufp<float>(p, ws, B_R), static_cast<int64_t>(p.n),
+                     twod, bufp<int32_t>(p, ws, B_LABELS), k, cw, part, rpb, st);
   TPO_LAUNCH_CHECK();
   sum_parts_i64(part, nb, k * twod + k, sums, s);
   hipLaunchKernelGGL(k_obj_final, dim3(1), dim3(1024), 0, s, sums, k, twod, static_cast<int64_t>(p.n), st);

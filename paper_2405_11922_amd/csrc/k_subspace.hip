@@ -1,5 +1,5 @@
-// Randomized subspace iteration on a small symmetric FP64 matrix A (N x N,
-// N <= 256: the attribute Gram C = X^T X of the reduction, or K = R^T R of
+// Randomized subspace iteration on a small symmetric FP64 matrix A (N x N:
+// the attribute Gram C = X^T X of the reduction, or K = R^T R of
 // RandomizedSVD), with the basis re-orthonormalised by Cholesky QR after
 // every product (Halko et al., Algorithms 4.4 and 5.1, as used by
 // Algorithm 2 and by the attribute reduction of Section 3.2.1).
@@ -18,7 +18,7 @@
 
 namespace tpo {
 
-constexpr int kSiMaxParts = 16;  // row blocks of 16: N <= 256
+constexpr int kSiBatch = 16;  // partials loaded per batch before they are summed
 
 // Y = A[rows] Pp;  Pn[rows] = Y Li^T (or Y when Li is null);  the lower
 // 16 x 16 tiles of Pn[rows]^T Pn[rows] to part[blockIdx];  when Qout is
@@ -145,13 +145,15 @@ k_si_chol(const double* __restrict__ part, int nparts, int l, double* __restrict
   for (int e = threadIdx.x; e < np * np; e += blockDim.x) {
     const int i = e / np, j = e - (e / np) * np;
     const bool in = i / 16 >= j / 16 && i < l && j < l;
-    double v[kSiMaxParts];
-#pragma unroll
-    for (int b = 0; b < kSiMaxParts; ++b)
-      v[b] = (in && b < nparts) ? part[static_cast<int64_t>(b) * np * np + e] : 0.0;
     double s = 0.0;
+    for (int b0 = 0; b0 < nparts; b0 += kSiBatch) {
+      double v[kSiBatch];
 #pragma unroll
-    for (int b = 0; b < kSiMaxParts; ++b) s += v[b];
+      for (int b = 0; b < kSiBatch; ++b)
+        v[b] = (in && b0 + b < nparts) ? part[static_cast<int64_t>(b0 + b) * np * np + e] : 0.0;
+#pragma unroll
+      for (int b = 0; b < kSiBatch; ++b) s += v[b];
+    }
     if (!in) s = (i / 16 >= j / 16 && i == j) ? 1.0 : 0.0;
     G[i * kC16Ld + j] = s;
   }
@@ -192,7 +194,6 @@ static void si_run(const double* A, int N, const double* omega, int l, int n_ort
 
 void subspace_iterate(const double* A, int N, const double* omega, int l, int n_orth, double* pa, double* pb,
                       double* li, double* part, double* m_out, double* p_out, int32_t* err_bits, hipStream_t s) {
-  if ((N + 15) / 16 > kSiMaxParts) throw std::runtime_error("subspace_iterate: N beyond 16 row blocks");
   switch ((l + 15) / 16) {
     case 1: si_run<1>(A, N, omega, l, n_orth, pa, pb, li, part, m_out, p_out, err_bits, s); break;
     case 2: si_run<2>(A, N, omega, l, n_orth, pa, pb, li, part, m_out, p_out, err_bits, s); break;

@@ -19,7 +19,7 @@ struct tpo_plan : public Plan {};
 
 namespace {
 
-constexpr int kMaxK = 64;
+constexpr int kMaxK = 128;
 constexpr int kMaxDEff = 128;
 constexpr int kMaxDu = 4096;
 
@@ -154,6 +154,7 @@ void build_layout(Plan& p) {
   add(B_UPS, 4 * n * k);
   add(B_H, 8 * twod * k);
   add(B_H32, 4 * twod * k);
+  add(B_H_NEW, 8 * twod * k);
   add(B_RTU, 8 * (twod * k + k * k));
   add(B_UTU, 8);
   add(B_A32, 4 * k * k);
@@ -417,6 +418,17 @@ tpo_status tpo_plan_buffer(const tpo_plan* plan, void* ws, int32_t which, void**
     case TPO_BUF_UPSILON: b = B_UPS; r = p.n; c = p.k; break;
     case TPO_BUF_H: b = B_H; r = p.twod; c = p.k; dt = TPO_DTYPE_F64; break;
     case TPO_BUF_LABELS: b = B_LABELS; r = p.n; dt = TPO_DTYPE_I32; break;
+    case TPO_BUF_T: b = B_T; r = p.m; c = p.dp; break;
+    case TPO_BUF_W_LAST:
+      if (p.par.gamma < 1) return TPO_EINVAL;
+      b = ((p.par.gamma - 1) % 2 == 0) ? B_W0 : B_W1;  // the hops alternate between the two
+      r = p.n;
+      c = p.dp;
+      break;
+    case TPO_BUF_SCALE_U: b = B_ISQ_U; r = p.n; break;
+    case TPO_BUF_SCALE_V: b = B_INV_V; r = p.m; break;
+    case TPO_BUF_RSUM: b = B_RSUM; r = p.twod; dt = TPO_DTYPE_F64; break;
+    case TPO_BUF_S: b = B_EEVAL; r = p.twod; c = p.k; dt = TPO_DTYPE_F64; break;
     default: return TPO_EINVAL;
   }
   *ptr = bufp<char>(p, ws, b);

@@ -65,7 +65,7 @@ enum Buf {
   B_OMEGA, B_K, B_M_A, B_M_B, B_EK_A, B_EK_B, B_EK_C, B_EEVAL, B_S32,
   B_GAMMA, B_SIGMA, B_PSI, B_OMR,
   // onmf
-  B_UPS, B_H, B_H32, B_RTU, B_UTU, B_A32, B_ONMF_PART,
+  B_UPS, B_H, B_H32, B_H_NEW, B_RTU, B_UTU, B_A32, B_ONMF_PART,
   // nci / objective
   B_LABELS, B_NCI_PART, B_NCI_SUM, B_OBJ_PART, B_OBJ_SUM,
   // subspace iteration (reduction and embedding)

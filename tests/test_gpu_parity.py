@@ -46,6 +46,20 @@ CASES = {
     "k64": (lambda: synth.planted_abg(5000, 4000, 60_000, 64, 48, zipf_a=2.0, seed=8, sigma=0.5,
                                       in_out_ratio=30.0),
             dict(k=64, alpha=0.5, gamma=3, d=0)),
+    # k = 100 (the 150M-edge workload's k): wide NCI, eight-tile row pass,
+    # sketch width 110 (the global-memory embedding path)
+    "k100": (lambda: synth.planted_abg(8000, 6000, 120_000, 100, 64, zipf_a=2.0, seed=12, sigma=0.5,
+                                       in_out_ratio=40.0),
+             dict(k=100, alpha=0.5, gamma=3, d=0)),
+    # k = 128 with d = 128 (2d = 256): the widest row pass, objective sums in
+    # several column ranges
+    "k128": (lambda: synth.planted_abg(7000, 5000, 100_000, 128, 128, zipf_a=2.0, seed=13, sigma=0.5,
+                                       in_out_ratio=40.0),
+             dict(k=128, alpha=0.5, gamma=2, d=0)),
+    # d_U = 512 reduced to 64 (the 150M-edge workload's attribute width): 32
+    # row blocks in the reduction's subspace iteration
+    "reduce512": (lambda: synth.planted_abg(3000, 4000, 30_000, 8, 512, zipf_a=2.0, seed=14),
+                  dict(k=8, alpha=0.5, gamma=3, d=64)),
     # heavy hubs on both sides (rows split into chunks)
     "hubs": (lambda: synth.planted_abg(1500, 1200, 60_000, 3, 16, zipf_a=1.5, max_degree=1000, seed=3),
              dict(k=3, alpha=0.5, gamma=3, d=0)),
