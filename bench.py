@@ -91,20 +91,31 @@ def main() -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
     shape = synth.CONFIGS[args.config]
-    t0 = time.time()
-    abg = synth.config_abg(shape, seed=args.seed)
-    log(f"[bench] generated {args.config}: n_u={abg.n_u} n_v={abg.n_v} E={abg.n_edges} "
-        f"d_u={abg.d_u} in {time.time() - t0:.1f}s")
     dev = torch.device("cuda:0")
-    eu = torch.from_numpy(abg.edge_u).to(dev)
-    ev = torch.from_numpy(abg.edge_v).to(dev)
-    x = torch.from_numpy(abg.x_u).to(dev)
+    t0 = time.time()
+    on_device = shape.n_edges > 20_000_000  # the host generator is too slow beyond this
+    if on_device:
+        eu, ev, x, _, _ = synth.planted_abg_device(shape.n_u, shape.n_v, shape.n_edges, shape.k, shape.d_u,
+                                                   device=dev, zipf_a=shape.zipf_a, sigma=shape.sigma,
+                                                   in_out_ratio=shape.in_out_ratio, max_degree=shape.max_degree,
+                                                   seed=args.seed)
+        torch.cuda.synchronize()
+        abg = None
+        abg_n_edges, abg_d_u = shape.n_edges, shape.d_u
+    else:
+        abg = synth.config_abg(shape, seed=args.seed)
+        eu = torch.from_numpy(abg.edge_u).to(dev)
+        ev = torch.from_numpy(abg.edge_v).to(dev)
+        x = torch.from_numpy(abg.x_u).to(dev)
+        abg_n_edges, abg_d_u = abg.n_edges, abg.d_u
+    log(f"[bench] generated {args.config} ({'on the GPU' if on_device else 'on the host'}): n_u={shape.n_u} "
+        f"n_v={shape.n_v} E={abg_n_edges} d_u={abg_d_u} in {time.time() - t0:.1f}s")
     kw = dict(k=shape.k, alpha=shape.alpha, gamma=shape.gamma, d=shape.d, q=shape.q,
               oversample=shape.oversample, t_f=shape.t_f, t_g=shape.t_g, seed=args.seed)
-    plan = tpo.Plan.create(abg.n_u, abg.n_v, abg.n_edges, abg.d_u, device=dev, timing=False, **kw)
-    plan_t = tpo.Plan.create(abg.n_u, abg.n_v, abg.n_edges, abg.d_u, device=dev, timing=True, **kw)
-    labels = torch.empty(abg.n_u, dtype=torch.int32, device=dev)
-    emb = torch.empty(abg.n_u, shape.k, dtype=torch.float32, device=dev)
+    plan = tpo.Plan.create(shape.n_u, shape.n_v, abg_n_edges, abg_d_u, device=dev, timing=False, **kw)
+    plan_t = tpo.Plan.create(shape.n_u, shape.n_v, abg_n_edges, abg_d_u, device=dev, timing=True, **kw)
+    labels = torch.empty(shape.n_u, dtype=torch.int32, device=dev)
+    emb = torch.empty(shape.n_u, shape.k, dtype=torch.float32, device=dev)
     d_eff, l_r, kp = tpo.tpo_plan_dims(plan.handle)
 
     if args.calibrate_copy:
@@ -136,16 +147,16 @@ def main() -> int:
     st = {key: statistics.median(s[key] for s in stats) for key in stats[0]}
     log("[bench] stages ms: " + " ".join(f"{k[3:]}={st[k]:.3f}" for k in st if k.startswith("ms_")))
     e_u = int(st["n_unique_edges"])
-    has_vals = e_u < abg.n_edges
+    has_vals = e_u < abg_n_edges
     gedge_hops = shape.gamma * e_u / (st["ms_propagate"] * 1e-3) / 1e9 if st["ms_propagate"] > 0 else None
     u_avg = st["ms_spmm_u"] / max(st["n_spmm_u"], 1)
     v_avg = st["ms_spmm_v"] / max(st["n_spmm_v"], 1)
     if u_avg >= v_avg:
         side, kern, per, avg = "U", "k_spmm_rowgroup<64,U> (Z = X' + alpha D_U^-1/2 B T)", spmm_u_bytes(
-            abg.n_u, abg.n_v, e_u, d_eff, has_vals), u_avg
+            shape.n_u, shape.n_v, e_u, d_eff, has_vals), u_avg
     else:
         side, kern, per, avg = "V", "k_spmm_rowgroup<64,V> (T = D_V^-1 B^T W)", spmm_v_bytes(
-            abg.n_u, abg.n_v, e_u, d_eff, has_vals), v_avg
+            shape.n_u, shape.n_v, e_u, d_eff, has_vals), v_avg
     achieved = per / (avg * 1e-3) / 1e9
     traffic = counted_traffic(args.config, side)
     roofline = {"kernel": kern, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -168,11 +179,11 @@ def main() -> int:
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"{args.config}: planted degree-corrected bipartite SBM, |U|={abg.n_u}, "
-                        f"|V|={abg.n_v}, {abg.n_edges} edges, k={shape.k}, Zipf({shape.zipf_a}) degrees, "
-                        f"d_U={abg.d_u} -> d={d_eff}, gamma={shape.gamma}, alpha={shape.alpha}, "
+            "workload": f"{args.config}: planted degree-corrected bipartite SBM, |U|={shape.n_u}, "
+                        f"|V|={shape.n_v}, {abg_n_edges} edges, k={shape.k}, Zipf({shape.zipf_a}) degrees, "
+                        f"d_U={abg_d_u} -> d={d_eff}, gamma={shape.gamma}, alpha={shape.alpha}, "
                         f"q={shape.q}, T_f={shape.t_f}, T_g={shape.t_g}",
-            "n_u": abg.n_u, "n_v": abg.n_v, "n_edges": abg.n_edges, "k": shape.k, "d_u": abg.d_u,
+            "n_u": shape.n_u, "n_v": shape.n_v, "n_edges": abg_n_edges, "k": shape.k, "d_u": abg_d_u,
             "d": d_eff, "k_prime": kp, "l_r": l_r, "gamma": shape.gamma,
         },
         "gedge_hop_per_s": round(gedge_hops, 3) if gedge_hops else None,
@@ -183,7 +194,9 @@ def main() -> int:
         "objective": obj[0],
     }
 
-    if args.cpu_baseline == "on":
+    if args.cpu_baseline == "on" and on_device:
+        log("[bench] no CPU baseline for the on-GPU generated workload (the oracle needs the host arrays)")
+    if args.cpu_baseline == "on" and not on_device:
         import oracle
         from threadpoolctl import threadpool_info
 
