@@ -16,6 +16,7 @@ namespace tpo {
 enum RowPassMode { kProject = 0, kOnmf = 1 };
 
 typedef float v4f_t __attribute__((ext_vector_type(4)));
+typedef double v4d_t __attribute__((ext_vector_type(4)));
 
 // Row passes on FP32 MFMA (v_mfma_f32_16x16x4f32: lane l supplies
 // A[l % 16][l / 16] and B[l / 16][l % 16], its v-th result is
@@ -463,17 +464,27 @@ k_nci_round(const float* __restrict__ U, int64_t n, int k, const long long* __re
 }
 
 // k > 64: scoring and the label sums in two kernels (Phi for 128 labels
-// fills most of the LDS on its own).  Scores go through in quarters of 32
-// labels, keeping the first maximum.
+// fills most of the LDS on its own).
+//
+// Scores on FP64 MFMA (v_mfma_f64_16x16x4f64: lane l supplies A[l % 16][l / 16]
+// and B[l / 16][l % 16], its v-th result is D[4 v + l / 16][l % 16]).  A wave
+// forms S^T = Phi^T U^T for 16 rows at a time: A = Phi^T (a 16-label tile),
+// B = U^T (the 16 rows), so lane l ends with the scores of row l % 16 for the
+// labels 16 c + 4 v + l / 16, and the first maximum is found in registers and
+// then over the four lanes that share the row.  Phi (k x 16 LT, zero padded)
+// sits in LDS; eight waves share it, two per SIMD.
 constexpr int kNciWide = 128;
 
-__global__ void __launch_bounds__(256)
-k_nci_score_wide(const float* __restrict__ U, int64_t n, int k, const long long* __restrict__ sums,
-                 int32_t* __restrict__ labels, int rows_per_block, const DevStatus* __restrict__ st) {
-  constexpr int KT = kNciWide;
-  __shared__ double phi[KT * KT];
-  __shared__ double fac[KT];
+template <int LT>
+__global__ void __launch_bounds__(512)
+k_nci_score_mfma(const float* __restrict__ U, int64_t n, int k, const long long* __restrict__ sums,
+                 int32_t* __restrict__ labels, const DevStatus* __restrict__ st) {
+  constexpr int NL = 16 * LT;
+  constexpr int KS = NL / 4;  // k steps of the padded contraction
+  __shared__ double phi[NL * NL];  // phi[t * NL + l]
+  __shared__ double fac[NL];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int i16 = lane & 15, g = lane >> 4;
   const int sft = fixed_point_shift(__uint_as_float(st->maxabs_ups_bits), n);
   const double inv_scale = ldexp(1.0, -sft);
   if (sums && tid < k) {
@@ -481,71 +492,125 @@ k_nci_score_wide(const float* __restrict__ U, int64_t n, int k, const long long*
     fac[tid] = c > 0 ? inv_scale / sqrt(static_cast<double>(c)) : 0.0;
   }
   __syncthreads();
-  for (int e = tid; e < KT * KT; e += 256) {
-    const int t = e / KT, l = e - (e / KT) * KT;
+  for (int e = tid; e < NL * NL; e += 512) {
+    const int t = e / NL, l = e - (e / NL) * NL;
     double v = 0.0;
     if (t < k && l < k) v = sums ? static_cast<double>(sums[l * k + t]) * fac[l] : (t == l ? 1.0 : 0.0);
     phi[e] = v;
   }
   __syncthreads();
-  const int64_t rb = static_cast<int64_t>(blockIdx.x) * rows_per_block;
-  const int64_t re = min(n, rb + rows_per_block);
-  for (int64_t b0 = rb + static_cast<int64_t>(w) * 64; b0 < re; b0 += 256) {
-    const int64_t row = b0 + lane;
-    const bool live = row < re;
-    float u[KT];
+  const int64_t ntiles = (n + 15) / 16;
+  for (int64_t tile = static_cast<int64_t>(blockIdx.x) * 8 + w; tile < ntiles;
+       tile += static_cast<int64_t>(gridDim.x) * 8) {
+    const int64_t row = tile * 16 + i16;
+    const bool live = row < n;
+    const float* urow = U + row * k;
+    float ub[KS];
 #pragma unroll
-    for (int t = 0; t < KT; ++t) u[t] = (live && t < k) ? U[row * k + t] : 0.0f;
-    int best = 0;
-    double bestv = 0.0;
+    for (int s = 0; s < KS; ++s) {
+      const int t = 4 * s + g;
+      ub[s] = (live && t < k) ? urow[t] : 0.0f;
+    }
+    v4d_t acc[LT];
 #pragma unroll
-    for (int h = 0; h < KT / 32; ++h) {
-      if (32 * h >= k) break;
-      double sc[32];
+    for (int c = 0; c < LT; ++c) acc[c] = v4d_t{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int l = 0; l < 32; ++l) sc[l] = 0.0;
+    for (int s = 0; s < KS; ++s) {
+      if (4 * s >= k) break;  // uniform: the padded steps add zeros
+      const double b = static_cast<double>(ub[s]);
+      const double* pr = phi + (4 * s + g) * NL + i16;
 #pragma unroll
-      for (int t = 0; t < KT; ++t) {
-        if (t < k) {
-          const double x = static_cast<double>(u[t]);
+      for (int c = 0; c < LT; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(pr[16 * c], b, acc[c], 0, 0, 0);
+    }
+    // first maximum: labels in increasing order within the lane, then the
+    // lower label wins a tie between lanes
+    int best = g;
+    double bestv = acc[0][0];
 #pragma unroll
-          for (int l = 0; l < 32; ++l) sc[l] = fma(x, phi[t * KT + 32 * h + l], sc[l]);
-        }
-      }
+    for (int c = 0; c < LT; ++c) {
 #pragma unroll
-      for (int l = 0; l < 32; ++l) {
-        const int L = 32 * h + l;
-        if (L < k && (L == 0 || sc[l] > bestv)) {
-          bestv = sc[l];
+      for (int v = 0; v < 4; ++v) {
+        const int L = 16 * c + 4 * v + g;
+        if (L < k && acc[c][v] > bestv) {
+          bestv = acc[c][v];
           best = L;
         }
       }
     }
-    if (live) labels[row] = best;
+#pragma unroll
+    for (int off = 16; off < 64; off <<= 1) {
+      const double ov = __shfl_xor(bestv, off, 64);
+      const int ob = __shfl_xor(best, off, 64);
+      if (ov > bestv || (ov == bestv && ob < best)) {
+        bestv = ov;
+        best = ob;
+      }
+    }
+    if (live && g == 0) labels[row] = best;
   }
 }
 
 // Fixed-point sums of the U rows per label and the label counts for this
-// workgroup's rows, written transposed (entry o at part[o * gridDim.x + block]).
-__global__ void __launch_bounds__(256)
+// workgroup's rows [rb, rb + rows_per_block), written transposed (entry o at
+// part[o * gridDim.x + block]).  A wave takes 64 rows at a time and reads
+// them as one contiguous run of 64 k values, eight loads in flight per lane;
+// element e of the run is (row e / k, column e % k).  For k > 64 the 64 lanes
+// of one addition touch 64 distinct sums.
+constexpr int kNciAccBatch = 8;
+
+__global__ void __launch_bounds__(1024)
 k_nci_accum_wide(const float* __restrict__ U, int64_t n, int k, const int32_t* __restrict__ labels,
-                 long long* __restrict__ part, int rows_per_block, const DevStatus* __restrict__ st) {
+                 long long* __restrict__ part, int64_t rows_per_block, const DevStatus* __restrict__ st) {
   __shared__ long long accl[kNciWide * kNciWide + kNciWide];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int sft = fixed_point_shift(__uint_as_float(st->maxabs_ups_bits), n);
-  for (int e = tid; e < k * k + k; e += 256) accl[e] = 0;
+  for (int e = tid; e < k * k + k; e += 1024) accl[e] = 0;
   __syncthreads();
   const int64_t rb = static_cast<int64_t>(blockIdx.x) * rows_per_block;
   const int64_t re = min(n, rb + rows_per_block);
-  for (int64_t r = rb + w; r < re; r += 4) {
-    const int lab = labels[r];
-    for (int t = lane; t < k; t += 64)
-      atomicAdd(reinterpret_cast<unsigned long long*>(&accl[lab * k + t]),
-                static_cast<unsigned long long>(to_fixed(U[r * k + t], sft)));
-    if (lane == 0) atomicAdd(reinterpret_cast<unsigned long long*>(&accl[k * k + lab]), 1ull);
+  for (int64_t r0 = rb + 64 * static_cast<int64_t>(w); r0 < re; r0 += 64 * 16) {
+    const int nr = static_cast<int>(min(static_cast<int64_t>(64), re - r0));
+    const int lab = lane < nr ? labels[r0 + lane] : 0;
+    if (lane < nr) atomicAdd(reinterpret_cast<unsigned long long*>(&accl[k * k + lab]), 1ull);
+    const float* src = U + r0 * k;
+    const int total = nr * k;
+    int row = 0, col = lane;  // of element lane; k > 64 keeps col < k
+    for (int e0 = 0; e0 < total; e0 += 64 * kNciAccBatch) {
+      float v[kNciAccBatch];
+#pragma unroll
+      for (int b = 0; b < kNciAccBatch; ++b) {
+        const int e = e0 + 64 * b + lane;
+        v[b] = e < total ? src[e] : 0.0f;
+      }
+#pragma unroll
+      for (int b = 0; b < kNciAccBatch; ++b) {
+        const int e = e0 + 64 * b + lane;
+        const int lr = __shfl(lab, row < 64 ? row : 63, 64);
+        if (e < total)
+          atomicAdd(reinterpret_cast<unsigned long long*>(&accl[lr * k + col]),
+                    static_cast<unsigned long long>(to_fixed(v[b], sft)));
+        col += 64;
+        if (col >= k) {
+          col -= k;
+          ++row;
+        }
+      }
+    }
   }
   __syncthreads();
-  for (int e = tid; e < k * k + k; e += 256) part[static_cast<int64_t>(e) * gridDim.x + blockIdx.x] = accl[e];
+  for (int e = tid; e < k * k + k; e += 1024) part[static_cast<int64_t>(e) * gridDim.x + blockIdx.x] = accl[e];
+}
+
+template <int LT>
+static void nci_score_mfma(const float* U, int64_t n, int k, const long long* sums, int32_t* labels,
+                          const DevStatus* st, hipStream_t s) {
+  constexpr int NL = 16 * LT;
+  constexpr size_t lds = static_cast<size_t>(NL) * NL * 8 + NL * 8;
+  const int per_cu = std::max<int>(1, static_cast<int>((160 * 1024) / lds));
+  const int64_t ntiles = (n + 15) / 16;
+  const int nb = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>((ntiles + 7) / 8, 256 * per_cu)));
+  hipLaunchKernelGGL((k_nci_score_mfma<LT>), dim3(nb), dim3(512), 0, s, U, n, k, sums, labels, st);
+  TPO_LAUNCH_CHECK();
 }
 
 static void nci_rounds_wide(const Plan& p, void* ws, hipStream_t s) {
@@ -553,18 +618,25 @@ static void nci_rounds_wide(const Plan& p, void* ws, hipStream_t s) {
   const int k = p.k;
   long long* part = bufp<long long>(p, ws, B_NCI_PART);
   long long* sums = bufp<long long>(p, ws, B_NCI_SUM);
-  const int nb = p.rowpass_blocks;
-  const int rpb = static_cast<int>((p.n + nb - 1) / nb);
+  const int64_t n = static_cast<int64_t>(p.n);
+  // one accumulation workgroup per CU at most, 64-row runs per wave
+  const int nb = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>({(n + 63) / 64, 256,
+                                                                           static_cast<int64_t>(p.rowpass_blocks)})));
+  const int64_t rpb = ((n + nb - 1) / nb + 63) / 64 * 64;
   const float* U = bufp<float>(p, ws, B_UPS);
   int32_t* labels = bufp<int32_t>(p, ws, B_LABELS);
   const int rounds = std::max(p.par.t_g, 1);
   for (int t = 1; t <= rounds; ++t) {
-    hipLaunchKernelGGL(k_nci_score_wide, dim3(nb), dim3(256), 0, s, U, static_cast<int64_t>(p.n), k,
-                       t == 1 ? nullptr : sums, labels, rpb, st);
-    TPO_LAUNCH_CHECK();
+    const long long* sm = t == 1 ? nullptr : sums;
+    switch ((k + 15) / 16) {
+      case 5: nci_score_mfma<5>(U, n, k, sm, labels, st, s); break;
+      case 6: nci_score_mfma<6>(U, n, k, sm, labels, st, s); break;
+      case 7: nci_score_mfma<7>(U, n, k, sm, labels, st, s); break;
+      case 8: nci_score_mfma<8>(U, n, k, sm, labels, st, s); break;
+      default: throw std::runtime_error("NCI: k beyond 128");
+    }
     if (t < p.par.t_g) {
-      hipLaunchKernelGGL(k_nci_accum_wide, dim3(nb), dim3(256), 0, s, U, static_cast<int64_t>(p.n), k, labels,
-                         part, rpb, st);
+      hipLaunchKernelGGL(k_nci_accum_wide, dim3(nb), dim3(1024), 0, s, U, n, k, labels, part, rpb, st);
       TPO_LAUNCH_CHECK();
       sum_parts_i64(part, nb, k * k + k, sums, s);
     }
