@@ -78,10 +78,10 @@ __device__ __forceinline__ bool wave_chol16(double* B, int ld, double* dinv) {
   bool ok = true;
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
-    const double d = __shfl(x[k >> 2], 16 * (k & 3) + k, 64);
-    if (!(d > 1e-290) || !isfinite(d)) {
+    double d = __shfl(x[k >> 2], 16 * (k & 3) + k, 64);
+    if (!(d > 1e-290) || !isfinite(d)) {  // uniform; the loop runs on (fully unrolled) with a harmless pivot
       ok = false;
-      break;
+      d = 1.0;
     }
     const double inv = rsqrt_refined(d);
     if (c == k) {
@@ -132,6 +132,110 @@ __device__ __forceinline__ void wave_inv16(const double* L, int ldl, const doubl
     for (int r = 0; r < 16; ++r) X[r * ldx + c] = x[r];
   }
   wave_sync();
+}
+
+// Lane 16 (l / 16) + K's copy of v in every lane l (DPP row broadcast: one
+// instruction for the 64-bit value).
+template <int K>
+__device__ __forceinline__ double row_bcast(double v) {
+  return __builtin_amdgcn_update_dpp(v, v, 0x150 + K, 0xF, 0xF, true);  // every lane written: no old value
+}
+
+__device__ __forceinline__ double row_bcast_k(double v, int k) {  // k: a constant after unrolling
+  switch (k) {
+    case 0: return row_bcast<0>(v);
+    case 1: return row_bcast<1>(v);
+    case 2: return row_bcast<2>(v);
+    case 3: return row_bcast<3>(v);
+    case 4: return row_bcast<4>(v);
+    case 5: return row_bcast<5>(v);
+    case 6: return row_bcast<6>(v);
+    case 7: return row_bcast<7>(v);
+    case 8: return row_bcast<8>(v);
+    case 9: return row_bcast<9>(v);
+    case 10: return row_bcast<10>(v);
+    case 11: return row_bcast<11>(v);
+    case 12: return row_bcast<12>(v);
+    case 13: return row_bcast<13>(v);
+    case 14: return row_bcast<14>(v);
+    default: return row_bcast<15>(v);
+  }
+}
+
+// One wave: L = chol(B) and X = L^{-1} for a 16 x 16 LDS tile whose lower
+// triangle holds the symmetric matrix.  On return the lower triangle of B
+// holds L, its strictly upper triangle holds X transposed (B[c][r] = X[r][c],
+// r > c), X (ldx) holds X with zeros above the diagonal, and dinv[k] =
+// 1 / L[k][k].  Lane l keeps column c = l % 16 of the symmetric trailing
+// matrix in registers (the four groups of 16 lanes hold the same, so a row
+// broadcast from lane k of each group reaches every lane).  Step k
+// broadcasts the pivot and column k of S, so every lane has column k of L;
+// lane c stores its own entry L[c][k] = S[k][c] / sqrt(S[k][k]) (by the
+// symmetry of the trailing matrix S) and then applies the rank-one update
+// to its whole column: the columns already finished are never read again,
+// so no lane needs a mask for it.  Column c of X solves L y = e_c and is
+// advanced in the same loop.  Returns false (wave-uniform) on a bad pivot.
+__device__ __forceinline__ bool wave_chol_inv16(double* B, int ld, double* dinv, double* X, int ldx) {
+  const int l = threadIdx.x & 63, c = l & 15;
+  double x[16], y[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    x[r] = r >= c ? B[r * ld + c] : B[c * ld + r];
+    y[r] = r == c ? 1.0 : 0.0;
+  }
+  wave_sync();  // every lane has read B before L is written into it
+  bool ok = true;
+  double d = row_bcast<0>(x[0]);
+  if (!(d > 1e-290) || !isfinite(d)) {  // uniform; the loop runs on (fully unrolled) with a harmless pivot
+    ok = false;
+    d = 1.0;
+  }
+  double inv = rsqrt_refined(d);
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    // with s_r = S[r][k] (lane k's column) and L[r][k] = s_r inv:
+    //   x[r] -= L[r][k] L[c][k] = s_r (inv L[c][k]),  y[r] -= L[r][k] y_k = s_r (inv y_k)
+    const double lck = x[k] * inv;  // L[c][k] for c >= k
+    if (l < 16 && c >= k) B[c * ld + k] = lck;
+    if (l == 0) dinv[k] = inv;
+    const double a = lck * inv;
+    const double yk = y[k] * inv;
+    const double b = yk * inv;
+    y[k] = yk;
+    double inv_next = 1.0;
+    if (k + 1 < 16) {
+      // the next pivot first, so that its square root overlaps the updates
+      const double s1 = row_bcast_k(x[k + 1], k);
+      x[k + 1] = fma(-s1, a, x[k + 1]);
+      y[k + 1] = fma(-s1, b, y[k + 1]);
+      double dn = row_bcast_k(x[k + 1], k + 1);
+      if (!(dn > 1e-290) || !isfinite(dn)) {
+        ok = false;
+        dn = 1.0;
+      }
+      inv_next = rsqrt_refined(dn);
+    }
+#pragma unroll
+    for (int r = k + 2; r < 16; ++r) {
+      const double sr = row_bcast_k(x[r], k);
+      x[r] = fma(-sr, a, x[r]);
+      y[r] = fma(-sr, b, y[r]);
+    }
+    inv = inv_next;
+    // keep each step's arithmetic in its step: left alone, the compiler
+    // defers it and holds every step's column of L live at once
+#pragma unroll
+    for (int r = 0; r < 16; ++r) __asm__ volatile("" : "+v"(x[r]), "+v"(y[r]));
+  }
+  if (ok && l < 16) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      if (r > c) B[c * ld + r] = y[r];
+      X[r * ldx + c] = y[r];
+    }
+  }
+  wave_sync();
+  return ok;
 }
 
 // Blocked Cholesky of the padded nb x nb tile matrix G (LDS, ld) with the
@@ -199,6 +303,89 @@ __device__ bool blk_chol_inv16(double* G, double* Li, int ld, int nb, double* sc
       v4d_t out = {0.0, 0.0, 0.0, 0.0};
       out = mma16(Li + 16 * I * ld + 16 * I, ld, false, T, 16, false, out, true);
       store16(Li + 16 * I * ld + 16 * J, ld, out);
+    }
+    __syncthreads();
+  }
+  return true;
+}
+
+// In-place variant: the lower tiles of G (LDS, ld) end as L^{-1}, so that
+// one n x n array serves for n up to 128.  Factorisation as above, with the
+// inverse of each diagonal tile kept in scratch tile 0 for the panel and
+// transposed above the diagonal for later; then, for the block
+// columns J from the last to the first, with the trailing block already
+// inverted in place,
+//   Li_IJ = -(sum_{J < K <= I} Li_IK L_KJ) Li_JJ   (I > J),
+// the sums formed before any tile of column J is overwritten.
+// scratch: nb tiles of 16 x 16 doubles; dinv: 16 nb doubles.
+// Returns false uniformly when a pivot fails (G is then left part-factored).
+__device__ __forceinline__ bool blk_chol_inv16_inplace(double* G, int ld, int nb, double* scratch, double* dinv, int* flag) {
+  const int w = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  double* S0 = scratch;
+  if (threadIdx.x == 0) *flag = 0;
+  __syncthreads();
+  for (int J = 0; J < nb; ++J) {
+    double* GJJ = G + 16 * J * ld + 16 * J;
+    if (w == 0 && !wave_chol_inv16(GJJ, ld, dinv + 16 * J, S0, 16) && (threadIdx.x & 63) == 0) *flag = 1;
+    __syncthreads();
+    if (*flag) return false;
+    for (int I = J + 1 + w; I < nb; I += nw) {
+      double* GIJ = G + 16 * I * ld + 16 * J;
+      v4d_t acc = {0.0, 0.0, 0.0, 0.0};
+      acc = mma16(GIJ, ld, false, S0, 16, true, acc);
+      store16(GIJ, ld, acc);
+    }
+    __syncthreads();
+    const int m = nb - 1 - J;
+    for (int p = w; p < m * (m + 1) / 2; p += nw) {
+      int I = 0, rem = p;
+      while (rem > I) {
+        rem -= I + 1;
+        ++I;
+      }
+      const int K = rem;
+      double* GIK = G + 16 * (J + 1 + I) * ld + 16 * (J + 1 + K);
+      const double* LIJ = G + 16 * (J + 1 + I) * ld + 16 * J;
+      const double* LKJ = G + 16 * (J + 1 + K) * ld + 16 * J;
+      v4d_t acc = load16(GIK, ld);
+      acc = mma16(LIJ, ld, false, LKJ, ld, true, acc, true);
+      store16(GIK, ld, acc);
+    }
+    __syncthreads();
+  }
+  for (int J = nb - 1; J >= 0; --J) {
+    double* GJJ = G + 16 * J * ld + 16 * J;
+    if (w == 0) {  // Li_JJ from its transposed copy above the diagonal
+      const int l = threadIdx.x & 63;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 4 * v + (l >> 4), c = l & 15;
+        S0[r * 16 + c] = r > c ? GJJ[c * ld + r] : (r == c ? dinv[16 * J + r] : 0.0);
+      }
+    }
+    const int I = J + 1 + w;  // nb - 1 - J <= 7 < nw tiles below the diagonal
+    v4d_t acc = {0.0, 0.0, 0.0, 0.0};
+    if (I < nb) {
+      for (int K = J + 1; K <= I; ++K)
+        acc = mma16(G + 16 * I * ld + 16 * K, ld, false, G + 16 * K * ld + 16 * J, ld, false, acc);
+    }
+    __syncthreads();
+    if (I < nb) {
+      double* T = scratch + 256 * (1 + w);
+      store16(T, 16, acc);
+      wave_sync();
+      v4d_t out = {0.0, 0.0, 0.0, 0.0};
+      out = mma16(T, 16, false, S0, 16, false, out, true);
+      store16(G + 16 * I * ld + 16 * J, ld, out);
+    }
+    if (w == nw - 1) {
+      const int l = threadIdx.x & 63;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 4 * v + (l >> 4), c = l & 15;
+        GJJ[r * ld + c] = S0[r * 16 + c];
+      }
     }
     __syncthreads();
   }

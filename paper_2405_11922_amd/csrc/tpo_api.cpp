@@ -169,12 +169,13 @@ void build_layout(Plan& p) {
     const bool red_si = p.reduce && p.lr <= kLdsMaxN;
     const bool emb_si = p.kp <= kLdsMaxN;
     const size_t mp = std::max(red_si ? du * lr : 0, emb_si ? twod * kp : 0);
-    const size_t li = std::max(red_si ? lr * lr : 0, emb_si ? kp * kp : 0);
+    const size_t li = std::max(red_si ? subspace_gsum_doubles(static_cast<int>(lr)) : 0,
+                               emb_si ? subspace_gsum_doubles(static_cast<int>(kp)) : 0);
     const size_t pt = std::max(red_si ? subspace_part_doubles(static_cast<int>(du), static_cast<int>(lr)) : 0,
                                emb_si ? subspace_part_doubles(static_cast<int>(twod), static_cast<int>(kp)) : 0);
     add(B_SI_M, 8 * mp);
     add(B_SI_P, 8 * mp);
-    add(B_SI_LI, 8 * li);
+    add(B_SI_GRAM, 8 * li);
     add(B_SI_PART, 8 * pt);
   }
   L.total = align256(cur);

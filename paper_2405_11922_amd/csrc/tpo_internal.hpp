@@ -69,7 +69,7 @@ enum Buf {
   // nci / objective
   B_LABELS, B_NCI_PART, B_NCI_SUM, B_OBJ_PART, B_OBJ_SUM,
   // subspace iteration (reduction and embedding)
-  B_SI_M, B_SI_P, B_SI_LI, B_SI_PART,
+  B_SI_M, B_SI_P, B_SI_GRAM, B_SI_PART,
   B_REDTMP,
   B_COUNT
 };
@@ -130,12 +130,14 @@ void launch_embed(const Plan& p, void* ws, hipStream_t s);
 constexpr int kLdsMaxN = 80;
 void cholqr_lds(double* A, int m, int n, int lda, int32_t* err_bits, hipStream_t s);
 // n_orth Cholesky-QR steps of subspace iteration on the symmetric N x N A from
-// the N x l start omega (l <= kLdsMaxN); m_out = the last basis (omega when
-// n_orth = 0), p_out = A m_out.  pa, pb: N x l scratch; li: l x l scratch;
-// part: subspace_part_doubles(N, l) scratch.
+// the N x l start omega (l <= 128); m_out = the last basis (omega when
+// n_orth = 0), p_out = A m_out.  pa, pb: N x l scratch; gram:
+// subspace_gsum_doubles(l) scratch; part: subspace_part_doubles(N, l) scratch.
+// One cooperative launch.
 void subspace_iterate(const double* A, int N, const double* omega, int l, int n_orth, double* pa, double* pb,
-                      double* li, double* part, double* m_out, double* p_out, int32_t* err_bits, hipStream_t s);
+                      double* gram, double* part, double* m_out, double* p_out, int32_t* err_bits, hipStream_t s);
 size_t subspace_part_doubles(int N, int l);
+size_t subspace_gsum_doubles(int l);
 void rr_reduce_lds(const double* M, const double* P, int du, int l, int d, int dp, const double* colsum_x,
                    int64_t n, double* evals, double* psi, float* psi32, hipStream_t s);
 void embed_final_lds(double* M, double* P, int twod, int kp, int k, const double* colsum_r, int64_t n, double* S,
