@@ -501,7 +501,7 @@ void launch_reduce(const Plan& p, void* ws, const float* x, int64_t ldx, hipStre
     double* m = bufp<double>(p, ws, B_SI_M);
     double* pm = bufp<double>(p, ws, B_SI_P);
     subspace_iterate(C, p.du, bufp<double>(p, ws, B_OMR), p.lr, p.par.q + 1, ma, mb, bufp<double>(p, ws, B_SI_GRAM),
-                     bufp<double>(p, ws, B_SI_PART), m, pm, &st->err_bits, s);
+                     bufp<double>(p, ws, B_SI_PART), bufp<unsigned>(p, ws, B_SI_BAR), m, pm, &st->err_bits, s);
     rr_reduce_lds(m, pm, p.du, p.lr, p.d, p.dp, colsum, static_cast<int64_t>(p.n), bufp<double>(p, ws, B_EVAL),
                   bufp<double>(p, ws, B_PSI_D), bufp<float>(p, ws, B_PSI_D32), s);
   } else {
@@ -792,8 +792,8 @@ void launch_embed(const Plan& p, void* ws, hipStream_t s) {
     double* m = bufp<double>(p, ws, B_SI_M);
     double* pm = bufp<double>(p, ws, B_SI_P);
     subspace_iterate(K, p.twod, bufp<double>(p, ws, B_OMEGA), p.kp, p.par.q, bufp<double>(p, ws, B_M_A),
-                     bufp<double>(p, ws, B_M_B), bufp<double>(p, ws, B_SI_GRAM), bufp<double>(p, ws, B_SI_PART), m, pm,
-                     &st->err_bits, s);
+                     bufp<double>(p, ws, B_M_B), bufp<double>(p, ws, B_SI_GRAM), bufp<double>(p, ws, B_SI_PART),
+                     bufp<unsigned>(p, ws, B_SI_BAR), m, pm, &st->err_bits, s);
     embed_final_lds(m, pm, p.twod, p.kp, p.k, bufp<double>(p, ws, B_RCOLSUM), static_cast<int64_t>(p.n),
                     bufp<double>(p, ws, B_EEVAL), bufp<float>(p, ws, B_S32), bufp<double>(p, ws, B_SIGMA),
                     bufp<double>(p, ws, B_PSI), bufp<double>(p, ws, B_H), bufp<float>(p, ws, B_H32), &st->err_bits,

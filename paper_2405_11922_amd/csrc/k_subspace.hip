@@ -7,7 +7,7 @@
 // With P_i = A Q_{i-1} and L_i = chol(P_i^T P_i), Q_i = P_i L_i^{-T}.  The
 // product of the next step is re-associated so that Q_i is never formed:
 //   P_{i+1} = A Q_i = (A P_i) L_i^{-T}.
-// The whole iteration is one cooperative kernel.  Each workgroup owns blocks
+// The whole iteration is one kernel with grid barriers.  Each workgroup owns blocks
 // of 16 rows of P (one wave per 16-column tile, FP64 MFMA) and adds their
 // contribution to the Gram P^T P into its own partial; after a grid barrier
 // the workgroups add the partials entry by entry in a fixed order; after a
@@ -15,21 +15,55 @@
 // LDS (blocked Cholesky with L^{-1} formed in place), so that the next
 // product has L^{-1} at hand without another launch.  All workgroups factor
 // the same sums in the same order and so hold the same L^{-1}.
-#include <hip/hip_cooperative_groups.h>
-
 #include "blk_chol16.hpp"
 #include "dev_common.hpp"
 #include "tpo_internal.hpp"
 
 namespace tpo {
 
-namespace cg = cooperative_groups;
-
 constexpr int kSiThreads = 512;  // 8 waves: one per 16-column tile, and one per tile below the diagonal (nb <= 8)
 constexpr int kSiBatch = 16;      // loads in flight per lane before they are used (A from global memory)
 constexpr int kSiWideBatch = 32;  // the same with A's row tile in LDS
 constexpr int kSiMaxGrid = 64;
 constexpr size_t kLdsBytes = 160 * 1024;
+
+// Grid-wide barrier.  The grid is small (at most kSiMaxGrid workgroups, one
+// per CU at most), so every workgroup is resident once the CUs it waits for
+// are free; the launch does not depend on any later work.  bar[0] counts
+// arrivals, bar[1] is the generation: the last workgroup to arrive resets
+// the count and advances the generation, the others wait for it to change.
+// Each workgroup's writes are released before it arrives and the others'
+// acquired after it leaves.  A wait longer than kSiBarrierTicks sets bit 64
+// of err_bits and goes on, so that the kernel always ends.
+constexpr uint64_t kSiBarrierTicks = 200000000;  // 2 s of the 100 MHz constant clock
+
+__device__ __forceinline__ void grid_barrier(unsigned* bar, int32_t* err_bits) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();
+    const unsigned arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (arrived == gridDim.x - 1) {
+      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      const uint64_t t0 = wall_clock64();
+      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        __builtin_amdgcn_s_sleep(1);
+        if (wall_clock64() - t0 > kSiBarrierTicks) {
+          atomicOr(err_bits, 64);
+          break;
+        }
+      }
+    }
+    __threadfence();
+  }
+  __syncthreads();
+}
+
+__global__ void k_si_bar_reset(unsigned* bar) {
+  if (threadIdx.x < 2) bar[threadIdx.x] = 0u;
+}
 
 // One product's K loop for this lane's 16 x 16 tile of Y = A[rows] P with
 // P^T (l x N) in global memory: lane (i16, kq) takes the contiguous k range
@@ -207,7 +241,8 @@ template <int NB>
 __global__ void __launch_bounds__(kSiThreads)
 k_si_fused(const double* __restrict__ A, int N, const double* __restrict__ omega, int l, int n_orth,
            double* __restrict__ pa, double* __restrict__ pb, double* __restrict__ part, double* __restrict__ gsum,
-           double* __restrict__ m_out, double* __restrict__ p_out, int32_t* __restrict__ err_bits, int a_lds) {
+           unsigned* __restrict__ bar, double* __restrict__ m_out, double* __restrict__ p_out,
+           int32_t* __restrict__ err_bits, int a_lds) {
   constexpr int NP = 16 * NB;
   constexpr int LD = NP + 1;
   __shared__ double G[NP * LD];  // Gram, factor and inverse (lower tiles)
@@ -215,7 +250,6 @@ k_si_fused(const double* __restrict__ A, int N, const double* __restrict__ omega
   __shared__ double dinv[NP];
   __shared__ int flag;
   extern __shared__ double As_dyn[];  // a_lds: rows 16 b .. 16 b + 15 of A (stride N + 1), b = blockIdx.x
-  cg::grid_group grid = cg::this_grid();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int i16 = lane & 15, kq = lane >> 4;
   const int nrt = (N + 15) / 16;
@@ -237,7 +271,7 @@ k_si_fused(const double* __restrict__ A, int N, const double* __restrict__ omega
     const int r = e / l, c = e - (e / l) * l;
     pb[static_cast<int64_t>(c) * N + r] = omega[e];
   }
-  grid.sync();
+  grid_barrier(bar, err_bits);
   prev = pb;
   for (int it = 0; it <= n_orth; ++it) {
     const bool last = it == n_orth;
@@ -246,7 +280,7 @@ k_si_fused(const double* __restrict__ A, int N, const double* __restrict__ omega
       si_rows<NB>(A, As, N, prev, l, have_li ? G : nullptr, LD, last ? p_out : cur, last, last ? m_out : nullptr,
                   Ys, rt, last ? nullptr : mypart, rt == static_cast<int>(blockIdx.x));
     if (last) break;
-    grid.sync();
+    grid_barrier(bar, err_bits);
     // Gram = sum of the partials, entry by entry in block order
     const int nparts = gridDim.x;
     for (int e = blockIdx.x * kSiThreads + threadIdx.x; e < NP * NP; e += gridDim.x * kSiThreads) {
@@ -263,7 +297,7 @@ k_si_fused(const double* __restrict__ A, int N, const double* __restrict__ omega
       }
       gsum[e] = s;
     }
-    grid.sync();
+    grid_barrier(bar, err_bits);
     // every workgroup: L = chol(Gram), L^{-1} in place; identity on the
     // padding beyond l, and after a breakdown (keeps later values finite)
 #pragma unroll 4
@@ -290,32 +324,36 @@ k_si_fused(const double* __restrict__ A, int N, const double* __restrict__ omega
 
 template <int NB>
 static void si_run(const double* A, int N, const double* omega, int l, int n_orth, double* pa, double* pb,
-                   double* gsum, double* part, double* m_out, double* p_out, int32_t* err_bits, hipStream_t s) {
+                   double* gsum, double* part, unsigned* bar, double* m_out, double* p_out, int32_t* err_bits,
+                   hipStream_t s) {
   const int nrt = (N + 15) / 16;
   const int grid = std::min(nrt, kSiMaxGrid);
   constexpr size_t kStatic = (16 * NB * (16 * NB + 1) + 16 * (16 * NB + 1) + 16 * NB) * sizeof(double) + 64;
   const size_t a_bytes = static_cast<size_t>(16) * (N + 1) * sizeof(double);
-  int a_lds = nrt <= grid && kStatic + a_bytes <= kLdsBytes ? 1 : 0;
+  const int a_lds = nrt <= grid && kStatic + a_bytes <= kLdsBytes ? 1 : 0;
   const size_t dyn = a_lds ? a_bytes : 0;
   if (dyn > 0)
     TPO_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_si_fused<NB>),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(dyn)));
-  void* args[] = {&A, &N, &omega, &l, &n_orth, &pa, &pb, &part, &gsum, &m_out, &p_out, &err_bits, &a_lds};
-  TPO_HIP_CHECK(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_si_fused<NB>), dim3(grid),
-                                           dim3(kSiThreads), args, static_cast<unsigned>(dyn), s));
+  hipLaunchKernelGGL(k_si_bar_reset, dim3(1), dim3(64), 0, s, bar);
+  TPO_LAUNCH_CHECK();
+  hipLaunchKernelGGL((k_si_fused<NB>), dim3(grid), dim3(kSiThreads), dyn, s, A, N, omega, l, n_orth, pa, pb, part,
+                     gsum, bar, m_out, p_out, err_bits, a_lds);
+  TPO_LAUNCH_CHECK();
 }
 
 void subspace_iterate(const double* A, int N, const double* omega, int l, int n_orth, double* pa, double* pb,
-                      double* gsum, double* part, double* m_out, double* p_out, int32_t* err_bits, hipStream_t s) {
+                      double* gsum, double* part, unsigned* bar, double* m_out, double* p_out, int32_t* err_bits,
+                      hipStream_t s) {
   switch ((l + 15) / 16) {
-    case 1: si_run<1>(A, N, omega, l, n_orth, pa, pb, gsum, part, m_out, p_out, err_bits, s); break;
-    case 2: si_run<2>(A, N, omega, l, n_orth, pa, pb, gsum, part, m_out, p_out, err_bits, s); break;
-    case 3: si_run<3>(A, N, omega, l, n_orth, pa, pb, gsum, part, m_out, p_out, err_bits, s); break;
-    case 4: si_run<4>(A, N, omega, l, n_orth, pa, pb, gsum, part, m_out, p_out, err_bits, s); break;
-    case 5: si_run<5>(A, N, omega, l, n_orth, pa, pb, gsum, part, m_out, p_out, err_bits, s); break;
-    case 6: si_run<6>(A, N, omega, l, n_orth, pa, pb, gsum, part, m_out, p_out, err_bits, s); break;
-    case 7: si_run<7>(A, N, omega, l, n_orth, pa, pb, gsum, part, m_out, p_out, err_bits, s); break;
-    case 8: si_run<8>(A, N, omega, l, n_orth, pa, pb, gsum, part, m_out, p_out, err_bits, s); break;
+    case 1: si_run<1>(A, N, omega, l, n_orth, pa, pb, gsum, part, bar, m_out, p_out, err_bits, s); break;
+    case 2: si_run<2>(A, N, omega, l, n_orth, pa, pb, gsum, part, bar, m_out, p_out, err_bits, s); break;
+    case 3: si_run<3>(A, N, omega, l, n_orth, pa, pb, gsum, part, bar, m_out, p_out, err_bits, s); break;
+    case 4: si_run<4>(A, N, omega, l, n_orth, pa, pb, gsum, part, bar, m_out, p_out, err_bits, s); break;
+    case 5: si_run<5>(A, N, omega, l, n_orth, pa, pb, gsum, part, bar, m_out, p_out, err_bits, s); break;
+    case 6: si_run<6>(A, N, omega, l, n_orth, pa, pb, gsum, part, bar, m_out, p_out, err_bits, s); break;
+    case 7: si_run<7>(A, N, omega, l, n_orth, pa, pb, gsum, part, bar, m_out, p_out, err_bits, s); break;
+    case 8: si_run<8>(A, N, omega, l, n_orth, pa, pb, gsum, part, bar, m_out, p_out, err_bits, s); break;
     default: throw std::runtime_error("subspace_iterate: width beyond 128");
   }
 }

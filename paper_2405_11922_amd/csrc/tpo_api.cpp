@@ -177,6 +177,7 @@ void build_layout(Plan& p) {
     add(B_SI_P, 8 * mp);
     add(B_SI_GRAM, 8 * li);
     add(B_SI_PART, 8 * pt);
+    add(B_SI_BAR, 8);
   }
   L.total = align256(cur);
 }
@@ -197,6 +198,7 @@ tpo_status map_bits(tpo_plan* p, int32_t bits) {
   if (bits & 8) return fail(p, TPO_ENUMERIC, "R'[i].r <= 0 or not finite (Eq. Ri)");
   if (bits & 16) return fail(p, TPO_ENUMERIC, "Cholesky breakdown in an orthonormalisation");
   if (bits & 32) return fail(p, TPO_ENUMERIC, "non-finite value in the ONMF updates");
+  if (bits & 64) return fail(p, TPO_EDEVICE, "grid barrier of the subspace iteration timed out");
   return TPO_OK;
 }
 

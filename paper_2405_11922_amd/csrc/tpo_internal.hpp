@@ -69,7 +69,7 @@ enum Buf {
   // nci / objective
   B_LABELS, B_NCI_PART, B_NCI_SUM, B_OBJ_PART, B_OBJ_SUM,
   // subspace iteration (reduction and embedding)
-  B_SI_M, B_SI_P, B_SI_GRAM, B_SI_PART,
+  B_SI_M, B_SI_P, B_SI_GRAM, B_SI_PART, B_SI_BAR,
   B_REDTMP,
   B_COUNT
 };
@@ -133,9 +133,10 @@ void cholqr_lds(double* A, int m, int n, int lda, int32_t* err_bits, hipStream_t
 // the N x l start omega (l <= 128); m_out = the last basis (omega when
 // n_orth = 0), p_out = A m_out.  pa, pb: N x l scratch; gram:
 // subspace_gsum_doubles(l) scratch; part: subspace_part_doubles(N, l) scratch.
-// One cooperative launch.
+// bar: two words of scratch for the grid barrier.  One launch.
 void subspace_iterate(const double* A, int N, const double* omega, int l, int n_orth, double* pa, double* pb,
-                      double* gram, double* part, double* m_out, double* p_out, int32_t* err_bits, hipStream_t s);
+                      double* gram, double* part, unsigned* bar, double* m_out, double* p_out, int32_t* err_bits,
+                      hipStream_t s);
 size_t subspace_part_doubles(int N, int l);
 size_t subspace_gsum_doubles(int l);
 void rr_reduce_lds(const double* M, const double* P, int du, int l, int d, int dp, const double* colsum_x,
