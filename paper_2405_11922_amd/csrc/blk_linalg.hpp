@@ -114,6 +114,13 @@ __device__ inline double blk_sum(double v, double* sh) {
 // Off-diagonal entries below this multiple of sqrt(|a_pp a_qq|) are treated
 // as converged (relative accuracy at the level of FP64 rounding).
 constexpr double kJacobiTol = 1e-16;
+constexpr int kJacobiMaxN = 160;  // largest n (steps per sweep: n - 1 or n)
+
+// Coupled above rounding level: |a_pq| > tol sqrt(|a_pp a_qq|), tested on
+// squares (no square root), and |a_pq| > 1e-140.
+__device__ __forceinline__ bool jacobi_coupled(double apq, double app, double aqq) {
+  return apq * apq > (kJacobiTol * kJacobiTol) * fabs(app * aqq) && fabs(apq) > 1e-140;
+}
 
 // 1/x and 1/sqrt(x) for positive normal x: the hardware estimates refined by
 // two Newton steps each (quadratic convergence: a few ulp from exact).
@@ -131,53 +138,100 @@ __device__ __forceinline__ double rsq_refined(double x) {
   return y;
 }
 
+// Pair i of step `step` of the round-robin order over np (even) indices:
+// (step, np - 1) for i = 0, else ((step + i) mod m, (step - i) mod m) with
+// m = np - 1; returned with p < q.
+__device__ __forceinline__ void jacobi_pair(int step, int i, int np, int& p, int& q) {
+  const int m = np - 1;
+  if (i == 0) {
+    p = step;
+    q = m;
+  } else {
+    p = step + i;
+    if (p >= m) p -= m;
+    q = step - i;
+    if (q < 0) q += m;
+  }
+  if (p > q) {
+    const int t = p;
+    p = q;
+    q = t;
+  }
+}
+
 // Cyclic Jacobi eigensolver for a symmetric n x n matrix A (in place; on exit
 // the diagonal holds the eigenvalues) with eigenvectors in the columns of V.
 // Parallel (round-robin) ordering: n/2 disjoint rotations per step.  A step
-// is two phases: thread i < n/2 forms the rotation of pair i; then wave w
-// applies A <- J^T A J to the 2 x 2 blocks (pair i rows, pair j columns) of
-// its pairs i = w, w + waves, ... with lane j taking block (i, j), and
-// V <- V J to the rows (one per lane) of the same pairs.  The coupling of a
-// rotated pair is set to zero.  Stops after a sweep that rotates nothing (or
-// after max_sweeps).  Returns the number of sweeps taken.
-// sh: scratch of 3 * ((n + 1) / 2) + 1 doubles; red: unused.
+// is two phases: thread i < n/2 forms the rotation of pair i; then the
+// threads share out the 2 x 2 blocks (pair i rows, pair j columns) of
+// A <- J^T A J and the (pair, row) items of V <- V J evenly.  The coupling of a
+// rotated pair is set to zero.  Each sweep starts by marking the steps that
+// hold a pair coupled above the threshold (pair (p, q) belongs to step p when
+// q is the fixed index np - 1, else to the step s with 2 s = p + q modulo
+// np - 1) and runs only those: a pair that becomes coupled again later in
+// the sweep waits for the next one.  Stops when no step is marked (or after
+// max_sweeps).  Returns the number of sweeps taken.
+// sh: scratch of 3 * ((n + 1) / 2) doubles (16-byte aligned); red: unused.
+// Each thread takes at most kA blocks and kV rows of V: (n / 2)^2 <= kA
+// blockDim.x and n^2 / 2 <= kV blockDim.x (2 and 4: n <= 80 with 1024
+// threads; 7 and 13: n <= 160).
 
+template <int kA = 2, int kV = 4>
 __device__ inline int blk_jacobi(double* A, int lda, double* V, int ldv, int n, double* sh, double* red,
                                  int max_sweeps) {
   (void)red;
   const int np = n + (n & 1);
   const int npairs = np / 2;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  double* cs = sh;               // c
-  double* sn = sh + npairs;      // s
-  int* pp = reinterpret_cast<int*>(sh + 2 * npairs);
-  int* qq = pp + npairs;
-  int* rotated = qq + npairs;    // set when a sweep applied any rotation
+  const int m = np - 1;          // steps per sweep (odd)
+  const int half = (m + 1) / 2;  // 2 half = 1 modulo m
+  double2* rot = reinterpret_cast<double2*>(sh);        // (c, s) of pair i
+  int2* pq = reinterpret_cast<int2*>(sh + 2 * npairs);  // (p, q) of pair i; q = -1 off the matrix
+  __shared__ int active[kJacobiMaxN];
+  __shared__ int any;
   for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
     const int r = idx / n, c = idx % n;
     V[r * ldv + c] = (r == c) ? 1.0 : 0.0;
   }
+  // this thread's items, fixed for the whole run: blocks (i, j) of J^T A J
+  // and (pair i, row r) items of V J
+  int bi[kA], bj[kA], vi[kV], vr[kV];
+#pragma unroll
+  for (int k = 0; k < kA; ++k) {
+    const int e = threadIdx.x + k * blockDim.x;
+    bi[k] = e < npairs * npairs ? e / npairs : -1;
+    bj[k] = e < npairs * npairs ? e - (e / npairs) * npairs : 0;
+  }
+#pragma unroll
+  for (int k = 0; k < kV; ++k) {
+    const int e = threadIdx.x + k * blockDim.x;
+    vi[k] = e < npairs * n ? e / n : -1;
+    vr[k] = e < npairs * n ? e - (e / n) * n : 0;
+  }
   int sweep = 0;
   for (; sweep < max_sweeps; ++sweep) {
-    if (threadIdx.x == 0) *rotated = 0;
+    if (threadIdx.x == 0) any = 0;
+    for (int st = threadIdx.x; st < m; st += blockDim.x) active[st] = 0;
     __syncthreads();
-    for (int step = 0; step < np - 1; ++step) {
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+      const int p = e / n, q = e - (e / n) * n;
+      if (p < q && jacobi_coupled(A[p * lda + q], A[p * lda + p], A[q * lda + q])) {
+        active[q == m ? p : ((p + q) * half) % m] = 1;
+        any = 1;
+      }
+    }
+    __syncthreads();
+    if (!any) break;
+    for (int step = 0; step < m; ++step) {
+      if (!active[step]) continue;  // uniform
       for (int i = threadIdx.x; i < npairs; i += blockDim.x) {
         int p, q;
-        if (i == 0) {
-          p = step;
-          q = np - 1;
-        } else {
-          p = (step + i) % (np - 1);
-          q = (step - i + (np - 1)) % (np - 1);
-        }
-        if (p > q) { const int t = p; p = q; q = t; }
+        jacobi_pair(step, i, np, p, q);
         double c = 1.0, s = 0.0;
         if (q < n) {
           const double apq = A[p * lda + q];
           const double app = A[p * lda + p], aqq = A[q * lda + q];
           // rotate only while the pair is coupled above rounding level
-          if (fabs(apq) > kJacobiTol * sqrt(fabs(app * aqq)) && fabs(apq) > 1e-140) {
+          if (jacobi_coupled(apq, app, aqq)) {
             // t = tan of the angle that annihilates a_pq: with a = a_qq - a_pp
             // and b = 2 a_pq, t = sign(a) b / (|a| + sqrt(a^2 + b^2))
             const double da = aqq - app, db = 2.0 * apq;
@@ -186,82 +240,111 @@ __device__ inline int blk_jacobi(double* A, int lda, double* V, int ldv, int n, 
             const double t = (da >= 0.0 ? db : -db) * rcp_refined(fabs(da) + root);
             c = rsq_refined(fma(t, t, 1.0));
             s = t * c;
-            if (s != 0.0) *rotated = 1;
           }
         }
-        cs[i] = c;
-        sn[i] = s;
-        pp[i] = p;
-        qq[i] = q < n ? q : -1;
+        rot[i] = make_double2(c, s);
+        pq[i] = make_int2(p, q < n ? q : -1);
       }
       __syncthreads();
-      for (int i = w; i < npairs; i += nw) {
-        const double si = sn[i];
-        const double ci = cs[i];
-        const int pi = pp[i], qi = qq[i];
-        // A <- J^T A J on blocks (i, j): rows of pair i by J_i^T, columns of pair j by J_j
-        for (int j = lane; j < npairs; j += 64) {
-          const double sj = sn[j], cj = cs[j];
-          const int pj = pp[j], qj = qq[j];
-          if (si == 0.0 && sj == 0.0) continue;
-          const double a = A[pi * lda + pj];
-          const double b = qj >= 0 ? A[pi * lda + qj] : 0.0;
-          const double c = qi >= 0 ? A[qi * lda + pj] : 0.0;
-          const double d = (qi >= 0 && qj >= 0) ? A[qi * lda + qj] : 0.0;
+      // the items of a step touch disjoint entries, so every load is issued
+      // before any store (the compiler cannot prove that on its own)
+      double2 ra[kA], rb[kA], rv[kV];
+      int2 xa[kA], xb[kA], xv[kV];
+      double va[kA][4], vv[kV][2];
+#pragma unroll
+      for (int k = 0; k < kA; ++k) {
+        ra[k] = rb[k] = make_double2(1.0, 0.0);
+        xa[k] = xb[k] = make_int2(-1, -1);
+        if (bi[k] >= 0) {
+          ra[k] = rot[bi[k]];
+          xa[k] = pq[bi[k]];
+          rb[k] = rot[bj[k]];
+          xb[k] = pq[bj[k]];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kV; ++k) {
+        rv[k] = make_double2(1.0, 0.0);
+        xv[k] = make_int2(-1, -1);
+        if (vi[k] >= 0) {
+          rv[k] = rot[vi[k]];
+          xv[k] = pq[vi[k]];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kA; ++k) {
+        va[k][0] = va[k][1] = va[k][2] = va[k][3] = 0.0;
+        const int p_i = xa[k].x, q_i = xa[k].y, p_j = xb[k].x, q_j = xb[k].y;
+        if (p_i >= 0 && (ra[k].y != 0.0 || rb[k].y != 0.0)) {
+          va[k][0] = A[p_i * lda + p_j];
+          if (q_j >= 0) va[k][1] = A[p_i * lda + q_j];
+          if (q_i >= 0) va[k][2] = A[q_i * lda + p_j];
+          if (q_i >= 0 && q_j >= 0) va[k][3] = A[q_i * lda + q_j];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kV; ++k) {
+        vv[k][0] = vv[k][1] = 0.0;
+        if (xv[k].x >= 0 && rv[k].y != 0.0) {
+          vv[k][0] = V[vr[k] * ldv + xv[k].x];
+          vv[k][1] = V[vr[k] * ldv + xv[k].y];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kA; ++k) {
+        const int p_i = xa[k].x, q_i = xa[k].y, p_j = xb[k].x, q_j = xb[k].y;
+        const double ci = ra[k].x, si = ra[k].y, cj = rb[k].x, sj = rb[k].y;
+        if (p_i >= 0 && (si != 0.0 || sj != 0.0)) {
+          const double a = va[k][0], b = va[k][1], c = va[k][2], d = va[k][3];
           const double a1 = ci * a - si * c, b1 = ci * b - si * d;
           const double c1 = si * a + ci * c, d1 = si * b + ci * d;
           const double a2 = cj * a1 - sj * b1;
           double b2 = sj * a1 + cj * b1;
           double c2 = cj * c1 - sj * d1;
           const double d2 = sj * c1 + cj * d1;
-          if (i == j && si != 0.0) {  // the rotated pair's own coupling is annihilated
+          if (bi[k] == bj[k] && si != 0.0) {  // the rotated pair's own coupling is annihilated
             b2 = 0.0;
             c2 = 0.0;
           }
-          A[pi * lda + pj] = a2;
-          if (qj >= 0) A[pi * lda + qj] = b2;
-          if (qi >= 0) A[qi * lda + pj] = c2;
-          if (qi >= 0 && qj >= 0) A[qi * lda + qj] = d2;
+          A[p_i * lda + p_j] = a2;
+          if (q_j >= 0) A[p_i * lda + q_j] = b2;
+          if (q_i >= 0) A[q_i * lda + p_j] = c2;
+          if (q_i >= 0 && q_j >= 0) A[q_i * lda + q_j] = d2;
         }
-        // V <- V J_i on this lane's rows
-        if (si != 0.0) {
-          for (int r = lane; r < n; r += 64) {
-            const double vp = V[r * ldv + pi], vq = V[r * ldv + qi];
-            V[r * ldv + pi] = ci * vp - si * vq;
-            V[r * ldv + qi] = si * vp + ci * vq;
-          }
+      }
+#pragma unroll
+      for (int k = 0; k < kV; ++k) {
+        if (xv[k].x >= 0 && rv[k].y != 0.0) {
+          const double c = rv[k].x, s = rv[k].y, vp = vv[k][0], vq = vv[k][1];
+          V[vr[k] * ldv + xv[k].x] = c * vp - s * vq;
+          V[vr[k] * ldv + xv[k].y] = s * vp + c * vq;
         }
       }
       __syncthreads();
     }
-    const int any = *rotated;
-    __syncthreads();
-    if (!any) break;
   }
   __syncthreads();
   return sweep;
 }
 
+
+
 // Order eigenpairs by decreasing eigenvalue (ties keep the lower index):
 // evals[i] <- sorted diagonal of A, perm[i] <- source column.
 __device__ inline void blk_sort_desc(const double* A, int lda, int n, double* evals, int* perm) {
-  if (threadIdx.x == 0) {
-    for (int i = 0; i < n; ++i) {
-      evals[i] = A[i * lda + i];
-      perm[i] = i;
+  // rank sort: element i goes after every larger value and after equal
+  // values of lower index (a NaN counts as -inf, so the ranks stay a permutation)
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double v = A[i * lda + i];
+    const double key = isnan(v) ? -INFINITY : v;
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+      double u = A[j * lda + j];
+      u = isnan(u) ? -INFINITY : u;
+      rank += (u > key || (u == key && j < i)) ? 1 : 0;
     }
-    for (int i = 1; i < n; ++i) {  // stable insertion sort, descending
-      const double v = evals[i];
-      const int pi = perm[i];
-      int j = i - 1;
-      while (j >= 0 && evals[j] < v) {
-        evals[j + 1] = evals[j];
-        perm[j + 1] = perm[j];
-        --j;
-      }
-      evals[j + 1] = v;
-      perm[j + 1] = pi;
-    }
+    evals[rank] = v;
+    perm[rank] = i;
   }
   __syncthreads();
 }

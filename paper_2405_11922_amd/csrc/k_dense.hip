@@ -283,7 +283,7 @@ k_reduce_rr(const double* __restrict__ M, const double* __restrict__ P, int du, 
             const double* __restrict__ colsum_x, int64_t n, double* __restrict__ T, double* __restrict__ V,
             double* __restrict__ evals, double* __restrict__ psi, float* __restrict__ psi32) {
   __shared__ double red[kSmallThreads];
-  __shared__ double sh[3 * 64 + 8 + 256];
+  __shared__ __align__(16) double sh[3 * 64 + 8 + 256];
   __shared__ int perm[256];
   __shared__ double ev[256];
   __shared__ double nrm[256];
@@ -297,7 +297,7 @@ k_reduce_rr(const double* __restrict__ M, const double* __restrict__ P, int du, 
     }
   }
   __syncthreads();
-  blk_jacobi(T, l, V, l, l, sh, red, 40);
+  blk_jacobi<7, 13>(T, l, V, l, l, sh, red, 40);
   blk_sort_desc(T, l, l, ev, perm);
   // psi = M V[:, perm[:d]]
   for (int idx = threadIdx.x; idx < du * d; idx += blockDim.x) {
@@ -332,7 +332,7 @@ k_embed_small(const double* __restrict__ K, const double* __restrict__ Omega, in
               float* __restrict__ S32, double* __restrict__ sigma, double* __restrict__ psi,
               double* __restrict__ H, float* __restrict__ H32, int32_t* __restrict__ err_bits) {
   __shared__ double red[kSmallThreads];
-  __shared__ double sh[3 * 64 + 8 + 256];
+  __shared__ __align__(16) double sh[3 * 64 + 8 + 256];
   __shared__ int perm[128];
   __shared__ double ev[128];
   __shared__ double nrm[128];
@@ -364,7 +364,7 @@ k_embed_small(const double* __restrict__ K, const double* __restrict__ Omega, in
     }
   }
   __syncthreads();
-  blk_jacobi(BBt, kp, V, kp, kp, sh, red, 40);
+  blk_jacobi<7, 13>(BBt, kp, V, kp, kp, sh, red, 40);
   blk_sort_desc(BBt, kp, kp, ev, perm);
   for (int c = threadIdx.x; c < k; c += blockDim.x) sigma[c] = sqrt(ev[c] > 0.0 ? ev[c] : 0.0);
   __syncthreads();

@@ -195,61 +195,81 @@ __global__ void __launch_bounds__(kLT)
 k_rr_reduce(const double* __restrict__ M, const double* __restrict__ P, int du, int l, int d, int dp,
             const double* __restrict__ colsum_x, int64_t n, double* __restrict__ evals, double* __restrict__ psi,
             float* __restrict__ psi32) {
-  __shared__ double T[kLdsN * kLdsN];
-  __shared__ double V[kLdsN * kLdsN];
-  __shared__ double sa[kStage * kLdsN];
-  __shared__ double red[kLT];
-  __shared__ double sh[3 * 40 + 8];
+  __shared__ double T[kLdsN * (kLdsN + 1)];
+  __shared__ double V[kLdsN * (kLdsN + 1)];
+  __shared__ double sa[kLdsN * kLdsN];  // rows of M in stages
+  __shared__ __align__(16) double sh[3 * 40 + 8];
   __shared__ int perm[kLdsN];
   __shared__ double ev[kLdsN];
   __shared__ double sgn[kLdsN];
-  mfma_gram_f64(M, l, P, l, du, l, T, l, false);
+  const int lt = l | 1;  // odd leading dimension of T and V: column walks spread over the LDS banks
+  mfma_gram_f64(M, l, P, l, du, l, T, lt, false);
   for (int e = threadIdx.x; e < l * l; e += kLT) {
     const int i = e / l, j = e % l;
     if (i < j) {
-      const double a = 0.5 * (T[i * l + j] + T[j * l + i]);
-      T[i * l + j] = a;
-      T[j * l + i] = a;
+      const double a = 0.5 * (T[i * lt + j] + T[j * lt + i]);
+      T[i * lt + j] = a;
+      T[j * lt + i] = a;
     }
   }
   __syncthreads();
-  lds_eig(T, V, l, sh, red, perm, ev);
-  // psi = M V[:, perm[:d]] (streamed rows of M)
-  for (int r0 = 0; r0 < du; r0 += kStage) {
-    for (int e = threadIdx.x; e < kStage * l; e += kLT) {
+  blk_jacobi(T, lt, V, lt, l, sh, nullptr, 40);
+  blk_sort_desc(T, lt, l, ev, perm);
+  // psi = M V[:, perm[:d]] (rows of M streamed through sa, as many as fit)
+  const int stage = (kLdsN * kLdsN) / l;
+  for (int r0 = 0; r0 < du; r0 += stage) {
+    for (int e = threadIdx.x; e < stage * l; e += kLT) {
       const int rr = e / l, c = e - (e / l) * l;
       sa[e] = (r0 + rr < du) ? M[(r0 + rr) * l + c] : 0.0;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < kStage * d; e += kLT) {
+    for (int e = threadIdx.x; e < stage * d; e += kLT) {
       const int rr = e / d, c = e - (e / d) * d;
       if (r0 + rr < du) {
         const int pc = perm[c];
         double s = 0.0;
-        for (int t = 0; t < l; ++t) s = fma(sa[rr * l + t], V[t * l + pc], s);
+        for (int t = 0; t < l; ++t) s = fma(sa[rr * l + t], V[t * lt + pc], s);
         psi[(r0 + rr) * d + c] = s;
       }
     }
     __syncthreads();
   }
   // sign: colsum(X') = colsum(X) Psi_d; degenerate -> largest |Psi_d| entry
-  for (int c = threadIdx.x; c < d; c += kLT) {
-    const double lam = ev[c] > 0.0 ? ev[c] : 0.0;
-    evals[c] = sqrt(lam);
-    double s = 0.0;
-    for (int i = 0; i < du; ++i) s = fma(colsum_x[i], psi[i * d + c], s);
-    if (fabs(s) <= 1e-9 * sqrt(static_cast<double>(n)) * sqrt(lam)) {
-      double best = -1.0;
-      s = 0.0;
-      for (int i = 0; i < du; ++i) {
-        const double v = psi[i * d + c];
-        if (fabs(v) > best) {
-          best = fabs(v);
-          s = v;
+  // (the first one on a tie).  One wave per column.
+  {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int c = w; c < d; c += kLT / 64) {
+      const double lam = ev[c] > 0.0 ? ev[c] : 0.0;
+      double s = 0.0;
+      for (int i = lane; i < du; i += 64) s = fma(colsum_x[i], psi[i * d + c], s);
+      s = wave_sum(s);
+      if (fabs(s) <= 1e-9 * sqrt(static_cast<double>(n)) * sqrt(lam)) {
+        double best = -1.0, bv = 0.0;
+        int bi = du;
+        for (int i = lane; i < du; i += 64) {
+          const double v = psi[i * d + c];
+          if (fabs(v) > best) {
+            best = fabs(v);
+            bv = v;
+            bi = i;
+          }
         }
+        for (int off = 32; off > 0; off >>= 1) {
+          const double ob = __shfl_xor(best, off, 64), ov = __shfl_xor(bv, off, 64);
+          const int oi = __shfl_xor(bi, off, 64);
+          if (ob > best || (ob == best && oi < bi)) {
+            best = ob;
+            bv = ov;
+            bi = oi;
+          }
+        }
+        s = bv;
+      }
+      if (lane == 0) {
+        evals[c] = sqrt(lam);
+        sgn[c] = s < 0.0 ? -1.0 : 1.0;
       }
     }
-    sgn[c] = s < 0.0 ? -1.0 : 1.0;
   }
   __syncthreads();
   for (int e = threadIdx.x; e < du * dp; e += kLT) {
@@ -278,7 +298,7 @@ k_embed_final(double* __restrict__ M, double* __restrict__ P, int twod, int kp, 
   __shared__ double scratch[4 * 256];
   __shared__ int flag;
   __shared__ double red[kLT];
-  __shared__ double sh[3 * 40 + 8];
+  __shared__ __align__(16) double sh[3 * 40 + 8];
   __shared__ int perm[kLdsN];
   __shared__ double ev[kLdsN];
   __shared__ double sgn[kLdsN];
