@@ -172,14 +172,16 @@ __device__ __forceinline__ void jacobi_pair(int step, int i, int np, int& p, int
 // the sweep waits for the next one.  Stops when no step is marked (or after
 // max_sweeps).  Returns the number of sweeps taken.
 // sh: scratch of 3 * ((n + 1) / 2) doubles (16-byte aligned); red: unused.
-// Each thread takes at most kA blocks and kV rows of V: (n / 2)^2 <= kA
-// blockDim.x and n^2 / 2 <= kV blockDim.x (2 and 4: n <= 80 with 1024
-// threads; 7 and 13: n <= 160).
+// Each thread takes kBatches batches of 2 blocks and 4 rows of V:
+// (n / 2)^2 <= 2 kBatches blockDim.x and n^2 / 2 <= 4 kBatches blockDim.x
+// (kBatches = 1: n <= 80 with 1024 threads; 2: n <= 128; 4: n <= 160).
 
-template <int kA = 2, int kV = 4>
+template <int kBatches = 1>
 __device__ inline int blk_jacobi(double* A, int lda, double* V, int ldv, int n, double* sh, double* red,
                                  int max_sweeps) {
   (void)red;
+  constexpr int kA = 2, kV = 4;  // blocks and rows of V per thread and batch
+  constexpr int kAT = kA * kBatches, kVT = kV * kBatches;
   const int np = n + (n & 1);
   const int npairs = np / 2;
   const int m = np - 1;          // steps per sweep (odd)
@@ -194,15 +196,15 @@ __device__ inline int blk_jacobi(double* A, int lda, double* V, int ldv, int n, 
   }
   // this thread's items, fixed for the whole run: blocks (i, j) of J^T A J
   // and (pair i, row r) items of V J
-  int bi[kA], bj[kA], vi[kV], vr[kV];
+  int bi[kAT], bj[kAT], vi[kVT], vr[kVT];
 #pragma unroll
-  for (int k = 0; k < kA; ++k) {
+  for (int k = 0; k < kAT; ++k) {
     const int e = threadIdx.x + k * blockDim.x;
     bi[k] = e < npairs * npairs ? e / npairs : -1;
     bj[k] = e < npairs * npairs ? e - (e / npairs) * npairs : 0;
   }
 #pragma unroll
-  for (int k = 0; k < kV; ++k) {
+  for (int k = 0; k < kVT; ++k) {
     const int e = threadIdx.x + k * blockDim.x;
     vi[k] = e < npairs * n ? e / n : -1;
     vr[k] = e < npairs * n ? e - (e / n) * n : 0;
@@ -246,78 +248,81 @@ __device__ inline int blk_jacobi(double* A, int lda, double* V, int ldv, int n, 
         pq[i] = make_int2(p, q < n ? q : -1);
       }
       __syncthreads();
-      // the items of a step touch disjoint entries, so every load is issued
-      // before any store (the compiler cannot prove that on its own)
-      double2 ra[kA], rb[kA], rv[kV];
-      int2 xa[kA], xb[kA], xv[kV];
-      double va[kA][4], vv[kV][2];
+      // the items of a step touch disjoint entries, so within a batch every
+      // load is issued before any store (the compiler cannot prove that on its own)
 #pragma unroll
-      for (int k = 0; k < kA; ++k) {
-        ra[k] = rb[k] = make_double2(1.0, 0.0);
-        xa[k] = xb[k] = make_int2(-1, -1);
-        if (bi[k] >= 0) {
-          ra[k] = rot[bi[k]];
-          xa[k] = pq[bi[k]];
-          rb[k] = rot[bj[k]];
-          xb[k] = pq[bj[k]];
-        }
-      }
+      for (int bt = 0; bt < kBatches; ++bt) {
+        double2 ra[kA], rb[kA], rv[kV];
+        int2 xa[kA], xb[kA], xv[kV];
+        double va[kA][4], vv[kV][2];
 #pragma unroll
-      for (int k = 0; k < kV; ++k) {
-        rv[k] = make_double2(1.0, 0.0);
-        xv[k] = make_int2(-1, -1);
-        if (vi[k] >= 0) {
-          rv[k] = rot[vi[k]];
-          xv[k] = pq[vi[k]];
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < kA; ++k) {
-        va[k][0] = va[k][1] = va[k][2] = va[k][3] = 0.0;
-        const int p_i = xa[k].x, q_i = xa[k].y, p_j = xb[k].x, q_j = xb[k].y;
-        if (p_i >= 0 && (ra[k].y != 0.0 || rb[k].y != 0.0)) {
-          va[k][0] = A[p_i * lda + p_j];
-          if (q_j >= 0) va[k][1] = A[p_i * lda + q_j];
-          if (q_i >= 0) va[k][2] = A[q_i * lda + p_j];
-          if (q_i >= 0 && q_j >= 0) va[k][3] = A[q_i * lda + q_j];
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < kV; ++k) {
-        vv[k][0] = vv[k][1] = 0.0;
-        if (xv[k].x >= 0 && rv[k].y != 0.0) {
-          vv[k][0] = V[vr[k] * ldv + xv[k].x];
-          vv[k][1] = V[vr[k] * ldv + xv[k].y];
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < kA; ++k) {
-        const int p_i = xa[k].x, q_i = xa[k].y, p_j = xb[k].x, q_j = xb[k].y;
-        const double ci = ra[k].x, si = ra[k].y, cj = rb[k].x, sj = rb[k].y;
-        if (p_i >= 0 && (si != 0.0 || sj != 0.0)) {
-          const double a = va[k][0], b = va[k][1], c = va[k][2], d = va[k][3];
-          const double a1 = ci * a - si * c, b1 = ci * b - si * d;
-          const double c1 = si * a + ci * c, d1 = si * b + ci * d;
-          const double a2 = cj * a1 - sj * b1;
-          double b2 = sj * a1 + cj * b1;
-          double c2 = cj * c1 - sj * d1;
-          const double d2 = sj * c1 + cj * d1;
-          if (bi[k] == bj[k] && si != 0.0) {  // the rotated pair's own coupling is annihilated
-            b2 = 0.0;
-            c2 = 0.0;
+        for (int k = 0; k < kA; ++k) {
+          ra[k] = rb[k] = make_double2(1.0, 0.0);
+          xa[k] = xb[k] = make_int2(-1, -1);
+          if (bi[bt * kA + k] >= 0) {
+            ra[k] = rot[bi[bt * kA + k]];
+            xa[k] = pq[bi[bt * kA + k]];
+            rb[k] = rot[bj[bt * kA + k]];
+            xb[k] = pq[bj[bt * kA + k]];
           }
-          A[p_i * lda + p_j] = a2;
-          if (q_j >= 0) A[p_i * lda + q_j] = b2;
-          if (q_i >= 0) A[q_i * lda + p_j] = c2;
-          if (q_i >= 0 && q_j >= 0) A[q_i * lda + q_j] = d2;
         }
-      }
 #pragma unroll
-      for (int k = 0; k < kV; ++k) {
-        if (xv[k].x >= 0 && rv[k].y != 0.0) {
-          const double c = rv[k].x, s = rv[k].y, vp = vv[k][0], vq = vv[k][1];
-          V[vr[k] * ldv + xv[k].x] = c * vp - s * vq;
-          V[vr[k] * ldv + xv[k].y] = s * vp + c * vq;
+        for (int k = 0; k < kV; ++k) {
+          rv[k] = make_double2(1.0, 0.0);
+          xv[k] = make_int2(-1, -1);
+          if (vi[bt * kV + k] >= 0) {
+            rv[k] = rot[vi[bt * kV + k]];
+            xv[k] = pq[vi[bt * kV + k]];
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < kA; ++k) {
+          va[k][0] = va[k][1] = va[k][2] = va[k][3] = 0.0;
+          const int p_i = xa[k].x, q_i = xa[k].y, p_j = xb[k].x, q_j = xb[k].y;
+          if (p_i >= 0 && (ra[k].y != 0.0 || rb[k].y != 0.0)) {
+            va[k][0] = A[p_i * lda + p_j];
+            if (q_j >= 0) va[k][1] = A[p_i * lda + q_j];
+            if (q_i >= 0) va[k][2] = A[q_i * lda + p_j];
+            if (q_i >= 0 && q_j >= 0) va[k][3] = A[q_i * lda + q_j];
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < kV; ++k) {
+          vv[k][0] = vv[k][1] = 0.0;
+          if (xv[k].x >= 0 && rv[k].y != 0.0) {
+            vv[k][0] = V[vr[bt * kV + k] * ldv + xv[k].x];
+            vv[k][1] = V[vr[bt * kV + k] * ldv + xv[k].y];
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < kA; ++k) {
+          const int p_i = xa[k].x, q_i = xa[k].y, p_j = xb[k].x, q_j = xb[k].y;
+          const double ci = ra[k].x, si = ra[k].y, cj = rb[k].x, sj = rb[k].y;
+          if (p_i >= 0 && (si != 0.0 || sj != 0.0)) {
+            const double a = va[k][0], b = va[k][1], c = va[k][2], d = va[k][3];
+            const double a1 = ci * a - si * c, b1 = ci * b - si * d;
+            const double c1 = si * a + ci * c, d1 = si * b + ci * d;
+            const double a2 = cj * a1 - sj * b1;
+            double b2 = sj * a1 + cj * b1;
+            double c2 = cj * c1 - sj * d1;
+            const double d2 = sj * c1 + cj * d1;
+            if (bi[bt * kA + k] == bj[bt * kA + k] && si != 0.0) {  // the rotated pair's own coupling is annihilated
+              b2 = 0.0;
+              c2 = 0.0;
+            }
+            A[p_i * lda + p_j] = a2;
+            if (q_j >= 0) A[p_i * lda + q_j] = b2;
+            if (q_i >= 0) A[q_i * lda + p_j] = c2;
+            if (q_i >= 0 && q_j >= 0) A[q_i * lda + q_j] = d2;
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < kV; ++k) {
+          if (xv[k].x >= 0 && rv[k].y != 0.0) {
+            const double c = rv[k].x, s = rv[k].y, vp = vv[k][0], vq = vv[k][1];
+            V[vr[bt * kV + k] * ldv + xv[k].x] = c * vp - s * vq;
+            V[vr[bt * kV + k] * ldv + xv[k].y] = s * vp + c * vq;
+          }
         }
       }
       __syncthreads();

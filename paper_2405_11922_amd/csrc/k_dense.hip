@@ -297,7 +297,7 @@ k_reduce_rr(const double* __restrict__ M, const double* __restrict__ P, int du, 
     }
   }
   __syncthreads();
-  blk_jacobi<7, 13>(T, l, V, l, l, sh, red, 40);
+  blk_jacobi<4>(T, l, V, l, l, sh, red, 40);
   blk_sort_desc(T, l, l, ev, perm);
   // psi = M V[:, perm[:d]]
   for (int idx = threadIdx.x; idx < du * d; idx += blockDim.x) {
@@ -364,7 +364,7 @@ k_embed_small(const double* __restrict__ K, const double* __restrict__ Omega, in
     }
   }
   __syncthreads();
-  blk_jacobi<7, 13>(BBt, kp, V, kp, kp, sh, red, 40);
+  blk_jacobi<4>(BBt, kp, V, kp, kp, sh, red, 40);
   blk_sort_desc(BBt, kp, kp, ev, perm);
   for (int c = threadIdx.x; c < k; c += blockDim.x) sigma[c] = sqrt(ev[c] > 0.0 ? ev[c] : 0.0);
   __syncthreads();
@@ -787,17 +787,23 @@ void launch_embed(const Plan& p, void* ws, hipStream_t s) {
   double* K = bufp<double>(p, ws, B_K);
   gram(bufp<float>(p, ws, B_R), p.n, p.twod, p.twod, p.gram_chunks_r, bufp<double>(p, ws, B_GRAM_PART), nullptr,
        K, nullptr, s);
-  if (p.kp <= kLdsMaxN) {
+  if (p.kp <= kWideMaxN) {
     // q products with K, each followed by Cholesky QR, then P = K M
     double* m = bufp<double>(p, ws, B_SI_M);
     double* pm = bufp<double>(p, ws, B_SI_P);
     subspace_iterate(K, p.twod, bufp<double>(p, ws, B_OMEGA), p.kp, p.par.q, bufp<double>(p, ws, B_M_A),
                      bufp<double>(p, ws, B_M_B), bufp<double>(p, ws, B_SI_GRAM), bufp<double>(p, ws, B_SI_PART),
                      bufp<unsigned>(p, ws, B_SI_BAR), m, pm, &st->err_bits, s);
-    embed_final_lds(m, pm, p.twod, p.kp, p.k, bufp<double>(p, ws, B_RCOLSUM), static_cast<int64_t>(p.n),
-                    bufp<double>(p, ws, B_EEVAL), bufp<float>(p, ws, B_S32), bufp<double>(p, ws, B_SIGMA),
-                    bufp<double>(p, ws, B_PSI), bufp<double>(p, ws, B_H), bufp<float>(p, ws, B_H32), &st->err_bits,
-                    s);
+    if (p.kp <= kLdsMaxN)
+      embed_final_lds(m, pm, p.twod, p.kp, p.k, bufp<double>(p, ws, B_RCOLSUM), static_cast<int64_t>(p.n),
+                      bufp<double>(p, ws, B_EEVAL), bufp<float>(p, ws, B_S32), bufp<double>(p, ws, B_SIGMA),
+                      bufp<double>(p, ws, B_PSI), bufp<double>(p, ws, B_H), bufp<float>(p, ws, B_H32), &st->err_bits,
+                      s);
+    else
+      embed_final_wide(m, pm, p.twod, p.kp, p.k, bufp<double>(p, ws, B_RCOLSUM), static_cast<int64_t>(p.n),
+                       bufp<double>(p, ws, B_EEVAL), bufp<float>(p, ws, B_S32), bufp<double>(p, ws, B_SIGMA),
+                       bufp<double>(p, ws, B_PSI), bufp<double>(p, ws, B_H), bufp<float>(p, ws, B_H32),
+                       bufp<double>(p, ws, B_EK_A), &st->err_bits, s);
     return;
   }
   hipLaunchKernelGGL(k_embed_small, dim3(1), dim3(kSmallThreads), 0, s, K, bufp<double>(p, ws, B_OMEGA), p.twod,

@@ -381,6 +381,123 @@ void rr_reduce_lds(const double* M, const double* P, int du, int l, int d, int d
   TPO_LAUNCH_CHECK();
 }
 
+// A (m x n, row-major, global) <- A Li^T with Li lower in LDS (ld), in
+// stages of 16 rows copied to st (16 n doubles of LDS) first.
+__device__ void apply_linv_t_staged(double* A, int m, int n, const double* Li, int ld, double* st) {
+  for (int r0 = 0; r0 < m; r0 += 16) {
+    const int nr = min(16, m - r0);
+    for (int e = threadIdx.x; e < nr * n; e += blockDim.x) st[e] = A[static_cast<int64_t>(r0) * n + e];
+    __syncthreads();
+    for (int e = threadIdx.x; e < nr * n; e += blockDim.x) {
+      const int r = e / n, c = e - (e / n) * n;
+      double s = 0.0;
+      for (int t = 0; t <= c; ++t) s = fma(st[r * n + t], Li[c * ld + t], s);
+      A[static_cast<int64_t>(r0) * n + e] = s;
+    }
+    __syncthreads();
+  }
+}
+
+// The same final step as k_embed_final for k' in 81..128, where the k' x k'
+// eigenproblem and its eigenvectors do not both fit in LDS: the Cholesky
+// factor is inverted in place (one k' x k' array), and the Jacobi keeps its
+// eigenvectors in Vg (global, k' x k') while B B^T stays in LDS; Vg is copied
+// into LDS for the products that follow.
+__global__ void __launch_bounds__(kLT)
+k_embed_final_wide(double* __restrict__ M, double* __restrict__ P, int twod, int kp, int k,
+                   const double* __restrict__ colsum_r, int64_t n, double* __restrict__ S, float* __restrict__ S32,
+                   double* __restrict__ sigma, double* __restrict__ psi, double* __restrict__ H,
+                   float* __restrict__ H32, double* __restrict__ Vg, int32_t* __restrict__ err_bits) {
+  constexpr int kW = 128;
+  __shared__ double G[kW * (kW + 1)];
+  __shared__ __align__(16) double scr[8 * 256];  // factorisation scratch tiles; staged rows
+  __shared__ double dinv[kW];
+  __shared__ int flag;
+  __shared__ __align__(16) double sh[3 * (kW / 2)];
+  __shared__ int perm[kW];
+  __shared__ double ev[kW];
+  __shared__ double sgn[kW];
+  const int nb = (kp + 15) / 16;
+  const int ld = 16 * nb + 1;
+  // M^T K M in the padded layout (identity on the padding)
+  mfma_gram_f64(M, kp, P, kp, twod, kp, G, ld, false);
+  for (int e = threadIdx.x; e < 16 * nb * 16 * nb; e += kLT) {
+    const int i = e / (16 * nb), j = e % (16 * nb);
+    if (i >= kp || j >= kp) {
+      G[i * ld + j] = (i == j) ? 1.0 : 0.0;
+    } else if (i < j) {
+      const double a = 0.5 * (G[i * ld + j] + G[j * ld + i]);
+      G[i * ld + j] = a;
+      G[j * ld + i] = a;
+    }
+  }
+  __syncthreads();
+  // L = chol(M^T K M) with L^{-1} in place; P <- B^T = K M L^{-T}; M <- M L^{-T}
+  if (!blk_chol_inv16_inplace(G, ld, nb, scr, dinv, &flag)) {
+    if (threadIdx.x == 0) atomicOr(err_bits, 16);
+    return;
+  }
+  apply_linv_t_staged(P, twod, kp, G, ld, scr);
+  apply_linv_t_staged(M, twod, kp, G, ld, scr);
+  const int lj = kp | 1;
+  mfma_gram_f64(P, kp, P, kp, twod, kp, G, lj, true);  // B B^T
+  __syncthreads();
+  blk_jacobi<2>(G, lj, Vg, kp, kp, sh, nullptr, 40);
+  blk_sort_desc(G, lj, kp, ev, perm);
+  for (int c = threadIdx.x; c < k; c += kLT) sigma[c] = sqrt(ev[c] > 0.0 ? ev[c] : 0.0);
+  double* Vs = G;  // the eigenvectors, now in LDS
+  for (int e = threadIdx.x; e < kp * kp; e += kLT) Vs[e] = Vg[e];
+  __syncthreads();
+  for (int e = threadIdx.x; e < twod * k; e += kLT) {
+    const int i = e / k, c = e % k;
+    const int pc = perm[c];
+    double a = 0.0, b = 0.0;
+    for (int t = 0; t < kp; ++t) {
+      a = fma(M[i * kp + t], Vs[t * kp + pc], a);
+      b = fma(P[i * kp + t], Vs[t * kp + pc], b);
+    }
+    S[e] = a;
+    psi[e] = sigma[c] > 0.0 ? b / sigma[c] : 0.0;
+  }
+  __syncthreads();
+  // sign: colsum(Gamma) = colsum(R) S, ||Gamma[:, c]|| = 1
+  for (int c = threadIdx.x; c < k; c += kLT) {
+    double s = 0.0;
+    for (int i = 0; i < twod; ++i) s = fma(colsum_r[i], S[i * k + c], s);
+    if (fabs(s) <= 1e-9 * sqrt(static_cast<double>(n))) {
+      double best = -1.0;
+      s = 0.0;
+      for (int i = 0; i < twod; ++i) {
+        const double v = psi[i * k + c];
+        if (fabs(v) > best) {
+          best = fabs(v);
+          s = v;
+        }
+      }
+    }
+    sgn[c] = s < 0.0 ? -1.0 : 1.0;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < twod * k; e += kLT) {
+    const int c = e % k;
+    const double sv = S[e] * sgn[c];
+    const double pv = psi[e] * sgn[c];
+    S[e] = sv;
+    psi[e] = pv;
+    S32[e] = static_cast<float>(sv);
+    H[e] = pv * sigma[c];
+    H32[e] = static_cast<float>(pv * sigma[c]);
+  }
+}
+
+void embed_final_wide(double* M, double* P, int twod, int kp, int k, const double* colsum_r, int64_t n, double* S,
+                      float* S32, double* sigma, double* psi, double* H, float* H32, double* vg, int32_t* err_bits,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_embed_final_wide, dim3(1), dim3(kLT), 0, s, M, P, twod, kp, k, colsum_r, n, S, S32, sigma,
+                     psi, H, H32, vg, err_bits);
+  TPO_LAUNCH_CHECK();
+}
+
 void embed_final_lds(double* M, double* P, int twod, int kp, int k, const double* colsum_r, int64_t n, double* S,
                      float* S32, double* sigma, double* psi, double* H, float* H32, int32_t* err_bits,
                      hipStream_t s) {

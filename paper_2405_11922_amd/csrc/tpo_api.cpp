@@ -167,7 +167,7 @@ void build_layout(Plan& p) {
   add(B_REDTMP, 8 * 16 * std::max(twod * k + k * k, twod));
   {
     const bool red_si = p.reduce && p.lr <= kLdsMaxN;
-    const bool emb_si = p.kp <= kLdsMaxN;
+    const bool emb_si = p.kp <= kWideMaxN;
     const size_t mp = std::max(red_si ? du * lr : 0, emb_si ? twod * kp : 0);
     const size_t li = std::max(red_si ? subspace_gsum_doubles(static_cast<int>(lr)) : 0,
                                emb_si ? subspace_gsum_doubles(static_cast<int>(kp)) : 0);

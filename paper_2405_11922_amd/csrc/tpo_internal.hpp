@@ -144,6 +144,11 @@ void rr_reduce_lds(const double* M, const double* P, int du, int l, int d, int d
 void embed_final_lds(double* M, double* P, int twod, int kp, int k, const double* colsum_r, int64_t n, double* S,
                      float* S32, double* sigma, double* psi, double* H, float* H32, int32_t* err_bits,
                      hipStream_t s);
+// k' in 81..128: the same, with the k' x k' eigenvectors kept in vg (global)
+constexpr int kWideMaxN = 128;
+void embed_final_wide(double* M, double* P, int twod, int kp, int k, const double* colsum_r, int64_t n, double* S,
+                      float* S32, double* sigma, double* psi, double* H, float* H32, double* vg, int32_t* err_bits,
+                      hipStream_t s);
 // deterministic two-level sum of nparts rows of length len (k_dense.hip)
 void reduce_parts(const double* part, int nparts, int len, double* tmp, double* out, hipStream_t s);
 // k_cluster.hip
