@@ -47,8 +47,9 @@ k_rowpass_mfma(const float* __restrict__ R, int64_t n, int twod, int k, const fl
   // Slab rows: 64, or 32 when 64 would not fit; RTILES row tiles, each formed
   // by WPR waves that split the output column tiles.
   constexpr bool SLDS = TD * OS * 4 <= 72 * 1024;
-  constexpr bool ALDS = KT <= 4;
-  constexpr int FIXED = (SLDS ? TD * OS : 0) + (ALDS ? KP * OS : 0);
+  constexpr int SFIX = SLDS ? TD * OS : 0;
+  constexpr bool ALDS = 4 * ((kRpRows / 2) * RS + kRpRows * OS + SFIX + KP * OS) <= 156 * 1024;
+  constexpr int FIXED = SFIX + (ALDS ? KP * OS : 0);
   constexpr int ROWS = 4 * (kRpRows * RS + 2 * kRpRows * OS + FIXED) <= 150 * 1024 ? kRpRows : kRpRows / 2;
   constexpr int RTILES = ROWS / 16, WPR = 4 / RTILES;
   constexpr int RPT = ROWS * TD / 256, UPT = ROWS * KP / 256;  // prefetched elements per thread
@@ -299,6 +300,12 @@ static void rowpass_j(const Plan& p, void* ws, int mode, const float* Sm, const 
     rowpass_jk<JT, 2>(p, ws, mode, Sm, A32, s);
   else if (p.k <= 64)
     rowpass_jk<JT, 4>(p, ws, mode, Sm, A32, s);
+  else if (p.k <= 80)
+    rowpass_jk<JT, 5>(p, ws, mode, Sm, A32, s);
+  else if (p.k <= 96)
+    rowpass_jk<JT, 6>(p, ws, mode, Sm, A32, s);
+  else if (p.k <= 112)
+    rowpass_jk<JT, 7>(p, ws, mode, Sm, A32, s);
   else
     rowpass_jk<JT, 8>(p, ws, mode, Sm, A32, s);
 }
