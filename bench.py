@@ -71,6 +71,11 @@ def main() -> int:
     ap.add_argument("--config", default="mid_fp32")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-baseline", default="on", choices=["on", "off"])
+    ap.add_argument("--x-dtype", default="auto", choices=["auto", "f32", "bf16"],
+                    help="attribute storage: auto = bf16 for the large precision form, f32 otherwise")
+    ap.add_argument("--compare-f32", action="store_true",
+                    help="with bf16 attributes, also run the plain FP32 job on the same graph and report the "
+                         "label agreement and objective difference")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also copy a 256 MiB buffer once (a kernel of known traffic, to scale "
                          "hardware byte counters)")
@@ -110,8 +115,15 @@ def main() -> int:
         abg_n_edges, abg_d_u = abg.n_edges, abg.d_u
     log(f"[bench] generated {args.config} ({'on the GPU' if on_device else 'on the host'}): n_u={shape.n_u} "
         f"n_v={shape.n_v} E={abg_n_edges} d_u={abg_d_u} in {time.time() - t0:.1f}s")
+    x_dtype = args.x_dtype if args.x_dtype != "auto" else ("bf16" if args.config == "large" else "f32")
+    x_f32 = x
+    if x_dtype == "bf16":
+        x = x_f32.to(torch.bfloat16)
+        if not args.compare_f32:
+            del x_f32
+            x_f32 = None
     kw = dict(k=shape.k, alpha=shape.alpha, gamma=shape.gamma, d=shape.d, q=shape.q,
-              oversample=shape.oversample, t_f=shape.t_f, t_g=shape.t_g, seed=args.seed)
+              oversample=shape.oversample, t_f=shape.t_f, t_g=shape.t_g, seed=args.seed, x_dtype=x_dtype)
     plan = tpo.Plan.create(shape.n_u, shape.n_v, abg_n_edges, abg_d_u, device=dev, timing=False, **kw)
     plan_t = tpo.Plan.create(shape.n_u, shape.n_v, abg_n_edges, abg_d_u, device=dev, timing=True, **kw)
     labels = torch.empty(shape.n_u, dtype=torch.int32, device=dev)
@@ -176,7 +188,7 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if x_dtype == "f32" else "bf16 attributes (BF16 MFMA Gram, FP32 accumulation), f32 path",
         "data": "synthetic",
         "config": {
             "workload": f"{args.config}: planted degree-corrected bipartite SBM, |U|={shape.n_u}, "
@@ -184,7 +196,7 @@ def main() -> int:
                         f"d_U={abg_d_u} -> d={d_eff}, gamma={shape.gamma}, alpha={shape.alpha}, "
                         f"q={shape.q}, T_f={shape.t_f}, T_g={shape.t_g}",
             "n_u": shape.n_u, "n_v": shape.n_v, "n_edges": abg_n_edges, "k": shape.k, "d_u": abg_d_u,
-            "d": d_eff, "k_prime": kp, "l_r": l_r, "gamma": shape.gamma,
+            "d": d_eff, "k_prime": kp, "l_r": l_r, "gamma": shape.gamma, "x_dtype": x_dtype,
         },
         "gedge_hop_per_s": round(gedge_hops, 3) if gedge_hops else None,
         "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 4),
@@ -193,6 +205,27 @@ def main() -> int:
         "roofline": roofline,
         "objective": obj[0],
     }
+
+    if x_dtype == "bf16" and args.compare_f32:
+        # the plain FP32 job on the same graph (X not rounded): how far the
+        # precision form moves the result
+        from scipy.optimize import linear_sum_assignment
+
+        kw32 = dict(kw, x_dtype="f32")
+        plan32 = tpo.Plan.create(shape.n_u, shape.n_v, abg_n_edges, abg_d_u, device=dev, timing=False, **kw32)
+        lab32 = torch.empty_like(labels)
+        obj32 = tpo.tpo_execute(plan32.handle, eu, ev, x_f32, plan32.workspace, lab32)
+        torch.cuda.synchronize()
+        plan32.close()
+        a, b = labels_np.astype(np.int64), lab32.cpu().numpy().astype(np.int64)
+        table = np.zeros((shape.k, shape.k), np.int64)
+        np.add.at(table, (a, b), 1)
+        r, c = linear_sum_assignment(-table)
+        agree = float(table[r, c].sum() / a.size)
+        result["vs_f32"] = {"label_agreement": round(agree, 6),
+                            "objective_rel_diff": abs(obj[0] - obj32[0]) / abs(obj32[0])}
+        log(f"[bench] plain FP32 run on the same graph: labels agree on {agree:.4%} of the rows (best matching), "
+            f"objective rel diff {result['vs_f32']['objective_rel_diff']:.2e}")
 
     if args.cpu_baseline == "on" and on_device:
         log("[bench] no CPU baseline for the on-GPU generated workload (the oracle needs the host arrays)")

@@ -53,8 +53,15 @@ typedef struct tpo_problem {
                           a (u, v) pair listed twice adds its weights (B_U[i,j]
                           is the summed weight) */
   int32_t weighted;    /* 1: tpo_inputs.edge_w is given; 0: every w = 1 */
-  int32_t reserved;
+  int32_t x_dtype;     /* element type of tpo_inputs.x_u: TPO_X_F32 or
+                          TPO_X_BF16 (the attribute precision form: the
+                          Gram C = X^T X of Section 3.2.1 on BF16 MFMA with
+                          FP32 accumulation, added up in FP64; the projection
+                          reads BF16 and multiplies in FP32) */
 } tpo_problem;
+
+#define TPO_X_F32 0
+#define TPO_X_BF16 1 /* bfloat16: the upper 16 bits of an IEEE binary32 */
 
 /* Method parameters: Table 1 of the paper plus the unstated RandomizedSVD
  * details.  Defaults used in the paper: t_f = 5, t_g = 20. */
@@ -88,7 +95,8 @@ typedef struct tpo_inputs {
   const int32_t* edge_u; /* [n_edges] endpoint in U, 0 <= u < n_u */
   const int32_t* edge_v; /* [n_edges] endpoint in V, 0 <= v < n_v */
   const float* edge_w;   /* [n_edges] weights >= 0, or NULL when unweighted */
-  const float* x_u;      /* X_U: n_u rows of ld_x floats, first d_u used */
+  const void* x_u;       /* X_U: n_u rows of ld_x elements of type
+                            tpo_problem.x_dtype, first d_u used */
   int64_t ld_x;          /* row stride of x_u in elements, >= d_u */
 } tpo_inputs;
 

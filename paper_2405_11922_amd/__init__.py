@@ -54,7 +54,7 @@ class TpoError(RuntimeError):
 class TpoProblem(C.Structure):
     _fields_ = [("abi_version", C.c_int32), ("n_u", C.c_int32), ("n_v", C.c_int32),
                 ("d_u", C.c_int32), ("n_edges", C.c_int64), ("weighted", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("x_dtype", C.c_int32)]
 
 
 class TpoParams(C.Structure):
@@ -152,12 +152,20 @@ def _dptr(arr):
     return a, a.ctypes.data_as(C.POINTER(C.c_double))
 
 
+X_DTYPES = {"f32": 0, "bf16": 1}  # TPO_X_F32, TPO_X_BF16
+_PLAN_XDT = {}  # plan handle -> x_dtype name, to check the tensors handed over
+
+
 def tpo_plan_create(n_u, n_v, n_edges, d_u, *, k, alpha, gamma, d=0, q=20, oversample=10,
                     t_f=5, t_g=20, seed=0, weighted=False, timing=False,
-                    omega_reduce=None, g=None, omega=None):
-    """Returns an opaque plan handle (int)."""
+                    omega_reduce=None, g=None, omega=None, x_dtype="f32"):
+    """Returns an opaque plan handle (int).  x_dtype: "f32" or "bf16" (X_U's
+    element type)."""
     lib = load_library()
-    prob = TpoProblem(TPO_ABI_VERSION, int(n_u), int(n_v), int(d_u), int(n_edges), int(bool(weighted)), 0)
+    if x_dtype not in X_DTYPES:
+        raise TpoError(1, f"x_dtype must be one of {sorted(X_DTYPES)}")
+    prob = TpoProblem(TPO_ABI_VERSION, int(n_u), int(n_v), int(d_u), int(n_edges), int(bool(weighted)),
+                      X_DTYPES[x_dtype])
     keep = [_dptr(omega_reduce), _dptr(g), _dptr(omega)]
     par = TpoParams(TPO_ABI_VERSION, int(k), float(alpha), int(gamma), int(d), int(q), int(oversample),
                     int(t_f), int(t_g), TPO_FLAG_TIMING if timing else 0, int(seed) & ((1 << 64) - 1),
@@ -165,10 +173,12 @@ def tpo_plan_create(n_u, n_v, n_edges, d_u, *, k, alpha, gamma, d=0, q=20, overs
                     keep[2][1] if keep[2] else None)
     h = C.c_void_p()
     _check(lib.tpo_plan_create(C.byref(prob), C.byref(par), C.byref(h)))
+    _PLAN_XDT[h.value] = x_dtype
     return h.value
 
 
 def tpo_plan_destroy(plan) -> None:
+    _PLAN_XDT.pop(plan, None)
     load_library().tpo_plan_destroy(plan)
 
 
@@ -184,7 +194,12 @@ def tpo_plan_dims(plan):
     return a.value, b.value, c.value
 
 
-def _inputs(edge_u, edge_v, x_u, edge_w=None):
+def _inputs(edge_u, edge_v, x_u, edge_w=None, plan=None):
+    if x_u is not None and plan in _PLAN_XDT:
+        want = _PLAN_XDT[plan]
+        have = {"torch.float32": "f32", "torch.bfloat16": "bf16"}.get(str(x_u.dtype))
+        if have != want:
+            raise TpoError(1, f"x_u is {x_u.dtype}, the plan expects {want}")
     ld = x_u.stride(0) if x_u is not None else 0
     return TpoInputs(edge_u.data_ptr() if edge_u is not None else None,
                      edge_v.data_ptr() if edge_v is not None else None,
@@ -203,7 +218,7 @@ def tpo_execute(plan, edge_u, edge_v, x_u, workspace, labels, embedding=None, ed
                 stream=None):
     """Runs the whole method; returns (obj1, trace form)."""
     lib = load_library()
-    inp = _inputs(edge_u, edge_v, x_u, edge_w)
+    inp = _inputs(edge_u, edge_v, x_u, edge_w, plan)
     obj = (C.c_double * 2)()
     out = TpoOutputs(labels.data_ptr(), embedding.data_ptr() if embedding is not None else None,
                      C.cast(obj, C.POINTER(C.c_double)))
@@ -217,12 +232,12 @@ def _ws(workspace):
 
 
 def tpo_stage_ingest(plan, edge_u, edge_v, x_u, workspace, edge_w=None, stream=None):
-    inp = _inputs(edge_u, edge_v, x_u, edge_w)
+    inp = _inputs(edge_u, edge_v, x_u, edge_w, plan)
     _check(load_library().tpo_stage_ingest(plan, C.byref(inp), *_ws(workspace), _stream(stream)), plan)
 
 
 def tpo_stage_reduce(plan, edge_u, edge_v, x_u, workspace, edge_w=None, stream=None):
-    inp = _inputs(edge_u, edge_v, x_u, edge_w)
+    inp = _inputs(edge_u, edge_v, x_u, edge_w, plan)
     _check(load_library().tpo_stage_reduce(plan, C.byref(inp), *_ws(workspace), _stream(stream)), plan)
 
 
@@ -294,6 +309,7 @@ class Plan:
 
     @classmethod
     def create(cls, n_u, n_v, n_edges, d_u, device="cuda", **params):
+        """params: those of tpo_plan_create (x_dtype "f32" or "bf16" included)."""
         import torch
         h = tpo_plan_create(n_u, n_v, n_edges, d_u, **params)
         nbytes = tpo_plan_workspace_bytes(h)
@@ -319,7 +335,7 @@ class Plan:
 
 def cluster(edge_u, edge_v, x_u, *, n_v, k, **kw):
     """Cluster the target nodes of one ABG given as device tensors
-    (edge_u/edge_v int32 [E], x_u float32 [n_u, d_u], optional edge_w float32).
+    (edge_u/edge_v int32 [E], x_u float32 or bfloat16 [n_u, d_u], optional edge_w float32).
     Returns (labels int32 [n_u], embedding float32 [n_u, k], (obj1, trace), stats)."""
     return cluster_sized(edge_u, edge_v, x_u, n_v=n_v, k=k, **kw)
 
@@ -329,10 +345,11 @@ def cluster_sized(edge_u, edge_v, x_u, *, n_v, k, alpha=0.5, gamma=5, d=0, q=20,
                   timing=False):
     import torch
     n_u, d_u = x_u.shape
+    xdt = "bf16" if str(x_u.dtype) == "torch.bfloat16" else "f32"
     plan = Plan.create(n_u, n_v, edge_u.numel(), d_u, device=x_u.device, k=k, alpha=alpha,
                        gamma=gamma, d=d, q=q, oversample=oversample, t_f=t_f, t_g=t_g, seed=seed,
                        weighted=edge_w is not None, timing=timing, omega_reduce=omega_reduce,
-                       g=g, omega=omega)
+                       g=g, omega=omega, x_dtype=xdt)
     try:
         labels = torch.empty(n_u, dtype=torch.int32, device=x_u.device)
         emb = torch.empty(n_u, k, dtype=torch.float32, device=x_u.device)

@@ -163,13 +163,170 @@ k_gram_reduce(const double* __restrict__ part, const double* __restrict__ colsum
   }
 }
 
-static void gram(const float* X, int64_t n, int c, int64_t ldx, int nchunks, double* part, double* colsum_part,
-                 double* G, double* colsum, hipStream_t s) {
+// The same partials for a bfloat16 X (the attribute precision form): BF16
+// MFMA 16x16x32 with FP32 accumulation (products of two BF16 values are
+// exact in FP32), each 64-row slab's FP32 sums added into FP64.  Slabs are
+// staged transposed in LDS (column-major, 72-element stride), so a lane's
+// eight consecutive rows of one column are one 16-byte read.  Operand
+// layout: lane l supplies A[l % 16][8 (l / 16) .. 8 (l / 16) + 7] and
+// B[8 (l / 16) ..][l % 16] (the same rows for both, so the contraction does
+// not depend on the order inside the instruction); result v of lane l is
+// D[4 (l / 16) + v][l % 16].  vec: X 16-byte aligned, ldx and c multiples of
+// 8 (eight columns per load); otherwise element loads.
+typedef float v4f_t __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf_t __attribute__((ext_vector_type(8)));
+typedef unsigned int v4u_t __attribute__((ext_vector_type(4)));
+constexpr int kGBLd = kGSub + 8;  // LDS stride (bf16 elements) of a staged column
+
+__global__ void __launch_bounds__(256)
+k_gram_part_bf16(const uint16_t* __restrict__ X, int64_t n, int c, int64_t ldx, int ntiles, int rows_per_chunk,
+                 int nchunks, int vec, double* __restrict__ part, double* __restrict__ colsum_part) {
+  __shared__ __align__(16) uint16_t At[kGT * kGBLd];
+  __shared__ __align__(16) uint16_t Bt[kGT * kGBLd];
+  __shared__ double csum[4][kGT];
+  // XCD-aware order: workgroups are dispatched to the eight XCDs in turn, so
+  // workgroup b runs on XCD b % 8; every tile pair of one row chunk is given
+  // to the same XCD, one after another, so that the chunk's rows are read
+  // from memory once per XCD and served to the other pairs from its L2.
+  const int npairs = ntiles * (ntiles + 1) / 2;
+  const int b = blockIdx.x;
+  const int xcd = b % 8, slot = b / 8;
+  const int per_xcd = (nchunks + 7) / 8;  // chunks of each XCD
+  const int chunk = (slot / npairs) + per_xcd * xcd;
+  int pi = slot % npairs, ti = 0;
+  if (chunk >= nchunks) return;  // uniform: the padding of the grid
+  while (pi >= ntiles - ti) {
+    pi -= ntiles - ti;
+    ++ti;
+  }
+  const int pair = slot % npairs;
+  const int tj = ti + pi;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int i16 = lane & 15, kq = lane >> 4;
+  const int qa = w >> 1, qb = w & 1;
+  const int64_t r_beg = static_cast<int64_t>(chunk) * rows_per_chunk;
+  const int64_t r_end = min(n, r_beg + rows_per_chunk);
+  const bool diag = ti == tj;
+  const uint16_t* Bp = diag ? At : Bt;
+  v4d_t acc[2][2];  // FP64 sums of the 2 x 2 tiles
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb) acc[a][bb] = v4d_t{0.0, 0.0, 0.0, 0.0};
+  double cs = 0.0;
+  // thread tid stages rows 2 (tid >> 3) and 2 (tid >> 3) + 1, columns
+  // 8 (tid & 7) ..: each column's two rows are one 32-bit LDS store
+  uint32_t ra[8], rb[8];
+  auto fetch = [&](int64_t r0) {
+    const int rr = 2 * (tid >> 3), cg = 8 * (tid & 7);
+    const int ca = ti * kGT + cg, cb = tj * kGT + cg;
+    uint16_t va[2][8], vb[2][8];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t row = r0 + rr + h;
+      if (vec) {
+        v4u_t ua = {0u, 0u, 0u, 0u}, ub = {0u, 0u, 0u, 0u};
+        if (row < r_end && ca < c) ua = *reinterpret_cast<const v4u_t*>(X + row * ldx + ca);
+        if (!diag && row < r_end && cb < c) ub = *reinterpret_cast<const v4u_t*>(X + row * ldx + cb);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          va[h][2 * e] = static_cast<uint16_t>(ua[e] & 0xffffu);
+          va[h][2 * e + 1] = static_cast<uint16_t>(ua[e] >> 16);
+          vb[h][2 * e] = static_cast<uint16_t>(ub[e] & 0xffffu);
+          vb[h][2 * e + 1] = static_cast<uint16_t>(ub[e] >> 16);
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          va[h][e] = (row < r_end && ca + e < c) ? X[row * ldx + ca + e] : uint16_t{0};
+          vb[h][e] = (!diag && row < r_end && cb + e < c) ? X[row * ldx + cb + e] : uint16_t{0};
+        }
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      ra[e] = static_cast<uint32_t>(va[0][e]) | (static_cast<uint32_t>(va[1][e]) << 16);
+      rb[e] = static_cast<uint32_t>(vb[0][e]) | (static_cast<uint32_t>(vb[1][e]) << 16);
+    }
+  };
+  if (r_beg < r_end) fetch(r_beg);
+  for (int64_t r0 = r_beg; r0 < r_end; r0 += kGSub) {
+    {
+      const int rr = 2 * (tid >> 3), cg = 8 * (tid & 7);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        *reinterpret_cast<uint32_t*>(At + (cg + e) * kGBLd + rr) = ra[e];
+        if (!diag) *reinterpret_cast<uint32_t*>(Bt + (cg + e) * kGBLd + rr) = rb[e];
+      }
+    }
+    __syncthreads();
+    if (r0 + kGSub < r_end) fetch(r0 + kGSub);
+    v4f_t s32[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int bb = 0; bb < 2; ++bb) s32[a][bb] = v4f_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < kGSub / 32; ++ks) {
+      const int k0 = 32 * ks + 8 * kq;
+      v8bf_t av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        av[a] = __builtin_bit_cast(v8bf_t, *reinterpret_cast<const v4u_t*>(At + (32 * qa + 16 * a + i16) * kGBLd + k0));
+        bv[a] = __builtin_bit_cast(v8bf_t, *reinterpret_cast<const v4u_t*>(Bp + (32 * qb + 16 * a + i16) * kGBLd + k0));
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int bb = 0; bb < 2; ++bb)
+          s32[a][bb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[bb], s32[a][bb], 0, 0, 0);
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[a][bb][v] += static_cast<double>(s32[a][bb][v]);
+    if (diag && colsum_part) {
+      for (int rr = w; rr < kGSub; rr += 4)
+        cs += static_cast<double>(__uint_as_float(static_cast<uint32_t>(At[lane * kGBLd + rr]) << 16));
+    }
+    __syncthreads();
+  }
+  double* out = part + (static_cast<int64_t>(chunk) * npairs + pair) * kGT * kGT;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        out[(32 * qa + 16 * a + 4 * kq + v) * kGT + 32 * qb + 16 * bb + i16] = acc[a][bb][v];
+  if (diag && colsum_part) {
+    csum[w][lane] = cs;
+    __syncthreads();
+    if (tid < kGT) {
+      const double v = ((csum[0][tid] + csum[1][tid]) + csum[2][tid]) + csum[3][tid];
+      const int j = ti * kGT + tid;
+      if (j < c) colsum_part[static_cast<int64_t>(chunk) * c + j] = v;
+    }
+  }
+}
+
+static void gram(const void* X, bool bf16, int64_t n, int c, int64_t ldx, int nchunks, double* part,
+                 double* colsum_part, double* G, double* colsum, hipStream_t s) {
   const int ntiles = (c + kGT - 1) / kGT;
   const int npairs = ntiles * (ntiles + 1) / 2;
   const int rows_per_chunk = static_cast<int>((n + nchunks - 1) / nchunks);
-  hipLaunchKernelGGL(k_gram_part, dim3(npairs, nchunks), dim3(256), 0, s, X, n, c, ldx, ntiles, rows_per_chunk,
-                     part, colsum_part);
+  if (bf16) {
+    const int vec = (reinterpret_cast<uintptr_t>(X) % 16 == 0 && ldx % 8 == 0 && c % 8 == 0) ? 1 : 0;
+    const int per_xcd = (nchunks + 7) / 8;
+    hipLaunchKernelGGL(k_gram_part_bf16, dim3(8 * per_xcd * npairs), dim3(256), 0, s,
+                       static_cast<const uint16_t*>(X), n, c, ldx, ntiles, rows_per_chunk, nchunks, vec, part,
+                       colsum_part);
+  } else {
+    hipLaunchKernelGGL(k_gram_part, dim3(npairs, nchunks), dim3(256), 0, s, static_cast<const float*>(X), n, c, ldx,
+                       ntiles, rows_per_chunk, part, colsum_part);
+  }
   TPO_LAUNCH_CHECK();
   const int64_t outs = std::max<int64_t>(static_cast<int64_t>(npairs) * kGT * kGT, c);
   hipLaunchKernelGGL(k_gram_reduce, dim3(ceil_div(outs, 256)), dim3(256), 0, s, part, colsum_part, nchunks, c,
@@ -409,14 +566,20 @@ k_embed_small(const double* __restrict__ K, const double* __restrict__ Omega, in
 // B[l / 16][l % 16]; its v-th result is D[4 (l / 16) + v][l % 16]).  A
 // workgroup takes 64 rows; wave w owns rows 16 w.. and all CT column tiles.
 // 32-column slabs of X and the matching rows of Psi_d are staged in LDS.
-typedef float v4f_t __attribute__((ext_vector_type(4)));
 constexpr int kPjRows = 64;
 constexpr int kPjK = 32;
 constexpr int kPjXLd = kPjK + 1;
 
-template <int CT>
+// An attribute as FP32: FP32 X as is, bfloat16 X (raw 16 bits) widened
+// exactly.
+__device__ __forceinline__ float x_at(const float* X, int64_t i) { return X[i]; }
+__device__ __forceinline__ float x_at(const uint16_t* X, int64_t i) {
+  return __uint_as_float(static_cast<uint32_t>(X[i]) << 16);
+}
+
+template <int CT, typename XT>
 __global__ void __launch_bounds__(256)
-k_project_mfma(const float* __restrict__ X, int64_t n, int du, int64_t ldx, const float* __restrict__ psi32, int dp,
+k_project_mfma(const XT* __restrict__ X, int64_t n, int du, int64_t ldx, const float* __restrict__ psi32, int dp,
                float* __restrict__ out, int32_t* __restrict__ err_bits) {
   constexpr int PLD = 16 * CT + 4;
   __shared__ float xs[kPjRows * kPjXLd];
@@ -434,7 +597,7 @@ k_project_mfma(const float* __restrict__ X, int64_t n, int du, int64_t ldx, cons
       const int e = tid + 256 * u;
       const int rr = e / kPjK, kk = e % kPjK;
       const int64_t row = row0 + rr;
-      float v = (row < n && k0 + kk < du) ? X[row * ldx + k0 + kk] : 0.0f;
+      float v = (row < n && k0 + kk < du) ? x_at(X, row * ldx + k0 + kk) : 0.0f;
       if (!isfinite(v)) {
         bad = true;
         v = 0.0f;
@@ -467,13 +630,14 @@ k_project_mfma(const float* __restrict__ X, int64_t n, int du, int64_t ldx, cons
   }
 }
 
-__global__ void k_pad_copy(const float* __restrict__ X, int64_t n, int du, int64_t ldx, int dp,
+template <typename XT>
+__global__ void k_pad_copy(const XT* __restrict__ X, int64_t n, int du, int64_t ldx, int dp,
                            float* __restrict__ out, int32_t* __restrict__ err_bits) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n * dp) return;
   const int64_t r = i / dp;
   const int c = static_cast<int>(i % dp);
-  float v = c < du ? X[r * ldx + c] : 0.0f;
+  float v = c < du ? x_at(X, r * ldx + c) : 0.0f;
   if (!isfinite(v)) {
     atomicOr(err_bits, 4);
     v = 0.0f;
@@ -481,18 +645,37 @@ __global__ void k_pad_copy(const float* __restrict__ X, int64_t n, int du, int64
   out[i] = v;
 }
 
-void launch_reduce(const Plan& p, void* ws, const float* x, int64_t ldx, hipStream_t s) {
+template <typename XT>
+static void project(const Plan& p, const XT* x, int64_t ldx, const float* psi32, float* xp, int32_t* err, hipStream_t s) {
+  const dim3 grid(ceil_div(p.n, kPjRows));
+  const int64_t n = p.n;
+  switch ((p.dp + 15) / 16) {
+    case 1: hipLaunchKernelGGL((k_project_mfma<1, XT>), grid, dim3(256), 0, s, x, n, p.du, ldx, psi32, p.dp, xp, err); break;
+    case 2: hipLaunchKernelGGL((k_project_mfma<2, XT>), grid, dim3(256), 0, s, x, n, p.du, ldx, psi32, p.dp, xp, err); break;
+    case 4: hipLaunchKernelGGL((k_project_mfma<4, XT>), grid, dim3(256), 0, s, x, n, p.du, ldx, psi32, p.dp, xp, err); break;
+    case 8: hipLaunchKernelGGL((k_project_mfma<8, XT>), grid, dim3(256), 0, s, x, n, p.du, ldx, psi32, p.dp, xp, err); break;
+    default: hipLaunchKernelGGL((k_project_mfma<16, XT>), grid, dim3(256), 0, s, x, n, p.du, ldx, psi32, p.dp, xp, err); break;
+  }
+  TPO_LAUNCH_CHECK();
+}
+
+void launch_reduce(const Plan& p, void* ws, const void* x, int64_t ldx, hipStream_t s) {
   DevStatus* st = bufp<DevStatus>(p, ws, B_STATUS);
   float* xp = bufp<float>(p, ws, B_XPRIME);
   if (!p.reduce) {
-    hipLaunchKernelGGL(k_pad_copy, dim3(ceil_div(static_cast<int64_t>(p.n) * p.dp, 256)), dim3(256), 0, s, x,
-                       static_cast<int64_t>(p.n), p.du, ldx, p.dp, xp, &st->err_bits);
+    const dim3 g(ceil_div(static_cast<int64_t>(p.n) * p.dp, 256));
+    if (p.xbf16)
+      hipLaunchKernelGGL(k_pad_copy<uint16_t>, g, dim3(256), 0, s, static_cast<const uint16_t*>(x),
+                         static_cast<int64_t>(p.n), p.du, ldx, p.dp, xp, &st->err_bits);
+    else
+      hipLaunchKernelGGL(k_pad_copy<float>, g, dim3(256), 0, s, static_cast<const float*>(x),
+                         static_cast<int64_t>(p.n), p.du, ldx, p.dp, xp, &st->err_bits);
     TPO_LAUNCH_CHECK();
     return;
   }
   double* C = bufp<double>(p, ws, B_C);
   double* colsum = bufp<double>(p, ws, B_COLSUM_X);
-  gram(x, p.n, p.du, ldx, p.gram_chunks_x, bufp<double>(p, ws, B_GRAM_PART), bufp<double>(p, ws, B_COLSUM_PART), C,
+  gram(x, p.xbf16, p.n, p.du, ldx, p.gram_chunks_x, bufp<double>(p, ws, B_GRAM_PART), bufp<double>(p, ws, B_COLSUM_PART), C,
        colsum, s);
   double* ma = bufp<double>(p, ws, B_MR_A);
   double* mb = bufp<double>(p, ws, B_MR_B);
@@ -520,17 +703,11 @@ void launch_reduce(const Plan& p, void* ws, const float* x, int64_t ldx, hipStre
                        bufp<double>(p, ws, B_EVAL), bufp<double>(p, ws, B_PSI_D), bufp<float>(p, ws, B_PSI_D32));
     TPO_LAUNCH_CHECK();
   }
-  const dim3 grid(ceil_div(p.n, kPjRows));
   const float* psi32 = bufp<float>(p, ws, B_PSI_D32);
-  const int64_t n = p.n;
-  switch ((p.dp + 15) / 16) {
-    case 1: hipLaunchKernelGGL((k_project_mfma<1>), grid, dim3(256), 0, s, x, n, p.du, ldx, psi32, p.dp, xp, &st->err_bits); break;
-    case 2: hipLaunchKernelGGL((k_project_mfma<2>), grid, dim3(256), 0, s, x, n, p.du, ldx, psi32, p.dp, xp, &st->err_bits); break;
-    case 4: hipLaunchKernelGGL((k_project_mfma<4>), grid, dim3(256), 0, s, x, n, p.du, ldx, psi32, p.dp, xp, &st->err_bits); break;
-    case 8: hipLaunchKernelGGL((k_project_mfma<8>), grid, dim3(256), 0, s, x, n, p.du, ldx, psi32, p.dp, xp, &st->err_bits); break;
-    default: hipLaunchKernelGGL((k_project_mfma<16>), grid, dim3(256), 0, s, x, n, p.du, ldx, psi32, p.dp, xp, &st->err_bits); break;
-  }
-  TPO_LAUNCH_CHECK();
+  if (p.xbf16)
+    project(p, static_cast<const uint16_t*>(x), ldx, psi32, xp, &st->err_bits, s);
+  else
+    project(p, static_cast<const float*>(x), ldx, psi32, xp, &st->err_bits, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -785,7 +962,7 @@ void launch_features(const Plan& p, void* ws, hipStream_t s) {
 void launch_embed(const Plan& p, void* ws, hipStream_t s) {
   DevStatus* st = bufp<DevStatus>(p, ws, B_STATUS);
   double* K = bufp<double>(p, ws, B_K);
-  gram(bufp<float>(p, ws, B_R), p.n, p.twod, p.twod, p.gram_chunks_r, bufp<double>(p, ws, B_GRAM_PART), nullptr,
+  gram(bufp<float>(p, ws, B_R), false, p.n, p.twod, p.twod, p.gram_chunks_r, bufp<double>(p, ws, B_GRAM_PART), nullptr,
        K, nullptr, s);
   if (p.kp <= kWideMaxN) {
     // q products with K, each followed by Cholesky QR, then P = K M

@@ -282,6 +282,7 @@ tpo_status tpo_plan_create(const tpo_problem* prob, const tpo_params* par, tpo_p
   if (prob->abi_version != TPO_ABI_VERSION || par->abi_version != TPO_ABI_VERSION) return TPO_EINVAL;
   if (prob->n_u < 1 || prob->n_v < 1 || prob->n_edges < 0 || prob->n_edges >= (int64_t{1} << 31)) return TPO_EINVAL;
   if (prob->d_u < 1 || prob->d_u > kMaxDu) return TPO_EINVAL;
+  if (prob->x_dtype != TPO_X_F32 && prob->x_dtype != TPO_X_BF16) return TPO_EINVAL;
   if (par->k < 1 || par->k > kMaxK) return TPO_EINVAL;
   if (!(par->alpha >= 0.0 && par->alpha < 1.0)) return TPO_EINVAL;
   if (par->gamma < 0 || par->gamma > 1000 || par->q < 0 || par->q > 100) return TPO_EINVAL;
@@ -300,6 +301,7 @@ tpo_status tpo_plan_create(const tpo_problem* prob, const tpo_params* par, tpo_p
   p->du = prob->d_u;
   p->E = prob->n_edges;
   p->reduce = reduce;
+  p->xbf16 = prob->x_dtype == TPO_X_BF16;
   p->d = d;
   p->dp = next_pow2_at_least(d, 16);
   p->k = par->k;

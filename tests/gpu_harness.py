@@ -14,8 +14,9 @@ def log(*a):
 
 
 def gpu_run(abg, *, k, alpha, gamma, d, q=20, oversample=10, t_f=5, t_g=20, seed=0,
-            mm=None, stages=True, device="cuda:0"):
-    """Runs the job on the GPU.  Returns a dict of numpy intermediates."""
+            mm=None, stages=True, device="cuda:0", x_bf16=False):
+    """Runs the job on the GPU.  Returns a dict of numpy intermediates.
+    x_bf16: hand X over as bfloat16 (its values must be representable)."""
     import torch
 
     import paper_2405_11922_amd as tpo
@@ -24,6 +25,10 @@ def gpu_run(abg, *, k, alpha, gamma, d, q=20, oversample=10, t_f=5, t_g=20, seed
     eu = torch.from_numpy(np.ascontiguousarray(abg.edge_u, dtype=np.int32)).to(dev)
     ev = torch.from_numpy(np.ascontiguousarray(abg.edge_v, dtype=np.int32)).to(dev)
     x = torch.from_numpy(np.ascontiguousarray(abg.x_u, dtype=np.float32)).to(dev)
+    if x_bf16:
+        xb = x.to(torch.bfloat16)
+        assert torch.equal(xb.float(), x), "X is not representable in bfloat16"
+        x = xb
     ew = None
     if abg.edge_w is not None:
         ew = torch.from_numpy(np.ascontiguousarray(abg.edge_w, dtype=np.float32)).to(dev)
@@ -32,7 +37,8 @@ def gpu_run(abg, *, k, alpha, gamma, d, q=20, oversample=10, t_f=5, t_g=20, seed
         kw = dict(omega_reduce=mm.omega_reduce, g=mm.g, omega=mm.omega)
     plan = tpo.Plan.create(abg.n_u, abg.n_v, abg.n_edges, abg.d_u, device=dev, k=k, alpha=alpha,
                            gamma=gamma, d=d, q=q, oversample=oversample, t_f=t_f, t_g=t_g,
-                           seed=seed, weighted=ew is not None, timing=True, **kw)
+                           seed=seed, weighted=ew is not None, timing=True,
+                           x_dtype="bf16" if x_bf16 else "f32", **kw)
     out = {}
     try:
         h, ws = plan.handle, plan.workspace

@@ -80,3 +80,31 @@ def test_plan_create_rejects_bad_shapes(shape):
 def test_status_strings():
     assert tpo.tpo_status_string(0) == "ok"
     assert tpo.tpo_status_string(3) == "workspace too small"
+
+
+def test_attribute_dtype_checked():
+    """x_dtype must be TPO_X_F32 (0) or TPO_X_BF16 (1); the binding refuses
+    other names and a tensor whose dtype is not the plan's."""
+    import ctypes as C
+
+    import torch
+
+    lib = tpo.load_library()
+    par = tpo.TpoParams(tpo.TPO_ABI_VERSION, 5, 0.5, 3, 0, 20, 10, 5, 20, 0, 0, None, None, None)
+    for xdt, want in ((0, 0), (1, 0), (2, 1), (-1, 1)):
+        prob = tpo.TpoProblem(tpo.TPO_ABI_VERSION, 100, 100, 32, 500, 0, xdt)
+        h = C.c_void_p()
+        st = lib.tpo_plan_create(C.byref(prob), C.byref(par), C.byref(h))
+        assert st == want, (xdt, st)
+        if st == 0:
+            lib.tpo_plan_destroy(h)
+    with pytest.raises(tpo.TpoError) as e:
+        tpo.tpo_plan_create(100, 100, 500, 32, k=5, alpha=0.5, gamma=3, x_dtype="fp8")
+    assert e.value.status == 1
+    h = tpo.tpo_plan_create(100, 100, 500, 32, k=5, alpha=0.5, gamma=3, x_dtype="bf16")
+    try:
+        with pytest.raises(tpo.TpoError) as e:
+            tpo.tpo_stage_reduce(h, None, None, torch.zeros(100, 32, dtype=torch.float32), None)
+        assert e.value.status == 1
+    finally:
+        tpo.tpo_plan_destroy(h)

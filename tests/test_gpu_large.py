@@ -13,7 +13,9 @@ checked through what holds at any size:
 * Gamma has orthonormal columns and R^T Gamma = Psi Sigma;
 * the NCI labels are the oracle's NCI run on the device's Upsilon, and the
   objective is the oracle's objective of the device's labels on the device's R.
-The input is drawn on the GPU (abg_synth.planted_abg_device).
+The input is drawn on the GPU (abg_synth.planted_abg_device).  The job runs
+twice: with X in FP32, and in the precision form with X stored as bfloat16
+(the BF16 MFMA Gram); the checks take X at the precision the job saw.
 """
 import math
 
@@ -33,7 +35,8 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def test_large_workload_properties():
+@pytest.mark.parametrize("x_dtype", ["f32", "bf16"])
+def test_large_workload_properties(x_dtype):
     import time
 
     import torch
@@ -48,14 +51,17 @@ def test_large_workload_properties():
                                                sigma=shape.sigma, in_out_ratio=shape.in_out_ratio,
                                                max_degree=shape.max_degree, seed=0)
     torch.cuda.synchronize()
-    log(f"[large] generated n_u={n} n_v={m} E={E} d_u={shape.d_u} in {time.time() - t0:.1f}s")
+    log(f"[large {x_dtype}] generated n_u={n} n_v={m} E={E} d_u={shape.d_u} in {time.time() - t0:.1f}s")
+    if x_dtype == "bf16":
+        x = x.to(torch.bfloat16)
     plan = tpo.Plan.create(n, m, E, shape.d_u, device=dev, k=k, alpha=shape.alpha, gamma=shape.gamma, d=shape.d,
-                           q=shape.q, oversample=shape.oversample, t_f=shape.t_f, t_g=shape.t_g, seed=0)
+                           q=shape.q, oversample=shape.oversample, t_f=shape.t_f, t_g=shape.t_g, seed=0,
+                           x_dtype=x_dtype)
     labels = torch.empty(n, dtype=torch.int32, device=dev)
     t0 = time.time()
     obj = tpo.tpo_execute(plan.handle, eu, ev, x, plan.workspace, labels)
     torch.cuda.synchronize()
-    log(f"[large] tpo_execute {1e3 * (time.time() - t0):.1f} ms, objective {obj[0]:.6g}")
+    log(f"[large {x_dtype}] tpo_execute {1e3 * (time.time() - t0):.1f} ms, objective {obj[0]:.6g}")
     st = tpo.tpo_plan_stats(plan.handle)
     assert st["n_unique_edges"] == E
 
@@ -74,7 +80,7 @@ def test_large_workload_properties():
     assert int(rp[0]) == 0 and torch.equal(rp[1:], torch.cumsum(cnt, 0))
     assert torch.equal(buf("col_v")[:E].long(), key % n)
     del key, cnt, rp
-    log("[large] CSR of B_U and B_U^T exact")
+    log(f"[large {x_dtype}] CSR of B_U and B_U^T exact")
 
     rng = np.random.default_rng(1)
     su = np.sort(rng.choice(n, SAMPLE, replace=False))
@@ -87,7 +93,7 @@ def test_large_workload_properties():
     xs = x[torch.from_numpy(su).to(dev)].double().cpu().numpy()
     xp = buf("xprime")[torch.from_numpy(su).to(dev)].cpu().numpy()[:, :d]
     e_xp = _rel(xp, xs @ psi)
-    log(f"[large] Psi_d orthonormal; X' on sampled rows rel err {e_xp:.2e}")
+    log(f"[large {x_dtype}] Psi_d orthonormal; X' on sampled rows rel err {e_xp:.2e}")
     assert e_xp < 2e-5
 
     # last hop of the propagation, from the device's own W and T
@@ -114,7 +120,7 @@ def test_large_workload_properties():
         ref = (1.0 - alpha) * (buf("xprime")[int(u)].double().cpu().numpy() + alpha * scu[u] * acc)
         got = z[int(u)].double().cpu().numpy()
         e_z = max(e_z, float(np.max(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-30)))
-    log(f"[large] last hop on sampled rows: T rel err {e_t:.2e}, Z rel err {e_z:.2e}")
+    log(f"[large {x_dtype}] last hop on sampled rows: T rel err {e_t:.2e}, Z rel err {e_z:.2e}")
     assert e_t < 1e-5 and e_z < 1e-5
 
     # random features: sampled rows, and r over all rows (FP64 on the GPU)
@@ -135,7 +141,7 @@ def test_large_workload_properties():
     ref = (rp_ / torch.sqrt(rp_ @ torch.from_numpy(rsum).to(dev))[:, None]).cpu().numpy()
     R = buf("r")
     e_rr = _rel(R[torch.from_numpy(su).to(dev)].double().cpu().numpy(), ref)
-    log(f"[large] features: r rel err {e_r:.2e}, sampled R rel err {e_rr:.2e}")
+    log(f"[large {x_dtype}] features: r rel err {e_r:.2e}, sampled R rel err {e_rr:.2e}")
     assert e_r < 1e-6 and e_rr < 2e-5
 
     # embedding: orthonormal Gamma and R^T Gamma = Psi Sigma (FP64 on the GPU)
@@ -150,7 +156,7 @@ def test_large_workload_properties():
     psi_e = buf("psi").cpu().numpy()
     e_o = float(np.max(np.abs(gtg.cpu().numpy() - np.eye(k))))
     e_b = _rel(rtg.cpu().numpy(), psi_e * sig[None, :])
-    log(f"[large] embedding: |Gamma^T Gamma - I| {e_o:.2e}, R^T Gamma vs Psi Sigma rel {e_b:.2e}")
+    log(f"[large {x_dtype}] embedding: |Gamma^T Gamma - I| {e_o:.2e}, R^T Gamma vs Psi Sigma rel {e_b:.2e}")
     assert e_o < 1e-4 and e_b < 1e-4
     assert np.all(np.diff(sig) <= 1e-12 * sig[0])
 
@@ -160,11 +166,11 @@ def test_large_workload_properties():
     t0 = time.time()
     lab_ref, _ = oracle.nci(ups, shape.t_g)
     lab = labels.cpu().numpy()
-    log(f"[large] oracle NCI on device Upsilon in {time.time() - t0:.1f}s")
+    log(f"[large {x_dtype}] oracle NCI on device Upsilon in {time.time() - t0:.1f}s")
     assert np.array_equal(lab, lab_ref)
     o, tr = oracle.objective(R.cpu().numpy(), lab, k)
     rel = abs(obj[0] - o) / abs(o)
     rel_t = abs(obj[1] - tr) / abs(tr)
-    log(f"[large] objective vs oracle objective of device labels: {rel:.2e} / {rel_t:.2e}")
+    log(f"[large {x_dtype}] objective vs oracle objective of device labels: {rel:.2e} / {rel_t:.2e}")
     assert rel < 1e-9 and rel_t < 1e-9
     plan.close()
