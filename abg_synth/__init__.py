@@ -368,3 +368,47 @@ def config_abg(shape: JobShape, seed: int = 0) -> ABG:
                        zipf_a=shape.zipf_a, sigma=shape.sigma,
                        in_out_ratio=shape.in_out_ratio,
                        max_degree=shape.max_degree, seed=seed)
+
+
+@dataclass(frozen=True)
+class ServingRequest:
+    """One request of the serving stream: its arrival time, the index of its
+    graph in the pool, and its method parameters."""
+
+    arrival: float
+    graph: int
+    k: int
+    d: int
+    params: dict
+
+
+def serving_stream(n_requests: int, rate: float, pool: int, seed: int = 0, *,
+                   n_min: int = 1_000, n_max: int = 500_000, deg=(10.0, 30.0), k_range=(2, 64),
+                   d_choices=(32, 128, 256)):
+    """The serving workload: Poisson arrivals at `rate` jobs/s of independent
+    planted-partition jobs.  Graph shapes: |U| log-uniform in [n_min, n_max],
+    |V| = 1.5 |U|, average degree uniform in `deg`, k uniform in k_range,
+    attribute width d_U from d_choices reduced to min(d_U, 64), 5 hops,
+    alpha 0.5.  `pool` distinct graphs are described (shapes and seeds);
+    requests draw one of them each.  Returns (shapes, requests): shapes[i] =
+    (n_u, n_v, n_edges, k, d_u, seed) of pool graph i."""
+    rng = np.random.default_rng(seed)
+    shapes = []
+    for i in range(pool):
+        n_u = int(round(math.exp(rng.uniform(math.log(n_min), math.log(n_max)))))
+        n_v = int(round(1.5 * n_u))
+        n_edges = int(round(n_u * rng.uniform(*deg)))
+        k = int(rng.integers(k_range[0], k_range[1] + 1))
+        d_u = int(rng.choice(d_choices))
+        shapes.append((n_u, n_v, n_edges, k, d_u, seed * 7919 + i))
+    t = 0.0
+    reqs = []
+    for _ in range(n_requests):
+        t += rng.exponential(1.0 / rate)
+        g = int(rng.integers(0, pool))
+        n_u, n_v, n_edges, k, d_u, _ = shapes[g]
+        d = min(d_u, 64)
+        params = dict(k=k, alpha=0.5, gamma=5, d=d if d < d_u else 0, q=20, oversample=10, t_f=5, t_g=20,
+                      seed=g)
+        reqs.append(ServingRequest(t, g, k, d, params))
+    return shapes, reqs

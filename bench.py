@@ -63,6 +63,68 @@ def counted_traffic(config: str, side: str):
     return int(1024 * (k["fetch_kib"] * rec["fetch_factor"] + k["write_kib"] * rec["write_factor"]))
 
 
+def run_serve(args) -> int:
+    """The serving workload: a Poisson stream of independent jobs of random
+    shape served with continuous batching (paper_2405_11922_amd.serve)."""
+    import torch
+
+    import abg_synth as synth
+    from paper_2405_11922_amd import serve
+
+    dev = torch.device("cuda:0")
+    shapes, reqs = synth.serving_stream(args.serve_jobs, args.serve_rate, args.serve_pool, seed=args.seed)
+    t0 = time.time()
+    graphs = []
+    for n_u, n_v, n_edges, k, d_u, gseed in shapes:
+        eu, ev, x, _, _ = synth.planted_abg_device(n_u, n_v, n_edges, k, d_u, device=dev, zipf_a=2.0, seed=gseed)
+        graphs.append((eu, ev, x.to(torch.bfloat16), n_v))
+    torch.cuda.synchronize()
+    log(f"[serve] {len(shapes)} pool graphs (|U| {min(s[0] for s in shapes)}..{max(s[0] for s in shapes)}, "
+        f"{sum(s[2] for s in shapes)} edges in all) drawn on the GPU in {time.time() - t0:.1f}s")
+    jobs = [serve.Job(i, r.arrival, *graphs[r.graph][:3], graphs[r.graph][3], r.params)
+            for i, r in enumerate(reqs)]
+    srv = serve.Server(device=dev, hbm_budget=args.serve_hbm_gb << 30, workers=args.serve_workers)
+    warm = [serve.Job(-1 - i, 0.0, *graphs[g][:3], graphs[g][3], reqs[0].params | dict(k=2))
+            for i, g in enumerate(range(min(4, len(graphs))))]
+    srv.run(warm, realtime=False)
+    torch.cuda.synchronize()
+    t1 = time.time()
+    res = srv.run(jobs, realtime=True)
+    torch.cuda.synchronize()
+    wall = time.time() - t1
+    summ = serve.summarize(res)
+    log(f"[serve] {summ['jobs']} jobs ({summ['failed']} failed) in {wall:.2f}s: {summ.get('jobs_per_s', 0):.1f} jobs/s, "
+        f"p50 {summ.get('p50_ms', 0):.2f} ms, p99 {summ.get('p99_ms', 0):.2f} ms; queueing p50 "
+        f"{summ.get('queue_p50_ms', 0):.2f} ms, inside tpo_execute p50 {summ.get('exec_p50_ms', 0):.2f} ms "
+        f"(mean {summ.get('exec_mean_ms', 0):.2f})")
+    result = {
+        "metric": "clusterings/s served (continuous batching) and p50/p99 job latency",
+        "value": round(summ["jobs_per_s"], 3) if summ.get("jobs_per_s") else None,
+        "unit": "clusterings/s",
+        "n_gpus": 1,
+        "steps": summ["jobs"],
+        "warmup": len(warm),
+        "ms_per_step": round(1e3 / summ["jobs_per_s"], 4) if summ.get("jobs_per_s") else None,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16 attributes, f32 path",
+        "data": "synthetic",
+        "config": {
+            "workload": f"serve: Poisson arrivals at {args.serve_rate} jobs/s, {args.serve_jobs} jobs drawn from "
+                        f"{args.serve_pool} planted-partition graphs, |U| log-uniform in [1e3, 5e5], |V| = 1.5|U|, "
+                        f"average degree 10-30, k in [2, 64], d_U in {{32, 128, 256}} bfloat16 -> min(d_U, 64), "
+                        f"gamma 5, alpha 0.5; {args.serve_workers} concurrent jobs, "
+                        f"{args.serve_hbm_gb} GiB workspace budget",
+        },
+        "latency_ms": {"p50": round(summ["p50_ms"], 4), "p99": round(summ["p99_ms"], 4),
+                       "mean": round(summ["mean_ms"], 4), "max": round(summ["max_ms"], 4)},
+        "failed": summ["failed"],
+    }
+    print(json.dumps(result), flush=True)
+    return 0 if summ["failed"] == 0 else 1
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,6 +133,11 @@ def main() -> int:
     ap.add_argument("--config", default="mid_fp32")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-baseline", default="on", choices=["on", "off"])
+    ap.add_argument("--serve-jobs", type=int, default=2000)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-pool", type=int, default=32)
+    ap.add_argument("--serve-workers", type=int, default=4)
+    ap.add_argument("--serve-hbm-gb", type=int, default=64)
     ap.add_argument("--x-dtype", default="auto", choices=["auto", "f32", "bf16"],
                     help="attribute storage: auto = bf16 for the large precision form, f32 otherwise")
     ap.add_argument("--compare-f32", action="store_true",
@@ -84,6 +151,10 @@ def main() -> int:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(independent jobs shard by job across GPUs; see the design notes)", file=sys.stderr)
         return 2
+    if args.config == "serve":
+        # one hardware queue per worker stream, so that concurrent jobs do not
+        # wait behind each other in a shared queue (read when HIP starts)
+        os.environ["GPU_MAX_HW_QUEUES"] = str(max(4, min(16, args.serve_workers)))
 
     import numpy as np
     import torch
@@ -95,6 +166,8 @@ def main() -> int:
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
+    if args.config == "serve":
+        return run_serve(args)
     shape = synth.CONFIGS[args.config]
     dev = torch.device("cuda:0")
     t0 = time.time()

@@ -89,6 +89,9 @@ typedef struct tpo_params {
 } tpo_params;
 
 #define TPO_FLAG_TIMING 1 /* record per-stage device times (tpo_plan_stats) */
+#define TPO_FLAG_ONE_STREAM 2 /* run everything on the caller's stream: no
+                                 plan-owned second stream for ingest (for
+                                 callers that overlap many jobs instead) */
 
 /* Inputs of one job (device memory unless stated). */
 typedef struct tpo_inputs {

@@ -24,6 +24,7 @@ __all__ = [
 
 TPO_ABI_VERSION = 1
 TPO_FLAG_TIMING = 1
+TPO_FLAG_ONE_STREAM = 2
 _HERE = os.path.dirname(os.path.abspath(__file__))
 lib_path = os.path.join(_HERE, "libtpo.so")
 
@@ -157,7 +158,7 @@ _PLAN_XDT = {}  # plan handle -> x_dtype name, to check the tensors handed over
 
 
 def tpo_plan_create(n_u, n_v, n_edges, d_u, *, k, alpha, gamma, d=0, q=20, oversample=10,
-                    t_f=5, t_g=20, seed=0, weighted=False, timing=False,
+                    t_f=5, t_g=20, seed=0, weighted=False, timing=False, one_stream=False,
                     omega_reduce=None, g=None, omega=None, x_dtype="f32"):
     """Returns an opaque plan handle (int).  x_dtype: "f32" or "bf16" (X_U's
     element type)."""
@@ -168,7 +169,7 @@ def tpo_plan_create(n_u, n_v, n_edges, d_u, *, k, alpha, gamma, d=0, q=20, overs
                       X_DTYPES[x_dtype])
     keep = [_dptr(omega_reduce), _dptr(g), _dptr(omega)]
     par = TpoParams(TPO_ABI_VERSION, int(k), float(alpha), int(gamma), int(d), int(q), int(oversample),
-                    int(t_f), int(t_g), TPO_FLAG_TIMING if timing else 0, int(seed) & ((1 << 64) - 1),
+                    int(t_f), int(t_g), (TPO_FLAG_TIMING if timing else 0) | (TPO_FLAG_ONE_STREAM if one_stream else 0), int(seed) & ((1 << 64) - 1),
                     keep[0][1] if keep[0] else None, keep[1][1] if keep[1] else None,
                     keep[2][1] if keep[2] else None)
     h = C.c_void_p()

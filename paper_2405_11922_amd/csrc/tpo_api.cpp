@@ -551,8 +551,8 @@ tpo_status tpo_execute(tpo_plan* plan, const tpo_inputs* in, void* ws, size_t by
     };
     upload_inputs(plan, ws, s);
     mark(0);
-    if (timing) {
-      // stage by stage on one stream, so that each stage's time is its own
+    if (timing || (plan->par.flags & TPO_FLAG_ONE_STREAM)) {
+      // stage by stage on one stream (timing: so that each stage's time is its own)
       launch_ingest(*plan, ws, in, s);
       mark(1);
       launch_reduce(*plan, ws, in->x_u, in->ld_x, s);

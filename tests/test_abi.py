@@ -108,3 +108,51 @@ def test_attribute_dtype_checked():
         assert e.value.status == 1
     finally:
         tpo.tpo_plan_destroy(h)
+
+
+def test_serving_stream_recipe():
+    """The serving workload's generator: Poisson arrivals in order, shapes
+    within the recipe's ranges, k <= 2 d_eff for every request."""
+    shapes, reqs = synth.serving_stream(500, 200.0, 16, seed=3)
+    assert len(shapes) == 16 and len(reqs) == 500
+    arr = np.array([r.arrival for r in reqs])
+    assert np.all(np.diff(arr) > 0)
+    assert 1.5 < arr[-1] < 3.5  # 500 arrivals at 200/s
+    for n_u, n_v, e, k, d_u, _ in shapes:
+        assert 1_000 <= n_u <= 500_000 and n_v == round(1.5 * n_u)
+        assert 10 * n_u - 1 <= e <= 30 * n_u + 1
+        assert 2 <= k <= 64 and d_u in (32, 128, 256)
+    for r in reqs:
+        d_eff = r.d
+        assert r.k <= 2 * d_eff
+
+
+def test_serving_worker_cap():
+    from paper_2405_11922_amd import serve
+
+    with pytest.raises(ValueError):
+        serve.Server(device="cpu", workers=serve.MAX_WORKERS + 1).run([], realtime=False)
+
+
+def test_serving_pool_and_summary():
+    """The serving workspace pool (first fit, 256-byte aligned, merged on
+    release) and the latency summary, on the host."""
+    from paper_2405_11922_amd import serve
+
+    p = serve._Pool(10_000)
+    a, b, c = p.take(1000), p.take(3000), p.take(5000)
+    assert (a, b, c) == (0, 1024, 4096)
+    assert p.take(1000) is None  # 784 bytes left
+    p.give(b, 3000)
+    assert p.take(2000) == 1024
+    p.give(a, 1000)
+    p.give(c, 5000)
+    p.give(1024, 2000)
+    assert p.free == [(0, 10_000)]
+    res = [serve.Result(i, 0.1 * i, 0.1 * i, 0.1 * i + 0.02 + 0.001 * i, started=0.1 * i, exec_s=0.02)
+           for i in range(10)]
+    res.append(serve.Result(10, 1.0, 1.0, 1.0, error="workspace above the HBM budget"))
+    s = serve.summarize(res)
+    assert s["jobs"] == 10 and s["failed"] == 1
+    assert abs(s["p50_ms"] - 24.5) < 1e-6 and abs(s["exec_p50_ms"] - 20.0) < 1e-9
+    assert abs(s["jobs_per_s"] - 10 / (0.9 + 0.029)) < 1e-9

@@ -1,0 +1,96 @@
+"""Serving with continuous batching on the GPU: a job's result is the same
+when it runs alone and when it runs beside others, a job that does not fit
+the HBM budget is refused while the rest are served, and a served job
+matches the oracle."""
+import numpy as np
+import pytest
+
+import abg_synth as synth
+import oracle
+from tests.gpu_harness import log, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+
+def _jobs(serve, torch, dev):
+    shapes = [(2000, 3000, 30_000, 5, 32, "f32"), (6000, 9000, 120_000, 12, 128, "bf16"),
+              (3000, 4500, 60_000, 20, 256, "bf16"), (12000, 18000, 200_000, 40, 64, "f32"),
+              (1500, 2250, 20_000, 3, 32, "bf16"), (9000, 13500, 250_000, 64, 128, "bf16")]
+    jobs = []
+    for i, (n_u, n_v, e, k, d_u, xdt) in enumerate(shapes):
+        eu, ev, x, _, _ = synth.planted_abg_device(n_u, n_v, e, k, d_u, device=dev, seed=100 + i)
+        if xdt == "bf16":
+            x = x.to(torch.bfloat16)
+        d = min(d_u, 64)
+        params = dict(k=k, alpha=0.5, gamma=5, d=d if d < d_u else 0, q=20, oversample=10, t_f=5, t_g=20, seed=i)
+        jobs.append(serve.Job(i, 0.0, eu, ev, x, n_v, params))
+    return jobs
+
+
+def test_alone_equals_in_the_mix():
+    import torch
+
+    from paper_2405_11922_amd import serve
+
+    dev = torch.device("cuda:0")
+    jobs = _jobs(serve, torch, dev)
+    alone = {}
+    for j in jobs:
+        (r,) = serve.Server(device=dev, workers=1).run([j], realtime=False)
+        assert not r.error, r.error
+        alone[j.job_id] = r
+    mixed = serve.Server(device=dev, workers=8).run(jobs + jobs, realtime=False)
+    assert len(mixed) == 2 * len(jobs)
+    for r in mixed:
+        a = alone[r.job_id]
+        assert not r.error, r.error
+        assert torch.equal(r.labels, a.labels), r.job_id
+        assert r.objective == a.objective, (r.job_id, r.objective, a.objective)
+    log(f"[serve] {len(jobs)} jobs, each twice among eight concurrent workers: labels and objectives "
+        f"identical to the job alone; {serve.summarize(mixed)}")
+
+
+def test_admission_by_workspace():
+    import torch
+
+    from paper_2405_11922_amd import serve
+
+    dev = torch.device("cuda:0")
+    jobs = _jobs(serve, torch, dev)[:4]
+    srv = serve.Server(device=dev, workers=4)
+    sizes = [srv._plan(j) for j in jobs]
+    for h, _, _ in sizes:
+        import paper_2405_11922_amd as tpo
+
+        tpo.tpo_plan_destroy(h)
+    nbytes = [n for _, n, _ in sizes]
+    budget = sorted(nbytes)[-2]  # the largest job does not fit, the others run (one at a time at worst)
+    res = serve.Server(device=dev, workers=4, hbm_budget=budget).run(jobs, realtime=False)
+    big = int(np.argmax(nbytes))
+    for r in res:
+        if r.job_id == big:
+            assert r.error == "workspace above the HBM budget"
+        else:
+            assert not r.error, r.error
+
+
+def test_served_job_matches_oracle():
+    import torch
+
+    from paper_2405_11922_amd import serve
+
+    dev = torch.device("cuda:0")
+    abg = synth.planted_abg(3001, 4507, 40_000, 6, 96, zipf_a=2.0, seed=1)
+    kw = dict(k=6, alpha=0.5, gamma=4, d=24)
+    ref = oracle_run(abg, **kw)
+    mm = synth.method_matrices(0, abg.d_u, kw["d"], kw["k"], 10)
+    params = dict(kw, q=20, oversample=10, t_f=5, t_g=20, seed=0, omega_reduce=mm.omega_reduce, g=mm.g,
+                  omega=mm.omega)
+    eu = torch.from_numpy(np.ascontiguousarray(abg.edge_u, dtype=np.int32)).to(dev)
+    ev = torch.from_numpy(np.ascontiguousarray(abg.edge_v, dtype=np.int32)).to(dev)
+    x = torch.from_numpy(np.ascontiguousarray(abg.x_u, dtype=np.float32)).to(dev)
+    (r,) = serve.Server(device=dev, workers=2).run([serve.Job(0, 0.0, eu, ev, x, abg.n_v, params)],
+                                                   realtime=False)
+    assert not r.error, r.error
+    assert oracle.labels_match_up_to_permutation(r.labels.cpu().numpy(), ref.labels)
+    assert abs(r.objective[0] - ref.objective) / abs(ref.objective) < 1e-6
