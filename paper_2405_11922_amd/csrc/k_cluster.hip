@@ -470,8 +470,9 @@ k_nci_round(const float* __restrict__ U, int64_t n, int k, const long long* __re
   }
 }
 
-// k > 64: scoring and the label sums in two kernels (Phi for 128 labels
-// fills most of the LDS on its own).
+// k > 32: scoring and the label sums in two kernels (Phi for 128 labels
+// fills most of the LDS on its own; for k in 33..64 the one-kernel round
+// above needs a whole SIMD's registers per wave for its k scores).
 //
 // Scores on FP64 MFMA (v_mfma_f64_16x16x4f64: lane l supplies A[l % 16][l / 16]
 // and B[l / 16][l % 16], its v-th result is D[4 v + l / 16][l % 16]).  A wave
@@ -561,8 +562,8 @@ k_nci_score_mfma(const float* __restrict__ U, int64_t n, int k, const long long*
 // workgroup's rows [rb, rb + rows_per_block), written transposed (entry o at
 // part[o * gridDim.x + block]).  A wave takes 64 rows at a time and reads
 // them as one contiguous run of 64 k values, eight loads in flight per lane;
-// element e of the run is (row e / k, column e % k).  For k > 64 the 64 lanes
-// of one addition touch 64 distinct sums.
+// element e of the run is (row e / k, column e % k), tracked incrementally
+// (k > 32: a step of 64 elements crosses at most two row ends).
 constexpr int kNciAccBatch = 8;
 
 __global__ void __launch_bounds__(1024)
@@ -581,7 +582,7 @@ k_nci_accum_wide(const float* __restrict__ U, int64_t n, int k, const int32_t* _
     if (lane < nr) atomicAdd(reinterpret_cast<unsigned long long*>(&accl[k * k + lab]), 1ull);
     const float* src = U + r0 * k;
     const int total = nr * k;
-    int row = 0, col = lane;  // of element lane; k > 64 keeps col < k
+    int row = lane / k, col = lane - (lane / k) * k;  // of element lane
     for (int e0 = 0; e0 < total; e0 += 64 * kNciAccBatch) {
       float v[kNciAccBatch];
 #pragma unroll
@@ -597,6 +598,10 @@ k_nci_accum_wide(const float* __restrict__ U, int64_t n, int k, const int32_t* _
           atomicAdd(reinterpret_cast<unsigned long long*>(&accl[lr * k + col]),
                     static_cast<unsigned long long>(to_fixed(v[b], sft)));
         col += 64;
+        if (col >= k) {
+          col -= k;
+          ++row;
+        }
         if (col >= k) {
           col -= k;
           ++row;
@@ -636,11 +641,13 @@ static void nci_rounds_wide(const Plan& p, void* ws, hipStream_t s) {
   for (int t = 1; t <= rounds; ++t) {
     const long long* sm = t == 1 ? nullptr : sums;
     switch ((k + 15) / 16) {
+      case 3: nci_score_mfma<3>(U, n, k, sm, labels, st, s); break;
+      case 4: nci_score_mfma<4>(U, n, k, sm, labels, st, s); break;
       case 5: nci_score_mfma<5>(U, n, k, sm, labels, st, s); break;
       case 6: nci_score_mfma<6>(U, n, k, sm, labels, st, s); break;
       case 7: nci_score_mfma<7>(U, n, k, sm, labels, st, s); break;
       case 8: nci_score_mfma<8>(U, n, k, sm, labels, st, s); break;
-      default: throw std::runtime_error("NCI: k beyond 128");
+      default: throw std::runtime_error("NCI: k outside 33..128 on the two-kernel path");
     }
     if (t < p.par.t_g) {
       hipLaunchKernelGGL(k_nci_accum_wide, dim3(nb), dim3(1024), 0, s, U, n, k, labels, part, rpb, st);
@@ -678,11 +685,7 @@ void launch_nci(const Plan& p, void* ws, hipStream_t s) {
     case 2: nci_rounds<16>(p, ws, s); break;
     case 3: nci_rounds<24>(p, ws, s); break;
     case 4: nci_rounds<32>(p, ws, s); break;
-    case 5: nci_rounds<40>(p, ws, s); break;
-    case 6: nci_rounds<48>(p, ws, s); break;
-    case 7: nci_rounds<56>(p, ws, s); break;
-    case 8: nci_rounds<64>(p, ws, s); break;
-    default: nci_rounds_wide(p, ws, s); break;
+    default: nci_rounds_wide(p, ws, s); break;  // k > 32
   }
 }
 

@@ -46,6 +46,11 @@ CASES = {
     "k64": (lambda: synth.planted_abg(5000, 4000, 60_000, 64, 48, zipf_a=2.0, seed=8, sigma=0.5,
                                       in_out_ratio=30.0),
             dict(k=64, alpha=0.5, gamma=3, d=0)),
+    # k = 33: the narrowest two-kernel NCI (48-label MFMA tiles; one 64-element
+    # step of the label sums crosses two row ends)
+    "k33": (lambda: synth.planted_abg(4001, 3500, 50_000, 33, 40, zipf_a=2.0, seed=15, sigma=0.5,
+                                      in_out_ratio=30.0),
+            dict(k=33, alpha=0.5, gamma=3, d=0)),
     # k = 100 (the 150M-edge workload's k): wide NCI, eight-tile row pass,
     # sketch width 110 (the global-memory embedding path)
     "k100": (lambda: synth.planted_abg(8000, 6000, 120_000, 100, 64, zipf_a=2.0, seed=12, sigma=0.5,
