@@ -289,6 +289,28 @@ def planted_abg(n_u: int, n_v: int, n_edges: int, k: int, d_u: int, *,
                          max_degree_v=mdv))
 
 
+def planted_attributes(labels: np.ndarray, d: int, *, sigma: float = 1.5, seed: int = 0) -> np.ndarray:
+    """Attributes for nodes with the given planted clusters, by the recipe of
+    planted_abg (X = mu_c + sigma * eps, mu_c ~ N(0, I)) from a random stream
+    of their own: used for X_V when V is the target set."""
+    labels = np.asarray(labels)
+    rng = np.random.default_rng([seed, 0x5856])
+    k = int(labels.max()) + 1 if labels.size else 0
+    mu = rng.standard_normal((k, d))
+    x = mu[labels] + sigma * rng.standard_normal((labels.shape[0], d))
+    return x.astype(np.float32)
+
+
+def target_v(abg: ABG, x_v: np.ndarray) -> ABG:
+    """The same graph with V as the target set: the two sides exchanged
+    (every edge (u, v) read as (v, u)) and x_v as the target's attributes."""
+    if x_v.shape[0] != abg.n_v:
+        raise ValueError("x_v needs one row per node of V")
+    return ABG(abg.n_v, abg.n_u, abg.edge_v.copy(), abg.edge_u.copy(), np.ascontiguousarray(x_v, np.float32),
+               abg.labels_v, abg.labels_u, None if abg.edge_w is None else abg.edge_w.copy(),
+               meta=dict(abg.meta, target="V"))
+
+
 def planted_abg_device(n_u: int, n_v: int, n_edges: int, k: int, d_u: int, *, device,
                        zipf_a: float = 2.0, sigma: float = 1.5, in_out_ratio: float = 8.0,
                        max_degree: int | None = None, seed: int = 0):

@@ -161,6 +161,7 @@ def main() -> int:
 
     import abg_synth as synth
     import paper_2405_11922_amd as tpo
+    from paper_2405_11922_amd import quality
 
     tpo.load_library()
     if not torch.cuda.is_available():
@@ -173,11 +174,12 @@ def main() -> int:
     t0 = time.time()
     on_device = shape.n_edges > 20_000_000  # the host generator is too slow beyond this
     if on_device:
-        eu, ev, x, _, _ = synth.planted_abg_device(shape.n_u, shape.n_v, shape.n_edges, shape.k, shape.d_u,
+        eu, ev, x, truth, _ = synth.planted_abg_device(shape.n_u, shape.n_v, shape.n_edges, shape.k, shape.d_u,
                                                    device=dev, zipf_a=shape.zipf_a, sigma=shape.sigma,
                                                    in_out_ratio=shape.in_out_ratio, max_degree=shape.max_degree,
                                                    seed=args.seed)
         torch.cuda.synchronize()
+        truth = truth.cpu().numpy()
         abg = None
         abg_n_edges, abg_d_u = shape.n_edges, shape.d_u
     else:
@@ -185,6 +187,7 @@ def main() -> int:
         eu = torch.from_numpy(abg.edge_u).to(dev)
         ev = torch.from_numpy(abg.edge_v).to(dev)
         x = torch.from_numpy(abg.x_u).to(dev)
+        truth = abg.labels_u
         abg_n_edges, abg_d_u = abg.n_edges, abg.d_u
     log(f"[bench] generated {args.config} ({'on the GPU' if on_device else 'on the host'}): n_u={shape.n_u} "
         f"n_v={shape.n_v} E={abg_n_edges} d_u={abg_d_u} in {time.time() - t0:.1f}s")
@@ -277,7 +280,10 @@ def main() -> int:
         "stage_ms": {k[3:]: round(v, 4) for k, v in st.items() if k.startswith("ms_")},
         "roofline": roofline,
         "objective": obj[0],
+        # recovery of the planted clusters (ACC, NMI, ARI of the paper's quality tables)
+        "quality": {key: round(v, 6) for key, v in quality.report(truth, labels_np).items()},
     }
+    log(f"[bench] planted clusters recovered: {result['quality']}")
 
     if x_dtype == "bf16" and args.compare_f32:
         # the plain FP32 job on the same graph (X not rounded): how far the

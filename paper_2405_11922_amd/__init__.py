@@ -341,6 +341,15 @@ def cluster(edge_u, edge_v, x_u, *, n_v, k, **kw):
     return cluster_sized(edge_u, edge_v, x_u, n_v=n_v, k=k, **kw)
 
 
+def cluster_target_v(edge_u, edge_v, x_v, *, n_u, k, **kw):
+    """Cluster the nodes of V instead of U: the same graph read from the
+    other side (edge (u, v) taken as (v, u)), with x_v [n_v, d_V] as the
+    target's attributes.  The call passes edge_v as the target side's column
+    and edge_u as the other side's; nothing is copied.  Returns what cluster
+    returns, for the n_v nodes of V."""
+    return cluster_sized(edge_v, edge_u, x_v, n_v=n_u, k=k, **kw)
+
+
 def cluster_sized(edge_u, edge_v, x_u, *, n_v, k, alpha=0.5, gamma=5, d=0, q=20, oversample=10,
                   t_f=5, t_g=20, seed=0, edge_w=None, omega_reduce=None, g=None, omega=None,
                   timing=False):
