@@ -48,6 +48,7 @@ __all__ = [
     "onmf",
     "onmf_loss",
     "nci",
+    "polar_factor",
     "objective",
     "objective_bruteforce",
     "tpo",
@@ -373,14 +374,41 @@ def onmf_loss(r, ups, h) -> float:
 # ---------------------------------------------------------------------------
 # Algorithm 3: effective NCI generation (Eqs. ell-ast, Y-update, y-norm)
 # ---------------------------------------------------------------------------
-def nci(ups: np.ndarray, t_g: int):
+POLAR_REL_TOL = 1e-6
+
+
+def polar_factor(m: np.ndarray) -> np.ndarray:
+    """The orthogonal factor of M's polar decomposition, U V^T for the SVD
+    M = U S V^T: the orthogonal Phi that minimises ||A Phi - B||_F when
+    M = A^T B (orthogonal Procrustes).
+
+    Reading: when M is singular (an empty cluster leaves a zero column) the
+    factor is not unique; the partial isometry sum_{s_i > tol s_1} u_i v_i^T
+    (tol = POLAR_REL_TOL) is taken, which leaves the empty cluster's column
+    zero as the literal update does; M = 0 gives Phi = 0."""
+    m = np.asarray(m, dtype=np.float64)
+    u, sv, vt = np.linalg.svd(m)
+    if sv.size == 0 or sv[0] == 0.0:
+        return np.zeros_like(m)
+    keep = sv > POLAR_REL_TOL * sv[0]
+    return u[:, keep] @ vt[keep, :]
+
+
+def nci(ups: np.ndarray, t_g: int, variant: str = "literal"):
     """Phi = I; t_g times: l* = argmax_l (Ups Phi)[i, l] per row, Y one-hot,
-    columns of Y scaled to unit L2 norm, Phi <- Ups^T Y.
+    columns of Y scaled to unit L2 norm, Phi <- Ups^T Y (Algorithm 3, Eqs.
+    ell-ast, Y-update, y-norm).
+
+    variant "procrustes": Phi <- the polar factor of Ups^T Y instead, the
+    minimiser over orthogonal Phi of ||Ups Phi - Y|| that Section 3.4 says the
+    update solves (Ups^T Y itself is not orthogonal).
 
     Readings: ties go to the lowest cluster index (numpy.argmax); an empty
     column of Y stays zero; the labels are those of the last argmax; with
     t_g = 0 they are argmax of Ups itself.  Returns (labels int64, Phi).
     """
+    if variant not in ("literal", "procrustes"):
+        raise ValueError("variant is 'literal' or 'procrustes'")
     ups = np.asarray(ups, dtype=np.float64)
     n, k = ups.shape
     phi = np.eye(k)
@@ -394,6 +422,8 @@ def nci(ups: np.ndarray, t_g: int):
         scale[cnt > 0] = 1.0 / np.sqrt(cnt[cnt > 0])
         y *= scale[None, :]
         phi = ups.T @ y
+        if variant == "procrustes":
+            phi = polar_factor(phi)
     return labels.astype(np.int64), phi
 
 
@@ -465,7 +495,7 @@ class OracleResult:
 
 
 def tpo(n_u, n_v, edge_u, edge_v, x, *, k, alpha, gamma, g, omega,
-        omega_r=None, d=0, q=20, t_f=5, t_g=20, edge_w=None) -> OracleResult:
+        omega_r=None, d=0, q=20, t_f=5, t_g=20, edge_w=None, nci_variant="literal") -> OracleResult:
     """TPO(G, k): optional reduction (Section 3.2.1), Algorithm 1, Algorithm 2,
     Algorithm 3, and Eq. obj1 of the result."""
     import time
@@ -500,7 +530,7 @@ def tpo(n_u, n_v, edge_u, edge_v, x, *, k, alpha, gamma, g, omega,
     ups, h, hits = onmf(r, gam, sig, psi, t_f)
     times["onmf"] = time.perf_counter() - t0
     t0 = time.perf_counter()
-    labels, phi = nci(ups, t_g)
+    labels, phi = nci(ups, t_g, nci_variant)
     times["nci"] = time.perf_counter() - t0
     t0 = time.perf_counter()
     obj, tr = objective(r, labels, k)
