@@ -138,6 +138,8 @@ def main() -> int:
     ap.add_argument("--serve-pool", type=int, default=32)
     ap.add_argument("--serve-workers", type=int, default=4)
     ap.add_argument("--serve-hbm-gb", type=int, default=64)
+    ap.add_argument("--nci", default="literal", choices=["literal", "procrustes"],
+                    help="NCI Phi update: the printed Ups^T Y, or its orthogonal polar factor")
     ap.add_argument("--x-dtype", default="auto", choices=["auto", "f32", "bf16"],
                     help="attribute storage: auto = bf16 for the large precision form, f32 otherwise")
     ap.add_argument("--compare-f32", action="store_true",
@@ -199,7 +201,8 @@ def main() -> int:
             del x_f32
             x_f32 = None
     kw = dict(k=shape.k, alpha=shape.alpha, gamma=shape.gamma, d=shape.d, q=shape.q,
-              oversample=shape.oversample, t_f=shape.t_f, t_g=shape.t_g, seed=args.seed, x_dtype=x_dtype)
+              oversample=shape.oversample, t_f=shape.t_f, t_g=shape.t_g, seed=args.seed, x_dtype=x_dtype,
+              nci=args.nci)
     plan = tpo.Plan.create(shape.n_u, shape.n_v, abg_n_edges, abg_d_u, device=dev, timing=False, **kw)
     plan_t = tpo.Plan.create(shape.n_u, shape.n_v, abg_n_edges, abg_d_u, device=dev, timing=True, **kw)
     labels = torch.empty(shape.n_u, dtype=torch.int32, device=dev)
@@ -272,7 +275,7 @@ def main() -> int:
                         f"d_U={abg_d_u} -> d={d_eff}, gamma={shape.gamma}, alpha={shape.alpha}, "
                         f"q={shape.q}, T_f={shape.t_f}, T_g={shape.t_g}",
             "n_u": shape.n_u, "n_v": shape.n_v, "n_edges": abg_n_edges, "k": shape.k, "d_u": abg_d_u,
-            "d": d_eff, "k_prime": kp, "l_r": l_r, "gamma": shape.gamma, "x_dtype": x_dtype,
+            "d": d_eff, "k_prime": kp, "l_r": l_r, "gamma": shape.gamma, "x_dtype": x_dtype, "nci": args.nci,
         },
         "gedge_hop_per_s": round(gedge_hops, 3) if gedge_hops else None,
         "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 4),
@@ -321,7 +324,7 @@ def main() -> int:
             ref = oracle.tpo(abg.n_u, abg.n_v, abg.edge_u, abg.edge_v, abg.x_u, k=shape.k,
                              alpha=shape.alpha, gamma=shape.gamma, g=mm.g, omega=mm.omega,
                              omega_r=mm.omega_reduce, d=shape.d, q=shape.q, t_f=shape.t_f,
-                             t_g=shape.t_g)
+                             t_g=shape.t_g, nci_variant=args.nci)
             jobs += 1
             if time.perf_counter() - c0 >= 10.0 or jobs >= 3:
                 break

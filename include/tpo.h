@@ -92,6 +92,13 @@ typedef struct tpo_params {
 #define TPO_FLAG_ONE_STREAM 2 /* run everything on the caller's stream: no
                                  plan-owned second stream for ingest (for
                                  callers that overlap many jobs instead) */
+#define TPO_FLAG_NCI_PROCRUSTES 4 /* NCI (Algorithm 3) with Phi <- the orthogonal
+                                     polar factor of Ups^T Y, the minimiser over
+                                     orthogonal Phi of ||Ups Phi - Y||_F that
+                                     Section 3.4 describes, instead of the
+                                     printed Phi <- Ups^T Y; an empty cluster's
+                                     zero column stays zero (the polar factor
+                                     of the other columns) */
 
 /* Inputs of one job (device memory unless stated). */
 typedef struct tpo_inputs {

@@ -374,24 +374,23 @@ def onmf_loss(r, ups, h) -> float:
 # ---------------------------------------------------------------------------
 # Algorithm 3: effective NCI generation (Eqs. ell-ast, Y-update, y-norm)
 # ---------------------------------------------------------------------------
-POLAR_REL_TOL = 1e-6
-
-
 def polar_factor(m: np.ndarray) -> np.ndarray:
     """The orthogonal factor of M's polar decomposition, U V^T for the SVD
     M = U S V^T: the orthogonal Phi that minimises ||A Phi - B||_F when
     M = A^T B (orthogonal Procrustes).
 
-    Reading: when M is singular (an empty cluster leaves a zero column) the
-    factor is not unique; the partial isometry sum_{s_i > tol s_1} u_i v_i^T
-    (tol = POLAR_REL_TOL) is taken, which leaves the empty cluster's column
-    zero as the literal update does; M = 0 gives Phi = 0."""
+    Reading: an empty cluster leaves a zero column in M, and the factor is
+    then not unique; the polar factor of the nonzero columns is taken, with
+    the empty cluster's column zero (the partial isometry, which leaves that
+    column zero as the literal update does); M = 0 gives Phi = 0.  M is taken
+    to have full rank on its nonzero columns."""
     m = np.asarray(m, dtype=np.float64)
-    u, sv, vt = np.linalg.svd(m)
-    if sv.size == 0 or sv[0] == 0.0:
-        return np.zeros_like(m)
-    keep = sv > POLAR_REL_TOL * sv[0]
-    return u[:, keep] @ vt[keep, :]
+    phi = np.zeros_like(m)
+    nz = np.any(m != 0.0, axis=0)
+    if nz.any():
+        u, _, vt = np.linalg.svd(m[:, nz], full_matrices=False)
+        phi[:, nz] = u @ vt
+    return phi
 
 
 def nci(ups: np.ndarray, t_g: int, variant: str = "literal"):

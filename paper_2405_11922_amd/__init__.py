@@ -25,6 +25,8 @@ __all__ = [
 TPO_ABI_VERSION = 1
 TPO_FLAG_TIMING = 1
 TPO_FLAG_ONE_STREAM = 2
+TPO_FLAG_NCI_PROCRUSTES = 4
+NCI_VARIANTS = ("literal", "procrustes")
 _HERE = os.path.dirname(os.path.abspath(__file__))
 lib_path = os.path.join(_HERE, "libtpo.so")
 
@@ -159,7 +161,7 @@ _PLAN_XDT = {}  # plan handle -> x_dtype name, to check the tensors handed over
 
 def tpo_plan_create(n_u, n_v, n_edges, d_u, *, k, alpha, gamma, d=0, q=20, oversample=10,
                     t_f=5, t_g=20, seed=0, weighted=False, timing=False, one_stream=False,
-                    omega_reduce=None, g=None, omega=None, x_dtype="f32"):
+                    omega_reduce=None, g=None, omega=None, x_dtype="f32", nci="literal"):
     """Returns an opaque plan handle (int).  x_dtype: "f32" or "bf16" (X_U's
     element type)."""
     lib = load_library()
@@ -169,13 +171,20 @@ def tpo_plan_create(n_u, n_v, n_edges, d_u, *, k, alpha, gamma, d=0, q=20, overs
                       X_DTYPES[x_dtype])
     keep = [_dptr(omega_reduce), _dptr(g), _dptr(omega)]
     par = TpoParams(TPO_ABI_VERSION, int(k), float(alpha), int(gamma), int(d), int(q), int(oversample),
-                    int(t_f), int(t_g), (TPO_FLAG_TIMING if timing else 0) | (TPO_FLAG_ONE_STREAM if one_stream else 0), int(seed) & ((1 << 64) - 1),
+                    int(t_f), int(t_g), _flags(timing, one_stream, nci), int(seed) & ((1 << 64) - 1),
                     keep[0][1] if keep[0] else None, keep[1][1] if keep[1] else None,
                     keep[2][1] if keep[2] else None)
     h = C.c_void_p()
     _check(lib.tpo_plan_create(C.byref(prob), C.byref(par), C.byref(h)))
     _PLAN_XDT[h.value] = x_dtype
     return h.value
+
+
+def _flags(timing, one_stream, nci) -> int:
+    if nci not in NCI_VARIANTS:
+        raise ValueError(f"nci must be one of {NCI_VARIANTS}")
+    return ((TPO_FLAG_TIMING if timing else 0) | (TPO_FLAG_ONE_STREAM if one_stream else 0)
+            | (TPO_FLAG_NCI_PROCRUSTES if nci == "procrustes" else 0))
 
 
 def tpo_plan_destroy(plan) -> None:
@@ -352,14 +361,14 @@ def cluster_target_v(edge_u, edge_v, x_v, *, n_u, k, **kw):
 
 def cluster_sized(edge_u, edge_v, x_u, *, n_v, k, alpha=0.5, gamma=5, d=0, q=20, oversample=10,
                   t_f=5, t_g=20, seed=0, edge_w=None, omega_reduce=None, g=None, omega=None,
-                  timing=False):
+                  timing=False, nci="literal"):
     import torch
     n_u, d_u = x_u.shape
     xdt = "bf16" if str(x_u.dtype) == "torch.bfloat16" else "f32"
     plan = Plan.create(n_u, n_v, edge_u.numel(), d_u, device=x_u.device, k=k, alpha=alpha,
                        gamma=gamma, d=d, q=q, oversample=oversample, t_f=t_f, t_g=t_g, seed=seed,
                        weighted=edge_w is not None, timing=timing, omega_reduce=omega_reduce,
-                       g=g, omega=omega, x_dtype=xdt)
+                       g=g, omega=omega, x_dtype=xdt, nci=nci)
     try:
         labels = torch.empty(n_u, dtype=torch.int32, device=x_u.device)
         emb = torch.empty(n_u, k, dtype=torch.float32, device=x_u.device)

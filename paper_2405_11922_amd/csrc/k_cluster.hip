@@ -382,7 +382,8 @@ static void sum_parts_i64(const long long* part, int nb, int len, long long* sum
 }
 
 // One round: scores = U Phi (FP64), l* = first argmax, labels written.  Phi
-// is the identity when `sums` is null, else Phi[t][l] = c_l[t] / sqrt(|C_l|)
+// is phi_g (k x k, Phi[t][l] at t * k + l) when given, else the identity when
+// `sums` is null, else Phi[t][l] = c_l[t] / sqrt(|C_l|)
 // with c_l the fixed-point sum of the U rows labelled l and |C_l| their count
 // (sums: k x k values c_l[t] at l * k + t, then k counts).  When `part` is
 // given, the block's own fixed-point sums and counts for the labels of this
@@ -392,8 +393,8 @@ static void sum_parts_i64(const long long* part, int nb, int len, long long* sum
 template <int KT>
 __global__ void __launch_bounds__(256)
 k_nci_round(const float* __restrict__ U, int64_t n, int k, const long long* __restrict__ sums,
-            long long* __restrict__ part, int32_t* __restrict__ labels, int rows_per_block,
-            const DevStatus* __restrict__ st) {
+            const double* __restrict__ phi_g, long long* __restrict__ part, int32_t* __restrict__ labels,
+            int rows_per_block, const DevStatus* __restrict__ st) {
   constexpr int LD = KT + 1;  // staging stride (odd for even KT)
   __shared__ double phi[KT * KT];
   __shared__ double fac[KT];
@@ -411,7 +412,8 @@ k_nci_round(const float* __restrict__ U, int64_t n, int k, const long long* __re
   for (int e = tid; e < KT * KT; e += 256) {
     const int t = e / KT, l = e - (e / KT) * KT;
     double v = 0.0;
-    if (t < k && l < k) v = sums ? static_cast<double>(sums[l * k + t]) * fac[l] : (t == l ? 1.0 : 0.0);
+    if (t < k && l < k)
+      v = phi_g ? phi_g[t * k + l] : sums ? static_cast<double>(sums[l * k + t]) * fac[l] : (t == l ? 1.0 : 0.0);
     phi[e] = v;
   }
   __syncthreads();
@@ -486,7 +488,7 @@ constexpr int kNciWide = 128;
 template <int LT>
 __global__ void __launch_bounds__(512)
 k_nci_score_mfma(const float* __restrict__ U, int64_t n, int k, const long long* __restrict__ sums,
-                 int32_t* __restrict__ labels, const DevStatus* __restrict__ st) {
+                 const double* __restrict__ phi_g, int32_t* __restrict__ labels, const DevStatus* __restrict__ st) {
   constexpr int NL = 16 * LT;
   constexpr int KS = NL / 4;  // k steps of the padded contraction
   __shared__ double phi[NL * NL];  // phi[t * NL + l]
@@ -503,7 +505,8 @@ k_nci_score_mfma(const float* __restrict__ U, int64_t n, int k, const long long*
   for (int e = tid; e < NL * NL; e += 512) {
     const int t = e / NL, l = e - (e / NL) * NL;
     double v = 0.0;
-    if (t < k && l < k) v = sums ? static_cast<double>(sums[l * k + t]) * fac[l] : (t == l ? 1.0 : 0.0);
+    if (t < k && l < k)
+      v = phi_g ? phi_g[t * k + l] : sums ? static_cast<double>(sums[l * k + t]) * fac[l] : (t == l ? 1.0 : 0.0);
     phi[e] = v;
   }
   __syncthreads();
@@ -614,15 +617,189 @@ k_nci_accum_wide(const float* __restrict__ U, int64_t n, int k, const int32_t* _
 }
 
 template <int LT>
-static void nci_score_mfma(const float* U, int64_t n, int k, const long long* sums, int32_t* labels,
-                          const DevStatus* st, hipStream_t s) {
+static void nci_score_mfma(const float* U, int64_t n, int k, const long long* sums, const double* phi_g,
+                           int32_t* labels, const DevStatus* st, hipStream_t s) {
   constexpr int NL = 16 * LT;
   constexpr size_t lds = static_cast<size_t>(NL) * NL * 8 + NL * 8;
   const int per_cu = std::max<int>(1, static_cast<int>((160 * 1024) / lds));
   const int64_t ntiles = (n + 15) / 16;
   const int nb = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>((ntiles + 7) / 8, 256 * per_cu)));
-  hipLaunchKernelGGL((k_nci_score_mfma<LT>), dim3(nb), dim3(512), 0, s, U, n, k, sums, labels, st);
+  hipLaunchKernelGGL((k_nci_score_mfma<LT>), dim3(nb), dim3(512), 0, s, U, n, k, sums, phi_g, labels, st);
   TPO_LAUNCH_CHECK();
+}
+
+// Procrustes form of the Phi update: Phi = the orthogonal factor of the polar
+// decomposition of M = Ups^T Y, which is the orthogonal matrix minimising
+// ||Ups Phi - Y||_F (Section 3.4 states this minimisation; the printed update
+// Ups^T Y is not orthogonal).  An empty cluster leaves a zero column in M;
+// Phi is then the polar factor of M's other columns with that column zero
+// (the partial isometry), M being of full rank on the nonzero columns.
+//
+// k <= 64: Newton-Schulz, X <- X (3 I - X^T X) / 2 from X = M / ||M||_F, which
+// takes every nonzero singular value to 1 (quadratically once near it) and
+// keeps a zero column zero; it stops when an iteration moves X by at most
+// 1e-14 sqrt(k) in Frobenius norm (at most kNsMaxIter iterations).  X, X^T X
+// and the next X in LDS, one workgroup.
+constexpr int kNsMaxIter = 200;
+
+template <int KW, int NT>
+__global__ void __launch_bounds__(NT)
+k_nci_polar_ns(const long long* __restrict__ sums, int k, int64_t n, const DevStatus* __restrict__ st,
+               double* __restrict__ phi) {
+  __shared__ double Xa[KW * (KW + 1)];
+  __shared__ double Xb[KW * (KW + 1)];
+  __shared__ double G[KW * (KW + 1)];
+  __shared__ double red[NT];
+  __shared__ double fac[KW];
+  const int tid = threadIdx.x;
+  const int la = k | 1;
+  const int sft = fixed_point_shift(__uint_as_float(st->maxabs_ups_bits), n);
+  const double inv_scale = ldexp(1.0, -sft);
+  for (int c = tid; c < k; c += NT) {
+    const long long cnt = sums[k * k + c];
+    fac[c] = cnt > 0 ? inv_scale / sqrt(static_cast<double>(cnt)) : 0.0;
+  }
+  __syncthreads();
+  double ss = 0.0;
+  for (int e = tid; e < k * k; e += NT) {
+    const int t = e / k, l = e - (e / k) * k;
+    const double v = static_cast<double>(sums[l * k + t]) * fac[l];
+    Xa[t * la + l] = v;
+    ss = fma(v, v, ss);
+  }
+  const double nrm2 = blk_sum(ss, red);
+  if (nrm2 == 0.0) {  // uniform: no rows at all
+    for (int e = tid; e < k * k; e += NT) phi[e] = 0.0;
+    return;
+  }
+  const double inv = 1.0 / sqrt(nrm2);
+  for (int e = tid; e < k * k; e += NT) {
+    const int t = e / k, l = e - (e / k) * k;
+    Xa[t * la + l] *= inv;
+  }
+  __syncthreads();
+  double* X = Xa;
+  double* Xn = Xb;
+  const double tol2 = 1e-28 * k;
+  for (int it = 0; it < kNsMaxIter; ++it) {
+    for (int e = tid; e < k * k; e += NT) {
+      const int i = e / k, j = e - (e / k) * k;
+      double a = 0.0;
+      for (int t = 0; t < k; ++t) a = fma(X[t * la + i], X[t * la + j], a);
+      G[i * la + j] = a;
+    }
+    __syncthreads();
+    double dd = 0.0;
+    for (int e = tid; e < k * k; e += NT) {
+      const int t = e / k, j = e - (e / k) * k;
+      double a = 0.0;
+      for (int i = 0; i < k; ++i) a = fma(X[t * la + i], G[i * la + j], a);
+      const double x = X[t * la + j];
+      const double y = fma(-0.5, a, 1.5 * x);
+      Xn[t * la + j] = y;
+      dd = fma(y - x, y - x, dd);
+    }
+    const double d2 = blk_sum(dd, red);  // ends with a barrier
+    double* tmp = X;
+    X = Xn;
+    Xn = tmp;
+    if (d2 <= tol2) break;  // uniform
+  }
+  for (int e = tid; e < k * k; e += NT) {
+    const int t = e / k, l = e - (e / k) * k;
+    phi[e] = X[t * la + l];
+  }
+}
+
+// k > 64: M^T M = V diag(lambda) V^T by Jacobi and Phi = M V diag(d) V^T with
+// d_i = 1 / sqrt(lambda_i) for lambda_i > 0 (an empty cluster's zero column
+// gives an exactly zero row and column of M^T M, which no rotation touches,
+// so its lambda is exactly 0; 1e-24 of the largest guards the division).  One
+// workgroup of NT threads for k <= KW; M and V in global scratch (k x k,
+// row-major), M^T M and then V diag(d) V^T in LDS.
+template <int KW, int NT, int KB>
+__global__ void __launch_bounds__(NT)
+k_nci_polar(const long long* __restrict__ sums, int k, int64_t n, const DevStatus* __restrict__ st,
+            double* __restrict__ Mg, double* __restrict__ Vg, double* __restrict__ phi) {
+  constexpr bool kInLds = KW <= 64;
+  __shared__ double A[KW * (KW + 1)];
+  __shared__ double Ml[kInLds ? KW * KW : 1];
+  __shared__ double Vl[kInLds ? KW * KW : 1];
+  __shared__ __align__(16) double sh[3 * (KW / 2)];
+  __shared__ double fac[KW];
+  __shared__ double dl[KW];
+  __shared__ double lmax;
+  double* M = kInLds ? Ml : Mg;
+  double* V = kInLds ? Vl : Vg;
+  const int tid = threadIdx.x;
+  const int sft = fixed_point_shift(__uint_as_float(st->maxabs_ups_bits), n);
+  const double inv_scale = ldexp(1.0, -sft);
+  for (int c = tid; c < k; c += NT) {
+    const long long cnt = sums[k * k + c];
+    fac[c] = cnt > 0 ? inv_scale / sqrt(static_cast<double>(cnt)) : 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < k * k; e += NT) {
+    const int t = e / k, l = e - (e / k) * k;
+    M[e] = static_cast<double>(sums[l * k + t]) * fac[l];
+  }
+  __syncthreads();
+  const int la = k | 1;
+  // M^T M, both triangles by the same product order (exactly symmetric)
+  for (int e = tid; e < k * k; e += NT) {
+    const int i = e / k, j = e - (e / k) * k;
+    double a = 0.0;
+    for (int t = 0; t < k; ++t) a = fma(M[t * k + i], M[t * k + j], a);
+    A[i * la + j] = a;
+  }
+  __syncthreads();
+  blk_jacobi<KB>(A, la, V, k, k, sh, nullptr, 40);
+  if (tid == 0) {
+    double m = 0.0;
+    for (int i = 0; i < k; ++i) m = fmax(m, A[i * la + i]);
+    lmax = m;
+  }
+  __syncthreads();
+  for (int c = tid; c < k; c += NT) {
+    const double lam = A[c * la + c];
+    dl[c] = (lmax > 0.0 && lam > 1e-24 * lmax) ? 1.0 / sqrt(lam) : 0.0;
+  }
+  __syncthreads();
+  // W = V diag(d) V^T into A
+  for (int e = tid; e < k * k; e += NT) {
+    const int i = e / k, j = e - (e / k) * k;
+    double a = 0.0;
+    for (int c = 0; c < k; ++c) a = fma(V[i * k + c] * dl[c], V[j * k + c], a);
+    A[i * la + j] = a;
+  }
+  __syncthreads();
+  for (int e = tid; e < k * k; e += NT) {
+    const int t = e / k, l = e - (e / k) * k;
+    double a = 0.0;
+    for (int j = 0; j < k; ++j) a = fma(M[t * k + j], A[j * la + l], a);
+    phi[e] = a;
+  }
+}
+
+// Phi for the next round from the label sums: the literal update leaves it to
+// the score kernel (built from `sums`); the Procrustes form computes it here.
+// Jacobi item counts (k > 64): (k/2)^2 <= 2 KB NT and k^2/2 <= 4 KB NT.
+static const double* nci_phi(const Plan& p, void* ws, const long long* sums, hipStream_t s) {
+  // k = 1: every row takes label 0 whatever Phi is
+  if (!(p.par.flags & TPO_FLAG_NCI_PROCRUSTES) || p.k == 1) return nullptr;
+  double* phi = bufp<double>(p, ws, B_NCI_PHI);
+  const int64_t n = static_cast<int64_t>(p.n);
+  DevStatus* st = bufp<DevStatus>(p, ws, B_STATUS);
+  double* mg = bufp<double>(p, ws, B_NCI_PM);
+  double* vg = bufp<double>(p, ws, B_NCI_PV);
+  if (p.k <= 32)
+    hipLaunchKernelGGL((k_nci_polar_ns<32, 256>), dim3(1), dim3(256), 0, s, sums, p.k, n, st, phi);
+  else if (p.k <= 64)
+    hipLaunchKernelGGL((k_nci_polar_ns<64, 256>), dim3(1), dim3(256), 0, s, sums, p.k, n, st, phi);
+  else
+    hipLaunchKernelGGL((k_nci_polar<kNciWide, 512, 4>), dim3(1), dim3(512), 0, s, sums, p.k, n, st, mg, vg, phi);
+  TPO_LAUNCH_CHECK();
+  return phi;
 }
 
 static void nci_rounds_wide(const Plan& p, void* ws, hipStream_t s) {
@@ -640,13 +817,15 @@ static void nci_rounds_wide(const Plan& p, void* ws, hipStream_t s) {
   const int rounds = std::max(p.par.t_g, 1);
   for (int t = 1; t <= rounds; ++t) {
     const long long* sm = t == 1 ? nullptr : sums;
+    const double* ph = t == 1 ? nullptr : nci_phi(p, ws, sums, s);
+    if (ph) sm = nullptr;
     switch ((k + 15) / 16) {
-      case 3: nci_score_mfma<3>(U, n, k, sm, labels, st, s); break;
-      case 4: nci_score_mfma<4>(U, n, k, sm, labels, st, s); break;
-      case 5: nci_score_mfma<5>(U, n, k, sm, labels, st, s); break;
-      case 6: nci_score_mfma<6>(U, n, k, sm, labels, st, s); break;
-      case 7: nci_score_mfma<7>(U, n, k, sm, labels, st, s); break;
-      case 8: nci_score_mfma<8>(U, n, k, sm, labels, st, s); break;
+      case 3: nci_score_mfma<3>(U, n, k, sm, ph, labels, st, s); break;
+      case 4: nci_score_mfma<4>(U, n, k, sm, ph, labels, st, s); break;
+      case 5: nci_score_mfma<5>(U, n, k, sm, ph, labels, st, s); break;
+      case 6: nci_score_mfma<6>(U, n, k, sm, ph, labels, st, s); break;
+      case 7: nci_score_mfma<7>(U, n, k, sm, ph, labels, st, s); break;
+      case 8: nci_score_mfma<8>(U, n, k, sm, ph, labels, st, s); break;
       default: throw std::runtime_error("NCI: k outside 33..128 on the two-kernel path");
     }
     if (t < p.par.t_g) {
@@ -672,8 +851,9 @@ static void nci_rounds(const Plan& p, void* ws, hipStream_t s) {
     // round 1 (and T_g = 0) scores against Phi = I; every round but the last
     // feeds the label sums to the next
     const bool acc = t < p.par.t_g;
+    const double* ph = t == 1 ? nullptr : nci_phi(p, ws, sums, s);
     hipLaunchKernelGGL((k_nci_round<KT>), dim3(nb), dim3(256), 0, s, U, static_cast<int64_t>(p.n), k,
-                       t == 1 ? nullptr : sums, acc ? part : nullptr, labels, rpb, st);
+                       (t == 1 || ph) ? nullptr : sums, ph, acc ? part : nullptr, labels, rpb, st);
     TPO_LAUNCH_CHECK();
     if (acc) sum_parts_i64(part, nb, k * k + k, sums, s);
   }

@@ -162,6 +162,9 @@ void build_layout(Plan& p) {
   add(B_LABELS, 4 * n);
   add(B_NCI_PART, 8 * nbr * (k * k + k));
   add(B_NCI_SUM, 8 * (k * k + k));
+  add(B_NCI_PHI, 8 * k * k);
+  add(B_NCI_PM, 8 * k * k);
+  add(B_NCI_PV, 8 * k * k);
   add(B_OBJ_PART, 8 * static_cast<size_t>(p.obj_blocks) * (k * twod + k));
   add(B_OBJ_SUM, 8 * (k * twod + k));
   add(B_REDTMP, 8 * 16 * std::max(twod * k + k * k, twod));

@@ -67,7 +67,7 @@ enum Buf {
   // onmf
   B_UPS, B_H, B_H32, B_H_NEW, B_RTU, B_UTU, B_A32, B_ONMF_PART,
   // nci / objective
-  B_LABELS, B_NCI_PART, B_NCI_SUM, B_OBJ_PART, B_OBJ_SUM,
+  B_LABELS, B_NCI_PART, B_NCI_SUM, B_NCI_PHI, B_NCI_PM, B_NCI_PV, B_OBJ_PART, B_OBJ_SUM,
   // subspace iteration (reduction and embedding)
   B_SI_M, B_SI_P, B_SI_GRAM, B_SI_PART, B_SI_BAR,
   B_REDTMP,

@@ -14,7 +14,7 @@ def log(*a):
 
 
 def gpu_run(abg, *, k, alpha, gamma, d, q=20, oversample=10, t_f=5, t_g=20, seed=0,
-            mm=None, stages=True, device="cuda:0", x_bf16=False):
+            mm=None, stages=True, device="cuda:0", x_bf16=False, nci="literal"):
     """Runs the job on the GPU.  Returns a dict of numpy intermediates.
     x_bf16: hand X over as bfloat16 (its values must be representable)."""
     import torch
@@ -38,7 +38,7 @@ def gpu_run(abg, *, k, alpha, gamma, d, q=20, oversample=10, t_f=5, t_g=20, seed
     plan = tpo.Plan.create(abg.n_u, abg.n_v, abg.n_edges, abg.d_u, device=dev, k=k, alpha=alpha,
                            gamma=gamma, d=d, q=q, oversample=oversample, t_f=t_f, t_g=t_g,
                            seed=seed, weighted=ew is not None, timing=True,
-                           x_dtype="bf16" if x_bf16 else "f32", **kw)
+                           x_dtype="bf16" if x_bf16 else "f32", nci=nci, **kw)
     out = {}
     try:
         h, ws = plan.handle, plan.workspace
@@ -74,7 +74,8 @@ def gpu_run(abg, *, k, alpha, gamma, d, q=20, oversample=10, t_f=5, t_g=20, seed
     return out
 
 
-def oracle_run(abg, *, k, alpha, gamma, d, q=20, oversample=10, t_f=5, t_g=20, seed=0, mm=None):
+def oracle_run(abg, *, k, alpha, gamma, d, q=20, oversample=10, t_f=5, t_g=20, seed=0, mm=None,
+               nci="literal"):
     import abg_synth as synth
     import oracle
 
@@ -82,7 +83,7 @@ def oracle_run(abg, *, k, alpha, gamma, d, q=20, oversample=10, t_f=5, t_g=20, s
         mm = synth.method_matrices(seed, abg.d_u, d, k, oversample)
     return oracle.tpo(abg.n_u, abg.n_v, abg.edge_u, abg.edge_v, abg.x_u, k=k, alpha=alpha,
                       gamma=gamma, g=mm.g, omega=mm.omega, omega_r=mm.omega_reduce, d=d, q=q,
-                      t_f=t_f, t_g=t_g, edge_w=abg.edge_w)
+                      t_f=t_f, t_g=t_g, edge_w=abg.edge_w, nci_variant=nci)
 
 
 def rel_fro(a, b) -> float:

@@ -156,6 +156,35 @@ def test_stage_parity(name):
     assert rel < 1e-6 and rel_t < 1e-6
 
 
+# NCI with the Procrustes form of the Phi update (the polar factor of
+# Ups^T Y, plan flag TPO_FLAG_NCI_PROCRUSTES): the one-kernel rounds (k <= 32),
+# the two-kernel rounds with 48- to 128-label tiles.
+@pytest.mark.parametrize("name", ["cpu_scale", "reduce_small", "k33", "k64", "k100", "k128"])
+def test_nci_procrustes(name):
+    make, kw = CASES[name]
+    abg = make()
+    t_g = kw.get("t_g", 20)
+    out = gpu_run(abg, **kw, nci="procrustes")
+    lab, _ = oracle.nci(out["upsilon"], t_g, "procrustes")
+    assert np.array_equal(out["labels"], lab), name
+    ref = oracle_run(abg, **kw, nci="procrustes")
+    same = oracle.labels_match_up_to_permutation(out["labels"], ref.labels)
+    frac = _mismatch_fraction(out["labels"], ref.labels)
+    rel = abs(out["objective"][0] - ref.objective) / abs(ref.objective)
+    lit, _ = oracle.nci(out["upsilon"], t_g)
+    log(f"[{name} procrustes] NCI labels identical on device Upsilon; end to end same up to permutation "
+        f"{same} (mismatch {frac:.2e}), objective rel err {rel:.2e}; rows labelled differently from the "
+        f"literal update (best matching) {_mismatch_fraction(lab, lit):.3e}")
+    assert same, name
+    assert rel < 1e-6
+
+
+def test_nci_procrustes_k1():
+    make, _ = CASES["cpu_scale"]
+    out = gpu_run(make(), k=1, alpha=0.5, gamma=3, d=0, nci="procrustes")
+    assert np.all(out["labels"] == 0)
+
+
 def _bf16_inputs(abg):
     """The same graph with X rounded to bfloat16 (round to nearest even):
     the oracle and the device then see identical attribute values."""
