@@ -301,6 +301,38 @@ def planted_attributes(labels: np.ndarray, d: int, *, sigma: float = 1.5, seed: 
     return x.astype(np.float32)
 
 
+def quantize_e4m3(x: np.ndarray):
+    """Per-column FP8 E4M3 (OCP e4m3fn) encoding of an attribute matrix: scale
+    s_j = max_i |x_ij| / 448 (the largest finite E4M3 magnitude; 1 for an
+    all-zero column), codes = round-to-nearest-even of x_ij / s_j.  Returns
+    (codes uint8 [n, d], s float32 [d], the encoded values code * s in
+    float64: what a consumer of the codes and scales sees)."""
+    import torch
+
+    x = np.asarray(x, dtype=np.float32)
+    amax = np.abs(x).max(axis=0) if x.shape[0] else np.zeros(x.shape[1], np.float32)
+    scale = np.where(amax > 0, amax / np.float32(448.0), np.float32(1.0)).astype(np.float32)
+    t = torch.from_numpy(np.ascontiguousarray(x / scale[None, :])).clamp(-448.0, 448.0)
+    q = t.to(torch.float8_e4m3fn)
+    codes = q.view(torch.uint8).numpy().copy()
+    values = q.to(torch.float64).numpy() * scale.astype(np.float64)[None, :]
+    return codes, scale, values
+
+
+def e4m3_value(code: int) -> float:
+    """The OCP E4M3 (e4m3fn) value of one byte from the format's definition:
+    sign bit, 4 exponent bits with bias 7, 3 mantissa bits; exponent 0 is
+    subnormal (m / 8 * 2^-6); 0x7F and 0xFF are NaN; no infinities."""
+    s = -1.0 if code & 0x80 else 1.0
+    e = (code >> 3) & 0xF
+    m = code & 7
+    if e == 0xF and m == 7:
+        return float("nan")
+    if e == 0:
+        return s * (m / 8.0) * 2.0 ** -6
+    return s * (1.0 + m / 8.0) * 2.0 ** (e - 7)
+
+
 def target_v(abg: ABG, x_v: np.ndarray) -> ABG:
     """The same graph with V as the target set: the two sides exchanged
     (every edge (u, v) read as (v, u)) and x_v as the target's attributes."""

@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define TPO_ABI_VERSION 1
+#define TPO_ABI_VERSION 2
 
 typedef enum tpo_status {
   TPO_OK = 0,
@@ -53,15 +53,19 @@ typedef struct tpo_problem {
                           a (u, v) pair listed twice adds its weights (B_U[i,j]
                           is the summed weight) */
   int32_t weighted;    /* 1: tpo_inputs.edge_w is given; 0: every w = 1 */
-  int32_t x_dtype;     /* element type of tpo_inputs.x_u: TPO_X_F32 or
-                          TPO_X_BF16 (the attribute precision form: the
-                          Gram C = X^T X of Section 3.2.1 on BF16 MFMA with
-                          FP32 accumulation, added up in FP64; the projection
-                          reads BF16 and multiplies in FP32) */
+  int32_t x_dtype;     /* element type of tpo_inputs.x_u: TPO_X_F32,
+                          TPO_X_BF16 or TPO_X_FP8 (the attribute precision
+                          forms: the Gram C = X^T X of Section 3.2.1 on BF16
+                          or FP8 MFMA with FP32 accumulation, added up in
+                          FP64; the projection reads the narrow type and
+                          multiplies in FP32) */
 } tpo_problem;
 
 #define TPO_X_F32 0
 #define TPO_X_BF16 1 /* bfloat16: the upper 16 bits of an IEEE binary32 */
+#define TPO_X_FP8 2  /* OCP FP8 E4M3 (exponent bias 7, no infinities, 0x7F and
+                        0xFF are NaN) with one FP32 scale per column: the
+                        attribute is decode(x_u[i][j]) * x_scale[j] */
 
 /* Method parameters: Table 1 of the paper plus the unstated RandomizedSVD
  * details.  Defaults used in the paper: t_f = 5, t_g = 20. */
@@ -108,6 +112,8 @@ typedef struct tpo_inputs {
   const void* x_u;       /* X_U: n_u rows of ld_x elements of type
                             tpo_problem.x_dtype, first d_u used */
   int64_t ld_x;          /* row stride of x_u in elements, >= d_u */
+  const float* x_scale;  /* [d_u] column scales, device memory; required with
+                            TPO_X_FP8 (EINVAL if NULL), ignored otherwise */
 } tpo_inputs;
 
 /* Outputs of one job. */

@@ -22,7 +22,7 @@ __all__ = [
     "tpo_status_string", "BUF", "Plan", "cluster",
 ]
 
-TPO_ABI_VERSION = 1
+TPO_ABI_VERSION = 2
 TPO_FLAG_TIMING = 1
 TPO_FLAG_ONE_STREAM = 2
 TPO_FLAG_NCI_PROCRUSTES = 4
@@ -71,7 +71,7 @@ class TpoParams(C.Structure):
 
 class TpoInputs(C.Structure):
     _fields_ = [("edge_u", C.c_void_p), ("edge_v", C.c_void_p), ("edge_w", C.c_void_p),
-                ("x_u", C.c_void_p), ("ld_x", C.c_int64)]
+                ("x_u", C.c_void_p), ("ld_x", C.c_int64), ("x_scale", C.c_void_p)]
 
 
 class TpoOutputs(C.Structure):
@@ -155,14 +155,15 @@ def _dptr(arr):
     return a, a.ctypes.data_as(C.POINTER(C.c_double))
 
 
-X_DTYPES = {"f32": 0, "bf16": 1}  # TPO_X_F32, TPO_X_BF16
+X_DTYPES = {"f32": 0, "bf16": 1, "fp8": 2}  # TPO_X_F32, TPO_X_BF16, TPO_X_FP8
+_TORCH_XDT = {"torch.float32": "f32", "torch.bfloat16": "bf16", "torch.float8_e4m3fn": "fp8"}
 _PLAN_XDT = {}  # plan handle -> x_dtype name, to check the tensors handed over
 
 
 def tpo_plan_create(n_u, n_v, n_edges, d_u, *, k, alpha, gamma, d=0, q=20, oversample=10,
                     t_f=5, t_g=20, seed=0, weighted=False, timing=False, one_stream=False,
                     omega_reduce=None, g=None, omega=None, x_dtype="f32", nci="literal"):
-    """Returns an opaque plan handle (int).  x_dtype: "f32" or "bf16" (X_U's
+    """Returns an opaque plan handle (int).  x_dtype: "f32", "bf16" or "fp8" (X_U's
     element type)."""
     lib = load_library()
     if x_dtype not in X_DTYPES:
@@ -204,17 +205,20 @@ def tpo_plan_dims(plan):
     return a.value, b.value, c.value
 
 
-def _inputs(edge_u, edge_v, x_u, edge_w=None, plan=None):
+def _inputs(edge_u, edge_v, x_u, edge_w=None, plan=None, x_scale=None):
     if x_u is not None and plan in _PLAN_XDT:
         want = _PLAN_XDT[plan]
-        have = {"torch.float32": "f32", "torch.bfloat16": "bf16"}.get(str(x_u.dtype))
+        have = _TORCH_XDT.get(str(x_u.dtype))
         if have != want:
             raise TpoError(1, f"x_u is {x_u.dtype}, the plan expects {want}")
+        if want == "fp8" and (x_scale is None or str(x_scale.dtype) != "torch.float32"
+                              or x_scale.numel() != x_u.shape[1] or not x_scale.is_contiguous()):
+            raise TpoError(1, "FP8 attributes need x_scale: a contiguous float32 tensor of d_u column scales")
     ld = x_u.stride(0) if x_u is not None else 0
     return TpoInputs(edge_u.data_ptr() if edge_u is not None else None,
                      edge_v.data_ptr() if edge_v is not None else None,
                      edge_w.data_ptr() if edge_w is not None else None,
-                     x_u.data_ptr(), ld)
+                     x_u.data_ptr(), ld, x_scale.data_ptr() if x_scale is not None else None)
 
 
 def _stream(stream):
@@ -225,10 +229,11 @@ def _stream(stream):
 
 
 def tpo_execute(plan, edge_u, edge_v, x_u, workspace, labels, embedding=None, edge_w=None,
-                stream=None):
-    """Runs the whole method; returns (obj1, trace form)."""
+                stream=None, x_scale=None):
+    """Runs the whole method; returns (obj1, trace form).  x_scale: the
+    column scales of FP8 attributes."""
     lib = load_library()
-    inp = _inputs(edge_u, edge_v, x_u, edge_w, plan)
+    inp = _inputs(edge_u, edge_v, x_u, edge_w, plan, x_scale)
     obj = (C.c_double * 2)()
     out = TpoOutputs(labels.data_ptr(), embedding.data_ptr() if embedding is not None else None,
                      C.cast(obj, C.POINTER(C.c_double)))
@@ -241,13 +246,13 @@ def _ws(workspace):
     return workspace.data_ptr(), workspace.numel() * workspace.element_size()
 
 
-def tpo_stage_ingest(plan, edge_u, edge_v, x_u, workspace, edge_w=None, stream=None):
-    inp = _inputs(edge_u, edge_v, x_u, edge_w, plan)
+def tpo_stage_ingest(plan, edge_u, edge_v, x_u, workspace, edge_w=None, stream=None, x_scale=None):
+    inp = _inputs(edge_u, edge_v, x_u, edge_w, plan, x_scale)
     _check(load_library().tpo_stage_ingest(plan, C.byref(inp), *_ws(workspace), _stream(stream)), plan)
 
 
-def tpo_stage_reduce(plan, edge_u, edge_v, x_u, workspace, edge_w=None, stream=None):
-    inp = _inputs(edge_u, edge_v, x_u, edge_w, plan)
+def tpo_stage_reduce(plan, edge_u, edge_v, x_u, workspace, edge_w=None, stream=None, x_scale=None):
+    inp = _inputs(edge_u, edge_v, x_u, edge_w, plan, x_scale)
     _check(load_library().tpo_stage_reduce(plan, C.byref(inp), *_ws(workspace), _stream(stream)), plan)
 
 
@@ -361,10 +366,10 @@ def cluster_target_v(edge_u, edge_v, x_v, *, n_u, k, **kw):
 
 def cluster_sized(edge_u, edge_v, x_u, *, n_v, k, alpha=0.5, gamma=5, d=0, q=20, oversample=10,
                   t_f=5, t_g=20, seed=0, edge_w=None, omega_reduce=None, g=None, omega=None,
-                  timing=False, nci="literal"):
+                  timing=False, nci="literal", x_scale=None):
     import torch
     n_u, d_u = x_u.shape
-    xdt = "bf16" if str(x_u.dtype) == "torch.bfloat16" else "f32"
+    xdt = _TORCH_XDT.get(str(x_u.dtype), "f32")
     plan = Plan.create(n_u, n_v, edge_u.numel(), d_u, device=x_u.device, k=k, alpha=alpha,
                        gamma=gamma, d=d, q=q, oversample=oversample, t_f=t_f, t_g=t_g, seed=seed,
                        weighted=edge_w is not None, timing=timing, omega_reduce=omega_reduce,
@@ -372,7 +377,7 @@ def cluster_sized(edge_u, edge_v, x_u, *, n_v, k, alpha=0.5, gamma=5, d=0, q=20,
     try:
         labels = torch.empty(n_u, dtype=torch.int32, device=x_u.device)
         emb = torch.empty(n_u, k, dtype=torch.float32, device=x_u.device)
-        obj = tpo_execute(plan.handle, edge_u, edge_v, x_u, plan.workspace, labels, emb, edge_w)
+        obj = tpo_execute(plan.handle, edge_u, edge_v, x_u, plan.workspace, labels, emb, edge_w, x_scale=x_scale)
         stats = tpo_plan_stats(plan.handle)
     finally:
         plan.close()

@@ -122,7 +122,7 @@ constexpr int kGramBatch = 16;
 
 __global__ void __launch_bounds__(256)
 k_gram_reduce(const double* __restrict__ part, const double* __restrict__ colsum_part, int nchunks, int c,
-              int ntiles, double* __restrict__ G, double* __restrict__ colsum) {
+              int ntiles, const float* __restrict__ scale, double* __restrict__ G, double* __restrict__ colsum) {
   const int npairs = ntiles * (ntiles + 1) / 2;
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx < static_cast<int64_t>(npairs) * kGT * kGT) {
@@ -145,6 +145,9 @@ k_gram_reduce(const double* __restrict__ part, const double* __restrict__ colsum
       for (int u = 0; u < kGramBatch; ++u) s += v[u];
     }
     if (i < c && j < c) {
+      // column scales of an FP8 X: C_ij = s_i s_j (sum of the raw products);
+      // s_i s_j is exact in FP64
+      if (scale) s *= static_cast<double>(scale[i]) * static_cast<double>(scale[j]);
       G[static_cast<int64_t>(i) * c + j] = s;
       G[static_cast<int64_t>(j) * c + i] = s;
     }
@@ -159,7 +162,7 @@ k_gram_reduce(const double* __restrict__ part, const double* __restrict__ colsum
 #pragma unroll
       for (int u = 0; u < kGramBatch; ++u) s += v[u];
     }
-    colsum[idx] = s;
+    colsum[idx] = scale ? s * static_cast<double>(scale[idx]) : s;
   }
 }
 
@@ -312,12 +315,158 @@ k_gram_part_bf16(const uint16_t* __restrict__ X, int64_t n, int c, int64_t ldx, 
   }
 }
 
-static void gram(const void* X, bool bf16, int64_t n, int c, int64_t ldx, int nchunks, double* part,
+// An FP8 E4M3 attribute (raw byte) as FP32, exactly.
+__device__ __forceinline__ float fp8_to_f32(uint32_t byte) {
+  return __builtin_amdgcn_cvt_f32_fp8(static_cast<int>(byte), 0);
+}
+
+// The same partials for an FP8 X (OCP E4M3 bytes; the column scales are
+// applied when the partials are summed): FP8 MFMA 16x16x32 with FP32
+// accumulation (a product of two E4M3 values has at most 8 significant bits,
+// exact in FP32), each 64-row slab's FP32 sums added into FP64.  Same tile
+// order, operand layout and transposed staging as the bfloat16 kernel with
+// one byte per element: a lane's eight consecutive rows of one column are one
+// 8-byte LDS read.  vec: X 4-byte aligned, ldx and c multiples of 4.
+constexpr int kG8Ld = kGSub + 8;  // LDS stride (bytes) of a staged column
+
+__global__ void __launch_bounds__(256)
+k_gram_part_fp8(const uint8_t* __restrict__ X, int64_t n, int c, int64_t ldx, int ntiles, int rows_per_chunk,
+                int nchunks, int vec, double* __restrict__ part, double* __restrict__ colsum_part) {
+  __shared__ __align__(16) uint8_t At[kGT * kG8Ld];
+  __shared__ __align__(16) uint8_t Bt[kGT * kG8Ld];
+  __shared__ double csum[4][kGT];
+  const int npairs = ntiles * (ntiles + 1) / 2;
+  const int b = blockIdx.x;
+  const int xcd = b % 8, slot = b / 8;
+  const int per_xcd = (nchunks + 7) / 8;
+  const int chunk = (slot / npairs) + per_xcd * xcd;
+  int pi = slot % npairs, ti = 0;
+  if (chunk >= nchunks) return;  // uniform: the padding of the grid
+  while (pi >= ntiles - ti) {
+    pi -= ntiles - ti;
+    ++ti;
+  }
+  const int pair = slot % npairs;
+  const int tj = ti + pi;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int i16 = lane & 15, kq = lane >> 4;
+  const int qa = w >> 1, qb = w & 1;
+  const int64_t r_beg = static_cast<int64_t>(chunk) * rows_per_chunk;
+  const int64_t r_end = min(n, r_beg + rows_per_chunk);
+  const bool diag = ti == tj;
+  const uint8_t* Bp = diag ? At : Bt;
+  v4d_t acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb) acc[a][bb] = v4d_t{0.0, 0.0, 0.0, 0.0};
+  double cs = 0.0;
+  // thread tid stages rows 4 (tid >> 4) .. + 3, columns 4 (tid & 15) .. + 3:
+  // the four rows of each column are one 32-bit LDS store
+  uint32_t ra[4], rb[4];
+  auto fetch = [&](int64_t r0) {
+    const int rr = 4 * (tid >> 4), cg = 4 * (tid & 15);
+    const int ca = ti * kGT + cg, cb = tj * kGT + cg;
+    uint32_t wa[4], wb[4];  // row h: the bytes of columns cg .. cg + 3
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int64_t row = r0 + rr + h;
+      if (vec) {
+        wa[h] = (row < r_end && ca < c) ? *reinterpret_cast<const uint32_t*>(X + row * ldx + ca) : 0u;
+        wb[h] = (!diag && row < r_end && cb < c) ? *reinterpret_cast<const uint32_t*>(X + row * ldx + cb) : 0u;
+      } else {
+        wa[h] = 0u;
+        wb[h] = 0u;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          if (row < r_end && ca + e < c) wa[h] |= static_cast<uint32_t>(X[row * ldx + ca + e]) << (8 * e);
+          if (!diag && row < r_end && cb + e < c) wb[h] |= static_cast<uint32_t>(X[row * ldx + cb + e]) << (8 * e);
+        }
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      ra[e] = ((wa[0] >> (8 * e)) & 0xffu) | (((wa[1] >> (8 * e)) & 0xffu) << 8) |
+              (((wa[2] >> (8 * e)) & 0xffu) << 16) | (((wa[3] >> (8 * e)) & 0xffu) << 24);
+      rb[e] = ((wb[0] >> (8 * e)) & 0xffu) | (((wb[1] >> (8 * e)) & 0xffu) << 8) |
+              (((wb[2] >> (8 * e)) & 0xffu) << 16) | (((wb[3] >> (8 * e)) & 0xffu) << 24);
+    }
+  };
+  if (r_beg < r_end) fetch(r_beg);
+  for (int64_t r0 = r_beg; r0 < r_end; r0 += kGSub) {
+    {
+      const int rr = 4 * (tid >> 4), cg = 4 * (tid & 15);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        *reinterpret_cast<uint32_t*>(At + (cg + e) * kG8Ld + rr) = ra[e];
+        if (!diag) *reinterpret_cast<uint32_t*>(Bt + (cg + e) * kG8Ld + rr) = rb[e];
+      }
+    }
+    __syncthreads();
+    if (r0 + kGSub < r_end) fetch(r0 + kGSub);
+    v4f_t s32[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int bb = 0; bb < 2; ++bb) s32[a][bb] = v4f_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < kGSub / 32; ++ks) {
+      const int k0 = 32 * ks + 8 * kq;
+      long av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        av[a] = *reinterpret_cast<const long*>(At + (32 * qa + 16 * a + i16) * kG8Ld + k0);
+        bv[a] = *reinterpret_cast<const long*>(Bp + (32 * qb + 16 * a + i16) * kG8Ld + k0);
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int bb = 0; bb < 2; ++bb)
+          s32[a][bb] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av[a], bv[bb], s32[a][bb], 0, 0, 0);
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[a][bb][v] += static_cast<double>(s32[a][bb][v]);
+    if (diag && colsum_part) {
+      for (int rr = w; rr < kGSub; rr += 4) cs += static_cast<double>(fp8_to_f32(At[lane * kG8Ld + rr]));
+    }
+    __syncthreads();
+  }
+  double* out = part + (static_cast<int64_t>(chunk) * npairs + pair) * kGT * kGT;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        out[(32 * qa + 16 * a + 4 * kq + v) * kGT + 32 * qb + 16 * bb + i16] = acc[a][bb][v];
+  if (diag && colsum_part) {
+    csum[w][lane] = cs;
+    __syncthreads();
+    if (tid < kGT) {
+      const double v = ((csum[0][tid] + csum[1][tid]) + csum[2][tid]) + csum[3][tid];
+      const int j = ti * kGT + tid;
+      if (j < c) colsum_part[static_cast<int64_t>(chunk) * c + j] = v;
+    }
+  }
+}
+
+// xdt: 0 FP32, 1 bfloat16, 2 FP8 E4M3 with column scales `scale`
+static void gram(const void* X, int xdt, const float* scale, int64_t n, int c, int64_t ldx, int nchunks, double* part,
                  double* colsum_part, double* G, double* colsum, hipStream_t s) {
   const int ntiles = (c + kGT - 1) / kGT;
   const int npairs = ntiles * (ntiles + 1) / 2;
   const int rows_per_chunk = static_cast<int>((n + nchunks - 1) / nchunks);
-  if (bf16) {
+  if (xdt == 2) {
+    const int vec = (reinterpret_cast<uintptr_t>(X) % 4 == 0 && ldx % 4 == 0 && c % 4 == 0) ? 1 : 0;
+    const int per_xcd = (nchunks + 7) / 8;
+    hipLaunchKernelGGL(k_gram_part_fp8, dim3(8 * per_xcd * npairs), dim3(256), 0, s,
+                       static_cast<const uint8_t*>(X), n, c, ldx, ntiles, rows_per_chunk, nchunks, vec, part,
+                       colsum_part);
+  } else if (xdt == 1) {
     const int vec = (reinterpret_cast<uintptr_t>(X) % 16 == 0 && ldx % 8 == 0 && c % 8 == 0) ? 1 : 0;
     const int per_xcd = (nchunks + 7) / 8;
     hipLaunchKernelGGL(k_gram_part_bf16, dim3(8 * per_xcd * npairs), dim3(256), 0, s,
@@ -330,7 +479,7 @@ static void gram(const void* X, bool bf16, int64_t n, int c, int64_t ldx, int nc
   TPO_LAUNCH_CHECK();
   const int64_t outs = std::max<int64_t>(static_cast<int64_t>(npairs) * kGT * kGT, c);
   hipLaunchKernelGGL(k_gram_reduce, dim3(ceil_div(outs, 256)), dim3(256), 0, s, part, colsum_part, nchunks, c,
-                     ntiles, G, colsum);
+                     ntiles, xdt == 2 ? scale : nullptr, G, colsum);
   TPO_LAUNCH_CHECK();
 }
 
@@ -571,16 +720,18 @@ constexpr int kPjK = 32;
 constexpr int kPjXLd = kPjK + 1;
 
 // An attribute as FP32: FP32 X as is, bfloat16 X (raw 16 bits) widened
-// exactly.
+// exactly, FP8 X (raw byte) decoded exactly (its column scale is applied by
+// the caller).
 __device__ __forceinline__ float x_at(const float* X, int64_t i) { return X[i]; }
 __device__ __forceinline__ float x_at(const uint16_t* X, int64_t i) {
   return __uint_as_float(static_cast<uint32_t>(X[i]) << 16);
 }
+__device__ __forceinline__ float x_at(const uint8_t* X, int64_t i) { return fp8_to_f32(X[i]); }
 
 template <int CT, typename XT>
 __global__ void __launch_bounds__(256)
-k_project_mfma(const XT* __restrict__ X, int64_t n, int du, int64_t ldx, const float* __restrict__ psi32, int dp,
-               float* __restrict__ out, int32_t* __restrict__ err_bits) {
+k_project_mfma(const XT* __restrict__ X, int64_t n, int du, int64_t ldx, const float* __restrict__ scale,
+               const float* __restrict__ psi32, int dp, float* __restrict__ out, int32_t* __restrict__ err_bits) {
   constexpr int PLD = 16 * CT + 4;
   __shared__ float xs[kPjRows * kPjXLd];
   __shared__ float ps[kPjK * PLD];
@@ -598,6 +749,7 @@ k_project_mfma(const XT* __restrict__ X, int64_t n, int du, int64_t ldx, const f
       const int rr = e / kPjK, kk = e % kPjK;
       const int64_t row = row0 + rr;
       float v = (row < n && k0 + kk < du) ? x_at(X, row * ldx + k0 + kk) : 0.0f;
+      if (scale && k0 + kk < du) v *= scale[k0 + kk];
       if (!isfinite(v)) {
         bad = true;
         v = 0.0f;
@@ -631,13 +783,14 @@ k_project_mfma(const XT* __restrict__ X, int64_t n, int du, int64_t ldx, const f
 }
 
 template <typename XT>
-__global__ void k_pad_copy(const XT* __restrict__ X, int64_t n, int du, int64_t ldx, int dp,
-                           float* __restrict__ out, int32_t* __restrict__ err_bits) {
+__global__ void k_pad_copy(const XT* __restrict__ X, int64_t n, int du, int64_t ldx, const float* __restrict__ scale,
+                           int dp, float* __restrict__ out, int32_t* __restrict__ err_bits) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n * dp) return;
   const int64_t r = i / dp;
   const int c = static_cast<int>(i % dp);
   float v = c < du ? x_at(X, r * ldx + c) : 0.0f;
+  if (scale && c < du) v *= scale[c];
   if (!isfinite(v)) {
     atomicOr(err_bits, 4);
     v = 0.0f;
@@ -646,36 +799,41 @@ __global__ void k_pad_copy(const XT* __restrict__ X, int64_t n, int du, int64_t 
 }
 
 template <typename XT>
-static void project(const Plan& p, const XT* x, int64_t ldx, const float* psi32, float* xp, int32_t* err, hipStream_t s) {
+static void project(const Plan& p, const XT* x, int64_t ldx, const float* sc, const float* psi32, float* xp,
+                    int32_t* err, hipStream_t s) {
   const dim3 grid(ceil_div(p.n, kPjRows));
   const int64_t n = p.n;
   switch ((p.dp + 15) / 16) {
-    case 1: hipLaunchKernelGGL((k_project_mfma<1, XT>), grid, dim3(256), 0, s, x, n, p.du, ldx, psi32, p.dp, xp, err); break;
-    case 2: hipLaunchKernelGGL((k_project_mfma<2, XT>), grid, dim3(256), 0, s, x, n, p.du, ldx, psi32, p.dp, xp, err); break;
-    case 4: hipLaunchKernelGGL((k_project_mfma<4, XT>), grid, dim3(256), 0, s, x, n, p.du, ldx, psi32, p.dp, xp, err); break;
-    case 8: hipLaunchKernelGGL((k_project_mfma<8, XT>), grid, dim3(256), 0, s, x, n, p.du, ldx, psi32, p.dp, xp, err); break;
-    default: hipLaunchKernelGGL((k_project_mfma<16, XT>), grid, dim3(256), 0, s, x, n, p.du, ldx, psi32, p.dp, xp, err); break;
+    case 1: hipLaunchKernelGGL((k_project_mfma<1, XT>), grid, dim3(256), 0, s, x, n, p.du, ldx, sc, psi32, p.dp, xp, err); break;
+    case 2: hipLaunchKernelGGL((k_project_mfma<2, XT>), grid, dim3(256), 0, s, x, n, p.du, ldx, sc, psi32, p.dp, xp, err); break;
+    case 4: hipLaunchKernelGGL((k_project_mfma<4, XT>), grid, dim3(256), 0, s, x, n, p.du, ldx, sc, psi32, p.dp, xp, err); break;
+    case 8: hipLaunchKernelGGL((k_project_mfma<8, XT>), grid, dim3(256), 0, s, x, n, p.du, ldx, sc, psi32, p.dp, xp, err); break;
+    default: hipLaunchKernelGGL((k_project_mfma<16, XT>), grid, dim3(256), 0, s, x, n, p.du, ldx, sc, psi32, p.dp, xp, err); break;
   }
   TPO_LAUNCH_CHECK();
 }
 
-void launch_reduce(const Plan& p, void* ws, const void* x, int64_t ldx, hipStream_t s) {
+void launch_reduce(const Plan& p, void* ws, const void* x, int64_t ldx, const float* xscale, hipStream_t s) {
   DevStatus* st = bufp<DevStatus>(p, ws, B_STATUS);
   float* xp = bufp<float>(p, ws, B_XPRIME);
+  const int xdt = p.xfp8 ? 2 : p.xbf16 ? 1 : 0;
   if (!p.reduce) {
     const dim3 g(ceil_div(static_cast<int64_t>(p.n) * p.dp, 256));
-    if (p.xbf16)
+    if (xdt == 2)
+      hipLaunchKernelGGL(k_pad_copy<uint8_t>, g, dim3(256), 0, s, static_cast<const uint8_t*>(x),
+                         static_cast<int64_t>(p.n), p.du, ldx, xscale, p.dp, xp, &st->err_bits);
+    else if (xdt == 1)
       hipLaunchKernelGGL(k_pad_copy<uint16_t>, g, dim3(256), 0, s, static_cast<const uint16_t*>(x),
-                         static_cast<int64_t>(p.n), p.du, ldx, p.dp, xp, &st->err_bits);
+                         static_cast<int64_t>(p.n), p.du, ldx, nullptr, p.dp, xp, &st->err_bits);
     else
       hipLaunchKernelGGL(k_pad_copy<float>, g, dim3(256), 0, s, static_cast<const float*>(x),
-                         static_cast<int64_t>(p.n), p.du, ldx, p.dp, xp, &st->err_bits);
+                         static_cast<int64_t>(p.n), p.du, ldx, nullptr, p.dp, xp, &st->err_bits);
     TPO_LAUNCH_CHECK();
     return;
   }
   double* C = bufp<double>(p, ws, B_C);
   double* colsum = bufp<double>(p, ws, B_COLSUM_X);
-  gram(x, p.xbf16, p.n, p.du, ldx, p.gram_chunks_x, bufp<double>(p, ws, B_GRAM_PART), bufp<double>(p, ws, B_COLSUM_PART), C,
+  gram(x, xdt, xscale, p.n, p.du, ldx, p.gram_chunks_x, bufp<double>(p, ws, B_GRAM_PART), bufp<double>(p, ws, B_COLSUM_PART), C,
        colsum, s);
   double* ma = bufp<double>(p, ws, B_MR_A);
   double* mb = bufp<double>(p, ws, B_MR_B);
@@ -704,10 +862,12 @@ void launch_reduce(const Plan& p, void* ws, const void* x, int64_t ldx, hipStrea
     TPO_LAUNCH_CHECK();
   }
   const float* psi32 = bufp<float>(p, ws, B_PSI_D32);
-  if (p.xbf16)
-    project(p, static_cast<const uint16_t*>(x), ldx, psi32, xp, &st->err_bits, s);
+  if (xdt == 2)
+    project(p, static_cast<const uint8_t*>(x), ldx, xscale, psi32, xp, &st->err_bits, s);
+  else if (xdt == 1)
+    project(p, static_cast<const uint16_t*>(x), ldx, nullptr, psi32, xp, &st->err_bits, s);
   else
-    project(p, static_cast<const float*>(x), ldx, psi32, xp, &st->err_bits, s);
+    project(p, static_cast<const float*>(x), ldx, nullptr, psi32, xp, &st->err_bits, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -962,7 +1122,7 @@ void launch_features(const Plan& p, void* ws, hipStream_t s) {
 void launch_embed(const Plan& p, void* ws, hipStream_t s) {
   DevStatus* st = bufp<DevStatus>(p, ws, B_STATUS);
   double* K = bufp<double>(p, ws, B_K);
-  gram(bufp<float>(p, ws, B_R), false, p.n, p.twod, p.twod, p.gram_chunks_r, bufp<double>(p, ws, B_GRAM_PART), nullptr,
+  gram(bufp<float>(p, ws, B_R), 0, nullptr, p.n, p.twod, p.twod, p.gram_chunks_r, bufp<double>(p, ws, B_GRAM_PART), nullptr,
        K, nullptr, s);
   if (p.kp <= kWideMaxN) {
     // q products with K, each followed by Cholesky QR, then P = K M

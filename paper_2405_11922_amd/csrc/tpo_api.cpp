@@ -250,6 +250,10 @@ bool valid_inputs(tpo_plan* p, const tpo_inputs* in, std::string* why) {
     *why = "ld_x < d_u";
     return false;
   }
+  if (p->xfp8 && !in->x_scale) {
+    *why = "x_scale is NULL for FP8 attributes";
+    return false;
+  }
   return true;
 }
 
@@ -285,7 +289,7 @@ tpo_status tpo_plan_create(const tpo_problem* prob, const tpo_params* par, tpo_p
   if (prob->abi_version != TPO_ABI_VERSION || par->abi_version != TPO_ABI_VERSION) return TPO_EINVAL;
   if (prob->n_u < 1 || prob->n_v < 1 || prob->n_edges < 0 || prob->n_edges >= (int64_t{1} << 31)) return TPO_EINVAL;
   if (prob->d_u < 1 || prob->d_u > kMaxDu) return TPO_EINVAL;
-  if (prob->x_dtype != TPO_X_F32 && prob->x_dtype != TPO_X_BF16) return TPO_EINVAL;
+  if (prob->x_dtype != TPO_X_F32 && prob->x_dtype != TPO_X_BF16 && prob->x_dtype != TPO_X_FP8) return TPO_EINVAL;
   if (par->k < 1 || par->k > kMaxK) return TPO_EINVAL;
   if (!(par->alpha >= 0.0 && par->alpha < 1.0)) return TPO_EINVAL;
   if (par->gamma < 0 || par->gamma > 1000 || par->q < 0 || par->q > 100) return TPO_EINVAL;
@@ -305,6 +309,7 @@ tpo_status tpo_plan_create(const tpo_problem* prob, const tpo_params* par, tpo_p
   p->E = prob->n_edges;
   p->reduce = reduce;
   p->xbf16 = prob->x_dtype == TPO_X_BF16;
+  p->xfp8 = prob->x_dtype == TPO_X_FP8;
   p->d = d;
   p->dp = next_pow2_at_least(d, 16);
   p->k = par->k;
@@ -465,7 +470,7 @@ tpo_status tpo_stage_reduce(tpo_plan* plan, const tpo_inputs* in, void* ws, size
   if (st != TPO_OK) return st;
   std::string why;
   if (!valid_inputs(plan, in, &why)) return fail(plan, TPO_EINVAL, why);
-  return guarded(plan, [&] { launch_reduce(*plan, ws, in->x_u, in->ld_x, static_cast<hipStream_t>(stream)); });
+  return guarded(plan, [&] { launch_reduce(*plan, ws, in->x_u, in->ld_x, in->x_scale, static_cast<hipStream_t>(stream)); });
 }
 
 tpo_status tpo_stage_propagate(tpo_plan* plan, const tpo_inputs* in, void* ws, size_t bytes, void* stream) {
@@ -558,7 +563,7 @@ tpo_status tpo_execute(tpo_plan* plan, const tpo_inputs* in, void* ws, size_t by
       // stage by stage on one stream (timing: so that each stage's time is its own)
       launch_ingest(*plan, ws, in, s);
       mark(1);
-      launch_reduce(*plan, ws, in->x_u, in->ld_x, s);
+      launch_reduce(*plan, ws, in->x_u, in->ld_x, in->x_scale, s);
       mark(2);
     } else {
       // ingest (edges only) and the attribute reduction (X only) are
@@ -574,7 +579,7 @@ tpo_status tpo_execute(tpo_plan* plan, const tpo_inputs* in, void* ws, size_t by
       TPO_HIP_CHECK(hipStreamWaitEvent(plan->side, plan->fork_ev, 0));
       launch_ingest(*plan, ws, in, plan->side);
       TPO_HIP_CHECK(hipEventRecord(plan->join_ev, plan->side));
-      launch_reduce(*plan, ws, in->x_u, in->ld_x, s);
+      launch_reduce(*plan, ws, in->x_u, in->ld_x, in->x_scale, s);
       TPO_HIP_CHECK(hipStreamWaitEvent(s, plan->join_ev, 0));
     }
     launch_propagate(*plan, ws, bufp<float>(*plan, ws, B_XPRIME), plan->dp, s);

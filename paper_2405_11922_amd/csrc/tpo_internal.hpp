@@ -87,6 +87,7 @@ struct Plan {
   int64_t E;
   bool reduce;
   bool xbf16;  // X_U is bfloat16
+  bool xfp8;   // X_U is FP8 E4M3 with column scales
   int rowbits, colbits;
   int sort_blocks;          // tiles of the radix sort
   int max_chunks_u, max_chunks_v;
@@ -124,7 +125,7 @@ void launch_ingest(const Plan& p, void* ws, const tpo_inputs* in, hipStream_t s)
 void launch_propagate(const Plan& p, void* ws, const float* xprime, int64_t ldxp,
                       hipStream_t s);
 // k_dense.hip
-void launch_reduce(const Plan& p, void* ws, const void* x, int64_t ldx, hipStream_t s);
+void launch_reduce(const Plan& p, void* ws, const void* x, int64_t ldx, const float* xscale, hipStream_t s);
 void launch_features(const Plan& p, void* ws, hipStream_t s);
 void launch_embed(const Plan& p, void* ws, hipStream_t s);
 // k_smallla.hip (single workgroup, small matrices in LDS, n <= 80)

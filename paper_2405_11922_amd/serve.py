@@ -117,7 +117,7 @@ class Server:
     def _plan(self, job: Job):
         x = job.x_u
         n_u, d_u = x.shape
-        xdt = "bf16" if str(x.dtype) == "torch.bfloat16" else "f32"
+        xdt = tpo._TORCH_XDT.get(str(x.dtype), "f32")
         h = tpo.tpo_plan_create(n_u, job.n_v, job.edge_u.numel(), d_u, weighted=job.edge_w is not None,
                                 x_dtype=xdt, one_stream=True, **job.params)
         return h, tpo.tpo_plan_workspace_bytes(h), barrier_workgroups(h, d_u)

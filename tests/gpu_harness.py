@@ -14,9 +14,11 @@ def log(*a):
 
 
 def gpu_run(abg, *, k, alpha, gamma, d, q=20, oversample=10, t_f=5, t_g=20, seed=0,
-            mm=None, stages=True, device="cuda:0", x_bf16=False, nci="literal"):
+            mm=None, stages=True, device="cuda:0", x_bf16=False, nci="literal", x_fp8=None):
     """Runs the job on the GPU.  Returns a dict of numpy intermediates.
-    x_bf16: hand X over as bfloat16 (its values must be representable)."""
+    x_bf16: hand X over as bfloat16 (its values must be representable).
+    x_fp8: (codes uint8, column scales float32) handed over as FP8 E4M3 in
+    place of abg.x_u (which then holds the encoded values, for the oracle)."""
     import torch
 
     import paper_2405_11922_amd as tpo
@@ -29,6 +31,10 @@ def gpu_run(abg, *, k, alpha, gamma, d, q=20, oversample=10, t_f=5, t_g=20, seed
         xb = x.to(torch.bfloat16)
         assert torch.equal(xb.float(), x), "X is not representable in bfloat16"
         x = xb
+    xs = None
+    if x_fp8 is not None:
+        x = torch.from_numpy(np.ascontiguousarray(x_fp8[0], dtype=np.uint8)).to(dev).view(torch.float8_e4m3fn)
+        xs = torch.from_numpy(np.ascontiguousarray(x_fp8[1], dtype=np.float32)).to(dev)
     ew = None
     if abg.edge_w is not None:
         ew = torch.from_numpy(np.ascontiguousarray(abg.edge_w, dtype=np.float32)).to(dev)
@@ -38,7 +44,7 @@ def gpu_run(abg, *, k, alpha, gamma, d, q=20, oversample=10, t_f=5, t_g=20, seed
     plan = tpo.Plan.create(abg.n_u, abg.n_v, abg.n_edges, abg.d_u, device=dev, k=k, alpha=alpha,
                            gamma=gamma, d=d, q=q, oversample=oversample, t_f=t_f, t_g=t_g,
                            seed=seed, weighted=ew is not None, timing=True,
-                           x_dtype="bf16" if x_bf16 else "f32", nci=nci, **kw)
+                           x_dtype="fp8" if x_fp8 is not None else "bf16" if x_bf16 else "f32", nci=nci, **kw)
     out = {}
     try:
         h, ws = plan.handle, plan.workspace
@@ -47,8 +53,8 @@ def gpu_run(abg, *, k, alpha, gamma, d, q=20, oversample=10, t_f=5, t_g=20, seed
         labels = torch.empty(abg.n_u, dtype=torch.int32, device=dev)
         emb = torch.empty(abg.n_u, k, dtype=torch.float32, device=dev)
         if stages:
-            tpo.tpo_stage_ingest(h, eu, ev, x, ws, edge_w=ew)
-            tpo.tpo_stage_reduce(h, eu, ev, x, ws, edge_w=ew)
+            tpo.tpo_stage_ingest(h, eu, ev, x, ws, edge_w=ew, x_scale=xs)
+            tpo.tpo_stage_reduce(h, eu, ev, x, ws, edge_w=ew, x_scale=xs)
             tpo.tpo_stage_propagate(h, ws)
             tpo.tpo_stage_features(h, ws)
             tpo.tpo_stage_embed(h, ws)
@@ -57,7 +63,7 @@ def gpu_run(abg, *, k, alpha, gamma, d, q=20, oversample=10, t_f=5, t_g=20, seed
             out["objective"] = tpo.tpo_stage_objective(h, ws)
             emb.copy_(plan.buffer("upsilon"))
         else:
-            out["objective"] = tpo.tpo_execute(h, eu, ev, x, ws, labels, emb, edge_w=ew)
+            out["objective"] = tpo.tpo_execute(h, eu, ev, x, ws, labels, emb, edge_w=ew, x_scale=xs)
             out["stats"] = tpo.tpo_plan_stats(h)
         torch.cuda.synchronize()
         out["labels"] = labels.cpu().numpy()

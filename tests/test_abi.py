@@ -83,15 +83,16 @@ def test_status_strings():
 
 
 def test_attribute_dtype_checked():
-    """x_dtype must be TPO_X_F32 (0) or TPO_X_BF16 (1); the binding refuses
-    other names and a tensor whose dtype is not the plan's."""
+    """x_dtype must be TPO_X_F32 (0), TPO_X_BF16 (1) or TPO_X_FP8 (2); the
+    binding refuses other names, a tensor whose dtype is not the plan's, and
+    FP8 attributes without their column scales."""
     import ctypes as C
 
     import torch
 
     lib = tpo.load_library()
     par = tpo.TpoParams(tpo.TPO_ABI_VERSION, 5, 0.5, 3, 0, 20, 10, 5, 20, 0, 0, None, None, None)
-    for xdt, want in ((0, 0), (1, 0), (2, 1), (-1, 1)):
+    for xdt, want in ((0, 0), (1, 0), (2, 0), (3, 1), (-1, 1)):
         prob = tpo.TpoProblem(tpo.TPO_ABI_VERSION, 100, 100, 32, 500, 0, xdt)
         h = C.c_void_p()
         st = lib.tpo_plan_create(C.byref(prob), C.byref(par), C.byref(h))
@@ -99,7 +100,7 @@ def test_attribute_dtype_checked():
         if st == 0:
             lib.tpo_plan_destroy(h)
     with pytest.raises(tpo.TpoError) as e:
-        tpo.tpo_plan_create(100, 100, 500, 32, k=5, alpha=0.5, gamma=3, x_dtype="fp8")
+        tpo.tpo_plan_create(100, 100, 500, 32, k=5, alpha=0.5, gamma=3, x_dtype="fp4")
     assert e.value.status == 1
     h = tpo.tpo_plan_create(100, 100, 500, 32, k=5, alpha=0.5, gamma=3, x_dtype="bf16")
     try:
@@ -108,6 +109,28 @@ def test_attribute_dtype_checked():
         assert e.value.status == 1
     finally:
         tpo.tpo_plan_destroy(h)
+    h = tpo.tpo_plan_create(100, 100, 500, 32, k=5, alpha=0.5, gamma=3, x_dtype="fp8")
+    try:
+        x8 = torch.zeros(100, 32, dtype=torch.float8_e4m3fn)
+        for bad in (None, torch.ones(31), torch.ones(32, dtype=torch.float64)):
+            with pytest.raises(tpo.TpoError) as e:
+                tpo.tpo_stage_reduce(h, None, None, x8, None, x_scale=bad)
+            assert e.value.status == 1
+    finally:
+        tpo.tpo_plan_destroy(h)
+    # the C ABI refuses FP8 inputs without scales before touching any memory
+    prob = tpo.TpoProblem(tpo.TPO_ABI_VERSION, 100, 100, 32, 0, 0, 2)
+    h = C.c_void_p()
+    assert lib.tpo_plan_create(C.byref(prob), C.byref(par), C.byref(h)) == 0
+    try:
+        inp = tpo.TpoInputs(None, None, None, 4096, 32, None)
+        ws = C.c_void_p(1 << 20)  # never dereferenced: the inputs are rejected first
+        nbytes = C.c_size_t()
+        lib.tpo_plan_workspace_bytes(h, C.byref(nbytes))
+        assert lib.tpo_stage_reduce(h, C.byref(inp), ws, nbytes.value, None) == 1
+        assert b"x_scale" in lib.tpo_plan_last_error(h)
+    finally:
+        lib.tpo_plan_destroy(h)
 
 
 def test_serving_stream_recipe():

@@ -230,6 +230,60 @@ def test_stage_parity_bf16(name):
     assert rel < 1e-6
 
 
+def _fp8_inputs(abg):
+    """X encoded as FP8 E4M3 codes with one scale per column; the oracle gets
+    the encoded values (code * scale, exact in FP64)."""
+    codes, scale, values = synth.quantize_e4m3(abg.x_u)
+    abg.x_u = values
+    return abg, (codes, scale)
+
+
+# The FP8 attribute form: X handed over as E4M3 codes plus FP32 column scales.
+# The Gram runs on FP8 MFMA (products of two E4M3 values are exact in FP32)
+# with FP32 sums over each 64-row slab added up in FP64, and the scales
+# s_i s_j applied in FP64, so the Gram's error bound is the bfloat16 form's
+# (64 u per slab); the same Psi_d tolerance applies with d = k.
+CASES_FP8 = {
+    # 96 -> 6: 4-byte row loads (d_U a multiple of 4)
+    "fp8_reduce": (lambda: synth.planted_abg(3001, 4507, 40_000, 6, 96, zipf_a=2.0, seed=1),
+                   dict(k=6, alpha=0.5, gamma=4, d=6)),
+    # 102 -> 8: byte loads (d_U not a multiple of 4), ragged tiles
+    "fp8_odd": (lambda: synth.planted_abg(2500, 2000, 30_000, 8, 102, zipf_a=2.0, seed=6),
+                dict(k=8, alpha=0.6, gamma=3, d=8)),
+    # 512 -> 8: 8 column tiles, 36 tile pairs
+    "fp8_512": (lambda: synth.planted_abg(3000, 4000, 30_000, 8, 512, zipf_a=2.0, seed=14),
+                dict(k=8, alpha=0.5, gamma=3, d=8)),
+    # no reduction: X' is the decoded codes times their scales
+    "fp8_noreduce": (lambda: synth.config_abg(synth.CONFIGS["cpu_scale"], seed=0),
+                     dict(k=5, alpha=0.5, gamma=5, d=0)),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES_FP8))
+def test_stage_parity_fp8(name):
+    make, kw = CASES_FP8[name]
+    abg, x8 = _fp8_inputs(make())
+    log(f"[{name}] n_u={abg.n_u} n_v={abg.n_v} E={abg.n_edges} d_u={abg.d_u} {kw} X FP8 E4M3")
+    ref = oracle_run(abg, **kw)
+    out = gpu_run(abg, **kw, stages=True, x_fp8=x8)
+    _stage_checks(name, abg, ref, out, psi_tol=1e-5)
+    _decision_checks(name, out, kw["k"], kw.get("t_g", 20))
+    same = oracle.labels_match_up_to_permutation(out["labels"], ref.labels)
+    rel = abs(out["objective"][0] - ref.objective) / abs(ref.objective)
+    log(f"[{name}] end to end: labels same up to permutation {same}; objective rel err {rel:.2e}")
+    assert same, name
+    assert rel < 1e-6
+
+
+def test_fp8_execute_equals_stages():
+    make, kw = CASES_FP8["fp8_reduce"]
+    abg, x8 = _fp8_inputs(make())
+    a = gpu_run(abg, **kw, stages=True, x_fp8=x8)
+    b = gpu_run(abg, **kw, stages=False, x_fp8=x8)
+    assert np.array_equal(a["labels"], b["labels"])
+    assert np.array_equal(a["xprime"], b["xprime"])
+
+
 def test_near_tie_input_decisions():
     """64 weakly separated clusters: here NCI's labels are not determined by
     the input at FP32 accuracy (the oracle itself relabels a few percent of
