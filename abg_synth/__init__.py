@@ -176,6 +176,11 @@ CONFIGS: dict[str, JobShape] = {
     # Large graph: 5M x 10M, 150M edges, k = 100, 512 attributes -> 64.
     "large": JobShape("large", 5_000_000, 10_000_000, 150_000_000, k=100, zipf_a=1.9,
                       d_u=512, d=64, gamma=10, max_degree=100_000),
+    # Sparse text-like attributes: 2M x 2M, 60M edges, k = 50, 4,096 TF-IDF
+    # columns at 2% density (tfidf_fp8_device) handed over as FP8 E4M3 with
+    # column scales, reduced to 64.
+    "fp8_tfidf": JobShape("fp8_tfidf", 2_000_000, 2_000_000, 60_000_000, k=50, zipf_a=2.0,
+                          d_u=4096, d=64, gamma=10, max_degree=100_000),
 }
 
 
@@ -317,6 +322,64 @@ def quantize_e4m3(x: np.ndarray):
     codes = q.view(torch.uint8).numpy().copy()
     values = q.to(torch.float64).numpy() * scale.astype(np.float64)[None, :]
     return codes, scale, values
+
+
+def tfidf_fp8_device(labels, d_u: int, *, device, density: float = 0.02, topic_frac: float = 0.5,
+                     zipf_s: float = 1.1, seed: int = 0, chunk: int = 131_072):
+    """Sparse TF-IDF-like attributes for nodes with planted clusters, drawn
+    on a GPU with torch and encoded as FP8 E4M3 with one scale per column.
+
+    * Each row draws round(density * d_u) words with replacement: with
+      probability topic_frac from its cluster's topic (d_u // k columns of a
+      seeded permutation, wrapping), else from a background Zipf(zipf_s) law
+      over a seeded permutation of the columns.
+    * Value = (1 + log tf) * w_j, with w_j = log(1 / p_j) (the background
+      probability's inverse document frequency); rows scaled to unit L2 norm.
+    * Column scale s_j = max_i x_ij / 448; codes = E4M3 round to nearest even
+      of x_ij / s_j (the quantize_e4m3 recipe).
+    Rows are drawn in chunks from per-chunk seeds, twice (column maxima, then
+    codes), so the n x d_u float matrix never exists whole.  Returns (codes
+    uint8 [n, d_u], scales float32 [d_u]) on the device."""
+    import torch
+
+    labels = labels.to(device=device, dtype=torch.int64)
+    n = labels.numel()
+    k = int(labels.max().item()) + 1 if n else 1
+    nnz = max(1, int(round(density * d_u)))
+    gh = torch.Generator().manual_seed(int(seed) * 7919 + 17)
+    ranks = torch.arange(1, d_u + 1, dtype=torch.float64) ** (-zipf_s)
+    p = torch.empty(d_u, dtype=torch.float64)
+    p[torch.randperm(d_u, generator=gh)] = ranks / ranks.sum()
+    w = torch.log(1.0 / p).to(torch.float32).to(device)
+    p_bg = p.to(torch.float32).to(device)
+    t = max(1, d_u // k)
+    topics = (torch.randperm(d_u, generator=gh).repeat((k * t + d_u - 1) // d_u)[: k * t].view(k, t)).to(device)
+    g = torch.Generator(device=device)
+
+    def values(r0, r1):
+        g.manual_seed(int(seed) * 1_000_003 + r0)
+        m = r1 - r0
+        lab = labels[r0:r1]
+        from_topic = torch.rand(m, nnz, generator=g, device=device) < topic_frac
+        tcol = topics[lab][torch.arange(m, device=device)[:, None],
+                           torch.randint(0, t, (m, nnz), generator=g, device=device)]
+        bcol = torch.multinomial(p_bg, m * nnz, replacement=True, generator=g).view(m, nnz)
+        col = torch.where(from_topic, tcol, bcol)
+        tf = torch.zeros(m, d_u, device=device)
+        tf.scatter_add_(1, col, torch.ones(m, nnz, device=device))
+        val = torch.where(tf > 0, (1.0 + torch.log(tf.clamp_min(1.0))) * w[None, :], torch.zeros_like(tf))
+        return val / val.norm(dim=1, keepdim=True).clamp_min(1e-30)
+
+    colmax = torch.zeros(d_u, device=device)
+    for r0 in range(0, n, chunk):
+        colmax = torch.maximum(colmax, values(r0, min(n, r0 + chunk)).amax(dim=0))
+    scale = torch.where(colmax > 0, colmax / 448.0, torch.ones_like(colmax)).to(torch.float32)
+    codes = torch.empty(n, d_u, dtype=torch.uint8, device=device)
+    for r0 in range(0, n, chunk):
+        r1 = min(n, r0 + chunk)
+        q = (values(r0, r1) / scale[None, :]).clamp(-448.0, 448.0).to(torch.float8_e4m3fn)
+        codes[r0:r1] = q.view(torch.uint8)
+    return codes, scale
 
 
 def e4m3_value(code: int) -> float:

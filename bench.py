@@ -173,13 +173,21 @@ def main() -> int:
         return run_serve(args)
     shape = synth.CONFIGS[args.config]
     dev = torch.device("cuda:0")
+    x_scale = None  # column scales of FP8 attributes
     t0 = time.time()
     on_device = shape.n_edges > 20_000_000  # the host generator is too slow beyond this
     if on_device:
-        eu, ev, x, truth, _ = synth.planted_abg_device(shape.n_u, shape.n_v, shape.n_edges, shape.k, shape.d_u,
+        tfidf = args.config == "fp8_tfidf"
+        eu, ev, x, truth, _ = synth.planted_abg_device(shape.n_u, shape.n_v, shape.n_edges, shape.k,
+                                                   1 if tfidf else shape.d_u,
                                                    device=dev, zipf_a=shape.zipf_a, sigma=shape.sigma,
                                                    in_out_ratio=shape.in_out_ratio, max_degree=shape.max_degree,
                                                    seed=args.seed)
+        if tfidf:
+            # the attributes: sparse TF-IDF rows encoded as FP8 E4M3 with column scales
+            del x
+            x, x_scale = synth.tfidf_fp8_device(truth, shape.d_u, device=dev, seed=args.seed)
+            x = x.view(torch.float8_e4m3fn)
         torch.cuda.synchronize()
         truth = truth.cpu().numpy()
         abg = None
@@ -193,7 +201,10 @@ def main() -> int:
         abg_n_edges, abg_d_u = abg.n_edges, abg.d_u
     log(f"[bench] generated {args.config} ({'on the GPU' if on_device else 'on the host'}): n_u={shape.n_u} "
         f"n_v={shape.n_v} E={abg_n_edges} d_u={abg_d_u} in {time.time() - t0:.1f}s")
-    x_dtype = args.x_dtype if args.x_dtype != "auto" else ("bf16" if args.config == "large" else "f32")
+    x_dtype = args.x_dtype if args.x_dtype != "auto" else {"large": "bf16", "fp8_tfidf": "fp8"}.get(args.config, "f32")
+    if (x_dtype == "fp8") != (args.config == "fp8_tfidf"):
+        print("FP8 attributes go with --config fp8_tfidf (and only there)", file=sys.stderr)
+        return 2
     x_f32 = x
     if x_dtype == "bf16":
         x = x_f32.to(torch.bfloat16)
@@ -216,14 +227,14 @@ def main() -> int:
         torch.cuda.synchronize()
         del src, dst
     for _ in range(args.warmup):
-        tpo.tpo_execute(plan.handle, eu, ev, x, plan.workspace, labels, emb)
+        tpo.tpo_execute(plan.handle, eu, ev, x, plan.workspace, labels, emb, x_scale=x_scale)
     torch.cuda.synchronize()
     step_ms = []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for _ in range(args.steps):
         s0 = time.perf_counter()
-        obj = tpo.tpo_execute(plan.handle, eu, ev, x, plan.workspace, labels, emb)
+        obj = tpo.tpo_execute(plan.handle, eu, ev, x, plan.workspace, labels, emb, x_scale=x_scale)
         step_ms.append((time.perf_counter() - s0) * 1e3)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
@@ -233,7 +244,7 @@ def main() -> int:
     # stage breakdown and SpMM kernel timing from an instrumented plan
     stats = []
     for _ in range(3):
-        tpo.tpo_execute(plan_t.handle, eu, ev, x, plan_t.workspace, labels, emb)
+        tpo.tpo_execute(plan_t.handle, eu, ev, x, plan_t.workspace, labels, emb, x_scale=x_scale)
         stats.append(tpo.tpo_plan_stats(plan_t.handle))
     st = {key: statistics.median(s[key] for s in stats) for key in stats[0]}
     log("[bench] stages ms: " + " ".join(f"{k[3:]}={st[k]:.3f}" for k in st if k.startswith("ms_")))
@@ -267,13 +278,17 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if x_dtype == "f32" else "bf16 attributes (BF16 MFMA Gram, FP32 accumulation), f32 path",
+        "dtype": {"f32": "f32", "bf16": "bf16 attributes (BF16 MFMA Gram, FP32 accumulation), f32 path",
+                  "fp8": "fp8 e4m3 attributes with column scales (FP8 MFMA Gram, FP32 accumulation), "
+                         "f32 path"}[x_dtype],
         "data": "synthetic",
         "config": {
             "workload": f"{args.config}: planted degree-corrected bipartite SBM, |U|={shape.n_u}, "
                         f"|V|={shape.n_v}, {abg_n_edges} edges, k={shape.k}, Zipf({shape.zipf_a}) degrees, "
                         f"d_U={abg_d_u} -> d={d_eff}, gamma={shape.gamma}, alpha={shape.alpha}, "
-                        f"q={shape.q}, T_f={shape.t_f}, T_g={shape.t_g}",
+                        f"q={shape.q}, T_f={shape.t_f}, T_g={shape.t_g}"
+                        + (", sparse TF-IDF attributes (2% density, abg_synth.tfidf_fp8_device) as FP8 E4M3 "
+                           "with column scales" if args.config == "fp8_tfidf" else ""),
             "n_u": shape.n_u, "n_v": shape.n_v, "n_edges": abg_n_edges, "k": shape.k, "d_u": abg_d_u,
             "d": d_eff, "k_prime": kp, "l_r": l_r, "gamma": shape.gamma, "x_dtype": x_dtype, "nci": args.nci,
         },

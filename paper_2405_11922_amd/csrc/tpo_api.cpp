@@ -328,8 +328,12 @@ tpo_status tpo_plan_create(const tpo_problem* prob, const tpo_params* par, tpo_p
   p->max_chunks_v = static_cast<int>(maxch);
   const int tiles_x = (p->du + 63) / 64, tiles_r = (p->twod + 63) / 64;
   const int pairs_x = tiles_x * (tiles_x + 1) / 2, pairs_r = tiles_r * (tiles_r + 1) / 2;
+  // row chunks of the Gram partials: about 1024 (chunk, pair) blocks, and a
+  // multiple of 8, at least 8, so that the narrow-type kernels (which give
+  // each XCD whole chunks) keep all eight XCDs busy
   auto chunks_for = [&](int pairs) {
-    int64_t want = std::max<int64_t>(1, 1024 / pairs);
+    int64_t want = std::max<int64_t>(8, 1024 / pairs);
+    want = (want + 7) / 8 * 8;
     int64_t by_rows = std::max<int64_t>(1, (p->n + 255) / 256);
     return static_cast<int>(std::min<int64_t>({want, by_rows, 65535}));
   };

@@ -253,6 +253,11 @@ CASES_FP8 = {
     # 512 -> 8: 8 column tiles, 36 tile pairs
     "fp8_512": (lambda: synth.planted_abg(3000, 4000, 30_000, 8, 512, zipf_a=2.0, seed=14),
                 dict(k=8, alpha=0.5, gamma=3, d=8)),
+    # 1100 -> 8: 69 row tiles of the 1100 x 1100 Gram, more than the 64
+    # workgroups of the subspace iteration, so A is read from global memory
+    # and some workgroups take two row tiles
+    "fp8_1100": (lambda: synth.planted_abg(3000, 3000, 30_000, 8, 1100, zipf_a=2.0, seed=15),
+                 dict(k=8, alpha=0.5, gamma=3, d=8)),
     # no reduction: X' is the decoded codes times their scales
     "fp8_noreduce": (lambda: synth.config_abg(synth.CONFIGS["cpu_scale"], seed=0),
                      dict(k=5, alpha=0.5, gamma=5, d=0)),
