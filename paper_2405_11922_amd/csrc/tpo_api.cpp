@@ -339,7 +339,10 @@ tpo_status tpo_plan_create(const tpo_problem* prob, const tpo_params* par, tpo_p
   };
   p->gram_chunks_x = chunks_for(pairs_x);
   p->gram_chunks_r = chunks_for(pairs_r);
-  p->rowpass_blocks = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>((p->n + 31) / 32, 1024)));
+  // row-pass workgroups (ONMF, features, NCI rounds): two per CU at most;
+  // measured against caps of 256, 384, 1024 and 2048 on the 4M- and
+  // 150M-edge jobs (fewer blocks write fewer FP64 partials per pass)
+  p->rowpass_blocks = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>((p->n + 31) / 32, 512)));
   p->obj_blocks = std::min(p->rowpass_blocks, 256);
   // Gaussian matrices
   if (reduce) {
