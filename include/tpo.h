@@ -243,6 +243,9 @@ typedef enum tpo_buffer_id {
   TPO_BUF_SCALE_V = 22, /* float [n_v] D_V^-1 (0 for isolated nodes) */
   TPO_BUF_RSUM = 23,    /* double [2 d_eff] r = sum_i R'_i (Eq. Ri) */
   TPO_BUF_S = 24,       /* double [2 d_eff x k] S with Gamma = R S */
+  TPO_BUF_GRAM_C = 25,  /* double [d_u x d_u] C = X^T X of the reduction
+                           (EINVAL when the reduction is off) */
+  TPO_BUF_COLSUM_X = 26, /* double [d_u] column sums of X (reduction on) */
   TPO_BUF_COUNT
 } tpo_buffer_id;
 

@@ -36,9 +36,9 @@ BUF = {
     "rowptr_u": 0, "col_u": 1, "val_u": 2, "rowptr_v": 3, "col_v": 4, "val_v": 5,
     "deg_u": 6, "deg_v": 7, "xprime": 8, "psi_d": 9, "z": 10, "q": 11, "r": 12,
     "gamma": 13, "sigma": 14, "psi": 15, "upsilon": 16, "h": 17, "labels": 18,
-    "t": 19, "w_last": 20, "scale_u": 21, "scale_v": 22, "rsum": 23, "s": 24,
+    "t": 19, "w_last": 20, "scale_u": 21, "scale_v": 22, "rsum": 23, "s": 24, "gram_c": 25, "colsum_x": 26,
 }
-_MATRICES = {"xprime", "psi_d", "z", "q", "r", "gamma", "psi", "upsilon", "h", "t", "w_last", "s"}
+_MATRICES = {"xprime", "psi_d", "z", "q", "r", "gamma", "psi", "upsilon", "h", "t", "w_last", "s", "gram_c"}
 EXPORTED = [
     "tpo_plan_create", "tpo_plan_workspace_bytes", "tpo_execute", "tpo_plan_destroy",
     "tpo_status_string", "tpo_plan_last_error", "tpo_plan_stats", "tpo_plan_dims",

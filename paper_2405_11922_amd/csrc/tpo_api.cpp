@@ -449,6 +449,19 @@ tpo_status tpo_plan_buffer(const tpo_plan* plan, void* ws, int32_t which, void**
     case TPO_BUF_SCALE_V: b = B_INV_V; r = p.m; break;
     case TPO_BUF_RSUM: b = B_RSUM; r = p.twod; dt = TPO_DTYPE_F64; break;
     case TPO_BUF_S: b = B_EEVAL; r = p.twod; c = p.k; dt = TPO_DTYPE_F64; break;
+    case TPO_BUF_GRAM_C:
+      if (!p.reduce) return TPO_EINVAL;
+      b = B_C;
+      r = p.du;
+      c = p.du;
+      dt = TPO_DTYPE_F64;
+      break;
+    case TPO_BUF_COLSUM_X:
+      if (!p.reduce) return TPO_EINVAL;
+      b = B_COLSUM_X;
+      r = p.du;
+      dt = TPO_DTYPE_F64;
+      break;
     default: return TPO_EINVAL;
   }
   *ptr = bufp<char>(p, ws, b);
