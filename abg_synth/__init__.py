@@ -325,7 +325,7 @@ def quantize_e4m3(x: np.ndarray):
 
 
 def tfidf_fp8_device(labels, d_u: int, *, device, density: float = 0.02, topic_frac: float = 0.5,
-                     zipf_s: float = 1.1, seed: int = 0, chunk: int = 131_072):
+                     zipf_s: float = 1.1, lognormal_sigma: float = 0.5, seed: int = 0, chunk: int = 131_072):
     """Sparse TF-IDF-like attributes for nodes with planted clusters, drawn
     on a GPU with torch and encoded as FP8 E4M3 with one scale per column.
 
@@ -333,8 +333,10 @@ def tfidf_fp8_device(labels, d_u: int, *, device, density: float = 0.02, topic_f
       probability topic_frac from its cluster's topic (d_u // k columns of a
       seeded permutation, wrapping), else from a background Zipf(zipf_s) law
       over a seeded permutation of the columns.
-    * Value = (1 + log tf) * w_j, with w_j = log(1 / p_j) (the background
-      probability's inverse document frequency); rows scaled to unit L2 norm.
+    * Each draw carries a log-normal weight exp(lognormal_sigma * N(0, 1));
+      value = (sum of the word's weights in the row) * w_j, with
+      w_j = log(1 / p_j) (the background probability's inverse document
+      frequency); rows scaled to unit L2 norm.
     * Column scale s_j = max_i x_ij / 448; codes = E4M3 round to nearest even
       of x_ij / s_j (the quantize_e4m3 recipe).
     Rows are drawn in chunks from per-chunk seeds, twice (column maxima, then
@@ -365,9 +367,10 @@ def tfidf_fp8_device(labels, d_u: int, *, device, density: float = 0.02, topic_f
                            torch.randint(0, t, (m, nnz), generator=g, device=device)]
         bcol = torch.multinomial(p_bg, m * nnz, replacement=True, generator=g).view(m, nnz)
         col = torch.where(from_topic, tcol, bcol)
+        wts = torch.exp(lognormal_sigma * torch.randn(m, nnz, generator=g, device=device))
         tf = torch.zeros(m, d_u, device=device)
-        tf.scatter_add_(1, col, torch.ones(m, nnz, device=device))
-        val = torch.where(tf > 0, (1.0 + torch.log(tf.clamp_min(1.0))) * w[None, :], torch.zeros_like(tf))
+        tf.scatter_add_(1, col, wts)
+        val = tf * w[None, :]
         return val / val.norm(dim=1, keepdim=True).clamp_min(1e-30)
 
     colmax = torch.zeros(d_u, device=device)

@@ -303,6 +303,30 @@ def main() -> int:
     }
     log(f"[bench] planted clusters recovered: {result['quality']}")
 
+    if x_dtype == "fp8":
+        # error of the FP8 path against FP64 arithmetic on the same codes: the
+        # attribute Gram entry by entry, and X' = X Psi_d on sampled rows
+        # (after the timed region; the FP64 Gram is torch's, on the GPU)
+        def plan_t_buf(name):
+            return tpo.tpo_plan_buffer(plan_t.handle, plan_t.workspace, name)
+
+        sc = x_scale.double()
+        c_ref = torch.zeros(abg_d_u, abg_d_u, dtype=torch.float64, device=dev)
+        for r0 in range(0, shape.n_u, 125_000):
+            xd = x[r0:r0 + 125_000].double() * sc[None, :]
+            c_ref += xd.T @ xd
+            del xd
+        gram_rel = float(((plan_t_buf("gram_c") - c_ref).abs() / c_ref.abs().clamp_min(1e-300)).max())
+        del c_ref
+        psi_d = plan_t_buf("psi_d")
+        idx = torch.from_numpy(np.sort(np.random.default_rng(1).choice(shape.n_u, 2000, replace=False))).to(dev)
+        ref = (x[idx].double() * sc[None, :]) @ psi_d
+        got = plan_t_buf("xprime")[idx][:, :psi_d.shape[1]].double()
+        xp_rel = float((got - ref).norm() / ref.norm())
+        result["vs_fp64"] = {"gram_max_rel_err": gram_rel, "xprime_rel_err_sampled_rows": xp_rel}
+        log(f"[bench] FP8 path vs FP64 on the same codes: Gram max entry rel err {gram_rel:.2e}, "
+            f"X' rel err on 2,000 sampled rows {xp_rel:.2e}")
+
     if x_dtype == "bf16" and args.compare_f32:
         # the plain FP32 job on the same graph (X not rounded): how far the
         # precision form moves the result

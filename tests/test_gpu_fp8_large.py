@@ -66,7 +66,12 @@ def test_fp8_workload_properties():
         cs_ref += xd.sum(0)
         del xd
     c_dev = buf("gram_c")
-    err = (c_dev - c_ref).abs()
+    diff = c_dev - c_ref
+    nz = c_ref > 0
+    log(f"[fp8 full] Gram entries below / above the FP64 value: {float((diff[nz] < 0).double().mean()):.3f} / "
+        f"{float((diff[nz] > 0).double().mean()):.3f}; mean signed rel err "
+        f"{float((diff[nz] / c_ref[nz]).mean()):.2e}")
+    err = diff.abs()
     bound = 64.0 * 2.0 ** -24 * c_ref * 1.01 + 1e-300
     worst = float((err / bound).max())
     log(f"[fp8 full] Gram: max |C - C_fp64| / (64 u C) = {worst:.3f}, max rel {float((err / c_ref.clamp_min(1e-300)).max()):.2e}")
