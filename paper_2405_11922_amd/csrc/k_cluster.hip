@@ -721,16 +721,13 @@ template <int KW, int NT, int KB>
 __global__ void __launch_bounds__(NT)
 k_nci_polar(const long long* __restrict__ sums, int k, int64_t n, const DevStatus* __restrict__ st,
             double* __restrict__ Mg, double* __restrict__ Vg, double* __restrict__ phi) {
-  constexpr bool kInLds = KW <= 64;
   __shared__ double A[KW * (KW + 1)];
-  __shared__ double Ml[kInLds ? KW * KW : 1];
-  __shared__ double Vl[kInLds ? KW * KW : 1];
   __shared__ __align__(16) double sh[3 * (KW / 2)];
   __shared__ double fac[KW];
   __shared__ double dl[KW];
   __shared__ double lmax;
-  double* M = kInLds ? Ml : Mg;
-  double* V = kInLds ? Vl : Vg;
+  double* M = Mg;
+  double* V = Vg;
   const int tid = threadIdx.x;
   const int sft = fixed_point_shift(__uint_as_float(st->maxabs_ups_bits), n);
   const double inv_scale = ldexp(1.0, -sft);

@@ -597,9 +597,12 @@ tpo_status tpo_execute(tpo_plan* plan, const tpo_inputs* in, void* ws, size_t by
       }
       TPO_HIP_CHECK(hipEventRecord(plan->fork_ev, s));
       TPO_HIP_CHECK(hipStreamWaitEvent(plan->side, plan->fork_ev, 0));
+      // the reduction is enqueued first: its long few-workgroup kernels
+      // (subspace iteration, Rayleigh-Ritz) then run beside ingest's
+      // whole-GPU sort and scan kernels instead of after them
+      launch_reduce(*plan, ws, in->x_u, in->ld_x, in->x_scale, s);
       launch_ingest(*plan, ws, in, plan->side);
       TPO_HIP_CHECK(hipEventRecord(plan->join_ev, plan->side));
-      launch_reduce(*plan, ws, in->x_u, in->ld_x, in->x_scale, s);
       TPO_HIP_CHECK(hipStreamWaitEvent(s, plan->join_ev, 0));
     }
     launch_propagate(*plan, ws, bufp<float>(*plan, ws, B_XPRIME), plan->dp, s);
