@@ -123,11 +123,11 @@ def _mismatch_fraction(a, b):
     return 1.0 - table[r, c].sum() / a.size
 
 
-def _decision_checks(name, out, k, t_g):
+def _decision_checks(name, out, k, t_g, nci="literal"):
     """The integer-valued steps on the device's own inputs: NCI labels from
     the device's Upsilon (FP64 scores on both sides) must be identical, and
     the objective of the device's labels on the device's R must agree."""
-    lab, _ = oracle.nci(out["upsilon"], t_g)
+    lab, _ = oracle.nci(out["upsilon"], t_g, nci)
     assert np.array_equal(out["labels"], lab), name
     o, t = oracle.objective(out["r"], out["labels"], k)
     rel = abs(out["objective"][0] - o) / abs(o)
@@ -307,23 +307,28 @@ def test_near_tie_input_decisions():
     _decision_checks("near_tie", out, kw["k"], 20)
 
 
-def test_full_size_mid_fp32():
+@pytest.mark.parametrize("nci", ["literal", "procrustes"])
+def test_full_size_mid_fp32(nci):
     """The benchmarked workload at its full size (200,000 x 400,000, 4M edges,
-    d_U 256 -> 64, k 20, 10 hops): every stage against the oracle, the
-    decisions on the device's own inputs, and the end-to-end labels and
-    objective."""
+    d_U 256 -> 64, k 20, 10 hops), with either form of the NCI Phi update:
+    every stage against the oracle, the decisions on the device's own
+    inputs, and the end-to-end labels and objective."""
+    from paper_2405_11922_amd import quality
+
     shape = synth.CONFIGS["mid_fp32"]
     abg = synth.config_abg(shape, seed=0)
     kw = dict(k=shape.k, alpha=shape.alpha, gamma=shape.gamma, d=shape.d, q=shape.q,
-              oversample=shape.oversample, t_f=shape.t_f, t_g=shape.t_g)
-    log(f"[mid_fp32] n_u={abg.n_u} n_v={abg.n_v} E={abg.n_edges} d_u={abg.d_u}")
+              oversample=shape.oversample, t_f=shape.t_f, t_g=shape.t_g, nci=nci)
+    log(f"[mid_fp32 {nci}] n_u={abg.n_u} n_v={abg.n_v} E={abg.n_edges} d_u={abg.d_u}")
     out = gpu_run(abg, **kw, stages=True)
     ref = oracle_run(abg, **kw)
     _stage_checks("mid_fp32", abg, ref, out)
-    _decision_checks("mid_fp32", out, shape.k, shape.t_g)
+    _decision_checks("mid_fp32", out, shape.k, shape.t_g, nci)
     assert oracle.labels_match_up_to_permutation(out["labels"], ref.labels)
     rel = abs(out["objective"][0] - ref.objective) / abs(ref.objective)
-    log(f"[mid_fp32] end to end: objective rel err {rel:.2e}")
+    q = quality.report(abg.labels_u, out["labels"])
+    log(f"[mid_fp32 {nci}] end to end: objective rel err {rel:.2e}; planted clusters ACC {q['acc']:.4f} "
+        f"NMI {q['nmi']:.4f} ARI {q['ari']:.4f}")
     assert rel < 1e-6
 
 
