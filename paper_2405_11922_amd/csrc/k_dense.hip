@@ -329,6 +329,20 @@ __device__ __forceinline__ float fp8_to_f32(uint32_t byte) {
 // 8-byte LDS read.  vec: X 4-byte aligned, ldx and c multiples of 4.
 constexpr int kG8Ld = kGSub + 8;  // LDS stride (bytes) of a staged column
 
+// 4 x 4 byte transpose: out[e] holds byte e of in[0], in[1], in[2], in[3] (in
+// that byte order), by v_perm_b32 (byte i of the result is byte sel_i of the
+// 8-byte value {hi : lo}).
+__device__ __forceinline__ void transpose4x4(const uint32_t (&in)[4], uint32_t (&out)[4]) {
+  const uint32_t x0 = __builtin_amdgcn_perm(in[1], in[0], 0x05010400u);  // in0.b0 in1.b0 in0.b1 in1.b1
+  const uint32_t x1 = __builtin_amdgcn_perm(in[1], in[0], 0x07030602u);  // in0.b2 in1.b2 in0.b3 in1.b3
+  const uint32_t y0 = __builtin_amdgcn_perm(in[3], in[2], 0x05010400u);
+  const uint32_t y1 = __builtin_amdgcn_perm(in[3], in[2], 0x07030602u);
+  out[0] = __builtin_amdgcn_perm(y0, x0, 0x05040100u);
+  out[1] = __builtin_amdgcn_perm(y0, x0, 0x07060302u);
+  out[2] = __builtin_amdgcn_perm(y1, x1, 0x05040100u);
+  out[3] = __builtin_amdgcn_perm(y1, x1, 0x07060302u);
+}
+
 __global__ void __launch_bounds__(256)
 k_gram_part_fp8(const uint8_t* __restrict__ X, int64_t n, int c, int64_t ldx, int ntiles, int rows_per_chunk,
                 int nchunks, int vec, double* __restrict__ part, double* __restrict__ colsum_part) {
@@ -362,9 +376,11 @@ k_gram_part_fp8(const uint8_t* __restrict__ X, int64_t n, int c, int64_t ldx, in
     for (int bb = 0; bb < 2; ++bb) acc[a][bb] = v4d_t{0.0, 0.0, 0.0, 0.0};
   double cs = 0.0;
   // thread tid stages rows 4 (tid >> 4) .. + 3, columns 4 (tid & 15) .. + 3:
-  // the four rows of each column are one 32-bit LDS store
-  uint32_t ra[4], rb[4];
-  auto fetch = [&](int64_t r0) {
+  // the four rows of each column are one 32-bit LDS store.  Two slabs are in
+  // flight in registers (buffers A and B, used alternately by the unrolled
+  // loop below), so a slab's loads have two slabs of work to arrive.
+  uint32_t raA[4], rbA[4], raB[4], rbB[4];
+  auto fetch = [&](int64_t r0, uint32_t (&ra)[4], uint32_t (&rb)[4]) {
     const int rr = 4 * (tid >> 4), cg = 4 * (tid & 15);
     const int ca = ti * kGT + cg, cb = tj * kGT + cg;
     uint32_t wa[4], wb[4];  // row h: the bytes of columns cg .. cg + 3
@@ -384,16 +400,13 @@ k_gram_part_fp8(const uint8_t* __restrict__ X, int64_t n, int c, int64_t ldx, in
         }
       }
     }
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      ra[e] = ((wa[0] >> (8 * e)) & 0xffu) | (((wa[1] >> (8 * e)) & 0xffu) << 8) |
-              (((wa[2] >> (8 * e)) & 0xffu) << 16) | (((wa[3] >> (8 * e)) & 0xffu) << 24);
-      rb[e] = ((wb[0] >> (8 * e)) & 0xffu) | (((wb[1] >> (8 * e)) & 0xffu) << 8) |
-              (((wb[2] >> (8 * e)) & 0xffu) << 16) | (((wb[3] >> (8 * e)) & 0xffu) << 24);
-    }
+    transpose4x4(wa, ra);
+    transpose4x4(wb, rb);
   };
-  if (r_beg < r_end) fetch(r_beg);
-  for (int64_t r0 = r_beg; r0 < r_end; r0 += kGSub) {
+  if (r_beg < r_end) fetch(r_beg, raA, rbA);
+  if (r_beg + kGSub < r_end) fetch(r_beg + kGSub, raB, rbB);
+  // one slab: stage the buffer, refill it with the slab two ahead, multiply
+  auto slab = [&](int64_t r0, uint32_t (&ra)[4], uint32_t (&rb)[4]) {
     {
       const int rr = 4 * (tid >> 4), cg = 4 * (tid & 15);
 #pragma unroll
@@ -403,7 +416,7 @@ k_gram_part_fp8(const uint8_t* __restrict__ X, int64_t n, int c, int64_t ldx, in
       }
     }
     __syncthreads();
-    if (r0 + kGSub < r_end) fetch(r0 + kGSub);
+    if (r0 + 2 * kGSub < r_end) fetch(r0 + 2 * kGSub, ra, rb);
     v4f_t s32[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -434,6 +447,10 @@ k_gram_part_fp8(const uint8_t* __restrict__ X, int64_t n, int c, int64_t ldx, in
       for (int rr = w; rr < kGSub; rr += 4) cs += static_cast<double>(fp8_to_f32(At[lane * kG8Ld + rr]));
     }
     __syncthreads();
+  };
+  for (int64_t r0 = r_beg; r0 < r_end; r0 += 2 * kGSub) {
+    slab(r0, raA, rbA);
+    if (r0 + kGSub < r_end) slab(r0 + kGSub, raB, rbB);  // uniform
   }
   double* out = part + (static_cast<int64_t>(chunk) * npairs + pair) * kGT * kGT;
 #pragma unroll
