@@ -815,6 +815,176 @@ __global__ void k_pad_copy(const XT* __restrict__ X, int64_t n, int du, int64_t 
   out[i] = v;
 }
 
+// Narrow attributes (bfloat16, or FP8 E4M3, both exact in bfloat16): X' =
+// X diag(s) Psi_d on BF16 MFMA 16x16x32.  Psi~ = diag(s) Psi_d is split once
+// into three bfloat16 parts hi + mid + lo (each the round-to-nearest of what
+// the previous parts leave, in FP64: 24 significant bits in all), stored
+// transposed (part, column n, k) so that the B operand's eight consecutive k
+// are one 16-byte read.  Products of two bfloat16 values are exact in FP32;
+// hi goes to one set of FP32 accumulators, mid and lo to another, added at
+// the end.  The A operand (eight consecutive columns of one row) is read
+// straight from row-major X staged in LDS, no transpose.
+__device__ __forceinline__ uint16_t f32_to_bf16_rn(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return static_cast<uint16_t>((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+__global__ void k_psi_split(const double* __restrict__ psi, const float* __restrict__ scale, int du, int d, int dp,
+                            int dup, uint16_t* __restrict__ out) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= static_cast<int64_t>(dp) * dup) return;
+  const int n = static_cast<int>(i / dup), k = static_cast<int>(i % dup);
+  double v = (n < d && k < du) ? psi[static_cast<int64_t>(k) * d + n] : 0.0;
+  if (scale && k < du) v *= static_cast<double>(scale[k]);
+  const uint16_t hi = f32_to_bf16_rn(static_cast<float>(v));
+  const double r1 = v - static_cast<double>(__uint_as_float(static_cast<uint32_t>(hi) << 16));
+  const uint16_t mid = f32_to_bf16_rn(static_cast<float>(r1));
+  const double r2 = r1 - static_cast<double>(__uint_as_float(static_cast<uint32_t>(mid) << 16));
+  const uint16_t lo = f32_to_bf16_rn(static_cast<float>(r2));
+  const int64_t plane = static_cast<int64_t>(dp) * dup;
+  out[i] = hi;
+  out[plane + i] = mid;
+  out[2 * plane + i] = lo;
+}
+
+constexpr int kPsK = 32;         // columns of X per slab
+constexpr int kPsLd = kPsK + 8;  // LDS row stride (bfloat16 elements; 80 bytes)
+
+// A narrow attribute as bfloat16 (raw bits).
+__device__ __forceinline__ uint16_t narrow_to_bf16(uint16_t v) { return v; }
+__device__ __forceinline__ uint16_t narrow_to_bf16(uint8_t v) {
+  return static_cast<uint16_t>(__float_as_uint(fp8_to_f32(v)) >> 16);  // exact: E4M3 is a subset of bfloat16
+}
+__device__ __forceinline__ bool bf16_finite(uint16_t b) { return (b & 0x7f80u) != 0x7f80u; }
+
+template <int CT, typename XT>
+__global__ void __launch_bounds__(256)
+k_project_split(const XT* __restrict__ X, int64_t n, int du, int64_t ldx, const uint16_t* __restrict__ psit, int dp,
+                int dup, float* __restrict__ out, int32_t* __restrict__ err_bits, int vec) {
+  constexpr int NC = 16 * CT;
+  __shared__ __align__(16) uint16_t xs[kPjRows * kPsLd];
+  __shared__ __align__(16) uint16_t ps[3 * NC * kPsLd];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int i16 = lane & 15, kq = lane >> 4;
+  const int64_t row0 = static_cast<int64_t>(blockIdx.x) * kPjRows;
+  const int64_t plane = static_cast<int64_t>(dp) * dup;
+  v4f_t acc_hi[CT], acc_lo[CT];
+#pragma unroll
+  for (int t = 0; t < CT; ++t) acc_hi[t] = acc_lo[t] = v4f_t{0.f, 0.f, 0.f, 0.f};
+  bool bad = false;
+  for (int k0 = 0; k0 < du; k0 += kPsK) {
+    {  // X: thread tid stages row tid / 4, columns 8 (tid % 4) .. + 7
+      const int rr = tid >> 2, c0 = 8 * (tid & 3);
+      const int64_t row = row0 + rr;
+      uint16_t v[8];
+      if (vec) {  // one 16-byte (bfloat16) or 8-byte (FP8) load; d_u is a multiple of 8
+        const bool in = row < n && k0 + c0 < du;
+        if constexpr (sizeof(XT) == 2) {
+          v4u_t raw = {0u, 0u, 0u, 0u};
+          if (in) raw = *reinterpret_cast<const v4u_t*>(X + row * ldx + k0 + c0);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            v[2 * j] = static_cast<uint16_t>(raw[j] & 0xffffu);
+            v[2 * j + 1] = static_cast<uint16_t>(raw[j] >> 16);
+          }
+        } else {
+          uint2 raw = make_uint2(0u, 0u);
+          if (in) raw = *reinterpret_cast<const uint2*>(X + row * ldx + k0 + c0);
+          const uint32_t wd[2] = {raw.x, raw.y};
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            // exact decodes, two bytes at a time (E4M3 is a subset of bfloat16)
+            const auto lo2 = __builtin_amdgcn_cvt_pk_f32_fp8(static_cast<int>(wd[h]), false);
+            const auto hi2 = __builtin_amdgcn_cvt_pk_f32_fp8(static_cast<int>(wd[h]), true);
+            v[4 * h + 0] = static_cast<uint16_t>(__float_as_uint(lo2[0]) >> 16);
+            v[4 * h + 1] = static_cast<uint16_t>(__float_as_uint(lo2[1]) >> 16);
+            v[4 * h + 2] = static_cast<uint16_t>(__float_as_uint(hi2[0]) >> 16);
+            v[4 * h + 3] = static_cast<uint16_t>(__float_as_uint(hi2[1]) >> 16);
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if (!bf16_finite(v[j])) {
+            bad = true;
+            v[j] = 0;
+          }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int c = k0 + c0 + j;
+          uint16_t b = (row < n && c < du) ? narrow_to_bf16(X[row * ldx + c]) : uint16_t{0};
+          if (!bf16_finite(b)) {
+            bad = true;
+            b = 0;
+          }
+          v[j] = b;
+        }
+      }
+      v4u_t wv;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) wv[j] = static_cast<uint32_t>(v[2 * j]) | (static_cast<uint32_t>(v[2 * j + 1]) << 16);
+      *reinterpret_cast<v4u_t*>(xs + rr * kPsLd + c0) = wv;
+    }
+    // the three parts of Psi~ for columns k0 .. k0 + 31 (dup is a multiple of
+    // 8, zero beyond d_u), 16-byte pieces
+    for (int e = tid; e < 3 * NC * (kPsK / 8); e += 256) {
+      const int part = e / (NC * (kPsK / 8)), rem = e - part * (NC * (kPsK / 8));
+      const int nn = rem / (kPsK / 8), q = rem - nn * (kPsK / 8);
+      const int kk = k0 + 8 * q;
+      v4u_t wv = {0u, 0u, 0u, 0u};
+      if (nn < dp && kk < dup)
+        wv = *reinterpret_cast<const v4u_t*>(psit + part * plane + static_cast<int64_t>(nn) * dup + kk);
+      *reinterpret_cast<v4u_t*>(ps + (part * NC + nn) * kPsLd + 8 * q) = wv;
+    }
+    __syncthreads();
+    const v8bf_t a = __builtin_bit_cast(v8bf_t, *reinterpret_cast<const v4u_t*>(xs + (16 * w + i16) * kPsLd + 8 * kq));
+#pragma unroll
+    for (int t = 0; t < CT; ++t) {
+      const int nn = 16 * t + i16;
+      const v8bf_t bh = __builtin_bit_cast(v8bf_t, *reinterpret_cast<const v4u_t*>(ps + nn * kPsLd + 8 * kq));
+      const v8bf_t bm = __builtin_bit_cast(v8bf_t, *reinterpret_cast<const v4u_t*>(ps + (NC + nn) * kPsLd + 8 * kq));
+      const v8bf_t bl = __builtin_bit_cast(v8bf_t, *reinterpret_cast<const v4u_t*>(ps + (2 * NC + nn) * kPsLd + 8 * kq));
+      acc_hi[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bh, acc_hi[t], 0, 0, 0);
+      acc_lo[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bl, acc_lo[t], 0, 0, 0);
+      acc_lo[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bm, acc_lo[t], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  if (bad) atomicOr(err_bits, 4);
+#pragma unroll
+  for (int t = 0; t < CT; ++t) {
+    const int col = 16 * t + i16;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t row = row0 + 16 * w + 4 * kq + v;
+      if (row < n && col < dp) out[row * dp + col] = acc_hi[t][v] + acc_lo[t][v];
+    }
+  }
+}
+
+template <typename XT>
+static void project_split(const Plan& p, void* ws, const XT* x, int64_t ldx, const float* sc, float* xp, int32_t* err,
+                          hipStream_t s) {
+  if (p.dp > 128) throw std::runtime_error("narrow-attribute projection: padded width above 128");
+  const int dup = (p.du + 7) / 8 * 8;
+  uint16_t* pst = bufp<uint16_t>(p, ws, B_PSI_SPLIT);
+  const int64_t cnt = static_cast<int64_t>(p.dp) * dup;
+  hipLaunchKernelGGL(k_psi_split, dim3(ceil_div(cnt, 256)), dim3(256), 0, s, bufp<double>(p, ws, B_PSI_D), sc, p.du,
+                     p.d, p.dp, dup, pst);
+  TPO_LAUNCH_CHECK();
+  const dim3 grid(ceil_div(p.n, kPjRows));
+  const int64_t n = p.n;
+  // word loads: eight elements (16 or 8 bytes) aligned to their size
+  const int vec = (reinterpret_cast<uintptr_t>(x) % (8 * sizeof(XT)) == 0 && ldx % 8 == 0 && p.du % 8 == 0) ? 1 : 0;
+  switch ((p.dp + 15) / 16) {
+    case 1: hipLaunchKernelGGL((k_project_split<1, XT>), grid, dim3(256), 0, s, x, n, p.du, ldx, pst, p.dp, dup, xp, err, vec); break;
+    case 2: hipLaunchKernelGGL((k_project_split<2, XT>), grid, dim3(256), 0, s, x, n, p.du, ldx, pst, p.dp, dup, xp, err, vec); break;
+    case 4: hipLaunchKernelGGL((k_project_split<4, XT>), grid, dim3(256), 0, s, x, n, p.du, ldx, pst, p.dp, dup, xp, err, vec); break;
+    default: hipLaunchKernelGGL((k_project_split<8, XT>), grid, dim3(256), 0, s, x, n, p.du, ldx, pst, p.dp, dup, xp, err, vec); break;
+  }
+  TPO_LAUNCH_CHECK();
+}
+
 template <typename XT>
 static void project(const Plan& p, const XT* x, int64_t ldx, const float* sc, const float* psi32, float* xp,
                     int32_t* err, hipStream_t s) {
@@ -880,9 +1050,9 @@ void launch_reduce(const Plan& p, void* ws, const void* x, int64_t ldx, const fl
   }
   const float* psi32 = bufp<float>(p, ws, B_PSI_D32);
   if (xdt == 2)
-    project(p, static_cast<const uint8_t*>(x), ldx, xscale, psi32, xp, &st->err_bits, s);
+    project_split(p, ws, static_cast<const uint8_t*>(x), ldx, xscale, xp, &st->err_bits, s);
   else if (xdt == 1)
-    project(p, static_cast<const uint16_t*>(x), ldx, nullptr, psi32, xp, &st->err_bits, s);
+    project_split(p, ws, static_cast<const uint16_t*>(x), ldx, nullptr, xp, &st->err_bits, s);
   else
     project(p, static_cast<const float*>(x), ldx, nullptr, psi32, xp, &st->err_bits, s);
 }

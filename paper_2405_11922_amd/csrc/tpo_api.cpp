@@ -126,6 +126,9 @@ void build_layout(Plan& p) {
   add(B_EVAL, 8 * std::max(lr, d));
   add(B_PSI_D, 8 * du * d);
   add(B_PSI_D32, 4 * du * dp);
+  // narrow attributes: diag(scale) Psi_d split into three bfloat16 parts,
+  // transposed (3 x dp x d_u rounded up to 8)
+  add(B_PSI_SPLIT, (p.xbf16 || p.xfp8) && p.reduce ? 2 * 3 * dp * ((du + 7) / 8 * 8) : 8);
   add(B_XPRIME, 4 * n * dp);
   add(B_W0, 4 * n * dp);
   add(B_W1, 4 * n * dp);

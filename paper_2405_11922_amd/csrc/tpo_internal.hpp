@@ -56,7 +56,7 @@ enum Buf {
   B_PARTIAL,                      // hub chunk partial sums (max chunks x d)
   // reduce
   B_GRAM_PART, B_COLSUM_PART, B_C, B_COLSUM_X, B_MR_A, B_MR_B, B_SMALL_A,
-  B_SMALL_B, B_SMALL_C, B_EVAL, B_PSI_D, B_PSI_D32, B_XPRIME,
+  B_SMALL_B, B_SMALL_C, B_EVAL, B_PSI_D, B_PSI_D32, B_PSI_SPLIT, B_XPRIME,
   // propagate
   B_W0, B_W1, B_T, B_Z,
   // features
