@@ -572,7 +572,7 @@ constexpr int kNciAccBatch = 8;
 __global__ void __launch_bounds__(1024)
 k_nci_accum_wide(const float* __restrict__ U, int64_t n, int k, const int32_t* __restrict__ labels,
                  long long* __restrict__ part, int64_t rows_per_block, const DevStatus* __restrict__ st) {
-  __shared__ long long accl[kNciWide * kNciWide + kNciWide];
+  extern __shared__ long long accl[];  // k x k sums, then k counts (dynamic: sized to k)
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int sft = fixed_point_shift(__uint_as_float(st->maxabs_ups_bits), n);
   for (int e = tid; e < k * k + k; e += 1024) accl[e] = 0;
@@ -805,8 +805,13 @@ static void nci_rounds_wide(const Plan& p, void* ws, hipStream_t s) {
   long long* part = bufp<long long>(p, ws, B_NCI_PART);
   long long* sums = bufp<long long>(p, ws, B_NCI_SUM);
   const int64_t n = static_cast<int64_t>(p.n);
-  // one accumulation workgroup per CU at most, 64-row runs per wave
-  const int nb = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>({(n + 63) / 64, 256,
+  // the label sums' LDS is sized to k, so up to k = 64 two accumulation
+  // workgroups share a CU; 64-row runs per wave
+  const size_t acc_lds = static_cast<size_t>(k * k + k) * sizeof(long long);
+  TPO_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_nci_accum_wide),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(acc_lds)));
+  const int64_t per_cu = acc_lds <= 80 * 1024 ? 2 : 1;
+  const int nb = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>({(n + 63) / 64, 256 * per_cu,
                                                                            static_cast<int64_t>(p.rowpass_blocks)})));
   const int64_t rpb = ((n + nb - 1) / nb + 63) / 64 * 64;
   const float* U = bufp<float>(p, ws, B_UPS);
@@ -826,7 +831,7 @@ static void nci_rounds_wide(const Plan& p, void* ws, hipStream_t s) {
       default: throw std::runtime_error("NCI: k outside 33..128 on the two-kernel path");
     }
     if (t < p.par.t_g) {
-      hipLaunchKernelGGL(k_nci_accum_wide, dim3(nb), dim3(1024), 0, s, U, n, k, labels, part, rpb, st);
+      hipLaunchKernelGGL(k_nci_accum_wide, dim3(nb), dim3(1024), acc_lds, s, U, n, k, labels, part, rpb, st);
       TPO_LAUNCH_CHECK();
       sum_parts_i64(part, nb, k * k + k, sums, s);
     }
