@@ -13,7 +13,9 @@
  *    addresses on the current device; "host" pointers are ordinary memory.
  *  - The caller owns every input, output and workspace buffer.  The library
  *    never allocates device memory (no hipMalloc); a plan owns host metadata
- *    only.  Inputs are read-only and not retained after a call returns.
+ *    only.  (tpo_execute_noalloc uses a fixed device array of the library's
+ *    own instead of a caller workspace.)  Inputs are read-only and not
+ *    retained after a call returns.
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *    Work is enqueued on it; tpo_execute synchronises it before returning.
  *  - All arguments are validated before the first launch; on error nothing
@@ -172,6 +174,23 @@ tpo_status tpo_plan_stats(const tpo_plan* plan, tpo_stats* out);
  * no reduction), the embedding sketch width k'. */
 tpo_status tpo_plan_dims(const tpo_plan* plan, int32_t* d_eff, int32_t* l_r,
                          int32_t* k_prime);
+
+/* For callers that cannot allocate device memory (code under HIP stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): tpo_execute
+ * with the workspace taken from a device array of TPO_NOALLOC_MAX_BYTES that
+ * the library holds on each GPU it runs on until the process ends.  The
+ * caller still passes inputs and outputs as for tpo_execute; the kernels are
+ * the same.  Calls no hipMalloc/hipFree and creates no stream or event: the
+ * plan must not have TPO_FLAG_TIMING (TPO_EINVAL), and everything runs on
+ * `stream`, which is synchronised before returning.  A job whose
+ * tpo_plan_workspace_bytes() exceeds TPO_NOALLOC_MAX_BYTES gets TPO_ENOMEM
+ * before any device work.  All calls on one GPU share that GPU's array,
+ * which keeps the last call's contents: calls that overlap on one GPU race
+ * and must be serialised by the caller.  Other errors as tpo_execute; after
+ * the call, tpo_plan_buffer on the array is not available. */
+#define TPO_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+tpo_status tpo_execute_noalloc(tpo_plan* plan, const tpo_inputs* in, void* stream,
+                               const tpo_outputs* out);
 
 /* ---- Stage entry points -------------------------------------------------
  * tpo_execute is exactly these calls in this order.  Each works on the

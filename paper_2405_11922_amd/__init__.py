@@ -19,13 +19,14 @@ __all__ = [
     "tpo_execute", "tpo_stage_ingest", "tpo_stage_reduce", "tpo_stage_propagate",
     "tpo_stage_features", "tpo_stage_embed", "tpo_stage_onmf", "tpo_stage_nci",
     "tpo_stage_objective", "tpo_plan_buffer", "tpo_plan_stats", "tpo_draw_normals",
-    "tpo_status_string", "BUF", "Plan", "cluster",
+    "tpo_status_string", "BUF", "Plan", "cluster", "tpo_execute_noalloc", "TPO_NOALLOC_MAX_BYTES",
 ]
 
 TPO_ABI_VERSION = 2
 TPO_FLAG_TIMING = 1
 TPO_FLAG_ONE_STREAM = 2
 TPO_FLAG_NCI_PROCRUSTES = 4
+TPO_NOALLOC_MAX_BYTES = 64 << 20  # the device array behind tpo_execute_noalloc
 NCI_VARIANTS = ("literal", "procrustes")
 _HERE = os.path.dirname(os.path.abspath(__file__))
 lib_path = os.path.join(_HERE, "libtpo.so")
@@ -44,7 +45,7 @@ EXPORTED = [
     "tpo_status_string", "tpo_plan_last_error", "tpo_plan_stats", "tpo_plan_dims",
     "tpo_stage_ingest", "tpo_stage_reduce", "tpo_stage_propagate", "tpo_stage_features",
     "tpo_stage_embed", "tpo_stage_onmf", "tpo_stage_nci", "tpo_stage_objective",
-    "tpo_plan_buffer", "tpo_draw_normals", "tpo_abi_version",
+    "tpo_plan_buffer", "tpo_draw_normals", "tpo_abi_version", "tpo_execute_noalloc",
 ]
 
 
@@ -109,6 +110,7 @@ def load_library() -> C.CDLL:
     lib.tpo_plan_workspace_bytes.argtypes = [vp, C.POINTER(sz)]
     lib.tpo_plan_dims.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
     lib.tpo_execute.argtypes = [vp, C.POINTER(TpoInputs), vp, sz, vp, C.POINTER(TpoOutputs)]
+    lib.tpo_execute_noalloc.argtypes = [vp, C.POINTER(TpoInputs), vp, C.POINTER(TpoOutputs)]
     lib.tpo_plan_destroy.argtypes = [vp]
     lib.tpo_plan_destroy.restype = None
     lib.tpo_status_string.argtypes = [C.c_int]
@@ -239,6 +241,20 @@ def tpo_execute(plan, edge_u, edge_v, x_u, workspace, labels, embedding=None, ed
                      C.cast(obj, C.POINTER(C.c_double)))
     _check(lib.tpo_execute(plan, C.byref(inp), workspace.data_ptr(), workspace.numel() * workspace.element_size(),
                            _stream(stream), C.byref(out)), plan)
+    return float(obj[0]), float(obj[1])
+
+
+def tpo_execute_noalloc(plan, edge_u, edge_v, x_u, labels, embedding=None, edge_w=None,
+                        stream=None, x_scale=None):
+    """tpo_execute with the library's own device array as the workspace (no
+    allocation anywhere in the call); returns (obj1, trace form)."""
+    lib = load_library()
+    inp = _inputs(edge_u, edge_v, x_u, edge_w, plan, x_scale)
+    obj = (C.c_double * 2)()
+    out = TpoOutputs(labels.data_ptr() if labels is not None else None,
+                     embedding.data_ptr() if embedding is not None else None,
+                     C.cast(obj, C.POINTER(C.c_double)))
+    _check(lib.tpo_execute_noalloc(plan, C.byref(inp), _stream(stream), C.byref(out)), plan)
     return float(obj[0]), float(obj[1])
 
 

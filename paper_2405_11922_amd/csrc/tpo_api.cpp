@@ -15,8 +15,6 @@
 
 using namespace tpo;
 
-struct tpo_plan : public Plan {};
-
 namespace {
 
 constexpr int kMaxK = 128;
@@ -261,6 +259,116 @@ bool valid_inputs(tpo_plan* p, const tpo_inputs* in, std::string* why) {
 }
 
 }  // namespace
+
+tpo_status tpo::execute_plan(tpo_plan* plan, const tpo_inputs* in, void* ws, size_t bytes, hipStream_t s,
+                             const tpo_outputs* out, bool no_alloc) {
+  if (!plan) return TPO_EINVAL;
+  tpo_status st = check_ws(plan, ws, bytes);
+  if (st != TPO_OK) return st;
+  std::string why;
+  if (!valid_inputs(plan, in, &why)) return fail(plan, TPO_EINVAL, why);
+  if (!out || !out->labels) return fail(plan, TPO_EINVAL, "outputs or labels are NULL");
+  const bool timing = (plan->par.flags & TPO_FLAG_TIMING) != 0;
+  if (no_alloc && timing) return fail(plan, TPO_EINVAL, "a plan with TPO_FLAG_TIMING creates events; use one without");
+  DevStatus& host = plan->host_status;
+  st = guarded(plan, [&] {
+    if (timing && !plan->events_made) {
+      for (auto& e : plan->ev) TPO_HIP_CHECK(hipEventCreate(&e));
+      for (auto& e : plan->kev) TPO_HIP_CHECK(hipEventCreate(&e));
+      plan->events_made = true;
+      plan->kev_made = true;
+    }
+    auto mark = [&](int i) {
+      if (timing) TPO_HIP_CHECK(hipEventRecord(plan->ev[i], s));
+    };
+    upload_inputs(plan, ws, s);
+    mark(0);
+    if (timing || no_alloc || (plan->par.flags & TPO_FLAG_ONE_STREAM)) {
+      // stage by stage on one stream (timing: so that each stage's time is its own)
+      launch_ingest(*plan, ws, in, s);
+      mark(1);
+      launch_reduce(*plan, ws, in->x_u, in->ld_x, in->x_scale, s);
+      mark(2);
+    } else {
+      // ingest (edges only) and the attribute reduction (X only) are
+      // independent: ingest runs on a second stream beside the reduction's
+      // chain of small dependent kernels
+      if (!plan->side_made) {
+        TPO_HIP_CHECK(hipStreamCreateWithFlags(&plan->side, hipStreamNonBlocking));
+        TPO_HIP_CHECK(hipEventCreateWithFlags(&plan->fork_ev, hipEventDisableTiming));
+        TPO_HIP_CHECK(hipEventCreateWithFlags(&plan->join_ev, hipEventDisableTiming));
+        plan->side_made = true;
+      }
+      TPO_HIP_CHECK(hipEventRecord(plan->fork_ev, s));
+      TPO_HIP_CHECK(hipStreamWaitEvent(plan->side, plan->fork_ev, 0));
+      // the reduction is enqueued first: its long few-workgroup kernels
+      // (subspace iteration, Rayleigh-Ritz) then run beside ingest's
+      // whole-GPU sort and scan kernels instead of after them
+      launch_reduce(*plan, ws, in->x_u, in->ld_x, in->x_scale, s);
+      launch_ingest(*plan, ws, in, plan->side);
+      TPO_HIP_CHECK(hipEventRecord(plan->join_ev, plan->side));
+      TPO_HIP_CHECK(hipStreamWaitEvent(s, plan->join_ev, 0));
+    }
+    launch_propagate(*plan, ws, bufp<float>(*plan, ws, B_XPRIME), plan->dp, s);
+    mark(3);
+    launch_features(*plan, ws, s);
+    mark(4);
+    launch_embed(*plan, ws, s);
+    mark(5);
+    launch_onmf(*plan, ws, s);
+    mark(6);
+    launch_nci(*plan, ws, s);
+    mark(7);
+    launch_objective(*plan, ws, s);
+    mark(8);
+    TPO_HIP_CHECK(hipMemcpyAsync(out->labels, bufp<int32_t>(*plan, ws, B_LABELS), sizeof(int32_t) * plan->n,
+                                 hipMemcpyDeviceToDevice, s));
+    if (out->embedding)
+      TPO_HIP_CHECK(hipMemcpyAsync(out->embedding, bufp<float>(*plan, ws, B_UPS),
+                                   sizeof(float) * static_cast<size_t>(plan->n) * plan->k, hipMemcpyDeviceToDevice, s));
+    TPO_HIP_CHECK(hipMemcpyAsync(&host, bufp<char>(*plan, ws, B_STATUS), sizeof(host), hipMemcpyDeviceToHost, s));
+    TPO_HIP_CHECK(hipStreamSynchronize(s));
+    if (timing) {
+      float ms[8];
+      for (int i = 0; i < 8; ++i) TPO_HIP_CHECK(hipEventElapsedTime(&ms[i], plan->ev[i], plan->ev[i + 1]));
+      tpo_stats& S = plan->stats;
+      S.ms_ingest = ms[0];
+      S.ms_reduce = ms[1];
+      S.ms_propagate = ms[2];
+      S.ms_features = ms[3];
+      S.ms_embed = ms[4];
+      S.ms_onmf = ms[5];
+      S.ms_nci = ms[6];
+      S.ms_objective = ms[7];
+      float tot;
+      TPO_HIP_CHECK(hipEventElapsedTime(&tot, plan->ev[0], plan->ev[8]));
+      S.ms_total = tot;
+      const int hops = std::min(plan->par.gamma, kMaxTimedHops);
+      S.ms_spmm_v = S.ms_spmm_u = 0.0;
+      for (int h = 0; h < hops; ++h) {
+        float a, b;
+        TPO_HIP_CHECK(hipEventElapsedTime(&a, plan->kev[4 * h], plan->kev[4 * h + 1]));
+        TPO_HIP_CHECK(hipEventElapsedTime(&b, plan->kev[4 * h + 2], plan->kev[4 * h + 3]));
+        S.ms_spmm_v += a;
+        S.ms_spmm_u += b;
+      }
+      S.n_spmm_v = S.n_spmm_u = hops;
+    }
+  });
+  if (st != TPO_OK) return st;
+  plan->stats.n_unique_edges = host.n_unique;
+  plan->stats.guard_hits = host.guard_hits;
+  plan->stats.isolated_u = host.iso_u;
+  plan->stats.isolated_v = host.iso_v;
+  if (out->objective) {
+    out->objective[0] = host.objective[0];
+    out->objective[1] = host.objective[1];
+  }
+  return map_bits(plan, host.err_bits);
+}
+
+
+tpo_status tpo::plan_fail(tpo_plan* plan, tpo_status st, const std::string& msg) { return fail(plan, st, msg); }
 
 extern "C" {
 
@@ -561,109 +669,7 @@ tpo_status tpo_stage_objective(tpo_plan* plan, void* ws, size_t bytes, void* str
 
 tpo_status tpo_execute(tpo_plan* plan, const tpo_inputs* in, void* ws, size_t bytes, void* stream,
                        const tpo_outputs* out) {
-  if (!plan) return TPO_EINVAL;
-  tpo_status st = check_ws(plan, ws, bytes);
-  if (st != TPO_OK) return st;
-  std::string why;
-  if (!valid_inputs(plan, in, &why)) return fail(plan, TPO_EINVAL, why);
-  if (!out || !out->labels) return fail(plan, TPO_EINVAL, "outputs or labels are NULL");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const bool timing = (plan->par.flags & TPO_FLAG_TIMING) != 0;
-  DevStatus& host = plan->host_status;
-  st = guarded(plan, [&] {
-    if (timing && !plan->events_made) {
-      for (auto& e : plan->ev) TPO_HIP_CHECK(hipEventCreate(&e));
-      for (auto& e : plan->kev) TPO_HIP_CHECK(hipEventCreate(&e));
-      plan->events_made = true;
-      plan->kev_made = true;
-    }
-    auto mark = [&](int i) {
-      if (timing) TPO_HIP_CHECK(hipEventRecord(plan->ev[i], s));
-    };
-    upload_inputs(plan, ws, s);
-    mark(0);
-    if (timing || (plan->par.flags & TPO_FLAG_ONE_STREAM)) {
-      // stage by stage on one stream (timing: so that each stage's time is its own)
-      launch_ingest(*plan, ws, in, s);
-      mark(1);
-      launch_reduce(*plan, ws, in->x_u, in->ld_x, in->x_scale, s);
-      mark(2);
-    } else {
-      // ingest (edges only) and the attribute reduction (X only) are
-      // independent: ingest runs on a second stream beside the reduction's
-      // chain of small dependent kernels
-      if (!plan->side_made) {
-        TPO_HIP_CHECK(hipStreamCreateWithFlags(&plan->side, hipStreamNonBlocking));
-        TPO_HIP_CHECK(hipEventCreateWithFlags(&plan->fork_ev, hipEventDisableTiming));
-        TPO_HIP_CHECK(hipEventCreateWithFlags(&plan->join_ev, hipEventDisableTiming));
-        plan->side_made = true;
-      }
-      TPO_HIP_CHECK(hipEventRecord(plan->fork_ev, s));
-      TPO_HIP_CHECK(hipStreamWaitEvent(plan->side, plan->fork_ev, 0));
-      // the reduction is enqueued first: its long few-workgroup kernels
-      // (subspace iteration, Rayleigh-Ritz) then run beside ingest's
-      // whole-GPU sort and scan kernels instead of after them
-      launch_reduce(*plan, ws, in->x_u, in->ld_x, in->x_scale, s);
-      launch_ingest(*plan, ws, in, plan->side);
-      TPO_HIP_CHECK(hipEventRecord(plan->join_ev, plan->side));
-      TPO_HIP_CHECK(hipStreamWaitEvent(s, plan->join_ev, 0));
-    }
-    launch_propagate(*plan, ws, bufp<float>(*plan, ws, B_XPRIME), plan->dp, s);
-    mark(3);
-    launch_features(*plan, ws, s);
-    mark(4);
-    launch_embed(*plan, ws, s);
-    mark(5);
-    launch_onmf(*plan, ws, s);
-    mark(6);
-    launch_nci(*plan, ws, s);
-    mark(7);
-    launch_objective(*plan, ws, s);
-    mark(8);
-    TPO_HIP_CHECK(hipMemcpyAsync(out->labels, bufp<int32_t>(*plan, ws, B_LABELS), sizeof(int32_t) * plan->n,
-                                 hipMemcpyDeviceToDevice, s));
-    if (out->embedding)
-      TPO_HIP_CHECK(hipMemcpyAsync(out->embedding, bufp<float>(*plan, ws, B_UPS),
-                                   sizeof(float) * static_cast<size_t>(plan->n) * plan->k, hipMemcpyDeviceToDevice, s));
-    TPO_HIP_CHECK(hipMemcpyAsync(&host, bufp<char>(*plan, ws, B_STATUS), sizeof(host), hipMemcpyDeviceToHost, s));
-    TPO_HIP_CHECK(hipStreamSynchronize(s));
-    if (timing) {
-      float ms[8];
-      for (int i = 0; i < 8; ++i) TPO_HIP_CHECK(hipEventElapsedTime(&ms[i], plan->ev[i], plan->ev[i + 1]));
-      tpo_stats& S = plan->stats;
-      S.ms_ingest = ms[0];
-      S.ms_reduce = ms[1];
-      S.ms_propagate = ms[2];
-      S.ms_features = ms[3];
-      S.ms_embed = ms[4];
-      S.ms_onmf = ms[5];
-      S.ms_nci = ms[6];
-      S.ms_objective = ms[7];
-      float tot;
-      TPO_HIP_CHECK(hipEventElapsedTime(&tot, plan->ev[0], plan->ev[8]));
-      S.ms_total = tot;
-      const int hops = std::min(plan->par.gamma, kMaxTimedHops);
-      S.ms_spmm_v = S.ms_spmm_u = 0.0;
-      for (int h = 0; h < hops; ++h) {
-        float a, b;
-        TPO_HIP_CHECK(hipEventElapsedTime(&a, plan->kev[4 * h], plan->kev[4 * h + 1]));
-        TPO_HIP_CHECK(hipEventElapsedTime(&b, plan->kev[4 * h + 2], plan->kev[4 * h + 3]));
-        S.ms_spmm_v += a;
-        S.ms_spmm_u += b;
-      }
-      S.n_spmm_v = S.n_spmm_u = hops;
-    }
-  });
-  if (st != TPO_OK) return st;
-  plan->stats.n_unique_edges = host.n_unique;
-  plan->stats.guard_hits = host.guard_hits;
-  plan->stats.isolated_u = host.iso_u;
-  plan->stats.isolated_v = host.iso_v;
-  if (out->objective) {
-    out->objective[0] = host.objective[0];
-    out->objective[1] = host.objective[1];
-  }
-  return map_bits(plan, host.err_bits);
+  return execute_plan(plan, in, ws, bytes, static_cast<hipStream_t>(stream), out, false);
 }
 
 }  // extern "C"

@@ -159,3 +159,18 @@ void launch_nci(const Plan& p, void* ws, hipStream_t s);
 void launch_objective(const Plan& p, void* ws, hipStream_t s);
 
 }  // namespace tpo
+
+// The opaque plan handle of the C ABI.
+struct tpo_plan : public tpo::Plan {};
+
+namespace tpo {
+// The body of tpo_execute: validates, runs the whole method for `plan` on `s`
+// in the workspace `ws` and synchronises `s`.  no_alloc: everything runs on
+// `s` with no plan-owned second stream and no events (plans with
+// TPO_FLAG_TIMING are rejected), for callers that must not create runtime
+// objects.
+tpo_status execute_plan(tpo_plan* plan, const tpo_inputs* in, void* ws, size_t bytes, hipStream_t s,
+                        const tpo_outputs* out, bool no_alloc);
+// Records `msg` as the plan's last error and returns `st`.
+tpo_status plan_fail(tpo_plan* plan, tpo_status st, const std::string& msg);
+}  // namespace tpo

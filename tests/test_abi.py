@@ -179,3 +179,29 @@ def test_serving_pool_and_summary():
     assert s["jobs"] == 10 and s["failed"] == 1
     assert abs(s["p50_ms"] - 24.5) < 1e-6 and abs(s["exec_p50_ms"] - 20.0) < 1e-9
     assert abs(s["jobs_per_s"] - 10 / (0.9 + 0.029)) < 1e-9
+
+
+def test_noalloc_entry_point_rejects_jobs_beyond_its_array():
+    """The no-allocation entry point refuses, before any device work, a job
+    whose workspace exceeds its fixed array, and says why."""
+    with open(os.path.join(ROOT, "include", "tpo.h")) as f:
+        m = re.search(r"#define TPO_NOALLOC_MAX_BYTES \(\(size_t\)(\d+) << (\d+)\)", f.read())
+    assert m and int(m.group(1)) << int(m.group(2)) == tpo.TPO_NOALLOC_MAX_BYTES
+    lib = tpo.load_library()
+    h = tpo.tpo_plan_create(200_000, 400_000, 4_000_000, 256, k=20, alpha=0.5, gamma=10, d=64)
+    try:
+        assert tpo.tpo_plan_workspace_bytes(h) > tpo.TPO_NOALLOC_MAX_BYTES
+        inp = tpo.TpoInputs(None, None, None, None, 256, None)
+        out = tpo.TpoOutputs(None, None, None)
+        st = lib.tpo_execute_noalloc(h, ctypes.byref(inp), None, ctypes.byref(out))
+        assert st == 3  # TPO_ENOMEM
+        assert b"no-allocation" in lib.tpo_plan_last_error(h)
+    finally:
+        tpo.tpo_plan_destroy(h)
+    h = tpo.tpo_plan_create(2000, 3000, 20_000, 64, k=5, alpha=0.5, gamma=5, timing=True)
+    try:
+        assert tpo.tpo_plan_workspace_bytes(h) <= tpo.TPO_NOALLOC_MAX_BYTES
+        st = lib.tpo_execute_noalloc(h, ctypes.byref(inp), None, ctypes.byref(out))
+        assert st == 1  # TPO_EINVAL: a timing plan would create events
+    finally:
+        tpo.tpo_plan_destroy(h)
