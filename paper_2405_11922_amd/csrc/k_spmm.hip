@@ -16,7 +16,11 @@
 // cross-lane permutes.  Rows with more than kHubChunk neighbours are split
 // into chunks of one wave each, in the same launch; a second kernel adds the
 // chunk partials in chunk order, so every sum has a fixed order (bitwise
-// reproducible).
+// reproducible).  The hub work is walked by a fixed grid of kHubBlocks
+// workgroups, so that a launch holds no waves for chunks that do not exist.
+
+#include <algorithm>
+
 #include "dev_common.hpp"
 #include "tpo_internal.hpp"
 
@@ -107,8 +111,8 @@ __device__ __forceinline__ void spmm_epilogue(int r, float4 acc, const float* __
 
 // One row per lane group: the LPR = D/4 lanes of a group own float4 column
 // slices of the output row, so no cross-group reduction is needed; a wave
-// carries 64/LPR rows at once.  Column ids come 16 (or LPR) at a time from
-// one load by the group and are handed out with cross-lane permutes.
+// carries 64/LPR rows at once.  Column ids come LPR at a time from one load
+// by the group and are handed out with cross-lane permutes.
 template <int D>
 __device__ __forceinline__ float4 gather_row_group(const int32_t* __restrict__ col, const float* __restrict__ val,
                                                    bool has_vals, const float* __restrict__ src, int b, int e) {
@@ -171,9 +175,10 @@ __device__ __forceinline__ void spmm_epilogue_group(int r, float4 acc, const flo
   *reinterpret_cast<float4*>(dst + static_cast<int64_t>(r) * D + q * 4) = o;
 }
 
-// One launch per SpMM side.  Blocks [0, chunk_blocks) take the hub chunks
-// (one wave per chunk, partial sums to `partial`); the remaining blocks take
-// the rows with at most kHubChunk neighbours, one row per lane group.
+// One launch per SpMM side.  The first `chunk_blocks` workgroups walk the hub
+// chunks, one wave per chunk, and write partial sums to `partial`; the
+// remaining workgroups take the rows of at most kHubChunk neighbours, one row
+// per lane group.
 template <int D, int MODE>
 __global__ void __launch_bounds__(256)
 k_spmm_rowgroup(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col, const float* __restrict__ val,
@@ -181,64 +186,65 @@ k_spmm_rowgroup(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ 
                 const int4* __restrict__ chunks, int chunk_blocks, const float* __restrict__ src, int nrows,
                 const float* __restrict__ rscale, const float* __restrict__ xp, float alpha, float one_minus_alpha,
                 float* __restrict__ dst, float* __restrict__ partial) {
-  constexpr int LPR = SpmmShape<D>::LPR;
   const bool has_vals = st->has_vals != 0;
   if (static_cast<int>(blockIdx.x) < chunk_blocks) {
-    const int c = static_cast<int>((static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6);
-    if (c >= *n_chunks) return;
-    const int4 ch = chunks[c];
-    const float4 acc = gather_sum<D>(col, val, has_vals, src, ch.y, ch.z);
+    constexpr int LPR = SpmmShape<D>::LPR;
     const int lane = threadIdx.x & 63;
-    if (lane < LPR) *reinterpret_cast<float4*>(partial + static_cast<int64_t>(ch.w) * D + lane * 4) = acc;
+    const int nc = *n_chunks;
+    const int waves = chunk_blocks * (256 / 64);
+    for (int c = static_cast<int>(blockIdx.x) * 4 + static_cast<int>(threadIdx.x >> 6); c < nc; c += waves) {
+      const int4 ch = chunks[c];
+      const float4 acc = gather_sum<D>(col, val, has_vals, src, ch.y, ch.z);
+      if (lane < LPR) *reinterpret_cast<float4*>(partial + static_cast<int64_t>(ch.w) * D + lane * 4) = acc;
+    }
     return;
   }
-  const int64_t gidx =
-      (static_cast<int64_t>(blockIdx.x - chunk_blocks) * blockDim.x + threadIdx.x) / LPR;
+  constexpr int LPR = SpmmShape<D>::LPR;
+  const int64_t gidx = (static_cast<int64_t>(blockIdx.x - chunk_blocks) * blockDim.x + threadIdx.x) / LPR;
+  if (gidx >= nrows) return;
   const int r = static_cast<int>(gidx);
-  int b = 0, e = 0;
-  const bool live = r < nrows;
-  if (live) {
-    b = rowptr[r];
-    e = rowptr[r + 1];
-  }
-  const bool mine = live && e - b <= kHubChunk;
-  const float4 acc = gather_row_group<D>(col, val, has_vals, src, b, mine ? e : b);
-  if (mine) spmm_epilogue_group<D, MODE>(r, acc, rscale, xp, alpha, one_minus_alpha, dst);
+  const int b = rowptr[r], e = rowptr[r + 1];
+  if (e - b > kHubChunk) return;
+  const float4 acc = gather_row_group<D>(col, val, has_vals, src, b, e);
+  spmm_epilogue_group<D, MODE>(r, acc, rscale, xp, alpha, one_minus_alpha, dst);
 }
 
 // One wave per hub row: add its chunk partials in order, then the epilogue.
+// The kHubBlocks workgroups (or fewer) walk the hub list.
 template <int D, int MODE>
 __global__ void __launch_bounds__(256)
 k_spmm_hubs(const int32_t* __restrict__ n_hubs, const int4* __restrict__ hubs, const float* __restrict__ partial,
             const float* __restrict__ rscale, const float* __restrict__ xp, float alpha, float one_minus_alpha,
             float* __restrict__ dst) {
-  const int h = static_cast<int>((static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6);
-  if (h >= *n_hubs) return;
-  const int4 hb = hubs[h];
   const int lane = threadIdx.x & 63;
-  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (lane < SpmmShape<D>::LPR) {
-    // chunk partials in chunk order; eight loads in flight at a time
-    for (int c0 = 0; c0 < hb.z; c0 += 8) {
-      float4 v[8];
+  const int nh = *n_hubs;
+  const int waves = static_cast<int>(gridDim.x) * 4;
+  for (int h = static_cast<int>(blockIdx.x) * 4 + static_cast<int>(threadIdx.x >> 6); h < nh; h += waves) {
+    const int4 hb = hubs[h];
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (lane < SpmmShape<D>::LPR) {
+      // chunk partials in chunk order; eight loads in flight at a time
+      for (int k0 = 0; k0 < hb.z; k0 += 8) {
+        float4 v[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (c0 + u < hb.z)
-          v[u] = *reinterpret_cast<const float4*>(partial + static_cast<int64_t>(hb.y + c0 + u) * D + lane * 4);
-      }
+        for (int u = 0; u < 8; ++u) {
+          v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+          if (k0 + u < hb.z)
+            v[u] = *reinterpret_cast<const float4*>(partial + static_cast<int64_t>(hb.y + k0 + u) * D + lane * 4);
+        }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        if (c0 + u < hb.z) {
-          acc.x += v[u].x;
-          acc.y += v[u].y;
-          acc.z += v[u].z;
-          acc.w += v[u].w;
+        for (int u = 0; u < 8; ++u) {
+          if (k0 + u < hb.z) {
+            acc.x += v[u].x;
+            acc.y += v[u].y;
+            acc.z += v[u].z;
+            acc.w += v[u].w;
+          }
         }
       }
     }
+    spmm_epilogue<D, MODE>(hb.x, acc, rscale, xp, alpha, one_minus_alpha, dst);
   }
-  spmm_epilogue<D, MODE>(hb.x, acc, rscale, xp, alpha, one_minus_alpha, dst);
 }
 
 // W0 = D_U^-1/2 X'  (or Z = (1 - alpha) X' when gamma = 0)
@@ -248,6 +254,19 @@ __global__ void k_scale_rows(const float* __restrict__ x, int n, int D, const fl
   if (i >= static_cast<int64_t>(n) * D) return;
   const int r = static_cast<int>(i / D);
   out[i] = (rscale ? rscale[r] : 1.0f) * c * x[i];
+}
+
+template <int D, int MODE>
+static void spmm_side(const Plan& p, void* ws, const int32_t* rowptr, const int32_t* col, const float* val,
+                      const int32_t* n_chunks, const int4* chunks, unsigned chunk_blocks, const float* src,
+                      int nrows, const float* rscale, const float* xp, float alpha, float oma, float* dst,
+                      float* partial, hipStream_t s) {
+  const DevStatus* st = bufp<DevStatus>(p, ws, B_STATUS);
+  const unsigned rows_blocks = ceil_div(static_cast<int64_t>(nrows) * SpmmShape<D>::LPR, 256);
+  hipLaunchKernelGGL((k_spmm_rowgroup<D, MODE>), dim3(chunk_blocks + rows_blocks), dim3(256), 0, s, rowptr, col, val,
+                     st, n_chunks, chunks, static_cast<int>(chunk_blocks), src, nrows, rscale, xp, alpha, oma, dst,
+                     partial);
+  TPO_LAUNCH_CHECK();
 }
 
 template <int D>
@@ -272,12 +291,10 @@ static void propagate_impl(const Plan& p, void* ws, const float* xp, hipStream_t
   hipLaunchKernelGGL(k_scale_rows, dim3(ceil_div(static_cast<int64_t>(n) * D, 256)), dim3(256), 0, s, xp, n, D,
                      isq, 1.0f, w0);
   TPO_LAUNCH_CHECK();
-  constexpr int LPR = SpmmShape<D>::LPR;
-  const unsigned ch_v = ceil_div(static_cast<int64_t>(p.max_chunks_v) * 64, 256);
-  const unsigned ch_u = ceil_div(static_cast<int64_t>(p.max_chunks_u) * 64, 256);
-  const unsigned grid_v = ch_v + ceil_div(static_cast<int64_t>(m) * LPR, 256);
-  const unsigned grid_u = ch_u + ceil_div(static_cast<int64_t>(n) * LPR, 256);
-  const unsigned hub_v = ch_v, hub_u = ch_u;
+  // hub-chunk workgroups: enough for every chunk the plan allows, at most
+  // kHubBlocks (they loop over the chunks ingest found)
+  const unsigned ch_v = std::min<int64_t>(ceil_div(static_cast<int64_t>(p.max_chunks_v) * 64, 256), kHubBlocks);
+  const unsigned ch_u = std::min<int64_t>(ceil_div(static_cast<int64_t>(p.max_chunks_u) * 64, 256), kHubBlocks);
   float* cur = w0;
   float* nxt = w1;
   for (int hop = 1; hop <= p.par.gamma; ++hop) {
@@ -285,14 +302,12 @@ static void propagate_impl(const Plan& p, void* ws, const float* xp, hipStream_t
     const hipEvent_t* ev = p.kev + 4 * (hop - 1);
     // V side: T = D_V^-1 B^T W
     if (tm) TPO_HIP_CHECK(hipEventRecord(ev[0], s));
-    hipLaunchKernelGGL((k_spmm_rowgroup<D, kModeV>), dim3(grid_v), dim3(256), 0, s, bufp<int32_t>(p, ws, B_ROWPTR_V),
-                       bufp<int32_t>(p, ws, B_COL_V), bufp<float>(p, ws, B_VAL_V), st, &st->hub_chunks_v,
-                       bufp<int4>(p, ws, B_CHUNK_V), static_cast<int>(ch_v), cur, m, invv, nullptr, alpha, oma, t,
-                       partial);
-    TPO_LAUNCH_CHECK();
+    spmm_side<D, kModeV>(p, ws, bufp<int32_t>(p, ws, B_ROWPTR_V), bufp<int32_t>(p, ws, B_COL_V),
+                         bufp<float>(p, ws, B_VAL_V), &st->hub_chunks_v, bufp<int4>(p, ws, B_CHUNK_V), ch_v, cur, m,
+                         invv, nullptr, alpha, oma, t, partial, s);
     if (tm) TPO_HIP_CHECK(hipEventRecord(ev[1], s));
     if (p.max_chunks_v > 0) {
-      hipLaunchKernelGGL((k_spmm_hubs<D, kModeV>), dim3(hub_v), dim3(256), 0, s, &st->hub_rows_v,
+      hipLaunchKernelGGL((k_spmm_hubs<D, kModeV>), dim3(ch_v), dim3(256), 0, s, &st->hub_rows_v,
                          bufp<int4>(p, ws, B_HUBLIST_V), partial, invv, nullptr, alpha, oma, t);
       TPO_LAUNCH_CHECK();
     }
@@ -301,23 +316,20 @@ static void propagate_impl(const Plan& p, void* ws, const float* xp, hipStream_t
     float* dst = last ? z : nxt;
     if (tm) TPO_HIP_CHECK(hipEventRecord(ev[2], s));
     if (last)
-      hipLaunchKernelGGL((k_spmm_rowgroup<D, kModeUFinal>), dim3(grid_u), dim3(256), 0, s,
-                         bufp<int32_t>(p, ws, B_ROWPTR_U), bufp<int32_t>(p, ws, B_COL_U), bufp<float>(p, ws, B_VAL_U),
-                         st, &st->hub_chunks_u, bufp<int4>(p, ws, B_CHUNK_U), static_cast<int>(ch_u), t, n, isq, xp,
-                         alpha, oma, dst, partial);
+      spmm_side<D, kModeUFinal>(p, ws, bufp<int32_t>(p, ws, B_ROWPTR_U), bufp<int32_t>(p, ws, B_COL_U),
+                                bufp<float>(p, ws, B_VAL_U), &st->hub_chunks_u, bufp<int4>(p, ws, B_CHUNK_U), ch_u, t,
+                                n, isq, xp, alpha, oma, dst, partial, s);
     else
-      hipLaunchKernelGGL((k_spmm_rowgroup<D, kModeUMid>), dim3(grid_u), dim3(256), 0, s,
-                         bufp<int32_t>(p, ws, B_ROWPTR_U), bufp<int32_t>(p, ws, B_COL_U), bufp<float>(p, ws, B_VAL_U),
-                         st, &st->hub_chunks_u, bufp<int4>(p, ws, B_CHUNK_U), static_cast<int>(ch_u), t, n, isq, xp,
-                         alpha, oma, dst, partial);
-    TPO_LAUNCH_CHECK();
+      spmm_side<D, kModeUMid>(p, ws, bufp<int32_t>(p, ws, B_ROWPTR_U), bufp<int32_t>(p, ws, B_COL_U),
+                              bufp<float>(p, ws, B_VAL_U), &st->hub_chunks_u, bufp<int4>(p, ws, B_CHUNK_U), ch_u, t, n,
+                              isq, xp, alpha, oma, dst, partial, s);
     if (tm) TPO_HIP_CHECK(hipEventRecord(ev[3], s));
     if (p.max_chunks_u > 0) {
       if (last)
-        hipLaunchKernelGGL((k_spmm_hubs<D, kModeUFinal>), dim3(hub_u), dim3(256), 0, s, &st->hub_rows_u,
+        hipLaunchKernelGGL((k_spmm_hubs<D, kModeUFinal>), dim3(ch_u), dim3(256), 0, s, &st->hub_rows_u,
                            bufp<int4>(p, ws, B_HUBLIST_U), partial, isq, xp, alpha, oma, dst);
       else
-        hipLaunchKernelGGL((k_spmm_hubs<D, kModeUMid>), dim3(hub_u), dim3(256), 0, s, &st->hub_rows_u,
+        hipLaunchKernelGGL((k_spmm_hubs<D, kModeUMid>), dim3(ch_u), dim3(256), 0, s, &st->hub_rows_u,
                            bufp<int4>(p, ws, B_HUBLIST_U), partial, isq, xp, alpha, oma, dst);
       TPO_LAUNCH_CHECK();
     }

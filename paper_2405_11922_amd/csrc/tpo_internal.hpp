@@ -16,6 +16,10 @@ namespace tpo {
 // Edges per hub chunk of the propagation SpMM: rows with more neighbours than
 // this are split into chunks whose partial sums are added in chunk order.
 constexpr int kHubChunk = 256;
+// Workgroups that walk the hub chunks and the hub rows of one SpMM launch
+// (grid-stride loops over the counts that ingest finds; 8192 waves fill the
+// GPU).
+constexpr int kHubBlocks = 2048;
 // Radix sort tile: 256 threads x 16 keys.
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;
