@@ -5,7 +5,11 @@ One step = one whole clustering job (ingest -> attribute reduction ->
 propagation -> random features -> RandomizedSVD -> ONMF -> NCI -> objective)
 through tpo_execute on inputs already resident in HBM.  Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--config mid_fp32] [--cpu-baseline on|off]
+  python bench.py [--steps K] [--warmup W] [--config large|mid_fp32|fp8_tfidf|serve] [--cpu-baseline on|off]
+
+The default workload is the 150M-edge job in the attribute precision form
+(X_U as bfloat16), timed beside the plain FP32 job on the same input; the
+mid-size FP32 workload is reported under "mid".
 
 Only one GPU is used: --gpus N with N > 1 exits with a message.
 """
@@ -125,12 +129,203 @@ def run_serve(args) -> int:
     return 0 if summ["failed"] == 0 else 1
 
 
+def mfma_util(config: str):
+    """MFMA utilisation of the attribute Gram (S1), the random features (S3)
+    and the embedding (S4) kernels from the rocprofv3 counter run recorded
+    under profiles/ for this workload, or None when no record exists or a
+    kernel source has changed since it was taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"mfma_util_{config}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    for src, sha in rec["sources"].items():
+        with open(os.path.join(ROOT, src), "rb") as fh:
+            if hashlib.sha256(fh.read()).hexdigest() != sha:
+                return None
+    return {"busy_pct": rec["busy_pct"], "profile": os.path.relpath(path, ROOT)}
+
+
+def make_input(args, config, dev):
+    """Seeded synthetic input of one workload, resident in HBM."""
+    import torch
+
+    import abg_synth as synth
+
+    shape = synth.CONFIGS[config]
+    x_scale = None  # column scales of FP8 attributes
+    t0 = time.time()
+    on_device = shape.n_edges > 20_000_000  # the host generator is too slow beyond this
+    if on_device:
+        tfidf = config == "fp8_tfidf"
+        eu, ev, x, truth, _ = synth.planted_abg_device(shape.n_u, shape.n_v, shape.n_edges, shape.k,
+                                                       1 if tfidf else shape.d_u,
+                                                       device=dev, zipf_a=shape.zipf_a, sigma=shape.sigma,
+                                                       in_out_ratio=shape.in_out_ratio, max_degree=shape.max_degree,
+                                                       seed=args.seed)
+        if tfidf:
+            # the attributes: sparse TF-IDF rows encoded as FP8 E4M3 with column scales
+            del x
+            x, x_scale = synth.tfidf_fp8_device(truth, shape.d_u, device=dev, seed=args.seed)
+            x = x.view(torch.float8_e4m3fn)
+        torch.cuda.synchronize()
+        truth = truth.cpu().numpy()
+        abg = None
+    else:
+        abg = synth.config_abg(shape, seed=args.seed)
+        eu = torch.from_numpy(abg.edge_u).to(dev)
+        ev = torch.from_numpy(abg.edge_v).to(dev)
+        x = torch.from_numpy(abg.x_u).to(dev)
+        truth = abg.labels_u
+    log(f"[bench] generated {config} ({'on the GPU' if on_device else 'on the host'}): n_u={shape.n_u} "
+        f"n_v={shape.n_v} E={shape.n_edges} d_u={shape.d_u} in {time.time() - t0:.1f}s")
+    return dict(shape=shape, eu=eu, ev=ev, x=x, x_scale=x_scale, truth=truth, abg=abg, on_device=on_device)
+
+
+def time_jobs(args, inp, x, x_dtype, dev, steps, warmup, instrument=True):
+    """W untimed and K timed whole jobs (tpo_execute) of one input; then, with
+    an instrumented plan, the stage split and the SpMM launch times."""
+    import numpy as np
+    import torch
+
+    import paper_2405_11922_amd as tpo
+
+    shape = inp["shape"]
+    kw = dict(k=shape.k, alpha=shape.alpha, gamma=shape.gamma, d=shape.d, q=shape.q,
+              oversample=shape.oversample, t_f=shape.t_f, t_g=shape.t_g, seed=args.seed, x_dtype=x_dtype,
+              nci=args.nci)
+    eu, ev, xs = inp["eu"], inp["ev"], inp["x_scale"]
+    plan = tpo.Plan.create(shape.n_u, shape.n_v, shape.n_edges, shape.d_u, device=dev, timing=False, **kw)
+    labels = torch.empty(shape.n_u, dtype=torch.int32, device=dev)
+    emb = torch.empty(shape.n_u, shape.k, dtype=torch.float32, device=dev)
+    dims = tpo.tpo_plan_dims(plan.handle)
+    for _ in range(warmup):
+        tpo.tpo_execute(plan.handle, eu, ev, x, plan.workspace, labels, emb, x_scale=xs)
+    torch.cuda.synchronize()
+    step_ms = []
+    t_start = time.perf_counter()
+    for _ in range(steps):
+        s0 = time.perf_counter()
+        obj = tpo.tpo_execute(plan.handle, eu, ev, x, plan.workspace, labels, emb, x_scale=xs)
+        step_ms.append((time.perf_counter() - s0) * 1e3)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    plan.close()
+    del plan
+    res = dict(value=steps / elapsed, ms_per_step=elapsed * 1e3 / steps, obj=obj, labels=labels, emb=emb,
+               dims=dims, p50=float(np.percentile(step_ms, 50)), p99=float(np.percentile(step_ms, 99)))
+    log(f"[bench] {x_dtype}: {steps} steps in {elapsed:.3f}s ({res['ms_per_step']:.3f} ms/step)")
+    if not instrument:
+        return res
+    plan_t = tpo.Plan.create(shape.n_u, shape.n_v, shape.n_edges, shape.d_u, device=dev, timing=True, **kw)
+    stats = []
+    for _ in range(3):
+        tpo.tpo_execute(plan_t.handle, eu, ev, x, plan_t.workspace, labels, emb, x_scale=xs)
+        stats.append(tpo.tpo_plan_stats(plan_t.handle))
+    st = {key: statistics.median(s[key] for s in stats) for key in stats[0]}
+    log(f"[bench] {x_dtype} stages ms: " + " ".join(f"{k[3:]}={st[k]:.3f}" for k in st if k.startswith("ms_")))
+    res.update(stats=st, plan_t=plan_t)
+    return res
+
+
+def spmm_roofline(config, shape, st, d_eff):
+    """Roofline of the dominant SpMM launch from the instrumented plan's HIP
+    events (the larger of the U- and V-side average launch times)."""
+    e_u = int(st["n_unique_edges"])
+    has_vals = e_u < shape.n_edges
+    u_avg = st["ms_spmm_u"] / max(st["n_spmm_u"], 1)
+    v_avg = st["ms_spmm_v"] / max(st["n_spmm_v"], 1)
+    if u_avg >= v_avg:
+        side, kern, per, avg = "U", "k_spmm_rowgroup<64,U> (Z = X' + alpha D_U^-1/2 B T)", spmm_u_bytes(
+            shape.n_u, shape.n_v, e_u, d_eff, has_vals), u_avg
+    else:
+        side, kern, per, avg = "V", "k_spmm_rowgroup<64,V> (T = D_V^-1 B^T W)", spmm_v_bytes(
+            shape.n_u, shape.n_v, e_u, d_eff, has_vals), v_avg
+    achieved = per / (avg * 1e-3) / 1e9
+    return {"kernel": kern, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counted_traffic(config, side),
+            "bytes_per_launch": per, "avg_launch_ms": round(avg, 5),
+            "spmm_u_avg_ms": round(u_avg, 5), "spmm_v_avg_ms": round(v_avg, 5)}
+
+
+def best_match_agreement(a, b, k):
+    """Fraction of rows whose labels agree under the best one-to-one relabelling."""
+    import numpy as np
+    from scipy.optimize import linear_sum_assignment
+
+    a, b = a.astype(np.int64), b.astype(np.int64)
+    table = np.zeros((k, k), np.int64)
+    np.add.at(table, (a, b), 1)
+    r, c = linear_sum_assignment(-table)
+    return float(table[r, c].sum() / a.size)
+
+
+def sin_theta_device(a, b):
+    """Largest principal-angle sine between the column spaces of two n x k
+    device matrices (FP64 Grams on the GPU, eigen step on the host)."""
+    import numpy as np
+    import torch
+
+    def orth(m):
+        g = torch.zeros(m.shape[1], m.shape[1], dtype=torch.float64, device=m.device)
+        for r0 in range(0, m.shape[0], 500_000):
+            blk = m[r0:r0 + 500_000].double()
+            g += blk.T @ blk
+        w, v = np.linalg.eigh(g.cpu().numpy())
+        w = np.maximum(w, 1e-300)
+        return torch.from_numpy(v / np.sqrt(w)[None, :]).to(m.device)
+
+    ia, ib = orth(a), orth(b)
+    c = torch.zeros(a.shape[1], b.shape[1], dtype=torch.float64, device=a.device)
+    for r0 in range(0, a.shape[0], 500_000):
+        c += a[r0:r0 + 500_000].double().T @ b[r0:r0 + 500_000].double()
+    s = np.linalg.svd((ia.T @ c @ ib).cpu().numpy(), compute_uv=False)
+    return float(np.sqrt(max(0.0, 1.0 - min(1.0, float(s.min())) ** 2)))
+
+
+def cpu_baseline_sample(inp, shape, rows_frac=10):
+    """The FP64 oracle's propagation timed on the host: one Horner hop
+    (both products of L L^T) over the subgraph of the first |U|/rows_frac
+    target rows (all their edges, every V node), at the workload's width d.
+    Returns its rate in GEdge-hop/s (edges of the subgraph per second)."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    import oracle
+
+    nu = shape.n_u // rows_frac
+    eu = inp["eu"].cpu().numpy()
+    keep = eu < nu
+    eu = eu[keep]
+    ev = inp["ev"].cpu().numpy()[keep]
+    del keep
+    b = oracle.bipartite_adjacency(nu, shape.n_v, eu, ev)
+    del eu, ev
+    x = np.random.default_rng(0).standard_normal((nu, shape.d))
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    t0 = time.perf_counter()
+    oracle.propagate(b, x, shape.alpha, 1)
+    t1 = time.perf_counter()
+    oracle.propagate(b, x, shape.alpha, 2)
+    t2 = time.perf_counter()
+    hop = (t2 - t1) - (t1 - t0)  # the second hop alone (each call also builds L)
+    rate = b.nnz / hop / 1e9
+    return {"value": round(rate, 6), "unit": "GEdge-hop/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"one Horner hop of the oracle's propagation (oracle.propagate, scipy sparse products, "
+                      f"single-threaded) over the subgraph of the first {nu} of {shape.n_u} target rows "
+                      f"({b.nnz} edges, all {shape.n_v} V nodes, d={shape.d}): the time of gamma=2 minus gamma=1, "
+                      f"{hop:.2f} s; rate = subgraph edges per second",
+            "oracle_hop_s": round(hop, 3)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="mid_fp32")
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="large")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-baseline", default="on", choices=["on", "off"])
     ap.add_argument("--serve-jobs", type=int, default=2000)
@@ -142,9 +337,11 @@ def main() -> int:
                     help="NCI Phi update: the printed Ups^T Y, or its orthogonal polar factor")
     ap.add_argument("--x-dtype", default="auto", choices=["auto", "f32", "bf16"],
                     help="attribute storage: auto = bf16 for the large precision form, f32 otherwise")
-    ap.add_argument("--compare-f32", action="store_true",
-                    help="with bf16 attributes, also run the plain FP32 job on the same graph and report the "
-                         "label agreement and objective difference")
+    ap.add_argument("--compare-f32", default="on", choices=["on", "off"],
+                    help="with bf16 attributes, also time the plain FP32 job on the same graph (the metric's "
+                         "'vs plain FP32 GPU') and report how far the results differ")
+    ap.add_argument("--mid", default="on", choices=["on", "off"],
+                    help="with --config large, also time the mid-size FP32 workload (reported under 'mid')")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also copy a 256 MiB buffer once (a kernel of known traffic, to scale "
                          "hardware byte counters)")
@@ -158,10 +355,8 @@ def main() -> int:
         # wait behind each other in a shared queue (read when HIP starts)
         os.environ["GPU_MAX_HW_QUEUES"] = str(max(4, min(16, args.serve_workers)))
 
-    import numpy as np
     import torch
 
-    import abg_synth as synth
     import paper_2405_11922_amd as tpo
     from paper_2405_11922_amd import quality
 
@@ -171,54 +366,20 @@ def main() -> int:
         return 1
     if args.config == "serve":
         return run_serve(args)
-    shape = synth.CONFIGS[args.config]
     dev = torch.device("cuda:0")
-    x_scale = None  # column scales of FP8 attributes
-    t0 = time.time()
-    on_device = shape.n_edges > 20_000_000  # the host generator is too slow beyond this
-    if on_device:
-        tfidf = args.config == "fp8_tfidf"
-        eu, ev, x, truth, _ = synth.planted_abg_device(shape.n_u, shape.n_v, shape.n_edges, shape.k,
-                                                   1 if tfidf else shape.d_u,
-                                                   device=dev, zipf_a=shape.zipf_a, sigma=shape.sigma,
-                                                   in_out_ratio=shape.in_out_ratio, max_degree=shape.max_degree,
-                                                   seed=args.seed)
-        if tfidf:
-            # the attributes: sparse TF-IDF rows encoded as FP8 E4M3 with column scales
-            del x
-            x, x_scale = synth.tfidf_fp8_device(truth, shape.d_u, device=dev, seed=args.seed)
-            x = x.view(torch.float8_e4m3fn)
-        torch.cuda.synchronize()
-        truth = truth.cpu().numpy()
-        abg = None
-        abg_n_edges, abg_d_u = shape.n_edges, shape.d_u
-    else:
-        abg = synth.config_abg(shape, seed=args.seed)
-        eu = torch.from_numpy(abg.edge_u).to(dev)
-        ev = torch.from_numpy(abg.edge_v).to(dev)
-        x = torch.from_numpy(abg.x_u).to(dev)
-        truth = abg.labels_u
-        abg_n_edges, abg_d_u = abg.n_edges, abg.d_u
-    log(f"[bench] generated {args.config} ({'on the GPU' if on_device else 'on the host'}): n_u={shape.n_u} "
-        f"n_v={shape.n_v} E={abg_n_edges} d_u={abg_d_u} in {time.time() - t0:.1f}s")
+    inp = make_input(args, args.config, dev)
+    shape = inp["shape"]
     x_dtype = args.x_dtype if args.x_dtype != "auto" else {"large": "bf16", "fp8_tfidf": "fp8"}.get(args.config, "f32")
     if (x_dtype == "fp8") != (args.config == "fp8_tfidf"):
         print("FP8 attributes go with --config fp8_tfidf (and only there)", file=sys.stderr)
         return 2
-    x_f32 = x
-    if x_dtype == "bf16":
-        x = x_f32.to(torch.bfloat16)
-        if not args.compare_f32:
-            del x_f32
-            x_f32 = None
-    kw = dict(k=shape.k, alpha=shape.alpha, gamma=shape.gamma, d=shape.d, q=shape.q,
-              oversample=shape.oversample, t_f=shape.t_f, t_g=shape.t_g, seed=args.seed, x_dtype=x_dtype,
-              nci=args.nci)
-    plan = tpo.Plan.create(shape.n_u, shape.n_v, abg_n_edges, abg_d_u, device=dev, timing=False, **kw)
-    plan_t = tpo.Plan.create(shape.n_u, shape.n_v, abg_n_edges, abg_d_u, device=dev, timing=True, **kw)
-    labels = torch.empty(shape.n_u, dtype=torch.int32, device=dev)
-    emb = torch.empty(shape.n_u, shape.k, dtype=torch.float32, device=dev)
-    d_eff, l_r, kp = tpo.tpo_plan_dims(plan.handle)
+    x_f32 = inp["x"]
+    x = x_f32.to(torch.bfloat16) if x_dtype == "bf16" else x_f32
+    compare = x_dtype == "bf16" and args.compare_f32 == "on"
+    if x_dtype == "bf16" and not compare:
+        del x_f32
+        x_f32 = None
+        inp["x"] = None
 
     if args.calibrate_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
@@ -226,55 +387,21 @@ def main() -> int:
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    for _ in range(args.warmup):
-        tpo.tpo_execute(plan.handle, eu, ev, x, plan.workspace, labels, emb, x_scale=x_scale)
-    torch.cuda.synchronize()
-    step_ms = []
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for _ in range(args.steps):
-        s0 = time.perf_counter()
-        obj = tpo.tpo_execute(plan.handle, eu, ev, x, plan.workspace, labels, emb, x_scale=x_scale)
-        step_ms.append((time.perf_counter() - s0) * 1e3)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    ms_per_step = elapsed * 1e3 / args.steps
-    log(f"[bench] {args.steps} steps in {elapsed:.3f}s ({ms_per_step:.3f} ms/step)")
 
-    # stage breakdown and SpMM kernel timing from an instrumented plan
-    stats = []
-    for _ in range(3):
-        tpo.tpo_execute(plan_t.handle, eu, ev, x, plan_t.workspace, labels, emb, x_scale=x_scale)
-        stats.append(tpo.tpo_plan_stats(plan_t.handle))
-    st = {key: statistics.median(s[key] for s in stats) for key in stats[0]}
-    log("[bench] stages ms: " + " ".join(f"{k[3:]}={st[k]:.3f}" for k in st if k.startswith("ms_")))
-    e_u = int(st["n_unique_edges"])
-    has_vals = e_u < abg_n_edges
-    gedge_hops = shape.gamma * e_u / (st["ms_propagate"] * 1e-3) / 1e9 if st["ms_propagate"] > 0 else None
-    u_avg = st["ms_spmm_u"] / max(st["n_spmm_u"], 1)
-    v_avg = st["ms_spmm_v"] / max(st["n_spmm_v"], 1)
-    if u_avg >= v_avg:
-        side, kern, per, avg = "U", "k_spmm_rowgroup<64,U> (Z = X' + alpha D_U^-1/2 B T)", spmm_u_bytes(
-            shape.n_u, shape.n_v, e_u, d_eff, has_vals), u_avg
-    else:
-        side, kern, per, avg = "V", "k_spmm_rowgroup<64,V> (T = D_V^-1 B^T W)", spmm_v_bytes(
-            shape.n_u, shape.n_v, e_u, d_eff, has_vals), v_avg
-    achieved = per / (avg * 1e-3) / 1e9
-    traffic = counted_traffic(args.config, side)
-    roofline = {"kernel": kern, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "bytes_per_launch": per, "avg_launch_ms": round(avg, 5),
-                "spmm_u_avg_ms": round(u_avg, 5), "spmm_v_avg_ms": round(v_avg, 5)}
-
-    labels_np = labels.cpu().numpy()
+    res = time_jobs(args, inp, x, x_dtype, dev, args.steps, args.warmup)
+    st = res["stats"]
+    d_eff, l_r, kp = res["dims"]
+    labels_np = res["labels"].cpu().numpy()
+    gedge_hops = shape.gamma * int(st["n_unique_edges"]) / (st["ms_propagate"] * 1e-3) / 1e9 \
+        if st["ms_propagate"] > 0 else None
     result = {
         "metric": METRIC,
-        "value": round(args.steps / elapsed, 3),
+        "value": round(res["value"], 4),
         "unit": "clusterings/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": round(res["ms_per_step"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -284,34 +411,39 @@ def main() -> int:
         "data": "synthetic",
         "config": {
             "workload": f"{args.config}: planted degree-corrected bipartite SBM, |U|={shape.n_u}, "
-                        f"|V|={shape.n_v}, {abg_n_edges} edges, k={shape.k}, Zipf({shape.zipf_a}) degrees, "
-                        f"d_U={abg_d_u} -> d={d_eff}, gamma={shape.gamma}, alpha={shape.alpha}, "
-                        f"q={shape.q}, T_f={shape.t_f}, T_g={shape.t_g}"
+                        f"|V|={shape.n_v}, {shape.n_edges} edges, k={shape.k}, Zipf({shape.zipf_a}) degrees"
+                        + (f" (largest expected degree {shape.max_degree})" if shape.max_degree else "")
+                        + f", d_U={shape.d_u} -> d={d_eff}, gamma={shape.gamma}, alpha={shape.alpha}, "
+                          f"q={shape.q}, T_f={shape.t_f}, T_g={shape.t_g}"
+                        + (", X_U stored as bfloat16" if x_dtype == "bf16" else "")
                         + (", sparse TF-IDF attributes (2% density, abg_synth.tfidf_fp8_device) as FP8 E4M3 "
                            "with column scales" if args.config == "fp8_tfidf" else ""),
-            "n_u": shape.n_u, "n_v": shape.n_v, "n_edges": abg_n_edges, "k": shape.k, "d_u": abg_d_u,
+            "n_u": shape.n_u, "n_v": shape.n_v, "n_edges": shape.n_edges, "k": shape.k, "d_u": shape.d_u,
             "d": d_eff, "k_prime": kp, "l_r": l_r, "gamma": shape.gamma, "x_dtype": x_dtype, "nci": args.nci,
         },
         "gedge_hop_per_s": round(gedge_hops, 3) if gedge_hops else None,
-        "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 4),
-                       "p99": round(float(np.percentile(step_ms, 99)), 4)},
+        "latency_ms": {"p50": round(res["p50"], 4), "p99": round(res["p99"], 4)},
         "stage_ms": {k[3:]: round(v, 4) for k, v in st.items() if k.startswith("ms_")},
-        "roofline": roofline,
-        "objective": obj[0],
+        "roofline": spmm_roofline(args.config, shape, st, d_eff),
+        "mfma_util": mfma_util(args.config + ("_bf16" if x_dtype == "bf16" else "")),
+        "objective": res["obj"][0],
         # recovery of the planted clusters (ACC, NMI, ARI of the paper's quality tables)
-        "quality": {key: round(v, 6) for key, v in quality.report(truth, labels_np).items()},
+        "quality": {key: round(v, 6) for key, v in quality.report(inp["truth"], labels_np).items()},
     }
     log(f"[bench] planted clusters recovered: {result['quality']}")
+    plan_t = res["plan_t"]
 
     if x_dtype == "fp8":
         # error of the FP8 path against FP64 arithmetic on the same codes: the
         # attribute Gram entry by entry, and X' = X Psi_d on sampled rows
         # (after the timed region; the FP64 Gram is torch's, on the GPU)
+        import numpy as np
+
         def plan_t_buf(name):
             return tpo.tpo_plan_buffer(plan_t.handle, plan_t.workspace, name)
 
-        sc = x_scale.double()
-        c_ref = torch.zeros(abg_d_u, abg_d_u, dtype=torch.float64, device=dev)
+        sc = inp["x_scale"].double()
+        c_ref = torch.zeros(shape.d_u, shape.d_u, dtype=torch.float64, device=dev)
         for r0 in range(0, shape.n_u, 125_000):
             xd = x[r0:r0 + 125_000].double() * sc[None, :]
             c_ref += xd.T @ xd
@@ -326,34 +458,41 @@ def main() -> int:
         result["vs_fp64"] = {"gram_max_rel_err": gram_rel, "xprime_rel_err_sampled_rows": xp_rel}
         log(f"[bench] FP8 path vs FP64 on the same codes: Gram max entry rel err {gram_rel:.2e}, "
             f"X' rel err on 2,000 sampled rows {xp_rel:.2e}")
+    plan_t.close()
+    del plan_t, res["plan_t"]
 
-    if x_dtype == "bf16" and args.compare_f32:
-        # the plain FP32 job on the same graph (X not rounded): how far the
-        # precision form moves the result
-        from scipy.optimize import linear_sum_assignment
+    if compare:
+        # the plain FP32 job on the same graph (X not rounded), timed the same
+        # way: the metric's "vs plain FP32 GPU", and how far the precision form
+        # moves the result
+        r32 = time_jobs(args, inp, x_f32, "f32", dev, args.steps, args.warmup, instrument=False)
+        agree = best_match_agreement(labels_np, r32["labels"].cpu().numpy(), shape.k)
+        sin_t = sin_theta_device(res["emb"], r32["emb"])
+        result["vs_plain_fp32"] = {
+            "value": round(r32["value"], 4), "ms_per_step": round(r32["ms_per_step"], 4),
+            "speedup": round(res["value"] / r32["value"], 4),
+            "latency_ms": {"p50": round(r32["p50"], 4), "p99": round(r32["p99"], 4)},
+            "label_agreement": round(agree, 6),
+            "objective_rel_diff": abs(res["obj"][0] - r32["obj"][0]) / abs(r32["obj"][0]),
+            "embedding_sin_theta": sin_t,
+        }
+        log(f"[bench] plain FP32 job on the same graph: {r32['ms_per_step']:.3f} ms/step "
+            f"(bf16 speedup {result['vs_plain_fp32']['speedup']:.3f}); labels agree on {agree:.4%} of the rows, "
+            f"objective rel diff {result['vs_plain_fp32']['objective_rel_diff']:.2e}, embedding sin theta {sin_t:.2e}")
+        del r32
 
-        kw32 = dict(kw, x_dtype="f32")
-        plan32 = tpo.Plan.create(shape.n_u, shape.n_v, abg_n_edges, abg_d_u, device=dev, timing=False, **kw32)
-        lab32 = torch.empty_like(labels)
-        obj32 = tpo.tpo_execute(plan32.handle, eu, ev, x_f32, plan32.workspace, lab32)
-        torch.cuda.synchronize()
-        plan32.close()
-        a, b = labels_np.astype(np.int64), lab32.cpu().numpy().astype(np.int64)
-        table = np.zeros((shape.k, shape.k), np.int64)
-        np.add.at(table, (a, b), 1)
-        r, c = linear_sum_assignment(-table)
-        agree = float(table[r, c].sum() / a.size)
-        result["vs_f32"] = {"label_agreement": round(agree, 6),
-                            "objective_rel_diff": abs(obj[0] - obj32[0]) / abs(obj32[0])}
-        log(f"[bench] plain FP32 run on the same graph: labels agree on {agree:.4%} of the rows (best matching), "
-            f"objective rel diff {result['vs_f32']['objective_rel_diff']:.2e}")
-
-    if args.cpu_baseline == "on" and on_device:
-        log("[bench] no CPU baseline for the on-GPU generated workload (the oracle needs the host arrays)")
-    if args.cpu_baseline == "on" and not on_device:
+    if args.cpu_baseline == "on" and inp["on_device"]:
+        # a bounded sample: the oracle's propagation hop on a tenth of the target rows
+        c0 = time.perf_counter()
+        result["cpu_baseline"] = cpu_baseline_sample(inp, shape)
+        log(f"[bench] oracle sample {result['cpu_baseline']['value']:.5f} GEdge-hop/s "
+            f"({time.perf_counter() - c0:.1f} s with its set-up)")
+    if args.cpu_baseline == "on" and not inp["on_device"]:
         import oracle
+        import abg_synth as synth
         from threadpoolctl import threadpool_info
 
+        abg = inp["abg"]
         mm = synth.method_matrices(args.seed, abg.d_u, shape.d, shape.k, shape.oversample)
         threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
         # whole jobs, repeated until about 10 s of CPU work (at most 3 jobs)
@@ -376,11 +515,31 @@ def main() -> int:
         }
         result["parity"] = {
             "labels_match_oracle": bool(oracle.labels_match_up_to_permutation(labels_np, ref.labels)),
-            "objective_rel_err": abs(obj[0] - ref.objective) / abs(ref.objective),
+            "objective_rel_err": abs(res["obj"][0] - ref.objective) / abs(ref.objective),
+            "embedding_sin_theta": float(oracle.subspace_sin_theta(res["emb"].cpu().numpy(), ref.ups)),
         }
         log(f"[bench] oracle {c_el:.1f}s on {threads} threads; parity {result['parity']}")
-    plan.close()
-    plan_t.close()
+
+    if args.config == "large" and args.mid == "on":
+        # the mid-size FP32 workload, beside the headline
+        del inp, x, x_f32
+        torch.cuda.empty_cache()
+        inp_m = make_input(args, "mid_fp32", dev)
+        rm = time_jobs(args, inp_m, inp_m["x"], "f32", dev, 20, 3)
+        stm = rm["stats"]
+        rm["plan_t"].close()
+        shm = inp_m["shape"]
+        result["mid"] = {
+            "workload": f"mid_fp32: |U|={shm.n_u}, |V|={shm.n_v}, {shm.n_edges} edges, k={shm.k}, "
+                        f"d_U={shm.d_u} -> d={shm.d}, FP32",
+            "value": round(rm["value"], 3), "unit": "clusterings/s", "ms_per_step": round(rm["ms_per_step"], 4),
+            "steps": 20, "warmup": 3,
+            "gedge_hop_per_s": round(shm.gamma * int(stm["n_unique_edges"]) / (stm["ms_propagate"] * 1e-3) / 1e9, 3),
+            "latency_ms": {"p50": round(rm["p50"], 4), "p99": round(rm["p99"], 4)},
+            "stage_ms": {k[3:]: round(v, 4) for k, v in stm.items() if k.startswith("ms_")},
+            "roofline": spmm_roofline("mid_fp32", shm, stm, rm["dims"][0]),
+            "mfma_util": mfma_util("mid_fp32"),
+        }
     print(json.dumps(result), flush=True)
     return 0
 

@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-#define TPO_ABI_VERSION 2
+#define TPO_ABI_VERSION 3
 
 typedef enum tpo_status {
   TPO_OK = 0,
@@ -140,6 +140,11 @@ typedef struct tpo_stats {
    * (Z = X' + alpha D_U^-1/2 B T), milliseconds and launch counts. */
   double ms_spmm_v, ms_spmm_u;
   int32_t n_spmm_v, n_spmm_u;
+  /* NCI with k > 32 scores on FP32 MFMA; rows whose two best scores lie
+   * within the FP32 error bound are scored again in FP64.  How many, summed
+   * over the rounds. */
+  int32_t nci_rechecked;
+  int32_t reserved;
 } tpo_stats;
 
 typedef struct tpo_plan tpo_plan;

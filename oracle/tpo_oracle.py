@@ -44,9 +44,9 @@ __all__ = [
     "column_sign_convention",
     "top_d_attribute_svd",
     "exact_top_d_attribute_svd",
+    "top_d_gram_basis",
     "reduce_attributes",
     "onmf",
-    "onmf_loss",
     "nci",
     "polar_factor",
     "objective",
@@ -316,6 +316,36 @@ def top_d_attribute_svd(x: np.ndarray, d: int, omega_r: np.ndarray, q: int):
     return psi, sig
 
 
+def top_d_gram_basis(c: np.ndarray, colsum_x: np.ndarray, n_rows: int, d: int, omega_r: np.ndarray, q: int):
+    """The reduction basis Psi_d of Section 3.2.1 from the Gram matrix alone:
+    the same randomized subspace iteration and Rayleigh-Ritz step as
+    top_d_attribute_svd, applied to a given C = X^T X, with the column sign
+    convention evaluated through X's column sums (sum_i (X Psi)[i, c] =
+    colsum_x . Psi[:, c], ||X Psi[:, c]||_2 = sqrt(Psi[:, c]^T C Psi[:, c])).
+    For checking a device's Psi_d against the device's own Gram when X itself
+    is too large to hold on the host.  Returns (Psi_d, sigma_d)."""
+    c = np.asarray(c, dtype=np.float64)
+    c = 0.5 * (c + c.T)
+    qm = orthonormal_basis(c @ omega_r)
+    for _ in range(q):
+        qm = orthonormal_basis(c @ qm)
+    t = qm.T @ c @ qm
+    t = 0.5 * (t + t.T)
+    evals, evecs = np.linalg.eigh(t)
+    order = np.argsort(-evals, kind="stable")[:d]
+    psi = qm @ evecs[:, order]
+    sig = np.sqrt(np.maximum(evals[order], 0.0))
+    colsum_x = np.asarray(colsum_x, dtype=np.float64)
+    for j in range(psi.shape[1]):
+        s = float(colsum_x @ psi[:, j])
+        norm2 = math.sqrt(max(float(psi[:, j] @ c @ psi[:, j]), 0.0))
+        if abs(s) <= 1e-9 * math.sqrt(n_rows) * norm2:
+            s = psi[int(np.argmax(np.abs(psi[:, j]))), j]
+        if s < 0:
+            psi[:, j] = -psi[:, j]
+    return psi, sig
+
+
 def exact_top_d_attribute_svd(x: np.ndarray, d: int):
     """Exact top-d right singular vectors of X (LAPACK), same sign convention."""
     x = np.asarray(x, dtype=np.float64)
@@ -366,14 +396,6 @@ def onmf(r: np.ndarray, gam: np.ndarray, sig: np.ndarray, psi: np.ndarray, t_f: 
     return ups, h, hits
 
 
-def onmf_loss(r, ups, h) -> float:
-    """||R - Ups H^T||_F^2 (Eq. obj4's objective)."""
-    return float(np.sum((np.asarray(r) - np.asarray(ups) @ np.asarray(h).T) ** 2))
-
-
-# ---------------------------------------------------------------------------
-# Algorithm 3: effective NCI generation (Eqs. ell-ast, Y-update, y-norm)
-# ---------------------------------------------------------------------------
 def polar_factor(m: np.ndarray) -> np.ndarray:
     """The orthogonal factor of M's polar decomposition, U V^T for the SVD
     M = U S V^T: the orthogonal Phi that minimises ||A Phi - B||_F when

@@ -22,7 +22,7 @@ __all__ = [
     "tpo_status_string", "BUF", "Plan", "cluster", "tpo_execute_noalloc", "TPO_NOALLOC_MAX_BYTES",
 ]
 
-TPO_ABI_VERSION = 2
+TPO_ABI_VERSION = 3
 TPO_FLAG_TIMING = 1
 TPO_FLAG_ONE_STREAM = 2
 TPO_FLAG_NCI_PROCRUSTES = 4
@@ -87,7 +87,8 @@ class TpoStats(C.Structure):
                 ("n_unique_edges", C.c_int64), ("guard_hits", C.c_int32),
                 ("isolated_u", C.c_int32), ("isolated_v", C.c_int32),
                 ("ms_spmm_v", C.c_double), ("ms_spmm_u", C.c_double),
-                ("n_spmm_v", C.c_int32), ("n_spmm_u", C.c_int32)]
+                ("n_spmm_v", C.c_int32), ("n_spmm_u", C.c_int32),
+                ("nci_rechecked", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -22,51 +22,60 @@ typedef double v4d_t __attribute__((ext_vector_type(4)));
 // A[l % 16][l / 16] and B[l / 16][l % 16], its v-th result is
 // D[4 (l / 16) + v][l % 16]).
 //
-// A workgroup walks 64-row slabs of R (rows padded to TD = 16 JT columns,
-// zeros beyond 2d), with the next slab's loads in flight while the current
-// one is processed.  Wave w forms rows 16 w.. of the 64 x k output block:
+// A workgroup of eight (or four) waves walks slabs of 64 (or 32) rows of R (rows padded
+// to TD = 16 JT columns, zeros beyond 2d), with the next slab's loads in
+// flight while the current one is processed.  The waves split the 16-row
+// tiles and the 16-column output tiles of the slab:
 //   kProject: O = R S            (Gamma; also written as Upsilon)
 //   kOnmf:    P = R H, Q = U A,  O = U * sqrt(P / Q)   (Eq. update-Y; a zero
 //             denominator keeps U, a negative ratio gives 0)
-// then the waves accumulate the tiles of R^T O (2d x k) and O^T O (k x k) in
-// FP32 registers over the workgroup's rows; the totals are written as FP64
-// partials.
+// Every wave first forms all its P and Q tiles in registers; after a barrier
+// O replaces U in the same LDS slab, so one slab buffer serves both.  Then the
+// waves accumulate the tiles of R^T O (2d x k) and O^T O (k x k) in FP32
+// registers over the workgroup's rows; the totals are written as FP64
+// partials.  S (or H) and A stay in LDS for the whole pass when they fit.
 constexpr int kRpRows = 64;
+// Waves per workgroup: eight for k in 65..128 with 2d <= 128, where a
+// workgroup of four could run only one wave per SIMD (S and A fill the LDS);
+// four otherwise (two or more such workgroups share a CU, and for 2d = 256
+// with k > 64 the registers would not fit two waves a SIMD).
+__host__ __device__ constexpr int rp_waves(int jt, int kt) { return (kt >= 5 && jt * kt <= 64) ? 8 : 4; }
 
 template <int MODE, int JT, int KT>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(64 * rp_waves(JT, KT))
 k_rowpass_mfma(const float* __restrict__ R, int64_t n, int twod, int k, const float* __restrict__ Sm,
                const float* __restrict__ A32, float* __restrict__ U, float* __restrict__ out,
                float* __restrict__ out2, int rows_per_block, double* __restrict__ part,
                DevStatus* __restrict__ st) {
+  constexpr int kRpWaves = rp_waves(JT, KT), kRpThreads = 64 * kRpWaves;
   constexpr int TD = 16 * JT, KP = 16 * KT;
   constexpr int RS = TD + 4, OS = KP + 4;
-  constexpr int NQ = (JT * KT + 3) / 4, NQ2 = (KT * KT + 3) / 4;
-  // S (or H) and A are staged in LDS when they fit (SLDS, ALDS); otherwise
-  // their operands are read from global memory (they are small and cached).
-  // Slab rows: 64, or 32 when 64 would not fit; RTILES row tiles, each formed
-  // by WPR waves that split the output column tiles.
+  constexpr int NQ = (JT * KT + kRpWaves - 1) / kRpWaves, NQ2 = (KT * KT + kRpWaves - 1) / kRpWaves;
+  constexpr int LDS_CAP = 156 * 1024;
+  // LDS: the R slab (ROWS x RS), the U/O slab (ROWS x OS), S (TD x OS) and,
+  // for kOnmf, A (KP x OS) when they fit; slabs of 64 rows, or 32 when 64
+  // would not fit.  Operands that do not fit are read from global memory.
   constexpr bool SLDS = TD * OS * 4 <= 72 * 1024;
   constexpr int SFIX = SLDS ? TD * OS : 0;
-  constexpr bool ALDS = 4 * ((kRpRows / 2) * RS + kRpRows * OS + SFIX + KP * OS) <= 156 * 1024;
+  constexpr bool ALDS = MODE == kOnmf && 4 * ((kRpRows / 2) * (RS + OS) + SFIX + KP * OS) <= LDS_CAP;
   constexpr int FIXED = SFIX + (ALDS ? KP * OS : 0);
-  constexpr int ROWS = 4 * (kRpRows * RS + 2 * kRpRows * OS + FIXED) <= 150 * 1024 ? kRpRows : kRpRows / 2;
-  constexpr int RTILES = ROWS / 16, WPR = 4 / RTILES;
-  constexpr int RPT = ROWS * TD / 256, UPT = ROWS * KP / 256;  // prefetched elements per thread
+  constexpr int ROWS = 4 * (kRpRows * (RS + OS) + FIXED) <= LDS_CAP ? kRpRows : kRpRows / 2;
+  constexpr int RTILES = ROWS / 16, WPR = kRpWaves / RTILES;  // waves per row tile
+  constexpr int KTW = (KT + WPR - 1) / WPR;                    // column tiles per wave
+  constexpr int RPT = ROWS * TD / kRpThreads, UPT = ROWS * KP / kRpThreads;  // prefetched per thread
   __shared__ float Rt[ROWS * RS];
   __shared__ float Ut[ROWS * OS];
-  __shared__ float Ot[ROWS * OS];
   __shared__ float Ss[SLDS ? TD * OS : 1];  // S (or H), TD x KP, zero padded
   __shared__ float As[ALDS ? KP * OS : 1];  // A (kOnmf), KP x KP, zero padded
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int i16 = lane & 15, kq = lane >> 4;
   if (SLDS)
-    for (int e = tid; e < TD * KP; e += 256) {
+    for (int e = tid; e < TD * KP; e += kRpThreads) {
       const int r = e / KP, c = e - (e / KP) * KP;
       Ss[r * OS + c] = (r < twod && c < k) ? Sm[r * k + c] : 0.0f;
     }
-  if (MODE == kOnmf && ALDS)
-    for (int e = tid; e < KP * KP; e += 256) {
+  if (ALDS)
+    for (int e = tid; e < KP * KP; e += kRpThreads) {
       const int r = e / KP, c = e - (e / KP) * KP;
       As[r * OS + c] = (r < k && c < k) ? A32[r * k + c] : 0.0f;
     }
@@ -92,7 +101,7 @@ k_rowpass_mfma(const float* __restrict__ R, int64_t n, int twod, int k, const fl
   auto fetch = [&](int64_t r0) {
 #pragma unroll
     for (int u = 0; u < RPT; ++u) {
-      const int e = tid + 256 * u;
+      const int e = tid + kRpThreads * u;
       const int rr = e / TD, c = e - rr * TD;
       const int64_t row = r0 + rr;
       rr_[u] = (row < re && c < twod) ? R[row * twod + c] : 0.0f;
@@ -100,7 +109,7 @@ k_rowpass_mfma(const float* __restrict__ R, int64_t n, int twod, int k, const fl
     if (MODE == kOnmf) {
 #pragma unroll
       for (int u = 0; u < UPT; ++u) {
-        const int e = tid + 256 * u;
+        const int e = tid + kRpThreads * u;
         const int rr = e / KP, c = e - rr * KP;
         const int64_t row = r0 + rr;
         uu_[u] = (row < re && c < k) ? U[row * k + c] : 0.0f;
@@ -108,38 +117,51 @@ k_rowpass_mfma(const float* __restrict__ R, int64_t n, int twod, int k, const fl
     }
   };
   if (rb < re) fetch(rb);
+  const int rw = 16 * (w % RTILES);  // this wave's rows in the slab
+  const int kt0 = w / RTILES;         // its column tiles: kt0, kt0 + WPR, ...
   for (int64_t r0 = rb; r0 < re; r0 += ROWS) {
 #pragma unroll
     for (int u = 0; u < RPT; ++u) {
-      const int e = tid + 256 * u;
+      const int e = tid + kRpThreads * u;
       const int rr = e / TD, c = e - rr * TD;
       Rt[rr * RS + c] = rr_[u];
     }
     if (MODE == kOnmf) {
 #pragma unroll
       for (int u = 0; u < UPT; ++u) {
-        const int e = tid + 256 * u;
+        const int e = tid + kRpThreads * u;
         const int rr = e / KP, c = e - rr * KP;
         Ut[rr * OS + c] = uu_[u];
       }
     }
     __syncthreads();
     if (r0 + ROWS < re) fetch(r0 + ROWS);
-    const int rw = 16 * (w % RTILES);  // this wave's rows in the slab
+    // P (and Q) of every owned tile, in registers
+    v4f_t pv[KTW], qv[KTW];
 #pragma unroll
-    for (int kt = w / RTILES; kt < KT; kt += WPR) {
-      v4f_t pv = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 8
-      for (int t = 0; t < TD / 4; ++t)
-        pv = __builtin_amdgcn_mfma_f32_16x16x4f32(Rt[(rw + i16) * RS + 4 * t + kq], s_op(4 * t + kq, 16 * kt + i16),
-                                                  pv, 0, 0, 0);
-      v4f_t qv = {0.f, 0.f, 0.f, 0.f};
-      if (MODE == kOnmf) {
-#pragma unroll 8
-        for (int t = 0; t < KP / 4; ++t)
-          qv = __builtin_amdgcn_mfma_f32_16x16x4f32(Ut[(rw + i16) * OS + 4 * t + kq], a_op(4 * t + kq, 16 * kt + i16),
-                                                    qv, 0, 0, 0);
+    for (int i = 0; i < KTW; ++i) {
+      const int kt = kt0 + i * WPR;
+      pv[i] = v4f_t{0.f, 0.f, 0.f, 0.f};
+      qv[i] = v4f_t{0.f, 0.f, 0.f, 0.f};
+      if (kt < KT) {
+#pragma unroll 4
+        for (int t = 0; t < TD / 4; ++t)
+          pv[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(Rt[(rw + i16) * RS + 4 * t + kq],
+                                                       s_op(4 * t + kq, 16 * kt + i16), pv[i], 0, 0, 0);
+        if (MODE == kOnmf) {
+#pragma unroll 4
+          for (int t = 0; t < KP / 4; ++t)
+            qv[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(Ut[(rw + i16) * OS + 4 * t + kq],
+                                                         a_op(4 * t + kq, 16 * kt + i16), qv[i], 0, 0, 0);
+        }
       }
+    }
+    // every wave has read the U slab; O replaces it
+    if (MODE == kOnmf) __syncthreads();
+#pragma unroll
+    for (int i = 0; i < KTW; ++i) {
+      const int kt = kt0 + i * WPR;
+      if (kt >= KT) continue;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int rl = rw + 4 * kq + v, c = 16 * kt + i16;
@@ -147,14 +169,14 @@ k_rowpass_mfma(const float* __restrict__ R, int64_t n, int twod, int k, const fl
         const bool live = row < re && c < k;
         float o;
         if (MODE == kProject) {
-          o = pv[v];
+          o = pv[i][v];
         } else {
           const float u = Ut[rl * OS + c];
-          if (qv[v] == 0.0f) {
+          if (qv[i][v] == 0.0f) {
             o = u;
             hits += live ? 1 : 0;
           } else {
-            const float ratio = pv[v] / qv[v];
+            const float ratio = pv[i][v] / qv[i][v];
             if (ratio < 0.0f) {
               o = 0.0f;
               hits += live ? 1 : 0;
@@ -164,7 +186,7 @@ k_rowpass_mfma(const float* __restrict__ R, int64_t n, int twod, int k, const fl
           }
         }
         if (!live) o = 0.0f;
-        Ot[rl * OS + c] = o;
+        Ut[rl * OS + c] = o;
         if (live) {
           if (!isfinite(o)) bad = true;
           mx = fmaxf(mx, fabsf(o));
@@ -181,26 +203,26 @@ k_rowpass_mfma(const float* __restrict__ R, int64_t n, int twod, int k, const fl
     __syncthreads();
 #pragma unroll
     for (int qi = 0; qi < NQ; ++qi) {
-      const int q = w + 4 * qi;
+      const int q = w + kRpWaves * qi;
       if (q < JT * KT) {
         const int jt = q / KT, kt = q - (q / KT) * KT;
 #pragma unroll 4
         for (int s4 = 0; s4 < ROWS / 4; ++s4) {
           const int rr = 4 * s4 + kq;
-          acc[qi] = __builtin_amdgcn_mfma_f32_16x16x4f32(Rt[rr * RS + 16 * jt + i16], Ot[rr * OS + 16 * kt + i16],
+          acc[qi] = __builtin_amdgcn_mfma_f32_16x16x4f32(Rt[rr * RS + 16 * jt + i16], Ut[rr * OS + 16 * kt + i16],
                                                          acc[qi], 0, 0, 0);
         }
       }
     }
 #pragma unroll
     for (int qi = 0; qi < NQ2; ++qi) {
-      const int q = w + 4 * qi;
+      const int q = w + kRpWaves * qi;
       if (q < KT * KT) {
         const int ta = q / KT, tb = q - (q / KT) * KT;
 #pragma unroll 4
         for (int s4 = 0; s4 < ROWS / 4; ++s4) {
           const int rr = 4 * s4 + kq;
-          acc2[qi] = __builtin_amdgcn_mfma_f32_16x16x4f32(Ot[rr * OS + 16 * ta + i16], Ot[rr * OS + 16 * tb + i16],
+          acc2[qi] = __builtin_amdgcn_mfma_f32_16x16x4f32(Ut[rr * OS + 16 * ta + i16], Ut[rr * OS + 16 * tb + i16],
                                                           acc2[qi], 0, 0, 0);
         }
       }
@@ -211,7 +233,7 @@ k_rowpass_mfma(const float* __restrict__ R, int64_t n, int twod, int k, const fl
   double* pb = part + static_cast<int64_t>(blockIdx.x) * len;
 #pragma unroll
   for (int qi = 0; qi < NQ; ++qi) {
-    const int q = w + 4 * qi;
+    const int q = w + kRpWaves * qi;
     if (q < JT * KT) {
       const int jt = q / KT, kt = q - (q / KT) * KT;
 #pragma unroll
@@ -223,7 +245,7 @@ k_rowpass_mfma(const float* __restrict__ R, int64_t n, int twod, int k, const fl
   }
 #pragma unroll
   for (int qi = 0; qi < NQ2; ++qi) {
-    const int q = w + 4 * qi;
+    const int q = w + kRpWaves * qi;
     if (q < KT * KT) {
       const int ta = q / KT, tb = q - (q / KT) * KT;
 #pragma unroll
@@ -281,12 +303,12 @@ static void rowpass_jk(const Plan& p, void* ws, int mode, const float* Sm, const
   const int nb = p.rowpass_blocks;
   const int rpb = static_cast<int>((p.n + nb - 1) / nb);
   if (mode == kProject)
-    hipLaunchKernelGGL((k_rowpass_mfma<kProject, JT, KT>), dim3(nb), dim3(256), 0, s, bufp<float>(p, ws, B_R),
+    hipLaunchKernelGGL((k_rowpass_mfma<kProject, JT, KT>), dim3(nb), dim3(64 * rp_waves(JT, KT)), 0, s, bufp<float>(p, ws, B_R),
                        static_cast<int64_t>(p.n), p.twod, p.k, Sm, A32, bufp<float>(p, ws, B_UPS),
                        bufp<float>(p, ws, B_GAMMA), bufp<float>(p, ws, B_UPS), rpb,
                        bufp<double>(p, ws, B_ONMF_PART), st);
   else
-    hipLaunchKernelGGL((k_rowpass_mfma<kOnmf, JT, KT>), dim3(nb), dim3(256), 0, s, bufp<float>(p, ws, B_R),
+    hipLaunchKernelGGL((k_rowpass_mfma<kOnmf, JT, KT>), dim3(nb), dim3(64 * rp_waves(JT, KT)), 0, s, bufp<float>(p, ws, B_R),
                        static_cast<int64_t>(p.n), p.twod, p.k, Sm, A32, bufp<float>(p, ws, B_UPS), nullptr,
                        nullptr, rpb, bufp<double>(p, ws, B_ONMF_PART), st);
   TPO_LAUNCH_CHECK();
@@ -473,43 +495,66 @@ k_nci_round(const float* __restrict__ U, int64_t n, int k, const long long* __re
 }
 
 // k > 32: scoring and the label sums in two kernels (Phi for 128 labels
-// fills most of the LDS on its own; for k in 33..64 the one-kernel round
+// fills much of the LDS on its own; for k in 33..64 the one-kernel round
 // above needs a whole SIMD's registers per wave for its k scores).
 //
-// Scores on FP64 MFMA (v_mfma_f64_16x16x4f64: lane l supplies A[l % 16][l / 16]
-// and B[l / 16][l % 16], its v-th result is D[4 v + l / 16][l % 16]).  A wave
+// Scores on FP32 MFMA (v_mfma_f32_16x16x4f32: lane l supplies A[l % 16][l / 16]
+// and B[l / 16][l % 16], its v-th result is D[4 (l / 16) + v][l % 16]).  A wave
 // forms S^T = Phi^T U^T for 16 rows at a time: A = Phi^T (a 16-label tile),
 // B = U^T (the 16 rows), so lane l ends with the scores of row l % 16 for the
-// labels 16 c + 4 v + l / 16, and the first maximum is found in registers and
-// then over the four lanes that share the row.  Phi (k x 16 LT, zero padded)
-// sits in LDS; eight waves share it, two per SIMD.
+// labels 16 c + 4 (l / 16) + v; the first maximum and the runner-up are found
+// in registers and then over the four lanes that share the row.  Phi (k x 16
+// LT, FP64 values rounded to FP32, zero padded) sits in LDS; eight waves share
+// it.
+//
+// The decision must be the one FP64 scores give.  Each FP32 score is within
+// (k + 2) 2^-24 ||u_i||_2 max_l ||phi_l||_2 of the exact one (k rounded
+// products and sums, and the rounding of Phi to FP32); a row whose two best
+// scores are closer than twice that (with a factor two to spare) goes to a
+// list, and k_nci_recheck recomputes its scores in FP64.
 constexpr int kNciWide = 128;
+constexpr int kNciMaxRounds = 1024;  // round counters of the recheck list
 
 template <int LT>
 __global__ void __launch_bounds__(512)
 k_nci_score_mfma(const float* __restrict__ U, int64_t n, int k, const long long* __restrict__ sums,
-                 const double* __restrict__ phi_g, int32_t* __restrict__ labels, const DevStatus* __restrict__ st) {
+                 const double* __restrict__ phi_g, int32_t* __restrict__ labels, int32_t* __restrict__ check_count,
+                 int32_t* __restrict__ check_rows, const DevStatus* __restrict__ st) {
   constexpr int NL = 16 * LT;
   constexpr int KS = NL / 4;  // k steps of the padded contraction
-  __shared__ double phi[NL * NL];  // phi[t * NL + l]
+  __shared__ float phi[NL * NL];  // phi[t * NL + l]
   __shared__ double fac[NL];
+  __shared__ unsigned int colmax_bits;  // max_l ||phi_l||_2 as float bits
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int i16 = lane & 15, g = lane >> 4;
   const int sft = fixed_point_shift(__uint_as_float(st->maxabs_ups_bits), n);
   const double inv_scale = ldexp(1.0, -sft);
+  if (tid == 0) colmax_bits = 0u;
   if (sums && tid < k) {
     const long long c = sums[k * k + tid];
     fac[tid] = c > 0 ? inv_scale / sqrt(static_cast<double>(c)) : 0.0;
   }
   __syncthreads();
+  auto phi64 = [&](int t, int l) -> double {
+    if (t >= k || l >= k) return 0.0;
+    return phi_g ? phi_g[t * k + l] : sums ? static_cast<double>(sums[l * k + t]) * fac[l] : (t == l ? 1.0 : 0.0);
+  };
   for (int e = tid; e < NL * NL; e += 512) {
     const int t = e / NL, l = e - (e / NL) * NL;
-    double v = 0.0;
-    if (t < k && l < k)
-      v = phi_g ? phi_g[t * k + l] : sums ? static_cast<double>(sums[l * k + t]) * fac[l] : (t == l ? 1.0 : 0.0);
-    phi[e] = v;
+    phi[e] = static_cast<float>(phi64(t, l));
+  }
+  if (tid < k) {
+    double ss = 0.0;
+    for (int t = 0; t < k; ++t) {
+      const double v = phi64(t, tid);
+      ss = fma(v, v, ss);
+    }
+    // rounded up: an upper bound on the column norm
+    atomicMax(&colmax_bits, __float_as_uint(__double2float_ru(sqrt(ss))));
   }
   __syncthreads();
+  const double tol_scale = static_cast<double>(k + 2) * ldexp(1.0, -24) * 2.0 * 2.0 *
+                           static_cast<double>(__uint_as_float(colmax_bits));
   const int64_t ntiles = (n + 15) / 16;
   for (int64_t tile = static_cast<int64_t>(blockIdx.x) * 8 + w; tile < ntiles;
        tile += static_cast<int64_t>(gridDim.x) * 8) {
@@ -517,48 +562,119 @@ k_nci_score_mfma(const float* __restrict__ U, int64_t n, int k, const long long*
     const bool live = row < n;
     const float* urow = U + row * k;
     float ub[KS];
+    double u2 = 0.0;
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
       const int t = 4 * s + g;
       ub[s] = (live && t < k) ? urow[t] : 0.0f;
+      u2 = fma(static_cast<double>(ub[s]), static_cast<double>(ub[s]), u2);
     }
-    v4d_t acc[LT];
+    v4f_t acc[LT];
 #pragma unroll
-    for (int c = 0; c < LT; ++c) acc[c] = v4d_t{0.0, 0.0, 0.0, 0.0};
+    for (int c = 0; c < LT; ++c) acc[c] = v4f_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
       if (4 * s >= k) break;  // uniform: the padded steps add zeros
-      const double b = static_cast<double>(ub[s]);
-      const double* pr = phi + (4 * s + g) * NL + i16;
+      const float* pr = phi + (4 * s + g) * NL + i16;
 #pragma unroll
-      for (int c = 0; c < LT; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(pr[16 * c], b, acc[c], 0, 0, 0);
+      for (int c = 0; c < LT; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(pr[16 * c], ub[s], acc[c], 0, 0, 0);
     }
-    // first maximum: labels in increasing order within the lane, then the
-    // lower label wins a tie between lanes
-    int best = g;
-    double bestv = acc[0][0];
+    // first maximum and runner-up: labels in increasing order within the
+    // lane, then the lower label wins a tie between lanes
+    int best = 4 * g;
+    float bestv = -INFINITY, second = -INFINITY;
 #pragma unroll
     for (int c = 0; c < LT; ++c) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int L = 16 * c + 4 * v + g;
-        if (L < k && acc[c][v] > bestv) {
-          bestv = acc[c][v];
-          best = L;
+        const int L = 16 * c + 4 * g + v;
+        if (L < k) {
+          const float x = acc[c][v];
+          if (x > bestv) {
+            second = bestv;
+            bestv = x;
+            best = L;
+          } else if (x > second) {
+            second = x;
+          }
         }
       }
     }
 #pragma unroll
     for (int off = 16; off < 64; off <<= 1) {
+      const float ov = __shfl_xor(bestv, off, 64);
+      const float os = __shfl_xor(second, off, 64);
+      const int ob = __shfl_xor(best, off, 64);
+      u2 += __shfl_xor(u2, off, 64);
+      if (ov > bestv || (ov == bestv && ob < best)) {
+        second = fmaxf(bestv, os);
+        bestv = ov;
+        best = ob;
+      } else {
+        second = fmaxf(second, ov);
+      }
+    }
+    if (live && g == 0) {
+      labels[row] = best;
+      if (static_cast<double>(bestv) - static_cast<double>(second) <= tol_scale * sqrt(u2)) {
+        const int slot = atomicAdd(check_count, 1);
+        check_rows[slot] = static_cast<int32_t>(row);
+      }
+    }
+  }
+}
+
+// The rows whose FP32 decision was too close: FP64 scores (Phi from the same
+// sums, or phi_g, or the identity), first maximum, one wave per row.
+__global__ void __launch_bounds__(256)
+k_nci_recheck(const float* __restrict__ U, int k, const long long* __restrict__ sums,
+              const double* __restrict__ phi_g, const int32_t* __restrict__ check_count,
+              const int32_t* __restrict__ check_rows, int32_t* __restrict__ labels, int64_t n,
+              DevStatus* __restrict__ st) {
+  const int lane = threadIdx.x & 63;
+  const int cnt = *check_count;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && cnt > 0) atomicAdd(&st->nci_rechecked, cnt);
+  const int sft = fixed_point_shift(__uint_as_float(st->maxabs_ups_bits), n);
+  const double inv_scale = ldexp(1.0, -sft);
+  const int waves = static_cast<int>(gridDim.x) * 4;
+  for (int i = static_cast<int>(blockIdx.x) * 4 + static_cast<int>(threadIdx.x >> 6); i < cnt; i += waves) {
+    const int64_t row = check_rows[i];
+    const float* urow = U + row * k;
+    int best = -1;
+    double bestv = 0.0;
+    for (int l = lane; l < k; l += 64) {
+      double f = 1.0;
+      if (!phi_g && sums) {
+        const long long c = sums[k * k + l];
+        f = c > 0 ? inv_scale / sqrt(static_cast<double>(c)) : 0.0;
+      }
+      double sc = 0.0;
+      for (int t = 0; t < k; ++t) {
+        const double ph = phi_g ? phi_g[t * k + l] : sums ? static_cast<double>(sums[l * k + t]) * f
+                                                          : (t == l ? 1.0 : 0.0);
+        sc = fma(static_cast<double>(urow[t]), ph, sc);
+      }
+      if (best < 0 || sc > bestv) {
+        bestv = sc;
+        best = l;
+      }
+    }
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
       const double ov = __shfl_xor(bestv, off, 64);
       const int ob = __shfl_xor(best, off, 64);
-      if (ov > bestv || (ov == bestv && ob < best)) {
+      if (ob >= 0 && (best < 0 || ov > bestv || (ov == bestv && ob < best))) {
         bestv = ov;
         best = ob;
       }
     }
-    if (live && g == 0) labels[row] = best;
+    if (lane == 0) labels[row] = best;
   }
+}
+
+__global__ void k_zero_i32(int32_t* __restrict__ a, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = 0;
 }
 
 // Fixed-point sums of the U rows per label and the label counts for this
@@ -618,13 +734,18 @@ k_nci_accum_wide(const float* __restrict__ U, int64_t n, int k, const int32_t* _
 
 template <int LT>
 static void nci_score_mfma(const float* U, int64_t n, int k, const long long* sums, const double* phi_g,
-                           int32_t* labels, const DevStatus* st, hipStream_t s) {
+                           int32_t* labels, int32_t* check_count, int32_t* check_rows, DevStatus* st,
+                           hipStream_t s) {
   constexpr int NL = 16 * LT;
-  constexpr size_t lds = static_cast<size_t>(NL) * NL * 8 + NL * 8;
+  constexpr size_t lds = static_cast<size_t>(NL) * NL * 4 + NL * 8 + 4;
   const int per_cu = std::max<int>(1, static_cast<int>((160 * 1024) / lds));
   const int64_t ntiles = (n + 15) / 16;
   const int nb = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>((ntiles + 7) / 8, 256 * per_cu)));
-  hipLaunchKernelGGL((k_nci_score_mfma<LT>), dim3(nb), dim3(512), 0, s, U, n, k, sums, phi_g, labels, st);
+  hipLaunchKernelGGL((k_nci_score_mfma<LT>), dim3(nb), dim3(512), 0, s, U, n, k, sums, phi_g, labels, check_count,
+                     check_rows, st);
+  TPO_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_nci_recheck, dim3(64), dim3(256), 0, s, U, k, sums, phi_g, check_count, check_rows, labels, n,
+                     st);
   TPO_LAUNCH_CHECK();
 }
 
@@ -817,17 +938,23 @@ static void nci_rounds_wide(const Plan& p, void* ws, hipStream_t s) {
   const float* U = bufp<float>(p, ws, B_UPS);
   int32_t* labels = bufp<int32_t>(p, ws, B_LABELS);
   const int rounds = std::max(p.par.t_g, 1);
+  // recheck lists: one counter per round (zeroed here), one row list
+  int32_t* cnt = bufp<int32_t>(p, ws, B_NCI_CHECK);
+  int32_t* rows = cnt + kNciMaxRounds;
+  hipLaunchKernelGGL(k_zero_i32, dim3(ceil_div(kNciMaxRounds, 256)), dim3(256), 0, s, cnt, kNciMaxRounds);
+  TPO_LAUNCH_CHECK();
   for (int t = 1; t <= rounds; ++t) {
     const long long* sm = t == 1 ? nullptr : sums;
     const double* ph = t == 1 ? nullptr : nci_phi(p, ws, sums, s);
     if (ph) sm = nullptr;
+    int32_t* c = cnt + (t - 1) % kNciMaxRounds;
     switch ((k + 15) / 16) {
-      case 3: nci_score_mfma<3>(U, n, k, sm, ph, labels, st, s); break;
-      case 4: nci_score_mfma<4>(U, n, k, sm, ph, labels, st, s); break;
-      case 5: nci_score_mfma<5>(U, n, k, sm, ph, labels, st, s); break;
-      case 6: nci_score_mfma<6>(U, n, k, sm, ph, labels, st, s); break;
-      case 7: nci_score_mfma<7>(U, n, k, sm, ph, labels, st, s); break;
-      case 8: nci_score_mfma<8>(U, n, k, sm, ph, labels, st, s); break;
+      case 3: nci_score_mfma<3>(U, n, k, sm, ph, labels, c, rows, st, s); break;
+      case 4: nci_score_mfma<4>(U, n, k, sm, ph, labels, c, rows, st, s); break;
+      case 5: nci_score_mfma<5>(U, n, k, sm, ph, labels, c, rows, st, s); break;
+      case 6: nci_score_mfma<6>(U, n, k, sm, ph, labels, c, rows, st, s); break;
+      case 7: nci_score_mfma<7>(U, n, k, sm, ph, labels, c, rows, st, s); break;
+      case 8: nci_score_mfma<8>(U, n, k, sm, ph, labels, c, rows, st, s); break;
       default: throw std::runtime_error("NCI: k outside 33..128 on the two-kernel path");
     }
     if (t < p.par.t_g) {

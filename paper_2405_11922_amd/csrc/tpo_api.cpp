@@ -166,6 +166,7 @@ void build_layout(Plan& p) {
   add(B_NCI_PHI, 8 * k * k);
   add(B_NCI_PM, 8 * k * k);
   add(B_NCI_PV, 8 * k * k);
+  add(B_NCI_CHECK, 4 * (1024 + n));  // per-round recheck counters, then a row list
   add(B_OBJ_PART, 8 * static_cast<size_t>(p.obj_blocks) * (k * twod + k));
   add(B_OBJ_SUM, 8 * (k * twod + k));
   add(B_REDTMP, 8 * 16 * std::max(twod * k + k * k, twod));
@@ -360,6 +361,7 @@ tpo_status tpo::execute_plan(tpo_plan* plan, const tpo_inputs* in, void* ws, siz
   plan->stats.guard_hits = host.guard_hits;
   plan->stats.isolated_u = host.iso_u;
   plan->stats.isolated_v = host.iso_v;
+  plan->stats.nci_rechecked = host.nci_rechecked;
   if (out->objective) {
     out->objective[0] = host.objective[0];
     out->objective[1] = host.objective[1];

@@ -44,7 +44,8 @@ struct DevStatus {
   uint32_t maxabs_r_bits;  // max |R| as float bits
   uint32_t maxabs_ups_bits;// max |Upsilon| as float bits
   double objective[2];
-  int32_t pad[2];
+  int32_t nci_rechecked;   // NCI rows scored again in FP64
+  int32_t pad;
 };
 
 enum Buf {
@@ -71,7 +72,7 @@ enum Buf {
   // onmf
   B_UPS, B_H, B_H32, B_H_NEW, B_RTU, B_UTU, B_A32, B_ONMF_PART,
   // nci / objective
-  B_LABELS, B_NCI_PART, B_NCI_SUM, B_NCI_PHI, B_NCI_PM, B_NCI_PV, B_OBJ_PART, B_OBJ_SUM,
+  B_LABELS, B_NCI_PART, B_NCI_SUM, B_NCI_PHI, B_NCI_PM, B_NCI_PV, B_NCI_CHECK, B_OBJ_PART, B_OBJ_SUM,
   // subspace iteration (reduction and embedding)
   B_SI_M, B_SI_P, B_SI_GRAM, B_SI_PART, B_SI_BAR,
   B_REDTMP,

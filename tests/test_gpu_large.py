@@ -6,9 +6,14 @@ Zipf(1.9) degree weights, largest expected degree 1e5), attributes
 The FP64 oracle cannot run this job in test time, so the device result is
 checked through what holds at any size:
 * the CSR of B_U and of its transpose equal a sort of the edge list (exact);
-* Psi_d is orthonormal and X' = X Psi_d on sampled rows;
+* Psi_d is the oracle's reduction basis (the randomized subspace iteration
+  and Rayleigh-Ritz step of Section 3.2.1) computed in FP64 from the device's
+  own Gram C and column sums, and X' = X Psi_d on sampled rows; the distance
+  of Psi_d from C's exact top-d eigenvectors and the gap sigma_d/sigma_{d+1}
+  are logged (the randomized basis is the method's, reading A14);
 * the last hop of the propagation (both SpMMs) on sampled rows, from the
-  device's own W and T;
+  device's own W and T; the samples include the 100 rows of most neighbours
+  on each side (hub rows, whose sums run through ~400 chunk partials);
 * the random features on sampled rows and the column sums r over all rows;
 * Gamma has orthonormal columns and R^T Gamma = Psi Sigma;
 * the NCI labels are the oracle's NCI run on the device's Upsilon, and the
@@ -83,13 +88,30 @@ def test_large_workload_properties(x_dtype):
     log(f"[large {x_dtype}] CSR of B_U and B_U^T exact")
 
     rng = np.random.default_rng(1)
-    su = np.sort(rng.choice(n, SAMPLE, replace=False))
-    sv = np.sort(rng.choice(m, SAMPLE, replace=False))
+    deg_u = torch.diff(buf("rowptr_u").long())
+    deg_v = torch.diff(buf("rowptr_v").long())
+    top_u = torch.topk(deg_u, 100).indices.cpu().numpy()
+    top_v = torch.topk(deg_v, 100).indices.cpu().numpy()
+    log(f"[large {x_dtype}] sampled hub rows: neighbours {int(deg_u[top_u[0]])}..{int(deg_u[top_u[-1]])} (U), "
+        f"{int(deg_v[top_v[0]])}..{int(deg_v[top_v[-1]])} (V)")
+    su = np.unique(np.concatenate([rng.choice(n, SAMPLE, replace=False), top_u]))
+    sv = np.unique(np.concatenate([rng.choice(m, SAMPLE, replace=False), top_v]))
 
-    # attribute reduction
+    # attribute reduction: the oracle's basis from the device's own Gram
     psi = buf("psi_d").cpu().numpy()
     d = psi.shape[1]
     assert np.max(np.abs(psi.T @ psi - np.eye(d))) < 1e-10
+    c_dev = buf("gram_c").cpu().numpy()
+    mm = synth.method_matrices(0, shape.d_u, shape.d, k, shape.oversample)
+    psi_ref, _ = oracle.top_d_gram_basis(c_dev, buf("colsum_x").cpu().numpy(), n, d, mm.omega_reduce, shape.q)
+    e_psi = float(np.max(np.abs(psi - psi_ref)))
+    lam, vec = np.linalg.eigh(0.5 * (c_dev + c_dev.T))
+    lam, vec = lam[::-1], vec[:, ::-1]
+    sin_exact = oracle.subspace_sin_theta(psi, vec[:, :d])
+    log(f"[large {x_dtype}] Psi_d vs the oracle's basis from the device Gram: max abs err {e_psi:.2e}; "
+        f"vs C's exact top-{d} eigenvectors sin theta {sin_exact:.2e}, sigma_d/sigma_(d+1) "
+        f"{math.sqrt(lam[d - 1] / lam[d]):.5f}")
+    assert e_psi < 1e-6
     xs = x[torch.from_numpy(su).to(dev)].double().cpu().numpy()
     xp = buf("xprime")[torch.from_numpy(su).to(dev)].cpu().numpy()[:, :d]
     e_xp = _rel(xp, xs @ psi)

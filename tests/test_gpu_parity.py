@@ -106,7 +106,7 @@ def _stage_checks(name, abg, ref, out, psi_tol=1e-9):
     assert e_q < 1e-9
     assert e_r < 2e-5
     assert e_s < 1e-5
-    assert sin_t < 1e-4
+    assert sin_t < 1e-5
     assert e_g < 1e-4
     assert e_u < 1e-4
 
@@ -305,6 +305,12 @@ def test_near_tie_input_decisions():
     out = gpu_run(abg, **kw, stages=True)
     _stage_checks("near_tie", abg, ref, out)
     _decision_checks("near_tie", out, kw["k"], 20)
+    # the FP32 scores leave the closest decisions to the FP64 recheck; the
+    # whole job takes the same decisions
+    whole = gpu_run(abg, **kw, stages=False)
+    log(f"[near_tie] NCI rows scored again in FP64: {whole['stats']['nci_rechecked']}")
+    assert whole["stats"]["nci_rechecked"] > 0
+    assert np.array_equal(whole["labels"], out["labels"])
 
 
 @pytest.mark.parametrize("nci", ["literal", "procrustes"])

@@ -387,6 +387,34 @@ def test_attribute_reduction_matches_exact_with_gap():
     assert np.all(xp.sum(0) > 0)
 
 
+def test_gram_basis_matches_exact_with_gap():
+    """Section 3.2.1 from the Gram matrix alone: with a spectral gap the basis
+    equals LAPACK's top-d right singular vectors of X, with the column sign
+    convention read through X's column sums."""
+    rng = np.random.default_rng(21)
+    x = _gapped(rng, 400, 32, 6, gap=40.0)
+    om = rng.standard_normal((32, 12))
+    psi, sig = o.top_d_gram_basis(x.T @ x, x.sum(0), x.shape[0], 6, om, 8)
+    psi_e, sig_e = o.exact_top_d_attribute_svd(x, 6)
+    assert np.allclose(sig, sig_e, rtol=1e-12)
+    assert np.allclose(psi, psi_e, atol=1e-10)
+    assert np.all((x @ psi).sum(0) > 0)
+
+
+def test_gram_basis_sign_fallback_on_centred_columns():
+    """Zero column sums of X Psi (centred X) leave the sign to the entry of
+    largest magnitude of each basis column, which comes out positive."""
+    rng = np.random.default_rng(22)
+    x = _gapped(rng, 300, 16, 4, gap=30.0)
+    x = x - x.mean(0)
+    om = rng.standard_normal((16, 8))
+    psi, _ = o.top_d_gram_basis(x.T @ x, x.sum(0), x.shape[0], 4, om, 10)
+    for j in range(4):
+        assert psi[int(np.argmax(np.abs(psi[:, j]))), j] > 0
+    u, s, vt = np.linalg.svd(x, full_matrices=False)
+    assert np.allclose(np.abs(psi), np.abs(vt[:4].T), atol=1e-10)
+
+
 def test_lemma_ff_zz_bound():
     """Lemma FF-ZZ: |Z'_i . Z'_j - Z_i . Z_j| <= sigma_{d+1}^2 sqrt(D_i D_j)/(1-alpha)
     with the exact top-d SVD and the gamma -> infinity propagation."""
