@@ -26,6 +26,7 @@ __all__ = [
     "ABG",
     "JobShape",
     "CONFIGS",
+    "tfidf_csr",
     "planted_abg",
     "splitmix64_normals",
     "method_matrices",
@@ -324,24 +325,10 @@ def quantize_e4m3(x: np.ndarray):
     return codes, scale, values
 
 
-def tfidf_fp8_device(labels, d_u: int, *, device, density: float = 0.02, topic_frac: float = 0.5,
-                     zipf_s: float = 1.1, lognormal_sigma: float = 0.5, seed: int = 0, chunk: int = 131_072):
-    """Sparse TF-IDF-like attributes for nodes with planted clusters, drawn
-    on a GPU with torch and encoded as FP8 E4M3 with one scale per column.
-
-    * Each row draws round(density * d_u) words with replacement: with
-      probability topic_frac from its cluster's topic (d_u // k columns of a
-      seeded permutation, wrapping), else from a background Zipf(zipf_s) law
-      over a seeded permutation of the columns.
-    * Each draw carries a log-normal weight exp(lognormal_sigma * N(0, 1));
-      value = (sum of the word's weights in the row) * w_j, with
-      w_j = log(1 / p_j) (the background probability's inverse document
-      frequency); rows scaled to unit L2 norm.
-    * Column scale s_j = max_i x_ij / 448; codes = E4M3 round to nearest even
-      of x_ij / s_j (the quantize_e4m3 recipe).
-    Rows are drawn in chunks from per-chunk seeds, twice (column maxima, then
-    codes), so the n x d_u float matrix never exists whole.  Returns (codes
-    uint8 [n, d_u], scales float32 [d_u]) on the device."""
+def _tfidf_rows(labels, d_u: int, *, device, density: float, topic_frac: float, zipf_s: float,
+                lognormal_sigma: float, seed: int):
+    """The TF-IDF row recipe shared by tfidf_fp8_device and tfidf_csr: returns
+    values(r0, r1), the dense float32 rows [r0, r1) on `device`."""
     import torch
 
     labels = labels.to(device=device, dtype=torch.int64)
@@ -373,6 +360,31 @@ def tfidf_fp8_device(labels, d_u: int, *, device, density: float = 0.02, topic_f
         val = tf * w[None, :]
         return val / val.norm(dim=1, keepdim=True).clamp_min(1e-30)
 
+    return values, n
+
+
+def tfidf_fp8_device(labels, d_u: int, *, device, density: float = 0.02, topic_frac: float = 0.5,
+                     zipf_s: float = 1.1, lognormal_sigma: float = 0.5, seed: int = 0, chunk: int = 131_072):
+    """Sparse TF-IDF-like attributes for nodes with planted clusters, drawn
+    on a GPU with torch and encoded as FP8 E4M3 with one scale per column.
+
+    * Each row draws round(density * d_u) words with replacement: with
+      probability topic_frac from its cluster's topic (d_u // k columns of a
+      seeded permutation, wrapping), else from a background Zipf(zipf_s) law
+      over a seeded permutation of the columns.
+    * Each draw carries a log-normal weight exp(lognormal_sigma * N(0, 1));
+      value = (sum of the word's weights in the row) * w_j, with
+      w_j = log(1 / p_j) (the background probability's inverse document
+      frequency); rows scaled to unit L2 norm.
+    * Column scale s_j = max_i x_ij / 448; codes = E4M3 round to nearest even
+      of x_ij / s_j (the quantize_e4m3 recipe).
+    Rows are drawn in chunks from per-chunk seeds, twice (column maxima, then
+    codes), so the n x d_u float matrix never exists whole.  Returns (codes
+    uint8 [n, d_u], scales float32 [d_u]) on the device."""
+    import torch
+
+    values, n = _tfidf_rows(labels, d_u, device=device, density=density, topic_frac=topic_frac, zipf_s=zipf_s,
+                            lognormal_sigma=lognormal_sigma, seed=seed)
     colmax = torch.zeros(d_u, device=device)
     for r0 in range(0, n, chunk):
         colmax = torch.maximum(colmax, values(r0, min(n, r0 + chunk)).amax(dim=0))
@@ -383,6 +395,31 @@ def tfidf_fp8_device(labels, d_u: int, *, device, density: float = 0.02, topic_f
         q = (values(r0, r1) / scale[None, :]).clamp(-448.0, 448.0).to(torch.float8_e4m3fn)
         codes[r0:r1] = q.view(torch.uint8)
     return codes, scale
+
+
+def tfidf_csr(labels, d_u: int, *, device, density: float = 0.02, topic_frac: float = 0.5, zipf_s: float = 1.1,
+              lognormal_sigma: float = 0.5, seed: int = 0, chunk: int = 131_072):
+    """The same TF-IDF rows as tfidf_fp8_device, kept sparse and in FP32:
+    returns (rowptr int64 [n + 1], col int32 [nnz], val float32 [nnz]) on
+    `device`, columns ascending within a row."""
+    import torch
+
+    values, n = _tfidf_rows(labels, d_u, device=device, density=density, topic_frac=topic_frac, zipf_s=zipf_s,
+                            lognormal_sigma=lognormal_sigma, seed=seed)
+    counts, cols, vals = [], [], []
+    for r0 in range(0, n, chunk):
+        v = values(r0, min(n, r0 + chunk))
+        nz = v != 0
+        counts.append(nz.sum(dim=1))
+        idx = nz.nonzero(as_tuple=True)
+        cols.append(idx[1].to(torch.int32))
+        vals.append(v[idx])
+    cnt = torch.cat(counts) if counts else torch.zeros(0, dtype=torch.int64, device=device)
+    rowptr = torch.zeros(n + 1, dtype=torch.int64, device=device)
+    rowptr[1:] = torch.cumsum(cnt, 0)
+    col = torch.cat(cols) if cols else torch.zeros(0, dtype=torch.int32, device=device)
+    val = torch.cat(vals) if vals else torch.zeros(0, dtype=torch.float32, device=device)
+    return rowptr, col.contiguous(), val.contiguous()
 
 
 def e4m3_value(code: int) -> float:

@@ -166,10 +166,13 @@ def make_input(args, config, dev):
                                                        in_out_ratio=shape.in_out_ratio, max_degree=shape.max_degree,
                                                        seed=args.seed)
         if tfidf:
-            # the attributes: sparse TF-IDF rows encoded as FP8 E4M3 with column scales
+            # the attributes: sparse TF-IDF rows in FP32 CSR (the library stages
+            # them as FP8 E4M3 codes with column scales for the Gram)
+            import paper_2405_11922_amd as tpo
+
             del x
-            x, x_scale = synth.tfidf_fp8_device(truth, shape.d_u, device=dev, seed=args.seed)
-            x = x.view(torch.float8_e4m3fn)
+            rowptr, col, val = synth.tfidf_csr(truth, shape.d_u, device=dev, seed=args.seed)
+            x = tpo.CsrX(rowptr, col, val, shape.d_u)
         torch.cuda.synchronize()
         truth = truth.cpu().numpy()
         abg = None
@@ -197,6 +200,8 @@ def time_jobs(args, inp, x, x_dtype, dev, steps, warmup, instrument=True):
               oversample=shape.oversample, t_f=shape.t_f, t_g=shape.t_g, seed=args.seed, x_dtype=x_dtype,
               nci=args.nci)
     eu, ev, xs = inp["eu"], inp["ev"], inp["x_scale"]
+    if x_dtype == "csr":
+        kw["x_nnz"] = x.nnz
     plan = tpo.Plan.create(shape.n_u, shape.n_v, shape.n_edges, shape.d_u, device=dev, timing=False, **kw)
     labels = torch.empty(shape.n_u, dtype=torch.int32, device=dev)
     emb = torch.empty(shape.n_u, shape.k, dtype=torch.float32, device=dev)
@@ -369,9 +374,9 @@ def main() -> int:
     dev = torch.device("cuda:0")
     inp = make_input(args, args.config, dev)
     shape = inp["shape"]
-    x_dtype = args.x_dtype if args.x_dtype != "auto" else {"large": "bf16", "fp8_tfidf": "fp8"}.get(args.config, "f32")
-    if (x_dtype == "fp8") != (args.config == "fp8_tfidf"):
-        print("FP8 attributes go with --config fp8_tfidf (and only there)", file=sys.stderr)
+    x_dtype = args.x_dtype if args.x_dtype != "auto" else {"large": "bf16", "fp8_tfidf": "csr"}.get(args.config, "f32")
+    if (x_dtype == "csr") != (args.config == "fp8_tfidf"):
+        print("sparse FP8-staged attributes go with --config fp8_tfidf (and only there)", file=sys.stderr)
         return 2
     x_f32 = inp["x"]
     x = x_f32.to(torch.bfloat16) if x_dtype == "bf16" else x_f32
@@ -406,8 +411,8 @@ def main() -> int:
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"f32": "f32", "bf16": "bf16 attributes (BF16 MFMA Gram, FP32 accumulation), f32 path",
-                  "fp8": "fp8 e4m3 attributes with column scales (FP8 MFMA Gram, FP32 accumulation), "
-                         "f32 path"}[x_dtype],
+                  "csr": "sparse f32 attributes staged as fp8 e4m3 with column scales (FP8 MFMA Gram, FP32 "
+                         "accumulation, one FP32 refinement step), f32 path"}[x_dtype],
         "data": "synthetic",
         "config": {
             "workload": f"{args.config}: planted degree-corrected bipartite SBM, |U|={shape.n_u}, "
@@ -416,8 +421,9 @@ def main() -> int:
                         + f", d_U={shape.d_u} -> d={d_eff}, gamma={shape.gamma}, alpha={shape.alpha}, "
                           f"q={shape.q}, T_f={shape.t_f}, T_g={shape.t_g}"
                         + (", X_U stored as bfloat16" if x_dtype == "bf16" else "")
-                        + (", sparse TF-IDF attributes (2% density, abg_synth.tfidf_fp8_device) as FP8 E4M3 "
-                           "with column scales" if args.config == "fp8_tfidf" else ""),
+                        + (", sparse TF-IDF attributes (2% of the words drawn per row, abg_synth.tfidf_csr) in "
+                           "FP32 CSR, densified per row group to FP8 E4M3 with column scales for the Gram"
+                           if args.config == "fp8_tfidf" else ""),
             "n_u": shape.n_u, "n_v": shape.n_v, "n_edges": shape.n_edges, "k": shape.k, "d_u": shape.d_u,
             "d": d_eff, "k_prime": kp, "l_r": l_r, "gamma": shape.gamma, "x_dtype": x_dtype, "nci": args.nci,
         },
@@ -433,31 +439,51 @@ def main() -> int:
     log(f"[bench] planted clusters recovered: {result['quality']}")
     plan_t = res["plan_t"]
 
-    if x_dtype == "fp8":
-        # error of the FP8 path against FP64 arithmetic on the same codes: the
-        # attribute Gram entry by entry, and X' = X Psi_d on sampled rows
-        # (after the timed region; the FP64 Gram is torch's, on the GPU)
+    if x_dtype == "csr":
+        # error of the form against FP64 on the exact attributes, for the
+        # reduction (the full-size job is beyond the oracle): the exact Gram
+        # in FP64 (torch, on the GPU, from the CSR rows densified in chunks),
+        # the oracle's basis from it, and X' on sampled rows
         import numpy as np
+
+        import abg_synth as synth
+        import oracle
 
         def plan_t_buf(name):
             return tpo.tpo_plan_buffer(plan_t.handle, plan_t.workspace, name)
 
-        sc = inp["x_scale"].double()
-        c_ref = torch.zeros(shape.d_u, shape.d_u, dtype=torch.float64, device=dev)
-        for r0 in range(0, shape.n_u, 125_000):
-            xd = x[r0:r0 + 125_000].double() * sc[None, :]
-            c_ref += xd.T @ xd
-            del xd
-        gram_rel = float(((plan_t_buf("gram_c") - c_ref).abs() / c_ref.abs().clamp_min(1e-300)).max())
-        del c_ref
-        psi_d = plan_t_buf("psi_d")
-        idx = torch.from_numpy(np.sort(np.random.default_rng(1).choice(shape.n_u, 2000, replace=False))).to(dev)
-        ref = (x[idx].double() * sc[None, :]) @ psi_d
-        got = plan_t_buf("xprime")[idx][:, :psi_d.shape[1]].double()
-        xp_rel = float((got - ref).norm() / ref.norm())
-        result["vs_fp64"] = {"gram_max_rel_err": gram_rel, "xprime_rel_err_sampled_rows": xp_rel}
-        log(f"[bench] FP8 path vs FP64 on the same codes: Gram max entry rel err {gram_rel:.2e}, "
-            f"X' rel err on 2,000 sampled rows {xp_rel:.2e}")
+        rp, cl, vl = x.rowptr, x.col, x.val
+        c_ex = torch.zeros(shape.d_u, shape.d_u, dtype=torch.float64, device=dev)
+        colsum = torch.zeros(shape.d_u, dtype=torch.float64, device=dev)
+        for r0 in range(0, shape.n_u, 100_000):
+            r1 = min(shape.n_u, r0 + 100_000)
+            b0, b1 = int(rp[r0]), int(rp[r1])
+            rows = torch.repeat_interleave(torch.arange(r1 - r0, device=dev), (rp[r0 + 1:r1 + 1] - rp[r0:r1]))
+            xd = torch.zeros(r1 - r0, shape.d_u, dtype=torch.float64, device=dev)
+            xd.index_put_((rows, cl[b0:b1].long()), vl[b0:b1].double(), accumulate=True)
+            c_ex += xd.T @ xd
+            colsum += xd.sum(0)
+            del xd, rows
+        c_dev = plan_t_buf("gram_c")
+        gram_rel = float((c_dev - c_ex).norm() / c_ex.norm())
+        mm = synth.method_matrices(args.seed, shape.d_u, shape.d, shape.k, shape.oversample)
+        psi_ref, _ = oracle.top_d_gram_basis(c_ex.cpu().numpy(), colsum.cpu().numpy(), shape.n_u, shape.d,
+                                             mm.omega_reduce, shape.q)
+        psi_d = plan_t_buf("psi_d").cpu().numpy()
+        sin_psi = oracle.subspace_sin_theta(psi_d, psi_ref)
+        idx = np.sort(np.random.default_rng(1).choice(shape.n_u, 2000, replace=False))
+        xs_rows = torch.zeros(len(idx), shape.d_u, dtype=torch.float64, device=dev)
+        for i, r in enumerate(idx):
+            b0, b1 = int(rp[r]), int(rp[r + 1])
+            xs_rows[i].index_put_((cl[b0:b1].long(),), vl[b0:b1].double(), accumulate=True)
+        ref = (xs_rows @ torch.from_numpy(psi_d).to(dev)).cpu().numpy()
+        got = plan_t_buf("xprime")[torch.from_numpy(idx).to(dev)][:, :shape.d].double().cpu().numpy()
+        xp_rel = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        result["vs_fp64"] = {"gram_rel_err_vs_exact": gram_rel, "psi_d_sin_theta_vs_exact_iteration": sin_psi,
+                             "xprime_rel_err_sampled_rows": xp_rel}
+        log(f"[bench] sparse FP8-staged form vs FP64 on the exact attributes: Gram rel err {gram_rel:.2e} "
+            f"(Frobenius), Psi_d sin theta vs the oracle's basis from the exact Gram {sin_psi:.2e}, X' rel err on "
+            f"2,000 sampled rows {xp_rel:.2e}")
     plan_t.close()
     del plan_t, res["plan_t"]
 

@@ -60,7 +60,10 @@ typedef struct tpo_problem {
                           forms: the Gram C = X^T X of Section 3.2.1 on BF16
                           or FP8 MFMA with FP32 accumulation, added up in
                           FP64; the projection reads the narrow type and
-                          multiplies in FP32) */
+                          multiplies in FP32), or TPO_X_CSR (sparse FP32
+                          attributes, see below) */
+  int64_t x_nnz;       /* TPO_X_CSR: stored entries of X_U, 0 <= x_nnz <
+                          2^31; ignored otherwise */
 } tpo_problem;
 
 #define TPO_X_F32 0
@@ -68,6 +71,21 @@ typedef struct tpo_problem {
 #define TPO_X_FP8 2  /* OCP FP8 E4M3 (exponent bias 7, no infinities, 0x7F and
                         0xFF are NaN) with one FP32 scale per column: the
                         attribute is decode(x_u[i][j]) * x_scale[j] */
+#define TPO_X_CSR 3  /* sparse FP32 attributes in CSR (tpo_inputs.x_rowptr,
+                        x_col, and x_u holding the FP32 values), for sparse
+                        text attributes such as TF-IDF rows.  With the
+                        reduction on, the Gram C = X^T X (Section 3.2.1) is
+                        formed on FP8 MFMA: row groups are densified into a
+                        staging tile as OCP E4M3 codes of x / s_j with one
+                        scale s_j = max_i |x_ij| / 448 per column (round to
+                        nearest even), FP32 sums per 64-row slab added in
+                        FP64.  FP32 refinement steps follow the subspace
+                        iteration on that Gram (tpo_params.x_refine): the
+                        Rayleigh-Ritz product, and the power steps before it,
+                        are taken with the exact attributes, P = X^T (X M).
+                        The projection X' = X Psi_d and
+                        the column sums read the exact FP32 values.  Without
+                        the reduction the rows are copied densely. */
 
 /* Method parameters: Table 1 of the paper plus the unstated RandomizedSVD
  * details.  Defaults used in the paper: t_f = 5, t_g = 20. */
@@ -92,6 +110,14 @@ typedef struct tpo_params {
   const double* omega_reduce; /* d_u x l_r sketch of the reduction */
   const double* g;            /* d_eff x d_eff matrix G of Algorithm 1 */
   const double* omega;        /* 2 d_eff x k' sketch of RandomizedSVD(R, k) */
+  int32_t x_refine;           /* TPO_X_CSR with the reduction on: refinement
+                                 steps with the exact FP32 attributes after
+                                 the iteration on the FP8 Gram, 0..8.  Each
+                                 step forms P = X^T (X M); the last feeds the
+                                 Rayleigh-Ritz step, earlier ones are further
+                                 power steps (M <- orth(P)).  0: none, the
+                                 Rayleigh-Ritz product is the FP8 Gram's. */
+  int32_t reserved;
 } tpo_params;
 
 #define TPO_FLAG_TIMING 1 /* record per-stage device times (tpo_plan_stats) */
@@ -116,6 +142,11 @@ typedef struct tpo_inputs {
   int64_t ld_x;          /* row stride of x_u in elements, >= d_u */
   const float* x_scale;  /* [d_u] column scales, device memory; required with
                             TPO_X_FP8 (EINVAL if NULL), ignored otherwise */
+  const int64_t* x_rowptr; /* TPO_X_CSR: [n_u + 1] row starts, x_rowptr[0] = 0,
+                              non-decreasing, x_rowptr[n_u] = x_nnz */
+  const int32_t* x_col;    /* TPO_X_CSR: [x_nnz] column of each stored entry,
+                              0 <= col < d_u (entries of one row in any order;
+                              a column listed twice in a row adds up) */
 } tpo_inputs;
 
 /* Outputs of one job. */
@@ -287,6 +318,11 @@ tpo_status tpo_plan_buffer(const tpo_plan* plan, void* workspace, int32_t which,
  * outputs mapped to 53-bit uniforms on (0, 1] and to two normals by the
  * Box-Muller transform.  Writes `count` doubles to host memory `out`. */
 tpo_status tpo_draw_normals(uint64_t seed, int32_t stream, int64_t count, double* out);
+
+/* The OCP FP8 E4M3 (e4m3fn) code the TPO_X_CSR form stages for the value v
+ * (x_ij / s_j): round to nearest even, saturating at +-448, 0x7F for NaN.
+ * Host function, for reproducing the staged codes. */
+uint8_t tpo_e4m3_encode(float v);
 
 int32_t tpo_abi_version(void);
 

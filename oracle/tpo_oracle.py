@@ -316,19 +316,27 @@ def top_d_attribute_svd(x: np.ndarray, d: int, omega_r: np.ndarray, q: int):
     return psi, sig
 
 
-def top_d_gram_basis(c: np.ndarray, colsum_x: np.ndarray, n_rows: int, d: int, omega_r: np.ndarray, q: int):
+def top_d_gram_basis(c: np.ndarray, colsum_x: np.ndarray, n_rows: int, d: int, omega_r: np.ndarray, q: int,
+                     c_final: np.ndarray = None):
     """The reduction basis Psi_d of Section 3.2.1 from the Gram matrix alone:
     the same randomized subspace iteration and Rayleigh-Ritz step as
     top_d_attribute_svd, applied to a given C = X^T X, with the column sign
     convention evaluated through X's column sums (sum_i (X Psi)[i, c] =
     colsum_x . Psi[:, c], ||X Psi[:, c]||_2 = sqrt(Psi[:, c]^T C Psi[:, c])).
     For checking a device's Psi_d against the device's own Gram when X itself
-    is too large to hold on the host.  Returns (Psi_d, sigma_d)."""
+    is too large to hold on the host.
+
+    c_final: the matrix of the Rayleigh-Ritz step, when it differs from the
+    one the iteration used (the sparse-attribute precision form iterates on a
+    Gram formed from FP8 codes and refines with the exact Gram; not in the
+    paper).  Returns (Psi_d, sigma_d)."""
     c = np.asarray(c, dtype=np.float64)
     c = 0.5 * (c + c.T)
+    cf = c if c_final is None else 0.5 * (np.asarray(c_final, dtype=np.float64) + np.asarray(c_final).T)
     qm = orthonormal_basis(c @ omega_r)
     for _ in range(q):
         qm = orthonormal_basis(c @ qm)
+    c = cf
     t = qm.T @ c @ qm
     t = 0.5 * (t + t.T)
     evals, evecs = np.linalg.eigh(t)

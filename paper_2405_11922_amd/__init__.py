@@ -19,7 +19,8 @@ __all__ = [
     "tpo_execute", "tpo_stage_ingest", "tpo_stage_reduce", "tpo_stage_propagate",
     "tpo_stage_features", "tpo_stage_embed", "tpo_stage_onmf", "tpo_stage_nci",
     "tpo_stage_objective", "tpo_plan_buffer", "tpo_plan_stats", "tpo_draw_normals",
-    "tpo_status_string", "BUF", "Plan", "cluster", "tpo_execute_noalloc", "TPO_NOALLOC_MAX_BYTES",
+    "tpo_status_string", "BUF", "Plan", "cluster", "tpo_execute_noalloc", "TPO_NOALLOC_MAX_BYTES", "CsrX",
+    "tpo_e4m3_encode",
 ]
 
 TPO_ABI_VERSION = 3
@@ -45,7 +46,7 @@ EXPORTED = [
     "tpo_status_string", "tpo_plan_last_error", "tpo_plan_stats", "tpo_plan_dims",
     "tpo_stage_ingest", "tpo_stage_reduce", "tpo_stage_propagate", "tpo_stage_features",
     "tpo_stage_embed", "tpo_stage_onmf", "tpo_stage_nci", "tpo_stage_objective",
-    "tpo_plan_buffer", "tpo_draw_normals", "tpo_abi_version", "tpo_execute_noalloc",
+    "tpo_plan_buffer", "tpo_draw_normals", "tpo_abi_version", "tpo_execute_noalloc", "tpo_e4m3_encode",
 ]
 
 
@@ -58,7 +59,7 @@ class TpoError(RuntimeError):
 class TpoProblem(C.Structure):
     _fields_ = [("abi_version", C.c_int32), ("n_u", C.c_int32), ("n_v", C.c_int32),
                 ("d_u", C.c_int32), ("n_edges", C.c_int64), ("weighted", C.c_int32),
-                ("x_dtype", C.c_int32)]
+                ("x_dtype", C.c_int32), ("x_nnz", C.c_int64)]
 
 
 class TpoParams(C.Structure):
@@ -67,12 +68,26 @@ class TpoParams(C.Structure):
                 ("oversample", C.c_int32), ("t_f", C.c_int32), ("t_g", C.c_int32),
                 ("flags", C.c_int32), ("seed", C.c_uint64),
                 ("omega_reduce", C.POINTER(C.c_double)), ("g", C.POINTER(C.c_double)),
-                ("omega", C.POINTER(C.c_double))]
+                ("omega", C.POINTER(C.c_double)), ("x_refine", C.c_int32), ("reserved", C.c_int32)]
 
 
 class TpoInputs(C.Structure):
     _fields_ = [("edge_u", C.c_void_p), ("edge_v", C.c_void_p), ("edge_w", C.c_void_p),
-                ("x_u", C.c_void_p), ("ld_x", C.c_int64), ("x_scale", C.c_void_p)]
+                ("x_u", C.c_void_p), ("ld_x", C.c_int64), ("x_scale", C.c_void_p),
+                ("x_rowptr", C.c_void_p), ("x_col", C.c_void_p)]
+
+
+class CsrX:
+    """Sparse attributes X_U (TPO_X_CSR): device tensors rowptr (int64,
+    n_u + 1), col (int32, nnz) and val (float32, nnz), d_u columns."""
+
+    def __init__(self, rowptr, col, val, d_u):
+        self.rowptr, self.col, self.val, self.d_u = rowptr, col, val, int(d_u)
+        self.dtype = "csr"
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.numel())
 
 
 class TpoOutputs(C.Structure):
@@ -128,6 +143,8 @@ def load_library() -> C.CDLL:
     lib.tpo_plan_buffer.argtypes = [vp, vp, i32, C.POINTER(vp), C.POINTER(C.c_int64),
                                     C.POINTER(C.c_int64), C.POINTER(i32)]
     lib.tpo_draw_normals.argtypes = [C.c_uint64, i32, C.c_int64, C.POINTER(C.c_double)]
+    lib.tpo_e4m3_encode.argtypes = [C.c_float]
+    lib.tpo_e4m3_encode.restype = C.c_uint8
     lib.tpo_abi_version.restype = i32
     for name in EXPORTED:
         if name not in ("tpo_plan_destroy", "tpo_status_string", "tpo_plan_last_error", "tpo_abi_version"):
@@ -158,26 +175,29 @@ def _dptr(arr):
     return a, a.ctypes.data_as(C.POINTER(C.c_double))
 
 
-X_DTYPES = {"f32": 0, "bf16": 1, "fp8": 2}  # TPO_X_F32, TPO_X_BF16, TPO_X_FP8
+X_DTYPES = {"f32": 0, "bf16": 1, "fp8": 2, "csr": 3}  # TPO_X_F32, TPO_X_BF16, TPO_X_FP8, TPO_X_CSR
 _TORCH_XDT = {"torch.float32": "f32", "torch.bfloat16": "bf16", "torch.float8_e4m3fn": "fp8"}
 _PLAN_XDT = {}  # plan handle -> x_dtype name, to check the tensors handed over
 
 
 def tpo_plan_create(n_u, n_v, n_edges, d_u, *, k, alpha, gamma, d=0, q=20, oversample=10,
                     t_f=5, t_g=20, seed=0, weighted=False, timing=False, one_stream=False,
-                    omega_reduce=None, g=None, omega=None, x_dtype="f32", nci="literal"):
-    """Returns an opaque plan handle (int).  x_dtype: "f32", "bf16" or "fp8" (X_U's
-    element type)."""
+                    omega_reduce=None, g=None, omega=None, x_dtype="f32", nci="literal", x_nnz=0,
+                    x_refine=1):
+    """Returns an opaque plan handle (int).  x_dtype: "f32", "bf16", "fp8" or
+    "csr" (X_U's element type; "csr": sparse FP32 rows with x_nnz stored
+    entries, x_refine FP32 refinement steps after the FP8-Gram iteration)."""
     lib = load_library()
     if x_dtype not in X_DTYPES:
         raise TpoError(1, f"x_dtype must be one of {sorted(X_DTYPES)}")
     prob = TpoProblem(TPO_ABI_VERSION, int(n_u), int(n_v), int(d_u), int(n_edges), int(bool(weighted)),
-                      X_DTYPES[x_dtype])
+                      X_DTYPES[x_dtype], int(x_nnz))
     keep = [_dptr(omega_reduce), _dptr(g), _dptr(omega)]
+    flags = _flags(timing, one_stream, nci)
     par = TpoParams(TPO_ABI_VERSION, int(k), float(alpha), int(gamma), int(d), int(q), int(oversample),
-                    int(t_f), int(t_g), _flags(timing, one_stream, nci), int(seed) & ((1 << 64) - 1),
+                    int(t_f), int(t_g), flags, int(seed) & ((1 << 64) - 1),
                     keep[0][1] if keep[0] else None, keep[1][1] if keep[1] else None,
-                    keep[2][1] if keep[2] else None)
+                    keep[2][1] if keep[2] else None, int(x_refine), 0)
     h = C.c_void_p()
     _check(lib.tpo_plan_create(C.byref(prob), C.byref(par), C.byref(h)))
     _PLAN_XDT[h.value] = x_dtype
@@ -189,6 +209,11 @@ def _flags(timing, one_stream, nci) -> int:
         raise ValueError(f"nci must be one of {NCI_VARIANTS}")
     return ((TPO_FLAG_TIMING if timing else 0) | (TPO_FLAG_ONE_STREAM if one_stream else 0)
             | (TPO_FLAG_NCI_PROCRUSTES if nci == "procrustes" else 0))
+
+
+def tpo_e4m3_encode(v: float) -> int:
+    """The E4M3 code the sparse-attribute form stages for the value v."""
+    return int(load_library().tpo_e4m3_encode(float(v)))
 
 
 def tpo_plan_destroy(plan) -> None:
@@ -209,6 +234,18 @@ def tpo_plan_dims(plan):
 
 
 def _inputs(edge_u, edge_v, x_u, edge_w=None, plan=None, x_scale=None):
+    if isinstance(x_u, CsrX):
+        if plan in _PLAN_XDT and _PLAN_XDT[plan] != "csr":
+            raise TpoError(1, f"sparse attributes given, the plan expects {_PLAN_XDT[plan]}")
+        for t, dt in ((x_u.rowptr, "torch.int64"), (x_u.col, "torch.int32"), (x_u.val, "torch.float32")):
+            if str(t.dtype) != dt or not t.is_contiguous():
+                raise TpoError(1, "CsrX needs contiguous int64 rowptr, int32 col and float32 val tensors")
+        return TpoInputs(edge_u.data_ptr() if edge_u is not None else None,
+                         edge_v.data_ptr() if edge_v is not None else None,
+                         edge_w.data_ptr() if edge_w is not None else None,
+                         x_u.val.data_ptr(), 0, None, x_u.rowptr.data_ptr(), x_u.col.data_ptr())
+    if plan in _PLAN_XDT and _PLAN_XDT[plan] == "csr":
+        raise TpoError(1, "the plan expects sparse attributes (CsrX)")
     if x_u is not None and plan in _PLAN_XDT:
         want = _PLAN_XDT[plan]
         have = _TORCH_XDT.get(str(x_u.dtype))
@@ -221,7 +258,7 @@ def _inputs(edge_u, edge_v, x_u, edge_w=None, plan=None, x_scale=None):
     return TpoInputs(edge_u.data_ptr() if edge_u is not None else None,
                      edge_v.data_ptr() if edge_v is not None else None,
                      edge_w.data_ptr() if edge_w is not None else None,
-                     x_u.data_ptr(), ld, x_scale.data_ptr() if x_scale is not None else None)
+                     x_u.data_ptr(), ld, x_scale.data_ptr() if x_scale is not None else None, None, None)
 
 
 def _stream(stream):

@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libtpo.so")
 
-SOURCES = ["tpo_api.cpp", "k_ingest.hip", "k_spmm.hip", "k_dense.hip", "k_cluster.hip", "k_smallla.hip", "k_subspace.hip", "k_noalloc.hip"]
+SOURCES = ["tpo_api.cpp", "k_ingest.hip", "k_spmm.hip", "k_dense.hip", "k_cluster.hip", "k_smallla.hip", "k_subspace.hip", "k_noalloc.hip", "k_xsparse.hip"]
 
 COMMON = [
     "--offload-arch=gfx950",

@@ -345,7 +345,7 @@ __device__ __forceinline__ void transpose4x4(const uint32_t (&in)[4], uint32_t (
 
 __global__ void __launch_bounds__(256)
 k_gram_part_fp8(const uint8_t* __restrict__ X, int64_t n, int c, int64_t ldx, int ntiles, int rows_per_chunk,
-                int nchunks, int vec, double* __restrict__ part, double* __restrict__ colsum_part) {
+                int nchunks, int vec, double* __restrict__ part, double* __restrict__ colsum_part, int accumulate) {
   __shared__ __align__(16) uint8_t At[kGT * kG8Ld];
   __shared__ __align__(16) uint8_t Bt[kGT * kG8Ld];
   __shared__ double csum[4][kGT];
@@ -453,13 +453,17 @@ k_gram_part_fp8(const uint8_t* __restrict__ X, int64_t n, int c, int64_t ldx, in
     if (r0 + kGSub < r_end) slab(r0 + kGSub, raB, rbB);  // uniform
   }
   double* out = part + (static_cast<int64_t>(chunk) * npairs + pair) * kGT * kGT;
+  // accumulate: add to the partial of an earlier launch over other rows (the
+  // row groups of a sparse X_U, staged one after another)
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int bb = 0; bb < 2; ++bb)
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
-        out[(32 * qa + 16 * a + 4 * kq + v) * kGT + 32 * qb + 16 * bb + i16] = acc[a][bb][v];
+      for (int v = 0; v < 4; ++v) {
+        double* o = out + (32 * qa + 16 * a + 4 * kq + v) * kGT + 32 * qb + 16 * bb + i16;
+        *o = accumulate ? *o + acc[a][bb][v] : acc[a][bb][v];
+      }
   if (diag && colsum_part) {
     csum[w][lane] = cs;
     __syncthreads();
@@ -482,7 +486,7 @@ static void gram(const void* X, int xdt, const float* scale, int64_t n, int c, i
     const int per_xcd = (nchunks + 7) / 8;
     hipLaunchKernelGGL(k_gram_part_fp8, dim3(8 * per_xcd * npairs), dim3(256), 0, s,
                        static_cast<const uint8_t*>(X), n, c, ldx, ntiles, rows_per_chunk, nchunks, vec, part,
-                       colsum_part);
+                       colsum_part, 0);
   } else if (xdt == 1) {
     const int vec = (reinterpret_cast<uintptr_t>(X) % 16 == 0 && ldx % 8 == 0 && c % 8 == 0) ? 1 : 0;
     const int per_xcd = (nchunks + 7) / 8;
@@ -1000,9 +1004,118 @@ static void project(const Plan& p, const XT* x, int64_t ldx, const float* sc, co
   TPO_LAUNCH_CHECK();
 }
 
-void launch_reduce(const Plan& p, void* ws, const void* x, int64_t ldx, const float* xscale, hipStream_t s) {
+// The FP8 Gram of a sparse X_U: row groups of p.xstage_rows rows staged as
+// E4M3 codes one after another, each group's tile-pair partials added to the
+// previous groups' (group order fixed), then the chunk partials summed with
+// the column scales.
+static void gram_xcsr(const Plan& p, void* ws, const tpo_inputs* in, hipStream_t s) {
+  const int c = p.du;
+  const int ld = (c + 3) / 4 * 4;
+  const int ntiles = (c + kGT - 1) / kGT;
+  const int npairs = ntiles * (ntiles + 1) / 2;
+  const int nchunks = p.gram_chunks_x;
+  const int per_xcd = (nchunks + 7) / 8;
+  double* part = bufp<double>(p, ws, B_GRAM_PART);
+  const uint8_t* stage = bufp<uint8_t>(p, ws, B_XS_STAGE);
+  for (int64_t r0 = 0; r0 < p.n; r0 += p.xstage_rows) {
+    const int rows = static_cast<int>(std::min<int64_t>(p.xstage_rows, p.n - r0));
+    xcsr_stage_fp8(p, ws, in->x_rowptr, in->x_col, static_cast<const float*>(in->x_u), r0, rows, ld, s);
+    const int rows_per_chunk = (rows + nchunks - 1) / nchunks;
+    hipLaunchKernelGGL(k_gram_part_fp8, dim3(8 * per_xcd * npairs), dim3(256), 0, s, stage,
+                       static_cast<int64_t>(rows), c, static_cast<int64_t>(ld), ntiles, rows_per_chunk, nchunks,
+                       (c % 4 == 0) ? 1 : 0, part, nullptr, r0 > 0 ? 1 : 0);
+    TPO_LAUNCH_CHECK();
+  }
+  const int64_t outs = static_cast<int64_t>(npairs) * kGT * kGT;
+  hipLaunchKernelGGL(k_gram_reduce, dim3(ceil_div(outs, 256)), dim3(256), 0, s, part, nullptr, nchunks, c, ntiles,
+                     bufp<float>(p, ws, B_XS_SCALE), bufp<double>(p, ws, B_C), nullptr);
+  TPO_LAUNCH_CHECK();
+}
+
+// Reduction of a sparse X_U (TPO_X_CSR): scales, transpose and column sums,
+// the FP8 Gram, subspace iteration on it, x_refine refinement steps with the
+// exact FP32 values (P = X^T (X M): power steps, the last one the
+// Rayleigh-Ritz product), Rayleigh-Ritz, and X' = X Psi_d from the exact
+// values.
+static void reduce_xcsr(const Plan& p, void* ws, const tpo_inputs* in, hipStream_t s) {
+  DevStatus* st = bufp<DevStatus>(p, ws, B_STATUS);
+  const float* val = static_cast<const float*>(in->x_u);
+  float* xp = bufp<float>(p, ws, B_XPRIME);
+  double* colsum = bufp<double>(p, ws, B_COLSUM_X);
+  xcsr_transpose(p, ws, in->x_rowptr, in->x_col, val, s);
+  xcsr_scales(p, ws, in->x_rowptr, in->x_col, val, s);
+  gram_xcsr(p, ws, in, s);
+  double* ma = bufp<double>(p, ws, B_MR_A);
+  double* mb = bufp<double>(p, ws, B_MR_B);
+  const double* C = bufp<double>(p, ws, B_C);
+  double* m;   // the basis after q + 1 products with C
+  double* pm;  // C m, replaced by X^T (X m) in the refinement step
+  if (p.lr <= kLdsMaxN) {
+    m = bufp<double>(p, ws, B_SI_M);
+    pm = bufp<double>(p, ws, B_SI_P);
+    subspace_iterate(C, p.du, bufp<double>(p, ws, B_OMR), p.lr, p.par.q + 1, ma, mb, bufp<double>(p, ws, B_SI_GRAM),
+                     bufp<double>(p, ws, B_SI_PART), bufp<unsigned>(p, ws, B_SI_BAR), m, pm, &st->err_bits, s);
+  } else {
+    double* gs = bufp<double>(p, ws, B_SMALL_A);
+    TPO_HIP_CHECK(hipMemcpyAsync(ma, bufp<double>(p, ws, B_OMR), sizeof(double) * p.du * p.lr,
+                                 hipMemcpyDeviceToDevice, s));
+    for (int it = 0; it <= p.par.q; ++it) {
+      gemm_f64(p.du, p.lr, p.du, C, p.du, ma, p.lr, mb, p.lr, s);
+      hipLaunchKernelGGL(k_cholqr, dim3(1), dim3(kSmallThreads), 0, s, mb, p.du, p.lr, p.lr, gs, &st->err_bits);
+      TPO_LAUNCH_CHECK();
+      std::swap(ma, mb);
+    }
+    gemm_f64(p.du, p.lr, p.du, C, p.du, ma, p.lr, mb, p.lr, s);
+    m = ma;
+    pm = mb;
+  }
+  // refinement: Y = X M (FP32 from FP64 sums), P = X^T Y with the exact
+  // values (and the column sums of X); all but the last step re-orthonormalise
+  // P into M as further power steps
+  float* y = bufp<float>(p, ws, B_XT_Y);
+  const int steps = p.par.x_refine;
+  for (int step = 0; step < std::max(steps, 1); ++step) {
+    xcsr_rowgather(p, in->x_rowptr, in->x_col, val, m, p.lr, p.lr, y, p.lr, p.lr, s);
+    xcsc_colgather(p, ws, y, p.lr, p.lr, steps > 0 ? pm : nullptr, p.lr, colsum, s);
+    if (step + 1 < steps) {
+      TPO_HIP_CHECK(hipMemcpyAsync(m, pm, sizeof(double) * p.du * p.lr, hipMemcpyDeviceToDevice, s));
+      if (p.lr <= kLdsMaxN) {
+        cholqr_lds(m, p.du, p.lr, p.lr, &st->err_bits, s);
+      } else {
+        hipLaunchKernelGGL(k_cholqr, dim3(1), dim3(kSmallThreads), 0, s, m, p.du, p.lr, p.lr,
+                           bufp<double>(p, ws, B_SMALL_A), &st->err_bits);
+        TPO_LAUNCH_CHECK();
+      }
+    }
+  }
+  if (p.lr <= kLdsMaxN) {
+    rr_reduce_lds(m, pm, p.du, p.lr, p.d, p.dp, colsum, static_cast<int64_t>(p.n), bufp<double>(p, ws, B_EVAL),
+                  bufp<double>(p, ws, B_PSI_D), bufp<float>(p, ws, B_PSI_D32), s);
+  } else {
+    hipLaunchKernelGGL(k_reduce_rr, dim3(1), dim3(kSmallThreads), 0, s, m, pm, p.du, p.lr, p.d, p.dp, colsum,
+                       static_cast<int64_t>(p.n), bufp<double>(p, ws, B_SMALL_B), bufp<double>(p, ws, B_SMALL_C),
+                       bufp<double>(p, ws, B_EVAL), bufp<double>(p, ws, B_PSI_D), bufp<float>(p, ws, B_PSI_D32));
+    TPO_LAUNCH_CHECK();
+  }
+  // X' = X Psi_d with the exact values, padded to dp columns
+  xcsr_rowgather(p, in->x_rowptr, in->x_col, val, bufp<double>(p, ws, B_PSI_D), p.d, p.d, xp, p.dp, p.dp, s);
+}
+
+void launch_reduce(const Plan& p, void* ws, const tpo_inputs* in, hipStream_t s) {
   DevStatus* st = bufp<DevStatus>(p, ws, B_STATUS);
   float* xp = bufp<float>(p, ws, B_XPRIME);
+  const void* x = in->x_u;
+  const int64_t ldx = in->ld_x;
+  const float* xscale = in->x_scale;
+  if (p.xcsr) {
+    if (p.reduce) {
+      reduce_xcsr(p, ws, in, s);
+    } else {
+      // rows copied densely into X' (d = d_u <= 128)
+      xcsr_dense(p, ws, in->x_rowptr, in->x_col, static_cast<const float*>(in->x_u), xp, s);
+    }
+    return;
+  }
   const int xdt = p.xfp8 ? 2 : p.xbf16 ? 1 : 0;
   if (!p.reduce) {
     const dim3 g(ceil_div(static_cast<int64_t>(p.n) * p.dp, 256));

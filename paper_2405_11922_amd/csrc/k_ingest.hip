@@ -216,13 +216,10 @@ k_radix_downsweep(const uint64_t* __restrict__ keys, const float* __restrict__ v
 }
 
 // Sort keys[0..n) on bits [lo, hi) (stable); result ends in keys (ping-pong
-// through keys_alt), values follow when vals != nullptr.
-static void radix_sort(const Plan& p, void* ws, uint64_t* keys, uint64_t* keys_alt, float* vals,
-                       float* vals_alt, int64_t n_static, const int32_t* n_dev, int lo, int hi,
-                       hipStream_t s) {
-  const int nb = p.sort_blocks;
-  uint32_t* hist = bufp<uint32_t>(p, ws, B_HIST);
-  uint32_t* aux = bufp<uint32_t>(p, ws, B_SCAN_AUX);
+// through keys_alt), values follow when vals != nullptr.  nb tiles of
+// kSortTile keys; hist holds 256 nb counters, aux the scan's block sums.
+static void radix_sort_nb(int nb, uint32_t* hist, uint32_t* aux, uint64_t* keys, uint64_t* keys_alt, float* vals,
+                          float* vals_alt, int64_t n_static, const int32_t* n_dev, int lo, int hi, hipStream_t s) {
   uint64_t* src = keys;
   uint64_t* dst = keys_alt;
   float* vsrc = vals;
@@ -247,6 +244,13 @@ static void radix_sort(const Plan& p, void* ws, uint64_t* keys, uint64_t* keys_a
       TPO_HIP_CHECK(hipMemcpyAsync(vals, vsrc, static_cast<size_t>(n_static) * sizeof(float),
                                    hipMemcpyDeviceToDevice, s));
   }
+}
+
+static void radix_sort(const Plan& p, void* ws, uint64_t* keys, uint64_t* keys_alt, float* vals,
+                       float* vals_alt, int64_t n_static, const int32_t* n_dev, int lo, int hi,
+                       hipStream_t s) {
+  radix_sort_nb(p.sort_blocks, bufp<uint32_t>(p, ws, B_HIST), bufp<uint32_t>(p, ws, B_SCAN_AUX), keys, keys_alt,
+                vals, vals_alt, n_static, n_dev, lo, hi, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -450,6 +454,85 @@ void launch_ingest(const Plan& p, void* ws, const tpo_inputs* in, hipStream_t s)
              &st->iso_u, &st->hub_chunks_u, &st->hub_rows_u, s);
   side_lists(p, ws, p.m, rowptr_v, val_v, 1, B_DEG_V, B_INV_V, B_HUBCNT_V, B_HUBROW_V, B_CHUNK_V, B_HUBLIST_V,
              &st->iso_v, &st->hub_chunks_v, &st->hub_rows_v, s);
+}
+
+// ---------------------------------------------------------------------------
+// Sparse attributes (TPO_X_CSR): the transpose of X_U (CSC), for the column
+// products of the reduction's refinement step
+// ---------------------------------------------------------------------------
+// Keys (col << rowbits | row) and values of the stored entries in CSR order,
+// one wave per row.  Row starts are clamped to [0, nnz] and an entry whose
+// column is out of range keeps column 0 with value 0 (the status word then
+// holds bit 7, reported as TPO_ERANGE), so every later access stays in bounds.
+__global__ void __launch_bounds__(256)
+k_xcsr_keys(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col, const float* __restrict__ val,
+            int n, int64_t nnz, int du, int rowbits, uint64_t* __restrict__ keys, float* __restrict__ vals,
+            int32_t* __restrict__ err_bits) {
+  const int lane = threadIdx.x & 63;
+  const int64_t r = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  if (r >= n) return;
+  int64_t b = rowptr[r], e = rowptr[r + 1];
+  const bool bad_row = b < 0 || e > nnz || b > e || (r == 0 && b != 0) || (r == n - 1 && e != nnz);
+  b = min(max(b, static_cast<int64_t>(0)), nnz);
+  e = min(max(e, b), nnz);
+  if (bad_row && lane == 0) atomicOr(err_bits, 128);
+  for (int64_t i = b + lane; i < e; i += 64) {
+    int c = col[i];
+    float v = val[i];
+    if (c < 0 || c >= du) {
+      atomicOr(err_bits, 128);
+      c = 0;
+      v = 0.0f;
+    }
+    if (!isfinite(v)) {
+      atomicOr(err_bits, 4);
+      v = 0.0f;
+    }
+    keys[i] = (static_cast<uint64_t>(c) << rowbits) | static_cast<uint64_t>(r);
+    vals[i] = v;
+  }
+}
+
+static int key_bits(int64_t n) {
+  int b = 1;
+  while ((int64_t{1} << b) < n) ++b;
+  return b;
+}
+
+__global__ void k_split_keys(const uint64_t* __restrict__ keys, int64_t nnz, int rowbits, int32_t* __restrict__ rows) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < nnz) rows[i] = static_cast<int32_t>(keys[i] & ((1ull << rowbits) - 1ull));
+}
+
+void xcsr_transpose(const Plan& p, void* ws, const int64_t* rowptr, const int32_t* col, const float* val,
+                    hipStream_t s) {
+  DevStatus* st = bufp<DevStatus>(p, ws, B_STATUS);
+  uint64_t* ka = bufp<uint64_t>(p, ws, B_XT_KA);
+  uint64_t* kb = bufp<uint64_t>(p, ws, B_XT_KB);
+  float* va = bufp<float>(p, ws, B_XT_VA);
+  float* vb = bufp<float>(p, ws, B_XT_VB);
+  int32_t* colptr = bufp<int32_t>(p, ws, B_XT_COLPTR);
+  const int64_t nnz = p.xnnz;
+  const int rowbits = key_bits(p.n);
+  const int colbits = key_bits(p.du);
+  if (nnz > 0) {
+    hipLaunchKernelGGL(k_xcsr_keys, dim3(ceil_div(static_cast<int64_t>(p.n) * 64, 256)), dim3(256), 0, s, rowptr,
+                       col, val, p.n, nnz, p.du, rowbits, ka, va, &st->err_bits);
+    TPO_LAUNCH_CHECK();
+    // stable sort on the column bits: rows stay ascending within a column
+    radix_sort_nb(p.xsort_blocks, bufp<uint32_t>(p, ws, B_XT_HIST), bufp<uint32_t>(p, ws, B_XT_AUX), ka, kb, va,
+                  vb, nnz, nullptr, rowbits, rowbits + colbits, s);
+    hipLaunchKernelGGL(k_rowptr, dim3(ceil_div(nnz + 1, 256)), dim3(256), 0, s, ka, nnz, nullptr, rowbits,
+                       (1ull << colbits) - 1ull, p.du, colptr);
+    TPO_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_split_keys, dim3(ceil_div(nnz, 256)), dim3(256), 0, s, ka, nnz, rowbits,
+                       bufp<int32_t>(p, ws, B_XT_ROW));
+    TPO_LAUNCH_CHECK();
+  } else {
+    hipLaunchKernelGGL(k_fill_i32, dim3(ceil_div(p.du + 1, 256)), dim3(256), 0, s, colptr,
+                       static_cast<int64_t>(p.du + 1), 0);
+    TPO_LAUNCH_CHECK();
+  }
 }
 
 }  // namespace tpo

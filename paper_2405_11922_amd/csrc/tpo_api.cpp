@@ -167,6 +167,29 @@ void build_layout(Plan& p) {
   add(B_NCI_PM, 8 * k * k);
   add(B_NCI_PV, 8 * k * k);
   add(B_NCI_CHECK, 4 * (1024 + n));  // per-round recheck counters, then a row list
+  {
+    // sparse attributes (TPO_X_CSR)
+    const bool xs = p.xcsr;
+    const bool xr = p.xcsr && p.reduce;
+    const size_t nnz = static_cast<size_t>(std::max<int64_t>(p.xnnz, 1));
+    const size_t ldst = (du + 3) / 4 * 4;
+    add(B_XS_SCALE, xs ? 4 * du : 8);
+    add(B_XS_COLMAX, xs ? 4 * du : 8);
+    add(B_XS_STAGE, xr ? ldst * static_cast<size_t>(p.xstage_rows) : 8);
+    add(B_XT_KA, xr ? 8 * nnz : 8);
+    add(B_XT_KB, xr ? 8 * nnz : 8);
+    add(B_XT_VA, xr ? 4 * nnz : 8);
+    add(B_XT_VB, xr ? 4 * nnz : 8);
+    add(B_XT_HIST, xr ? 4 * 256 * static_cast<size_t>(p.xsort_blocks) : 8);
+    // its own scan scratch: ingest may run beside the reduction on a second stream
+    add(B_XT_AUX, xr ? 4 * ((256 * static_cast<size_t>(p.xsort_blocks) + 2047) / 2048 + 1) : 8);
+    add(B_XT_COLPTR, xr ? 4 * (du + 1) : 8);
+    add(B_XT_ROW, xr ? 4 * nnz : 8);
+    add(B_XT_CHUNK, xr ? 16 * static_cast<size_t>(p.xchunks_max) : 8);
+    add(B_XT_CINFO, xr ? 8 * (du + 1) : 8);
+    add(B_XT_CPART, xr ? 8 * static_cast<size_t>(p.xchunks_max) * (lr + 1) : 8);
+    add(B_XT_Y, xr ? 4 * n * lr : 8);
+  }
   add(B_OBJ_PART, 8 * static_cast<size_t>(p.obj_blocks) * (k * twod + k));
   add(B_OBJ_SUM, 8 * (k * twod + k));
   add(B_REDTMP, 8 * 16 * std::max(twod * k + k * k, twod));
@@ -204,6 +227,7 @@ tpo_status map_bits(tpo_plan* p, int32_t bits) {
   if (bits & 16) return fail(p, TPO_ENUMERIC, "Cholesky breakdown in an orthonormalisation");
   if (bits & 32) return fail(p, TPO_ENUMERIC, "non-finite value in the ONMF updates");
   if (bits & 64) return fail(p, TPO_EDEVICE, "grid barrier of the subspace iteration timed out");
+  if (bits & 128) return fail(p, TPO_ERANGE, "sparse attributes: row starts or column ids out of range");
   return TPO_OK;
 }
 
@@ -243,6 +267,13 @@ bool valid_inputs(tpo_plan* p, const tpo_inputs* in, std::string* why) {
   if (p->prob.weighted && p->E > 0 && !in->edge_w) {
     *why = "weighted problem without edge_w";
     return false;
+  }
+  if (p->xcsr) {
+    if (!in->x_rowptr || (p->xnnz > 0 && (!in->x_col || !in->x_u))) {
+      *why = "x_rowptr, x_col or x_u (the values) is NULL for sparse attributes";
+      return false;
+    }
+    return true;
   }
   if (!in->x_u) {
     *why = "x_u is NULL";
@@ -288,7 +319,7 @@ tpo_status tpo::execute_plan(tpo_plan* plan, const tpo_inputs* in, void* ws, siz
       // stage by stage on one stream (timing: so that each stage's time is its own)
       launch_ingest(*plan, ws, in, s);
       mark(1);
-      launch_reduce(*plan, ws, in->x_u, in->ld_x, in->x_scale, s);
+      launch_reduce(*plan, ws, in, s);
       mark(2);
     } else {
       // ingest (edges only) and the attribute reduction (X only) are
@@ -305,7 +336,7 @@ tpo_status tpo::execute_plan(tpo_plan* plan, const tpo_inputs* in, void* ws, siz
       // the reduction is enqueued first: its long few-workgroup kernels
       // (subspace iteration, Rayleigh-Ritz) then run beside ingest's
       // whole-GPU sort and scan kernels instead of after them
-      launch_reduce(*plan, ws, in->x_u, in->ld_x, in->x_scale, s);
+      launch_reduce(*plan, ws, in, s);
       launch_ingest(*plan, ws, in, plan->side);
       TPO_HIP_CHECK(hipEventRecord(plan->join_ev, plan->side));
       TPO_HIP_CHECK(hipStreamWaitEvent(s, plan->join_ev, 0));
@@ -376,6 +407,8 @@ extern "C" {
 
 int32_t tpo_abi_version(void) { return TPO_ABI_VERSION; }
 
+uint8_t tpo_e4m3_encode(float v) { return tpo::e4m3_encode(v); }
+
 const char* tpo_status_string(tpo_status status) {
   switch (status) {
     case TPO_OK: return "ok";
@@ -402,12 +435,16 @@ tpo_status tpo_plan_create(const tpo_problem* prob, const tpo_params* par, tpo_p
   if (prob->abi_version != TPO_ABI_VERSION || par->abi_version != TPO_ABI_VERSION) return TPO_EINVAL;
   if (prob->n_u < 1 || prob->n_v < 1 || prob->n_edges < 0 || prob->n_edges >= (int64_t{1} << 31)) return TPO_EINVAL;
   if (prob->d_u < 1 || prob->d_u > kMaxDu) return TPO_EINVAL;
-  if (prob->x_dtype != TPO_X_F32 && prob->x_dtype != TPO_X_BF16 && prob->x_dtype != TPO_X_FP8) return TPO_EINVAL;
+  if (prob->x_dtype != TPO_X_F32 && prob->x_dtype != TPO_X_BF16 && prob->x_dtype != TPO_X_FP8 &&
+      prob->x_dtype != TPO_X_CSR)
+    return TPO_EINVAL;
+  if (prob->x_dtype == TPO_X_CSR && (prob->x_nnz < 0 || prob->x_nnz >= (int64_t{1} << 31))) return TPO_EINVAL;
   if (par->k < 1 || par->k > kMaxK) return TPO_EINVAL;
   if (!(par->alpha >= 0.0 && par->alpha < 1.0)) return TPO_EINVAL;
   if (par->gamma < 0 || par->gamma > 1000 || par->q < 0 || par->q > 100) return TPO_EINVAL;
   if (par->oversample < 0 || par->oversample > 64) return TPO_EINVAL;
   if (par->t_f < 0 || par->t_f > 1000 || par->t_g < 0 || par->t_g > 1000) return TPO_EINVAL;
+  if (par->x_refine < 0 || par->x_refine > 8) return TPO_EINVAL;
   const bool reduce = par->d > 0 && par->d < prob->d_u;
   const int d = reduce ? par->d : prob->d_u;
   if (d > kMaxDEff) return TPO_EINVAL;
@@ -423,6 +460,8 @@ tpo_status tpo_plan_create(const tpo_problem* prob, const tpo_params* par, tpo_p
   p->reduce = reduce;
   p->xbf16 = prob->x_dtype == TPO_X_BF16;
   p->xfp8 = prob->x_dtype == TPO_X_FP8;
+  p->xcsr = prob->x_dtype == TPO_X_CSR;
+  p->xnnz = p->xcsr ? prob->x_nnz : 0;
   p->d = d;
   p->dp = next_pow2_at_least(d, 16);
   p->k = par->k;
@@ -432,6 +471,20 @@ tpo_status tpo_plan_create(const tpo_problem* prob, const tpo_params* par, tpo_p
   if (p->lr > 256) {
     delete p;
     return TPO_EINVAL;
+  }
+  // sparse attributes: the sums of the refinement step hold up to 128 sketch
+  // columns (two per lane)
+  if (p->xcsr && reduce && p->lr > 128) {
+    delete p;
+    return TPO_EINVAL;
+  }
+  p->xsort_blocks = static_cast<int>(std::max<int64_t>((p->xnnz + kSortTile - 1) / kSortTile, 1));
+  p->xchunks_max = p->xnnz / 8192 + p->du + 1;
+  {
+    // FP8 staging tile: row groups of about 128 MiB of codes (64-row multiples)
+    const int64_t ld = (p->du + 3) / 4 * 4;
+    const int64_t g = std::max<int64_t>(64, ((int64_t{128} << 20) / ld) / 64 * 64);
+    p->xstage_rows = static_cast<int>(std::min<int64_t>(g, (int64_t{p->n} + 63) / 64 * 64));
   }
   p->rowbits = bits_for(p->n);
   p->colbits = bits_for(p->m);
@@ -603,7 +656,7 @@ tpo_status tpo_stage_reduce(tpo_plan* plan, const tpo_inputs* in, void* ws, size
   if (st != TPO_OK) return st;
   std::string why;
   if (!valid_inputs(plan, in, &why)) return fail(plan, TPO_EINVAL, why);
-  return guarded(plan, [&] { launch_reduce(*plan, ws, in->x_u, in->ld_x, in->x_scale, static_cast<hipStream_t>(stream)); });
+  return guarded(plan, [&] { launch_reduce(*plan, ws, in, static_cast<hipStream_t>(stream)); });
 }
 
 tpo_status tpo_stage_propagate(tpo_plan* plan, const tpo_inputs* in, void* ws, size_t bytes, void* stream) {

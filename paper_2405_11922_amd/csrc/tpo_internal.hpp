@@ -35,7 +35,9 @@ constexpr int kMaxTimedHops = 64;
 struct DevStatus {
   int32_t err_bits;        // bit 0: edge out of range, bit 1: bad weight,
                            // bit 2: non-finite attribute, bit 3: R'.r <= 0,
-                           // bit 4: Cholesky breakdown, bit 5: non-finite value
+                           // bit 4: Cholesky breakdown, bit 5: non-finite value,
+                           // bit 6: grid barrier timed out, bit 7: sparse
+                           // attribute row starts or columns out of range
   int32_t has_vals;        // CSR carries a value array (weights / duplicates)
   int32_t n_unique;        // distinct (u, v) pairs
   int32_t guard_hits;      // ONMF guards applied
@@ -76,6 +78,11 @@ enum Buf {
   // subspace iteration (reduction and embedding)
   B_SI_M, B_SI_P, B_SI_GRAM, B_SI_PART, B_SI_BAR,
   B_REDTMP,
+  // sparse attributes (TPO_X_CSR): column scales and maxima, the FP8 staging
+  // tile, the transpose (CSC) and its sort buffers, the column-chunk table
+  // and partials, and Y = X M of the refinement step
+  B_XS_SCALE, B_XS_COLMAX, B_XS_STAGE, B_XT_KA, B_XT_KB, B_XT_VA, B_XT_VB, B_XT_HIST, B_XT_AUX,
+  B_XT_COLPTR, B_XT_ROW, B_XT_CHUNK, B_XT_CINFO, B_XT_CPART, B_XT_Y,
   B_COUNT
 };
 
@@ -93,6 +100,11 @@ struct Plan {
   bool reduce;
   bool xbf16;  // X_U is bfloat16
   bool xfp8;   // X_U is FP8 E4M3 with column scales
+  bool xcsr;   // X_U is sparse FP32 (CSR)
+  int64_t xnnz;        // stored entries of a sparse X_U
+  int xsort_blocks;    // radix-sort tiles of the transpose of a sparse X_U
+  int xstage_rows;     // rows of the FP8 staging tile
+  int64_t xchunks_max; // column chunks of the transpose, upper bound
   int rowbits, colbits;
   int sort_blocks;          // tiles of the radix sort
   int max_chunks_u, max_chunks_v;
@@ -126,11 +138,29 @@ inline T* bufp(const Plan& p, void* ws, Buf b) {
 // ---------------------------------------------------------------------------
 // k_ingest.hip
 void launch_ingest(const Plan& p, void* ws, const tpo_inputs* in, hipStream_t s);
+// sparse attributes: the transpose (CSC) of X_U into B_XT_* (k_ingest.hip)
+void xcsr_transpose(const Plan& p, void* ws, const int64_t* rowptr, const int32_t* col, const float* val,
+                    hipStream_t s);
+// k_xsparse.hip: column scales into B_XS_SCALE; rows [r0, r0 + rows) as E4M3
+// codes into B_XS_STAGE (row stride ld); out = X B (FP64 sums, FP32 out, zero
+// columns lb..wo); P = X^T Y (ldp, or no P when NULL) and the column sums of
+// X from the transpose; dense rows without the reduction.
+constexpr int kXMaxDu = 4096;
+void xcsr_scales(const Plan& p, void* ws, const int64_t* rowptr, const int32_t* col, const float* val,
+                 hipStream_t s);
+void xcsr_stage_fp8(const Plan& p, void* ws, const int64_t* rowptr, const int32_t* col, const float* val,
+                    int64_t r0, int rows, int ld, hipStream_t s);
+void xcsr_rowgather(const Plan& p, const int64_t* rowptr, const int32_t* col, const float* val, const double* B,
+                    int lb, int ldb, float* out, int ldo, int wo, hipStream_t s);
+void xcsc_colgather(const Plan& p, void* ws, const float* Y, int l, int ldy, double* P, int ldp, double* colsum,
+                    hipStream_t s);
+void xcsr_dense(const Plan& p, void* ws, const int64_t* rowptr, const int32_t* col, const float* val, float* xp,
+                hipStream_t s);
 // k_spmm.hip
 void launch_propagate(const Plan& p, void* ws, const float* xprime, int64_t ldxp,
                       hipStream_t s);
 // k_dense.hip
-void launch_reduce(const Plan& p, void* ws, const void* x, int64_t ldx, const float* xscale, hipStream_t s);
+void launch_reduce(const Plan& p, void* ws, const tpo_inputs* in, hipStream_t s);
 void launch_features(const Plan& p, void* ws, hipStream_t s);
 void launch_embed(const Plan& p, void* ws, hipStream_t s);
 // k_smallla.hip (single workgroup, small matrices in LDS, n <= 80)

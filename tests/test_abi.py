@@ -18,7 +18,7 @@ def _declared_symbols():
     with open(os.path.join(ROOT, "include", "tpo.h")) as f:
         text = f.read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(tpo_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(tpo_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -92,11 +92,12 @@ def test_attribute_dtype_checked():
 
     lib = tpo.load_library()
     par = tpo.TpoParams(tpo.TPO_ABI_VERSION, 5, 0.5, 3, 0, 20, 10, 5, 20, 0, 0, None, None, None)
-    for xdt, want in ((0, 0), (1, 0), (2, 0), (3, 1), (-1, 1)):
-        prob = tpo.TpoProblem(tpo.TPO_ABI_VERSION, 100, 100, 32, 500, 0, xdt)
+    for xdt, nnz, want in ((0, 0, 0), (1, 0, 0), (2, 0, 0), (3, 800, 0), (3, -1, 1), (3, 1 << 31, 1), (4, 0, 1),
+                           (-1, 0, 1)):
+        prob = tpo.TpoProblem(tpo.TPO_ABI_VERSION, 100, 100, 32, 500, 0, xdt, nnz)
         h = C.c_void_p()
         st = lib.tpo_plan_create(C.byref(prob), C.byref(par), C.byref(h))
-        assert st == want, (xdt, st)
+        assert st == want, (xdt, nnz, st)
         if st == 0:
             lib.tpo_plan_destroy(h)
     with pytest.raises(tpo.TpoError) as e:

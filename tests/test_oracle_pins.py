@@ -415,6 +415,29 @@ def test_gram_basis_sign_fallback_on_centred_columns():
     assert np.allclose(np.abs(psi), np.abs(vt[:4].T), atol=1e-10)
 
 
+def test_gram_basis_rayleigh_ritz_with_another_matrix():
+    """With c_final the Rayleigh-Ritz step uses that matrix: when the iterated
+    matrix and c_final share their leading invariant subspace but order its
+    eigenvalues differently, the basis comes out as c_final's eigenvectors in
+    c_final's order (LAPACK eigh of c_final)."""
+    rng = np.random.default_rng(23)
+    v, _ = np.linalg.qr(rng.standard_normal((20, 20)))
+    lam1 = np.concatenate([[50, 45, 40, 35, 30, 25], 0.1 * rng.uniform(size=14)])
+    lam2 = np.concatenate([[30, 50, 25, 45, 35, 40], 0.1 * rng.uniform(size=14)])
+    c1 = (v * lam1) @ v.T
+    c2 = (v * lam2) @ v.T
+    x_colsum = rng.standard_normal(20)
+    om = rng.standard_normal((20, 6))
+    psi, sig = o.top_d_gram_basis(c1, x_colsum, 100, 4, om, 30, c_final=c2)
+    w, u = np.linalg.eigh(c2)
+    top = u[:, np.argsort(-w)[:4]]
+    assert np.allclose(sig ** 2, np.sort(w)[::-1][:4], rtol=1e-10)
+    assert np.allclose(np.abs(psi.T @ top), np.eye(4), atol=1e-8)
+    # without c_final: c1's own order
+    psi1, _ = o.top_d_gram_basis(c1, x_colsum, 100, 4, om, 30)
+    assert np.allclose(np.abs(psi1.T @ v[:, :4]), np.eye(4), atol=1e-8)
+
+
 def test_lemma_ff_zz_bound():
     """Lemma FF-ZZ: |Z'_i . Z'_j - Z_i . Z_j| <= sigma_{d+1}^2 sqrt(D_i D_j)/(1-alpha)
     with the exact top-d SVD and the gamma -> infinity propagation."""
