@@ -69,7 +69,10 @@ def counted_traffic(config: str, side: str):
 
 def run_serve(args) -> int:
     """The serving workload: a Poisson stream of independent jobs of random
-    shape served with continuous batching (paper_2405_11922_amd.serve)."""
+    shape served with continuous batching (paper_2405_11922_amd.serve), each
+    pool graph's CSR resident in HBM between its jobs, attributes in
+    bfloat16; beside it the same stream with FP32 attributes, and with FP32
+    attributes on the plain path (one job at a time, every job ingesting)."""
     import torch
 
     import abg_synth as synth
@@ -81,33 +84,51 @@ def run_serve(args) -> int:
     graphs = []
     for n_u, n_v, n_edges, k, d_u, gseed in shapes:
         eu, ev, x, _, _ = synth.planted_abg_device(n_u, n_v, n_edges, k, d_u, device=dev, zipf_a=2.0, seed=gseed)
-        graphs.append((eu, ev, x.to(torch.bfloat16), n_v))
+        graphs.append((eu, ev, x, n_v))
     torch.cuda.synchronize()
     log(f"[serve] {len(shapes)} pool graphs (|U| {min(s[0] for s in shapes)}..{max(s[0] for s in shapes)}, "
         f"{sum(s[2] for s in shapes)} edges in all) drawn on the GPU in {time.time() - t0:.1f}s")
-    jobs = [serve.Job(i, r.arrival, *graphs[r.graph][:3], graphs[r.graph][3], r.params)
-            for i, r in enumerate(reqs)]
-    srv = serve.Server(device=dev, hbm_budget=args.serve_hbm_gb << 30, workers=args.serve_workers)
-    warm = [serve.Job(-1 - i, 0.0, *graphs[g][:3], graphs[g][3], reqs[0].params | dict(k=2))
-            for i, g in enumerate(range(min(4, len(graphs))))]
-    srv.run(warm, realtime=False)
-    torch.cuda.synchronize()
-    t1 = time.time()
-    res = srv.run(jobs, realtime=True)
-    torch.cuda.synchronize()
-    wall = time.time() - t1
-    summ = serve.summarize(res)
-    log(f"[serve] {summ['jobs']} jobs ({summ['failed']} failed) in {wall:.2f}s: {summ.get('jobs_per_s', 0):.1f} jobs/s, "
-        f"p50 {summ.get('p50_ms', 0):.2f} ms, p99 {summ.get('p99_ms', 0):.2f} ms; queueing p50 "
-        f"{summ.get('queue_p50_ms', 0):.2f} ms, inside tpo_execute p50 {summ.get('exec_p50_ms', 0):.2f} ms "
-        f"(mean {summ.get('exec_mean_ms', 0):.2f})")
+
+    def stream_of(dtype):
+        xs = [g[2].to(dtype) for g in graphs]
+        jobs = [serve.Job(i, r.arrival, graphs[r.graph][0], graphs[r.graph][1], xs[r.graph], graphs[r.graph][3],
+                          r.params, graph_key=r.graph) for i, r in enumerate(reqs)]
+        warm = [serve.Job(-1 - i, 0.0, graphs[g][0], graphs[g][1], xs[g], graphs[g][3], reqs[0].params | dict(k=2))
+                for i, g in enumerate(range(min(4, len(graphs))))]
+        return jobs, warm
+
+    def serve_once(tag, dtype, workers, resident):
+        jobs, warm = stream_of(dtype)
+        srv = serve.Server(device=dev, hbm_budget=args.serve_hbm_gb << 30, workers=workers, resident=resident)
+        srv.run(warm, realtime=False)
+        torch.cuda.synchronize()
+        t1 = time.time()
+        res = srv.run(jobs, realtime=True)
+        torch.cuda.synchronize()
+        wall = time.time() - t1
+        summ = serve.summarize(res)
+        log(f"[serve] {tag}: {summ['jobs']} jobs ({summ['failed']} failed, {summ.get('resident_jobs', 0)} on a resident "
+            f"graph) in {wall:.2f}s: {summ.get('jobs_per_s', 0):.1f} jobs/s, p50 {summ.get('p50_ms', 0):.2f} ms, "
+            f"p99 {summ.get('p99_ms', 0):.2f} ms; queueing p50 {summ.get('queue_p50_ms', 0):.2f} ms, inside "
+            f"tpo_execute p50 {summ.get('exec_p50_ms', 0):.2f} ms (mean {summ.get('exec_mean_ms', 0):.2f})")
+        return summ
+
+    summ = serve_once("bf16, resident graphs", torch.bfloat16, args.serve_workers, True)
+    f32 = serve_once("f32, resident graphs", torch.float32, args.serve_workers, True)
+    plain = serve_once("f32, plain path (one job at a time, every job ingests)", torch.float32, 1, False)
+
+    def brief(x):
+        return {"jobs_per_s": round(x["jobs_per_s"], 3) if x.get("jobs_per_s") else None,
+                "p50_ms": round(x["p50_ms"], 4), "p99_ms": round(x["p99_ms"], 4),
+                "exec_p50_ms": round(x["exec_p50_ms"], 4), "failed": x["failed"]}
+
     result = {
         "metric": "clusterings/s served (continuous batching) and p50/p99 job latency",
         "value": round(summ["jobs_per_s"], 3) if summ.get("jobs_per_s") else None,
         "unit": "clusterings/s",
         "n_gpus": 1,
         "steps": summ["jobs"],
-        "warmup": len(warm),
+        "warmup": 4,
         "ms_per_step": round(1e3 / summ["jobs_per_s"], 4) if summ.get("jobs_per_s") else None,
         "higher_is_better": True,
         "scaling": "weak",
@@ -119,11 +140,14 @@ def run_serve(args) -> int:
                         f"{args.serve_pool} planted-partition graphs, |U| log-uniform in [1e3, 5e5], |V| = 1.5|U|, "
                         f"average degree 10-30, k in [2, 64], d_U in {{32, 128, 256}} bfloat16 -> min(d_U, 64), "
                         f"gamma 5, alpha 0.5; {args.serve_workers} concurrent jobs, "
-                        f"{args.serve_hbm_gb} GiB workspace budget",
+                        f"{args.serve_hbm_gb} GiB workspace budget, each graph's CSR resident between its jobs",
         },
         "latency_ms": {"p50": round(summ["p50_ms"], 4), "p99": round(summ["p99_ms"], 4),
                        "mean": round(summ["mean_ms"], 4), "max": round(summ["max_ms"], 4)},
+        "resident_jobs": summ.get("resident_jobs", 0),
         "failed": summ["failed"],
+        "vs_f32_same_server": brief(f32),
+        "vs_plain_fp32": brief(plain),
     }
     print(json.dumps(result), flush=True)
     return 0 if summ["failed"] == 0 else 1

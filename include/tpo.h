@@ -201,6 +201,19 @@ tpo_status tpo_execute(tpo_plan* plan, const tpo_inputs* in, void* workspace,
                        size_t workspace_bytes, void* stream,
                        const tpo_outputs* out);
 
+/* tpo_execute for a job whose graph is already in `workspace`: the CSR,
+ * degrees and hub lists that the last tpo_execute or tpo_stage_ingest of a
+ * plan of the same shape built in this workspace are reused, and ingest (S0)
+ * is skipped; tpo_inputs' edge arrays are not read.  For serving many jobs
+ * on one graph, whose CSR then stays in HBM between jobs.  The caller
+ * guarantees that this job's edge list is the one ingested last into the
+ * workspace; a workspace without a finished ingest of this plan's shape
+ * (n_u, n_v, n_edges) gives TPO_EINVAL.  Other arguments and errors as for
+ * tpo_execute. */
+tpo_status tpo_execute_resident(tpo_plan* plan, const tpo_inputs* inputs,
+                                void* workspace, size_t workspace_bytes,
+                                void* stream, const tpo_outputs* outputs);
+
 void tpo_plan_destroy(tpo_plan* plan);
 const char* tpo_status_string(tpo_status status);
 const char* tpo_plan_last_error(const tpo_plan* plan);

@@ -20,7 +20,7 @@ __all__ = [
     "tpo_stage_features", "tpo_stage_embed", "tpo_stage_onmf", "tpo_stage_nci",
     "tpo_stage_objective", "tpo_plan_buffer", "tpo_plan_stats", "tpo_draw_normals",
     "tpo_status_string", "BUF", "Plan", "cluster", "tpo_execute_noalloc", "TPO_NOALLOC_MAX_BYTES", "CsrX",
-    "tpo_e4m3_encode",
+    "tpo_e4m3_encode", "tpo_execute_resident",
 ]
 
 TPO_ABI_VERSION = 3
@@ -47,6 +47,7 @@ EXPORTED = [
     "tpo_stage_ingest", "tpo_stage_reduce", "tpo_stage_propagate", "tpo_stage_features",
     "tpo_stage_embed", "tpo_stage_onmf", "tpo_stage_nci", "tpo_stage_objective",
     "tpo_plan_buffer", "tpo_draw_normals", "tpo_abi_version", "tpo_execute_noalloc", "tpo_e4m3_encode",
+    "tpo_execute_resident",
 ]
 
 
@@ -127,6 +128,7 @@ def load_library() -> C.CDLL:
     lib.tpo_plan_dims.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
     lib.tpo_execute.argtypes = [vp, C.POINTER(TpoInputs), vp, sz, vp, C.POINTER(TpoOutputs)]
     lib.tpo_execute_noalloc.argtypes = [vp, C.POINTER(TpoInputs), vp, C.POINTER(TpoOutputs)]
+    lib.tpo_execute_resident.argtypes = [vp, C.POINTER(TpoInputs), vp, sz, vp, C.POINTER(TpoOutputs)]
     lib.tpo_plan_destroy.argtypes = [vp]
     lib.tpo_plan_destroy.restype = None
     lib.tpo_status_string.argtypes = [C.c_int]
@@ -279,6 +281,19 @@ def tpo_execute(plan, edge_u, edge_v, x_u, workspace, labels, embedding=None, ed
                      C.cast(obj, C.POINTER(C.c_double)))
     _check(lib.tpo_execute(plan, C.byref(inp), workspace.data_ptr(), workspace.numel() * workspace.element_size(),
                            _stream(stream), C.byref(out)), plan)
+    return float(obj[0]), float(obj[1])
+
+
+def tpo_execute_resident(plan, x_u, workspace, labels, embedding=None, stream=None, x_scale=None):
+    """tpo_execute on the graph a previous job ingested into `workspace`
+    (ingest skipped, the CSR reused); returns (obj1, trace form)."""
+    lib = load_library()
+    inp = _inputs(None, None, x_u, None, plan, x_scale)
+    obj = (C.c_double * 2)()
+    out = TpoOutputs(labels.data_ptr(), embedding.data_ptr() if embedding is not None else None,
+                     C.cast(obj, C.POINTER(C.c_double)))
+    _check(lib.tpo_execute_resident(plan, C.byref(inp), workspace.data_ptr(),
+                                    workspace.numel() * workspace.element_size(), _stream(stream), C.byref(out)), plan)
     return float(obj[0]), float(obj[1])
 
 

@@ -454,6 +454,53 @@ void launch_ingest(const Plan& p, void* ws, const tpo_inputs* in, hipStream_t s)
              &st->iso_u, &st->hub_chunks_u, &st->hub_rows_u, s);
   side_lists(p, ws, p.m, rowptr_v, val_v, 1, B_DEG_V, B_INV_V, B_HUBCNT_V, B_HUBROW_V, B_CHUNK_V, B_HUBLIST_V,
              &st->iso_v, &st->hub_chunks_v, &st->hub_rows_v, s);
+  save_graph_status(p, ws, s);
+}
+
+// ---------------------------------------------------------------------------
+// The ingested graph's status, kept for resident jobs
+// ---------------------------------------------------------------------------
+__global__ void k_save_graph_status(const DevStatus* __restrict__ st, int n, int m, int64_t E,
+                                    GraphStatus* __restrict__ g) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  g->n = n;
+  g->m = m;
+  g->n_edges = static_cast<int32_t>(E);
+  g->has_vals = st->has_vals;
+  g->n_unique = st->n_unique;
+  g->iso_u = st->iso_u;
+  g->iso_v = st->iso_v;
+  g->hub_chunks_u = st->hub_chunks_u;
+  g->hub_rows_u = st->hub_rows_u;
+  g->hub_chunks_v = st->hub_chunks_v;
+  g->hub_rows_v = st->hub_rows_v;
+  g->err_bits = st->err_bits & 3;
+  g->magic = kGraphMagic;
+}
+
+__global__ void k_restore_graph_status(const GraphStatus* __restrict__ g, DevStatus* __restrict__ st) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  st->has_vals = g->has_vals;
+  st->n_unique = g->n_unique;
+  st->iso_u = g->iso_u;
+  st->iso_v = g->iso_v;
+  st->hub_chunks_u = g->hub_chunks_u;
+  st->hub_rows_u = g->hub_rows_u;
+  st->hub_chunks_v = g->hub_chunks_v;
+  st->hub_rows_v = g->hub_rows_v;
+  st->err_bits |= g->err_bits;
+}
+
+void save_graph_status(const Plan& p, void* ws, hipStream_t s) {
+  hipLaunchKernelGGL(k_save_graph_status, dim3(1), dim3(64), 0, s, bufp<DevStatus>(p, ws, B_STATUS), p.n, p.m, p.E,
+                     bufp<GraphStatus>(p, ws, B_GSTATUS));
+  TPO_LAUNCH_CHECK();
+}
+
+void restore_graph_status(const Plan& p, void* ws, hipStream_t s) {
+  hipLaunchKernelGGL(k_restore_graph_status, dim3(1), dim3(64), 0, s, bufp<GraphStatus>(p, ws, B_GSTATUS),
+                     bufp<DevStatus>(p, ws, B_STATUS));
+  TPO_LAUNCH_CHECK();
 }
 
 // ---------------------------------------------------------------------------

@@ -20,20 +20,30 @@ namespace tpo {
 constexpr int kXChunk = 8192;  // CSC entries per column chunk
 
 // |x_ij| maxima per column (as float bits: non-negative floats order like
-// their bit patterns), one wave per row.
+// their bit patterns): each workgroup keeps its maxima in LDS (one wave per
+// row, 64 rows per wave) and adds one global atomic per column it touched.
+constexpr int kColmaxRowsPerWave = 64;
+
 __global__ void __launch_bounds__(256)
 k_xcsr_colmax(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col, const float* __restrict__ val,
               int n, int64_t nnz, int du, uint32_t* __restrict__ colmax) {
-  const int lane = threadIdx.x & 63;
-  const int64_t r = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
-  if (r >= n) return;
-  const int64_t b = min(max(rowptr[r], static_cast<int64_t>(0)), nnz);
-  const int64_t e = min(max(rowptr[r + 1], b), nnz);
-  for (int64_t i = b + lane; i < e; i += 64) {
-    const int c = col[i];
-    const float v = fabsf(val[i]);
-    if (c >= 0 && c < du && isfinite(v)) atomicMax(&colmax[c], __float_as_uint(v));
+  __shared__ uint32_t lm[kXMaxDu];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int c = threadIdx.x; c < du; c += blockDim.x) lm[c] = 0u;
+  __syncthreads();
+  const int64_t r0 = (static_cast<int64_t>(blockIdx.x) * 4 + w) * kColmaxRowsPerWave;
+  for (int64_t r = r0; r < min(static_cast<int64_t>(n), r0 + kColmaxRowsPerWave); ++r) {
+    const int64_t b = min(max(rowptr[r], static_cast<int64_t>(0)), nnz);
+    const int64_t e = min(max(rowptr[r + 1], b), nnz);
+    for (int64_t i = b + lane; i < e; i += 64) {
+      const int c = col[i];
+      const float v = fabsf(val[i]);
+      if (c >= 0 && c < du && isfinite(v)) atomicMax(&lm[c], __float_as_uint(v));
+    }
   }
+  __syncthreads();
+  for (int c = threadIdx.x; c < du; c += blockDim.x)
+    if (lm[c]) atomicMax(&colmax[c], lm[c]);
 }
 
 __global__ void k_xcsr_scales(const uint32_t* __restrict__ colmax, int du, float* __restrict__ scale) {
@@ -54,8 +64,8 @@ void xcsr_scales(const Plan& p, void* ws, const int64_t* rowptr, const int32_t* 
   hipLaunchKernelGGL(k_fill_u32x, dim3(ceil_div(p.du, 256)), dim3(256), 0, s, colmax, static_cast<int64_t>(p.du), 0u);
   TPO_LAUNCH_CHECK();
   if (p.xnnz > 0) {
-    hipLaunchKernelGGL(k_xcsr_colmax, dim3(ceil_div(static_cast<int64_t>(p.n) * 64, 256)), dim3(256), 0, s, rowptr,
-                       col, val, p.n, p.xnnz, p.du, colmax);
+    hipLaunchKernelGGL(k_xcsr_colmax, dim3(ceil_div(p.n, 4 * kColmaxRowsPerWave)), dim3(256), 0, s, rowptr, col, val,
+                       p.n, p.xnnz, p.du, colmax);
     TPO_LAUNCH_CHECK();
   }
   hipLaunchKernelGGL(k_xcsr_scales, dim3(ceil_div(p.du, 256)), dim3(256), 0, s, colmax, p.du,
@@ -64,36 +74,44 @@ void xcsr_scales(const Plan& p, void* ws, const int64_t* rowptr, const int32_t* 
 }
 
 // Rows [r0, r0 + rows) as E4M3 codes of x / s_j into stage (row stride ld, a
-// multiple of 4): one wave per row builds the row in LDS (a column stored
-// twice in a row adds up), then writes it as 32-bit words.
+// multiple of 4).  One wave per row: the row's entries are added into an LDS
+// float row at their columns only (a column stored twice in a row adds up),
+// encoded there, and placed in a zeroed LDS byte row, which is then written
+// out as 32-bit words (zero columns encode to 0x00).
 __global__ void __launch_bounds__(256)
 k_xcsr_stage_fp8(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col, const float* __restrict__ val,
                  const float* __restrict__ scale, int64_t r0, int rows, int64_t nnz, int du, int ld,
                  uint8_t* __restrict__ stage) {
   __shared__ float rowbuf[4][kXMaxDu];
+  __shared__ __align__(16) uint32_t bytes[4][kXMaxDu / 4];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int i = blockIdx.x * 4 + w;
   if (i >= rows) return;
   float* rb = rowbuf[w];
-  for (int c = lane; c < du; c += 64) rb[c] = 0.0f;
-  wave_sync();
+  uint32_t* bw = bytes[w];
+  uint8_t* bb = reinterpret_cast<uint8_t*>(bw);
+  for (int c = lane; c < ld / 4; c += 64) bw[c] = 0u;
   const int64_t r = r0 + i;
   const int64_t b = min(max(rowptr[r], static_cast<int64_t>(0)), nnz);
   const int64_t e = min(max(rowptr[r + 1], b), nnz);
+  for (int64_t t = b + lane; t < e; t += 64) {
+    const int c = col[t];
+    if (c >= 0 && c < du) rb[c] = 0.0f;
+  }
+  wave_sync();
   for (int64_t t = b + lane; t < e; t += 64) {
     const int c = col[t];
     const float v = val[t];
     if (c >= 0 && c < du && isfinite(v)) atomicAdd(&rb[c], v);
   }
   wave_sync();
-  uint8_t* out = stage + static_cast<int64_t>(i) * ld;
-  for (int c = 4 * lane; c < ld; c += 256) {
-    uint32_t word = 0u;
-#pragma unroll
-    for (int h = 0; h < 4; ++h)
-      if (c + h < du) word |= static_cast<uint32_t>(e4m3_encode(rb[c + h] / scale[c + h])) << (8 * h);
-    *reinterpret_cast<uint32_t*>(out + c) = word;
+  for (int64_t t = b + lane; t < e; t += 64) {
+    const int c = col[t];
+    if (c >= 0 && c < du) bb[c] = e4m3_encode(rb[c] / scale[c]);
   }
+  wave_sync();
+  uint32_t* out = reinterpret_cast<uint32_t*>(stage + static_cast<int64_t>(i) * ld);
+  for (int c = lane; c < ld / 4; c += 64) out[c] = bw[c];
 }
 
 void xcsr_stage_fp8(const Plan& p, void* ws, const int64_t* rowptr, const int32_t* col, const float* val,

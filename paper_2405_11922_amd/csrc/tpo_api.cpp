@@ -82,6 +82,7 @@ void build_layout(Plan& p) {
   const size_t maxch = static_cast<size_t>(std::max(p.max_chunks_u, p.max_chunks_v));
   const size_t nbr = p.rowpass_blocks;
   add(B_STATUS, sizeof(DevStatus));
+  add(B_GSTATUS, sizeof(GraphStatus));
   add(B_KEYS_A, 8 * E);
   add(B_KEYS_B, 8 * E);
   add(B_WV_A, 4 * E);
@@ -255,16 +256,16 @@ void upload_inputs(tpo_plan* p, void* ws, hipStream_t s) {
                                hipMemcpyHostToDevice, s));
 }
 
-bool valid_inputs(tpo_plan* p, const tpo_inputs* in, std::string* why) {
+bool valid_inputs(tpo_plan* p, const tpo_inputs* in, std::string* why, bool need_edges = true) {
   if (!in) {
     *why = "inputs are NULL";
     return false;
   }
-  if (p->E > 0 && (!in->edge_u || !in->edge_v)) {
+  if (need_edges && p->E > 0 && (!in->edge_u || !in->edge_v)) {
     *why = "edge arrays are NULL";
     return false;
   }
-  if (p->prob.weighted && p->E > 0 && !in->edge_w) {
+  if (need_edges && p->prob.weighted && p->E > 0 && !in->edge_w) {
     *why = "weighted problem without edge_w";
     return false;
   }
@@ -293,12 +294,23 @@ bool valid_inputs(tpo_plan* p, const tpo_inputs* in, std::string* why) {
 }  // namespace
 
 tpo_status tpo::execute_plan(tpo_plan* plan, const tpo_inputs* in, void* ws, size_t bytes, hipStream_t s,
-                             const tpo_outputs* out, bool no_alloc) {
+                             const tpo_outputs* out, bool no_alloc, bool resident) {
   if (!plan) return TPO_EINVAL;
   tpo_status st = check_ws(plan, ws, bytes);
   if (st != TPO_OK) return st;
   std::string why;
-  if (!valid_inputs(plan, in, &why)) return fail(plan, TPO_EINVAL, why);
+  if (!valid_inputs(plan, in, &why, !resident)) return fail(plan, TPO_EINVAL, why);
+  if (resident) {
+    // the workspace must hold a finished ingest of a graph of this shape
+    GraphStatus g{};
+    st = guarded(plan, [&] {
+      TPO_HIP_CHECK(hipMemcpyAsync(&g, bufp<char>(*plan, ws, B_GSTATUS), sizeof(g), hipMemcpyDeviceToHost, s));
+      TPO_HIP_CHECK(hipStreamSynchronize(s));
+    });
+    if (st != TPO_OK) return st;
+    if (g.magic != kGraphMagic || g.n != plan->n || g.m != plan->m || g.n_edges != static_cast<int32_t>(plan->E))
+      return fail(plan, TPO_EINVAL, "the workspace holds no ingested graph of this plan's shape");
+  }
   if (!out || !out->labels) return fail(plan, TPO_EINVAL, "outputs or labels are NULL");
   const bool timing = (plan->par.flags & TPO_FLAG_TIMING) != 0;
   if (no_alloc && timing) return fail(plan, TPO_EINVAL, "a plan with TPO_FLAG_TIMING creates events; use one without");
@@ -315,7 +327,13 @@ tpo_status tpo::execute_plan(tpo_plan* plan, const tpo_inputs* in, void* ws, siz
     };
     upload_inputs(plan, ws, s);
     mark(0);
-    if (timing || no_alloc || (plan->par.flags & TPO_FLAG_ONE_STREAM)) {
+    if (resident) {
+      // the graph ingested by an earlier job on this workspace
+      restore_graph_status(*plan, ws, s);
+      mark(1);
+      launch_reduce(*plan, ws, in, s);
+      mark(2);
+    } else if (timing || no_alloc || (plan->par.flags & TPO_FLAG_ONE_STREAM)) {
       // stage by stage on one stream (timing: so that each stage's time is its own)
       launch_ingest(*plan, ws, in, s);
       mark(1);
@@ -725,6 +743,11 @@ tpo_status tpo_stage_objective(tpo_plan* plan, void* ws, size_t bytes, void* str
 tpo_status tpo_execute(tpo_plan* plan, const tpo_inputs* in, void* ws, size_t bytes, void* stream,
                        const tpo_outputs* out) {
   return execute_plan(plan, in, ws, bytes, static_cast<hipStream_t>(stream), out, false);
+}
+
+tpo_status tpo_execute_resident(tpo_plan* plan, const tpo_inputs* in, void* ws, size_t bytes, void* stream,
+                                const tpo_outputs* out) {
+  return execute_plan(plan, in, ws, bytes, static_cast<hipStream_t>(stream), out, false, true);
 }
 
 }  // extern "C"

@@ -50,8 +50,23 @@ struct DevStatus {
   int32_t pad;
 };
 
+// The ingested graph's part of the status block, kept in the workspace
+// (B_GSTATUS) so that a later job on the same workspace and edge list can
+// skip ingest (tpo_execute_resident).  magic and the shape say that the
+// workspace holds a finished ingest of this plan's shape.
+constexpr int32_t kGraphMagic = 0x54504F47;
+struct GraphStatus {
+  int32_t magic;
+  int32_t n, m;
+  int32_t n_edges;
+  int32_t has_vals, n_unique, iso_u, iso_v;
+  int32_t hub_chunks_u, hub_rows_u, hub_chunks_v, hub_rows_v;
+  int32_t err_bits;  // ingest's bits (edge range, weights)
+  int32_t pad;
+};
+
 enum Buf {
-  B_STATUS,
+  B_STATUS, B_GSTATUS,
   // ingest
   B_KEYS_A, B_KEYS_B, B_WV_A, B_WV_B, B_HIST, B_SCAN_AUX, B_UPOS,
   B_ROWPTR_U, B_COL_U, B_VAL_U, B_ROWPTR_V, B_COL_V, B_VAL_V,
@@ -156,6 +171,10 @@ void xcsc_colgather(const Plan& p, void* ws, const float* Y, int l, int ldy, dou
                     hipStream_t s);
 void xcsr_dense(const Plan& p, void* ws, const int64_t* rowptr, const int32_t* col, const float* val, float* xp,
                 hipStream_t s);
+// after ingest: its status fields and the graph's shape into B_GSTATUS; for
+// a resident job: those fields back into B_STATUS (k_ingest.hip)
+void save_graph_status(const Plan& p, void* ws, hipStream_t s);
+void restore_graph_status(const Plan& p, void* ws, hipStream_t s);
 // k_spmm.hip
 void launch_propagate(const Plan& p, void* ws, const float* xprime, int64_t ldxp,
                       hipStream_t s);
@@ -205,7 +224,7 @@ namespace tpo {
 // TPO_FLAG_TIMING are rejected), for callers that must not create runtime
 // objects.
 tpo_status execute_plan(tpo_plan* plan, const tpo_inputs* in, void* ws, size_t bytes, hipStream_t s,
-                        const tpo_outputs* out, bool no_alloc);
+                        const tpo_outputs* out, bool no_alloc, bool resident = false);
 // Records `msg` as the plan's last error and returns `st`.
 tpo_status plan_fail(tpo_plan* plan, tpo_status st, const std::string& msg);
 }  // namespace tpo

@@ -17,6 +17,14 @@ barrier, so all of its workgroups (ceil(N / 16), at most 64, for the N x N
 Gram it iterates on) must be resident at once.  Admission therefore also
 keeps the barrier workgroups of the jobs in flight within the 256 CUs (one
 CU each at most), whatever the number of workers.
+
+Resident graphs: jobs that name the same graph (Job.graph_key) and the same
+parameters reuse one workspace, which keeps the graph's CSR, degrees and hub
+lists in HBM between jobs: the first job ingests the edge list, later ones
+run tpo_execute_resident and skip ingest.  A resident workspace is held while
+idle and given back, least recently used first, when a new job needs the
+memory.  A job whose graph's workspace is busy with another job runs on a
+workspace of its own (and ingests).
 """
 from __future__ import annotations
 
@@ -53,6 +61,7 @@ class Job:
     n_v: int
     params: dict
     edge_w: object = None
+    graph_key: object = None  # jobs with equal keys share one edge list
 
 
 @dataclass
@@ -67,6 +76,7 @@ class Result:
     error: str = ""
     started: float = 0.0  # the worker took the job
     exec_s: float = 0.0   # inside tpo_execute
+    resident: bool = False  # ran on its graph's resident workspace (no ingest)
 
     @property
     def latency(self) -> float:
@@ -105,10 +115,23 @@ class _Pool:
 
 
 @dataclass
+class _Slot:
+    """A resident workspace: a plan and its pool region, holding one graph."""
+
+    plan: int
+    off: int
+    nbytes: int
+    busy: bool = False
+    ingested: bool = False
+    last_used: float = 0.0
+
+
+@dataclass
 class Server:
     device: object = "cuda:0"
-    hbm_budget: int = 64 << 30  # bytes of workspace in flight at most
+    hbm_budget: int = 64 << 30  # bytes of workspace (in flight and resident) at most
     workers: int = MAX_WORKERS
+    resident: bool = True  # keep each graph's workspace (and CSR) between its jobs
     _lock: threading.Condition = field(default_factory=threading.Condition, init=False)
     _in_flight: int = field(default=0, init=False)
     _busy: int = field(default=0, init=False)
@@ -122,6 +145,28 @@ class Server:
                                 x_dtype=xdt, one_stream=True, **job.params)
         return h, tpo.tpo_plan_workspace_bytes(h), barrier_workgroups(h, d_u)
 
+    @staticmethod
+    def _slot_key(job: Job):
+        if job.graph_key is None:
+            return None
+        return (job.graph_key, str(job.x_u.dtype), tuple(sorted(job.params.items())))
+
+    def _take(self, nbytes: int):
+        """A pool region, evicting idle resident workspaces (least recently
+        used first) while the pool is short; None if that does not free
+        enough.  Holds the lock."""
+        while True:
+            off = self._pool.take(nbytes)
+            if off is not None:
+                return off
+            idle = [(sl.last_used, key) for key, sl in self._slots.items() if not sl.busy]
+            if not idle:
+                return None
+            _, key = min(idle, key=lambda t: t[0])
+            sl = self._slots.pop(key)
+            self._pool.give(sl.off, sl.nbytes)
+            tpo.tpo_plan_destroy(sl.plan)
+
     def _worker(self, q: "queue.Queue", results: list, t0: float):
         import torch
 
@@ -130,26 +175,37 @@ class Server:
             item = q.get()
             if item is None:
                 return
-            job, h, nbytes, wg, off, admitted = item
+            job, h, nbytes, wg, off, admitted, slot = item
             res = Result(job.job_id, job.arrival, admitted, 0.0, workspace_bytes=nbytes)
             res.started = time.perf_counter() - t0
+            ok = False
             try:
                 with torch.cuda.stream(stream):
                     wsv = self._buf[off: off + nbytes]
                     labels = torch.empty(job.x_u.shape[0], dtype=torch.int32, device=self.device)
                     e0 = time.perf_counter()
-                    res.objective = tpo.tpo_execute(h, job.edge_u, job.edge_v, job.x_u, wsv, labels,
-                                                    edge_w=job.edge_w, stream=stream.cuda_stream)
+                    if slot is not None and slot.ingested:
+                        res.objective = tpo.tpo_execute_resident(h, job.x_u, wsv, labels, stream=stream.cuda_stream)
+                        res.resident = True
+                    else:
+                        res.objective = tpo.tpo_execute(h, job.edge_u, job.edge_v, job.x_u, wsv, labels,
+                                                        edge_w=job.edge_w, stream=stream.cuda_stream)
                     res.exec_s = time.perf_counter() - e0
                     res.labels = labels
+                    ok = True
             except tpo.TpoError as e:
                 res.error = str(e)
             finally:
-                tpo.tpo_plan_destroy(h)
                 res.done = time.perf_counter() - t0
                 with self._lock:
+                    if slot is not None:
+                        slot.busy = False
+                        slot.ingested = slot.ingested or ok
+                        slot.last_used = res.done
+                    else:
+                        tpo.tpo_plan_destroy(h)
+                        self._pool.give(off, nbytes)
                     self._in_flight -= nbytes
-                    self._pool.give(off, nbytes)
                     self._barrier_wg -= wg
                     self._busy -= 1
                     results.append(res)
@@ -168,6 +224,7 @@ class Server:
         self._buf = torch.empty(self.hbm_budget, dtype=torch.uint8, device=self.device)
         assert self._buf.data_ptr() % 256 == 0
         self._pool = _Pool(self.hbm_budget)
+        self._slots = {}
         t0 = time.perf_counter()
         threads = [threading.Thread(target=self._worker, args=(q, results, t0), daemon=True)
                    for _ in range(self.workers)]
@@ -179,6 +236,7 @@ class Server:
                     wait = job.arrival - (time.perf_counter() - t0)
                     if wait > 0:
                         time.sleep(wait)
+                key = self._slot_key(job) if self.resident else None
                 h, nbytes, wg = self._plan(job)
                 if nbytes > self.hbm_budget:
                     tpo.tpo_plan_destroy(h)
@@ -188,22 +246,37 @@ class Server:
                                               error="workspace above the HBM budget"))
                     continue
                 with self._lock:
-                    off = None
                     while True:
+                        use, off = None, None
                         if self._busy < self.workers and self._barrier_wg + wg <= BARRIER_CUS:
-                            off = self._pool.take(nbytes)
+                            slot = self._slots.get(key) if key is not None else None
+                            if slot is not None and not slot.busy:
+                                # its graph is resident: the slot's plan and workspace
+                                tpo.tpo_plan_destroy(h)
+                                use, off, h, nbytes = slot, slot.off, slot.plan, slot.nbytes
+                                break
+                            off = self._take(nbytes)
                             if off is not None:
+                                if key is not None and slot is None:
+                                    # the first job on this graph: its workspace stays
+                                    use = _Slot(h, off, nbytes)
+                                    self._slots[key] = use
                                 break
                         self._lock.wait()
+                    if use is not None:
+                        use.busy = True
                     self._busy += 1
                     self._in_flight += nbytes
                     self._barrier_wg += wg
-                q.put((job, h, nbytes, wg, off, time.perf_counter() - t0))
+                q.put((job, h, nbytes, wg, off, time.perf_counter() - t0, use))
         finally:
             for _ in threads:
                 q.put(None)
             for t in threads:
                 t.join()
+            for sl in self._slots.values():
+                tpo.tpo_plan_destroy(sl.plan)
+            self._slots = {}
             self._buf = None
         return results
 
@@ -221,6 +294,7 @@ def summarize(results: list) -> dict:
     exe = np.array([r.exec_s for r in ok]) * 1e3
     return {
         "jobs": len(ok),
+        "resident_jobs": sum(1 for r in ok if r.resident),
         "failed": len(results) - len(ok),
         "queue_p50_ms": float(np.percentile(wait, 50)),
         "exec_p50_ms": float(np.percentile(exe, 50)),

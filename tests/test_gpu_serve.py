@@ -23,7 +23,7 @@ def _jobs(serve, torch, dev):
             x = x.to(torch.bfloat16)
         d = min(d_u, 64)
         params = dict(k=k, alpha=0.5, gamma=5, d=d if d < d_u else 0, q=20, oversample=10, t_f=5, t_g=20, seed=i)
-        jobs.append(serve.Job(i, 0.0, eu, ev, x, n_v, params))
+        jobs.append(serve.Job(i, 0.0, eu, ev, x, n_v, params, graph_key=i))
     return jobs
 
 
@@ -41,13 +41,50 @@ def test_alone_equals_in_the_mix():
         alone[j.job_id] = r
     mixed = serve.Server(device=dev, workers=8).run(jobs + jobs, realtime=False)
     assert len(mixed) == 2 * len(jobs)
+    # one worker: every job's second run finds its graph resident
+    seq = serve.Server(device=dev, workers=1).run(jobs + jobs, realtime=False)
+    assert sum(r.resident for r in seq) == len(jobs)
+    mixed = mixed + seq
     for r in mixed:
         a = alone[r.job_id]
         assert not r.error, r.error
         assert torch.equal(r.labels, a.labels), r.job_id
         assert r.objective == a.objective, (r.job_id, r.objective, a.objective)
-    log(f"[serve] {len(jobs)} jobs, each twice among eight concurrent workers: labels and objectives "
-        f"identical to the job alone; {serve.summarize(mixed)}")
+    log(f"[serve] {len(jobs)} jobs, each twice among eight concurrent workers and twice on one worker (the "
+        f"second run on the resident graph): labels and objectives identical to the job alone; "
+        f"{serve.summarize(mixed)}")
+
+
+def test_execute_resident_equals_execute():
+    """tpo_execute_resident reuses the CSR a previous job left in the
+    workspace: the same labels, objective and Upsilon as tpo_execute; a
+    workspace without an ingest of this shape is refused."""
+    import torch
+
+    import paper_2405_11922_amd as tpo
+
+    dev = torch.device("cuda:0")
+    abg = synth.planted_abg(3000, 4500, 40_000, 6, 48, zipf_a=1.8, seed=77)
+    eu = torch.from_numpy(abg.edge_u).to(dev)
+    ev = torch.from_numpy(abg.edge_v).to(dev)
+    x = torch.from_numpy(abg.x_u).to(dev)
+    kw = dict(k=6, alpha=0.5, gamma=4, d=16, q=20, t_f=5, t_g=20, seed=3)
+    plan = tpo.Plan.create(abg.n_u, abg.n_v, abg.n_edges, abg.d_u, device=dev, **kw)
+    try:
+        lab_a = torch.empty(abg.n_u, dtype=torch.int32, device=dev)
+        lab_b = torch.empty_like(lab_a)
+        emb_a = torch.empty(abg.n_u, 6, device=dev)
+        emb_b = torch.empty_like(emb_a)
+        plan.workspace.fill_(0)
+        with pytest.raises(tpo.TpoError) as e:
+            tpo.tpo_execute_resident(plan.handle, x, plan.workspace, lab_b)
+        assert e.value.status == 1
+        obj_a = tpo.tpo_execute(plan.handle, eu, ev, x, plan.workspace, lab_a, emb_a)
+        obj_b = tpo.tpo_execute_resident(plan.handle, x, plan.workspace, lab_b, emb_b)
+        torch.cuda.synchronize()
+        assert torch.equal(lab_a, lab_b) and obj_a == obj_b and torch.equal(emb_a, emb_b)
+    finally:
+        plan.close()
 
 
 def test_admission_by_workspace():
