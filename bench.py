@@ -320,7 +320,6 @@ def cpu_baseline_sample(inp, shape, rows_frac=10):
     target rows (all their edges, every V node), at the workload's width d.
     Returns its rate in GEdge-hop/s (edges of the subgraph per second)."""
     import numpy as np
-    from threadpoolctl import threadpool_info
 
     import oracle
 
@@ -333,7 +332,6 @@ def cpu_baseline_sample(inp, shape, rows_frac=10):
     b = oracle.bipartite_adjacency(nu, shape.n_v, eu, ev)
     del eu, ev
     x = np.random.default_rng(0).standard_normal((nu, shape.d))
-    threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
     t0 = time.perf_counter()
     oracle.propagate(b, x, shape.alpha, 1)
     t1 = time.perf_counter()
@@ -341,7 +339,8 @@ def cpu_baseline_sample(inp, shape, rows_frac=10):
     t2 = time.perf_counter()
     hop = (t2 - t1) - (t1 - t0)  # the second hop alone (each call also builds L)
     rate = b.nnz / hop / 1e9
-    return {"value": round(rate, 6), "unit": "GEdge-hop/s", "cores": int(threads), "kind": "oracle",
+    # scipy's sparse-times-dense product runs on one thread
+    return {"value": round(rate, 6), "unit": "GEdge-hop/s", "cores": 1, "kind": "oracle",
             "sample": f"one Horner hop of the oracle's propagation (oracle.propagate, scipy sparse products, "
                       f"single-threaded) over the subgraph of the first {nu} of {shape.n_u} target rows "
                       f"({b.nnz} edges, all {shape.n_v} V nodes, d={shape.d}): the time of gamma=2 minus gamma=1, "
@@ -396,6 +395,17 @@ def main() -> int:
     if args.config == "serve":
         return run_serve(args)
     dev = torch.device("cuda:0")
+    if args.config == "copy":
+        # one device copy of 256 MiB and nothing else: the kernel of known
+        # traffic that scales the hardware byte counters
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"metric": "calibration copy", "bytes_read": src.numel() * 4,
+                          "bytes_written": dst.numel() * 4}), flush=True)
+        return 0
     inp = make_input(args, args.config, dev)
     shape = inp["shape"]
     x_dtype = args.x_dtype if args.x_dtype != "auto" else {"large": "bf16", "fp8_tfidf": "csr"}.get(args.config, "f32")

@@ -7,6 +7,8 @@
 // update (Eq. update-Q).  Sums grouped by cluster label (NCI's Phi = Ups^T Y
 // and the cluster sums of R in the objective) use 64-bit fixed point so that
 // their result does not depend on the order of the atomic additions.
+#include <mutex>
+
 #include "blk_linalg.hpp"
 #include "dev_common.hpp"
 #include "tpo_internal.hpp"
@@ -926,11 +928,17 @@ static void nci_rounds_wide(const Plan& p, void* ws, hipStream_t s) {
   long long* part = bufp<long long>(p, ws, B_NCI_PART);
   long long* sums = bufp<long long>(p, ws, B_NCI_SUM);
   const int64_t n = static_cast<int64_t>(p.n);
-  // the label sums' LDS is sized to k, so up to k = 64 two accumulation
+  // the label sums' LDS is sized to k, so up to k = 100 two accumulation
   // workgroups share a CU; 64-row runs per wave
   const size_t acc_lds = static_cast<size_t>(k * k + k) * sizeof(long long);
-  TPO_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_nci_accum_wide),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(acc_lds)));
+  // the dynamic-LDS limit is a process-wide attribute: set once, to the
+  // largest k's need, so that concurrent callers never race on it
+  static std::once_flag once;
+  std::call_once(once, [] {
+    TPO_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_nci_accum_wide),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      static_cast<int>((kNciWide * kNciWide + kNciWide) * sizeof(long long))));
+  });
   const int64_t per_cu = acc_lds <= 80 * 1024 ? 2 : 1;
   const int nb = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>({(n + 63) / 64, 256 * per_cu,
                                                                            static_cast<int64_t>(p.rowpass_blocks)})));

@@ -15,6 +15,8 @@
 // LDS (blocked Cholesky with L^{-1} formed in place), so that the next
 // product has L^{-1} at hand without another launch.  All workgroups factor
 // the same sums in the same order and so hold the same L^{-1}.
+#include <mutex>
+
 #include "blk_chol16.hpp"
 #include "dev_common.hpp"
 #include "tpo_internal.hpp"
@@ -332,9 +334,16 @@ static void si_run(const double* A, int N, const double* omega, int l, int n_ort
   const size_t a_bytes = static_cast<size_t>(16) * (N + 1) * sizeof(double);
   const int a_lds = nrt <= grid && kStatic + a_bytes <= kLdsBytes ? 1 : 0;
   const size_t dyn = a_lds ? a_bytes : 0;
-  if (dyn > 0)
+  // the kernel's dynamic-LDS limit is a process-wide attribute: set once, to
+  // the most any launch can ask for, so that concurrent callers (serving
+  // threads) never see a smaller value set by another thread between their
+  // own set and launch
+  static std::once_flag once;
+  std::call_once(once, [] {
     TPO_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_si_fused<NB>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(dyn)));
+                                      hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      static_cast<int>(kLdsBytes - kStatic)));
+  });
   hipLaunchKernelGGL(k_si_bar_reset, dim3(1), dim3(64), 0, s, bar);
   TPO_LAUNCH_CHECK();
   hipLaunchKernelGGL((k_si_fused<NB>), dim3(grid), dim3(kSiThreads), dyn, s, A, N, omega, l, n_orth, pa, pb, part,
