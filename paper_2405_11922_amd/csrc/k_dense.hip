@@ -166,168 +166,41 @@ k_gram_reduce(const double* __restrict__ part, const double* __restrict__ colsum
   }
 }
 
-// The same partials for a bfloat16 X (the attribute precision form): BF16
-// MFMA 16x16x32 with FP32 accumulation (products of two BF16 values are
-// exact in FP32), each 64-row slab's FP32 sums added into FP64.  Slabs are
-// staged transposed in LDS (column-major, 72-element stride), so a lane's
-// eight consecutive rows of one column are one 16-byte read.  Operand
-// layout: lane l supplies A[l % 16][8 (l / 16) .. 8 (l / 16) + 7] and
-// B[8 (l / 16) ..][l % 16] (the same rows for both, so the contraction does
-// not depend on the order inside the instruction); result v of lane l is
-// D[4 (l / 16) + v][l % 16].  vec: X 16-byte aligned, ldx and c multiples of
-// 8 (eight columns per load); otherwise element loads.
 typedef float v4f_t __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf_t __attribute__((ext_vector_type(8)));
 typedef unsigned int v4u_t __attribute__((ext_vector_type(4)));
-constexpr int kGBLd = kGSub + 8;  // LDS stride (bf16 elements) of a staged column
 
-__global__ void __launch_bounds__(256)
-k_gram_part_bf16(const uint16_t* __restrict__ X, int64_t n, int c, int64_t ldx, int ntiles, int rows_per_chunk,
-                 int nchunks, int vec, double* __restrict__ part, double* __restrict__ colsum_part) {
-  __shared__ __align__(16) uint16_t At[kGT * kGBLd];
-  __shared__ __align__(16) uint16_t Bt[kGT * kGBLd];
-  __shared__ double csum[4][kGT];
-  // XCD-aware order: workgroups are dispatched to the eight XCDs in turn, so
-  // workgroup b runs on XCD b % 8; every tile pair of one row chunk is given
-  // to the same XCD, one after another, so that the chunk's rows are read
-  // from memory once per XCD and served to the other pairs from its L2.
-  const int npairs = ntiles * (ntiles + 1) / 2;
-  const int b = blockIdx.x;
-  const int xcd = b % 8, slot = b / 8;
-  const int per_xcd = (nchunks + 7) / 8;  // chunks of each XCD
-  const int chunk = (slot / npairs) + per_xcd * xcd;
-  int pi = slot % npairs, ti = 0;
-  if (chunk >= nchunks) return;  // uniform: the padding of the grid
-  while (pi >= ntiles - ti) {
-    pi -= ntiles - ti;
-    ++ti;
-  }
-  const int pair = slot % npairs;
-  const int tj = ti + pi;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int i16 = lane & 15, kq = lane >> 4;
-  const int qa = w >> 1, qb = w & 1;
-  const int64_t r_beg = static_cast<int64_t>(chunk) * rows_per_chunk;
-  const int64_t r_end = min(n, r_beg + rows_per_chunk);
-  const bool diag = ti == tj;
-  const uint16_t* Bp = diag ? At : Bt;
-  v4d_t acc[2][2];  // FP64 sums of the 2 x 2 tiles
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int bb = 0; bb < 2; ++bb) acc[a][bb] = v4d_t{0.0, 0.0, 0.0, 0.0};
-  double cs = 0.0;
-  // thread tid stages rows 2 (tid >> 3) and 2 (tid >> 3) + 1, columns
-  // 8 (tid & 7) ..: each column's two rows are one 32-bit LDS store
-  uint32_t ra[8], rb[8];
-  auto fetch = [&](int64_t r0) {
-    const int rr = 2 * (tid >> 3), cg = 8 * (tid & 7);
-    const int ca = ti * kGT + cg, cb = tj * kGT + cg;
-    uint16_t va[2][8], vb[2][8];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int64_t row = r0 + rr + h;
-      if (vec) {
-        v4u_t ua = {0u, 0u, 0u, 0u}, ub = {0u, 0u, 0u, 0u};
-        if (row < r_end && ca < c) ua = *reinterpret_cast<const v4u_t*>(X + row * ldx + ca);
-        if (!diag && row < r_end && cb < c) ub = *reinterpret_cast<const v4u_t*>(X + row * ldx + cb);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          va[h][2 * e] = static_cast<uint16_t>(ua[e] & 0xffffu);
-          va[h][2 * e + 1] = static_cast<uint16_t>(ua[e] >> 16);
-          vb[h][2 * e] = static_cast<uint16_t>(ub[e] & 0xffffu);
-          vb[h][2 * e + 1] = static_cast<uint16_t>(ub[e] >> 16);
-        }
-      } else {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          va[h][e] = (row < r_end && ca + e < c) ? X[row * ldx + ca + e] : uint16_t{0};
-          vb[h][e] = (!diag && row < r_end && cb + e < c) ? X[row * ldx + cb + e] : uint16_t{0};
-        }
-      }
-    }
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      ra[e] = static_cast<uint32_t>(va[0][e]) | (static_cast<uint32_t>(va[1][e]) << 16);
-      rb[e] = static_cast<uint32_t>(vb[0][e]) | (static_cast<uint32_t>(vb[1][e]) << 16);
-    }
-  };
-  if (r_beg < r_end) fetch(r_beg);
-  for (int64_t r0 = r_beg; r0 < r_end; r0 += kGSub) {
-    {
-      const int rr = 2 * (tid >> 3), cg = 8 * (tid & 7);
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        *reinterpret_cast<uint32_t*>(At + (cg + e) * kGBLd + rr) = ra[e];
-        if (!diag) *reinterpret_cast<uint32_t*>(Bt + (cg + e) * kGBLd + rr) = rb[e];
-      }
-    }
-    __syncthreads();
-    if (r0 + kGSub < r_end) fetch(r0 + kGSub);
-    v4f_t s32[2][2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int bb = 0; bb < 2; ++bb) s32[a][bb] = v4f_t{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int ks = 0; ks < kGSub / 32; ++ks) {
-      const int k0 = 32 * ks + 8 * kq;
-      v8bf_t av[2], bv[2];
-#pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        av[a] = __builtin_bit_cast(v8bf_t, *reinterpret_cast<const v4u_t*>(At + (32 * qa + 16 * a + i16) * kGBLd + k0));
-        bv[a] = __builtin_bit_cast(v8bf_t, *reinterpret_cast<const v4u_t*>(Bp + (32 * qb + 16 * a + i16) * kGBLd + k0));
-      }
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int bb = 0; bb < 2; ++bb)
-          s32[a][bb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[bb], s32[a][bb], 0, 0, 0);
-    }
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int bb = 0; bb < 2; ++bb)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[a][bb][v] += static_cast<double>(s32[a][bb][v]);
-    if (diag && colsum_part) {
-      for (int rr = w; rr < kGSub; rr += 4)
-        cs += static_cast<double>(__uint_as_float(static_cast<uint32_t>(At[lane * kGBLd + rr]) << 16));
-    }
-    __syncthreads();
-  }
-  double* out = part + (static_cast<int64_t>(chunk) * npairs + pair) * kGT * kGT;
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int bb = 0; bb < 2; ++bb)
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-        out[(32 * qa + 16 * a + 4 * kq + v) * kGT + 32 * qb + 16 * bb + i16] = acc[a][bb][v];
-  if (diag && colsum_part) {
-    csum[w][lane] = cs;
-    __syncthreads();
-    if (tid < kGT) {
-      const double v = ((csum[0][tid] + csum[1][tid]) + csum[2][tid]) + csum[3][tid];
-      const int j = ti * kGT + tid;
-      if (j < c) colsum_part[static_cast<int64_t>(chunk) * c + j] = v;
-    }
-  }
-}
-
-// An FP8 E4M3 attribute (raw byte) as FP32, exactly.
-__device__ __forceinline__ float fp8_to_f32(uint32_t byte) {
-  return __builtin_amdgcn_cvt_f32_fp8(static_cast<int>(byte), 0);
-}
-
-// The same partials for an FP8 X (OCP E4M3 bytes; the column scales are
-// applied when the partials are summed): FP8 MFMA 16x16x32 with FP32
-// accumulation (a product of two E4M3 values has at most 8 significant bits,
-// exact in FP32), each 64-row slab's FP32 sums added into FP64.  Same tile
-// order, operand layout and transposed staging as the bfloat16 kernel with
-// one byte per element: a lane's eight consecutive rows of one column are one
-// 8-byte LDS read.  vec: X 4-byte aligned, ldx and c multiples of 4.
-constexpr int kG8Ld = kGSub + 8;  // LDS stride (bytes) of a staged column
+// The same partials for a narrow-type X (the attribute precision forms):
+// FMT 1 = bfloat16 on BF16 MFMA 16x16x32, FMT 2 = FP8 E4M3 (raw codes; the
+// column scales are applied when the partials are summed) on the gfx950 FP8
+// MFMA 16x16x128 with unit block scales.  Products of two BF16 or two E4M3
+// values are exact in FP32; each output's FP32 sums over a block of kNFlush
+// rows are added into FP64 registers, so an entry's error is at most
+// kNFlush u times the sum of its products' magnitudes (u = 2^-24).
+//
+// A workgroup of 8 waves owns one 128 x 128 tile pair (ti <= tj) of the Gram
+// over one row chunk.  Each slab (128 bytes of every column: 64 BF16 rows or
+// 128 FP8 rows) of both column tiles is staged transposed in LDS (one
+// column's slab contiguous, stride kNColLd bytes), double-buffered, with the
+// next slab's global loads in flight in registers.  Wave w computes the
+// 64 x 32 block (rows 64 (w / 4) .., columns 32 (w % 4) ..) as 4 x 2 MFMA
+// tiles.  On a diagonal tile the two waves below the diagonal (w = 4, 5)
+// form the tile's column sums instead.  Operand layout: lane l supplies the
+// rows of k-group l / 16 of its column l % 16 for both operands (the same
+// rows for A and B, so the contraction does not depend on the order inside
+// the instruction); result v of lane l is D[4 (l / 16) + v][l % 16].
+//
+// Workgroups are dispatched to the eight XCDs in turn (workgroup b runs on
+// XCD b % 8); every tile pair of one row chunk goes to the same XCD, so the
+// chunk's rows are fetched from memory about once per XCD and served to the
+// other pairs from its L2.  vec: X 16-byte aligned and the row stride a
+// multiple of 16 bytes (16-byte loads); otherwise element loads.
+constexpr int kNT = 128;                  // column tile
+constexpr int kNColB = 128;               // staged bytes of one column per slab
+constexpr int kNColLd = kNColB + 16;      // LDS stride of a staged column
+constexpr int kNOpBytes = kNT * kNColLd;  // one staged operand
+constexpr int kNFlush = 256;              // rows per FP32 block
+typedef int v8i_t __attribute__((ext_vector_type(8)));
 
 // 4 x 4 byte transpose: out[e] holds byte e of in[0], in[1], in[2], in[3] (in
 // that byte order), by v_perm_b32 (byte i of the result is byte sel_i of the
@@ -343,164 +216,329 @@ __device__ __forceinline__ void transpose4x4(const uint32_t (&in)[4], uint32_t (
   out[3] = __builtin_amdgcn_perm(y1, x1, 0x07060302u);
 }
 
-__global__ void __launch_bounds__(256)
-k_gram_part_fp8(const uint8_t* __restrict__ X, int64_t n, int c, int64_t ldx, int ntiles, int rows_per_chunk,
-                int nchunks, int vec, double* __restrict__ part, double* __restrict__ colsum_part, int accumulate) {
-  __shared__ __align__(16) uint8_t At[kGT * kG8Ld];
-  __shared__ __align__(16) uint8_t Bt[kGT * kG8Ld];
-  __shared__ double csum[4][kGT];
+// An FP8 E4M3 attribute (raw byte) as FP32, exactly.
+__device__ __forceinline__ float fp8_to_f32(uint32_t byte) {
+  return __builtin_amdgcn_cvt_f32_fp8(static_cast<int>(byte), 0);
+}
+
+template <int FMT>
+__global__ void __launch_bounds__(512)
+k_gram_narrow(const uint8_t* __restrict__ X, int64_t n, int c, int64_t ldx, int ntiles, int rows_per_chunk,
+              int nchunks, int vec, double* __restrict__ part, double* __restrict__ colsum_part, int accumulate) {
+  constexpr int ES = FMT == 1 ? 2 : 1;  // bytes per element
+  constexpr int SR = kNColB / ES;       // rows per slab
+  constexpr int EPG = 16 / ES;          // elements per 16-byte group
+  constexpr int RG = SR / 4;            // 4-row groups per slab
+  constexpr int FLUSH_SLABS = kNFlush / SR;
+  __shared__ __align__(16) uint8_t lds[2 * 2 * kNOpBytes];  // [buffer][operand]
   const int npairs = ntiles * (ntiles + 1) / 2;
   const int b = blockIdx.x;
   const int xcd = b % 8, slot = b / 8;
   const int per_xcd = (nchunks + 7) / 8;
-  const int chunk = (slot / npairs) + per_xcd * xcd;
-  int pi = slot % npairs, ti = 0;
+  const int chunk = slot / npairs + per_xcd * xcd;
   if (chunk >= nchunks) return;  // uniform: the padding of the grid
+  const int pair = slot % npairs;
+  int pi = pair, ti = 0;
   while (pi >= ntiles - ti) {
     pi -= ntiles - ti;
     ++ti;
   }
-  const int pair = slot % npairs;
   const int tj = ti + pi;
+  const bool diag = ti == tj;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int i16 = lane & 15, kq = lane >> 4;
-  const int qa = w >> 1, qb = w & 1;
+  const int qa = w >> 2, qb = w & 3;
+  const bool colsum_wave = diag && qa == 1 && qb < 2;  // wave-uniform
   const int64_t r_beg = static_cast<int64_t>(chunk) * rows_per_chunk;
   const int64_t r_end = min(n, r_beg + rows_per_chunk);
-  const bool diag = ti == tj;
-  const uint8_t* Bp = diag ? At : Bt;
-  v4d_t acc[2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int bb = 0; bb < 2; ++bb) acc[a][bb] = v4d_t{0.0, 0.0, 0.0, 0.0};
-  double cs = 0.0;
-  // thread tid stages rows 4 (tid >> 4) .. + 3, columns 4 (tid & 15) .. + 3:
-  // the four rows of each column are one 32-bit LDS store.  Two slabs are in
-  // flight in registers (buffers A and B, used alternately by the unrolled
-  // loop below), so a slab's loads have two slabs of work to arrive.
-  uint32_t raA[4], rbA[4], raB[4], rbB[4];
-  auto fetch = [&](int64_t r0, uint32_t (&ra)[4], uint32_t (&rb)[4]) {
-    const int rr = 4 * (tid >> 4), cg = 4 * (tid & 15);
-    const int ca = ti * kGT + cg, cb = tj * kGT + cg;
-    uint32_t wa[4], wb[4];  // row h: the bytes of columns cg .. cg + 3
+  const int nslabs = r_end > r_beg ? static_cast<int>((r_end - r_beg + SR - 1) / SR) : 0;
+
+  // staging: threads 0..255 stage column tile ti, 256..511 tile tj (idle on a
+  // diagonal tile); thread (rg, cg) moves rows 4 rg .. 4 rg + 3 of the
+  // 16-byte column group cg (consecutive lanes take consecutive row groups, so
+  // the transposed LDS stores of one instruction fall in distinct banks)
+  const int op = tid >> 8, sb = tid & 255;
+  const bool loader = !(diag && op == 1);
+  const int rg = sb % RG, cg = sb / RG;
+  const int gcol = (op ? tj : ti) * kNT + cg * EPG;  // first column of the group
+  uint32_t pre[4][4];  // rows 4 rg + h, 16 bytes each
+  auto fetch = [&](int64_t r0, uint32_t (&pf)[4][4]) {
 #pragma unroll
     for (int h = 0; h < 4; ++h) {
-      const int64_t row = r0 + rr + h;
-      if (vec) {
-        wa[h] = (row < r_end && ca < c) ? *reinterpret_cast<const uint32_t*>(X + row * ldx + ca) : 0u;
-        wb[h] = (!diag && row < r_end && cb < c) ? *reinterpret_cast<const uint32_t*>(X + row * ldx + cb) : 0u;
-      } else {
-        wa[h] = 0u;
-        wb[h] = 0u;
+      const int64_t row = r0 + 4 * rg + h;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          if (row < r_end && ca + e < c) wa[h] |= static_cast<uint32_t>(X[row * ldx + ca + e]) << (8 * e);
-          if (!diag && row < r_end && cb + e < c) wb[h] |= static_cast<uint32_t>(X[row * ldx + cb + e]) << (8 * e);
+      for (int d = 0; d < 4; ++d) pf[h][d] = 0u;
+      if (!loader || row >= r_end || gcol >= c) continue;
+      const uint8_t* src = X + (row * ldx + gcol) * ES;
+      if (vec && gcol + EPG <= c) {
+        const v4u_t v = *reinterpret_cast<const v4u_t*>(src);
+#pragma unroll
+        for (int d = 0; d < 4; ++d) pf[h][d] = v[d];
+      } else {
+#pragma unroll
+        for (int e = 0; e < EPG; ++e) {
+          if (gcol + e >= c) break;
+          const uint32_t val = ES == 2 ? static_cast<uint32_t>(reinterpret_cast<const uint16_t*>(src)[e])
+                                       : static_cast<uint32_t>(src[e]);
+          pf[h][(e * ES) / 4] |= val << (8 * ((e * ES) % 4));
         }
       }
     }
-    transpose4x4(wa, ra);
-    transpose4x4(wb, rb);
   };
-  if (r_beg < r_end) fetch(r_beg, raA, rbA);
-  if (r_beg + kGSub < r_end) fetch(r_beg + kGSub, raB, rbB);
-  // one slab: stage the buffer, refill it with the slab two ahead, multiply
-  auto slab = [&](int64_t r0, uint32_t (&ra)[4], uint32_t (&rb)[4]) {
-    {
-      const int rr = 4 * (tid >> 4), cg = 4 * (tid & 15);
+  auto store = [&](int buf, const uint32_t (&ps)[4][4]) {
+    if (!loader) return;
+    uint8_t* base = lds + (2 * buf + op) * kNOpBytes;
+    if constexpr (FMT == 1) {
+      // column 2 d + e: rows 0, 1 (low word) and 2, 3 (high word)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        *reinterpret_cast<uint32_t*>(At + (cg + e) * kG8Ld + rr) = ra[e];
-        if (!diag) *reinterpret_cast<uint32_t*>(Bt + (cg + e) * kG8Ld + rr) = rb[e];
+      for (int d = 0; d < 4; ++d)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const uint32_t sel = e ? 0x07060302u : 0x05040100u;
+          uint2 v;
+          v.x = __builtin_amdgcn_perm(ps[1][d], ps[0][d], sel);
+          v.y = __builtin_amdgcn_perm(ps[3][d], ps[2][d], sel);
+          *reinterpret_cast<uint2*>(base + (cg * EPG + 2 * d + e) * kNColLd + 8 * rg) = v;
+        }
+    } else {
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        const uint32_t in[4] = {ps[0][d], ps[1][d], ps[2][d], ps[3][d]};
+        uint32_t out[4];
+        transpose4x4(in, out);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          *reinterpret_cast<uint32_t*>(base + (cg * EPG + 4 * d + e) * kNColLd + 4 * rg) = out[e];
       }
     }
-    __syncthreads();
-    if (r0 + 2 * kGSub < r_end) fetch(r0 + 2 * kGSub, ra, rb);
-    v4f_t s32[2][2];
+  };
+
+  v4f_t s32[4][2];
+  v4d_t acc[4][2];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+  for (int m = 0; m < 4; ++m)
 #pragma unroll
-      for (int bb = 0; bb < 2; ++bb) s32[a][bb] = v4f_t{0.f, 0.f, 0.f, 0.f};
+    for (int mb = 0; mb < 2; ++mb) {
+      s32[m][mb] = v4f_t{0.f, 0.f, 0.f, 0.f};
+      acc[m][mb] = v4d_t{0.0, 0.0, 0.0, 0.0};
+    }
+  double cs = 0.0;  // column sum of column 64 qb + lane (colsum waves)
+  const int a_col = 64 * qa + i16, b_col = 32 * qb + i16;
+
+  auto mma = [&](int buf) {
+    const uint8_t* la = lds + (2 * buf) * kNOpBytes;
+    const uint8_t* lb = diag ? la : la + kNOpBytes;
+    if constexpr (FMT == 1) {
 #pragma unroll
-    for (int ks = 0; ks < kGSub / 32; ++ks) {
-      const int k0 = 32 * ks + 8 * kq;
-      long av[2], bv[2];
+      for (int ks = 0; ks < 2; ++ks) {
+        const int off = 64 * ks + 16 * kq;
+        v8bf_t av[4], bv[2];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        av[a] = *reinterpret_cast<const long*>(At + (32 * qa + 16 * a + i16) * kG8Ld + k0);
-        bv[a] = *reinterpret_cast<const long*>(Bp + (32 * qb + 16 * a + i16) * kG8Ld + k0);
+        for (int m = 0; m < 4; ++m)
+          av[m] = __builtin_bit_cast(v8bf_t, *reinterpret_cast<const v4u_t*>(la + (a_col + 16 * m) * kNColLd + off));
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+          bv[mb] = __builtin_bit_cast(v8bf_t, *reinterpret_cast<const v4u_t*>(lb + (b_col + 16 * mb) * kNColLd + off));
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+          for (int mb = 0; mb < 2; ++mb)
+            s32[m][mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], bv[mb], s32[m][mb], 0, 0, 0);
+      }
+    } else {
+      const int off = 32 * kq;
+      v8i_t av[4], bv[2];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const v4u_t lo = *reinterpret_cast<const v4u_t*>(la + (a_col + 16 * m) * kNColLd + off);
+        const v4u_t hi = *reinterpret_cast<const v4u_t*>(la + (a_col + 16 * m) * kNColLd + off + 16);
+        av[m] = v8i_t{static_cast<int>(lo[0]), static_cast<int>(lo[1]), static_cast<int>(lo[2]), static_cast<int>(lo[3]),
+                      static_cast<int>(hi[0]), static_cast<int>(hi[1]), static_cast<int>(hi[2]), static_cast<int>(hi[3])};
       }
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int mb = 0; mb < 2; ++mb) {
+        const v4u_t lo = *reinterpret_cast<const v4u_t*>(lb + (b_col + 16 * mb) * kNColLd + off);
+        const v4u_t hi = *reinterpret_cast<const v4u_t*>(lb + (b_col + 16 * mb) * kNColLd + off + 16);
+        bv[mb] = v8i_t{static_cast<int>(lo[0]), static_cast<int>(lo[1]), static_cast<int>(lo[2]), static_cast<int>(lo[3]),
+                       static_cast<int>(hi[0]), static_cast<int>(hi[1]), static_cast<int>(hi[2]), static_cast<int>(hi[3])};
+      }
+      // formats 0 (E4M3) for both operands; block scales 127 (2^0)
 #pragma unroll
-        for (int bb = 0; bb < 2; ++bb)
-          s32[a][bb] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av[a], bv[bb], s32[a][bb], 0, 0, 0);
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+          s32[m][mb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(av[m], bv[mb], s32[m][mb], 0, 0, 0, 127, 0, 127);
     }
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int bb = 0; bb < 2; ++bb)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[a][bb][v] += static_cast<double>(s32[a][bb][v]);
-    if (diag && colsum_part) {
-      for (int rr = w; rr < kGSub; rr += 4) cs += static_cast<double>(fp8_to_f32(At[lane * kG8Ld + rr]));
-    }
-    __syncthreads();
   };
-  for (int64_t r0 = r_beg; r0 < r_end; r0 += 2 * kGSub) {
-    slab(r0, raA, rbA);
-    if (r0 + kGSub < r_end) slab(r0 + kGSub, raB, rbB);  // uniform
+  // column sums of the staged slab: BF16 in FP32 groups of 8 rows, E4M3 in
+  // FP32 groups of 64 rows (exact: E4M3 values are multiples of 2^-9 below
+  // 2^9, so 64 of them sum below 2^24 units), each group added into FP64
+  auto colsum = [&](int buf) {
+    const uint8_t* col = lds + (2 * buf) * kNOpBytes + (64 * qb + lane) * kNColLd;
+    if constexpr (FMT == 1) {
+#pragma unroll
+      for (int g = 0; g < 8; ++g) {
+        const v4u_t v = *reinterpret_cast<const v4u_t*>(col + 16 * g);
+        float s = 0.0f;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) s += __uint_as_float(v[d] << 16) + __uint_as_float(v[d] & 0xffff0000u);
+        cs += static_cast<double>(s);
+      }
+    } else {
+#pragma unroll
+      for (int hgrp = 0; hgrp < 2; ++hgrp) {
+        float s = 0.0f;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const v4u_t v = *reinterpret_cast<const v4u_t*>(col + 64 * hgrp + 16 * g);
+#pragma unroll
+          for (int d = 0; d < 4; ++d) {
+            const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8(static_cast<int>(v[d]), false);
+            const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8(static_cast<int>(v[d]), true);
+            s += (lo[0] + lo[1]) + (hi[0] + hi[1]);
+          }
+        }
+        cs += static_cast<double>(s);
+      }
+    }
+  };
+  auto flush = [&]() {
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[m][mb][v] += static_cast<double>(s32[m][mb][v]);
+        s32[m][mb] = v4f_t{0.f, 0.f, 0.f, 0.f};
+      }
+  };
+
+  // slab s is read from LDS buffer s & 1 while slab s + 1 waits in
+  // registers; after the products it is staged into the other buffer (last
+  // read one slab earlier, before the barrier) and slab s + 2 is fetched
+  if (nslabs > 0) {
+    fetch(r_beg, pre);
+    store(0, pre);
+    if (nslabs > 1) fetch(r_beg + SR, pre);
   }
-  double* out = part + (static_cast<int64_t>(chunk) * npairs + pair) * kGT * kGT;
-  // accumulate: add to the partial of an earlier launch over other rows (the
-  // row groups of a sparse X_U, staged one after another)
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int bb = 0; bb < 2; ++bb)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        double* o = out + (32 * qa + 16 * a + 4 * kq + v) * kGT + 32 * qb + 16 * bb + i16;
-        *o = accumulate ? *o + acc[a][bb][v] : acc[a][bb][v];
-      }
-  if (diag && colsum_part) {
-    csum[w][lane] = cs;
-    __syncthreads();
-    if (tid < kGT) {
-      const double v = ((csum[0][tid] + csum[1][tid]) + csum[2][tid]) + csum[3][tid];
-      const int j = ti * kGT + tid;
-      if (j < c) colsum_part[static_cast<int64_t>(chunk) * c + j] = v;
+  __syncthreads();
+  for (int s = 0; s < nslabs; ++s) {
+    const int cur = s & 1;
+    if (colsum_wave) {
+      if (colsum_part) colsum(cur);
+    } else {
+      mma(cur);
     }
+    if (s + 1 < nslabs) {
+      store(cur ^ 1, pre);
+      if (s + 2 < nslabs) fetch(r_beg + static_cast<int64_t>(s + 2) * SR, pre);
+    }
+    if (!colsum_wave && ((s + 1) % FLUSH_SLABS == 0 || s + 1 == nslabs)) flush();
+    __syncthreads();
+  }
+
+  double* out = part + (static_cast<int64_t>(chunk) * npairs + pair) * kNT * kNT;
+  if (!colsum_wave) {
+    // accumulate: add to the partial of an earlier launch over other rows (the
+    // row groups of a sparse X_U, staged one after another)
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          double* o = out + (64 * qa + 16 * m + 4 * kq + v) * kNT + 32 * qb + 16 * mb + i16;
+          *o = accumulate ? *o + acc[m][mb][v] : acc[m][mb][v];
+        }
+  } else if (colsum_part) {
+    const int j = ti * kNT + 64 * qb + lane;
+    if (j < c) colsum_part[static_cast<int64_t>(chunk) * c + j] = cs;
+  }
+}
+
+// G (c x c, both triangles) from the 128 x 128 tile partials of the narrow
+// kernel, summed in chunk order; on a diagonal tile only the entries on and
+// above its diagonal are read (the block below it is not formed).
+__global__ void __launch_bounds__(256)
+k_gram_reduce_n(const double* __restrict__ part, const double* __restrict__ colsum_part, int nchunks, int c,
+                int ntiles, const float* __restrict__ scale, double* __restrict__ G, double* __restrict__ colsum) {
+  const int npairs = ntiles * (ntiles + 1) / 2;
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx < static_cast<int64_t>(npairs) * kNT * kNT) {
+    const int pr = static_cast<int>(idx / (kNT * kNT)), e = static_cast<int>(idx % (kNT * kNT));
+    int pi = pr, ti = 0;
+    while (pi >= ntiles - ti) {
+      pi -= ntiles - ti;
+      ++ti;
+    }
+    const int tj = ti + pi;
+    const int a = e / kNT, bcol = e % kNT;
+    const int i = ti * kNT + a, j = tj * kNT + bcol;
+    if (i < c && j < c && !(ti == tj && a > bcol)) {
+      const double* src = part + idx;
+      const int64_t stride = static_cast<int64_t>(npairs) * kNT * kNT;
+      double s = 0.0;
+      for (int ch0 = 0; ch0 < nchunks; ch0 += kGramBatch) {
+        double v[kGramBatch];
+#pragma unroll
+        for (int u = 0; u < kGramBatch; ++u) v[u] = ch0 + u < nchunks ? src[(ch0 + u) * stride] : 0.0;
+#pragma unroll
+        for (int u = 0; u < kGramBatch; ++u) s += v[u];
+      }
+      // column scales of an FP8 X: C_ij = s_i s_j (sum of the raw products);
+      // s_i s_j is exact in FP64
+      if (scale) s *= static_cast<double>(scale[i]) * static_cast<double>(scale[j]);
+      G[static_cast<int64_t>(i) * c + j] = s;
+      G[static_cast<int64_t>(j) * c + i] = s;
+    }
+  }
+  if (colsum && idx < c) {
+    double s = 0.0;
+    for (int ch0 = 0; ch0 < nchunks; ch0 += kGramBatch) {
+      double v[kGramBatch];
+#pragma unroll
+      for (int u = 0; u < kGramBatch; ++u)
+        v[u] = ch0 + u < nchunks ? colsum_part[static_cast<int64_t>(ch0 + u) * c + idx] : 0.0;
+#pragma unroll
+      for (int u = 0; u < kGramBatch; ++u) s += v[u];
+    }
+    colsum[idx] = scale ? s * static_cast<double>(scale[idx]) : s;
   }
 }
 
 // xdt: 0 FP32, 1 bfloat16, 2 FP8 E4M3 with column scales `scale`
 static void gram(const void* X, int xdt, const float* scale, int64_t n, int c, int64_t ldx, int nchunks, double* part,
                  double* colsum_part, double* G, double* colsum, hipStream_t s) {
+  const int rows_per_chunk = static_cast<int>((n + nchunks - 1) / nchunks);
+  if (xdt == 1 || xdt == 2) {
+    const int ntiles = (c + kNT - 1) / kNT;
+    const int npairs = ntiles * (ntiles + 1) / 2;
+    const int es = xdt == 1 ? 2 : 1;
+    const int vec = (reinterpret_cast<uintptr_t>(X) % 16 == 0 && (ldx * es) % 16 == 0) ? 1 : 0;
+    const int per_xcd = (nchunks + 7) / 8;
+    if (xdt == 1)
+      hipLaunchKernelGGL(k_gram_narrow<1>, dim3(8 * per_xcd * npairs), dim3(512), 0, s,
+                         static_cast<const uint8_t*>(X), n, c, ldx, ntiles, rows_per_chunk, nchunks, vec, part,
+                         colsum_part, 0);
+    else
+      hipLaunchKernelGGL(k_gram_narrow<2>, dim3(8 * per_xcd * npairs), dim3(512), 0, s,
+                         static_cast<const uint8_t*>(X), n, c, ldx, ntiles, rows_per_chunk, nchunks, vec, part,
+                         colsum_part, 0);
+    TPO_LAUNCH_CHECK();
+    const int64_t outs = std::max<int64_t>(static_cast<int64_t>(npairs) * kNT * kNT, c);
+    hipLaunchKernelGGL(k_gram_reduce_n, dim3(ceil_div(outs, 256)), dim3(256), 0, s, part, colsum_part, nchunks, c,
+                       ntiles, xdt == 2 ? scale : nullptr, G, colsum);
+    TPO_LAUNCH_CHECK();
+    return;
+  }
   const int ntiles = (c + kGT - 1) / kGT;
   const int npairs = ntiles * (ntiles + 1) / 2;
-  const int rows_per_chunk = static_cast<int>((n + nchunks - 1) / nchunks);
-  if (xdt == 2) {
-    const int vec = (reinterpret_cast<uintptr_t>(X) % 4 == 0 && ldx % 4 == 0 && c % 4 == 0) ? 1 : 0;
-    const int per_xcd = (nchunks + 7) / 8;
-    hipLaunchKernelGGL(k_gram_part_fp8, dim3(8 * per_xcd * npairs), dim3(256), 0, s,
-                       static_cast<const uint8_t*>(X), n, c, ldx, ntiles, rows_per_chunk, nchunks, vec, part,
-                       colsum_part, 0);
-  } else if (xdt == 1) {
-    const int vec = (reinterpret_cast<uintptr_t>(X) % 16 == 0 && ldx % 8 == 0 && c % 8 == 0) ? 1 : 0;
-    const int per_xcd = (nchunks + 7) / 8;
-    hipLaunchKernelGGL(k_gram_part_bf16, dim3(8 * per_xcd * npairs), dim3(256), 0, s,
-                       static_cast<const uint16_t*>(X), n, c, ldx, ntiles, rows_per_chunk, nchunks, vec, part,
-                       colsum_part);
-  } else {
-    hipLaunchKernelGGL(k_gram_part, dim3(npairs, nchunks), dim3(256), 0, s, static_cast<const float*>(X), n, c, ldx,
-                       ntiles, rows_per_chunk, part, colsum_part);
-  }
+  hipLaunchKernelGGL(k_gram_part, dim3(npairs, nchunks), dim3(256), 0, s, static_cast<const float*>(X), n, c, ldx,
+                     ntiles, rows_per_chunk, part, colsum_part);
   TPO_LAUNCH_CHECK();
   const int64_t outs = std::max<int64_t>(static_cast<int64_t>(npairs) * kGT * kGT, c);
   hipLaunchKernelGGL(k_gram_reduce, dim3(ceil_div(outs, 256)), dim3(256), 0, s, part, colsum_part, nchunks, c,
-                     ntiles, xdt == 2 ? scale : nullptr, G, colsum);
+                     ntiles, nullptr, G, colsum);
   TPO_LAUNCH_CHECK();
 }
 
@@ -1010,8 +1048,8 @@ static void project(const Plan& p, const XT* x, int64_t ldx, const float* sc, co
 // the column scales.
 static void gram_xcsr(const Plan& p, void* ws, const tpo_inputs* in, hipStream_t s) {
   const int c = p.du;
-  const int ld = (c + 3) / 4 * 4;
-  const int ntiles = (c + kGT - 1) / kGT;
+  const int ld = xcsr_stage_ld(c);
+  const int ntiles = (c + kNT - 1) / kNT;
   const int npairs = ntiles * (ntiles + 1) / 2;
   const int nchunks = p.gram_chunks_x;
   const int per_xcd = (nchunks + 7) / 8;
@@ -1019,15 +1057,15 @@ static void gram_xcsr(const Plan& p, void* ws, const tpo_inputs* in, hipStream_t
   const uint8_t* stage = bufp<uint8_t>(p, ws, B_XS_STAGE);
   for (int64_t r0 = 0; r0 < p.n; r0 += p.xstage_rows) {
     const int rows = static_cast<int>(std::min<int64_t>(p.xstage_rows, p.n - r0));
-    xcsr_stage_fp8(p, ws, in->x_rowptr, in->x_col, static_cast<const float*>(in->x_u), r0, rows, ld, s);
+    xcsr_stage_fp8(p, ws, r0, rows, ld, s);
     const int rows_per_chunk = (rows + nchunks - 1) / nchunks;
-    hipLaunchKernelGGL(k_gram_part_fp8, dim3(8 * per_xcd * npairs), dim3(256), 0, s, stage,
-                       static_cast<int64_t>(rows), c, static_cast<int64_t>(ld), ntiles, rows_per_chunk, nchunks,
-                       (c % 4 == 0) ? 1 : 0, part, nullptr, r0 > 0 ? 1 : 0);
+    hipLaunchKernelGGL(k_gram_narrow<2>, dim3(8 * per_xcd * npairs), dim3(512), 0, s, stage,
+                       static_cast<int64_t>(rows), c, static_cast<int64_t>(ld), ntiles, rows_per_chunk, nchunks, 1,
+                       part, nullptr, r0 > 0 ? 1 : 0);
     TPO_LAUNCH_CHECK();
   }
-  const int64_t outs = static_cast<int64_t>(npairs) * kGT * kGT;
-  hipLaunchKernelGGL(k_gram_reduce, dim3(ceil_div(outs, 256)), dim3(256), 0, s, part, nullptr, nchunks, c, ntiles,
+  const int64_t outs = static_cast<int64_t>(npairs) * kNT * kNT;
+  hipLaunchKernelGGL(k_gram_reduce_n, dim3(ceil_div(outs, 256)), dim3(256), 0, s, part, nullptr, nchunks, c, ntiles,
                      bufp<float>(p, ws, B_XS_SCALE), bufp<double>(p, ws, B_C), nullptr);
   TPO_LAUNCH_CHECK();
 }
@@ -1043,7 +1081,8 @@ static void reduce_xcsr(const Plan& p, void* ws, const tpo_inputs* in, hipStream
   float* xp = bufp<float>(p, ws, B_XPRIME);
   double* colsum = bufp<double>(p, ws, B_COLSUM_X);
   xcsr_transpose(p, ws, in->x_rowptr, in->x_col, val, s);
-  xcsr_scales(p, ws, in->x_rowptr, in->x_col, val, s);
+  xcsc_make_chunks(p, ws, s);
+  xcsr_scales(p, ws, s);
   gram_xcsr(p, ws, in, s);
   double* ma = bufp<double>(p, ws, B_MR_A);
   double* mb = bufp<double>(p, ws, B_MR_B);

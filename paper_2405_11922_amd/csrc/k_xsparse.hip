@@ -2,11 +2,12 @@
 // Section 3.2.1 (Eq. Xd) on sparse text rows such as TF-IDF vectors.
 //
 // * Column scales s_j = max_i |x_ij| / 448 (the largest finite E4M3 value),
-//   from the stored entries (a maximum does not depend on order).
-// * FP8 staging: a group of rows is densified into a byte tile of E4M3 codes
-//   of x_ij / s_j (round to nearest even, e4m3_encode), which the FP8 Gram
-//   kernel reads like a dense FP8 X_U.  The dense codes of all rows never
-//   exist at once.
+//   over the columns of the transpose (a maximum does not depend on order);
+//   a column stored twice in a row counts once, with its summed value.
+// * FP8 staging: a group of rows is scattered from the transpose into a
+//   zeroed byte tile of E4M3 codes of x_ij / s_j (round to nearest even,
+//   e4m3_encode), which the FP8 Gram kernel reads like a dense FP8 X_U.  The
+//   dense codes of all rows never exist at once.
 // * Products with the exact FP32 values for the refinement step and the
 //   projection: Y = X B by rows of the CSR (one wave per row, FP64 sums in
 //   the row's stored order), and P = X^T Y by columns of the transpose (CSC,
@@ -19,31 +20,50 @@ namespace tpo {
 
 constexpr int kXChunk = 8192;  // CSC entries per column chunk
 
-// |x_ij| maxima per column (as float bits: non-negative floats order like
-// their bit patterns): each workgroup keeps its maxima in LDS (one wave per
-// row, 64 rows per wave) and adds one global atomic per column it touched.
-constexpr int kColmaxRowsPerWave = 64;
+__global__ void k_fill_u32x(uint32_t* __restrict__ a, int64_t n, uint32_t v) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
 
+__global__ void k_zero_u32x4(uint4* __restrict__ a, int64_t n) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// The value of X at the entry t of the transpose that starts a run of one
+// row (entries of one column stored twice in a row are adjacent, in stored
+// order, and add up): that run's sum in stored order.  False for an entry
+// inside a run (its run's first entry counts it).
+__device__ __forceinline__ bool xcsc_run(const int32_t* __restrict__ rows, const float* __restrict__ cval, int t,
+                                         int cb, int ce, int r, float& v) {
+  if (t > cb && rows[t - 1] == r) return false;
+  v = cval[t];
+  for (int u = t + 1; u < ce && rows[u] == r; ++u) v += cval[u];
+  return true;
+}
+
+// |x_ij| maxima per column (as float bits: non-negative floats order like
+// their bit patterns) from the transpose: one workgroup per column chunk,
+// one global atomic maximum per wave.
 __global__ void __launch_bounds__(256)
-k_xcsr_colmax(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col, const float* __restrict__ val,
-              int n, int64_t nnz, int du, uint32_t* __restrict__ colmax) {
-  __shared__ uint32_t lm[kXMaxDu];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int c = threadIdx.x; c < du; c += blockDim.x) lm[c] = 0u;
-  __syncthreads();
-  const int64_t r0 = (static_cast<int64_t>(blockIdx.x) * 4 + w) * kColmaxRowsPerWave;
-  for (int64_t r = r0; r < min(static_cast<int64_t>(n), r0 + kColmaxRowsPerWave); ++r) {
-    const int64_t b = min(max(rowptr[r], static_cast<int64_t>(0)), nnz);
-    const int64_t e = min(max(rowptr[r + 1], b), nnz);
-    for (int64_t i = b + lane; i < e; i += 64) {
-      const int c = col[i];
-      const float v = fabsf(val[i]);
-      if (c >= 0 && c < du && isfinite(v)) atomicMax(&lm[c], __float_as_uint(v));
+k_xcsc_colmax(const int4* __restrict__ chunk, const int32_t* __restrict__ nchunks, const int32_t* __restrict__ colptr,
+              const int32_t* __restrict__ rows, const float* __restrict__ cval, uint32_t* __restrict__ colmax) {
+  const int nc = *nchunks;
+  for (int c = blockIdx.x; c < nc; c += gridDim.x) {
+    const int4 ch = chunk[c];
+    const int cb = colptr[ch.x], ce = colptr[ch.x + 1];
+    uint32_t m = 0u;
+    for (int t = ch.y + static_cast<int>(threadIdx.x); t < ch.z; t += blockDim.x) {
+      float v;
+      if (xcsc_run(rows, cval, t, cb, ce, rows[t], v)) {
+        v = fabsf(v);
+        if (isfinite(v)) m = max(m, __float_as_uint(v));
+      }
     }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = max(m, static_cast<uint32_t>(__shfl_xor(static_cast<int>(m), o, 64)));
+    if ((threadIdx.x & 63) == 0 && m) atomicMax(&colmax[ch.x], m);
   }
-  __syncthreads();
-  for (int c = threadIdx.x; c < du; c += blockDim.x)
-    if (lm[c]) atomicMax(&colmax[c], lm[c]);
 }
 
 __global__ void k_xcsr_scales(const uint32_t* __restrict__ colmax, int du, float* __restrict__ scale) {
@@ -53,19 +73,19 @@ __global__ void k_xcsr_scales(const uint32_t* __restrict__ colmax, int du, float
   scale[j] = m > 0.0f ? m / 448.0f : 1.0f;
 }
 
-__global__ void k_fill_u32x(uint32_t* __restrict__ a, int64_t n, uint32_t v) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) a[i] = v;
+static unsigned xcsc_grid(const Plan& p) {
+  return static_cast<unsigned>(std::min<int64_t>(std::max<int64_t>(p.xchunks_max, 1), 4096));
 }
 
-void xcsr_scales(const Plan& p, void* ws, const int64_t* rowptr, const int32_t* col, const float* val,
-                 hipStream_t s) {
+void xcsr_scales(const Plan& p, void* ws, hipStream_t s) {
   uint32_t* colmax = bufp<uint32_t>(p, ws, B_XS_COLMAX);
   hipLaunchKernelGGL(k_fill_u32x, dim3(ceil_div(p.du, 256)), dim3(256), 0, s, colmax, static_cast<int64_t>(p.du), 0u);
   TPO_LAUNCH_CHECK();
   if (p.xnnz > 0) {
-    hipLaunchKernelGGL(k_xcsr_colmax, dim3(ceil_div(p.n, 4 * kColmaxRowsPerWave)), dim3(256), 0, s, rowptr, col, val,
-                       p.n, p.xnnz, p.du, colmax);
+    const int32_t* nchunks = reinterpret_cast<const int32_t*>(bufp<int2>(p, ws, B_XT_CINFO) + p.du);
+    hipLaunchKernelGGL(k_xcsc_colmax, dim3(xcsc_grid(p)), dim3(256), 0, s, bufp<int4>(p, ws, B_XT_CHUNK), nchunks,
+                       bufp<int32_t>(p, ws, B_XT_COLPTR), bufp<int32_t>(p, ws, B_XT_ROW), bufp<float>(p, ws, B_XT_VA),
+                       colmax);
     TPO_LAUNCH_CHECK();
   }
   hipLaunchKernelGGL(k_xcsr_scales, dim3(ceil_div(p.du, 256)), dim3(256), 0, s, colmax, p.du,
@@ -73,53 +93,54 @@ void xcsr_scales(const Plan& p, void* ws, const int64_t* rowptr, const int32_t* 
   TPO_LAUNCH_CHECK();
 }
 
-// Rows [r0, r0 + rows) as E4M3 codes of x / s_j into stage (row stride ld, a
-// multiple of 4).  One wave per row: the row's entries are added into an LDS
-// float row at their columns only (a column stored twice in a row adds up),
-// encoded there, and placed in a zeroed LDS byte row, which is then written
-// out as 32-bit words (zero columns encode to 0x00).
+// Rows [r0, r0 + nrows) as E4M3 codes of x / s_j at byte (i - r0) ld + j of
+// the (zeroed) staging tile, from the transpose: one wave per column chunk.
+// Rows ascend within a column, so a chunk's entries of these rows are the
+// ones from its cursor (chunk[c].w, the first entry not yet staged) up to
+// the first row past the group; the cursor then moves there.
 __global__ void __launch_bounds__(256)
-k_xcsr_stage_fp8(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col, const float* __restrict__ val,
-                 const float* __restrict__ scale, int64_t r0, int rows, int64_t nnz, int du, int ld,
-                 uint8_t* __restrict__ stage) {
-  __shared__ float rowbuf[4][kXMaxDu];
-  __shared__ __align__(16) uint32_t bytes[4][kXMaxDu / 4];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int i = blockIdx.x * 4 + w;
-  if (i >= rows) return;
-  float* rb = rowbuf[w];
-  uint32_t* bw = bytes[w];
-  uint8_t* bb = reinterpret_cast<uint8_t*>(bw);
-  for (int c = lane; c < ld / 4; c += 64) bw[c] = 0u;
-  const int64_t r = r0 + i;
-  const int64_t b = min(max(rowptr[r], static_cast<int64_t>(0)), nnz);
-  const int64_t e = min(max(rowptr[r + 1], b), nnz);
-  for (int64_t t = b + lane; t < e; t += 64) {
-    const int c = col[t];
-    if (c >= 0 && c < du) rb[c] = 0.0f;
+k_xcsc_stage_fp8(int4* __restrict__ chunk, const int32_t* __restrict__ nchunks, const int32_t* __restrict__ colptr,
+                 const int32_t* __restrict__ rows, const float* __restrict__ cval, const float* __restrict__ scale,
+                 int64_t r0, int nrows, int ld, uint8_t* __restrict__ stage) {
+  const int lane = threadIdx.x & 63;
+  const int wv = static_cast<int>((static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6);
+  const int nwaves = static_cast<int>((static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6);
+  const int nc = *nchunks;
+  const int64_t r1 = r0 + nrows;
+  for (int c = wv; c < nc; c += nwaves) {
+    const int4 ch = chunk[c];
+    const int cb = colptr[ch.x], ce = colptr[ch.x + 1];
+    const float sc = scale[ch.x];
+    int t0 = ch.w;
+    while (t0 < ch.z) {
+      const int t = t0 + lane;
+      const int r = t < ch.z ? rows[t] : 0;
+      const bool in = t < ch.z && r < r1;
+      float v;
+      if (in && xcsc_run(rows, cval, t, cb, ce, r, v) && isfinite(v))
+        stage[static_cast<int64_t>(r - r0) * ld + ch.x] = e4m3_encode(v / sc);
+      const int cnt = __popcll(__ballot(in));  // the group's entries are a prefix
+      t0 += cnt;
+      if (cnt < 64) break;
+    }
+    if (lane == 0) chunk[c].w = t0;
   }
-  wave_sync();
-  for (int64_t t = b + lane; t < e; t += 64) {
-    const int c = col[t];
-    const float v = val[t];
-    if (c >= 0 && c < du && isfinite(v)) atomicAdd(&rb[c], v);
-  }
-  wave_sync();
-  for (int64_t t = b + lane; t < e; t += 64) {
-    const int c = col[t];
-    if (c >= 0 && c < du) bb[c] = e4m3_encode(rb[c] / scale[c]);
-  }
-  wave_sync();
-  uint32_t* out = reinterpret_cast<uint32_t*>(stage + static_cast<int64_t>(i) * ld);
-  for (int c = lane; c < ld / 4; c += 64) out[c] = bw[c];
 }
 
-void xcsr_stage_fp8(const Plan& p, void* ws, const int64_t* rowptr, const int32_t* col, const float* val,
-                    int64_t r0, int rows, int ld, hipStream_t s) {
+void xcsr_stage_fp8(const Plan& p, void* ws, int64_t r0, int rows, int ld, hipStream_t s) {
   if (rows <= 0) return;
-  hipLaunchKernelGGL(k_xcsr_stage_fp8, dim3(ceil_div(rows, 4)), dim3(256), 0, s, rowptr, col, val,
-                     bufp<float>(p, ws, B_XS_SCALE), r0, rows, p.xnnz, p.du, ld, bufp<uint8_t>(p, ws, B_XS_STAGE));
+  uint8_t* stage = bufp<uint8_t>(p, ws, B_XS_STAGE);
+  const int64_t words = static_cast<int64_t>(rows) * ld / 16;
+  hipLaunchKernelGGL(k_zero_u32x4, dim3(ceil_div(words, 256)), dim3(256), 0, s, reinterpret_cast<uint4*>(stage), words);
   TPO_LAUNCH_CHECK();
+  if (p.xnnz > 0) {
+    const int32_t* nchunks = reinterpret_cast<const int32_t*>(bufp<int2>(p, ws, B_XT_CINFO) + p.du);
+    hipLaunchKernelGGL(k_xcsc_stage_fp8, dim3(ceil_div(xcsc_grid(p), 4)), dim3(256), 0, s,
+                       bufp<int4>(p, ws, B_XT_CHUNK), nchunks, bufp<int32_t>(p, ws, B_XT_COLPTR),
+                       bufp<int32_t>(p, ws, B_XT_ROW), bufp<float>(p, ws, B_XT_VA), bufp<float>(p, ws, B_XS_SCALE),
+                       r0, rows, ld, stage);
+    TPO_LAUNCH_CHECK();
+  }
 }
 
 // Without the reduction (d_u <= 128): X' rows written densely (zero padded
@@ -208,8 +229,8 @@ void xcsr_rowgather(const Plan& p, const int64_t* rowptr, const int32_t* col, co
 }
 
 // Column chunks of the transpose: cinfo[j] = {first chunk, chunk count} and
-// chunk[c] = {column, begin, end, 0}.  One workgroup; thread j takes column
-// j's count, a sequential scan gives the offsets.
+// chunk[c] = {column, begin, end, staging cursor (= begin)}.  One workgroup;
+// thread j takes column j's count, a sequential scan gives the offsets.
 __global__ void __launch_bounds__(1024)
 k_xcsc_chunks(const int32_t* __restrict__ colptr, int du, int4* __restrict__ chunk, int2* __restrict__ cinfo,
               int32_t* __restrict__ nchunks_out) {
@@ -233,7 +254,10 @@ k_xcsc_chunks(const int32_t* __restrict__ colptr, int du, int4* __restrict__ chu
     const int b = colptr[j], e = colptr[j + 1];
     const int nc = (e - b + kXChunk - 1) / kXChunk;
     cinfo[j] = make_int2(cnt[j], nc);
-    for (int q = 0; q < nc; ++q) chunk[cnt[j] + q] = make_int4(j, b + q * kXChunk, min(e, b + (q + 1) * kXChunk), 0);
+    for (int q = 0; q < nc; ++q) {
+      const int qb = b + q * kXChunk;
+      chunk[cnt[j] + q] = make_int4(j, qb, min(e, qb + kXChunk), qb);
+    }
   }
 }
 
@@ -299,14 +323,17 @@ k_xcsc_colsum(const int2* __restrict__ cinfo, const double* __restrict__ cpart, 
   }
 }
 
-void xcsc_colgather(const Plan& p, void* ws, const float* Y, int l, int ldy, double* P, int ldp, double* colsum,
-                    hipStream_t s) {
+void xcsc_make_chunks(const Plan& p, void* ws, hipStream_t s) {
   int32_t* nchunks = reinterpret_cast<int32_t*>(bufp<int2>(p, ws, B_XT_CINFO) + p.du);
   hipLaunchKernelGGL(k_xcsc_chunks, dim3(1), dim3(1024), 0, s, bufp<int32_t>(p, ws, B_XT_COLPTR), p.du,
                      bufp<int4>(p, ws, B_XT_CHUNK), bufp<int2>(p, ws, B_XT_CINFO), nchunks);
   TPO_LAUNCH_CHECK();
-  const unsigned grid = static_cast<unsigned>(std::min<int64_t>(std::max<int64_t>(p.xchunks_max, 1), 4096));
-  hipLaunchKernelGGL(k_xcsc_gather, dim3(grid), dim3(256), 0, s, bufp<int4>(p, ws, B_XT_CHUNK), nchunks,
+}
+
+void xcsc_colgather(const Plan& p, void* ws, const float* Y, int l, int ldy, double* P, int ldp, double* colsum,
+                    hipStream_t s) {
+  const int32_t* nchunks = reinterpret_cast<const int32_t*>(bufp<int2>(p, ws, B_XT_CINFO) + p.du);
+  hipLaunchKernelGGL(k_xcsc_gather, dim3(xcsc_grid(p)), dim3(256), 0, s, bufp<int4>(p, ws, B_XT_CHUNK), nchunks,
                      bufp<int32_t>(p, ws, B_XT_ROW), bufp<float>(p, ws, B_XT_VA), Y, l, ldy,
                      bufp<double>(p, ws, B_XT_CPART));
   TPO_LAUNCH_CHECK();

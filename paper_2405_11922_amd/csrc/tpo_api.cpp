@@ -109,9 +109,11 @@ void build_layout(Plan& p) {
   add(B_HUBLIST_U, 16 * static_cast<size_t>(p.max_chunks_u + 1));
   add(B_HUBLIST_V, 16 * static_cast<size_t>(p.max_chunks_v + 1));
   add(B_PARTIAL, 4 * dp * (maxch + 1));
-  // Gram partials: one 64 x 64 tile per (chunk, upper tile pair)
-  const size_t tx = (du + 63) / 64, tr = (twod + 63) / 64;
-  const size_t gpart_x = p.reduce ? static_cast<size_t>(p.gram_chunks_x) * (tx * (tx + 1) / 2) * 4096 : 0;
+  // Gram partials: one tile per (chunk, upper tile pair); 64 x 64 tiles for
+  // FP32 X and R, 128 x 128 for the narrow types
+  const size_t gt = narrow_gram(p) ? kNarrowTile : 64;
+  const size_t tx = (du + gt - 1) / gt, tr = (twod + 63) / 64;
+  const size_t gpart_x = p.reduce ? static_cast<size_t>(p.gram_chunks_x) * (tx * (tx + 1) / 2) * gt * gt : 0;
   const size_t gpart_r = static_cast<size_t>(p.gram_chunks_r) * (tr * (tr + 1) / 2) * 4096;
   add(B_GRAM_PART, 8 * std::max(gpart_x, gpart_r));
   add(B_COLSUM_PART, 8 * (p.reduce ? static_cast<size_t>(p.gram_chunks_x) * du : 1));
@@ -173,7 +175,7 @@ void build_layout(Plan& p) {
     const bool xs = p.xcsr;
     const bool xr = p.xcsr && p.reduce;
     const size_t nnz = static_cast<size_t>(std::max<int64_t>(p.xnnz, 1));
-    const size_t ldst = (du + 3) / 4 * 4;
+    const size_t ldst = static_cast<size_t>(xcsr_stage_ld(static_cast<int>(du)));
     add(B_XS_SCALE, xs ? 4 * du : 8);
     add(B_XS_COLMAX, xs ? 4 * du : 8);
     add(B_XS_STAGE, xr ? ldst * static_cast<size_t>(p.xstage_rows) : 8);
@@ -499,9 +501,11 @@ tpo_status tpo_plan_create(const tpo_problem* prob, const tpo_params* par, tpo_p
   p->xsort_blocks = static_cast<int>(std::max<int64_t>((p->xnnz + kSortTile - 1) / kSortTile, 1));
   p->xchunks_max = p->xnnz / 8192 + p->du + 1;
   {
-    // FP8 staging tile: row groups of about 128 MiB of codes (64-row multiples)
-    const int64_t ld = (p->du + 3) / 4 * 4;
-    const int64_t g = std::max<int64_t>(64, ((int64_t{128} << 20) / ld) / 64 * 64);
+    // FP8 staging tile: row groups of about 512 MiB of codes (64-row
+    // multiples); each group's Gram launch reads and writes every tile-pair
+    // partial once, so fewer, larger groups cost less of that traffic
+    const int64_t ld = xcsr_stage_ld(p->du);
+    const int64_t g = std::max<int64_t>(64, ((int64_t{512} << 20) / ld) / 64 * 64);
     p->xstage_rows = static_cast<int>(std::min<int64_t>(g, (int64_t{p->n} + 63) / 64 * 64));
   }
   p->rowbits = bits_for(p->n);
@@ -510,19 +514,22 @@ tpo_status tpo_plan_create(const tpo_problem* prob, const tpo_params* par, tpo_p
   const int64_t maxch = 2 * (p->E / kHubChunk) + 2;
   p->max_chunks_u = static_cast<int>(maxch);
   p->max_chunks_v = static_cast<int>(maxch);
-  const int tiles_x = (p->du + 63) / 64, tiles_r = (p->twod + 63) / 64;
+  const int gtx = narrow_gram(*p) ? kNarrowTile : 64;
+  const int tiles_x = (p->du + gtx - 1) / gtx, tiles_r = (p->twod + 63) / 64;
   const int pairs_x = tiles_x * (tiles_x + 1) / 2, pairs_r = tiles_r * (tiles_r + 1) / 2;
-  // row chunks of the Gram partials: about 1024 (chunk, pair) blocks, and a
-  // multiple of 8, at least 8, so that the narrow-type kernels (which give
-  // each XCD whole chunks) keep all eight XCDs busy
-  auto chunks_for = [&](int pairs) {
-    int64_t want = std::max<int64_t>(8, 1024 / pairs);
+  // row chunks of the Gram partials: about `blocks` (chunk, pair) workgroups,
+  // and a multiple of 8, at least 8, so that the narrow-type kernels (which
+  // give each XCD whole chunks) keep all eight XCDs busy
+  auto chunks_for = [&](int pairs, int64_t blocks) {
+    int64_t want = std::max<int64_t>(8, blocks / pairs);
     want = (want + 7) / 8 * 8;
     int64_t by_rows = std::max<int64_t>(1, (p->n + 255) / 256);
     return static_cast<int>(std::min<int64_t>({want, by_rows, 65535}));
   };
-  p->gram_chunks_x = chunks_for(pairs_x);
-  p->gram_chunks_r = chunks_for(pairs_r);
+  // the narrow kernel's 512-thread workgroups run one per CU: about eight
+  // rounds of them over the 256 CUs
+  p->gram_chunks_x = chunks_for(pairs_x, narrow_gram(*p) ? 2048 : 1024);
+  p->gram_chunks_r = chunks_for(pairs_r, 1024);
   // row-pass workgroups (ONMF, features, NCI rounds): two per CU at most;
   // measured against caps of 256, 384, 1024 and 2048 on the 4M- and
   // 150M-edge jobs (fewer blocks write fewer FP64 partials per pass)

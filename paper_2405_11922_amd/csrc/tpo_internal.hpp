@@ -143,6 +143,9 @@ struct Plan {
   DevStatus host_status;  // last status block read back
 };
 
+// the attribute Gram runs on the narrow-type kernel (128 x 128 tile pairs)
+inline bool narrow_gram(const Plan& p) { return p.xbf16 || p.xfp8 || p.xcsr; }
+
 template <typename T>
 inline T* bufp(const Plan& p, void* ws, Buf b) {
   return reinterpret_cast<T*>(static_cast<char*>(ws) + p.lay.off[b]);
@@ -156,15 +159,20 @@ void launch_ingest(const Plan& p, void* ws, const tpo_inputs* in, hipStream_t s)
 // sparse attributes: the transpose (CSC) of X_U into B_XT_* (k_ingest.hip)
 void xcsr_transpose(const Plan& p, void* ws, const int64_t* rowptr, const int32_t* col, const float* val,
                     hipStream_t s);
-// k_xsparse.hip: column scales into B_XS_SCALE; rows [r0, r0 + rows) as E4M3
-// codes into B_XS_STAGE (row stride ld); out = X B (FP64 sums, FP32 out, zero
-// columns lb..wo); P = X^T Y (ldp, or no P when NULL) and the column sums of
-// X from the transpose; dense rows without the reduction.
+// k_xsparse.hip: the column chunks of the transpose (after xcsr_transpose);
+// column scales into B_XS_SCALE; rows [r0, r0 + rows) as E4M3 codes into
+// B_XS_STAGE (row stride ld, groups staged in row order); out = X B (FP64
+// sums, FP32 out, zero columns lb..wo); P = X^T Y (ldp, or no P when NULL)
+// and the column sums of X from the transpose; dense rows without the
+// reduction.
 constexpr int kXMaxDu = 4096;
-void xcsr_scales(const Plan& p, void* ws, const int64_t* rowptr, const int32_t* col, const float* val,
-                 hipStream_t s);
-void xcsr_stage_fp8(const Plan& p, void* ws, const int64_t* rowptr, const int32_t* col, const float* val,
-                    int64_t r0, int rows, int ld, hipStream_t s);
+// row stride (bytes) of the FP8 staging tile of a sparse X_U: 16-byte rows
+inline int xcsr_stage_ld(int du) { return (du + 15) / 16 * 16; }
+// column tile of the narrow-type (BF16, FP8) Gram partials
+constexpr int kNarrowTile = 128;
+void xcsc_make_chunks(const Plan& p, void* ws, hipStream_t s);
+void xcsr_scales(const Plan& p, void* ws, hipStream_t s);
+void xcsr_stage_fp8(const Plan& p, void* ws, int64_t r0, int rows, int ld, hipStream_t s);
 void xcsr_rowgather(const Plan& p, const int64_t* rowptr, const int32_t* col, const float* val, const double* B,
                     int lb, int ldb, float* out, int ldo, int wo, hipStream_t s);
 void xcsc_colgather(const Plan& p, void* ws, const float* Y, int l, int ldy, double* P, int ldp, double* colsum,

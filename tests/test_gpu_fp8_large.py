@@ -7,8 +7,9 @@ The oracle cannot run this job in test time; the device result is checked
 through what holds at any size:
 * the attribute Gram C = X^T X of the FP8 MFMA kernel, entry by entry,
   against an FP64 Gram of the decoded attributes (computed on the GPU with
-  torch): X >= 0, so each entry's FP32 slab sums are within 64 u of the entry
-  itself (u = 2^-24); the column sums of X to FP64 rounding;
+  torch): X >= 0, so each entry's FP32 sums over 256-row blocks are within
+  256 u of the entry itself (u = 2^-24); the column sums of X to FP64
+  rounding (the kernel sums the codes exactly in FP32 groups of 64 rows);
 * Psi_d is orthonormal and X' = X Psi_d on sampled rows;
 * the NCI labels are the oracle's NCI run on the device's Upsilon, and the
   objective is the oracle's objective of the device's labels on the device's R.
@@ -72,9 +73,9 @@ def test_fp8_workload_properties():
         f"{float((diff[nz] > 0).double().mean()):.3f}; mean signed rel err "
         f"{float((diff[nz] / c_ref[nz]).mean()):.2e}")
     err = diff.abs()
-    bound = 64.0 * 2.0 ** -24 * c_ref * 1.01 + 1e-300
+    bound = 256.0 * 2.0 ** -24 * c_ref * 1.01 + 1e-300
     worst = float((err / bound).max())
-    log(f"[fp8 full] Gram: max |C - C_fp64| / (64 u C) = {worst:.3f}, max rel {float((err / c_ref.clamp_min(1e-300)).max()):.2e}")
+    log(f"[fp8 full] Gram: max |C - C_fp64| / (256 u C) = {worst:.3f}, max rel {float((err / c_ref.clamp_min(1e-300)).max()):.2e}")
     assert worst <= 1.0
     e_cs = float(((buf("colsum_x") - cs_ref).abs() / cs_ref.abs().clamp_min(1e-300)).max())
     log(f"[fp8 full] column sums of X: max rel err {e_cs:.2e}")
