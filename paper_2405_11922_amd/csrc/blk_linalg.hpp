@@ -171,6 +171,11 @@ __device__ __forceinline__ void jacobi_pair(int step, int i, int np, int& p, int
 // np - 1) and runs only those: a pair that becomes coupled again later in
 // the sweep waits for the next one.  Stops when no step is marked (or after
 // max_sweeps).  Returns the number of sweeps taken.
+// V may be null: then no eigenvectors are formed, and when rlog is given the
+// rotations of every step run are logged instead (rlog[e * (np / 2) + i] =
+// (c, s) of pair i of the e-th step run, rsteps[e] = that step's index in its
+// sweep, *rcount = steps run), for k_jacobi_replay to apply to other rows:
+// V <- V J is then the same as x <- x J on every row x.
 // sh: scratch of 3 * ((n + 1) / 2) doubles (16-byte aligned); red: unused.
 // Each thread takes kBatches batches of 2 blocks and 4 rows of V:
 // (n / 2)^2 <= 2 kBatches blockDim.x and n^2 / 2 <= 4 kBatches blockDim.x
@@ -178,7 +183,8 @@ __device__ __forceinline__ void jacobi_pair(int step, int i, int np, int& p, int
 
 template <int kBatches = 1>
 __device__ inline int blk_jacobi(double* A, int lda, double* V, int ldv, int n, double* sh, double* red,
-                                 int max_sweeps) {
+                                 int max_sweeps, double2* rlog = nullptr, int* rsteps = nullptr,
+                                 int* rcount = nullptr) {
   (void)red;
   constexpr int kA = 2, kV = 4;  // blocks and rows of V per thread and batch
   constexpr int kAT = kA * kBatches, kVT = kV * kBatches;
@@ -190,10 +196,13 @@ __device__ inline int blk_jacobi(double* A, int lda, double* V, int ldv, int n, 
   int2* pq = reinterpret_cast<int2*>(sh + 2 * npairs);  // (p, q) of pair i; q = -1 off the matrix
   __shared__ int active[kJacobiMaxN];
   __shared__ int any;
-  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
-    const int r = idx / n, c = idx % n;
-    V[r * ldv + c] = (r == c) ? 1.0 : 0.0;
+  if (V) {
+    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+      const int r = idx / n, c = idx % n;
+      V[r * ldv + c] = (r == c) ? 1.0 : 0.0;
+    }
   }
+  int nrun = 0;  // steps run (the rotation log's length)
   // this thread's items, fixed for the whole run: blocks (i, j) of J^T A J
   // and (pair i, row r) items of V J
   int bi[kAT], bj[kAT], vi[kVT], vr[kVT];
@@ -206,7 +215,7 @@ __device__ inline int blk_jacobi(double* A, int lda, double* V, int ldv, int n, 
 #pragma unroll
   for (int k = 0; k < kVT; ++k) {
     const int e = threadIdx.x + k * blockDim.x;
-    vi[k] = e < npairs * n ? e / n : -1;
+    vi[k] = (V && e < npairs * n) ? e / n : -1;
     vr[k] = e < npairs * n ? e - (e / n) * n : 0;
   }
   int sweep = 0;
@@ -246,7 +255,10 @@ __device__ inline int blk_jacobi(double* A, int lda, double* V, int ldv, int n, 
         }
         rot[i] = make_double2(c, s);
         pq[i] = make_int2(p, q < n ? q : -1);
+        if (rlog) rlog[static_cast<int64_t>(nrun) * npairs + i] = make_double2(c, s);
       }
+      if (rlog && threadIdx.x == 0) rsteps[nrun] = step;
+      ++nrun;
       __syncthreads();
       // the items of a step touch disjoint entries, so within a batch every
       // load is issued before any store (the compiler cannot prove that on its own)
@@ -328,9 +340,11 @@ __device__ inline int blk_jacobi(double* A, int lda, double* V, int ldv, int n, 
       __syncthreads();
     }
   }
+  if (rlog && threadIdx.x == 0) *rcount = nrun;
   __syncthreads();
   return sweep;
 }
+
 
 
 

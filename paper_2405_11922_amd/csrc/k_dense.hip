@@ -1458,6 +1458,17 @@ void launch_features(const Plan& p, void* ws, hipStream_t s) {
   }
 }
 
+static JacobiLog jacobi_log(const Plan& p, void* ws) {
+  char* base = bufp<char>(p, ws, B_JLOG);
+  JacobiLog j;
+  j.rot = reinterpret_cast<double2*>(base);
+  int* ints = reinterpret_cast<int*>(base + sizeof(double2) * kJacobiLogSweeps * 127 * 64);
+  j.steps = ints;
+  j.count = ints + kJacobiLogSweeps * 127;
+  j.perm = j.count + 1;
+  return j;
+}
+
 void launch_embed(const Plan& p, void* ws, hipStream_t s) {
   DevStatus* st = bufp<DevStatus>(p, ws, B_STATUS);
   double* K = bufp<double>(p, ws, B_K);
@@ -1479,7 +1490,7 @@ void launch_embed(const Plan& p, void* ws, hipStream_t s) {
       embed_final_wide(m, pm, p.twod, p.kp, p.k, bufp<double>(p, ws, B_RCOLSUM), static_cast<int64_t>(p.n),
                        bufp<double>(p, ws, B_EEVAL), bufp<float>(p, ws, B_S32), bufp<double>(p, ws, B_SIGMA),
                        bufp<double>(p, ws, B_PSI), bufp<double>(p, ws, B_H), bufp<float>(p, ws, B_H32),
-                       bufp<double>(p, ws, B_EK_A), &st->err_bits, s);
+                       jacobi_log(p, ws), &st->err_bits, s);
     return;
   }
   hipLaunchKernelGGL(k_embed_small, dim3(1), dim3(kSmallThreads), 0, s, K, bufp<double>(p, ws, B_OMEGA), p.twod,

@@ -399,15 +399,17 @@ __device__ void apply_linv_t_staged(double* A, int m, int n, const double* Li, i
 }
 
 // The same final step as k_embed_final for k' in 81..128, where the k' x k'
-// eigenproblem and its eigenvectors do not both fit in LDS: the Cholesky
-// factor is inverted in place (one k' x k' array), and the Jacobi keeps its
-// eigenvectors in Vg (global, k' x k') while B B^T stays in LDS; Vg is copied
-// into LDS for the products that follow.
+// eigenproblem and its eigenvectors do not both fit in LDS.  Three launches:
+// (1) the Cholesky factor is inverted in place, M <- M L^-T and P <- K M L^-T
+// in global memory, and the Jacobi runs on B B^T in LDS without
+// eigenvectors, logging its rotations (jlog); (2) k_jacobi_replay applies the
+// logged rotations to the rows of M and P (M V and P V, as V itself would be
+// formed: V = J_1 J_2 ...); (3) the top k columns in eigenvalue order, the
+// sign convention and the FP32 copies.
+// jlog: the rotation log (JacobiLog), then the eigenvalue order.
 __global__ void __launch_bounds__(kLT)
-k_embed_final_wide(double* __restrict__ M, double* __restrict__ P, int twod, int kp, int k,
-                   const double* __restrict__ colsum_r, int64_t n, double* __restrict__ S, float* __restrict__ S32,
-                   double* __restrict__ sigma, double* __restrict__ psi, double* __restrict__ H,
-                   float* __restrict__ H32, double* __restrict__ Vg, int32_t* __restrict__ err_bits) {
+k_embed_wide_eig(double* __restrict__ M, double* __restrict__ P, int twod, int kp, int k,
+                 double* __restrict__ sigma, JacobiLog jlog, int32_t* __restrict__ err_bits) {
   constexpr int kW = 128;
   __shared__ double G[kW * (kW + 1)];
   __shared__ __align__(16) double scr[8 * 256];  // factorisation scratch tiles; staged rows
@@ -416,7 +418,6 @@ k_embed_final_wide(double* __restrict__ M, double* __restrict__ P, int twod, int
   __shared__ __align__(16) double sh[3 * (kW / 2)];
   __shared__ int perm[kW];
   __shared__ double ev[kW];
-  __shared__ double sgn[kW];
   const int nb = (kp + 15) / 16;
   const int ld = 16 * nb + 1;
   // M^T K M in the padded layout (identity on the padding)
@@ -434,7 +435,15 @@ k_embed_final_wide(double* __restrict__ M, double* __restrict__ P, int twod, int
   __syncthreads();
   // L = chol(M^T K M) with L^{-1} in place; P <- B^T = K M L^{-T}; M <- M L^{-T}
   if (!blk_chol_inv16_inplace(G, ld, nb, scr, dinv, &flag)) {
-    if (threadIdx.x == 0) atomicOr(err_bits, 16);
+    // breakdown (flagged): no rotations, the identity order, sigma zero
+    if (threadIdx.x == 0) {
+      atomicOr(err_bits, 16);
+      *jlog.count = 0;
+    }
+    for (int c = threadIdx.x; c < k; c += kLT) {
+      sigma[c] = 0.0;
+      jlog.perm[c] = c;
+    }
     return;
   }
   apply_linv_t_staged(P, twod, kp, G, ld, scr);
@@ -442,25 +451,63 @@ k_embed_final_wide(double* __restrict__ M, double* __restrict__ P, int twod, int
   const int lj = kp | 1;
   mfma_gram_f64(P, kp, P, kp, twod, kp, G, lj, true);  // B B^T
   __syncthreads();
-  blk_jacobi<2>(G, lj, Vg, kp, kp, sh, nullptr, 40);
+  blk_jacobi<2>(G, lj, nullptr, 0, kp, sh, nullptr, kJacobiLogSweeps, jlog.rot, jlog.steps, jlog.count);
   blk_sort_desc(G, lj, kp, ev, perm);
-  for (int c = threadIdx.x; c < k; c += kLT) sigma[c] = sqrt(ev[c] > 0.0 ? ev[c] : 0.0);
-  double* Vs = G;  // the eigenvectors, now in LDS
-  for (int e = threadIdx.x; e < kp * kp; e += kLT) Vs[e] = Vg[e];
-  __syncthreads();
+  for (int c = threadIdx.x; c < k; c += kLT) {
+    sigma[c] = sqrt(ev[c] > 0.0 ? ev[c] : 0.0);
+    jlog.perm[c] = perm[c];
+  }
+}
+
+// Rows [0, rows) of X (leading dimension ldx, n <= 128 columns, global) times
+// the rotations blk_jacobi logged, in the logged order: x <- x J_1 J_2 ...
+// One wave per row, the row staged in LDS; lane i applies pair i of each
+// step (the pairs of a step are disjoint; the wave's LDS accesses are in
+// program order).
+__global__ void __launch_bounds__(256)
+k_jacobi_replay(const double2* __restrict__ rlog, const int* __restrict__ rsteps, const int* __restrict__ rcount,
+                int n, double* __restrict__ X, int rows, int ldx) {
+  __shared__ double xs[4][kJacobiMaxN];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r = blockIdx.x * 4 + w;
+  if (r >= rows) return;  // wave-uniform; no workgroup barrier below
+  double* x = xs[w];
+  for (int c = lane; c < n; c += 64) x[c] = X[static_cast<int64_t>(r) * ldx + c];
+  wave_sync();
+  const int np = n + (n & 1), npairs = np / 2;
+  const int cnt = *rcount;
+  for (int e = 0; e < cnt; ++e) {
+    if (lane < npairs) {
+      int p, q;
+      jacobi_pair(rsteps[e], lane, np, p, q);
+      const double2 cs = rlog[static_cast<int64_t>(e) * npairs + lane];
+      if (q < n && cs.y != 0.0) {
+        const double vp = x[p], vq = x[q];
+        x[p] = cs.x * vp - cs.y * vq;
+        x[q] = cs.y * vp + cs.x * vq;
+      }
+    }
+    wave_sync();
+  }
+  for (int c = lane; c < n; c += 64) X[static_cast<int64_t>(r) * ldx + c] = x[c];
+}
+
+// S = (M V)[:, perm[:k]], psi = (P V)[:, perm[:k]] / sigma, then the sign
+// convention (colsum(Gamma) = colsum(R) S; degenerate -> largest |psi| entry)
+// and the FP32 copies.
+__global__ void __launch_bounds__(kLT)
+k_embed_wide_finish(const double* __restrict__ MV, const double* __restrict__ PV, int twod, int kp, int k,
+                    const double* __restrict__ colsum_r, int64_t n, const int* __restrict__ perm,
+                    double* __restrict__ S, float* __restrict__ S32, const double* __restrict__ sigma,
+                    double* __restrict__ psi, double* __restrict__ H, float* __restrict__ H32) {
+  __shared__ double sgn[128];
   for (int e = threadIdx.x; e < twod * k; e += kLT) {
     const int i = e / k, c = e % k;
-    const int pc = perm[c];
-    double a = 0.0, b = 0.0;
-    for (int t = 0; t < kp; ++t) {
-      a = fma(M[i * kp + t], Vs[t * kp + pc], a);
-      b = fma(P[i * kp + t], Vs[t * kp + pc], b);
-    }
-    S[e] = a;
-    psi[e] = sigma[c] > 0.0 ? b / sigma[c] : 0.0;
+    const int pc = min(max(perm[c], 0), kp - 1);
+    S[e] = MV[i * kp + pc];
+    psi[e] = sigma[c] > 0.0 ? PV[i * kp + pc] / sigma[c] : 0.0;
   }
   __syncthreads();
-  // sign: colsum(Gamma) = colsum(R) S, ||Gamma[:, c]|| = 1
   for (int c = threadIdx.x; c < k; c += kLT) {
     double s = 0.0;
     for (int i = 0; i < twod; ++i) s = fma(colsum_r[i], S[i * k + c], s);
@@ -491,10 +538,18 @@ k_embed_final_wide(double* __restrict__ M, double* __restrict__ P, int twod, int
 }
 
 void embed_final_wide(double* M, double* P, int twod, int kp, int k, const double* colsum_r, int64_t n, double* S,
-                      float* S32, double* sigma, double* psi, double* H, float* H32, double* vg, int32_t* err_bits,
-                      hipStream_t s) {
-  hipLaunchKernelGGL(k_embed_final_wide, dim3(1), dim3(kLT), 0, s, M, P, twod, kp, k, colsum_r, n, S, S32, sigma,
-                     psi, H, H32, vg, err_bits);
+                      float* S32, double* sigma, double* psi, double* H, float* H32, JacobiLog jlog,
+                      int32_t* err_bits, hipStream_t s) {
+  hipLaunchKernelGGL(k_embed_wide_eig, dim3(1), dim3(kLT), 0, s, M, P, twod, kp, k, sigma, jlog, err_bits);
+  TPO_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_jacobi_replay, dim3(ceil_div(twod, 4)), dim3(256), 0, s, jlog.rot, jlog.steps, jlog.count, kp,
+                     M, twod, kp);
+  TPO_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_jacobi_replay, dim3(ceil_div(twod, 4)), dim3(256), 0, s, jlog.rot, jlog.steps, jlog.count, kp,
+                     P, twod, kp);
+  TPO_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_embed_wide_finish, dim3(1), dim3(kLT), 0, s, M, P, twod, kp, k, colsum_r, n, jlog.perm, S, S32,
+                     sigma, psi, H, H32);
   TPO_LAUNCH_CHECK();
 }
 

@@ -149,6 +149,7 @@ void build_layout(Plan& p) {
   add(B_EK_A, 8 * kp * kp);
   add(B_EK_B, 8 * kp * kp);
   add(B_EK_C, 8 * kp * kp);
+  add(B_JLOG, (p.kp > kLdsMaxN && p.kp <= kWideMaxN) ? jacobi_log_bytes() : 8);
   add(B_EEVAL, 8 * twod * kp);
   add(B_S32, 4 * twod * k);
   add(B_GAMMA, 4 * n * k);

@@ -84,7 +84,7 @@ enum Buf {
   // features
   B_G, B_Q, B_QT32, B_R, B_RPART, B_RSUM, B_RCOLSUM,
   // embed
-  B_OMEGA, B_K, B_M_A, B_M_B, B_EK_A, B_EK_B, B_EK_C, B_EEVAL, B_S32,
+  B_OMEGA, B_K, B_M_A, B_M_B, B_EK_A, B_EK_B, B_EK_C, B_JLOG, B_EEVAL, B_S32,
   B_GAMMA, B_SIGMA, B_PSI, B_OMR,
   // onmf
   B_UPS, B_H, B_H32, B_H_NEW, B_RTU, B_UTU, B_A32, B_ONMF_PART,
@@ -208,11 +208,22 @@ void rr_reduce_lds(const double* M, const double* P, int du, int l, int d, int d
 void embed_final_lds(double* M, double* P, int twod, int kp, int k, const double* colsum_r, int64_t n, double* S,
                      float* S32, double* sigma, double* psi, double* H, float* H32, int32_t* err_bits,
                      hipStream_t s);
-// k' in 81..128: the same, with the k' x k' eigenvectors kept in vg (global)
 constexpr int kWideMaxN = 128;
+// k' in 81..128: the same in three steps, the Jacobi's rotations logged in
+// jlog and applied to the rows of M and P afterwards
+constexpr int kJacobiLogSweeps = 40;
+struct JacobiLog {
+  double2* rot;  // kJacobiLogSweeps * 127 steps * 64 pairs
+  int* steps;    // kJacobiLogSweeps * 127
+  int* count;
+  int* perm;     // 128: eigenvalue order
+};
+inline size_t jacobi_log_bytes() {
+  return sizeof(double2) * kJacobiLogSweeps * 127 * 64 + sizeof(int) * (kJacobiLogSweeps * 127 + 1 + 128) + 64;
+}
 void embed_final_wide(double* M, double* P, int twod, int kp, int k, const double* colsum_r, int64_t n, double* S,
-                      float* S32, double* sigma, double* psi, double* H, float* H32, double* vg, int32_t* err_bits,
-                      hipStream_t s);
+                      float* S32, double* sigma, double* psi, double* H, float* H32, JacobiLog jlog,
+                      int32_t* err_bits, hipStream_t s);
 // deterministic two-level sum of nparts rows of length len (k_dense.hip)
 void reduce_parts(const double* part, int nparts, int len, double* tmp, double* out, hipStream_t s);
 // k_cluster.hip
