@@ -464,6 +464,9 @@ def main() -> int:
         "gedge_hop_per_s": round(gedge_hops, 3) if gedge_hops else None,
         "latency_ms": {"p50": round(res["p50"], 4), "p99": round(res["p99"], 4)},
         "stage_ms": {k[3:]: round(v, 4) for k, v in st.items() if k.startswith("ms_")},
+        # NCI rounds run of T_g (a round repeating the previous one's label
+        # sums ends them: the later rounds would repeat it exactly)
+        "nci_rounds": int(st["nci_rounds"]),
         "roofline": spmm_roofline(args.config, shape, st, d_eff),
         "mfma_util": mfma_util(args.config + ("_bf16" if x_dtype == "bf16" else "")),
         "objective": res["obj"][0],
@@ -597,6 +600,7 @@ def main() -> int:
             "gedge_hop_per_s": round(shm.gamma * int(stm["n_unique_edges"]) / (stm["ms_propagate"] * 1e-3) / 1e9, 3),
             "latency_ms": {"p50": round(rm["p50"], 4), "p99": round(rm["p99"], 4)},
             "stage_ms": {k[3:]: round(v, 4) for k, v in stm.items() if k.startswith("ms_")},
+            "nci_rounds": int(stm["nci_rounds"]),
             "roofline": spmm_roofline("mid_fp32", shm, stm, rm["dims"][0]),
             "mfma_util": mfma_util("mid_fp32"),
         }

@@ -175,7 +175,10 @@ typedef struct tpo_stats {
    * within the FP32 error bound are scored again in FP64.  How many, summed
    * over the rounds. */
   int32_t nci_rechecked;
-  int32_t reserved;
+  /* NCI rounds run: T_g, or fewer when the label sums of a round equal those
+   * of the round before (Algorithm 3 then repeats that round's labels and
+   * Phi in every later round, so the rest are skipped on the device). */
+  int32_t nci_rounds;
 } tpo_stats;
 
 typedef struct tpo_plan tpo_plan;

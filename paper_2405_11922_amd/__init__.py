@@ -104,7 +104,7 @@ class TpoStats(C.Structure):
                 ("isolated_u", C.c_int32), ("isolated_v", C.c_int32),
                 ("ms_spmm_v", C.c_double), ("ms_spmm_u", C.c_double),
                 ("n_spmm_v", C.c_int32), ("n_spmm_u", C.c_int32),
-                ("nci_rechecked", C.c_int32), ("reserved", C.c_int32)]
+                ("nci_rechecked", C.c_int32), ("nci_rounds", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -381,15 +381,40 @@ __device__ __forceinline__ int fixed_point_shift(float maxabs, int64_t n) {
   return sft;
 }
 
+// round(v 2^sft) to nearest, ties to even (the value llrint(ldexp(v, sft))
+// has), from the float's bits with integer operations only: v = m 2^e with a
+// 24-bit m, so v 2^sft is m shifted left, or m shifted right with the
+// dropped bits rounded.  Callers keep |v| 2^sft below 2^61.
 __device__ __forceinline__ long long to_fixed(float v, int sft) {
-  return static_cast<long long>(llrint(ldexp(static_cast<double>(v), sft)));
+  const uint32_t b = __float_as_uint(v);
+  const uint32_t ex = (b >> 23) & 0xffu;
+  uint32_t m = b & 0x7fffffu;
+  int e = -149;
+  if (ex != 0) {
+    m |= 0x800000u;
+    e = static_cast<int>(ex) - 150;
+  }
+  const int sh = e + sft;
+  unsigned long long r = 0;
+  if (sh >= 0) {
+    r = static_cast<unsigned long long>(m) << sh;
+  } else if (sh >= -24) {
+    const int s = -sh;
+    const uint32_t q = m >> s, rem = m & ((1u << s) - 1u), half = 1u << (s - 1);
+    r = q + ((rem > half || (rem == half && (q & 1u))) ? 1u : 0u);
+  }
+  return (b >> 31) ? -static_cast<long long>(r) : static_cast<long long>(r);
 }
 
 // Sum of per-block integer partials.  part holds len x nb values (entry o of
 // block b at part[o * nb + b]); one wave per entry.  Integer addition makes
-// the result independent of the order.
+// the result independent of the order.  NCI rounds: nothing when *skip is 0
+// (see nci_skip), and *changed set when a sum differs from the one it
+// replaces.
 __global__ void __launch_bounds__(256)
-k_sum_parts_i64(const long long* __restrict__ part, int nb, int len, long long* __restrict__ sum) {
+k_sum_parts_i64(const long long* __restrict__ part, int nb, int len, long long* __restrict__ sum,
+                const int32_t* __restrict__ skip, int32_t* __restrict__ changed) {
+  if (skip && *skip == 0) return;
   const int o = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (o >= len) return;
@@ -397,12 +422,29 @@ k_sum_parts_i64(const long long* __restrict__ part, int nb, int len, long long* 
   const long long* src = part + static_cast<int64_t>(o) * nb;
   for (int b = lane; b < nb; b += 64) acc += src[b];
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-  if (lane == 0) sum[o] = acc;
+  if (lane == 0) {
+    if (changed && sum[o] != acc) atomicOr(changed, 1);
+    sum[o] = acc;
+  }
 }
 
-static void sum_parts_i64(const long long* part, int nb, int len, long long* sum, hipStream_t s) {
-  hipLaunchKernelGGL(k_sum_parts_i64, dim3(ceil_div(len, 4)), dim3(256), 0, s, part, nb, len, sum);
+static void sum_parts_i64(const long long* part, int nb, int len, long long* sum, hipStream_t s,
+                          const int32_t* skip = nullptr, int32_t* changed = nullptr) {
+  hipLaunchKernelGGL(k_sum_parts_i64, dim3(ceil_div(len, 4)), dim3(256), 0, s, part, nb, len, sum, skip, changed);
   TPO_LAUNCH_CHECK();
+}
+
+// A fixed point of the NCI rounds: round t scores against Phi of the label
+// sums of round t - 1.  When the sums of round t - 1 equal those of round
+// t - 2 (integer sums, compared exactly), Phi and therefore every later
+// round's labels and sums repeat round t - 1's, so rounds t.. are skipped and
+// the result is the one all T_g rounds give.  changed[t - 1] (zeroed before
+// the rounds) is set by round t - 1's sums when they differ from round t -
+// 2's; round t's kernels do nothing when it is 0.  A skipped round leaves
+// its own flag 0, so the rounds after it are skipped too.  Rounds 1 and 2
+// always run (round 1 scores against the identity, not against sums).
+static const int32_t* nci_skip(const int32_t* changed, int t) {
+  return t >= 3 ? changed + (t - 2) : nullptr;
 }
 
 // One round: scores = U Phi (FP64), l* = first argmax, labels written.  Phi
@@ -418,7 +460,9 @@ template <int KT>
 __global__ void __launch_bounds__(256)
 k_nci_round(const float* __restrict__ U, int64_t n, int k, const long long* __restrict__ sums,
             const double* __restrict__ phi_g, long long* __restrict__ part, int32_t* __restrict__ labels,
-            int rows_per_block, const DevStatus* __restrict__ st) {
+            int rows_per_block, DevStatus* __restrict__ st, const int32_t* __restrict__ skip, int round) {
+  if (skip && *skip == 0) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) atomicMax(&st->nci_rounds, round);
   constexpr int LD = KT + 1;  // staging stride (odd for even KT)
   __shared__ double phi[KT * KT];
   __shared__ double fac[KT];
@@ -521,7 +565,9 @@ template <int LT>
 __global__ void __launch_bounds__(512)
 k_nci_score_mfma(const float* __restrict__ U, int64_t n, int k, const long long* __restrict__ sums,
                  const double* __restrict__ phi_g, int32_t* __restrict__ labels, int32_t* __restrict__ check_count,
-                 int32_t* __restrict__ check_rows, const DevStatus* __restrict__ st) {
+                 int32_t* __restrict__ check_rows, const DevStatus* __restrict__ st,
+                 const int32_t* __restrict__ skip) {
+  if (skip && *skip == 0) return;
   constexpr int NL = 16 * LT;
   constexpr int KS = NL / 4;  // k steps of the padded contraction
   __shared__ float phi[NL * NL];  // phi[t * NL + l]
@@ -632,7 +678,9 @@ __global__ void __launch_bounds__(256)
 k_nci_recheck(const float* __restrict__ U, int k, const long long* __restrict__ sums,
               const double* __restrict__ phi_g, const int32_t* __restrict__ check_count,
               const int32_t* __restrict__ check_rows, int32_t* __restrict__ labels, int64_t n,
-              DevStatus* __restrict__ st) {
+              DevStatus* __restrict__ st, const int32_t* __restrict__ skip, int round) {
+  if (skip && *skip == 0) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) atomicMax(&st->nci_rounds, round);
   const int lane = threadIdx.x & 63;
   const int cnt = *check_count;
   if (blockIdx.x == 0 && threadIdx.x == 0 && cnt > 0) atomicAdd(&st->nci_rechecked, cnt);
@@ -689,7 +737,9 @@ constexpr int kNciAccBatch = 8;
 
 __global__ void __launch_bounds__(1024)
 k_nci_accum_wide(const float* __restrict__ U, int64_t n, int k, const int32_t* __restrict__ labels,
-                 long long* __restrict__ part, int64_t rows_per_block, const DevStatus* __restrict__ st) {
+                 long long* __restrict__ part, int64_t rows_per_block, const DevStatus* __restrict__ st,
+                 const int32_t* __restrict__ skip) {
+  if (skip && *skip == 0) return;
   extern __shared__ long long accl[];  // k x k sums, then k counts (dynamic: sized to k)
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int sft = fixed_point_shift(__uint_as_float(st->maxabs_ups_bits), n);
@@ -737,17 +787,17 @@ k_nci_accum_wide(const float* __restrict__ U, int64_t n, int k, const int32_t* _
 template <int LT>
 static void nci_score_mfma(const float* U, int64_t n, int k, const long long* sums, const double* phi_g,
                            int32_t* labels, int32_t* check_count, int32_t* check_rows, DevStatus* st,
-                           hipStream_t s) {
+                           const int32_t* skip, int round, hipStream_t s) {
   constexpr int NL = 16 * LT;
   constexpr size_t lds = static_cast<size_t>(NL) * NL * 4 + NL * 8 + 4;
   const int per_cu = std::max<int>(1, static_cast<int>((160 * 1024) / lds));
   const int64_t ntiles = (n + 15) / 16;
   const int nb = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>((ntiles + 7) / 8, 256 * per_cu)));
   hipLaunchKernelGGL((k_nci_score_mfma<LT>), dim3(nb), dim3(512), 0, s, U, n, k, sums, phi_g, labels, check_count,
-                     check_rows, st);
+                     check_rows, st, skip);
   TPO_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_nci_recheck, dim3(64), dim3(256), 0, s, U, k, sums, phi_g, check_count, check_rows, labels, n,
-                     st);
+                     st, skip, round);
   TPO_LAUNCH_CHECK();
 }
 
@@ -768,7 +818,8 @@ constexpr int kNsMaxIter = 200;
 template <int KW, int NT>
 __global__ void __launch_bounds__(NT)
 k_nci_polar_ns(const long long* __restrict__ sums, int k, int64_t n, const DevStatus* __restrict__ st,
-               double* __restrict__ phi) {
+               double* __restrict__ phi, const int32_t* __restrict__ skip) {
+  if (skip && *skip == 0) return;
   __shared__ double Xa[KW * (KW + 1)];
   __shared__ double Xb[KW * (KW + 1)];
   __shared__ double G[KW * (KW + 1)];
@@ -843,7 +894,9 @@ k_nci_polar_ns(const long long* __restrict__ sums, int k, int64_t n, const DevSt
 template <int KW, int NT, int KB>
 __global__ void __launch_bounds__(NT)
 k_nci_polar(const long long* __restrict__ sums, int k, int64_t n, const DevStatus* __restrict__ st,
-            double* __restrict__ Mg, double* __restrict__ Vg, double* __restrict__ phi) {
+            double* __restrict__ Mg, double* __restrict__ Vg, double* __restrict__ phi,
+            const int32_t* __restrict__ skip) {
+  if (skip && *skip == 0) return;
   __shared__ double A[KW * (KW + 1)];
   __shared__ __align__(16) double sh[3 * (KW / 2)];
   __shared__ double fac[KW];
@@ -904,7 +957,7 @@ k_nci_polar(const long long* __restrict__ sums, int k, int64_t n, const DevStatu
 // Phi for the next round from the label sums: the literal update leaves it to
 // the score kernel (built from `sums`); the Procrustes form computes it here.
 // Jacobi item counts (k > 64): (k/2)^2 <= 2 KB NT and k^2/2 <= 4 KB NT.
-static const double* nci_phi(const Plan& p, void* ws, const long long* sums, hipStream_t s) {
+static const double* nci_phi(const Plan& p, void* ws, const long long* sums, const int32_t* skip, hipStream_t s) {
   // k = 1: every row takes label 0 whatever Phi is
   if (!(p.par.flags & TPO_FLAG_NCI_PROCRUSTES) || p.k == 1) return nullptr;
   double* phi = bufp<double>(p, ws, B_NCI_PHI);
@@ -913,11 +966,12 @@ static const double* nci_phi(const Plan& p, void* ws, const long long* sums, hip
   double* mg = bufp<double>(p, ws, B_NCI_PM);
   double* vg = bufp<double>(p, ws, B_NCI_PV);
   if (p.k <= 32)
-    hipLaunchKernelGGL((k_nci_polar_ns<32, 256>), dim3(1), dim3(256), 0, s, sums, p.k, n, st, phi);
+    hipLaunchKernelGGL((k_nci_polar_ns<32, 256>), dim3(1), dim3(256), 0, s, sums, p.k, n, st, phi, skip);
   else if (p.k <= 64)
-    hipLaunchKernelGGL((k_nci_polar_ns<64, 256>), dim3(1), dim3(256), 0, s, sums, p.k, n, st, phi);
+    hipLaunchKernelGGL((k_nci_polar_ns<64, 256>), dim3(1), dim3(256), 0, s, sums, p.k, n, st, phi, skip);
   else
-    hipLaunchKernelGGL((k_nci_polar<kNciWide, 512, 4>), dim3(1), dim3(512), 0, s, sums, p.k, n, st, mg, vg, phi);
+    hipLaunchKernelGGL((k_nci_polar<kNciWide, 512, 4>), dim3(1), dim3(512), 0, s, sums, p.k, n, st, mg, vg, phi,
+                       skip);
   TPO_LAUNCH_CHECK();
   return phi;
 }
@@ -946,29 +1000,32 @@ static void nci_rounds_wide(const Plan& p, void* ws, hipStream_t s) {
   const float* U = bufp<float>(p, ws, B_UPS);
   int32_t* labels = bufp<int32_t>(p, ws, B_LABELS);
   const int rounds = std::max(p.par.t_g, 1);
-  // recheck lists: one counter per round (zeroed here), one row list
+  // recheck lists: one counter per round, then the rounds' changed flags
+  // (nci_skip), both zeroed here; then one row list
   int32_t* cnt = bufp<int32_t>(p, ws, B_NCI_CHECK);
-  int32_t* rows = cnt + kNciMaxRounds;
-  hipLaunchKernelGGL(k_zero_i32, dim3(ceil_div(kNciMaxRounds, 256)), dim3(256), 0, s, cnt, kNciMaxRounds);
+  int32_t* changed = cnt + kNciMaxRounds;
+  int32_t* rows = changed + kNciMaxRounds;
+  hipLaunchKernelGGL(k_zero_i32, dim3(ceil_div(2 * kNciMaxRounds, 256)), dim3(256), 0, s, cnt, 2 * kNciMaxRounds);
   TPO_LAUNCH_CHECK();
   for (int t = 1; t <= rounds; ++t) {
+    const int32_t* skip = nci_skip(changed, t);
     const long long* sm = t == 1 ? nullptr : sums;
-    const double* ph = t == 1 ? nullptr : nci_phi(p, ws, sums, s);
+    const double* ph = t == 1 ? nullptr : nci_phi(p, ws, sums, skip, s);
     if (ph) sm = nullptr;
-    int32_t* c = cnt + (t - 1) % kNciMaxRounds;
+    int32_t* c = cnt + (t - 1);
     switch ((k + 15) / 16) {
-      case 3: nci_score_mfma<3>(U, n, k, sm, ph, labels, c, rows, st, s); break;
-      case 4: nci_score_mfma<4>(U, n, k, sm, ph, labels, c, rows, st, s); break;
-      case 5: nci_score_mfma<5>(U, n, k, sm, ph, labels, c, rows, st, s); break;
-      case 6: nci_score_mfma<6>(U, n, k, sm, ph, labels, c, rows, st, s); break;
-      case 7: nci_score_mfma<7>(U, n, k, sm, ph, labels, c, rows, st, s); break;
-      case 8: nci_score_mfma<8>(U, n, k, sm, ph, labels, c, rows, st, s); break;
+      case 3: nci_score_mfma<3>(U, n, k, sm, ph, labels, c, rows, st, skip, t, s); break;
+      case 4: nci_score_mfma<4>(U, n, k, sm, ph, labels, c, rows, st, skip, t, s); break;
+      case 5: nci_score_mfma<5>(U, n, k, sm, ph, labels, c, rows, st, skip, t, s); break;
+      case 6: nci_score_mfma<6>(U, n, k, sm, ph, labels, c, rows, st, skip, t, s); break;
+      case 7: nci_score_mfma<7>(U, n, k, sm, ph, labels, c, rows, st, skip, t, s); break;
+      case 8: nci_score_mfma<8>(U, n, k, sm, ph, labels, c, rows, st, skip, t, s); break;
       default: throw std::runtime_error("NCI: k outside 33..128 on the two-kernel path");
     }
     if (t < p.par.t_g) {
-      hipLaunchKernelGGL(k_nci_accum_wide, dim3(nb), dim3(1024), acc_lds, s, U, n, k, labels, part, rpb, st);
+      hipLaunchKernelGGL(k_nci_accum_wide, dim3(nb), dim3(1024), acc_lds, s, U, n, k, labels, part, rpb, st, skip);
       TPO_LAUNCH_CHECK();
-      sum_parts_i64(part, nb, k * k + k, sums, s);
+      sum_parts_i64(part, nb, k * k + k, sums, s, skip, t >= 2 ? changed + (t - 1) : nullptr);
     }
   }
 }
@@ -984,15 +1041,19 @@ static void nci_rounds(const Plan& p, void* ws, hipStream_t s) {
   const float* U = bufp<float>(p, ws, B_UPS);
   int32_t* labels = bufp<int32_t>(p, ws, B_LABELS);
   const int rounds = std::max(p.par.t_g, 1);
+  int32_t* changed = bufp<int32_t>(p, ws, B_NCI_CHECK) + kNciMaxRounds;  // see nci_skip
+  hipLaunchKernelGGL(k_zero_i32, dim3(ceil_div(kNciMaxRounds, 256)), dim3(256), 0, s, changed, kNciMaxRounds);
+  TPO_LAUNCH_CHECK();
   for (int t = 1; t <= rounds; ++t) {
     // round 1 (and T_g = 0) scores against Phi = I; every round but the last
     // feeds the label sums to the next
     const bool acc = t < p.par.t_g;
-    const double* ph = t == 1 ? nullptr : nci_phi(p, ws, sums, s);
+    const int32_t* skip = nci_skip(changed, t);
+    const double* ph = t == 1 ? nullptr : nci_phi(p, ws, sums, skip, s);
     hipLaunchKernelGGL((k_nci_round<KT>), dim3(nb), dim3(256), 0, s, U, static_cast<int64_t>(p.n), k,
-                       (t == 1 || ph) ? nullptr : sums, ph, acc ? part : nullptr, labels, rpb, st);
+                       (t == 1 || ph) ? nullptr : sums, ph, acc ? part : nullptr, labels, rpb, st, skip, t);
     TPO_LAUNCH_CHECK();
-    if (acc) sum_parts_i64(part, nb, k * k + k, sums, s);
+    if (acc) sum_parts_i64(part, nb, k * k + k, sums, s, skip, t >= 2 ? changed + (t - 1) : nullptr);
   }
 }
 

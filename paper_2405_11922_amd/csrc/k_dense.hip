@@ -1129,7 +1129,7 @@ static void reduce_xcsr(const Plan& p, void* ws, const tpo_inputs* in, hipStream
   }
   if (p.lr <= kLdsMaxN) {
     rr_reduce_lds(m, pm, p.du, p.lr, p.d, p.dp, colsum, static_cast<int64_t>(p.n), bufp<double>(p, ws, B_EVAL),
-                  bufp<double>(p, ws, B_PSI_D), bufp<float>(p, ws, B_PSI_D32), s);
+                  bufp<double>(p, ws, B_PSI_D), bufp<float>(p, ws, B_PSI_D32), jacobi_log(p, ws), s);
   } else {
     hipLaunchKernelGGL(k_reduce_rr, dim3(1), dim3(kSmallThreads), 0, s, m, pm, p.du, p.lr, p.d, p.dp, colsum,
                        static_cast<int64_t>(p.n), bufp<double>(p, ws, B_SMALL_B), bufp<double>(p, ws, B_SMALL_C),
@@ -1183,7 +1183,7 @@ void launch_reduce(const Plan& p, void* ws, const tpo_inputs* in, hipStream_t s)
     subspace_iterate(C, p.du, bufp<double>(p, ws, B_OMR), p.lr, p.par.q + 1, ma, mb, bufp<double>(p, ws, B_SI_GRAM),
                      bufp<double>(p, ws, B_SI_PART), bufp<unsigned>(p, ws, B_SI_BAR), m, pm, &st->err_bits, s);
     rr_reduce_lds(m, pm, p.du, p.lr, p.d, p.dp, colsum, static_cast<int64_t>(p.n), bufp<double>(p, ws, B_EVAL),
-                  bufp<double>(p, ws, B_PSI_D), bufp<float>(p, ws, B_PSI_D32), s);
+                  bufp<double>(p, ws, B_PSI_D), bufp<float>(p, ws, B_PSI_D32), jacobi_log(p, ws), s);
   } else {
     double* gs = bufp<double>(p, ws, B_SMALL_A);
     TPO_HIP_CHECK(hipMemcpyAsync(ma, bufp<double>(p, ws, B_OMR), sizeof(double) * p.du * p.lr,
@@ -1458,13 +1458,22 @@ void launch_features(const Plan& p, void* ws, hipStream_t s) {
   }
 }
 
-static JacobiLog jacobi_log(const Plan& p, void* ws) {
+int jacobi_log_n(const Plan& p) {
+  int n = 0;
+  if (p.reduce && p.lr <= kLdsMaxN) n = p.lr;
+  if (p.kp > kLdsMaxN && p.kp <= kWideMaxN) n = std::max(n, p.kp);
+  return n;
+}
+
+JacobiLog jacobi_log(const Plan& p, void* ws) {
+  const int n = jacobi_log_n(p);
+  const int np = n + (n & 1);
   char* base = bufp<char>(p, ws, B_JLOG);
   JacobiLog j;
   j.rot = reinterpret_cast<double2*>(base);
-  int* ints = reinterpret_cast<int*>(base + sizeof(double2) * kJacobiLogSweeps * 127 * 64);
+  int* ints = reinterpret_cast<int*>(base + sizeof(double2) * jacobi_log_steps(n) * (np / 2 > 0 ? np / 2 : 1));
   j.steps = ints;
-  j.count = ints + kJacobiLogSweeps * 127;
+  j.count = ints + jacobi_log_steps(n);
   j.perm = j.count + 1;
   return j;
 }

@@ -189,20 +189,66 @@ __device__ void lds_eig(double* A, double* V, int n, double* sh, double* red, in
   blk_sort_desc(A, n, n, ev, perm);
 }
 
+// Rows [0, rows) of X (leading dimension ldx, n <= 128 columns, global) times
+// the rotations blk_jacobi logged, in the logged order: x <- x J_1 J_2 ...
+// One wave per row, the row staged in LDS; lane i applies pair i of each
+// step (the pairs of a step are disjoint; the wave's LDS accesses are in
+// program order).
+__global__ void __launch_bounds__(256)
+k_jacobi_replay(const double2* __restrict__ rlog, const int* __restrict__ rsteps, const int* __restrict__ rcount,
+                int n, double* __restrict__ X, int rows, int ldx) {
+  __shared__ double xs[4][kJacobiMaxN];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r = blockIdx.x * 4 + w;
+  if (r >= rows) return;  // wave-uniform; no workgroup barrier below
+  double* x = xs[w];
+  for (int c = lane; c < n; c += 64) x[c] = X[static_cast<int64_t>(r) * ldx + c];
+  wave_sync();
+  const int np = n + (n & 1), npairs = np / 2;
+  const int cnt = *rcount;
+  // eight steps' rotations are loaded before they are applied
+  constexpr int kB = 8;
+  for (int e0 = 0; e0 < cnt; e0 += kB) {
+    double2 cs[kB];
+    int st[kB];
+#pragma unroll
+    for (int b = 0; b < kB; ++b) {
+      const bool ok = e0 + b < cnt && lane < npairs;
+      st[b] = e0 + b < cnt ? rsteps[e0 + b] : 0;
+      cs[b] = ok ? rlog[static_cast<int64_t>(e0 + b) * npairs + lane] : make_double2(1.0, 0.0);
+    }
+#pragma unroll
+    for (int b = 0; b < kB; ++b) {
+      if (lane < npairs && cs[b].y != 0.0) {
+        int p, q;
+        jacobi_pair(st[b], lane, np, p, q);
+        if (q < n) {
+          const double vp = x[p], vq = x[q];
+          x[p] = cs[b].x * vp - cs[b].y * vq;
+          x[q] = cs[b].y * vp + cs[b].x * vq;
+        }
+      }
+      wave_sync();
+    }
+  }
+  for (int c = lane; c < n; c += 64) X[static_cast<int64_t>(r) * ldx + c] = x[c];
+}
+
 // Rayleigh-Ritz of the reduction: T = M^T P (P = C M), eigenpairs, top d:
 // Psi_d = M V_d, sigma_d = sqrt(lambda); sign convention on X' = X Psi_d.
+// Three launches: the Jacobi on T in LDS without eigenvectors, logging its
+// rotations (jlog; the raw eigenvalues in decreasing order go to evals);
+// k_jacobi_replay applies them to the rows of M (M V, as V itself would be
+// formed); the top d columns of M V in eigenvalue order, the sign convention
+// and the FP32 copy.
 __global__ void __launch_bounds__(kLT)
-k_rr_reduce(const double* __restrict__ M, const double* __restrict__ P, int du, int l, int d, int dp,
-            const double* __restrict__ colsum_x, int64_t n, double* __restrict__ evals, double* __restrict__ psi,
-            float* __restrict__ psi32) {
+k_rr_eig(const double* __restrict__ M, const double* __restrict__ P, int du, int l, double* __restrict__ evals,
+         JacobiLog jlog) {
   __shared__ double T[kLdsN * (kLdsN + 1)];
-  __shared__ double V[kLdsN * (kLdsN + 1)];
-  __shared__ double sa[kLdsN * kLdsN];  // rows of M in stages
   __shared__ __align__(16) double sh[3 * 40 + 8];
   __shared__ int perm[kLdsN];
   __shared__ double ev[kLdsN];
-  __shared__ double sgn[kLdsN];
-  const int lt = l | 1;  // odd leading dimension of T and V: column walks spread over the LDS banks
+  const int lt = l | 1;  // odd leading dimension of T: column walks spread over the LDS banks
   mfma_gram_f64(M, l, P, l, du, l, T, lt, false);
   for (int e = threadIdx.x; e < l * l; e += kLT) {
     const int i = e / l, j = e % l;
@@ -213,27 +259,27 @@ k_rr_reduce(const double* __restrict__ M, const double* __restrict__ P, int du, 
     }
   }
   __syncthreads();
-  blk_jacobi(T, lt, V, lt, l, sh, nullptr, 40);
+  blk_jacobi(T, lt, nullptr, 0, l, sh, nullptr, kJacobiLogSweeps, jlog.rot, jlog.steps, jlog.count);
   blk_sort_desc(T, lt, l, ev, perm);
-  // psi = M V[:, perm[:d]] (rows of M streamed through sa, as many as fit)
-  const int stage = (kLdsN * kLdsN) / l;
-  for (int r0 = 0; r0 < du; r0 += stage) {
-    for (int e = threadIdx.x; e < stage * l; e += kLT) {
-      const int rr = e / l, c = e - (e / l) * l;
-      sa[e] = (r0 + rr < du) ? M[(r0 + rr) * l + c] : 0.0;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < stage * d; e += kLT) {
-      const int rr = e / d, c = e - (e / d) * d;
-      if (r0 + rr < du) {
-        const int pc = perm[c];
-        double s = 0.0;
-        for (int t = 0; t < l; ++t) s = fma(sa[rr * l + t], V[t * lt + pc], s);
-        psi[(r0 + rr) * d + c] = s;
-      }
-    }
-    __syncthreads();
+  for (int c = threadIdx.x; c < l; c += kLT) {
+    evals[c] = ev[c];
+    jlog.perm[c] = perm[c];
   }
+}
+
+// psi = (M V)[:, perm[:d]] from the replayed rows of M; evals[c] <- sigma_c.
+__global__ void __launch_bounds__(kLT)
+k_rr_finish(const double* __restrict__ MV, int du, int l, int d, int dp, const double* __restrict__ colsum_x,
+            int64_t n, const int* __restrict__ perm, double* __restrict__ evals, double* __restrict__ psi,
+            float* __restrict__ psi32) {
+  __shared__ double ev[kLdsN];
+  __shared__ double sgn[kLdsN];
+  for (int c = threadIdx.x; c < d; c += kLT) ev[c] = evals[c];
+  for (int e = threadIdx.x; e < du * d; e += kLT) {
+    const int i = e / d, c = e - (e / d) * d;
+    psi[e] = MV[static_cast<int64_t>(i) * l + min(max(perm[c], 0), l - 1)];
+  }
+  __syncthreads();
   // sign: colsum(X') = colsum(X) Psi_d; degenerate -> largest |Psi_d| entry
   // (the first one on a tie).  One wave per column.
   {
@@ -282,6 +328,18 @@ k_rr_reduce(const double* __restrict__ M, const double* __restrict__ P, int du, 
       psi32[e] = 0.0f;
     }
   }
+}
+
+void rr_reduce_lds(double* M, const double* P, int du, int l, int d, int dp, const double* colsum_x, int64_t n,
+                   double* evals, double* psi, float* psi32, JacobiLog jlog, hipStream_t s) {
+  hipLaunchKernelGGL(k_rr_eig, dim3(1), dim3(kLT), 0, s, M, P, du, l, evals, jlog);
+  TPO_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_jacobi_replay, dim3(ceil_div(du, 4)), dim3(256), 0, s, jlog.rot, jlog.steps, jlog.count, l, M,
+                     du, l);
+  TPO_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_rr_finish, dim3(1), dim3(kLT), 0, s, M, du, l, d, dp, colsum_x, n, jlog.perm, evals, psi,
+                     psi32);
+  TPO_LAUNCH_CHECK();
 }
 
 // Final step of RandomizedSVD(R, k) on K = R^T R with P = K M given:
@@ -375,11 +433,6 @@ void cholqr_lds(double* A, int m, int n, int lda, int32_t* err_bits, hipStream_t
   TPO_LAUNCH_CHECK();
 }
 
-void rr_reduce_lds(const double* M, const double* P, int du, int l, int d, int dp, const double* colsum_x, int64_t n,
-                   double* evals, double* psi, float* psi32, hipStream_t s) {
-  hipLaunchKernelGGL(k_rr_reduce, dim3(1), dim3(kLT), 0, s, M, P, du, l, d, dp, colsum_x, n, evals, psi, psi32);
-  TPO_LAUNCH_CHECK();
-}
 
 // A (m x n, row-major, global) <- A Li^T with Li lower in LDS (ld), in
 // stages of 16 rows copied to st (16 n doubles of LDS) first.
@@ -459,38 +512,7 @@ k_embed_wide_eig(double* __restrict__ M, double* __restrict__ P, int twod, int k
   }
 }
 
-// Rows [0, rows) of X (leading dimension ldx, n <= 128 columns, global) times
-// the rotations blk_jacobi logged, in the logged order: x <- x J_1 J_2 ...
-// One wave per row, the row staged in LDS; lane i applies pair i of each
-// step (the pairs of a step are disjoint; the wave's LDS accesses are in
-// program order).
-__global__ void __launch_bounds__(256)
-k_jacobi_replay(const double2* __restrict__ rlog, const int* __restrict__ rsteps, const int* __restrict__ rcount,
-                int n, double* __restrict__ X, int rows, int ldx) {
-  __shared__ double xs[4][kJacobiMaxN];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int r = blockIdx.x * 4 + w;
-  if (r >= rows) return;  // wave-uniform; no workgroup barrier below
-  double* x = xs[w];
-  for (int c = lane; c < n; c += 64) x[c] = X[static_cast<int64_t>(r) * ldx + c];
-  wave_sync();
-  const int np = n + (n & 1), npairs = np / 2;
-  const int cnt = *rcount;
-  for (int e = 0; e < cnt; ++e) {
-    if (lane < npairs) {
-      int p, q;
-      jacobi_pair(rsteps[e], lane, np, p, q);
-      const double2 cs = rlog[static_cast<int64_t>(e) * npairs + lane];
-      if (q < n && cs.y != 0.0) {
-        const double vp = x[p], vq = x[q];
-        x[p] = cs.x * vp - cs.y * vq;
-        x[q] = cs.y * vp + cs.x * vq;
-      }
-    }
-    wave_sync();
-  }
-  for (int c = lane; c < n; c += 64) X[static_cast<int64_t>(r) * ldx + c] = x[c];
-}
+
 
 // S = (M V)[:, perm[:k]], psi = (P V)[:, perm[:k]] / sigma, then the sign
 // convention (colsum(Gamma) = colsum(R) S; degenerate -> largest |psi| entry)

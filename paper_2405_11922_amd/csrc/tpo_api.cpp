@@ -149,7 +149,7 @@ void build_layout(Plan& p) {
   add(B_EK_A, 8 * kp * kp);
   add(B_EK_B, 8 * kp * kp);
   add(B_EK_C, 8 * kp * kp);
-  add(B_JLOG, (p.kp > kLdsMaxN && p.kp <= kWideMaxN) ? jacobi_log_bytes() : 8);
+  add(B_JLOG, jacobi_log_n(p) > 0 ? jacobi_log_bytes(jacobi_log_n(p)) : 8);
   add(B_EEVAL, 8 * twod * kp);
   add(B_S32, 4 * twod * k);
   add(B_GAMMA, 4 * n * k);
@@ -170,7 +170,7 @@ void build_layout(Plan& p) {
   add(B_NCI_PHI, 8 * k * k);
   add(B_NCI_PM, 8 * k * k);
   add(B_NCI_PV, 8 * k * k);
-  add(B_NCI_CHECK, 4 * (1024 + n));  // per-round recheck counters, then a row list
+  add(B_NCI_CHECK, 4 * (2048 + n));  // per-round recheck counters and changed flags, then a row list
   {
     // sparse attributes (TPO_X_CSR)
     const bool xs = p.xcsr;
@@ -414,6 +414,7 @@ tpo_status tpo::execute_plan(tpo_plan* plan, const tpo_inputs* in, void* ws, siz
   plan->stats.isolated_u = host.iso_u;
   plan->stats.isolated_v = host.iso_v;
   plan->stats.nci_rechecked = host.nci_rechecked;
+  plan->stats.nci_rounds = host.nci_rounds;
   if (out->objective) {
     out->objective[0] = host.objective[0];
     out->objective[1] = host.objective[1];

@@ -47,7 +47,7 @@ struct DevStatus {
   uint32_t maxabs_ups_bits;// max |Upsilon| as float bits
   double objective[2];
   int32_t nci_rechecked;   // NCI rows scored again in FP64
-  int32_t pad;
+  int32_t nci_rounds;      // the last NCI round run (later ones repeat it)
 };
 
 // The ingested graph's part of the status block, kept in the workspace
@@ -146,6 +146,28 @@ struct Plan {
 // the attribute Gram runs on the narrow-type kernel (128 x 128 tile pairs)
 inline bool narrow_gram(const Plan& p) { return p.xbf16 || p.xfp8 || p.xcsr; }
 
+// The rotation log of the Jacobi eigensolvers that run without eigenvectors
+// (the reduction's Rayleigh-Ritz for l <= 80, the embedding finish for k' in
+// 81..128): the (c, s) of every pair of every step run, the steps' indices,
+// their count, then the eigenvalue order.
+constexpr int kJacobiLogSweeps = 40;
+struct JacobiLog {
+  double2* rot;
+  int* steps;
+  int* count;
+  int* perm;  // 128
+};
+int jacobi_log_n(const Plan& p);  // the largest order logged (0: none)
+inline size_t jacobi_log_steps(int n) {
+  const int np = n + (n & 1);
+  return static_cast<size_t>(kJacobiLogSweeps) * static_cast<size_t>(np > 1 ? np - 1 : 1);
+}
+inline size_t jacobi_log_bytes(int n) {
+  const int np = n + (n & 1);
+  return sizeof(double2) * jacobi_log_steps(n) * static_cast<size_t>(np / 2 > 0 ? np / 2 : 1) +
+         sizeof(int) * (jacobi_log_steps(n) + 1 + 128) + 64;
+}
+
 template <typename T>
 inline T* bufp(const Plan& p, void* ws, Buf b) {
   return reinterpret_cast<T*>(static_cast<char*>(ws) + p.lay.off[b]);
@@ -203,24 +225,15 @@ void subspace_iterate(const double* A, int N, const double* omega, int l, int n_
                       hipStream_t s);
 size_t subspace_part_doubles(int N, int l);
 size_t subspace_gsum_doubles(int l);
-void rr_reduce_lds(const double* M, const double* P, int du, int l, int d, int dp, const double* colsum_x,
-                   int64_t n, double* evals, double* psi, float* psi32, hipStream_t s);
+void rr_reduce_lds(double* M, const double* P, int du, int l, int d, int dp, const double* colsum_x, int64_t n,
+                   double* evals, double* psi, float* psi32, JacobiLog jlog, hipStream_t s);
+JacobiLog jacobi_log(const Plan& p, void* ws);
 void embed_final_lds(double* M, double* P, int twod, int kp, int k, const double* colsum_r, int64_t n, double* S,
                      float* S32, double* sigma, double* psi, double* H, float* H32, int32_t* err_bits,
                      hipStream_t s);
 constexpr int kWideMaxN = 128;
 // k' in 81..128: the same in three steps, the Jacobi's rotations logged in
 // jlog and applied to the rows of M and P afterwards
-constexpr int kJacobiLogSweeps = 40;
-struct JacobiLog {
-  double2* rot;  // kJacobiLogSweeps * 127 steps * 64 pairs
-  int* steps;    // kJacobiLogSweeps * 127
-  int* count;
-  int* perm;     // 128: eigenvalue order
-};
-inline size_t jacobi_log_bytes() {
-  return sizeof(double2) * kJacobiLogSweeps * 127 * 64 + sizeof(int) * (kJacobiLogSweeps * 127 + 1 + 128) + 64;
-}
 void embed_final_wide(double* M, double* P, int twod, int kp, int k, const double* colsum_r, int64_t n, double* S,
                       float* S32, double* sigma, double* psi, double* H, float* H32, JacobiLog jlog,
                       int32_t* err_bits, hipStream_t s);

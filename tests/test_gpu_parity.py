@@ -315,6 +315,28 @@ def test_near_tie_input_decisions():
     assert np.array_equal(whole["labels"], out["labels"])
 
 
+@pytest.mark.parametrize("name,nci", [("reduce_small", "literal"), ("k100", "literal"), ("k100", "procrustes"),
+                                      ("k128", "literal")])
+def test_nci_fixed_point_skip(name, nci):
+    """When a round's label sums equal the previous round's, Algorithm 3
+    repeats that round in every later one, so the device skips the rest of
+    the rounds.  Checked: the rounds run are reported, and with 20 and with
+    200 rounds the labels and the objective are bit-identical whenever the
+    fixed point came before round 20 (the 20-round labels are the oracle's in
+    the stage parity cases)."""
+    make, kw = CASES[name]
+    abg = make()
+    a = gpu_run(abg, **{**kw, "t_g": 20}, nci=nci, stages=False)
+    b = gpu_run(abg, **{**kw, "t_g": 200}, nci=nci, stages=False)
+    ra, rb = a["stats"]["nci_rounds"], b["stats"]["nci_rounds"]
+    log(f"[{name} {nci}] NCI rounds run: {ra} of 20, {rb} of 200")
+    assert 1 <= ra <= 20 and 1 <= rb <= 200
+    if ra < 20:
+        assert rb == ra
+        assert np.array_equal(a["labels"], b["labels"])
+        assert a["objective"] == b["objective"]
+
+
 @pytest.mark.parametrize("nci", ["literal", "procrustes"])
 def test_full_size_mid_fp32(nci):
     """The benchmarked workload at its full size (200,000 x 400,000, 4M edges,
