@@ -164,28 +164,66 @@ k_radix_upsweep(const uint64_t* __restrict__ keys, int64_t n_static, const int32
   hist[static_cast<int64_t>(t) * nb + blockIdx.x] = cnt[t];
 }
 
+// One tile's keys in digit order: ranked as the tile is read (iteration r,
+// then wave, then lane order among equal digits, so the sort stays stable),
+// placed in LDS at their position within the tile's digit-ordered sequence,
+// then written out in that order: consecutive threads write consecutive
+// addresses of one digit's run instead of scattering one key per lane.
 __global__ void __launch_bounds__(kSortThreads)
 k_radix_downsweep(const uint64_t* __restrict__ keys, const float* __restrict__ vals, int64_t n_static,
                   const int32_t* n_dev, int shift, const uint32_t* __restrict__ hist_scan, int nb,
                   uint64_t* __restrict__ okeys, float* __restrict__ ovals) {
-  __shared__ uint32_t goff[256];
+  constexpr int NW = kSortThreads / 64;
+  __shared__ uint32_t goff[256];  // global start of each digit for this tile
+  __shared__ uint32_t loff[256];  // start of each digit within the tile's order
   __shared__ uint32_t tile_cnt[256];
-  __shared__ uint32_t wcnt[kSortThreads / 64][256];
-  __shared__ uint32_t wpre[kSortThreads / 64][256];
+  __shared__ uint32_t wcnt[NW][256];
+  __shared__ uint32_t wpre[NW][256];
+  __shared__ uint32_t wsum[NW];
+  __shared__ uint64_t skeys[kSortTile];
+  __shared__ float svals[kSortTile];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  goff[t] = hist_scan[static_cast<int64_t>(t) * nb + blockIdx.x];
-  tile_cnt[t] = 0;
-  for (int i = 0; i < kSortThreads / 64; ++i) wcnt[i][t] = 0;
-  __syncthreads();
   const int64_t n = sort_count(n_static, n_dev);
   const int64_t base = static_cast<int64_t>(blockIdx.x) * kSortTile;
-  const uint64_t lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+  const int nvalid = static_cast<int>(max(static_cast<int64_t>(0), min(static_cast<int64_t>(kSortTile), n - base)));
+  uint64_t key[kSortItems];
+  float val[kSortItems];
+#pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
-    const int64_t idx = base + static_cast<int64_t>(r) * kSortThreads + t;
-    const bool valid = idx < n;
-    uint64_t key = valid ? keys[idx] : 0ull;
-    float val = (valid && vals) ? vals[idx] : 0.0f;
-    const uint32_t d = static_cast<uint32_t>((key >> shift) & 255u);
+    const int li = r * kSortThreads + t;
+    key[r] = li < nvalid ? keys[base + li] : 0ull;
+    val[r] = (li < nvalid && vals) ? vals[base + li] : 0.0f;
+  }
+  goff[t] = hist_scan[static_cast<int64_t>(t) * nb + blockIdx.x];
+  tile_cnt[t] = 0;
+  for (int i = 0; i < NW; ++i) wcnt[i][t] = 0;
+  __syncthreads();
+  // the tile's digit counts, then their exclusive scan (loff)
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r)
+    if (r * kSortThreads + t < nvalid) atomicAdd(&tile_cnt[static_cast<uint32_t>((key[r] >> shift) & 255u)], 1u);
+  __syncthreads();
+  {
+    const uint32_t c = tile_cnt[t];
+    uint32_t v = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(v, o, 64);
+      if (lane >= o) v += y;
+    }
+    if (lane == 63) wsum[w] = v;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int i = 0; i < w; ++i) before += wsum[i];
+    loff[t] = before + v - c;
+    tile_cnt[t] = 0;
+  }
+  __syncthreads();
+  const uint64_t lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const bool valid = r * kSortThreads + t < nvalid;
+    const uint32_t d = static_cast<uint32_t>((key[r] >> shift) & 255u);
     uint64_t peers = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
@@ -198,8 +236,8 @@ k_radix_downsweep(const uint64_t* __restrict__ keys, const float* __restrict__ v
     __syncthreads();
     {
       uint32_t run = tile_cnt[t];
-      for (int i = 0; i < kSortThreads / 64; ++i) {
-        uint32_t c = wcnt[i][t];
+      for (int i = 0; i < NW; ++i) {
+        const uint32_t c = wcnt[i][t];
         wpre[i][t] = run;
         run += c;
         wcnt[i][t] = 0;
@@ -208,18 +246,34 @@ k_radix_downsweep(const uint64_t* __restrict__ keys, const float* __restrict__ v
     }
     __syncthreads();
     if (valid) {
-      const uint32_t pos = goff[d] + wpre[w][d] + rank;
-      okeys[pos] = key;
-      if (vals) ovals[pos] = val;
+      const uint32_t lp = loff[d] + wpre[w][d] + rank;
+      skeys[lp] = key[r];
+      if (vals) svals[lp] = val[r];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const int j = r * kSortThreads + t;
+    if (j < nvalid) {
+      const uint64_t k = skeys[j];
+      const uint32_t d = static_cast<uint32_t>((k >> shift) & 255u);
+      const uint32_t pos = goff[d] + static_cast<uint32_t>(j) - loff[d];
+      okeys[pos] = k;
+      if (vals) ovals[pos] = svals[j];
     }
   }
 }
 
-// Sort keys[0..n) on bits [lo, hi) (stable); result ends in keys (ping-pong
-// through keys_alt), values follow when vals != nullptr.  nb tiles of
-// kSortTile keys; hist holds 256 nb counters, aux the scan's block sums.
-static void radix_sort_nb(int nb, uint32_t* hist, uint32_t* aux, uint64_t* keys, uint64_t* keys_alt, float* vals,
-                          float* vals_alt, int64_t n_static, const int32_t* n_dev, int lo, int hi, hipStream_t s) {
+// Sort keys[0..n) on bits [lo, hi) (stable), ping-pong through keys_alt;
+// values follow when vals != nullptr.  The result ends in keys (copied back
+// after an odd number of passes), or, with copy_back false, wherever the last
+// pass left it: the return value says whether that is keys_alt / vals_alt.
+// nb tiles of kSortTile keys; hist holds 256 nb counters, aux the scan's
+// block sums.
+static bool radix_sort_nb(int nb, uint32_t* hist, uint32_t* aux, uint64_t* keys, uint64_t* keys_alt, float* vals,
+                          float* vals_alt, int64_t n_static, const int32_t* n_dev, int lo, int hi, hipStream_t s,
+                          bool copy_back = true) {
   uint64_t* src = keys;
   uint64_t* dst = keys_alt;
   float* vsrc = vals;
@@ -237,6 +291,7 @@ static void radix_sort_nb(int nb, uint32_t* hist, uint32_t* aux, uint64_t* keys,
     std::swap(vsrc, vdst);
     ++passes;
   }
+  if ((passes & 1) && !copy_back) return true;
   if (passes & 1) {
     TPO_HIP_CHECK(hipMemcpyAsync(keys, src, static_cast<size_t>(n_static) * sizeof(uint64_t),
                                  hipMemcpyDeviceToDevice, s));
@@ -244,13 +299,14 @@ static void radix_sort_nb(int nb, uint32_t* hist, uint32_t* aux, uint64_t* keys,
       TPO_HIP_CHECK(hipMemcpyAsync(vals, vsrc, static_cast<size_t>(n_static) * sizeof(float),
                                    hipMemcpyDeviceToDevice, s));
   }
+  return false;
 }
 
-static void radix_sort(const Plan& p, void* ws, uint64_t* keys, uint64_t* keys_alt, float* vals,
+static bool radix_sort(const Plan& p, void* ws, uint64_t* keys, uint64_t* keys_alt, float* vals,
                        float* vals_alt, int64_t n_static, const int32_t* n_dev, int lo, int hi,
-                       hipStream_t s) {
-  radix_sort_nb(p.sort_blocks, bufp<uint32_t>(p, ws, B_HIST), bufp<uint32_t>(p, ws, B_SCAN_AUX), keys, keys_alt,
-                vals, vals_alt, n_static, n_dev, lo, hi, s);
+                       hipStream_t s, bool copy_back = true) {
+  return radix_sort_nb(p.sort_blocks, bufp<uint32_t>(p, ws, B_HIST), bufp<uint32_t>(p, ws, B_SCAN_AUX), keys,
+                       keys_alt, vals, vals_alt, n_static, n_dev, lo, hi, s, copy_back);
 }
 
 // ---------------------------------------------------------------------------
@@ -336,8 +392,16 @@ __global__ void k_degrees(const int32_t* __restrict__ rowptr, const float* __res
   }
   double s = static_cast<double>(e - b);
   if (st_ro->has_vals) {
+    // a row of at most 64 entries is summed by its own lane in stored order;
+    // a longer one by the whole wave (strided partial sums, then a tree)
     double mine = 0.0;
-    for (int j = 0; j < 64 && row0 + j < nrows; ++j) {
+    const bool serial = live && e - b <= 64;
+    if (serial)
+      for (int i = b; i < e; ++i) mine += static_cast<double>(val[i]);
+    uint64_t longs = __ballot(live && !serial);
+    while (longs) {
+      const int j = __ffsll(static_cast<unsigned long long>(longs)) - 1;
+      longs &= longs - 1;
       const int bj = __shfl(b, j, 64), ej = __shfl(e, j, 64);
       double t = 0.0;
       for (int i = bj + lane; i < ej; i += 64) t += static_cast<double>(val[i]);
@@ -434,12 +498,16 @@ void launch_ingest(const Plan& p, void* ws, const tpo_inputs* in, hipStream_t s)
     hipLaunchKernelGGL(k_rowptr, dim3(ceil_div(E + 1, 256)), dim3(256), 0, s, kb, E, &st->n_unique, 0, rowmask,
                        p.n, rowptr_u);
     TPO_LAUNCH_CHECK();
-    // B_U^T: stable sort on the column bits only keeps rows ascending per column
-    radix_sort(p, ws, kb, ka, wb, wa, E, &st->n_unique, p.rowbits, p.rowbits + p.colbits, s);
-    hipLaunchKernelGGL(k_rowptr, dim3(ceil_div(E + 1, 256)), dim3(256), 0, s, kb, E, &st->n_unique, p.rowbits,
+    // B_U^T: stable sort on the column bits only keeps rows ascending per
+    // column; read from whichever buffers the last pass wrote
+    const bool alt = radix_sort(p, ws, kb, ka, wb, wa, E, &st->n_unique, p.rowbits, p.rowbits + p.colbits, s,
+                                false);
+    const uint64_t* tk = alt ? ka : kb;
+    const float* tw = alt ? wa : wb;
+    hipLaunchKernelGGL(k_rowptr, dim3(ceil_div(E + 1, 256)), dim3(256), 0, s, tk, E, &st->n_unique, p.rowbits,
                        colmask, p.m, rowptr_v);
     TPO_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_extract_cols, dim3(ceil_div(E, 256)), dim3(256), 0, s, kb, wb, &st->n_unique, p.rowbits,
+    hipLaunchKernelGGL(k_extract_cols, dim3(ceil_div(E, 256)), dim3(256), 0, s, tk, tw, &st->n_unique, p.rowbits,
                        col_v, val_v, E);
     TPO_LAUNCH_CHECK();
   } else {
