@@ -179,8 +179,8 @@ typedef unsigned int v4u_t __attribute__((ext_vector_type(4)));
 // kNFlush u times the sum of its products' magnitudes (u = 2^-24).
 //
 // A workgroup of 8 waves owns one 128 x 128 tile pair (ti <= tj) of the Gram
-// over one row chunk.  Each slab (128 bytes of every column: 64 BF16 rows or
-// 128 FP8 rows) of both column tiles is staged transposed in LDS (one
+// over one row chunk.  Each slab (256 bytes of every column: 128 BF16 rows or
+// 256 FP8 rows) of both column tiles is staged transposed in LDS (one
 // column's slab contiguous, stride kNColLd bytes), double-buffered, with the
 // next slab's global loads in flight in registers.  Wave w computes the
 // 64 x 32 block (rows 64 (w / 4) .., columns 32 (w % 4) ..) as 4 x 2 MFMA
@@ -196,7 +196,7 @@ typedef unsigned int v4u_t __attribute__((ext_vector_type(4)));
 // other pairs from its L2.  vec: X 16-byte aligned and the row stride a
 // multiple of 16 bytes (16-byte loads); otherwise element loads.
 constexpr int kNT = 128;                  // column tile
-constexpr int kNColB = 128;               // staged bytes of one column per slab
+constexpr int kNColB = 256;               // staged bytes of one column per slab
 constexpr int kNColLd = kNColB + 16;      // LDS stride of a staged column
 constexpr int kNOpBytes = kNT * kNColLd;  // one staged operand
 constexpr int kNFlush = 256;              // rows per FP32 block
@@ -228,7 +228,9 @@ k_gram_narrow(const uint8_t* __restrict__ X, int64_t n, int c, int64_t ldx, int 
   constexpr int ES = FMT == 1 ? 2 : 1;  // bytes per element
   constexpr int SR = kNColB / ES;       // rows per slab
   constexpr int EPG = 16 / ES;          // elements per 16-byte group
-  constexpr int RG = SR / 4;            // 4-row groups per slab
+  constexpr int HR = 8;                 // rows a staging thread moves
+  constexpr int RG = SR / HR;           // row groups per slab
+  constexpr int KS = FMT == 1 ? SR / 32 : SR / 128;  // MFMA k steps per slab
   constexpr int FLUSH_SLABS = kNFlush / SR;
   __shared__ __align__(16) uint8_t lds[2 * 2 * kNOpBytes];  // [buffer][operand]
   const int npairs = ntiles * (ntiles + 1) / 2;
@@ -254,18 +256,18 @@ k_gram_narrow(const uint8_t* __restrict__ X, int64_t n, int c, int64_t ldx, int 
   const int nslabs = r_end > r_beg ? static_cast<int>((r_end - r_beg + SR - 1) / SR) : 0;
 
   // staging: threads 0..255 stage column tile ti, 256..511 tile tj (idle on a
-  // diagonal tile); thread (rg, cg) moves rows 4 rg .. 4 rg + 3 of the
+  // diagonal tile); thread (rg, cg) moves rows 8 rg .. 8 rg + 7 of the
   // 16-byte column group cg (consecutive lanes take consecutive row groups, so
   // the transposed LDS stores of one instruction fall in distinct banks)
   const int op = tid >> 8, sb = tid & 255;
   const bool loader = !(diag && op == 1);
   const int rg = sb % RG, cg = sb / RG;
   const int gcol = (op ? tj : ti) * kNT + cg * EPG;  // first column of the group
-  uint32_t pre[4][4];  // rows 4 rg + h, 16 bytes each
-  auto fetch = [&](int64_t r0, uint32_t (&pf)[4][4]) {
+  uint32_t pre[HR][4];  // rows HR rg + h, 16 bytes each
+  auto fetch = [&](int64_t r0, uint32_t (&pf)[HR][4]) {
 #pragma unroll
-    for (int h = 0; h < 4; ++h) {
-      const int64_t row = r0 + 4 * rg + h;
+    for (int h = 0; h < HR; ++h) {
+      const int64_t row = r0 + HR * rg + h;
 #pragma unroll
       for (int d = 0; d < 4; ++d) pf[h][d] = 0u;
       if (!loader || row >= r_end || gcol >= c) continue;
@@ -285,30 +287,33 @@ k_gram_narrow(const uint8_t* __restrict__ X, int64_t n, int c, int64_t ldx, int 
       }
     }
   };
-  auto store = [&](int buf, const uint32_t (&ps)[4][4]) {
+  auto store = [&](int buf, const uint32_t (&ps)[HR][4]) {
     if (!loader) return;
     uint8_t* base = lds + (2 * buf + op) * kNOpBytes;
     if constexpr (FMT == 1) {
-      // column 2 d + e: rows 0, 1 (low word) and 2, 3 (high word)
+      // column 2 d + e: word p holds rows 2 p (low half) and 2 p + 1
 #pragma unroll
       for (int d = 0; d < 4; ++d)
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
           const uint32_t sel = e ? 0x07060302u : 0x05040100u;
-          uint2 v;
-          v.x = __builtin_amdgcn_perm(ps[1][d], ps[0][d], sel);
-          v.y = __builtin_amdgcn_perm(ps[3][d], ps[2][d], sel);
-          *reinterpret_cast<uint2*>(base + (cg * EPG + 2 * d + e) * kNColLd + 8 * rg) = v;
+          v4u_t v;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) v[q] = __builtin_amdgcn_perm(ps[2 * q + 1][d], ps[2 * q][d], sel);
+          *reinterpret_cast<v4u_t*>(base + (cg * EPG + 2 * d + e) * kNColLd + 16 * rg) = v;
         }
     } else {
+      // column 4 d + e: rows 0..3 from one 4 x 4 transpose, rows 4..7 from another
 #pragma unroll
       for (int d = 0; d < 4; ++d) {
-        const uint32_t in[4] = {ps[0][d], ps[1][d], ps[2][d], ps[3][d]};
-        uint32_t out[4];
-        transpose4x4(in, out);
+        const uint32_t lo_in[4] = {ps[0][d], ps[1][d], ps[2][d], ps[3][d]};
+        const uint32_t hi_in[4] = {ps[4][d], ps[5][d], ps[6][d], ps[7][d]};
+        uint32_t lo[4], hi[4];
+        transpose4x4(lo_in, lo);
+        transpose4x4(hi_in, hi);
 #pragma unroll
         for (int e = 0; e < 4; ++e)
-          *reinterpret_cast<uint32_t*>(base + (cg * EPG + 4 * d + e) * kNColLd + 4 * rg) = out[e];
+          *reinterpret_cast<uint2*>(base + (cg * EPG + 4 * d + e) * kNColLd + 8 * rg) = make_uint2(lo[e], hi[e]);
       }
     }
   };
@@ -330,7 +335,7 @@ k_gram_narrow(const uint8_t* __restrict__ X, int64_t n, int c, int64_t ldx, int 
     const uint8_t* lb = diag ? la : la + kNOpBytes;
     if constexpr (FMT == 1) {
 #pragma unroll
-      for (int ks = 0; ks < 2; ++ks) {
+      for (int ks = 0; ks < KS; ++ks) {
         const int off = 64 * ks + 16 * kq;
         v8bf_t av[4], bv[2];
 #pragma unroll
@@ -346,28 +351,32 @@ k_gram_narrow(const uint8_t* __restrict__ X, int64_t n, int c, int64_t ldx, int 
             s32[m][mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], bv[mb], s32[m][mb], 0, 0, 0);
       }
     } else {
-      const int off = 32 * kq;
-      v8i_t av[4], bv[2];
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const v4u_t lo = *reinterpret_cast<const v4u_t*>(la + (a_col + 16 * m) * kNColLd + off);
-        const v4u_t hi = *reinterpret_cast<const v4u_t*>(la + (a_col + 16 * m) * kNColLd + off + 16);
-        av[m] = v8i_t{static_cast<int>(lo[0]), static_cast<int>(lo[1]), static_cast<int>(lo[2]), static_cast<int>(lo[3]),
-                      static_cast<int>(hi[0]), static_cast<int>(hi[1]), static_cast<int>(hi[2]), static_cast<int>(hi[3])};
+      for (int ks = 0; ks < KS; ++ks) {
+        const int off = 128 * ks + 32 * kq;
+        v8i_t av[4], bv[2];
+  #pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const v4u_t lo = *reinterpret_cast<const v4u_t*>(la + (a_col + 16 * m) * kNColLd + off);
+          const v4u_t hi = *reinterpret_cast<const v4u_t*>(la + (a_col + 16 * m) * kNColLd + off + 16);
+          av[m] = v8i_t{static_cast<int>(lo[0]), static_cast<int>(lo[1]), static_cast<int>(lo[2]), static_cast<int>(lo[3]),
+                        static_cast<int>(hi[0]), static_cast<int>(hi[1]), static_cast<int>(hi[2]), static_cast<int>(hi[3])};
+        }
+  #pragma unroll
+        for (int mb = 0; mb < 2; ++mb) {
+          const v4u_t lo = *reinterpret_cast<const v4u_t*>(lb + (b_col + 16 * mb) * kNColLd + off);
+          const v4u_t hi = *reinterpret_cast<const v4u_t*>(lb + (b_col + 16 * mb) * kNColLd + off + 16);
+          bv[mb] = v8i_t{static_cast<int>(lo[0]), static_cast<int>(lo[1]), static_cast<int>(lo[2]), static_cast<int>(lo[3]),
+                         static_cast<int>(hi[0]), static_cast<int>(hi[1]), static_cast<int>(hi[2]), static_cast<int>(hi[3])};
+        }
+        // formats 0 (E4M3) for both operands; block scales 127 (2^0)
+  #pragma unroll
+        for (int m = 0; m < 4; ++m)
+  #pragma unroll
+          for (int mb = 0; mb < 2; ++mb)
+            s32[m][mb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(av[m], bv[mb], s32[m][mb], 0, 0, 0, 127,
+                                                                          0, 127);
       }
-#pragma unroll
-      for (int mb = 0; mb < 2; ++mb) {
-        const v4u_t lo = *reinterpret_cast<const v4u_t*>(lb + (b_col + 16 * mb) * kNColLd + off);
-        const v4u_t hi = *reinterpret_cast<const v4u_t*>(lb + (b_col + 16 * mb) * kNColLd + off + 16);
-        bv[mb] = v8i_t{static_cast<int>(lo[0]), static_cast<int>(lo[1]), static_cast<int>(lo[2]), static_cast<int>(lo[3]),
-                       static_cast<int>(hi[0]), static_cast<int>(hi[1]), static_cast<int>(hi[2]), static_cast<int>(hi[3])};
-      }
-      // formats 0 (E4M3) for both operands; block scales 127 (2^0)
-#pragma unroll
-      for (int m = 0; m < 4; ++m)
-#pragma unroll
-        for (int mb = 0; mb < 2; ++mb)
-          s32[m][mb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(av[m], bv[mb], s32[m][mb], 0, 0, 0, 127, 0, 127);
     }
   };
   // column sums of the staged slab: BF16 in FP32 groups of 8 rows, E4M3 in
@@ -377,7 +386,7 @@ k_gram_narrow(const uint8_t* __restrict__ X, int64_t n, int c, int64_t ldx, int 
     const uint8_t* col = lds + (2 * buf) * kNOpBytes + (64 * qb + lane) * kNColLd;
     if constexpr (FMT == 1) {
 #pragma unroll
-      for (int g = 0; g < 8; ++g) {
+      for (int g = 0; g < SR / 8; ++g) {
         const v4u_t v = *reinterpret_cast<const v4u_t*>(col + 16 * g);
         float s = 0.0f;
 #pragma unroll
@@ -386,7 +395,7 @@ k_gram_narrow(const uint8_t* __restrict__ X, int64_t n, int c, int64_t ldx, int 
       }
     } else {
 #pragma unroll
-      for (int hgrp = 0; hgrp < 2; ++hgrp) {
+      for (int hgrp = 0; hgrp < SR / 64; ++hgrp) {
         float s = 0.0f;
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
