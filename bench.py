@@ -353,7 +353,8 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="large")
+    ap.add_argument("--config", default="large",
+                    help="large (default), mid_fp32, fp8_tfidf, cpu_scale, serve, or copy (one 256 MiB device copy, the kernel of known traffic that scales the hardware byte counters)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-baseline", default="on", choices=["on", "off"])
     ap.add_argument("--serve-jobs", type=int, default=2000)
@@ -370,9 +371,6 @@ def main() -> int:
                          "'vs plain FP32 GPU') and report how far the results differ")
     ap.add_argument("--mid", default="on", choices=["on", "off"],
                     help="with --config large, also time the mid-size FP32 workload (reported under 'mid')")
-    ap.add_argument("--calibrate-copy", action="store_true",
-                    help="also copy a 256 MiB buffer once (a kernel of known traffic, to scale "
-                         "hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -419,13 +417,6 @@ def main() -> int:
         del x_f32
         x_f32 = None
         inp["x"] = None
-
-    if args.calibrate_copy:
-        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
 
     res = time_jobs(args, inp, x, x_dtype, dev, args.steps, args.warmup)
     st = res["stats"]
