@@ -7,6 +7,7 @@
 // update (Eq. update-Q).  Sums grouped by cluster label (NCI's Phi = Ups^T Y
 // and the cluster sums of R in the objective) use 64-bit fixed point so that
 // their result does not depend on the order of the atomic additions.
+#include <algorithm>
 #include <mutex>
 
 #include "blk_linalg.hpp"
@@ -31,90 +32,140 @@ typedef double v4d_t __attribute__((ext_vector_type(4)));
 //   kProject: O = R S            (Gamma; also written as Upsilon)
 //   kOnmf:    P = R H, Q = U A,  O = U * sqrt(P / Q)   (Eq. update-Y; a zero
 //             denominator keeps U, a negative ratio gives 0)
-// Every wave first forms all its P and Q tiles in registers; after a barrier
-// O replaces U in the same LDS slab, so one slab buffer serves both.  Then the
-// waves accumulate the tiles of R^T O (2d x k) and O^T O (k x k) in FP32
-// registers over the workgroup's rows; the totals are written as FP64
-// partials.  S (or H) and A stay in LDS for the whole pass when they fit.
+// Which contraction index an MFMA's four depth slots stand for is free as
+// long as both operands agree: the j-th of four consecutive MFMAs gives slot
+// q the index 16 m + 4 q + j, so a lane's four A values are adjacent in a row
+// of the slab and its four B values adjacent in a row of S^T (or A^T), and
+// each comes in with one 16-byte LDS read.  A wave reads its slab rows once
+// for all its output tiles.  Every wave first forms all its P and Q tiles in
+// registers; after a barrier O replaces U in the same LDS slab, so one slab
+// buffer serves both.  Then the waves accumulate R^T O (2d x k) and the upper
+// triangle of the symmetric O^T O (k x k), tiles dealt round-robin from one
+// list, in FP32 registers over the workgroup's rows; the totals are written as
+// FP64 partials (both halves of O^T O).  S^T (or H^T) and A^T stay in LDS for
+// the whole pass when they fit.
 constexpr int kRpRows = 64;
 // Waves per workgroup: eight for k in 65..128 with 2d <= 128, where a
 // workgroup of four could run only one wave per SIMD (S and A fill the LDS);
 // four otherwise (two or more such workgroups share a CU, and for 2d = 256
 // with k > 64 the registers would not fit two waves a SIMD).
 __host__ __device__ constexpr int rp_waves(int jt, int kt) { return (kt >= 5 && jt * kt <= 64) ? 8 : 4; }
+// Waves per SIMD the registers must allow: two, except where a workgroup of
+// four carries 2d = 256 and k > 64.
+__host__ __device__ constexpr int rp_occupancy(int jt, int kt) { return jt * kt > 64 ? 1 : 2; }
 
 template <int MODE, int JT, int KT>
-__global__ void __launch_bounds__(64 * rp_waves(JT, KT))
+__global__ void __launch_bounds__(64 * rp_waves(JT, KT)) __attribute__((amdgpu_waves_per_eu(rp_occupancy(JT, KT))))
 k_rowpass_mfma(const float* __restrict__ R, int64_t n, int twod, int k, const float* __restrict__ Sm,
                const float* __restrict__ A32, float* __restrict__ U, float* __restrict__ out,
                float* __restrict__ out2, int rows_per_block, double* __restrict__ part,
                DevStatus* __restrict__ st) {
   constexpr int kRpWaves = rp_waves(JT, KT), kRpThreads = 64 * kRpWaves;
   constexpr int TD = 16 * JT, KP = 16 * KT;
-  constexpr int RS = TD + 4, OS = KP + 4;
-  constexpr int NQ = (JT * KT + kRpWaves - 1) / kRpWaves, NQ2 = (KT * KT + kRpWaves - 1) / kRpWaves;
+  // row strides of the slabs and of S^T, A^T: 4 floats past a multiple of 16,
+  // so the 16-byte reads of 8 consecutive lanes fall in distinct banks
+  constexpr int RS = TD + 4, OS = KP + 4, SS = TD + 4, AS = KP + 4;
+  // tiles of R^T O and of the upper triangle of O^T O, each list dealt
+  // round-robin over the waves
+  constexpr int NT1 = JT * KT, NT2 = KT * (KT + 1) / 2;
+  constexpr int NQ1 = (NT1 + kRpWaves - 1) / kRpWaves, NQ2 = (NT2 + kRpWaves - 1) / kRpWaves, NQ = NQ1 + NQ2;
   constexpr int LDS_CAP = 156 * 1024;
-  // LDS: the R slab (ROWS x RS), the U/O slab (ROWS x OS), S (TD x OS) and,
-  // for kOnmf, A (KP x OS) when they fit; slabs of 64 rows, or 32 when 64
+  // LDS: the R slab (ROWS x RS), the U/O slab (ROWS x OS), S^T (KP x SS) and,
+  // for kOnmf, A^T (KP x AS) when they fit; slabs of 64 rows, or 32 when 64
   // would not fit.  Operands that do not fit are read from global memory.
-  constexpr bool SLDS = TD * OS * 4 <= 72 * 1024;
-  constexpr int SFIX = SLDS ? TD * OS : 0;
-  constexpr bool ALDS = MODE == kOnmf && 4 * ((kRpRows / 2) * (RS + OS) + SFIX + KP * OS) <= LDS_CAP;
-  constexpr int FIXED = SFIX + (ALDS ? KP * OS : 0);
-  constexpr int ROWS = 4 * (kRpRows * (RS + OS) + FIXED) <= LDS_CAP ? kRpRows : kRpRows / 2;
+  constexpr bool SLDS = KP * SS * 4 <= 72 * 1024;
+  constexpr int SFIX = SLDS ? KP * SS : 0;
+  constexpr bool ALDS = MODE == kOnmf && 4 * ((kRpRows / 2) * (RS + OS) + SFIX + KP * AS) <= LDS_CAP;
+  constexpr int FIXED = SFIX + (ALDS ? KP * AS : 0);
+  // (64-row slabs also only where their prefetch keeps to 32 values of R a
+  // thread, and in eight-wave kernels, capped at 256 registers, to 24 of R
+  // and U together)
+  constexpr bool R64 = 4 * (kRpRows * (RS + OS) + FIXED) <= LDS_CAP && kRpRows * TD / kRpThreads <= 32 &&
+                       (kRpWaves < 8 || kRpRows * (TD + KP) / kRpThreads <= 24);
+  constexpr int ROWS = R64 ? kRpRows : kRpRows / 2;
   constexpr int RTILES = ROWS / 16, WPR = kRpWaves / RTILES;  // waves per row tile
   constexpr int KTW = (KT + WPR - 1) / WPR;                    // column tiles per wave
-  constexpr int RPT = ROWS * TD / kRpThreads, UPT = ROWS * KP / kRpThreads;  // prefetched per thread
-  __shared__ float Rt[ROWS * RS];
-  __shared__ float Ut[ROWS * OS];
-  __shared__ float Ss[SLDS ? TD * OS : 1];  // S (or H), TD x KP, zero padded
-  __shared__ float As[ALDS ? KP * OS : 1];  // A (kOnmf), KP x KP, zero padded
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  // slab prefetch: thread tid loads column tid % TD (of U: tid % KP) of
+  // slab rows tid / TD + RSTEP u (tid / KP + USTEP u), RPT (UPT) values
+  constexpr int RSTEP = kRpThreads / TD, USTEP = kRpThreads / KP;
+  constexpr int RPT = ROWS / RSTEP, UPT = (ROWS + USTEP - 1) / USTEP;
+  __shared__ __align__(16) float Rt[ROWS * RS];
+  __shared__ __align__(16) float Ut[ROWS * OS];
+  __shared__ __align__(16) float Ss[SLDS ? KP * SS : 4];  // S^T (or H^T): Ss[c * SS + r] = S[r][c], zero padded
+  __shared__ __align__(16) float As[ALDS ? KP * AS : 4];  // A^T (kOnmf): As[c * AS + t] = A[t][c], zero padded
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int i16 = lane & 15, kq = lane >> 4;
   if (SLDS)
     for (int e = tid; e < TD * KP; e += kRpThreads) {
       const int r = e / KP, c = e - (e / KP) * KP;
-      Ss[r * OS + c] = (r < twod && c < k) ? Sm[r * k + c] : 0.0f;
+      Ss[c * SS + r] = (r < twod && c < k) ? Sm[r * k + c] : 0.0f;
     }
   if (ALDS)
     for (int e = tid; e < KP * KP; e += kRpThreads) {
       const int r = e / KP, c = e - (e / KP) * KP;
-      As[r * OS + c] = (r < k && c < k) ? A32[r * k + c] : 0.0f;
+      As[c * AS + r] = (r < k && c < k) ? A32[r * k + c] : 0.0f;
     }
-  auto s_op = [&](int r, int c) -> float {
-    if (SLDS) return Ss[r * OS + c];
-    return (r < twod && c < k) ? Sm[r * k + c] : 0.0f;
+  // B operands of the P and Q tiles: contraction indices 16 m + 4 kq + (0..3)
+  // of output column 16 kt + i16
+  auto s_frag = [&](int m, int kt) -> v4f_t {
+    if (SLDS) return *reinterpret_cast<const v4f_t*>(&Ss[(16 * kt + i16) * SS + 16 * m + 4 * kq]);
+    v4f_t b;
+    const int c = 16 * kt + i16;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = 16 * m + 4 * kq + j;
+      b[j] = (r < twod && c < k) ? Sm[r * k + c] : 0.0f;
+    }
+    return b;
   };
-  auto a_op = [&](int r, int c) -> float {
-    if (ALDS) return As[r * OS + c];
-    return (r < k && c < k) ? A32[r * k + c] : 0.0f;
+  auto a_frag = [&](int m, int kt) -> v4f_t {
+    if (ALDS) return *reinterpret_cast<const v4f_t*>(&As[(16 * kt + i16) * AS + 16 * m + 4 * kq]);
+    v4f_t b;
+    const int c = 16 * kt + i16;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = 16 * m + 4 * kq + j;
+      b[j] = (r < k && c < k) ? A32[r * k + c] : 0.0f;
+    }
+    return b;
   };
-  v4f_t acc[NQ], acc2[NQ2];
+  // the q-th tile of the upper triangle of O^T O: its two column tiles
+  auto tri_tile = [&](int q, int& ta, int& tb) {
+    int t = 0, rem = q;
+    while (rem >= KT - t) {
+      rem -= KT - t;
+      ++t;
+    }
+    ta = t;
+    tb = t + rem;
+  };
+  v4f_t acc[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) acc[q] = v4f_t{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int q = 0; q < NQ2; ++q) acc2[q] = v4f_t{0.f, 0.f, 0.f, 0.f};
   float mx = 0.0f;
   int hits = 0;
   bool bad = false;
   const int64_t rb = static_cast<int64_t>(blockIdx.x) * rows_per_block;
   const int64_t re = min(n, rb + rows_per_block);
   float rr_[RPT], uu_[UPT];
+  const int rrow = tid / TD, rcol = tid - (tid / TD) * TD;
+  const int urow = tid / KP, ucol = tid - (tid / KP) * KP;
+  const bool uact = urow < USTEP;  // threads beyond USTEP whole rows of KP idle
   auto fetch = [&](int64_t r0) {
+    const int left = static_cast<int>(min<int64_t>(re - r0, ROWS));  // rows of this slab that exist
+    const float* rs = R + r0 * twod;
 #pragma unroll
     for (int u = 0; u < RPT; ++u) {
-      const int e = tid + kRpThreads * u;
-      const int rr = e / TD, c = e - rr * TD;
-      const int64_t row = r0 + rr;
-      rr_[u] = (row < re && c < twod) ? R[row * twod + c] : 0.0f;
+      const int rr = rrow + RSTEP * u;
+      rr_[u] = (rr < left && rcol < twod) ? rs[rr * twod + rcol] : 0.0f;
     }
     if (MODE == kOnmf) {
+      const float* us = U + r0 * k;
 #pragma unroll
       for (int u = 0; u < UPT; ++u) {
-        const int e = tid + kRpThreads * u;
-        const int rr = e / KP, c = e - rr * KP;
-        const int64_t row = r0 + rr;
-        uu_[u] = (row < re && c < k) ? U[row * k + c] : 0.0f;
+        const int rr = urow + USTEP * u;
+        uu_[u] = (uact && rr < left && ucol < k) ? us[rr * k + ucol] : 0.0f;
       }
     }
   };
@@ -123,17 +174,12 @@ k_rowpass_mfma(const float* __restrict__ R, int64_t n, int twod, int k, const fl
   const int kt0 = w / RTILES;         // its column tiles: kt0, kt0 + WPR, ...
   for (int64_t r0 = rb; r0 < re; r0 += ROWS) {
 #pragma unroll
-    for (int u = 0; u < RPT; ++u) {
-      const int e = tid + kRpThreads * u;
-      const int rr = e / TD, c = e - rr * TD;
-      Rt[rr * RS + c] = rr_[u];
-    }
+    for (int u = 0; u < RPT; ++u) Rt[(rrow + RSTEP * u) * RS + rcol] = rr_[u];
     if (MODE == kOnmf) {
 #pragma unroll
       for (int u = 0; u < UPT; ++u) {
-        const int e = tid + kRpThreads * u;
-        const int rr = e / KP, c = e - rr * KP;
-        Ut[rr * OS + c] = uu_[u];
+        const int rr = urow + USTEP * u;
+        if (uact && rr < ROWS) Ut[rr * OS + ucol] = uu_[u];
       }
     }
     __syncthreads();
@@ -142,24 +188,39 @@ k_rowpass_mfma(const float* __restrict__ R, int64_t n, int twod, int k, const fl
     v4f_t pv[KTW], qv[KTW];
 #pragma unroll
     for (int i = 0; i < KTW; ++i) {
-      const int kt = kt0 + i * WPR;
       pv[i] = v4f_t{0.f, 0.f, 0.f, 0.f};
       qv[i] = v4f_t{0.f, 0.f, 0.f, 0.f};
-      if (kt < KT) {
-#pragma unroll 4
-        for (int t = 0; t < TD / 4; ++t)
-          pv[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(Rt[(rw + i16) * RS + 4 * t + kq],
-                                                       s_op(4 * t + kq, 16 * kt + i16), pv[i], 0, 0, 0);
-        if (MODE == kOnmf) {
-#pragma unroll 4
-          for (int t = 0; t < KP / 4; ++t)
-            qv[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(Ut[(rw + i16) * OS + 4 * t + kq],
-                                                         a_op(4 * t + kq, 16 * kt + i16), qv[i], 0, 0, 0);
-        }
-      }
     }
-    // every wave has read the U slab; O replaces it
-    if (MODE == kOnmf) __syncthreads();
+    // a wave with fewer than KTW tiles repeats its last one (the copy is
+    // discarded), so that no MFMA sits behind a branch
+    constexpr bool LIGHT = RPT + UPT <= 24;  // the slab prefetch holds few registers
+    constexpr int UNS = SLDS && LIGHT ? 2 : 1, UNA = ALDS && LIGHT ? 2 : 1;
+#pragma unroll UNS
+    for (int m = 0; m < JT; ++m) {
+      const v4f_t a = *reinterpret_cast<const v4f_t*>(&Rt[(rw + i16) * RS + 16 * m + 4 * kq]);
+      v4f_t b[KTW];
+#pragma unroll
+      for (int i = 0; i < KTW; ++i) b[i] = s_frag(m, min(kt0 + i * WPR, KT - 1));
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int i = 0; i < KTW; ++i) pv[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], b[i][j], pv[i], 0, 0, 0);
+    }
+    if (MODE == kOnmf) {
+#pragma unroll UNA
+      for (int m = 0; m < KT; ++m) {
+        const v4f_t a = *reinterpret_cast<const v4f_t*>(&Ut[(rw + i16) * OS + 16 * m + 4 * kq]);
+        v4f_t b[KTW];
+#pragma unroll
+        for (int i = 0; i < KTW; ++i) b[i] = a_frag(m, min(kt0 + i * WPR, KT - 1));
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int i = 0; i < KTW; ++i) qv[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], b[i][j], qv[i], 0, 0, 0);
+      }
+      // every wave has read the U slab; O replaces it
+      __syncthreads();
+    }
 #pragma unroll
     for (int i = 0; i < KTW; ++i) {
       const int kt = kt0 + i * WPR;
@@ -203,57 +264,84 @@ k_rowpass_mfma(const float* __restrict__ R, int64_t n, int twod, int k, const fl
       }
     }
     __syncthreads();
+    // R^T O, then O^T O, in chunks of CH MFMAs; a chunk's operands are read
+    // while the previous chunk's MFMAs run (eight reads in flight, within what
+    // the LDS counter tracks)
+    constexpr int S4 = ROWS / 4, CH = 4, NCH = S4 / CH;
+    float fa[2][CH], fb[2][CH];  // (the second buffer only with DB)
+    auto load1 = [&](int q, int h, float* xa, float* xb) {
+      const int jt = q / KT, kt = q - (q / KT) * KT;
+      const float* pa = Rt + (4 * h * CH + kq) * RS + 16 * jt + i16;
+      const float* pb = Ut + (4 * h * CH + kq) * OS + 16 * kt + i16;
 #pragma unroll
-    for (int qi = 0; qi < NQ; ++qi) {
-      const int q = w + kRpWaves * qi;
-      if (q < JT * KT) {
-        const int jt = q / KT, kt = q - (q / KT) * KT;
-#pragma unroll 4
-        for (int s4 = 0; s4 < ROWS / 4; ++s4) {
-          const int rr = 4 * s4 + kq;
-          acc[qi] = __builtin_amdgcn_mfma_f32_16x16x4f32(Rt[rr * RS + 16 * jt + i16], Ut[rr * OS + 16 * kt + i16],
-                                                         acc[qi], 0, 0, 0);
-        }
+      for (int s4 = 0; s4 < CH; ++s4) {
+        xa[s4] = pa[4 * s4 * RS];
+        xb[s4] = pb[4 * s4 * OS];
       }
-    }
+    };
+    auto load2 = [&](int q, int h, float* xa, float* xb) {
+      int ta, tb;
+      tri_tile(q, ta, tb);
+      const float* pa = Ut + (4 * h * CH + kq) * OS + 16 * ta + i16;
+      const float* pb = Ut + (4 * h * CH + kq) * OS + 16 * tb + i16;
 #pragma unroll
-    for (int qi = 0; qi < NQ2; ++qi) {
-      const int q = w + kRpWaves * qi;
-      if (q < KT * KT) {
-        const int ta = q / KT, tb = q - (q / KT) * KT;
-#pragma unroll 4
-        for (int s4 = 0; s4 < ROWS / 4; ++s4) {
-          const int rr = 4 * s4 + kq;
-          acc2[qi] = __builtin_amdgcn_mfma_f32_16x16x4f32(Ut[rr * OS + 16 * ta + i16], Ut[rr * OS + 16 * tb + i16],
-                                                          acc2[qi], 0, 0, 0);
-        }
+      for (int s4 = 0; s4 < CH; ++s4) {
+        xa[s4] = pa[4 * s4 * OS];
+        xb[s4] = pb[4 * s4 * OS];
       }
+    };
+    // step t < NQ1 * NCH: chunk t % NCH of R^T O tile w + waves (t / NCH);
+    // then the O^T O tiles likewise
+    // A wave with fewer tiles than NQ1 (NQ2) repeats the list's last tile
+    // (the copy is not written out), so that no MFMA sits behind a branch.
+    auto load_step = [&](int t, float* xa, float* xb) {
+      if (t < NQ1 * NCH)
+        load1(min(w + kRpWaves * (t / NCH), NT1 - 1), t % NCH, xa, xb);
+      else
+        load2(min(w + kRpWaves * ((t - NQ1 * NCH) / NCH), NT2 - 1), t % NCH, xa, xb);
+    };
+    // (kernels whose slab prefetch holds many registers read each chunk just
+    // before its MFMAs)
+    constexpr bool DB = LIGHT;
+    if (DB) load_step(0, fa[0], fb[0]);
+#pragma unroll
+    for (int t = 0; t < NQ * NCH; ++t) {
+      if (DB && t + 1 < NQ * NCH) load_step(t + 1, fa[(t + 1) & 1], fb[(t + 1) & 1]);
+      if (!DB) load_step(t, fa[0], fb[0]);
+      const int qi = t / NCH;
+#pragma unroll
+      for (int s4 = 0; s4 < CH; ++s4)
+        acc[qi] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[DB ? t & 1 : 0][s4], fb[DB ? t & 1 : 0][s4], acc[qi], 0, 0,
+                                                       0);
     }
     __syncthreads();
   }
   const int len = twod * k + k * k;
   double* pb = part + static_cast<int64_t>(blockIdx.x) * len;
 #pragma unroll
-  for (int qi = 0; qi < NQ; ++qi) {
+  for (int qi = 0; qi < NQ1; ++qi) {
     const int q = w + kRpWaves * qi;
-    if (q < JT * KT) {
-      const int jt = q / KT, kt = q - (q / KT) * KT;
+    if (q >= NT1) continue;
+    const int jt = q / KT, kt = q - (q / KT) * KT;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int j = 16 * jt + 4 * kq + v, c = 16 * kt + i16;
-        if (j < twod && c < k) pb[j * k + c] = static_cast<double>(acc[qi][v]);
-      }
+    for (int v = 0; v < 4; ++v) {
+      const int j = 16 * jt + 4 * kq + v, c = 16 * kt + i16;
+      if (j < twod && c < k) pb[j * k + c] = static_cast<double>(acc[qi][v]);
     }
   }
 #pragma unroll
   for (int qi = 0; qi < NQ2; ++qi) {
     const int q = w + kRpWaves * qi;
-    if (q < KT * KT) {
-      const int ta = q / KT, tb = q - (q / KT) * KT;
+    if (q >= NT2) continue;
+    int ta, tb;
+    tri_tile(q, ta, tb);
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int a = 16 * ta + 4 * kq + v, c = 16 * tb + i16;
-        if (a < k && c < k) pb[twod * k + a * k + c] = static_cast<double>(acc2[qi][v]);
+    for (int v = 0; v < 4; ++v) {
+      const int a = 16 * ta + 4 * kq + v, c = 16 * tb + i16;
+      const double x = static_cast<double>(acc[NQ1 + qi][v]);
+      if (a < k && c < k) {
+        pb[twod * k + a * k + c] = x;
+        if (ta != tb) pb[twod * k + c * k + a] = x;
       }
     }
   }
@@ -263,40 +351,45 @@ k_rowpass_mfma(const float* __restrict__ R, int64_t n, int twod, int k, const fl
   if (lane == 0) atomic_max_nonneg(&st->maxabs_ups_bits, mx);
 }
 
-// H update (Eq. update-Q) and A = (R^T U)^T H_new for the U update.
-// H_new is formed in LDS first (every entry reads the old row of H).
-__global__ void __launch_bounds__(1024)
-k_onmf_small(const double* __restrict__ rtu_utu, int twod, int k, double* __restrict__ H, float* __restrict__ H32,
-             float* __restrict__ A32, double* __restrict__ hn, DevStatus* __restrict__ st) {
-  // hn: twod x k global scratch for the new H (read back by this workgroup
-  // after the barrier)
+// H update (Eq. update-Q), one thread per entry of the new H; every entry
+// reads the old row of H, so the new values go to hn.
+__global__ void __launch_bounds__(256)
+k_onmf_h(const double* __restrict__ rtu_utu, int twod, int k, const double* __restrict__ H,
+         double* __restrict__ hn, DevStatus* __restrict__ st) {
   const double* RtU = rtu_utu;
   const double* UtU = rtu_utu + twod * k;
-  int hits = 0;
-  for (int idx = threadIdx.x; idx < twod * k; idx += blockDim.x) {
-    const int j = idx / k, c = idx % k;
-    double den = 0.0;
-    for (int t = 0; t < k; ++t) den = fma(H[j * k + t], UtU[t * k + c], den);
-    const double h = H[idx];
-    if (den == 0.0) {
-      hn[idx] = h;
-      ++hits;
-    } else {
-      hn[idx] = h * (RtU[idx] / den);
-    }
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx >= twod * k) return;
+  const int j = idx / k, c = idx - (idx / k) * k;
+  double den = 0.0;
+#pragma unroll 8
+  for (int t = 0; t < k; ++t) den = fma(H[j * k + t], UtU[t * k + c], den);
+  const double h = H[idx];
+  if (den == 0.0) {
+    hn[idx] = h;
+    atomicAdd(&st->guard_hits, 1);
+  } else {
+    hn[idx] = h * (RtU[idx] / den);
   }
-  __syncthreads();
-  for (int idx = threadIdx.x; idx < twod * k; idx += blockDim.x) {
-    H[idx] = hn[idx];
-    H32[idx] = static_cast<float>(hn[idx]);
-  }
-  for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) {
-    const int a = idx / k, b = idx % k;
+}
+
+// A = (R^T U)^T H_new for the U update, and H <- H_new (FP64 and FP32).
+__global__ void __launch_bounds__(256)
+k_onmf_a(const double* __restrict__ rtu_utu, int twod, int k, const double* __restrict__ hn, double* __restrict__ H,
+         float* __restrict__ H32, float* __restrict__ A32) {
+  const double* RtU = rtu_utu;
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx < k * k) {
+    const int a = idx / k, b = idx - (idx / k) * k;
     double s = 0.0;
+#pragma unroll 8
     for (int j = 0; j < twod; ++j) s = fma(RtU[j * k + a], hn[j * k + b], s);
     A32[idx] = static_cast<float>(s);
   }
-  if (hits) atomicAdd(&st->guard_hits, hits);
+  if (idx < twod * k) {
+    H[idx] = hn[idx];
+    H32[idx] = static_cast<float>(hn[idx]);
+  }
 }
 
 template <int JT, int KT>
@@ -355,8 +448,13 @@ void launch_onmf(const Plan& p, void* ws, hipStream_t s) {
   rowpass_any(p, ws, kProject, bufp<float>(p, ws, B_S32), nullptr, s);
   for (int t = 0; t < p.par.t_f; ++t) {
     reduce_parts(bufp<double>(p, ws, B_ONMF_PART), p.rowpass_blocks, len, bufp<double>(p, ws, B_REDTMP), rtu, s);
-    hipLaunchKernelGGL(k_onmf_small, dim3(1), dim3(1024), 0, s, rtu, p.twod, p.k, bufp<double>(p, ws, B_H),
-                       bufp<float>(p, ws, B_H32), bufp<float>(p, ws, B_A32), bufp<double>(p, ws, B_H_NEW), st);
+    const int nh = p.twod * p.k, na = std::max(nh, p.k * p.k);
+    hipLaunchKernelGGL(k_onmf_h, dim3((nh + 255) / 256), dim3(256), 0, s, rtu, p.twod, p.k, bufp<double>(p, ws, B_H),
+                       bufp<double>(p, ws, B_H_NEW), st);
+    TPO_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_onmf_a, dim3((na + 255) / 256), dim3(256), 0, s, rtu, p.twod, p.k,
+                       bufp<double>(p, ws, B_H_NEW), bufp<double>(p, ws, B_H), bufp<float>(p, ws, B_H32),
+                       bufp<float>(p, ws, B_A32));
     TPO_LAUNCH_CHECK();
     rowpass_any(p, ws, kOnmf, bufp<float>(p, ws, B_H32), bufp<float>(p, ws, B_A32), s);
   }
