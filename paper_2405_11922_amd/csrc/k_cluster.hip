@@ -221,44 +221,39 @@ k_rowpass_mfma(const float* __restrict__ R, int64_t n, int twod, int k, const fl
       // every wave has read the U slab; O replaces it
       __syncthreads();
     }
+    // O, without branches: the ratio as P times the hardware reciprocal and
+    // its hardware square root (each within about one unit in the last place)
+    {
+      const int rl0 = rw + 4 * kq;
+      const int left = static_cast<int>(min<int64_t>(re - (r0 + rl0), 4));  // rows of the lane's four that exist
+      float* ob = (MODE == kProject ? out : U) + (r0 + rl0) * k;
+      float* ob2 = MODE == kProject ? out2 + (r0 + rl0) * k : nullptr;
 #pragma unroll
-    for (int i = 0; i < KTW; ++i) {
-      const int kt = kt0 + i * WPR;
-      if (kt >= KT) continue;
+      for (int i = 0; i < KTW; ++i) {
+        const int kt = kt0 + i * WPR;
+        if (kt >= KT) continue;
+        const int c = 16 * kt + i16;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int rl = rw + 4 * kq + v, c = 16 * kt + i16;
-        const int64_t row = r0 + rl;
-        const bool live = row < re && c < k;
-        float o;
-        if (MODE == kProject) {
-          o = pv[i][v];
-        } else {
-          const float u = Ut[rl * OS + c];
-          if (qv[i][v] == 0.0f) {
-            o = u;
-            hits += live ? 1 : 0;
-          } else {
-            const float ratio = pv[i][v] / qv[i][v];
-            if (ratio < 0.0f) {
-              o = 0.0f;
-              hits += live ? 1 : 0;
-            } else {
-              o = u * sqrtf(ratio);
-            }
-          }
-        }
-        if (!live) o = 0.0f;
-        Ut[rl * OS + c] = o;
-        if (live) {
-          if (!isfinite(o)) bad = true;
-          mx = fmaxf(mx, fabsf(o));
-          const int64_t gi = row * k + c;
+        for (int v = 0; v < 4; ++v) {
+          const bool live = v < left && c < k;
+          float o;
           if (MODE == kProject) {
-            out[gi] = o;
-            out2[gi] = o;
+            o = pv[i][v];
           } else {
-            U[gi] = o;
+            const float u = Ut[(rl0 + v) * OS + c];
+            const float q = qv[i][v];
+            const float ratio = pv[i][v] * __builtin_amdgcn_rcpf(q);
+            const bool keep = q == 0.0f, neg = !keep && ratio < 0.0f;
+            o = keep ? u : (neg ? 0.0f : u * __builtin_amdgcn_sqrtf(ratio));
+            hits += (live && (keep || neg)) ? 1 : 0;
+          }
+          o = live ? o : 0.0f;
+          Ut[(rl0 + v) * OS + c] = o;
+          if (live) {
+            bad = bad || !isfinite(o);
+            mx = fmaxf(mx, fabsf(o));
+            ob[v * k + c] = o;
+            if (MODE == kProject) ob2[v * k + c] = o;
           }
         }
       }
