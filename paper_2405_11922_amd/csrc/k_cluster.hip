@@ -642,9 +642,12 @@ k_nci_round(const float* __restrict__ U, int64_t n, int k, const long long* __re
 // forms S^T = Phi^T U^T for 16 rows at a time: A = Phi^T (a 16-label tile),
 // B = U^T (the 16 rows), so lane l ends with the scores of row l % 16 for the
 // labels 16 c + 4 (l / 16) + v; the first maximum and the runner-up are found
-// in registers and then over the four lanes that share the row.  Phi (k x 16
-// LT, FP64 values rounded to FP32, zero padded) sits in LDS; eight waves share
-// it.
+// in registers and then over the four lanes that share the row.  Phi^T (16 LT
+// x k, FP64 values rounded to FP32, zero padded) sits in LDS, shared by the
+// workgroup's eight waves.  The j-th of four consecutive MFMAs gives depth slot l / 16 the
+// contraction index 16 m + 4 (l / 16) + j, so a lane's four values of a U row
+// come in with one 16-byte load (k a multiple of 4) and its four of Phi^T
+// with one 16-byte LDS read.
 //
 // The decision must be the one FP64 scores give.  Each FP32 score is within
 // (k + 2) 2^-24 ||u_i||_2 max_l ||phi_l||_2 of the exact one (k rounded
@@ -654,16 +657,18 @@ k_nci_round(const float* __restrict__ U, int64_t n, int k, const long long* __re
 constexpr int kNciWide = 128;
 constexpr int kNciMaxRounds = 1024;  // round counters of the recheck list
 
+constexpr int kNciScoreWaves = 8;
+
 template <int LT>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(64 * kNciScoreWaves)
 k_nci_score_mfma(const float* __restrict__ U, int64_t n, int k, const long long* __restrict__ sums,
                  const double* __restrict__ phi_g, int32_t* __restrict__ labels, int32_t* __restrict__ check_count,
                  int32_t* __restrict__ check_rows, const DevStatus* __restrict__ st,
                  const int32_t* __restrict__ skip) {
   if (skip && *skip == 0) return;
   constexpr int NL = 16 * LT;
-  constexpr int KS = NL / 4;  // k steps of the padded contraction
-  __shared__ float phi[NL * NL];  // phi[t * NL + l]
+  constexpr int NLP = NL + 4;  // row stride of Phi^T: 16-byte reads of 8 consecutive lanes in distinct banks
+  __shared__ __align__(16) float phit[NL * NLP];  // phit[l * NLP + t] = Phi[t][l]
   __shared__ double fac[NL];
   __shared__ unsigned int colmax_bits;  // max_l ||phi_l||_2 as float bits
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -680,9 +685,9 @@ k_nci_score_mfma(const float* __restrict__ U, int64_t n, int k, const long long*
     if (t >= k || l >= k) return 0.0;
     return phi_g ? phi_g[t * k + l] : sums ? static_cast<double>(sums[l * k + t]) * fac[l] : (t == l ? 1.0 : 0.0);
   };
-  for (int e = tid; e < NL * NL; e += 512) {
+  for (int e = tid; e < NL * NL; e += 64 * kNciScoreWaves) {
     const int t = e / NL, l = e - (e / NL) * NL;
-    phi[e] = static_cast<float>(phi64(t, l));
+    phit[l * NLP + t] = static_cast<float>(phi64(t, l));
   }
   if (tid < k) {
     double ss = 0.0;
@@ -696,29 +701,39 @@ k_nci_score_mfma(const float* __restrict__ U, int64_t n, int k, const long long*
   __syncthreads();
   const double tol_scale = static_cast<double>(k + 2) * ldexp(1.0, -24) * 2.0 * 2.0 *
                            static_cast<double>(__uint_as_float(colmax_bits));
+  const bool vec = (k & 3) == 0;  // rows of U start on 16-byte boundaries
   const int64_t ntiles = (n + 15) / 16;
-  for (int64_t tile = static_cast<int64_t>(blockIdx.x) * 8 + w; tile < ntiles;
-       tile += static_cast<int64_t>(gridDim.x) * 8) {
+  for (int64_t tile = static_cast<int64_t>(blockIdx.x) * kNciScoreWaves + w; tile < ntiles;
+       tile += static_cast<int64_t>(gridDim.x) * kNciScoreWaves) {
     const int64_t row = tile * 16 + i16;
     const bool live = row < n;
     const float* urow = U + row * k;
-    float ub[KS];
+    v4f_t ub[LT];
     double u2 = 0.0;
 #pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      const int t = 4 * s + g;
-      ub[s] = (live && t < k) ? urow[t] : 0.0f;
-      u2 = fma(static_cast<double>(ub[s]), static_cast<double>(ub[s]), u2);
+    for (int m = 0; m < LT; ++m) {
+      const int t0 = 16 * m + 4 * g;
+      if (vec) {
+        ub[m] = (live && t0 < k) ? *reinterpret_cast<const v4f_t*>(urow + t0) : v4f_t{0.f, 0.f, 0.f, 0.f};
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) ub[m][j] = (live && t0 + j < k) ? urow[t0 + j] : 0.0f;
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) u2 = fma(static_cast<double>(ub[m][j]), static_cast<double>(ub[m][j]), u2);
     }
     v4f_t acc[LT];
 #pragma unroll
     for (int c = 0; c < LT; ++c) acc[c] = v4f_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      if (4 * s >= k) break;  // uniform: the padded steps add zeros
-      const float* pr = phi + (4 * s + g) * NL + i16;
+    for (int m = 0; m < LT; ++m) {
+      if (16 * m >= k) break;  // uniform: the padded steps add zeros
 #pragma unroll
-      for (int c = 0; c < LT; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(pr[16 * c], ub[s], acc[c], 0, 0, 0);
+      for (int c = 0; c < LT; ++c) {
+        const v4f_t a = *reinterpret_cast<const v4f_t*>(&phit[(16 * c + i16) * NLP + 16 * m + 4 * g]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], ub[m][j], acc[c], 0, 0, 0);
+      }
     }
     // first maximum and runner-up: labels in increasing order within the
     // lane, then the lower label wins a tie between lanes
@@ -881,12 +896,20 @@ template <int LT>
 static void nci_score_mfma(const float* U, int64_t n, int k, const long long* sums, const double* phi_g,
                            int32_t* labels, int32_t* check_count, int32_t* check_rows, DevStatus* st,
                            const int32_t* skip, int round, hipStream_t s) {
-  constexpr int NL = 16 * LT;
-  constexpr size_t lds = static_cast<size_t>(NL) * NL * 4 + NL * 8 + 4;
-  const int per_cu = std::max<int>(1, static_cast<int>((160 * 1024) / lds));
+  // workgroups resident per CU (LDS and registers), asked once: the grid is
+  // the number that fits, so the last of its tiles does not run alone
+  static const int per_cu = [] {
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, reinterpret_cast<const void*>(&k_nci_score_mfma<LT>),
+                                                     64 * kNciScoreWaves, 0) != hipSuccess ||
+        b < 1)
+      b = 1;
+    return b;
+  }();
   const int64_t ntiles = (n + 15) / 16;
-  const int nb = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>((ntiles + 7) / 8, 256 * per_cu)));
-  hipLaunchKernelGGL((k_nci_score_mfma<LT>), dim3(nb), dim3(512), 0, s, U, n, k, sums, phi_g, labels, check_count,
+  const int nb = static_cast<int>(
+      std::max<int64_t>(1, std::min<int64_t>((ntiles + kNciScoreWaves - 1) / kNciScoreWaves, 256 * per_cu)));
+  hipLaunchKernelGGL((k_nci_score_mfma<LT>), dim3(nb), dim3(64 * kNciScoreWaves), 0, s, U, n, k, sums, phi_g, labels, check_count,
                      check_rows, st, skip);
   TPO_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_nci_recheck, dim3(64), dim3(256), 0, s, U, k, sums, phi_g, check_count, check_rows, labels, n,
