@@ -7,6 +7,8 @@
 // pass, so the result is a deterministic function of the input.  The
 // transpose is a stable sort of the deduplicated (row, col) list on its
 // column bits only.
+#include <algorithm>
+
 #include "dev_common.hpp"
 #include "tpo_internal.hpp"
 
@@ -374,54 +376,67 @@ __global__ void k_fill_i32(int32_t* __restrict__ a, int64_t n, int32_t v) {
 
 // Weighted degree per row, the propagation scale and the hub chunk count.
 // mode 0: U side, scale = D^-1/2; mode 1: V side, D^-1.  A wave owns 64
-// consecutive rows, one per lane; summed edge weights (when present) are
-// formed row by row by the whole wave in a fixed order.  Isolated rows are
-// counted with one atomic per wave.
-__global__ void k_degrees(const int32_t* __restrict__ rowptr, const float* __restrict__ val, int nrows,
-                          const DevStatus* __restrict__ st_ro, int mode, float* __restrict__ deg,
-                          float* __restrict__ scale, uint32_t* __restrict__ nchunk,
-                          uint32_t* __restrict__ ishub, int32_t* __restrict__ iso_count) {
+// consecutive rows at a time, one per lane, and a fixed grid walks the rows;
+// summed edge weights (when present) are formed row by row by the whole wave
+// in a fixed order.  Isolated rows are counted per workgroup and added to
+// the total with one atomic per workgroup (a graph with many isolated rows
+// would otherwise queue an atomic per wave on one address).
+constexpr int kDegBlocks = 2048;
+
+__global__ void __launch_bounds__(256)
+k_degrees(const int32_t* __restrict__ rowptr, const float* __restrict__ val, int nrows,
+          const DevStatus* __restrict__ st_ro, int mode, float* __restrict__ deg, float* __restrict__ scale,
+          uint32_t* __restrict__ nchunk, uint32_t* __restrict__ ishub, int32_t* __restrict__ iso_count) {
+  __shared__ int iso_blk;
   const int lane = threadIdx.x & 63;
-  const int row0 = static_cast<int>((static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) - lane);
-  const int r = row0 + lane;
-  const bool live = r < nrows;
-  int b = 0, e = 0;
-  if (live) {
-    b = rowptr[r];
-    e = rowptr[r + 1];
-  }
-  double s = static_cast<double>(e - b);
-  if (st_ro->has_vals) {
-    // a row of at most 64 entries is summed by its own lane in stored order;
-    // a longer one by the whole wave (strided partial sums, then a tree)
-    double mine = 0.0;
-    const bool serial = live && e - b <= 64;
-    if (serial)
-      for (int i = b; i < e; ++i) mine += static_cast<double>(val[i]);
-    uint64_t longs = __ballot(live && !serial);
-    while (longs) {
-      const int j = __ffsll(static_cast<unsigned long long>(longs)) - 1;
-      longs &= longs - 1;
-      const int bj = __shfl(b, j, 64), ej = __shfl(e, j, 64);
-      double t = 0.0;
-      for (int i = bj + lane; i < ej; i += 64) t += static_cast<double>(val[i]);
-      t = wave_sum(t);
-      if (lane == j) mine = t;
+  if (threadIdx.x == 0) iso_blk = 0;
+  __syncthreads();
+  const bool has_vals = st_ro->has_vals != 0;
+  int iso_w = 0;  // isolated rows seen by this wave (lane 0's count)
+  for (int64_t base = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x - lane; base < nrows;
+       base += static_cast<int64_t>(gridDim.x) * 256) {
+    const int r = static_cast<int>(base) + lane;
+    const bool live = r < nrows;
+    int b = 0, e = 0;
+    if (live) {
+      b = rowptr[r];
+      e = rowptr[r + 1];
     }
-    s = mine;
+    double s = static_cast<double>(e - b);
+    if (has_vals) {
+      // a row of at most 64 entries is summed by its own lane in stored order;
+      // a longer one by the whole wave (strided partial sums, then a tree)
+      double mine = 0.0;
+      const bool serial = live && e - b <= 64;
+      if (serial)
+        for (int i = b; i < e; ++i) mine += static_cast<double>(val[i]);
+      uint64_t longs = __ballot(live && !serial);
+      while (longs) {
+        const int j = __ffsll(static_cast<unsigned long long>(longs)) - 1;
+        longs &= longs - 1;
+        const int bj = __shfl(b, j, 64), ej = __shfl(e, j, 64);
+        double t = 0.0;
+        for (int i = bj + lane; i < ej; i += 64) t += static_cast<double>(val[i]);
+        t = wave_sum(t);
+        if (lane == j) mine = t;
+      }
+      s = mine;
+    }
+    if (live) {
+      deg[r] = static_cast<float>(s);
+      double sc = 0.0;
+      if (s > 0.0) sc = (mode == 0) ? 1.0 / sqrt(s) : 1.0 / s;
+      scale[r] = static_cast<float>(sc);
+      const int cnt = e - b;
+      const uint32_t nc = cnt > kHubChunk ? static_cast<uint32_t>((cnt + kHubChunk - 1) / kHubChunk) : 0u;
+      nchunk[r] = nc;
+      ishub[r] = nc > 0 ? 1u : 0u;
+    }
+    iso_w += __popcll(__ballot(live && !(s > 0.0)));
   }
-  if (live) {
-    deg[r] = static_cast<float>(s);
-    double sc = 0.0;
-    if (s > 0.0) sc = (mode == 0) ? 1.0 / sqrt(s) : 1.0 / s;
-    scale[r] = static_cast<float>(sc);
-    const int cnt = e - b;
-    const uint32_t nc = cnt > kHubChunk ? static_cast<uint32_t>((cnt + kHubChunk - 1) / kHubChunk) : 0u;
-    nchunk[r] = nc;
-    ishub[r] = nc > 0 ? 1u : 0u;
-  }
-  const uint64_t iso = __ballot(live && !(s > 0.0));
-  if (lane == 0 && iso != 0) atomicAdd(iso_count, static_cast<int32_t>(__popcll(iso)));
+  if (lane == 0 && iso_w != 0) atomicAdd(&iso_blk, iso_w);
+  __syncthreads();
+  if (threadIdx.x == 0 && iso_blk != 0) atomicAdd(iso_count, iso_blk);
 }
 
 __global__ void k_hub_lists(const int32_t* __restrict__ rowptr, int nrows, const uint32_t* __restrict__ nchunk_raw,
@@ -450,7 +465,7 @@ static void side_lists(const Plan& p, void* ws, int nrows, const int32_t* rowptr
   uint32_t* nchunk = bufp<uint32_t>(p, ws, cnt_b);
   uint32_t* ishub = bufp<uint32_t>(p, ws, hub_b);
   uint32_t* aux = bufp<uint32_t>(p, ws, B_SCAN_AUX);
-  hipLaunchKernelGGL(k_degrees, dim3(ceil_div(static_cast<int64_t>(nrows), 256)), dim3(256), 0, s, rowptr,
+  hipLaunchKernelGGL(k_degrees, dim3(std::max<int64_t>(1, std::min<int64_t>(ceil_div(static_cast<int64_t>(nrows), 256), kDegBlocks))), dim3(256), 0, s, rowptr,
                      val, nrows, st, mode, bufp<float>(p, ws, deg_b), bufp<float>(p, ws, scale_b), nchunk, ishub,
                      iso);
   TPO_LAUNCH_CHECK();
