@@ -166,21 +166,24 @@ k_radix_upsweep(const uint64_t* __restrict__ keys, int64_t n_static, const int32
   hist[static_cast<int64_t>(t) * nb + blockIdx.x] = cnt[t];
 }
 
-// One tile's keys in digit order: ranked as the tile is read (iteration r,
-// then wave, then lane order among equal digits, so the sort stays stable),
-// placed in LDS at their position within the tile's digit-ordered sequence,
-// then written out in that order: consecutive threads write consecutive
-// addresses of one digit's run instead of scattering one key per lane.
+// One tile's keys in digit order.  Wave w holds the tile's w-th quarter
+// (keys w WK + 64 r + lane, r = 0..kSortItems-1), so the tile's order is
+// (wave, r, lane).  Each wave ranks its own keys against a running count per
+// digit in its own LDS row (eight ballots match a lane's digit; no barrier
+// inside the loop), then one pass over the digits turns the four waves'
+// counts into their offsets and the tile's digit starts.  Equal digits keep
+// the tile's order, so the sort is stable.  The keys are placed in LDS at
+// their position in the tile's digit order and written out in that order:
+// consecutive threads write consecutive addresses of one digit's run.
 __global__ void __launch_bounds__(kSortThreads)
 k_radix_downsweep(const uint64_t* __restrict__ keys, const float* __restrict__ vals, int64_t n_static,
                   const int32_t* n_dev, int shift, const uint32_t* __restrict__ hist_scan, int nb,
                   uint64_t* __restrict__ okeys, float* __restrict__ ovals) {
   constexpr int NW = kSortThreads / 64;
+  constexpr int WK = kSortTile / NW;  // keys per wave
   __shared__ uint32_t goff[256];  // global start of each digit for this tile
   __shared__ uint32_t loff[256];  // start of each digit within the tile's order
-  __shared__ uint32_t tile_cnt[256];
-  __shared__ uint32_t wcnt[NW][256];
-  __shared__ uint32_t wpre[NW][256];
+  __shared__ uint32_t wcnt[NW][256];  // each wave's running digit counts, then its offsets
   __shared__ uint32_t wsum[NW];
   __shared__ uint64_t skeys[kSortTile];
   __shared__ float svals[kSortTile];
@@ -192,22 +195,45 @@ k_radix_downsweep(const uint64_t* __restrict__ keys, const float* __restrict__ v
   float val[kSortItems];
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
-    const int li = r * kSortThreads + t;
+    const int li = w * WK + r * 64 + lane;
     key[r] = li < nvalid ? keys[base + li] : 0ull;
     val[r] = (li < nvalid && vals) ? vals[base + li] : 0.0f;
   }
   goff[t] = hist_scan[static_cast<int64_t>(t) * nb + blockIdx.x];
-  tile_cnt[t] = 0;
+#pragma unroll
   for (int i = 0; i < NW; ++i) wcnt[i][t] = 0;
   __syncthreads();
-  // the tile's digit counts, then their exclusive scan (loff)
+  const uint64_t lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+  uint32_t rk[kSortItems];  // rank among the wave's earlier keys of the same digit
 #pragma unroll
-  for (int r = 0; r < kSortItems; ++r)
-    if (r * kSortThreads + t < nvalid) atomicAdd(&tile_cnt[static_cast<uint32_t>((key[r] >> shift) & 255u)], 1u);
+  for (int r = 0; r < kSortItems; ++r) {
+    const bool valid = w * WK + r * 64 + lane < nvalid;
+    const uint32_t d = static_cast<uint32_t>((key[r] >> shift) & 255u);
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t bb = __ballot(bit);
+      peers &= bit ? bb : ~bb;
+    }
+    const uint32_t before = wcnt[w][d];
+    rk[r] = before + static_cast<uint32_t>(__popcll(peers & lt_mask));
+    // the first lane of each digit advances the count (every lane of the wave
+    // has read it above: a wave's LDS accesses complete in program order)
+    if (valid && (peers & lt_mask) == 0) wcnt[w][d] = before + static_cast<uint32_t>(__popcll(peers));
+  }
   __syncthreads();
   {
-    const uint32_t c = tile_cnt[t];
-    uint32_t v = c;
+    // digit t: the waves' exclusive offsets, then the tile's exclusive scan
+    // of the digit totals
+    uint32_t run = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+      const uint32_t c = wcnt[i][t];
+      wcnt[i][t] = run;
+      run += c;
+    }
+    uint32_t v = run;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
       const uint32_t y = __shfl_up(v, o, 64);
@@ -217,38 +243,14 @@ k_radix_downsweep(const uint64_t* __restrict__ keys, const float* __restrict__ v
     __syncthreads();
     uint32_t before = 0;
     for (int i = 0; i < w; ++i) before += wsum[i];
-    loff[t] = before + v - c;
-    tile_cnt[t] = 0;
+    loff[t] = before + v - run;
   }
   __syncthreads();
-  const uint64_t lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
-    const bool valid = r * kSortThreads + t < nvalid;
-    const uint32_t d = static_cast<uint32_t>((key[r] >> shift) & 255u);
-    uint64_t peers = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const uint64_t bb = __ballot(bit);
-      peers &= bit ? bb : ~bb;
-    }
-    const uint32_t rank = __popcll(peers & lt_mask);
-    if (valid && rank == 0) wcnt[w][d] = static_cast<uint32_t>(__popcll(peers));
-    __syncthreads();
-    {
-      uint32_t run = tile_cnt[t];
-      for (int i = 0; i < NW; ++i) {
-        const uint32_t c = wcnt[i][t];
-        wpre[i][t] = run;
-        run += c;
-        wcnt[i][t] = 0;
-      }
-      tile_cnt[t] = run;
-    }
-    __syncthreads();
-    if (valid) {
-      const uint32_t lp = loff[d] + wpre[w][d] + rank;
+    if (w * WK + r * 64 + lane < nvalid) {
+      const uint32_t d = static_cast<uint32_t>((key[r] >> shift) & 255u);
+      const uint32_t lp = loff[d] + wcnt[w][d] + rk[r];
       skeys[lp] = key[r];
       if (vals) svals[lp] = val[r];
     }
