@@ -1193,6 +1193,7 @@ void launch_nci(const Plan& p, void* ws, hipStream_t s) {
 // Written transposed: entry o (l * twod + j, then k * twod + l for counts) at
 // part[o * gridDim.x + blockIdx.x].
 constexpr int kObjLdsBytes = 128 * 1024;
+constexpr int kObjRows = 8;
 
 __global__ void __launch_bounds__(1024)
 k_obj_accum(const float* __restrict__ R, int64_t n, int twod, const int32_t* __restrict__ labels, int k,
@@ -1207,12 +1208,34 @@ k_obj_accum(const float* __restrict__ R, int64_t n, int twod, const int32_t* __r
   __syncthreads();
   const int64_t rb = static_cast<int64_t>(blockIdx.x) * rows_per_block;
   const int64_t re = min(n, rb + rows_per_block);
-  for (int64_t r = rb + w; r < re; r += blockDim.x >> 6) {
-    const int lab = labels[r];
-    for (int j = lane; j < cn; j += 64)
-      atomicAdd(reinterpret_cast<unsigned long long*>(&accl[lab * cw + j]),
-                static_cast<unsigned long long>(to_fixed(R[r * twod + c0 + j], sft)));
-    if (lane == 0 && blockIdx.y == 0) atomicAdd(reinterpret_cast<unsigned long long*>(&cntl[lab]), 1ull);
+  // a wave takes kObjRows rows at a time, all their loads issued before the
+  // sums (cn <= 2d <= 256: four values of a row per lane)
+  const int waves = blockDim.x >> 6;
+  for (int64_t r0 = rb + static_cast<int64_t>(w) * kObjRows; r0 < re; r0 += static_cast<int64_t>(waves) * kObjRows) {
+    int lab[kObjRows];
+    float v[kObjRows][4];
+#pragma unroll
+    for (int u = 0; u < kObjRows; ++u) {
+      const int64_t r = r0 + u;
+      lab[u] = r < re ? labels[r] : 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j = lane + 64 * q;
+        v[u][q] = (r < re && j < cn) ? R[r * twod + c0 + j] : 0.0f;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kObjRows; ++u) {
+      if (r0 + u >= re) break;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j = lane + 64 * q;
+        if (j < cn)
+          atomicAdd(reinterpret_cast<unsigned long long*>(&accl[lab[u] * cw + j]),
+                    static_cast<unsigned long long>(to_fixed(v[u][q], sft)));
+      }
+      if (lane == 0 && blockIdx.y == 0) atomicAdd(reinterpret_cast<unsigned long long*>(&cntl[lab[u]]), 1ull);
+    }
   }
   __syncthreads();
   for (int e = tid; e < k * cn; e += blockDim.x) {

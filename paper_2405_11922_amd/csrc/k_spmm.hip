@@ -247,13 +247,17 @@ k_spmm_hubs(const int32_t* __restrict__ n_hubs, const int4* __restrict__ hubs, c
   }
 }
 
-// W0 = D_U^-1/2 X'  (or Z = (1 - alpha) X' when gamma = 0)
-__global__ void k_scale_rows(const float* __restrict__ x, int n, int D, const float* __restrict__ rscale,
-                             float c, float* __restrict__ out) {
-  int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= static_cast<int64_t>(n) * D) return;
-  const int r = static_cast<int>(i / D);
-  out[i] = (rscale ? rscale[r] : 1.0f) * c * x[i];
+// W0 = D_U^-1/2 X'  (or Z = (1 - alpha) X' when gamma = 0); one float4 per
+// thread (D a power of two, at least 4)
+template <int D>
+__global__ void k_scale_rows(const float* __restrict__ x, int n, const float* __restrict__ rscale, float c,
+                             float* __restrict__ out) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= static_cast<int64_t>(n) * (D / 4)) return;
+  const int r = static_cast<int>(i / (D / 4));
+  const float f = (rscale ? rscale[r] : 1.0f) * c;
+  const float4 v = reinterpret_cast<const float4*>(x)[i];
+  reinterpret_cast<float4*>(out)[i] = make_float4(f * v.x, f * v.y, f * v.z, f * v.w);
 }
 
 template <int D, int MODE>
@@ -283,12 +287,12 @@ static void propagate_impl(const Plan& p, void* ws, const float* xp, hipStream_t
   const float* isq = bufp<float>(p, ws, B_ISQ_U);
   const float* invv = bufp<float>(p, ws, B_INV_V);
   if (p.par.gamma == 0) {
-    hipLaunchKernelGGL(k_scale_rows, dim3(ceil_div(static_cast<int64_t>(n) * D, 256)), dim3(256), 0, s, xp, n, D,
-                       nullptr, oma, z);
+    hipLaunchKernelGGL(k_scale_rows<D>, dim3(ceil_div(static_cast<int64_t>(n) * (D / 4), 256)), dim3(256), 0, s, xp,
+                       n, nullptr, oma, z);
     TPO_LAUNCH_CHECK();
     return;
   }
-  hipLaunchKernelGGL(k_scale_rows, dim3(ceil_div(static_cast<int64_t>(n) * D, 256)), dim3(256), 0, s, xp, n, D,
+  hipLaunchKernelGGL(k_scale_rows<D>, dim3(ceil_div(static_cast<int64_t>(n) * (D / 4), 256)), dim3(256), 0, s, xp, n,
                      isq, 1.0f, w0);
   TPO_LAUNCH_CHECK();
   // hub-chunk workgroups: enough for every chunk the plan allows, at most
