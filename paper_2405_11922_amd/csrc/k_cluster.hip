@@ -658,14 +658,22 @@ constexpr int kNciWide = 128;
 constexpr int kNciMaxRounds = 1024;  // round counters of the recheck list
 
 constexpr int kNciScoreWaves = 8;
+constexpr int kNciFusedWaves = 16;
 
-template <int LT>
-__global__ void __launch_bounds__(64 * kNciScoreWaves)
+// ACC: the same kernel also forms this round's label sums (the next round's
+// Phi) for the rows whose decision it makes, in int64 fixed point in LDS
+// (dynamic, k x k + k), written as partial column blockIdx.x of part (entry
+// o at part[o * pstride + column]); the last column, pstride - 1, is zeroed
+// here by workgroup 0 and takes the rows k_nci_recheck decides.
+template <int LT, bool ACC>
+__global__ void __launch_bounds__(64 * (ACC ? kNciFusedWaves : kNciScoreWaves))
 k_nci_score_mfma(const float* __restrict__ U, int64_t n, int k, const long long* __restrict__ sums,
                  const double* __restrict__ phi_g, int32_t* __restrict__ labels, int32_t* __restrict__ check_count,
                  int32_t* __restrict__ check_rows, const DevStatus* __restrict__ st,
-                 const int32_t* __restrict__ skip) {
+                 const int32_t* __restrict__ skip, long long* __restrict__ part, int pstride) {
   if (skip && *skip == 0) return;
+  constexpr int WV = ACC ? kNciFusedWaves : kNciScoreWaves;
+  extern __shared__ long long accl[];  // ACC: k x k sums, then k counts
   constexpr int NL = 16 * LT;
   constexpr int NLP = NL + 4;  // row stride of Phi^T: 16-byte reads of 8 consecutive lanes in distinct banks
   __shared__ __align__(16) float phit[NL * NLP];  // phit[l * NLP + t] = Phi[t][l]
@@ -685,9 +693,14 @@ k_nci_score_mfma(const float* __restrict__ U, int64_t n, int k, const long long*
     if (t >= k || l >= k) return 0.0;
     return phi_g ? phi_g[t * k + l] : sums ? static_cast<double>(sums[l * k + t]) * fac[l] : (t == l ? 1.0 : 0.0);
   };
-  for (int e = tid; e < NL * NL; e += 64 * kNciScoreWaves) {
+  for (int e = tid; e < NL * NL; e += 64 * WV) {
     const int t = e / NL, l = e - (e / NL) * NL;
     phit[l * NLP + t] = static_cast<float>(phi64(t, l));
+  }
+  if (ACC) {
+    for (int e = tid; e < k * k + k; e += 64 * WV) accl[e] = 0;
+    if (blockIdx.x == 0)
+      for (int e = tid; e < k * k + k; e += 64 * WV) part[static_cast<int64_t>(e) * pstride + (pstride - 1)] = 0;
   }
   if (tid < k) {
     double ss = 0.0;
@@ -703,8 +716,8 @@ k_nci_score_mfma(const float* __restrict__ U, int64_t n, int k, const long long*
                            static_cast<double>(__uint_as_float(colmax_bits));
   const bool vec = (k & 3) == 0;  // rows of U start on 16-byte boundaries
   const int64_t ntiles = (n + 15) / 16;
-  for (int64_t tile = static_cast<int64_t>(blockIdx.x) * kNciScoreWaves + w; tile < ntiles;
-       tile += static_cast<int64_t>(gridDim.x) * kNciScoreWaves) {
+  for (int64_t tile = static_cast<int64_t>(blockIdx.x) * WV + w; tile < ntiles;
+       tile += static_cast<int64_t>(gridDim.x) * WV) {
     const int64_t row = tile * 16 + i16;
     const bool live = row < n;
     const float* urow = U + row * k;
@@ -770,13 +783,31 @@ k_nci_score_mfma(const float* __restrict__ U, int64_t n, int k, const long long*
         second = fmaxf(second, ov);
       }
     }
+    // (the four lanes of a row hold the same best, runner-up and norm)
+    const bool close = static_cast<double>(bestv) - static_cast<double>(second) <= tol_scale * sqrt(u2);
     if (live && g == 0) {
       labels[row] = best;
-      if (static_cast<double>(bestv) - static_cast<double>(second) <= tol_scale * sqrt(u2)) {
+      if (close) {
         const int slot = atomicAdd(check_count, 1);
         check_rows[slot] = static_cast<int32_t>(row);
       }
     }
+    if (ACC && live && !close) {
+#pragma unroll
+      for (int m = 0; m < LT; ++m)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int t = 16 * m + 4 * g + j;
+          if (t < k)
+            atomicAdd(reinterpret_cast<unsigned long long*>(&accl[best * k + t]),
+                      static_cast<unsigned long long>(to_fixed(ub[m][j], sft)));
+        }
+      if (g == 0) atomicAdd(reinterpret_cast<unsigned long long*>(&accl[k * k + best]), 1ull);
+    }
+  }
+  if (ACC) {
+    __syncthreads();
+    for (int e = tid; e < k * k + k; e += 64 * WV) part[static_cast<int64_t>(e) * pstride + blockIdx.x] = accl[e];
   }
 }
 
@@ -786,7 +817,8 @@ __global__ void __launch_bounds__(256)
 k_nci_recheck(const float* __restrict__ U, int k, const long long* __restrict__ sums,
               const double* __restrict__ phi_g, const int32_t* __restrict__ check_count,
               const int32_t* __restrict__ check_rows, int32_t* __restrict__ labels, int64_t n,
-              DevStatus* __restrict__ st, const int32_t* __restrict__ skip, int round) {
+              DevStatus* __restrict__ st, const int32_t* __restrict__ skip, int round, long long* __restrict__ part,
+              int pstride) {
   if (skip && *skip == 0) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) atomicMax(&st->nci_rounds, round);
   const int lane = threadIdx.x & 63;
@@ -827,6 +859,14 @@ k_nci_recheck(const float* __restrict__ U, int k, const long long* __restrict__ 
       }
     }
     if (lane == 0) labels[row] = best;
+    if (part) {  // the fused scoring left this row's sums to its final decision
+      long long* col = part + (pstride - 1);
+      for (int l = lane; l < k; l += 64)
+        atomicAdd(reinterpret_cast<unsigned long long*>(&col[static_cast<int64_t>(best * k + l) * pstride]),
+                  static_cast<unsigned long long>(to_fixed(urow[l], sft)));
+      if (lane == 0)
+        atomicAdd(reinterpret_cast<unsigned long long*>(&col[static_cast<int64_t>(k * k + best) * pstride]), 1ull);
+    }
   }
 }
 
@@ -892,29 +932,61 @@ k_nci_accum_wide(const float* __restrict__ U, int64_t n, int k, const int32_t* _
   for (int e = tid; e < k * k + k; e += 1024) part[static_cast<int64_t>(e) * gridDim.x + blockIdx.x] = accl[e];
 }
 
+// One round's scores and decisions.  With `acc` and k <= 112 (Phi^T and the
+// k x k + k sums both fit the LDS) the scoring kernel also forms the round's
+// label sums, as partial columns of part: the return value is their number
+// (at most max_cols), 0 when the sums are left to k_nci_accum_wide.
 template <int LT>
-static void nci_score_mfma(const float* U, int64_t n, int k, const long long* sums, const double* phi_g,
-                           int32_t* labels, int32_t* check_count, int32_t* check_rows, DevStatus* st,
-                           const int32_t* skip, int round, hipStream_t s) {
+static int nci_score_mfma(const float* U, int64_t n, int k, const long long* sums, const double* phi_g,
+                          int32_t* labels, int32_t* check_count, int32_t* check_rows, DevStatus* st,
+                          const int32_t* skip, int round, long long* part, int max_cols, bool acc, hipStream_t s) {
+  const int64_t ntiles = (n + 15) / 16;
+  if constexpr (LT <= 7) {
+    if (acc && max_cols >= 2) {
+      constexpr int NL = 16 * LT;
+      static std::once_flag once;
+      std::call_once(once, [] {
+        TPO_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_nci_score_mfma<LT, true>),
+                                          hipFuncAttributeMaxDynamicSharedMemorySize,
+                                          static_cast<int>((NL * NL + NL) * sizeof(long long))));
+      });
+      const size_t dyn = static_cast<size_t>(k * k + k) * sizeof(long long);
+      int b = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, reinterpret_cast<const void*>(&k_nci_score_mfma<LT, true>),
+                                                       64 * kNciFusedWaves, dyn) != hipSuccess ||
+          b < 1)
+        b = 1;
+      const int nb = static_cast<int>(std::max<int64_t>(
+          1, std::min<int64_t>({(ntiles + kNciFusedWaves - 1) / kNciFusedWaves, 256 * static_cast<int64_t>(b),
+                                static_cast<int64_t>(max_cols - 1)})));
+      hipLaunchKernelGGL((k_nci_score_mfma<LT, true>), dim3(nb), dim3(64 * kNciFusedWaves), dyn, s, U, n, k, sums,
+                         phi_g, labels, check_count, check_rows, st, skip, part, nb + 1);
+      TPO_LAUNCH_CHECK();
+      hipLaunchKernelGGL(k_nci_recheck, dim3(64), dim3(256), 0, s, U, k, sums, phi_g, check_count, check_rows, labels,
+                         n, st, skip, round, part, nb + 1);
+      TPO_LAUNCH_CHECK();
+      return nb + 1;
+    }
+  }
   // workgroups resident per CU (LDS and registers), asked once: the grid is
   // the number that fits, so the last of its tiles does not run alone
   static const int per_cu = [] {
     int b = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, reinterpret_cast<const void*>(&k_nci_score_mfma<LT>),
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, reinterpret_cast<const void*>(&k_nci_score_mfma<LT, false>),
                                                      64 * kNciScoreWaves, 0) != hipSuccess ||
         b < 1)
       b = 1;
     return b;
   }();
-  const int64_t ntiles = (n + 15) / 16;
   const int nb = static_cast<int>(
       std::max<int64_t>(1, std::min<int64_t>((ntiles + kNciScoreWaves - 1) / kNciScoreWaves, 256 * per_cu)));
-  hipLaunchKernelGGL((k_nci_score_mfma<LT>), dim3(nb), dim3(64 * kNciScoreWaves), 0, s, U, n, k, sums, phi_g, labels, check_count,
-                     check_rows, st, skip);
+  hipLaunchKernelGGL((k_nci_score_mfma<LT, false>), dim3(nb), dim3(64 * kNciScoreWaves), 0, s, U, n, k, sums, phi_g,
+                     labels, check_count, check_rows, st, skip, nullptr, 0);
   TPO_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_nci_recheck, dim3(64), dim3(256), 0, s, U, k, sums, phi_g, check_count, check_rows, labels, n,
-                     st, skip, round);
+                     st, skip, round, nullptr, 0);
   TPO_LAUNCH_CHECK();
+  return 0;
 }
 
 // Procrustes form of the Phi update: Phi = the orthogonal factor of the polar
@@ -1129,19 +1201,25 @@ static void nci_rounds_wide(const Plan& p, void* ws, hipStream_t s) {
     const double* ph = t == 1 ? nullptr : nci_phi(p, ws, sums, skip, s);
     if (ph) sm = nullptr;
     int32_t* c = cnt + (t - 1);
+    const bool acc = t < p.par.t_g;  // the last round's sums are not used
+    const int pcols = p.rowpass_blocks + 1;  // partial columns the workspace holds
+    int cols = 0;
     switch ((k + 15) / 16) {
-      case 3: nci_score_mfma<3>(U, n, k, sm, ph, labels, c, rows, st, skip, t, s); break;
-      case 4: nci_score_mfma<4>(U, n, k, sm, ph, labels, c, rows, st, skip, t, s); break;
-      case 5: nci_score_mfma<5>(U, n, k, sm, ph, labels, c, rows, st, skip, t, s); break;
-      case 6: nci_score_mfma<6>(U, n, k, sm, ph, labels, c, rows, st, skip, t, s); break;
-      case 7: nci_score_mfma<7>(U, n, k, sm, ph, labels, c, rows, st, skip, t, s); break;
-      case 8: nci_score_mfma<8>(U, n, k, sm, ph, labels, c, rows, st, skip, t, s); break;
+      case 3: cols = nci_score_mfma<3>(U, n, k, sm, ph, labels, c, rows, st, skip, t, part, pcols, acc, s); break;
+      case 4: cols = nci_score_mfma<4>(U, n, k, sm, ph, labels, c, rows, st, skip, t, part, pcols, acc, s); break;
+      case 5: cols = nci_score_mfma<5>(U, n, k, sm, ph, labels, c, rows, st, skip, t, part, pcols, acc, s); break;
+      case 6: cols = nci_score_mfma<6>(U, n, k, sm, ph, labels, c, rows, st, skip, t, part, pcols, acc, s); break;
+      case 7: cols = nci_score_mfma<7>(U, n, k, sm, ph, labels, c, rows, st, skip, t, part, pcols, acc, s); break;
+      case 8: cols = nci_score_mfma<8>(U, n, k, sm, ph, labels, c, rows, st, skip, t, part, pcols, acc, s); break;
       default: throw std::runtime_error("NCI: k outside 33..128 on the two-kernel path");
     }
-    if (t < p.par.t_g) {
-      hipLaunchKernelGGL(k_nci_accum_wide, dim3(nb), dim3(1024), acc_lds, s, U, n, k, labels, part, rpb, st, skip);
-      TPO_LAUNCH_CHECK();
-      sum_parts_i64(part, nb, k * k + k, sums, s, skip, t >= 2 ? changed + (t - 1) : nullptr);
+    if (acc) {
+      if (cols == 0) {
+        hipLaunchKernelGGL(k_nci_accum_wide, dim3(nb), dim3(1024), acc_lds, s, U, n, k, labels, part, rpb, st, skip);
+        TPO_LAUNCH_CHECK();
+        cols = nb;
+      }
+      sum_parts_i64(part, cols, k * k + k, sums, s, skip, t >= 2 ? changed + (t - 1) : nullptr);
     }
   }
 }

@@ -165,7 +165,7 @@ void build_layout(Plan& p) {
   add(B_A32, 4 * k * k);
   add(B_ONMF_PART, 8 * nbr * (twod * k + k * k));
   add(B_LABELS, 4 * n);
-  add(B_NCI_PART, 8 * nbr * (k * k + k));
+  add(B_NCI_PART, 8 * (nbr + 1) * (k * k + k));  // partial columns: workgroups, then rechecked rows
   add(B_NCI_SUM, 8 * (k * k + k));
   add(B_NCI_PHI, 8 * k * k);
   add(B_NCI_PM, 8 * k * k);

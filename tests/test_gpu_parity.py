@@ -407,10 +407,27 @@ def test_no_edges_and_tiny_graph():
 def test_isolated_nodes_keep_attributes():
     abg = synth.planted_abg(800, 600, 2000, 3, 16, zipf_a=2.5, seed=9)
     kw = dict(k=3, alpha=0.5, gamma=3, d=0)
-    out = gpu_run(abg, **kw)
+    out = gpu_run(abg, stages=False, **kw)
     iso = np.bincount(abg.edge_u, minlength=abg.n_u) == 0
     assert iso.sum() > 0
     assert np.allclose(out["z"][iso], 0.5 * abg.x_u[iso], rtol=1e-6, atol=0)
+    assert out["stats"]["isolated_u"] == int(iso.sum())
+    assert out["stats"]["isolated_v"] == int((np.bincount(abg.edge_v, minlength=abg.n_v) == 0).sum())
+
+
+def test_degrees_and_isolated_counts_many_rows():
+    """More rows than the degree kernel's fixed grid covers in one sweep
+    (2,048 workgroups of 256 rows), most of them isolated: every degree and
+    both isolated counts exact."""
+    abg = synth.planted_abg(700_000, 900_000, 150_000, 3, 8, zipf_a=2.0, seed=21)
+    out = gpu_run(abg, k=3, alpha=0.5, gamma=1, d=0, t_f=1, t_g=2, stages=False)
+    deg_u = np.bincount(abg.edge_u, minlength=abg.n_u)
+    deg_v = np.bincount(abg.edge_v, minlength=abg.n_v)
+    log(f"[many rows] isolated U {int((deg_u == 0).sum())} of {abg.n_u}, V {int((deg_v == 0).sum())} of {abg.n_v}")
+    assert np.array_equal(out["deg_u"], deg_u.astype(np.float32))
+    assert np.array_equal(out["deg_v"], deg_v.astype(np.float32))
+    assert out["stats"]["isolated_u"] == int((deg_u == 0).sum())
+    assert out["stats"]["isolated_v"] == int((deg_v == 0).sum())
 
 
 def test_error_paths():
