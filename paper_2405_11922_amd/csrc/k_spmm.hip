@@ -11,7 +11,7 @@
 // Kernel shape (d-wide FP32 rows, d a power of two): a neighbour row of d
 // floats is read by a group of d/4 lanes with float4 loads.  Ordinary rows
 // (at most kHubChunk neighbours) take one lane group each, so a wave works on
-// 64/(d/4) output rows at once and keeps several gathers in flight per lane;
+// 64/(d/4) output rows at once and keeps eight gathers in flight per lane;
 // their column ids come in with one load per group and are handed out with
 // cross-lane permutes.  Rows with more than kHubChunk neighbours are split
 // into chunks of one wave each, in the same launch; a second kernel adds the
@@ -117,7 +117,7 @@ template <int D>
 __device__ __forceinline__ float4 gather_row_group(const int32_t* __restrict__ col, const float* __restrict__ val,
                                                    bool has_vals, const float* __restrict__ src, int b, int e) {
   using S = SpmmShape<D>;
-  constexpr int U = S::LPR >= 16 ? 4 : 8;  // gathers in flight per lane
+  constexpr int U = 8;  // gathers in flight per lane
   const int lane = threadIdx.x & 63;
   const int q = lane % S::LPR;
   const int g0 = lane - q;  // first lane of this group
