@@ -26,12 +26,12 @@ namespace tpo {
 constexpr int kSiThreads = 512;  // 8 waves: one per 16-column tile, and one per tile below the diagonal (nb <= 8)
 constexpr int kSiBatch = 16;      // loads in flight per lane before they are used (A from global memory)
 constexpr int kSiWideBatch = 32;  // the same with A's row tile in LDS
-constexpr int kSiMaxGrid = 64;
+constexpr int kSiMaxGrid = 256;  // and at most the device's CU count
 constexpr size_t kLdsBytes = 160 * 1024;
 
-// Grid-wide barrier.  The grid is small (at most kSiMaxGrid workgroups, one
-// per CU at most), so every workgroup is resident once the CUs it waits for
-// are free; the launch does not depend on any later work.  bar[0] counts
+// Grid-wide barrier.  The grid has at most one workgroup per CU (and at most
+// kSiMaxGrid), so every workgroup is resident once the CUs it waits for are
+// free; the launch does not depend on any later work.  bar[0] counts
 // arrivals, bar[1] is the generation: the last workgroup to arrive resets
 // the count and advances the generation, the others wait for it to change.
 // Each workgroup's writes are released before it arrives and the others'
@@ -329,7 +329,15 @@ static void si_run(const double* A, int N, const double* omega, int l, int n_ort
                    double* gsum, double* part, unsigned* bar, double* m_out, double* p_out, int32_t* err_bits,
                    hipStream_t s) {
   const int nrt = (N + 15) / 16;
-  const int grid = std::min(nrt, kSiMaxGrid);
+  // one workgroup per CU at most, so that the whole grid is resident
+  static const int cus = [] {
+    int dev = 0, c = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c < 1)
+      c = 64;
+    return c;
+  }();
+  const int grid = std::min({nrt, kSiMaxGrid, cus});
   constexpr size_t kStatic = (16 * NB * (16 * NB + 1) + 16 * (16 * NB + 1) + 16 * NB) * sizeof(double) + 64;
   const size_t a_bytes = static_cast<size_t>(16) * (N + 1) * sizeof(double);
   const int a_lds = nrt <= grid && kStatic + a_bytes <= kLdsBytes ? 1 : 0;

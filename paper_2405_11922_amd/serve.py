@@ -13,8 +13,8 @@ job ends, so serving makes no device allocation per job.  Every kernel is
 deterministic, so a job's result does not depend on what runs beside it.
 
 The subspace-iteration kernel synchronises its workgroups with a grid
-barrier, so all of its workgroups (ceil(N / 16), at most 64, for the N x N
-Gram it iterates on) must be resident at once.  Admission therefore also
+barrier, so all of its workgroups (ceil(N / 16), at most 256 and at most one
+per CU, for the N x N Gram it iterates on) must be resident at once.  Admission therefore also
 keeps the barrier workgroups of the jobs in flight within the 256 CUs (one
 CU each at most), whatever the number of workers.
 
@@ -44,7 +44,7 @@ def barrier_workgroups(plan, d_u: int) -> int:
     reduction's (N = d_U, when it reduces) and the embedding's (N = 2 d_eff)."""
     d_eff, l_r, _ = tpo.tpo_plan_dims(plan)
     n_red = d_u if l_r > 0 else 0
-    return min(64, max((n_red + 15) // 16, (2 * d_eff + 15) // 16))
+    return min(BARRIER_CUS, max((n_red + 15) // 16, (2 * d_eff + 15) // 16))
 
 
 @dataclass
