@@ -180,40 +180,56 @@ typedef unsigned int v4u_t __attribute__((ext_vector_type(4)));
 //
 // A workgroup of 8 waves owns one 128 x 128 tile pair (ti <= tj) of the Gram
 // over one row chunk.  Each slab (256 bytes of every column: 128 BF16 rows or
-// 256 FP8 rows) of both column tiles is staged transposed in LDS (one
-// column's slab contiguous, stride kNColLd bytes), double-buffered, with the
-// next slab's global loads in flight in registers.  Wave w computes the
-// 64 x 32 block (rows 64 (w / 4) .., columns 32 (w % 4) ..) as 4 x 2 MFMA
-// tiles.  On a diagonal tile the two waves below the diagonal (w = 4, 5)
-// form the tile's column sums instead.  Operand layout: lane l supplies the
-// rows of k-group l / 16 of its column l % 16 for both operands (the same
-// rows for A and B, so the contraction does not depend on the order inside
-// the instruction); result v of lane l is D[4 (l / 16) + v][l % 16].
+// 256 FP8 rows) of both column tiles is staged row-major in LDS as it is read
+// (16-byte pieces of a row, row stride kNRowLd bytes), double-buffered, with
+// the next slab's global loads in flight in registers.  The MFMA operands,
+// which run down columns, come out of the row-major slab through gfx950's
+// transposing LDS reads: within each group of 16 lanes, ds_read_b64_tr_b16
+// gives lane j element j mod 4 of the 8-byte pieces read by lanes
+// 4 r + j / 4 (r = 0..3), and ds_read_b64_tr_b8 byte j mod 8 of those of
+// lanes 2 r + j / 8 (r = 0..7).  So when lane 4 r + q (2 r + q) points at row
+// r of a 4- (8-) row block, columns 4 q (8 q) on, lane j receives column j of
+// the block: two reads give a BF16 operand's 8 rows, four an FP8 operand's
+// 32.  Wave w computes the 64 x 32 block (rows 64 (w / 4) .., columns
+// 32 (w % 4) ..) as 4 x 2 MFMA tiles.  On a diagonal tile the two waves below
+// the diagonal (w = 4, 5) form the tile's column sums instead.  Operand
+// layout: lane l supplies the rows of k-group l / 16 of its column l % 16 for
+// both operands (the same rows for A and B, so the contraction does not
+// depend on the order inside the instruction); result v of lane l is
+// D[4 (l / 16) + v][l % 16].
 //
 // Workgroups are dispatched to the eight XCDs in turn (workgroup b runs on
 // XCD b % 8); every tile pair of one row chunk goes to the same XCD, so the
 // chunk's rows are fetched from memory about once per XCD and served to the
 // other pairs from its L2.  vec: X 16-byte aligned and the row stride a
 // multiple of 16 bytes (16-byte loads); otherwise element loads.
-constexpr int kNT = 128;                  // column tile
-constexpr int kNColB = 256;               // staged bytes of one column per slab
-constexpr int kNColLd = kNColB + 16;      // LDS stride of a staged column
-constexpr int kNOpBytes = kNT * kNColLd;  // one staged operand
-constexpr int kNFlush = 256;              // rows per FP32 block
+constexpr int kNT = 128;       // column tile
+constexpr int kNColB = 256;    // staged bytes of one column per slab
+constexpr int kNFlush = 256;   // rows per FP32 block
 typedef int v8i_t __attribute__((ext_vector_type(8)));
+typedef int v2i_t __attribute__((ext_vector_type(2)));
+typedef short v4s_t __attribute__((ext_vector_type(4)));
+typedef short v8s_t __attribute__((ext_vector_type(8)));
+typedef __attribute__((address_space(3))) v2i_t lds_v2i_t;
+typedef __attribute__((address_space(3))) v4s_t lds_v4s_t;
 
-// 4 x 4 byte transpose: out[e] holds byte e of in[0], in[1], in[2], in[3] (in
-// that byte order), by v_perm_b32 (byte i of the result is byte sel_i of the
-// 8-byte value {hi : lo}).
-__device__ __forceinline__ void transpose4x4(const uint32_t (&in)[4], uint32_t (&out)[4]) {
-  const uint32_t x0 = __builtin_amdgcn_perm(in[1], in[0], 0x05010400u);  // in0.b0 in1.b0 in0.b1 in1.b1
-  const uint32_t x1 = __builtin_amdgcn_perm(in[1], in[0], 0x07030602u);  // in0.b2 in1.b2 in0.b3 in1.b3
-  const uint32_t y0 = __builtin_amdgcn_perm(in[3], in[2], 0x05010400u);
-  const uint32_t y1 = __builtin_amdgcn_perm(in[3], in[2], 0x07030602u);
-  out[0] = __builtin_amdgcn_perm(y0, x0, 0x05040100u);
-  out[1] = __builtin_amdgcn_perm(y0, x0, 0x07060302u);
-  out[2] = __builtin_amdgcn_perm(y1, x1, 0x05040100u);
-  out[3] = __builtin_amdgcn_perm(y1, x1, 0x07060302u);
+// LDS row stride of a staged slab (bytes): 128 columns, then padding that
+// puts the rows one transposing read touches (4 of 32 bytes for BF16, 8 of
+// 16 bytes for FP8) in distinct banks
+template <int ES>
+__host__ __device__ constexpr int narrow_row_ld() { return ES == 2 ? 2 * kNT + 32 : kNT + 16; }
+// bytes of one staged operand (a slab of one column tile)
+template <int ES>
+__host__ __device__ constexpr int narrow_op_bytes() { return (kNColB / ES) * narrow_row_ld<ES>(); }
+
+// the transposing LDS reads at a byte offset of an LDS array
+__device__ __forceinline__ v2i_t lds_tr8(const uint8_t* lds_base, int off) {
+  return __builtin_amdgcn_ds_read_tr8_b64_v2i32(
+      (lds_v2i_t*)((__attribute__((address_space(3))) uint8_t*)(lds_base) + off));
+}
+__device__ __forceinline__ v4s_t lds_tr16(const uint8_t* lds_base, int off) {
+  return __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+      (lds_v4s_t*)((__attribute__((address_space(3))) uint8_t*)(lds_base) + off));
 }
 
 // An FP8 E4M3 attribute (raw byte) as FP32, exactly.
@@ -227,12 +243,13 @@ k_gram_narrow(const uint8_t* __restrict__ X, int64_t n, int c, int64_t ldx, int 
               int nchunks, int vec, double* __restrict__ part, double* __restrict__ colsum_part, int accumulate) {
   constexpr int ES = FMT == 1 ? 2 : 1;  // bytes per element
   constexpr int SR = kNColB / ES;       // rows per slab
-  constexpr int EPG = 16 / ES;          // elements per 16-byte group
-  constexpr int HR = 8;                 // rows a staging thread moves
-  constexpr int RG = SR / HR;           // row groups per slab
+  constexpr int EPG = 16 / ES;          // elements per 16-byte piece
+  constexpr int CPR = kNT / EPG;        // 16-byte pieces per row of a column tile
+  constexpr int HR = SR * CPR / 256;    // pieces a staging thread moves (8)
   constexpr int KS = FMT == 1 ? SR / 32 : SR / 128;  // MFMA k steps per slab
   constexpr int FLUSH_SLABS = kNFlush / SR;
-  __shared__ __align__(16) uint8_t lds[2 * 2 * kNOpBytes];  // [buffer][operand]
+  constexpr int RLD = narrow_row_ld<ES>(), OPB = narrow_op_bytes<ES>();
+  __shared__ __align__(16) uint8_t lds[2 * 2 * OPB];  // [buffer][operand]
   const int npairs = ntiles * (ntiles + 1) / 2;
   const int b = blockIdx.x;
   const int xcd = b % 8, slot = b / 8;
@@ -256,18 +273,18 @@ k_gram_narrow(const uint8_t* __restrict__ X, int64_t n, int c, int64_t ldx, int 
   const int nslabs = r_end > r_beg ? static_cast<int>((r_end - r_beg + SR - 1) / SR) : 0;
 
   // staging: threads 0..255 stage column tile ti, 256..511 tile tj (idle on a
-  // diagonal tile); thread (rg, cg) moves rows 8 rg .. 8 rg + 7 of the
-  // 16-byte column group cg (consecutive lanes take consecutive row groups, so
-  // the transposed LDS stores of one instruction fall in distinct banks)
+  // diagonal tile); piece e = sb + 256 h of the slab is 16-byte piece e % CPR
+  // of row e / CPR (consecutive threads read consecutive pieces of a row)
   const int op = tid >> 8, sb = tid & 255;
   const bool loader = !(diag && op == 1);
-  const int rg = sb % RG, cg = sb / RG;
-  const int gcol = (op ? tj : ti) * kNT + cg * EPG;  // first column of the group
-  uint32_t pre[HR][4];  // rows HR rg + h, 16 bytes each
+  const int tcol0 = (op ? tj : ti) * kNT;  // first column of the staged tile
+  uint32_t pre[HR][4];
   auto fetch = [&](int64_t r0, uint32_t (&pf)[HR][4]) {
 #pragma unroll
     for (int h = 0; h < HR; ++h) {
-      const int64_t row = r0 + HR * rg + h;
+      const int e = sb + 256 * h;
+      const int64_t row = r0 + e / CPR;
+      const int gcol = tcol0 + (e % CPR) * EPG;
 #pragma unroll
       for (int d = 0; d < 4; ++d) pf[h][d] = 0u;
       if (!loader || row >= r_end || gcol >= c) continue;
@@ -278,46 +295,29 @@ k_gram_narrow(const uint8_t* __restrict__ X, int64_t n, int c, int64_t ldx, int 
         for (int d = 0; d < 4; ++d) pf[h][d] = v[d];
       } else {
 #pragma unroll
-        for (int e = 0; e < EPG; ++e) {
-          if (gcol + e >= c) break;
-          const uint32_t val = ES == 2 ? static_cast<uint32_t>(reinterpret_cast<const uint16_t*>(src)[e])
-                                       : static_cast<uint32_t>(src[e]);
-          pf[h][(e * ES) / 4] |= val << (8 * ((e * ES) % 4));
+        for (int el = 0; el < EPG; ++el) {
+          if (gcol + el >= c) break;
+          const uint32_t val = ES == 2 ? static_cast<uint32_t>(reinterpret_cast<const uint16_t*>(src)[el])
+                                       : static_cast<uint32_t>(src[el]);
+          pf[h][(el * ES) / 4] |= val << (8 * ((el * ES) % 4));
         }
       }
     }
   };
   auto store = [&](int buf, const uint32_t (&ps)[HR][4]) {
     if (!loader) return;
-    uint8_t* base = lds + (2 * buf + op) * kNOpBytes;
-    if constexpr (FMT == 1) {
-      // column 2 d + e: word p holds rows 2 p (low half) and 2 p + 1
+    uint8_t* base = lds + (2 * buf + op) * OPB;
 #pragma unroll
-      for (int d = 0; d < 4; ++d)
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-          const uint32_t sel = e ? 0x07060302u : 0x05040100u;
-          v4u_t v;
-#pragma unroll
-          for (int q = 0; q < 4; ++q) v[q] = __builtin_amdgcn_perm(ps[2 * q + 1][d], ps[2 * q][d], sel);
-          *reinterpret_cast<v4u_t*>(base + (cg * EPG + 2 * d + e) * kNColLd + 16 * rg) = v;
-        }
-    } else {
-      // column 4 d + e: rows 0..3 from one 4 x 4 transpose, rows 4..7 from another
-#pragma unroll
-      for (int d = 0; d < 4; ++d) {
-        const uint32_t lo_in[4] = {ps[0][d], ps[1][d], ps[2][d], ps[3][d]};
-        const uint32_t hi_in[4] = {ps[4][d], ps[5][d], ps[6][d], ps[7][d]};
-        uint32_t lo[4], hi[4];
-        transpose4x4(lo_in, lo);
-        transpose4x4(hi_in, hi);
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          *reinterpret_cast<uint2*>(base + (cg * EPG + 4 * d + e) * kNColLd + 8 * rg) = make_uint2(lo[e], hi[e]);
-      }
+    for (int h = 0; h < HR; ++h) {
+      const int e = sb + 256 * h;
+      *reinterpret_cast<v4u_t*>(base + (e / CPR) * RLD + (e % CPR) * 16) =
+          v4u_t{ps[h][0], ps[h][1], ps[h][2], ps[h][3]};
     }
   };
-
+  // lane offsets of the transposing reads inside a 16-lane group: the row
+  // within the block and the byte offset of the lane's 8-byte piece
+  const int tr_row = ES == 2 ? (i16 >> 2) : (i16 >> 1);
+  const int tr_col = ES == 2 ? 8 * (i16 & 3) : 8 * (i16 & 1);
   v4f_t s32[4][2];
   v4d_t acc[4][2];
 #pragma unroll
@@ -331,19 +331,26 @@ k_gram_narrow(const uint8_t* __restrict__ X, int64_t n, int c, int64_t ldx, int 
   const int a_col = 64 * qa + i16, b_col = 32 * qb + i16;
 
   auto mma = [&](int buf) {
-    const uint8_t* la = lds + (2 * buf) * kNOpBytes;
-    const uint8_t* lb = diag ? la : la + kNOpBytes;
+    const uint8_t* la = lds + (2 * buf) * OPB;
+    const uint8_t* lb = diag ? la : la + OPB;
     if constexpr (FMT == 1) {
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
-        const int off = 64 * ks + 16 * kq;
+        // rows 32 ks + 8 kq + (0..3), then + 4
+        const int roff = (32 * ks + 8 * kq + tr_row) * RLD + tr_col;
         v8bf_t av[4], bv[2];
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
-          av[m] = __builtin_bit_cast(v8bf_t, *reinterpret_cast<const v4u_t*>(la + (a_col + 16 * m) * kNColLd + off));
+        for (int m = 0; m < 4; ++m) {
+          const int off = roff + 2 * (64 * qa + 16 * m);
+          const v4s_t lo = lds_tr16(la, off), hi = lds_tr16(la, off + 4 * RLD);
+          av[m] = __builtin_bit_cast(v8bf_t, v8s_t{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]});
+        }
 #pragma unroll
-        for (int mb = 0; mb < 2; ++mb)
-          bv[mb] = __builtin_bit_cast(v8bf_t, *reinterpret_cast<const v4u_t*>(lb + (b_col + 16 * mb) * kNColLd + off));
+        for (int mb = 0; mb < 2; ++mb) {
+          const int off = roff + 2 * (32 * qb + 16 * mb);
+          const v4s_t lo = lds_tr16(lb, off), hi = lds_tr16(lb, off + 4 * RLD);
+          bv[mb] = __builtin_bit_cast(v8bf_t, v8s_t{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]});
+        }
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -353,61 +360,68 @@ k_gram_narrow(const uint8_t* __restrict__ X, int64_t n, int c, int64_t ldx, int 
     } else {
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
-        const int off = 128 * ks + 32 * kq;
+        // rows 128 ks + 32 kq + 8 h + (0..7), h = 0..3
+        const int roff = (128 * ks + 32 * kq + tr_row) * RLD + tr_col;
         v8i_t av[4], bv[2];
-  #pragma unroll
+#pragma unroll
         for (int m = 0; m < 4; ++m) {
-          const v4u_t lo = *reinterpret_cast<const v4u_t*>(la + (a_col + 16 * m) * kNColLd + off);
-          const v4u_t hi = *reinterpret_cast<const v4u_t*>(la + (a_col + 16 * m) * kNColLd + off + 16);
-          av[m] = v8i_t{static_cast<int>(lo[0]), static_cast<int>(lo[1]), static_cast<int>(lo[2]), static_cast<int>(lo[3]),
-                        static_cast<int>(hi[0]), static_cast<int>(hi[1]), static_cast<int>(hi[2]), static_cast<int>(hi[3])};
+          const int off = roff + 64 * qa + 16 * m;
+          const v2i_t x0 = lds_tr8(la, off), x1 = lds_tr8(la, off + 8 * RLD);
+          const v2i_t x2 = lds_tr8(la, off + 16 * RLD), x3 = lds_tr8(la, off + 24 * RLD);
+          av[m] = v8i_t{x0[0], x0[1], x1[0], x1[1], x2[0], x2[1], x3[0], x3[1]};
         }
-  #pragma unroll
+#pragma unroll
         for (int mb = 0; mb < 2; ++mb) {
-          const v4u_t lo = *reinterpret_cast<const v4u_t*>(lb + (b_col + 16 * mb) * kNColLd + off);
-          const v4u_t hi = *reinterpret_cast<const v4u_t*>(lb + (b_col + 16 * mb) * kNColLd + off + 16);
-          bv[mb] = v8i_t{static_cast<int>(lo[0]), static_cast<int>(lo[1]), static_cast<int>(lo[2]), static_cast<int>(lo[3]),
-                         static_cast<int>(hi[0]), static_cast<int>(hi[1]), static_cast<int>(hi[2]), static_cast<int>(hi[3])};
+          const int off = roff + 32 * qb + 16 * mb;
+          const v2i_t x0 = lds_tr8(lb, off), x1 = lds_tr8(lb, off + 8 * RLD);
+          const v2i_t x2 = lds_tr8(lb, off + 16 * RLD), x3 = lds_tr8(lb, off + 24 * RLD);
+          bv[mb] = v8i_t{x0[0], x0[1], x1[0], x1[1], x2[0], x2[1], x3[0], x3[1]};
         }
         // formats 0 (E4M3) for both operands; block scales 127 (2^0)
-  #pragma unroll
+#pragma unroll
         for (int m = 0; m < 4; ++m)
-  #pragma unroll
+#pragma unroll
           for (int mb = 0; mb < 2; ++mb)
             s32[m][mb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(av[m], bv[mb], s32[m][mb], 0, 0, 0, 127,
                                                                           0, 127);
       }
     }
   };
-  // column sums of the staged slab: BF16 in FP32 groups of 8 rows, E4M3 in
-  // FP32 groups of 64 rows (exact: E4M3 values are multiples of 2^-9 below
-  // 2^9, so 64 of them sum below 2^24 units), each group added into FP64
+  // column sums of the staged slab (column 64 qb + lane of tile ti, read
+  // down the column with the same transposing reads): BF16 in FP32 groups of
+  // 8 rows, E4M3 in FP32 groups of 64 rows (exact: E4M3 values are multiples
+  // of 2^-9 below 2^9, so 64 of them sum below 2^24 units), each group added
+  // into FP64
   auto colsum = [&](int buf) {
-    const uint8_t* col = lds + (2 * buf) * kNOpBytes + (64 * qb + lane) * kNColLd;
+    const uint8_t* la = lds + (2 * buf) * OPB;
+    const int coff = tr_row * RLD + tr_col + ES * (64 * qb + 16 * kq);  // this lane's column: 64 qb + lane
     if constexpr (FMT == 1) {
 #pragma unroll
       for (int g = 0; g < SR / 8; ++g) {
-        const v4u_t v = *reinterpret_cast<const v4u_t*>(col + 16 * g);
-        float s = 0.0f;
+        const v4s_t lo = lds_tr16(la, coff + 8 * g * RLD), hi = lds_tr16(la, coff + (8 * g + 4) * RLD);
+        const short x[8] = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+        float sg = 0.0f;
 #pragma unroll
-        for (int d = 0; d < 4; ++d) s += __uint_as_float(v[d] << 16) + __uint_as_float(v[d] & 0xffff0000u);
-        cs += static_cast<double>(s);
+        for (int d = 0; d < 4; ++d)
+          sg += __uint_as_float(static_cast<uint32_t>(static_cast<uint16_t>(x[2 * d])) << 16) +
+                __uint_as_float(static_cast<uint32_t>(static_cast<uint16_t>(x[2 * d + 1])) << 16);
+        cs += static_cast<double>(sg);
       }
     } else {
 #pragma unroll
       for (int hgrp = 0; hgrp < SR / 64; ++hgrp) {
-        float s = 0.0f;
+        float sg = 0.0f;
 #pragma unroll
-        for (int g = 0; g < 4; ++g) {
-          const v4u_t v = *reinterpret_cast<const v4u_t*>(col + 64 * hgrp + 16 * g);
+        for (int g = 0; g < 8; ++g) {
+          const v2i_t x = lds_tr8(la, coff + (64 * hgrp + 8 * g) * RLD);
 #pragma unroll
-          for (int d = 0; d < 4; ++d) {
-            const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8(static_cast<int>(v[d]), false);
-            const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8(static_cast<int>(v[d]), true);
-            s += (lo[0] + lo[1]) + (hi[0] + hi[1]);
+          for (int d = 0; d < 2; ++d) {
+            const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8(x[d], false);
+            const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8(x[d], true);
+            sg += (lo[0] + lo[1]) + (hi[0] + hi[1]);
           }
         }
-        cs += static_cast<double>(s);
+        cs += static_cast<double>(sg);
       }
     }
   };
