@@ -227,7 +227,7 @@ k_rowpass_mfma(const float* __restrict__ R, int64_t n, int twod, int k, const fl
       const int rl0 = rw + 4 * kq;
       const int left = static_cast<int>(min<int64_t>(re - (r0 + rl0), 4));  // rows of the lane's four that exist
       float* ob = (MODE == kProject ? out : U) + (r0 + rl0) * k;
-      float* ob2 = MODE == kProject ? out2 + (r0 + rl0) * k : nullptr;
+      float* ob2 = out2 ? out2 + (r0 + rl0) * k : nullptr;  // a second copy (kProject: Upsilon; kOnmf: the output)
 #pragma unroll
       for (int i = 0; i < KTW; ++i) {
         const int kt = kt0 + i * WPR;
@@ -253,7 +253,7 @@ k_rowpass_mfma(const float* __restrict__ R, int64_t n, int twod, int k, const fl
             bad = bad || !isfinite(o);
             mx = fmaxf(mx, fabsf(o));
             ob[v * k + c] = o;
-            if (MODE == kProject) ob2[v * k + c] = o;
+            if (ob2) ob2[v * k + c] = o;
           }
         }
       }
@@ -388,7 +388,8 @@ k_onmf_a(const double* __restrict__ rtu_utu, int twod, int k, const double* __re
 }
 
 template <int JT, int KT>
-static void rowpass_jk(const Plan& p, void* ws, int mode, const float* Sm, const float* A32, hipStream_t s) {
+static void rowpass_jk(const Plan& p, void* ws, int mode, const float* Sm, const float* A32, float* copy,
+                       hipStream_t s) {
   DevStatus* st = bufp<DevStatus>(p, ws, B_STATUS);
   const int nb = p.rowpass_blocks;
   const int rpb = static_cast<int>((p.n + nb - 1) / nb);
@@ -400,47 +401,49 @@ static void rowpass_jk(const Plan& p, void* ws, int mode, const float* Sm, const
   else
     hipLaunchKernelGGL((k_rowpass_mfma<kOnmf, JT, KT>), dim3(nb), dim3(64 * rp_waves(JT, KT)), 0, s, bufp<float>(p, ws, B_R),
                        static_cast<int64_t>(p.n), p.twod, p.k, Sm, A32, bufp<float>(p, ws, B_UPS), nullptr,
-                       nullptr, rpb, bufp<double>(p, ws, B_ONMF_PART), st);
+                       copy, rpb, bufp<double>(p, ws, B_ONMF_PART), st);
   TPO_LAUNCH_CHECK();
 }
 
 template <int JT>
-static void rowpass_j(const Plan& p, void* ws, int mode, const float* Sm, const float* A32, hipStream_t s) {
+static void rowpass_j(const Plan& p, void* ws, int mode, const float* Sm, const float* A32, float* copy,
+                      hipStream_t s) {
   if (p.k <= 16)
-    rowpass_jk<JT, 1>(p, ws, mode, Sm, A32, s);
+    rowpass_jk<JT, 1>(p, ws, mode, Sm, A32, copy, s);
   else if (p.k <= 32)
-    rowpass_jk<JT, 2>(p, ws, mode, Sm, A32, s);
+    rowpass_jk<JT, 2>(p, ws, mode, Sm, A32, copy, s);
   else if (p.k <= 64)
-    rowpass_jk<JT, 4>(p, ws, mode, Sm, A32, s);
+    rowpass_jk<JT, 4>(p, ws, mode, Sm, A32, copy, s);
   else if (p.k <= 80)
-    rowpass_jk<JT, 5>(p, ws, mode, Sm, A32, s);
+    rowpass_jk<JT, 5>(p, ws, mode, Sm, A32, copy, s);
   else if (p.k <= 96)
-    rowpass_jk<JT, 6>(p, ws, mode, Sm, A32, s);
+    rowpass_jk<JT, 6>(p, ws, mode, Sm, A32, copy, s);
   else if (p.k <= 112)
-    rowpass_jk<JT, 7>(p, ws, mode, Sm, A32, s);
+    rowpass_jk<JT, 7>(p, ws, mode, Sm, A32, copy, s);
   else
-    rowpass_jk<JT, 8>(p, ws, mode, Sm, A32, s);
+    rowpass_jk<JT, 8>(p, ws, mode, Sm, A32, copy, s);
 }
 
-static void rowpass_any(const Plan& p, void* ws, int mode, const float* Sm, const float* A32, hipStream_t s) {
+static void rowpass_any(const Plan& p, void* ws, int mode, const float* Sm, const float* A32, float* copy,
+                        hipStream_t s) {
   if (p.twod <= 16)
-    rowpass_j<1>(p, ws, mode, Sm, A32, s);
+    rowpass_j<1>(p, ws, mode, Sm, A32, copy, s);
   else if (p.twod <= 32)
-    rowpass_j<2>(p, ws, mode, Sm, A32, s);
+    rowpass_j<2>(p, ws, mode, Sm, A32, copy, s);
   else if (p.twod <= 64)
-    rowpass_j<4>(p, ws, mode, Sm, A32, s);
+    rowpass_j<4>(p, ws, mode, Sm, A32, copy, s);
   else if (p.twod <= 128)
-    rowpass_j<8>(p, ws, mode, Sm, A32, s);
+    rowpass_j<8>(p, ws, mode, Sm, A32, copy, s);
   else
-    rowpass_j<16>(p, ws, mode, Sm, A32, s);
+    rowpass_j<16>(p, ws, mode, Sm, A32, copy, s);
 }
 
-void launch_onmf(const Plan& p, void* ws, hipStream_t s) {
+void launch_onmf(const Plan& p, void* ws, hipStream_t s, float* emb_out) {
   DevStatus* st = bufp<DevStatus>(p, ws, B_STATUS);
   const int len = p.twod * p.k + p.k * p.k;
   double* rtu = bufp<double>(p, ws, B_RTU);
   // Gamma = R S, Upsilon = Gamma, and R^T Ups, Ups^T Ups for the first round
-  rowpass_any(p, ws, kProject, bufp<float>(p, ws, B_S32), nullptr, s);
+  rowpass_any(p, ws, kProject, bufp<float>(p, ws, B_S32), nullptr, nullptr, s);
   for (int t = 0; t < p.par.t_f; ++t) {
     reduce_parts(bufp<double>(p, ws, B_ONMF_PART), p.rowpass_blocks, len, bufp<double>(p, ws, B_REDTMP), rtu, s);
     const int nh = p.twod * p.k, na = std::max(nh, p.k * p.k);
@@ -451,7 +454,9 @@ void launch_onmf(const Plan& p, void* ws, hipStream_t s) {
                        bufp<double>(p, ws, B_H_NEW), bufp<double>(p, ws, B_H), bufp<float>(p, ws, B_H32),
                        bufp<float>(p, ws, B_A32));
     TPO_LAUNCH_CHECK();
-    rowpass_any(p, ws, kOnmf, bufp<float>(p, ws, B_H32), bufp<float>(p, ws, B_A32), s);
+    // the last round also writes Upsilon to the caller's embedding
+    rowpass_any(p, ws, kOnmf, bufp<float>(p, ws, B_H32), bufp<float>(p, ws, B_A32),
+                t + 1 == p.par.t_f ? emb_out : nullptr, s);
   }
 }
 

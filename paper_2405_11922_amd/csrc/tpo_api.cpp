@@ -368,7 +368,9 @@ tpo_status tpo::execute_plan(tpo_plan* plan, const tpo_inputs* in, void* ws, siz
     mark(4);
     launch_embed(*plan, ws, s);
     mark(5);
-    launch_onmf(*plan, ws, s);
+    // with ONMF rounds to run, the last one writes the output embedding too
+    float* emb_direct = plan->par.t_f >= 1 ? static_cast<float*>(out->embedding) : nullptr;
+    launch_onmf(*plan, ws, s, emb_direct);
     mark(6);
     launch_nci(*plan, ws, s);
     mark(7);
@@ -376,7 +378,7 @@ tpo_status tpo::execute_plan(tpo_plan* plan, const tpo_inputs* in, void* ws, siz
     mark(8);
     TPO_HIP_CHECK(hipMemcpyAsync(out->labels, bufp<int32_t>(*plan, ws, B_LABELS), sizeof(int32_t) * plan->n,
                                  hipMemcpyDeviceToDevice, s));
-    if (out->embedding)
+    if (out->embedding && !emb_direct)
       TPO_HIP_CHECK(hipMemcpyAsync(out->embedding, bufp<float>(*plan, ws, B_UPS),
                                    sizeof(float) * static_cast<size_t>(plan->n) * plan->k, hipMemcpyDeviceToDevice, s));
     TPO_HIP_CHECK(hipMemcpyAsync(&host, bufp<char>(*plan, ws, B_STATUS), sizeof(host), hipMemcpyDeviceToHost, s));

@@ -240,7 +240,8 @@ void embed_final_wide(double* M, double* P, int twod, int kp, int k, const doubl
 // deterministic two-level sum of nparts rows of length len (k_dense.hip)
 void reduce_parts(const double* part, int nparts, int len, double* tmp, double* out, hipStream_t s);
 // k_cluster.hip
-void launch_onmf(const Plan& p, void* ws, hipStream_t s);
+// emb_out: also written with Upsilon by the last ONMF round (or null)
+void launch_onmf(const Plan& p, void* ws, hipStream_t s, float* emb_out = nullptr);
 void launch_nci(const Plan& p, void* ws, hipStream_t s);
 void launch_objective(const Plan& p, void* ws, hipStream_t s);
 

@@ -413,6 +413,8 @@ def test_isolated_nodes_keep_attributes():
     assert np.allclose(out["z"][iso], 0.5 * abg.x_u[iso], rtol=1e-6, atol=0)
     assert out["stats"]["isolated_u"] == int(iso.sum())
     assert out["stats"]["isolated_v"] == int((np.bincount(abg.edge_v, minlength=abg.n_v) == 0).sum())
+    # the embedding tpo_execute hands back is the final Upsilon, bit for bit
+    assert np.array_equal(out["embedding"], out["upsilon"])
 
 
 def test_degrees_and_isolated_counts_many_rows():
@@ -428,6 +430,7 @@ def test_degrees_and_isolated_counts_many_rows():
     assert np.array_equal(out["deg_v"], deg_v.astype(np.float32))
     assert out["stats"]["isolated_u"] == int((deg_u == 0).sum())
     assert out["stats"]["isolated_v"] == int((deg_v == 0).sum())
+    assert np.array_equal(out["embedding"], out["upsilon"])  # one ONMF round: written by that round
 
 
 def test_error_paths():
