@@ -8,6 +8,7 @@
 // and the cluster sums of R in the objective) use 64-bit fixed point so that
 // their result does not depend on the order of the atomic additions.
 #include <algorithm>
+#include <type_traits>
 #include <mutex>
 
 #include "blk_linalg.hpp"
@@ -85,6 +86,13 @@ k_rowpass_mfma(const float* __restrict__ R, int64_t n, int twod, int k, const fl
   constexpr int ROWS = R64 ? kRpRows : kRpRows / 2;
   constexpr int RTILES = ROWS / 16, WPR = kRpWaves / RTILES;  // waves per row tile
   constexpr int KTW = (KT + WPR - 1) / WPR;                    // column tiles per wave
+  // Splitting one tile pair between two SIMDs: when exactly one wave per row
+  // tile has no last tile (KT = 7 over four waves), that wave (the helper)
+  // forms the P of the last tile of the wave before it (the owner), which
+  // forms only that tile's Q and takes its P from LDS: the SIMDs then carry
+  // 208 / 212 MFMAs per slab instead of 240 / 240 with a repeated tile pair.
+  constexpr int RLAST = KT - (KTW - 1) * WPR;  // waves per row tile with a last tile
+  constexpr bool SPLIT = MODE == kOnmf && KTW >= 2 && RLAST == WPR - 1;
   // slab prefetch: thread tid loads column tid % TD (of U: tid % KP) of
   // slab rows tid / TD + RSTEP u (tid / KP + USTEP u), RPT (UPT) values
   constexpr int RSTEP = kRpThreads / TD, USTEP = kRpThreads / KP;
@@ -93,6 +101,7 @@ k_rowpass_mfma(const float* __restrict__ R, int64_t n, int twod, int k, const fl
   __shared__ __align__(16) float Ut[ROWS * OS];
   __shared__ __align__(16) float Ss[SLDS ? KP * SS : 4];  // S^T (or H^T): Ss[c * SS + r] = S[r][c], zero padded
   __shared__ __align__(16) float As[ALDS ? KP * AS : 4];  // A^T (kOnmf): As[c * AS + t] = A[t][c], zero padded
+  __shared__ float Pex[SPLIT ? RTILES * 256 : 1];          // the helpers' P tiles, one per row tile
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int i16 = lane & 15, kq = lane >> 4;
@@ -195,31 +204,57 @@ k_rowpass_mfma(const float* __restrict__ R, int64_t n, int twod, int k, const fl
     // discarded), so that no MFMA sits behind a branch
     constexpr bool LIGHT = RPT + UPT <= 24;  // the slab prefetch holds few registers
     constexpr int UNS = SLDS && LIGHT ? 2 : 1, UNA = ALDS && LIGHT ? 2 : 1;
+    // P over the first NS of the wave's tiles
+    auto p_loop = [&](auto ns_c) {
+      constexpr int NS = decltype(ns_c)::value;
 #pragma unroll UNS
-    for (int m = 0; m < JT; ++m) {
-      const v4f_t a = *reinterpret_cast<const v4f_t*>(&Rt[(rw + i16) * RS + 16 * m + 4 * kq]);
-      v4f_t b[KTW];
+      for (int m = 0; m < JT; ++m) {
+        const v4f_t a = *reinterpret_cast<const v4f_t*>(&Rt[(rw + i16) * RS + 16 * m + 4 * kq]);
+        v4f_t b[NS];
 #pragma unroll
-      for (int i = 0; i < KTW; ++i) b[i] = s_frag(m, min(kt0 + i * WPR, KT - 1));
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-#pragma unroll
-        for (int i = 0; i < KTW; ++i) pv[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], b[i][j], pv[i], 0, 0, 0);
-    }
-    if (MODE == kOnmf) {
-#pragma unroll UNA
-      for (int m = 0; m < KT; ++m) {
-        const v4f_t a = *reinterpret_cast<const v4f_t*>(&Ut[(rw + i16) * OS + 16 * m + 4 * kq]);
-        v4f_t b[KTW];
-#pragma unroll
-        for (int i = 0; i < KTW; ++i) b[i] = a_frag(m, min(kt0 + i * WPR, KT - 1));
+        for (int i = 0; i < NS; ++i) b[i] = s_frag(m, min(kt0 + i * WPR, KT - 1));
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
-          for (int i = 0; i < KTW; ++i) qv[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], b[i][j], qv[i], 0, 0, 0);
+          for (int i = 0; i < NS; ++i) pv[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], b[i][j], pv[i], 0, 0, 0);
       }
-      // every wave has read the U slab; O replaces it
+    };
+    // Q over the first NS of the wave's tiles
+    auto q_loop = [&](auto ns_c) {
+      constexpr int NS = decltype(ns_c)::value;
+#pragma unroll UNA
+      for (int m = 0; m < KT; ++m) {
+        const v4f_t a = *reinterpret_cast<const v4f_t*>(&Ut[(rw + i16) * OS + 16 * m + 4 * kq]);
+        v4f_t b[NS];
+#pragma unroll
+        for (int i = 0; i < NS; ++i) b[i] = a_frag(m, min(kt0 + i * WPR, KT - 1));
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int i = 0; i < NS; ++i) qv[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], b[i][j], qv[i], 0, 0, 0);
+      }
+    };
+    const bool owner = SPLIT && kt0 == RLAST - 1, helper = SPLIT && kt0 == RLAST;  // wave-uniform
+    constexpr int KTS = SPLIT ? KTW - 1 : KTW;  // tiles of the owner's P and the helper's Q
+    if (owner)
+      p_loop(std::integral_constant<int, KTS>{});
+    else
+      p_loop(std::integral_constant<int, KTW>{});
+    if (MODE == kOnmf) {
+      if (helper) {
+        // the owner's last tile is this wave's repeated slot: hand its P over
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Pex[(rw / 16) * 256 + (4 * kq + v) * 16 + i16] = pv[KTW - 1][v];
+        q_loop(std::integral_constant<int, KTS>{});
+      } else {
+        q_loop(std::integral_constant<int, KTW>{});
+      }
+      // every wave has read the U slab (and the helpers' P tiles are in LDS);
+      // O replaces U
       __syncthreads();
+      if (owner)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) pv[KTW - 1][v] = Pex[(rw / 16) * 256 + (4 * kq + v) * 16 + i16];
     }
     // O, without branches: the ratio as P times the hardware reciprocal and
     // its hardware square root (each within about one unit in the last place)
