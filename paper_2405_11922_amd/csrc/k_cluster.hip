@@ -52,8 +52,11 @@ constexpr int kRpRows = 64;
 // with k > 64 the registers would not fit two waves a SIMD).
 __host__ __device__ constexpr int rp_waves(int jt, int kt) { return (kt >= 5 && jt * kt <= 64) ? 8 : 4; }
 // Waves per SIMD the registers must allow: two, except where a workgroup of
-// four carries 2d = 256 and k > 64.
-__host__ __device__ constexpr int rp_occupancy(int jt, int kt) { return jt * kt > 64 ? 1 : 2; }
+// four carries 2d >= 128 with k in 33..64 (its 64-row slabs need more than
+// half a SIMD's registers) or 2d = 256 with k > 64.
+__host__ __device__ constexpr int rp_occupancy(int jt, int kt) {
+  return (jt * kt > 64 || (kt == 4 && jt >= 8)) ? 1 : 2;
+}
 
 template <int MODE, int JT, int KT>
 __global__ void __launch_bounds__(64 * rp_waves(JT, KT)) __attribute__((amdgpu_waves_per_eu(rp_occupancy(JT, KT))))

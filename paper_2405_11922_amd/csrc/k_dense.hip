@@ -328,7 +328,6 @@ k_gram_narrow(const uint8_t* __restrict__ X, int64_t n, int c, int64_t ldx, int 
       acc[m][mb] = v4d_t{0.0, 0.0, 0.0, 0.0};
     }
   double cs = 0.0;  // column sum of column 64 qb + lane (colsum waves)
-  const int a_col = 64 * qa + i16, b_col = 32 * qb + i16;
 
   auto mma = [&](int buf) {
     const uint8_t* la = lds + (2 * buf) * OPB;

@@ -252,8 +252,6 @@ k_si_fused(const double* __restrict__ A, int N, const double* __restrict__ omega
   __shared__ double dinv[NP];
   __shared__ int flag;
   extern __shared__ double As_dyn[];  // a_lds: rows 16 b .. 16 b + 15 of A (stride N + 1), b = blockIdx.x
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int i16 = lane & 15, kq = lane >> 4;
   const int nrt = (N + 15) / 16;
   const double* prev = omega;
   double* cur = pa;
