@@ -154,7 +154,7 @@ k_radix_upsweep(const uint64_t* __restrict__ keys, int64_t n_static, const int32
                 uint32_t* __restrict__ hist, int nb) {
   __shared__ uint32_t cnt[256];
   const int t = threadIdx.x;
-  cnt[t] = 0;
+  if (t < 256) cnt[t] = 0;
   __syncthreads();
   const int64_t n = sort_count(n_static, n_dev);
   const int64_t base = static_cast<int64_t>(blockIdx.x) * kSortTile;
@@ -163,15 +163,16 @@ k_radix_upsweep(const uint64_t* __restrict__ keys, int64_t n_static, const int32
     if (idx < n) atomicAdd(&cnt[(keys[idx] >> shift) & 255u], 1u);
   }
   __syncthreads();
-  hist[static_cast<int64_t>(t) * nb + blockIdx.x] = cnt[t];
+  if (t < 256) hist[static_cast<int64_t>(t) * nb + blockIdx.x] = cnt[t];
 }
 
-// One tile's keys in digit order.  Wave w holds the tile's w-th quarter
+// One tile's keys in digit order.  Wave w holds the tile's w-th eighth
 // (keys w WK + 64 r + lane, r = 0..kSortItems-1), so the tile's order is
 // (wave, r, lane).  Each wave ranks its own keys against a running count per
 // digit in its own LDS row (eight ballots match a lane's digit; no barrier
-// inside the loop), then one pass over the digits turns the four waves'
-// counts into their offsets and the tile's digit starts.  Equal digits keep
+// inside the loop), then one pass over the digits (thread t < 256 takes
+// digit t) turns the eight waves' counts into their offsets and the tile's
+// digit starts.  Equal digits keep
 // the tile's order, so the sort is stable.  The keys are placed in LDS at
 // their position in the tile's digit order and written out in that order:
 // consecutive threads write consecutive addresses of one digit's run.
@@ -199,9 +200,13 @@ k_radix_downsweep(const uint64_t* __restrict__ keys, const float* __restrict__ v
     key[r] = li < nvalid ? keys[base + li] : 0ull;
     val[r] = (li < nvalid && vals) ? vals[base + li] : 0.0f;
   }
-  goff[t] = hist_scan[static_cast<int64_t>(t) * nb + blockIdx.x];
+  static_assert(kSortThreads >= 256 && kSortThreads % 256 == 0, "one thread per digit");
+  constexpr int DW = 256 / 64;  // waves that hold one digit per lane
+  if (t < 256) {
+    goff[t] = hist_scan[static_cast<int64_t>(t) * nb + blockIdx.x];
 #pragma unroll
-  for (int i = 0; i < NW; ++i) wcnt[i][t] = 0;
+    for (int i = 0; i < NW; ++i) wcnt[i][t] = 0;
+  }
   __syncthreads();
   const uint64_t lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
   uint32_t rk[kSortItems];  // rank among the wave's earlier keys of the same digit
@@ -225,25 +230,29 @@ k_radix_downsweep(const uint64_t* __restrict__ keys, const float* __restrict__ v
   __syncthreads();
   {
     // digit t: the waves' exclusive offsets, then the tile's exclusive scan
-    // of the digit totals
-    uint32_t run = 0;
+    // of the digit totals (waves 0..DW-1; the others only meet the barriers)
+    uint32_t run = 0, v = 0;
+    if (w < DW) {
 #pragma unroll
-    for (int i = 0; i < NW; ++i) {
-      const uint32_t c = wcnt[i][t];
-      wcnt[i][t] = run;
-      run += c;
-    }
-    uint32_t v = run;
+      for (int i = 0; i < NW; ++i) {
+        const uint32_t c = wcnt[i][t];
+        wcnt[i][t] = run;
+        run += c;
+      }
+      v = run;
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t y = __shfl_up(v, o, 64);
-      if (lane >= o) v += y;
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(v, o, 64);
+        if (lane >= o) v += y;
+      }
+      if (lane == 63) wsum[w] = v;
     }
-    if (lane == 63) wsum[w] = v;
     __syncthreads();
-    uint32_t before = 0;
-    for (int i = 0; i < w; ++i) before += wsum[i];
-    loff[t] = before + v - run;
+    if (w < DW) {
+      uint32_t before = 0;
+      for (int i = 0; i < w; ++i) before += wsum[i];
+      loff[t] = before + v - run;
+    }
   }
   __syncthreads();
 #pragma unroll

@@ -20,8 +20,9 @@ constexpr int kHubChunk = 256;
 // (grid-stride loops over the counts that ingest finds; 8192 waves fill the
 // GPU).
 constexpr int kHubBlocks = 2048;
-// Radix sort tile: 256 threads x 16 keys.
-constexpr int kSortThreads = 256;
+// Radix sort tile: 512 threads x 16 keys (8,192 keys: runs of 32 keys per
+// digit on average when a tile is scattered).
+constexpr int kSortThreads = 512;
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortThreads * kSortItems;
 // Rows per workgroup chunk of the FP64 Gram kernels.
