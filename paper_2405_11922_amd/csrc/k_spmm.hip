@@ -26,6 +26,8 @@
 
 namespace tpo {
 
+typedef float v4f_t __attribute__((ext_vector_type(4)));
+
 enum SpmmMode { kModeV = 0, kModeUMid = 1, kModeUFinal = 2 };
 
 template <int D>
@@ -172,7 +174,8 @@ __device__ __forceinline__ void spmm_epilogue_group(int r, float4 acc, const flo
       o = make_float4(one_minus_alpha * z.x, one_minus_alpha * z.y, one_minus_alpha * z.z,
                       one_minus_alpha * z.w);
   }
-  *reinterpret_cast<float4*>(dst + static_cast<int64_t>(r) * D + q * 4) = o;
+  __builtin_nontemporal_store(v4f_t{o.x, o.y, o.z, o.w},
+                              reinterpret_cast<v4f_t*>(dst + static_cast<int64_t>(r) * D + q * 4));
 }
 
 // One launch per SpMM side.  The first `chunk_blocks` workgroups walk the hub
