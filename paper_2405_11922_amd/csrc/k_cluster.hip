@@ -736,9 +736,20 @@ k_nci_score_mfma(const float* __restrict__ U, int64_t n, int k, const long long*
     if (t >= k || l >= k) return 0.0;
     return phi_g ? phi_g[t * k + l] : sums ? static_cast<double>(sums[l * k + t]) * fac[l] : (t == l ? 1.0 : 0.0);
   };
+  // k < 16 LT: the last step (m = LT - 1) gives slot l / 16 of its j-th MFMA
+  // the index 16 m + 4 j + l / 16 instead, so that the MFMAs whose four
+  // slots all lie at or beyond k are left out (uniform); that block of Phi^T
+  // is stored permuted to match (index 16 m + 4 j + q at 16 m + 4 q + j), so
+  // its 16-byte reads are the same as the other steps'
+  const bool tail = k < 16 * LT;
   for (int e = tid; e < NL * NL; e += 64 * WV) {
     const int t = e / NL, l = e - (e / NL) * NL;
-    phit[l * NLP + t] = static_cast<float>(phi64(t, l));
+    int pos = t;
+    if (tail && t >= 16 * (LT - 1)) {
+      const int r = t - 16 * (LT - 1);
+      pos = 16 * (LT - 1) + 4 * (r & 3) + (r >> 2);
+    }
+    phit[l * NLP + pos] = static_cast<float>(phi64(t, l));
   }
   if (ACC) {
     for (int e = tid; e < k * k + k; e += 64 * WV) accl[e] = 0;
@@ -769,7 +780,13 @@ k_nci_score_mfma(const float* __restrict__ U, int64_t n, int k, const long long*
 #pragma unroll
     for (int m = 0; m < LT; ++m) {
       const int t0 = 16 * m + 4 * g;
-      if (vec) {
+      if (m == LT - 1 && tail) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int t = 16 * m + 4 * j + g;
+          ub[m][j] = (live && t < k) ? urow[t] : 0.0f;
+        }
+      } else if (vec) {
         ub[m] = (live && t0 < k) ? *reinterpret_cast<const v4f_t*>(urow + t0) : v4f_t{0.f, 0.f, 0.f, 0.f};
       } else {
 #pragma unroll
@@ -788,7 +805,10 @@ k_nci_score_mfma(const float* __restrict__ U, int64_t n, int k, const long long*
       for (int c = 0; c < LT; ++c) {
         const v4f_t a = *reinterpret_cast<const v4f_t*>(&phit[(16 * c + i16) * NLP + 16 * m + 4 * g]);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], ub[m][j], acc[c], 0, 0, 0);
+        for (int j = 0; j < 4; ++j) {
+          if (m == LT - 1 && tail && 16 * m + 4 * j >= k) break;  // uniform
+          acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], ub[m][j], acc[c], 0, 0, 0);
+        }
       }
     }
     // first maximum and runner-up: labels in increasing order within the
@@ -840,7 +860,7 @@ k_nci_score_mfma(const float* __restrict__ U, int64_t n, int k, const long long*
       for (int m = 0; m < LT; ++m)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int t = 16 * m + 4 * g + j;
+          const int t = (m == LT - 1 && tail) ? 16 * m + 4 * j + g : 16 * m + 4 * g + j;
           if (t < k)
             atomicAdd(reinterpret_cast<unsigned long long*>(&accl[best * k + t]),
                       static_cast<unsigned long long>(to_fixed(ub[m][j], sft)));
