@@ -56,6 +56,12 @@ CASES = {
     "k100": (lambda: synth.planted_abg(8000, 6000, 120_000, 100, 64, zipf_a=2.0, seed=12, sigma=0.5,
                                        in_out_ratio=40.0),
              dict(k=100, alpha=0.5, gamma=3, d=0)),
+    # k = 72: five label tiles (the row pass's eight-wave form with three
+    # waves per row tile lacking a second tile; the NCI scores' trimmed last
+    # step keeps two MFMAs)
+    "k72": (lambda: synth.planted_abg(6000, 5000, 80_000, 72, 64, zipf_a=2.0, seed=19, sigma=0.5,
+                                      in_out_ratio=40.0),
+            dict(k=72, alpha=0.5, gamma=3, d=0)),
     # k = 90: the NCI scores' last contraction step keeps three of its four
     # MFMAs, the third with two of its four slots inside k.  (Seed 16 of this
     # shape has one ONMF entry whose update ratio is negative in FP64 and
