@@ -875,7 +875,10 @@ k_nci_score_mfma(const float* __restrict__ U, int64_t n, int k, const long long*
 }
 
 // The rows whose FP32 decision was too close: FP64 scores (Phi from the same
-// sums, or phi_g, or the identity), first maximum, one wave per row.
+// sums, or phi_g, or the identity), first maximum, one wave per row.  A
+// workgroup with rows to decide forms Phi (k x k, FP64) in LDS once, and each
+// wave stages its row of U there, so the scores read both from LDS.
+constexpr int kNciRecheckMaxLds = 128 * 128 * 8;
 __global__ void __launch_bounds__(256)
 k_nci_recheck(const float* __restrict__ U, int k, const long long* __restrict__ sums,
               const double* __restrict__ phi_g, const int32_t* __restrict__ check_count,
@@ -890,28 +893,41 @@ k_nci_recheck(const float* __restrict__ U, int k, const long long* __restrict__ 
   const int sft = fixed_point_shift(__uint_as_float(st->maxabs_ups_bits), n);
   const double inv_scale = ldexp(1.0, -sft);
   const int waves = static_cast<int>(gridDim.x) * 4;
+  if (static_cast<int>(blockIdx.x) * 4 >= cnt) return;  // uniform: no row for this workgroup
+  extern __shared__ double phs[];  // phs[t k + l] = Phi[t][l]
+  __shared__ float us[4][128];      // each wave's row of U
+  for (int e = threadIdx.x; e < k * k; e += 256) {
+    const int t = e / k, l = e - (e / k) * k;
+    double ph;
+    if (phi_g) {
+      ph = phi_g[e];
+    } else if (sums) {
+      const long long c = sums[k * k + l];
+      const double f = c > 0 ? inv_scale / sqrt(static_cast<double>(c)) : 0.0;
+      ph = static_cast<double>(sums[l * k + t]) * f;
+    } else {
+      ph = t == l ? 1.0 : 0.0;
+    }
+    phs[e] = ph;
+  }
+  __syncthreads();
+  float* ur = us[threadIdx.x >> 6];
   for (int i = static_cast<int>(blockIdx.x) * 4 + static_cast<int>(threadIdx.x >> 6); i < cnt; i += waves) {
     const int64_t row = check_rows[i];
     const float* urow = U + row * k;
+    for (int t = lane; t < k; t += 64) ur[t] = urow[t];
+    wave_sync();
     int best = -1;
     double bestv = 0.0;
     for (int l = lane; l < k; l += 64) {
-      double f = 1.0;
-      if (!phi_g && sums) {
-        const long long c = sums[k * k + l];
-        f = c > 0 ? inv_scale / sqrt(static_cast<double>(c)) : 0.0;
-      }
       double sc = 0.0;
-      for (int t = 0; t < k; ++t) {
-        const double ph = phi_g ? phi_g[t * k + l] : sums ? static_cast<double>(sums[l * k + t]) * f
-                                                          : (t == l ? 1.0 : 0.0);
-        sc = fma(static_cast<double>(urow[t]), ph, sc);
-      }
+      for (int t = 0; t < k; ++t) sc = fma(static_cast<double>(ur[t]), phs[t * k + l], sc);
       if (best < 0 || sc > bestv) {
         bestv = sc;
         best = l;
       }
     }
+    wave_sync();  // every lane has read the row before the next one replaces it
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
       const double ov = __shfl_xor(bestv, off, 64);
@@ -995,6 +1011,16 @@ k_nci_accum_wide(const float* __restrict__ U, int64_t n, int k, const int32_t* _
   for (int e = tid; e < k * k + k; e += 1024) part[static_cast<int64_t>(e) * gridDim.x + blockIdx.x] = accl[e];
 }
 
+// dynamic LDS of k_nci_recheck (Phi, k x k FP64); its limit is set once
+static size_t nci_recheck_lds(int k) {
+  static std::once_flag once;
+  std::call_once(once, [] {
+    TPO_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_nci_recheck),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, kNciRecheckMaxLds));
+  });
+  return static_cast<size_t>(k) * k * sizeof(double);
+}
+
 // One round's scores and decisions.  With `acc` and k <= 112 (Phi^T and the
 // k x k + k sums both fit the LDS) the scoring kernel also forms the round's
 // label sums, as partial columns of part: the return value is their number
@@ -1025,7 +1051,8 @@ static int nci_score_mfma(const float* U, int64_t n, int k, const long long* sum
       hipLaunchKernelGGL((k_nci_score_mfma<LT, true>), dim3(nb), dim3(64 * kNciFusedWaves), dyn, s, U, n, k, sums,
                          phi_g, labels, check_count, check_rows, st, skip, part, nb + 1);
       TPO_LAUNCH_CHECK();
-      hipLaunchKernelGGL(k_nci_recheck, dim3(64), dim3(256), 0, s, U, k, sums, phi_g, check_count, check_rows, labels,
+      hipLaunchKernelGGL(k_nci_recheck, dim3(64), dim3(256), nci_recheck_lds(k), s, U, k, sums, phi_g, check_count,
+                         check_rows, labels,
                          n, st, skip, round, part, nb + 1);
       TPO_LAUNCH_CHECK();
       return nb + 1;
@@ -1046,7 +1073,8 @@ static int nci_score_mfma(const float* U, int64_t n, int k, const long long* sum
   hipLaunchKernelGGL((k_nci_score_mfma<LT, false>), dim3(nb), dim3(64 * kNciScoreWaves), 0, s, U, n, k, sums, phi_g,
                      labels, check_count, check_rows, st, skip, nullptr, 0);
   TPO_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_nci_recheck, dim3(64), dim3(256), 0, s, U, k, sums, phi_g, check_count, check_rows, labels, n,
+  hipLaunchKernelGGL(k_nci_recheck, dim3(64), dim3(256), nci_recheck_lds(k), s, U, k, sums, phi_g, check_count,
+                     check_rows, labels, n,
                      st, skip, round, nullptr, 0);
   TPO_LAUNCH_CHECK();
   return 0;
