@@ -921,24 +921,34 @@ __device__ __forceinline__ uint16_t narrow_to_bf16(uint8_t v) {
 }
 __device__ __forceinline__ bool bf16_finite(uint16_t b) { return (b & 0x7f80u) != 0x7f80u; }
 
+// Rows per workgroup of the split projection: each wave takes RT row tiles
+// against the same staged slab of the three parts of Psi~ (four for up to 32
+// output columns, two for 64, one for 128, as the accumulators allow).
+__host__ __device__ constexpr int ps_row_tiles(int ct) { return ct <= 2 ? 4 : (ct == 4 ? 2 : 1); }
+
 template <int CT, typename XT>
 __global__ void __launch_bounds__(256)
 k_project_split(const XT* __restrict__ X, int64_t n, int du, int64_t ldx, const uint16_t* __restrict__ psit, int dp,
                 int dup, float* __restrict__ out, int32_t* __restrict__ err_bits, int vec) {
   constexpr int NC = 16 * CT;
-  __shared__ __align__(16) uint16_t xs[kPjRows * kPsLd];
+  constexpr int RT = ps_row_tiles(CT), ROWS = 64 * RT;
+  __shared__ __align__(16) uint16_t xs[ROWS * kPsLd];
   __shared__ __align__(16) uint16_t ps[3 * NC * kPsLd];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int i16 = lane & 15, kq = lane >> 4;
-  const int64_t row0 = static_cast<int64_t>(blockIdx.x) * kPjRows;
+  const int64_t row0 = static_cast<int64_t>(blockIdx.x) * ROWS;
   const int64_t plane = static_cast<int64_t>(dp) * dup;
-  v4f_t acc_hi[CT], acc_lo[CT];
+  v4f_t acc_hi[RT][CT], acc_lo[RT][CT];
 #pragma unroll
-  for (int t = 0; t < CT; ++t) acc_hi[t] = acc_lo[t] = v4f_t{0.f, 0.f, 0.f, 0.f};
+  for (int r = 0; r < RT; ++r)
+#pragma unroll
+    for (int t = 0; t < CT; ++t) acc_hi[r][t] = acc_lo[r][t] = v4f_t{0.f, 0.f, 0.f, 0.f};
   bool bad = false;
   for (int k0 = 0; k0 < du; k0 += kPsK) {
-    {  // X: thread tid stages row tid / 4, columns 8 (tid % 4) .. + 7
-      const int rr = tid >> 2, c0 = 8 * (tid & 3);
+    constexpr int PPR = kPsK / 8, RPP = 256 / PPR;  // 16-byte pieces per row, rows per pass
+#pragma unroll
+    for (int u = 0; u < ROWS / RPP; ++u) {  // X: thread tid stages row tid / PPR + RPP u, piece tid % PPR
+      const int rr = tid / PPR + RPP * u, c0 = 8 * (tid % PPR);
       const int64_t row = row0 + rr;
       uint16_t v[8];
       if (vec) {  // one 16-byte (bfloat16) or 8-byte (FP8) load; d_u is a multiple of 8
@@ -1001,29 +1011,42 @@ k_project_split(const XT* __restrict__ X, int64_t n, int du, int64_t ldx, const 
       *reinterpret_cast<v4u_t*>(ps + (part * NC + nn) * kPsLd + 8 * q) = wv;
     }
     __syncthreads();
-    const v8bf_t a = __builtin_bit_cast(v8bf_t, *reinterpret_cast<const v4u_t*>(xs + (16 * w + i16) * kPsLd + 8 * kq));
 #pragma unroll
-    for (int t = 0; t < CT; ++t) {
-      const int nn = 16 * t + i16;
-      const v8bf_t bh = __builtin_bit_cast(v8bf_t, *reinterpret_cast<const v4u_t*>(ps + nn * kPsLd + 8 * kq));
-      const v8bf_t bm = __builtin_bit_cast(v8bf_t, *reinterpret_cast<const v4u_t*>(ps + (NC + nn) * kPsLd + 8 * kq));
-      const v8bf_t bl = __builtin_bit_cast(v8bf_t, *reinterpret_cast<const v4u_t*>(ps + (2 * NC + nn) * kPsLd + 8 * kq));
-      acc_hi[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bh, acc_hi[t], 0, 0, 0);
-      acc_lo[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bl, acc_lo[t], 0, 0, 0);
-      acc_lo[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bm, acc_lo[t], 0, 0, 0);
+    for (int ks = 0; ks < kPsK / 32; ++ks) {
+      v8bf_t a[RT];
+#pragma unroll
+      for (int r = 0; r < RT; ++r)
+        a[r] = __builtin_bit_cast(
+            v8bf_t, *reinterpret_cast<const v4u_t*>(xs + (16 * (w + 4 * r) + i16) * kPsLd + 32 * ks + 8 * kq));
+#pragma unroll
+      for (int t = 0; t < CT; ++t) {
+        const int nn = 16 * t + i16, kc = 32 * ks + 8 * kq;
+        const v8bf_t bh = __builtin_bit_cast(v8bf_t, *reinterpret_cast<const v4u_t*>(ps + nn * kPsLd + kc));
+        const v8bf_t bm = __builtin_bit_cast(v8bf_t, *reinterpret_cast<const v4u_t*>(ps + (NC + nn) * kPsLd + kc));
+        const v8bf_t bl =
+            __builtin_bit_cast(v8bf_t, *reinterpret_cast<const v4u_t*>(ps + (2 * NC + nn) * kPsLd + kc));
+#pragma unroll
+        for (int r = 0; r < RT; ++r) {
+          acc_hi[r][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], bh, acc_hi[r][t], 0, 0, 0);
+          acc_lo[r][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], bl, acc_lo[r][t], 0, 0, 0);
+          acc_lo[r][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], bm, acc_lo[r][t], 0, 0, 0);
+        }
+      }
     }
     __syncthreads();
   }
   if (bad) atomicOr(err_bits, 4);
 #pragma unroll
-  for (int t = 0; t < CT; ++t) {
-    const int col = 16 * t + i16;
+  for (int r = 0; r < RT; ++r)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t row = row0 + 16 * w + 4 * kq + v;
-      if (row < n && col < dp) out[row * dp + col] = acc_hi[t][v] + acc_lo[t][v];
+    for (int t = 0; t < CT; ++t) {
+      const int col = 16 * t + i16;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = row0 + 16 * (w + 4 * r) + 4 * kq + v;
+        if (row < n && col < dp) out[row * dp + col] = acc_hi[r][t][v] + acc_lo[r][t][v];
+      }
     }
-  }
 }
 
 template <typename XT>
@@ -1036,8 +1059,9 @@ static void project_split(const Plan& p, void* ws, const XT* x, int64_t ldx, con
   hipLaunchKernelGGL(k_psi_split, dim3(ceil_div(cnt, 256)), dim3(256), 0, s, bufp<double>(p, ws, B_PSI_D), sc, p.du,
                      p.d, p.dp, dup, pst);
   TPO_LAUNCH_CHECK();
-  const dim3 grid(ceil_div(p.n, kPjRows));
   const int64_t n = p.n;
+  const int ct = (p.dp + 15) / 16;
+  const dim3 grid(ceil_div(p.n, 64 * ps_row_tiles(ct == 1 || ct == 2 || ct == 4 ? ct : 8)));
   // word loads: eight elements (16 or 8 bytes) aligned to their size
   const int vec = (reinterpret_cast<uintptr_t>(x) % (8 * sizeof(XT)) == 0 && ldx % 8 == 0 && p.du % 8 == 0) ? 1 : 0;
   switch ((p.dp + 15) / 16) {
